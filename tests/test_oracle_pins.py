@@ -1,0 +1,301 @@
+"""Pins for the CPU oracle: each check compares it with something other than
+itself -- brute-force walk enumeration, closed forms derived by hand for
+complete, star and cycle graphs, symmetry, reachability, relabelling and the
+convergence condition (Section 3.1).  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import katz_inputs as ki
+import oracle
+from oracle import reference as ko
+
+
+def _graph(n, edges):
+    g = ki.from_edges(n, edges)
+    return g.n, g.row_ptr, g.col
+
+
+def complete(n):
+    return _graph(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+
+
+def star(m):
+    return _graph(m + 1, [(0, i) for i in range(1, m + 1)])
+
+
+def cycle(n):
+    return _graph(n, [(i, (i + 1) % n) for i in range(n)])
+
+
+def path(n):
+    return _graph(n, [(i, i + 1) for i in range(n - 1)])
+
+
+# The series stops when its tail bound is below 1e-13 of ||k||; allow that
+# plus rounding.  The dense solve is accurate to a few ulps times kappa(M).
+SER = 3e-13
+
+
+def both(n, rp, col, q, beta):
+    """Series and dense solve of the oracle, for one query."""
+    out = oracle.katz_oracle(n, rp, col, [q], beta=beta, direct=True)
+    return out["k"][:, 0], out["k_direct"][:, 0], out
+
+
+# ----------------------------------------------------------------- P2
+@pytest.mark.parametrize("n,beta", [(6, 0.1), (7, 0.15), (12, 0.02)])
+def test_complete_graph_closed_form(n, beta):
+    # A = J - I; Sherman-Morrison on (1+beta) I - beta J gives
+    # K_pq = beta / ((1+beta)(1-(n-1)beta)), K_qq = (n-1) beta^2 / (same).
+    g = complete(n)
+    den = (1 + beta) * (1 - (n - 1) * beta)
+    for q in (0, n - 1):
+        ks, kd, _ = both(*g, q, beta)
+        exp = np.full(n, beta / den)
+        exp[q] = (n - 1) * beta ** 2 / den
+        np.testing.assert_allclose(ks, exp, rtol=SER, atol=0)
+        np.testing.assert_allclose(kd, exp, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("m,c", [(5, 0.5), (9, 0.9), (3, 0.1)])
+def test_star_closed_form(m, c):
+    # lambda_max(star with m leaves) = sqrt(m); d = 1 - m beta^2.
+    beta = c / math.sqrt(m)
+    d = 1 - m * beta ** 2
+    g = star(m)
+    ks, kd, out = both(*g, 0, beta)           # centre query
+    exp = np.full(m + 1, beta / d)
+    exp[0] = m * beta ** 2 / d
+    np.testing.assert_allclose(ks, exp, rtol=SER)
+    np.testing.assert_allclose(kd, exp, rtol=1e-13)
+    assert abs(out["lambda_max"] - math.sqrt(m)) < 1e-12
+    ks, kd, _ = both(*g, 2, beta)             # leaf query
+    exp = np.full(m + 1, beta ** 2 / d)       # other leaves and the leaf itself
+    exp[0] = beta / d
+    np.testing.assert_allclose(ks, exp, rtol=SER)
+    np.testing.assert_allclose(kd, exp, rtol=1e-13)
+
+
+@pytest.mark.parametrize("n,beta", [(9, 0.2), (8, 0.45), (5, 0.05)])
+def test_cycle_closed_form(n, beta):
+    # Periodic Green's function of x_j - beta (x_{j-1} + x_{j+1}) = delta_j0:
+    # s = sqrt(1 - 4 beta^2), t = (1 - s) / (2 beta),
+    # x_delta = (t^delta + t^(n-delta)) / (s (1 - t^n)); K = x - [delta = 0].
+    s = math.sqrt(1 - 4 * beta ** 2)
+    t = (1 - s) / (2 * beta)
+    g = cycle(n)
+    q = 3 % n
+    ks, kd, _ = both(*g, q, beta)
+    exp = np.empty(n)
+    for v in range(n):
+        dl = (v - q) % n
+        exp[v] = (t ** dl + t ** (n - dl)) / (s * (1 - t ** n)) - (1.0 if dl == 0 else 0.0)
+    # the series error bound is norm-wise (tail <= 1e-13 ||k||)
+    np.testing.assert_allclose(ks, exp, rtol=1e-12, atol=SER * np.linalg.norm(exp))
+    np.testing.assert_allclose(kd, exp, rtol=1e-12)
+
+
+# ----------------------------------------------------------------- P1
+def test_walk_enumeration_path3_by_hand():
+    # Path 0-1-2 from node 0: odd l reaches node 1 by 2^((l-1)/2) walks, even
+    # l reaches nodes 0 and 2 by 2^(l/2-1) walks each.
+    n, rp, col = path(3)
+    cnt = oracle.walk_counts(n, rp, col, 0, 9)
+    for l in range(1, 10):
+        if l % 2:
+            assert cnt[l] == [0, 2 ** ((l - 1) // 2), 0]
+        else:
+            assert cnt[l] == [2 ** (l // 2 - 1), 0, 2 ** (l // 2 - 1)]
+
+
+SMALL = {
+    "tree": (7, [(0, 1), (0, 2), (1, 3), (1, 4), (2, 5), (5, 6)]),
+    "tri_tail": (5, [(0, 1), (1, 2), (0, 2), (2, 3), (3, 4)]),
+    "c5_chord": (5, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0), (1, 3)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_walk_sum_matches_solver(name):
+    # eq. KatzPath summed over explicitly enumerated walks, plus the rigorous
+    # entrywise tail bound sum_{l>L} c^l = c^(L+1)/(1-c), must contain both the
+    # series and the dense solve (and lie below them: every term is >= 0).
+    n, edges = SMALL[name]
+    n, rp, col = _graph(n, edges)
+    L = 10
+    A = ko.csr_matrix(n, rp, col)
+    lam = ko.lambda_max(A)
+    for c in (0.05, 0.6):
+        beta = c / lam
+        for q in range(n):
+            cnt = oracle.walk_counts(n, rp, col, q, L)
+            trunc = np.array([sum(beta ** l * cnt[l][v] for l in range(1, L + 1)) for v in range(n)])
+            bound = c ** (L + 1) / (1 - c)
+            ks, kd, _ = both(n, rp, col, q, beta)
+            for k in (ks, kd):
+                assert np.all(k >= trunc - 1e-15)
+                assert np.all(k - trunc <= bound + 1e-15)
+            if c == 0.05:
+                np.testing.assert_allclose(ks, trunc, rtol=0, atol=1e-14)
+
+
+def test_walk_counts_golden():
+    # Stored walk counts (tests/golden/walks_tri_tail.json, written by
+    # tests/golden/make_golden.py with oracle.walk_counts) re-derived here.
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", "walks_tri_tail.json")
+    with open(p) as f:
+        gold = json.load(f)
+    n, rp, col = _graph(gold["n"], [tuple(e) for e in gold["edges"]])
+    got = oracle.walk_counts(n, rp, col, gold["q"], gold["max_len"])
+    assert got == gold["counts"]
+    # the same counts are the entries of A^l e_q (integer matrix powers)
+    A = np.zeros((n, n), dtype=object)
+    for u in range(n):
+        for v in col[rp[u]:rp[u + 1]]:
+            A[u, v] = 1
+    x = np.zeros(n, dtype=object)
+    x[gold["q"]] = 1
+    for l in range(1, gold["max_len"] + 1):
+        x = A.dot(x)
+        assert list(x) == gold["counts"][l]
+
+
+# ----------------------------------------------------------- P3, P4, P9
+def _small_sbm():
+    return ki.sbm([40, 30, 50], [0.2, 0.25, 0.15], 0.02, seed=77)
+
+
+def test_symmetry_kpq_equals_kqp():
+    g = _small_sbm()
+    qs = ki.sample_queries(g, 6, 5)
+    out = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, c=0.7)
+    K = out["k"]
+    for i, p in enumerate(qs):
+        for j, q in enumerate(qs):
+            assert abs(K[q, i] - K[p, j]) <= 1e-13 * max(abs(K[q, i]), 1e-300)
+
+
+def test_reachability_and_isolated_query():
+    # disjoint union: a 5-cycle (0..4), a triangle (5..7) and isolated node 8
+    n, rp, col = _graph(9, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0), (5, 6), (6, 7), (5, 7)])
+    out = oracle.katz_oracle(n, rp, col, [1, 6, 8], c=0.8)
+    k = out["k"]
+    assert np.all(k[0:5, 0] > 0) and np.all(k[5:, 0] == 0)
+    assert np.all(k[5:8, 1] > 0) and np.all(k[[0, 1, 2, 3, 4, 8], 1] == 0)
+    assert np.all(k[:, 2] == 0)
+
+
+def test_relabelling_permutes_scores():
+    g = _small_sbm()
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(g.n)           # new label of old node v is perm[v]
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    h = ki.from_edges(g.n, zip(perm[rows], perm[g.col]))
+    qs = ki.sample_queries(g, 3, 9)
+    a = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, c=0.6)
+    b = oracle.katz_oracle(h.n, h.row_ptr, h.col, perm[qs], beta=a["beta"])
+    np.testing.assert_allclose(b["k"][perm, :], a["k"], rtol=1e-12, atol=1e-300)
+
+
+# ----------------------------------------------------------------- P5
+def test_convergence_condition():
+    n, rp, col = _graph(2, [(0, 1)])
+    with pytest.raises(oracle.OracleError):
+        oracle.katz_oracle(n, rp, col, [0], beta=1.0)      # c = 1: M singular
+    with pytest.raises(oracle.OracleError):
+        oracle.katz_oracle(n, rp, col, [0], c=1.2)
+    out = oracle.katz_oracle(n, rp, col, [0], c=0.999)
+    b = 0.999
+    # K_2: K_01 = b / (1 - b^2), K_00 = b^2 / (1 - b^2)
+    np.testing.assert_allclose(out["k"][:, 0], [b * b / (1 - b * b), b / (1 - b * b)], rtol=1e-9)
+
+
+@pytest.mark.parametrize("bad", ["asym", "loop", "unsorted", "range"])
+def test_validation_rejects(bad):
+    rp = np.array([0, 1, 2, 2], np.int32)
+    col = np.array([1, 0], np.int32)
+    if bad == "asym":
+        rp, col = np.array([0, 1, 1, 1], np.int32), np.array([1], np.int32)
+    elif bad == "loop":
+        rp, col = np.array([0, 2, 3, 3], np.int32), np.array([0, 1, 0], np.int32)
+    elif bad == "unsorted":
+        rp, col = np.array([0, 2, 3, 4], np.int32), np.array([2, 1, 0, 0], np.int32)
+    elif bad == "range":
+        col = np.array([1, 5], np.int32)
+    with pytest.raises(oracle.OracleError):
+        oracle.validate_csr(3, rp, col)
+
+
+# ------------------------------------------------------ series vs direct
+@pytest.mark.parametrize("c", [0.1, 0.5, 0.9, 0.99])
+def test_series_and_direct_agree_on_sbm(c):
+    w = ki.workload("sbm2k", scale=0.3)
+    g = w.graph
+    qs = ki.sample_queries(g, 4, 11)
+    out = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, c=c)
+    assert np.all(out["cross_rel"] <= 1e-11)
+    assert np.all(out["residual"] <= 1e-12)
+    assert np.all(out["k"] >= 0)
+
+
+# ------------------------------------------------------------------ top-K
+def test_topk_star_leaf_query_ties_by_id():
+    n, rp, col = star(6)
+    out = oracle.katz_oracle(n, rp, col, [3], c=0.5)
+    ids, sc, sids, ss = oracle.topk_links(n, rp, col, out["k"][:, 0], 3, 4)
+    # centre 0 is the only neighbour; all other leaves tie -> ascending id
+    assert list(ids) == [1, 2, 4, 5]
+    assert np.all(sc == sc[0])
+    ids, sc, _, _ = oracle.topk_links(n, rp, col, out["k"][:, 0], 3, 8)
+    assert list(ids) == [1, 2, 4, 5, 6, -1, -1, -1] and np.isnan(sc[5:]).all()
+
+
+def test_topk_path_orders_by_distance():
+    n, rp, col = path(8)
+    out = oracle.katz_oracle(n, rp, col, [0], c=0.5)
+    ids, _, _, _ = oracle.topk_links(n, rp, col, out["k"][:, 0], 0, 6)
+    assert list(ids) == [2, 3, 4, 5, 6, 7]
+
+
+def test_tie_rule_acceptance():
+    sids = np.array([10, 11, 12, 13, 14, 15])
+    ss = np.array([5.0, 4.0, 4.0 - 1e-9, 3.0, 3.0, 1.0])
+    ok = lambda b, K: oracle.topk_accept(b, sids, ss, K, 1e-6)[0]
+    assert ok([10, 11, 12, 13], 4)
+    assert ok([10, 12, 11, 14], 4)        # swap within class, straddle subset
+    assert not ok([11, 10, 12, 13], 4)    # 10 and 11 are 1.0 apart
+    assert not ok([10, 11, 12, 15], 4)
+    assert ok([10, 11, 12, 13, 14, 15, -1], 7)
+    assert not ok([10, 11, 12, 13, 14, 15, 99], 7)
+
+
+# ------------------------------------------------- planted oracle mistakes
+def test_pins_catch_planted_mistakes(monkeypatch):
+    """Plants plausible mistakes in the oracle (on the CPU) and checks that the
+    closed-form pins above reject each one."""
+    n, rp, col = star(5)
+    beta = 0.5 / math.sqrt(5)
+    d = 1 - 5 * beta ** 2
+    exp = np.full(6, beta / d)
+    exp[0] = 5 * beta ** 2 / d
+
+    def series_only():
+        return oracle.katz_oracle(n, rp, col, [0], beta=beta, direct=False)["k"][:, 0]
+
+    good = series_only()
+    np.testing.assert_allclose(good, exp, rtol=SER)
+    orig_rhs = ko.katz_rhs
+    mistakes = {
+        "dropped beta": lambda A, b, q: orig_rhs(A, 1.0, q),
+        "e_q instead of A e_q": lambda A, b, q: b * np.eye(A.shape[0])[:, np.atleast_1d(q)],
+        "transposed index": lambda A, b, q: b * A[np.atleast_1d(q), :].toarray().T[::-1],
+    }
+    for name, bad in mistakes.items():
+        monkeypatch.setattr(ko, "katz_rhs", bad)
+        got = series_only()
+        assert not np.allclose(got, exp, rtol=1e-6), name
+    monkeypatch.setattr(ko, "katz_rhs", orig_rhs)
