@@ -1,0 +1,231 @@
+"""Benchmark: Katz queries/sec at 1e-6 relative residual, LRC-Katz vs plain GPU CG,
+on one MI355X.
+
+Workload (default): Chung-Lu power-law graph, 1,000,000 nodes, exponent 2.5,
+mean degree 20 (seeded, synthetic), damping c = beta * lambda_max in
+{0.1, 0.5, 0.9}, rank 32, FP64, one query node per solve.  A step is one query
+solved through the whole path (right-hand side, Schur RHS, PCG on S, block
+back-solve, FP64 residual check, unpermute into a device buffer).  The headline
+value is LRC queries/sec at c = 0.5; CG at the same c, latency percentiles,
+iterations and the other c values are reported beside it.
+
+Prints ONE JSON line.  Options: --gpus (1 only), --steps, --warmup, --c,
+--scale (node-count factor for quick runs), --no-cpu (skip the oracle leg),
+--copy-calib (adds a plain 1 GiB device copy, to calibrate rocprofv3 byte
+counters), --profile-kernels (HIP-event kernel timing in a repeat of the timed
+steps; on by default).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("solver.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1912_06525_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str, achieved_bytes_per_launch: float):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
+    when absent or taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--c", type=str, default="0.1,0.5,0.9")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--rank", type=int, default=32)
+    ap.add_argument("--max-block", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile-kernels", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(queries would shard across GPUs with a replicated index)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import katz_inputs as ki
+    import paper_1912_06525_amd as K
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    w = ki.workload("cl1m", scale=args.scale)
+    g = w.graph
+    log("graph: n=%d nnz=%d (%.1fs)" % (g.n, g.nnz, time.time() - t0))
+    cs = [float(x) for x in args.c.split(",")]
+    head_c = 0.5 if 0.5 in cs else cs[0]
+    tol = 1e-6
+    queries = w.queries
+    results = {}
+    roofline = None
+    kernel_table = None
+    out = torch.empty((1, g.n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def run(idx, method, steps, offset):
+        lat, its, res = [], [], []
+        for s in range(steps):
+            q = queries[(offset + s) % len(queries)]
+            t = time.perf_counter()
+            _, st = idx.query([q], out=out, tol=tol, method=method, stream=stream)
+            lat.append(time.perf_counter() - t)
+            its.append(st[0]["iters"])
+            res.append(st[0]["rel_residual"])
+            if st[0]["status"] != 0:
+                raise RuntimeError("query %d did not converge: %r" % (q, st[0]))
+        return lat, its, res
+
+    for c in cs:
+        tb = time.time()
+        idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=args.rank, max_block=args.max_block, device=0)
+        info = idx.info
+        log("c=%.2f index: n1=%d n2=%d blocks=%d sigma1=%.4f sigma_r+1=%.5f build %.1fs"
+            % (c, info.n1, info.n2, info.nblocks, info.sigma_max, info.sigma_next, time.time() - tb))
+        entry = {"n1": info.n1, "n2": info.n2, "nblocks": info.nblocks, "build_s": round(info.build_seconds, 2),
+                 "beta": info.beta, "lambda_max": info.lambda_max}
+        for name, method in (("lrc", K.KATZ_METHOD_LRC), ("cg", K.KATZ_METHOD_CG)):
+            run(idx, method, args.warmup, 0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            lat, its, res = run(idx, method, args.steps, args.warmup)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            lat_ms = np.array(lat) * 1e3
+            entry[name] = {"qps": args.steps / el, "ms_per_query": el * 1e3 / args.steps,
+                           "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+                           "iters_median": float(np.median(its)), "iters_max": int(np.max(its)),
+                           "max_rel_residual": float(np.max(res))}
+            log("  %s: %.1f q/s, %.3f ms/query, iters median %g" % (name, entry[name]["qps"],
+                                                                    entry[name]["ms_per_query"],
+                                                                    entry[name]["iters_median"]))
+            if c == head_c and not args.no_profile_kernels:
+                # repeat of the timed steps with HIP-event timing of every hot kernel launch
+                K.katz_profile_reset()
+                K.katz_profile_enable(True)
+                run(idx, method, args.steps, args.warmup)
+                torch.cuda.synchronize()
+                K.katz_profile_enable(False)
+                tab = [r for r in K.katz_profile_read() if r["launches"] > 0]
+                for r in tab:
+                    r["avg_us"] = 1e3 * r["total_ms"] / r["launches"]
+                    r["alg_bytes_per_launch"] = r["alg_bytes"] / r["launches"]
+                    r["achieved_GBs"] = r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
+                entry[name]["kernels"] = tab
+                if name == "lrc":
+                    kernel_table = tab
+        if c == head_c:
+            head_idx_info = entry
+            if not args.no_cpu:
+                cpu = cpu_baseline(g, idx, queries, tol, out, stream, K)
+                entry["cpu"] = cpu
+        results["c=%g" % c] = entry
+        idx.close()
+
+    if args.copy_calib:
+        x = torch.empty(2 ** 27, dtype=torch.float64, device=dev)   # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    head = results["c=%g" % head_c]
+    if kernel_table:
+        dom = max(kernel_table, key=lambda r: r["total_ms"])
+        wl = "cl1m" if args.scale == 1.0 else "cl1m_s%g" % args.scale
+        traffic = load_traffic(dom["name"], wl, dom["alg_bytes_per_launch"])
+        roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["achieved_GBs"], 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "avg_launch_us": round(dom["avg_us"], 2),
+                    "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
+    value = head["lrc"]["qps"]
+    line = {
+        "metric": "Katz queries/sec at 1e-6 rel. residual, LRC-Katz vs CG, 1 MI355X; p99 ms",
+        "value": round(value, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["lrc"]["ms_per_query"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Chung-Lu power-law graph, %d nodes, exponent 2.5, mean degree 20, "
+                               "c = beta*lambda_max = %g, rank %d, FP64, 1 query per solve"
+                               % (g.n, head_c, args.rank),
+                   "n": g.n, "nnz": g.nnz, "c": head_c, "rank": args.rank, "batch": 1, "tol": tol},
+        "p99_ms": round(head["lrc"]["p99_ms"], 4),
+        "p50_ms": round(head["lrc"]["p50_ms"], 4),
+        "cg_qps": round(head["cg"]["qps"], 2),
+        "lrc_over_cg": round(value / head["cg"]["qps"], 3),
+        "roofline": roofline,
+        "cpu_baseline": head.get("cpu", {}).get("baseline"),
+        "results": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(g, idx, queries, tol, out, stream, K):
+    """Times the CPU oracle (never tuned) on a bounded sample of the queries and
+    checks the GPU's scores for those queries against it (full-size parity)."""
+    import numpy as np
+
+    import oracle
+    info = idx.info
+    sample = [int(q) for q in queries[:4]]
+    t = time.perf_counter()
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, sample, beta=info.beta, lam=info.lambda_max, validate=False)
+    el = time.perf_counter() - t
+    errs = []
+    for j, q in enumerate(sample):
+        sc, st = idx.query([q], tol=tol)
+        k = ref["k"][:, j]
+        errs.append(float(np.linalg.norm(sc[0] - k) / np.linalg.norm(k)))
+    bound = tol * (1 + info.c) / (1 - info.c)
+    log("  cpu oracle: %d queries in %.1fs; GPU rel err max %.2e (bound %.2e)" % (len(sample), el, max(errs), bound))
+    return {"baseline": {"value": round(len(sample) / el, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
+                         "sample": "%d queries of the same graph and c, truncated Neumann series to a 1e-13 tail "
+                                   "bound (scipy CSR SpMV, single thread)" % len(sample)},
+            "gpu_rel_err_max": max(errs), "err_bound": bound, "oracle_terms": ref["terms"].tolist()}
+
+
+if __name__ == "__main__":
+    main()

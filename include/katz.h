@@ -1,0 +1,227 @@
+/*
+ * katz.h -- query-time Katz proximity on one MI355X (gfx950).
+ *
+ * Method: Coskun, Baggag, Koyuturk, "Fast Computation of Katz Index for
+ * Efficient Processing of Link Prediction Queries" (arXiv:1912.06525).
+ *
+ * For a query node q of an undirected graph with adjacency matrix A the
+ * library returns the Katz vector k_q, the q-th column of
+ *     K = sum_{l>=1} beta^l A^l = (I - beta A)^{-1} - I          (Sec. 3.1,
+ * eqs. KatzPath/KatzMatrix), obtained by solving
+ *     M k_q = beta A e_q,   M = I - beta A                      (eq. LinearSystem).
+ * It needs 0 < beta < 1/lambda_max(A) (Sec. 3.1), so that M is SPD.
+ *
+ * Index (Algorithm 1, Sec. 3.2 steps 1-4): nodes are reordered into
+ * independent blocks plus a vertex separator, so that
+ *     M = [[M11, M12], [M12^T, M22]]
+ * with M11 block diagonal (Lemma 1).  Each M11 block is factorised and its
+ * inverse stored; the Schur complement S = M22 - M12^T M11^{-1} M12 is never
+ * formed.  A rank-r preconditioner (eqs. RMatrix, inverseTildeS)
+ *     S~^{-1} = L^{-T} (I + U~ D U~^T) L^{-1},  D = diag(sigma_i / (1 - sigma_i)),
+ * uses the top r eigenpairs (sigma_i, u_i) of R = I - L^{-1} S L^{-T}.
+ *
+ * Query (Algorithm 2, Sec. 3.2 steps 5-6; Lemma 1 eqs. 5-6): build
+ * b = beta A e_q in the permuted order, f = b2 - M12^T M11^{-1} b1, solve
+ * S k2 = f by preconditioned conjugate gradients, then
+ * k1 = M11^{-1} (b1 - M12 k2), merge and unpermute.  Plain CG on M (the
+ * paper's comparison method) is available as a method and is the fallback.
+ * Every result is checked by its true FP64 residual ||b - M k||_2 / ||b||_2
+ * and refined in FP64 until it meets the requested tolerance.
+ *
+ * Threading: an index is immutable after build; katz_query and
+ * katz_topk_links may run concurrently on one index from several host threads
+ * (each call takes its own device workspace).  Errors are returned as status
+ * codes; katz_last_error() returns the calling thread's last message.
+ */
+#ifndef KATZ_H
+#define KATZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct katz_index katz_index; /* opaque; immutable after build */
+
+enum katz_status {
+  KATZ_OK = 0,
+  KATZ_EINVAL = -1,   /* bad argument (null pointer, out-of-range id, bad CSR) */
+  KATZ_ENOTSYM = -2,  /* adjacency matrix is not symmetric */
+  KATZ_EDIVERGE = -3, /* beta * lambda_max(A) >= 1: series diverges, M not SPD */
+  KATZ_ENOMEM = -4,   /* host or device allocation failed */
+  KATZ_EDEVICE = -5,  /* HIP error, or index built without a device */
+  KATZ_ENOCONV = -6,  /* some query missed the tolerance (see stats) */
+  KATZ_EBUSY = -7,    /* server queue full */
+  KATZ_EIO = -8       /* file error or corrupt index file */
+};
+
+enum katz_precision {
+  KATZ_PREC_FP64 = 0, /* every panel, factor and reduction in FP64 */
+  KATZ_PREC_MIXED = 1 /* FP32 SpMM/block solves, BF16 low-rank factor with
+                         FP32 accumulation, FP64 dots, FP64 residual refinement */
+};
+
+enum katz_l_kind {
+  KATZ_L_AUTO = 0,    /* CHOL when the separator is small (<= 1024), else IDENTITY */
+  KATZ_L_CHOL = 1,    /* L = dense Cholesky factor of M22 (eq. RMatrix as printed); n2 <= 4096 */
+  KATZ_L_IDENTITY = 2 /* L = I: R = I - S, preconditioner I + U~ D U~^T */
+};
+
+enum katz_method { KATZ_METHOD_LRC = 0, KATZ_METHOD_CG = 1 };
+
+enum katz_path {
+  KATZ_PATH_LRC = 0,        /* Schur-complement PCG with the rank-r preconditioner */
+  KATZ_PATH_CG = 1,         /* plain CG on M (requested) */
+  KATZ_PATH_CG_FALLBACK = 2 /* LRC broke down or stalled; CG finished the query */
+};
+
+typedef struct {
+  double beta;            /* damping factor beta; used when > 0 */
+  double beta_frac;       /* else c in (0,1): beta = c / lambda_max(A) */
+  int32_t rank;           /* r, low-rank correction dimension (>= 0) */
+  int32_t max_block;      /* cap on the size of an M11 block (0: 64) */
+  const int32_t* labels;  /* optional initial partition, n entries, or NULL */
+  int32_t l_kind;         /* enum katz_l_kind */
+  int32_t precision;      /* enum katz_precision */
+  uint64_t seed;          /* Lanczos start vector seed */
+  int32_t device;         /* HIP device ordinal; -1 builds a host-only index
+                             (inspectable, not queryable) */
+  int32_t lanczos_steps;  /* 0: max(2r, r + 20) */
+} katz_build_opts;
+
+typedef struct {
+  double rel_tol;      /* target true FP64 ||b - M k||_2 / ||b||_2 (default 1e-6) */
+  int32_t max_iter;    /* inner iterations per refinement sweep (default 1000) */
+  int32_t method;      /* enum katz_method (default LRC) */
+  int32_t max_sweeps;  /* FP64 refinement sweeps (default 6) */
+  int32_t check_every; /* inner iterations between host convergence polls (default 8) */
+  int32_t force_fallback; /* fault injection for tests: every LRC solve stops after
+                             one iteration and counts as broken down, so the
+                             refinement sweeps run plain CG (default 0) */
+} katz_query_opts;
+
+typedef struct {
+  int32_t status;      /* KATZ_OK, or KATZ_ENOCONV if the tolerance was missed */
+  int32_t iters;       /* inner (P)CG iterations, summed over sweeps */
+  int32_t sweeps;      /* FP64 residual/refinement sweeps */
+  int32_t path;        /* enum katz_path */
+  double rel_residual; /* true FP64 ||b - M k||_2 / ||b||_2 of the returned k */
+  double err_bound;    /* bound on ||k - k*||_2 / ||k*||_2:
+                          rel_residual * (1 + c) / (1 - c) */
+} katz_query_stats;
+
+typedef struct {
+  int32_t n, n1, n2;       /* nodes; block-interior nodes; separator nodes */
+  int64_t nnz;             /* stored adjacency entries (2 |E|) */
+  int32_t nblocks;         /* M11 blocks */
+  int32_t max_block_size;  /* largest M11 block */
+  int32_t rank;            /* r actually kept */
+  int32_t l_kind;          /* resolved katz_l_kind (CHOL or IDENTITY) */
+  int32_t precision;
+  int32_t device;          /* -1 for a host-only index */
+  double beta, lambda_max, c;
+  double sigma_max;        /* largest kept eigenvalue of R (0 if r = 0) */
+  double sigma_next;       /* Ritz estimate of sigma_{r+1} (0 if unknown) */
+  int64_t factor_bytes;    /* M11 block inverses as stored on the device */
+  int64_t device_bytes;    /* total resident index bytes on the device */
+  double build_seconds;
+} katz_index_info_t;
+
+/* Sets the documented defaults. */
+void katz_build_opts_default(katz_build_opts* o);
+void katz_query_opts_default(katz_query_opts* o);
+
+/*
+ * Builds the index (Algorithm 1): validates the CSR, computes lambda_max(A)
+ * by Lanczos, partitions the graph into blocks of at most max_block nodes
+ * plus a vertex separator (Sec. 3.2 steps 2-3), inverts every M11 block
+ * through its Cholesky factor (step 4), factors M22 when l_kind is CHOL, and
+ * runs Lanczos on R for the top `rank` eigenpairs (eq. RMatrix).  Then the
+ * index is copied to the device once.
+ *   n, nnz, row_ptr[n+1], col_idx[nnz]: host CSR, int32, strictly increasing
+ *     columns per row, no diagonal, symmetric.
+ *   val: host FP64 nonnegative weights [nnz], or NULL for an unweighted graph.
+ *   opts: may be NULL (defaults with beta_frac 0.5).
+ * The inputs are copied; the caller keeps ownership.  *out receives the index
+ * (free with katz_index_free).  Errors: KATZ_EINVAL (malformed CSR, bad
+ * options), KATZ_ENOTSYM, KATZ_EDIVERGE (beta * lambda_max >= 1),
+ * KATZ_ENOMEM, KATZ_EDEVICE.
+ */
+int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                     const double* val, const katz_build_opts* opts, katz_index** out);
+
+/*
+ * Katz vectors of nq query nodes (Algorithm 2; Lemma 1 eqs. 5-6).
+ *   q[nq]: host array of node ids in [0, n), original numbering.
+ *   scores: nq * n FP64, query-major: scores[i*n + v] = K[v, q[i]]
+ *     (entry v = q[i] holds K_qq, the weighted closed walks).  Host or
+ *     device pointer (detected); caller-allocated.
+ *   st: nullable, nq entries.
+ *   stream: hipStream_t to run on, or NULL for the null stream.  The call
+ *     returns after the results are complete.
+ * Queries run together as the columns of one batched solve.  Returns KATZ_OK,
+ * or KATZ_ENOCONV if some query missed opts->rel_tol (its stats say which;
+ * its scores are still the best iterate), KATZ_EINVAL, KATZ_EDEVICE,
+ * KATZ_ENOMEM.
+ */
+int katz_query(const katz_index* idx, const int32_t* q, int32_t nq, const katz_query_opts* opts,
+               double* scores, katz_query_stats* st, void* stream);
+
+/*
+ * Top-k predicted links per query (Sec. 3.3; the descending sort of
+ * Algorithm 3): candidates are all nodes except q and its neighbours, ranked
+ * by (Katz score descending, node id ascending).
+ *   ids: nq * k int32 (query-major), padded with -1 when fewer than k
+ *     candidates exist; scores: nq * k FP64 (NaN padding) or NULL.  Host or
+ *     device pointers.  Other arguments as katz_query.
+ */
+int katz_topk_links(const katz_index* idx, const int32_t* q, int32_t nq, int32_t k,
+                    const katz_query_opts* opts, int32_t* ids, double* scores,
+                    katz_query_stats* st, void* stream);
+
+/* Frees host and device memory of the index.  NULL is a no-op. */
+void katz_index_free(katz_index* idx);
+
+/* Sizes and parameters of an index. */
+int katz_index_info(const katz_index* idx, katz_index_info_t* info);
+
+/*
+ * Host copies of the index's reordering (Sec. 3.2 step 3), for inspection:
+ *   perm[n]: new position of original node v (NULL to skip);
+ *   block_ptr[nblocks + 1]: first new position of each M11 block, ending at
+ *   n1 (NULL to skip).  Separator nodes occupy positions [n1, n).
+ */
+int katz_index_partition(const katz_index* idx, int32_t* perm, int32_t* block_ptr);
+
+/*
+ * Host copy of the low-rank factors (eqs. RMatrix, inverseTildeS):
+ *   U[n2 * rank]: Ritz vectors of R, row-major (row = separator position);
+ *   sigma[rank]: their Ritz values, descending.  Either may be NULL.
+ */
+int katz_index_lowrank(const katz_index* idx, double* U, double* sigma);
+
+/* Per-kernel timing of the query path (tracing aid): with profiling on, every
+ * launch of the hot kernels is bracketed by HIP events on the solve stream and
+ * the algorithmic bytes it moves are booked to its kind. */
+typedef struct {
+  char name[32];      /* kernel kind */
+  int64_t launches;   /* timed launches */
+  double total_ms;    /* summed event time */
+  double alg_bytes;   /* summed algorithmic bytes (each operand counted once) */
+} katz_kernel_stat;
+
+/* Turns profiling on (1) or off (0); returns the previous setting. */
+int katz_profile_enable(int on);
+/* Clears the accumulated statistics. */
+void katz_profile_reset(void);
+/* Copies up to max kinds into out; returns the number written. */
+int katz_profile_read(katz_kernel_stat* out, int max);
+
+/* Thread-local message describing the last error on this thread. */
+const char* katz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KATZ_H */

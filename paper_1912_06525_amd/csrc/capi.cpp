@@ -1,0 +1,200 @@
+// C ABI of the Katz library (include/katz.h): argument checks, error codes,
+// thread-local error messages; no exceptions cross the boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "katz.h"
+#include "katz_internal.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const katz::Error& e) {
+    return set_error(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return set_error(KATZ_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_error(KATZ_EINVAL, e.what());
+  }
+}
+
+int check_queries(const katz_index* idx, const int32_t* q, int32_t nq) {
+  if (!idx) return set_error(KATZ_EINVAL, "null index");
+  if (nq < 0) return set_error(KATZ_EINVAL, "nq must be >= 0");
+  if (nq > 0 && !q) return set_error(KATZ_EINVAL, "null query array");
+  for (int32_t i = 0; i < nq; i++)
+    if (q[i] < 0 || q[i] >= idx->host.n) return set_error(KATZ_EINVAL, "query id out of range");
+  if (!idx->dev) return set_error(KATZ_EDEVICE, "index was built without a device (device = -1)");
+  return KATZ_OK;
+}
+
+katz_query_opts resolve(const katz_query_opts* o) {
+  katz_query_opts r;
+  katz_query_opts_default(&r);
+  if (o) r = *o;
+  if (!(r.rel_tol > 0)) r.rel_tol = 1e-6;
+  if (r.max_iter <= 0) r.max_iter = 1000;
+  if (r.max_sweeps <= 0) r.max_sweeps = 6;
+  if (r.check_every <= 0) r.check_every = 8;
+  return r;
+}
+}  // namespace
+
+extern "C" {
+
+void katz_build_opts_default(katz_build_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->beta = 0.0;
+  o->beta_frac = 0.5;
+  o->rank = 32;
+  o->max_block = 64;
+  o->labels = nullptr;
+  o->l_kind = KATZ_L_AUTO;
+  o->precision = KATZ_PREC_FP64;
+  o->seed = 12345;
+  o->device = 0;
+  o->lanczos_steps = 0;
+}
+
+void katz_query_opts_default(katz_query_opts* o) {
+  if (!o) return;
+  o->rel_tol = 1e-6;
+  o->max_iter = 1000;
+  o->method = KATZ_METHOD_LRC;
+  o->max_sweeps = 6;
+  o->check_every = 8;
+  o->force_fallback = 0;
+}
+
+int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                     const double* val, const katz_build_opts* opts, katz_index** out) {
+  return guarded([&]() -> int {
+    if (!out) return set_error(KATZ_EINVAL, "null output pointer");
+    *out = nullptr;
+    katz_build_opts o;
+    katz_build_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.max_block > 256) return set_error(KATZ_EINVAL, "max_block must be <= 256");
+    auto* idx = new katz_index();
+    try {
+      katz::build_host_index(n, nnz, row_ptr, col_idx, val, o, idx->host);
+      idx->device = o.device;
+      if (o.device >= 0) idx->dev = katz::device_upload(idx->host, o.device);
+    } catch (...) {
+      delete idx;
+      throw;
+    }
+    *out = idx;
+    return KATZ_OK;
+  });
+}
+
+int katz_query(const katz_index* idx, const int32_t* q, int32_t nq, const katz_query_opts* opts,
+               double* scores, katz_query_stats* st, void* stream) {
+  return guarded([&]() -> int {
+    int rc = check_queries(idx, q, nq);
+    if (rc) return rc;
+    if (nq == 0) return KATZ_OK;
+    if (!scores) return set_error(KATZ_EINVAL, "null scores buffer");
+    katz::QueryArgs a{};
+    a.q = q; a.nq = nq; a.opts = resolve(opts); a.scores = scores; a.topk = 0;
+    a.st = st; a.stream = stream;
+    rc = katz::device_query(idx->host, idx->dev, a);
+    if (rc == KATZ_ENOCONV) set_error(rc, "some queries did not reach the tolerance (see stats)");
+    return rc;
+  });
+}
+
+int katz_topk_links(const katz_index* idx, const int32_t* q, int32_t nq, int32_t k,
+                    const katz_query_opts* opts, int32_t* ids, double* scores, katz_query_stats* st,
+                    void* stream) {
+  return guarded([&]() -> int {
+    int rc = check_queries(idx, q, nq);
+    if (rc) return rc;
+    if (k < 0) return set_error(KATZ_EINVAL, "k must be >= 0");
+    if (nq == 0 || k == 0) return KATZ_OK;
+    if (!ids) return set_error(KATZ_EINVAL, "null ids buffer");
+    katz::QueryArgs a{};
+    a.q = q; a.nq = nq; a.opts = resolve(opts); a.scores = nullptr; a.topk = k; a.ids = ids;
+    a.topk_scores = scores; a.st = st; a.stream = stream;
+    rc = katz::device_query(idx->host, idx->dev, a);
+    if (rc == KATZ_ENOCONV) set_error(rc, "some queries did not reach the tolerance (see stats)");
+    return rc;
+  });
+}
+
+void katz_index_free(katz_index* idx) {
+  if (!idx) return;
+  try {
+    katz::device_free(idx->dev);
+  } catch (...) {
+  }
+  delete idx;
+}
+
+int katz_index_info(const katz_index* idx, katz_index_info_t* info) {
+  if (!idx || !info) return set_error(KATZ_EINVAL, "null argument");
+  const katz::HostIndex& H = idx->host;
+  std::memset(info, 0, sizeof(*info));
+  info->n = H.n;
+  info->n1 = H.n1;
+  info->n2 = H.n2;
+  info->nnz = H.nnz;
+  info->nblocks = (int32_t)H.blk_start.size() - 1;
+  int32_t mb = 0;
+  for (size_t b = 0; b + 1 < H.blk_start.size(); b++) mb = std::max(mb, H.blk_start[b + 1] - H.blk_start[b]);
+  info->max_block_size = mb;
+  info->rank = H.rank;
+  info->l_kind = H.l_kind;
+  info->precision = H.precision;
+  info->device = idx->dev ? idx->device : -1;
+  info->beta = H.beta;
+  info->lambda_max = H.lambda_max;
+  info->c = H.c;
+  info->sigma_max = H.rank > 0 ? H.sigma[0] : 0.0;
+  info->sigma_next = H.sigma_next;
+  info->factor_bytes = idx->dev ? katz::device_factor_bytes(idx->dev) : (int64_t)H.minv.size() * 8;
+  info->device_bytes = katz::device_bytes(idx->dev);
+  info->build_seconds = H.build_seconds;
+  return KATZ_OK;
+}
+
+int katz_index_partition(const katz_index* idx, int32_t* perm, int32_t* block_ptr) {
+  if (!idx) return set_error(KATZ_EINVAL, "null index");
+  const katz::HostIndex& H = idx->host;
+  if (perm) std::memcpy(perm, H.perm.data(), sizeof(int32_t) * H.perm.size());
+  if (block_ptr) std::memcpy(block_ptr, H.blk_start.data(), sizeof(int32_t) * H.blk_start.size());
+  return KATZ_OK;
+}
+
+int katz_index_lowrank(const katz_index* idx, double* U, double* sigma) {
+  if (!idx) return set_error(KATZ_EINVAL, "null index");
+  const katz::HostIndex& H = idx->host;
+  if (U && !H.U.empty()) std::memcpy(U, H.U.data(), sizeof(double) * H.U.size());
+  if (sigma && !H.sigma.empty()) std::memcpy(sigma, H.sigma.data(), sizeof(double) * H.sigma.size());
+  return KATZ_OK;
+}
+
+int katz_profile_enable(int on) { return katz::profile_enable(on); }
+void katz_profile_reset(void) { katz::profile_reset(); }
+int katz_profile_read(katz_kernel_stat* out, int max) {
+  if (!out || max <= 0) return 0;
+  return katz::profile_read(out, max);
+}
+
+const char* katz_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

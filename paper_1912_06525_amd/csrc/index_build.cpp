@@ -1,0 +1,787 @@
+// Host-side index construction (Algorithm 1; Sec. 3.2 steps 1-4).
+//
+//  1. validate the CSR and compute lambda_max(A) (Lanczos) to fix beta;
+//  2. partition: initial parts (caller labels, or BFS growing), each part cut
+//     into BFS-ordered chunks of at most max_block nodes; a greedy vertex
+//     cover of the cut edges becomes the separator, so the remaining blocks
+//     have no edges between them and M11 is block diagonal (Lemma 1);
+//  3. reorder: blocks contiguous (largest first), separator last;
+//  4. factor every block M_bb = I - beta A_bb = L1 L1^T and store
+//     M_bb^{-1} = L1^{-T} L1^{-1}; factor M22 when L is its Cholesky factor;
+//  5. Lanczos with full reorthogonalisation on R = I - L^{-1} S L^{-T}
+//     (eq. RMatrix; R is only applied, never formed) for the top r pairs.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "katz_internal.h"
+
+namespace katz {
+
+void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+int host_threads() {
+  static int n = [] {
+    unsigned h = std::thread::hardware_concurrency();
+    const char* e = getenv("KATZ_HOST_THREADS");
+    if (e && atoi(e) > 0) return atoi(e);
+    return (int)std::max(1u, std::min(h, 64u));
+  }();
+  return n;
+}
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn, int64_t grain) {
+  if (n <= 0) return;
+  int T = host_threads();
+  int64_t chunks = (n + grain - 1) / grain;
+  if (T <= 1 || chunks <= 1) { fn(0, n); return; }
+  std::atomic<int64_t> next{0};
+  auto work = [&] {
+    for (;;) {
+      int64_t c = next.fetch_add(1);
+      if (c >= chunks) break;
+      int64_t b = c * grain, e = std::min(n, b + grain);
+      fn(b, e);
+    }
+  };
+  int nt = (int)std::min<int64_t>(T, chunks);
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; t++) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
+}
+
+namespace {
+
+// ------------------------------------------------------------ SplitMix64
+struct Rng {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  }
+  double unif() { return ((double)(next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+  double normal() { return std::sqrt(-2.0 * std::log(unif())) * std::cos(6.283185307179586 * unif()); }
+};
+
+double dot(const double* a, const double* b, int64_t n) {
+  int T = host_threads();
+  if (n < 200000 || T == 1) {
+    double s = 0;
+    for (int64_t i = 0; i < n; i++) s += a[i] * b[i];
+    return s;
+  }
+  const int64_t grain = 65536;
+  int64_t chunks = (n + grain - 1) / grain;
+  std::vector<double> part(chunks, 0.0);
+  parallel_for(chunks, [&](int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; c++) {
+      double s = 0;
+      int64_t lo = c * grain, hi = std::min(n, lo + grain);
+      for (int64_t i = lo; i < hi; i++) s += a[i] * b[i];
+      part[c] = s;
+    }
+  }, 1);
+  double s = 0;
+  for (double v : part) s += v;
+  return s;
+}
+
+// ------------------------------------------------ symmetric tridiagonal
+// Eigen-decomposition of the symmetric tridiagonal matrix with diagonal d[0..m)
+// and off-diagonal e[0..m-1) by the implicitly shifted QL iteration with
+// Wilkinson-type shifts.  On return d holds the eigenvalues (unsorted) and
+// z (m x m, row-major, z[row*m + k]) the orthonormal eigenvectors as columns.
+void tridiag_eig(std::vector<double>& d, std::vector<double> e, std::vector<double>& z, int m) {
+  z.assign((size_t)m * m, 0.0);
+  for (int i = 0; i < m; i++) z[(size_t)i * m + i] = 1.0;
+  e.resize(m, 0.0);
+  if (m > 0) e[m - 1] = 0.0;
+  const double eps = 2.220446049250313e-16;
+  for (int l = 0; l < m; l++) {
+    int iter = 0;
+    for (;;) {
+      int mm = l;
+      for (; mm < m - 1; mm++) {
+        double dd = std::fabs(d[mm]) + std::fabs(d[mm + 1]);
+        if (std::fabs(e[mm]) <= eps * dd) break;
+      }
+      if (mm == l) break;
+      if (++iter > 200) fail(KATZ_EINVAL, "tridiagonal eigensolver did not converge");
+      // shift from the trailing 2x2 of the active window's top
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[mm] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = mm - 1;
+      bool deflated = false;
+      for (; i >= l; i--) {
+        double f = s * e[i], b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {  // underflow: split here
+          d[i + 1] -= p;
+          e[mm] = 0.0;
+          deflated = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        for (int k = 0; k < m; k++) {  // accumulate the rotation in z
+          double* zk = &z[(size_t)k * m];
+          double t = zk[i + 1];
+          zk[i + 1] = s * zk[i] + c * t;
+          zk[i] = c * zk[i] - s * t;
+        }
+      }
+      if (deflated) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[mm] = 0.0;
+    }
+  }
+}
+
+// --------------------------------------------------------- dense helpers
+// In-place lower Cholesky of the b x b row-major SPD matrix a (column by
+// column; the rows below the diagonal of a column are independent and run in
+// parallel for large b).
+bool chol_lower(double* a, int b) {
+  const bool par = b > 256;
+  for (int j = 0; j < b; j++) {
+    double s = a[(size_t)j * b + j];
+    const double* aj = &a[(size_t)j * b];
+    for (int k = 0; k < j; k++) s -= aj[k] * aj[k];
+    if (!(s > 0.0)) return false;
+    const double ljj = std::sqrt(s);
+    a[(size_t)j * b + j] = ljj;
+    auto rows = [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; i++) {
+        double* ai = &a[(size_t)i * b];
+        double t = ai[j];
+        for (int k = 0; k < j; k++) t -= ai[k] * aj[k];
+        ai[j] = t / ljj;
+      }
+    };
+    if (par) parallel_for(b - j - 1, [&](int64_t i0, int64_t i1) { rows(j + 1 + i0, j + 1 + i1); }, 64);
+    else rows(j + 1, b);
+  }
+  for (int j = 0; j < b; j++)
+    for (int k = j + 1; k < b; k++) a[(size_t)j * b + k] = 0.0;
+  return true;
+}
+
+// Given the lower factor l (b x b), writes inv = (l l^T)^{-1} (full,
+// symmetric): column j of l^{-1} is stored as row j of w (forward
+// substitution on contiguous rows), then inv[i][j] = <w row i, w row j>.
+void chol_inverse(const double* l, int b, double* inv, std::vector<double>& w) {
+  w.assign((size_t)b * b, 0.0);
+  const int64_t grain = b > 256 ? 16 : b;
+  parallel_for(b, [&](int64_t j0, int64_t j1) {
+    for (int64_t j = j0; j < j1; j++) {
+      double* x = &w[(size_t)j * b];
+      x[j] = 1.0 / l[(size_t)j * b + j];
+      for (int i = (int)j + 1; i < b; i++) {
+        const double* li = &l[(size_t)i * b];
+        double s = 0;
+        for (int k = (int)j; k < i; k++) s += li[k] * x[k];
+        x[i] = -s / li[i];
+      }
+    }
+  }, grain);
+  parallel_for(b, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; i++) {
+      const double* wi = &w[(size_t)i * b];
+      for (int64_t j = 0; j <= i; j++) {
+        const double* wj = &w[(size_t)j * b];
+        double s = 0;
+        for (int k = (int)i; k < b; k++) s += wi[k] * wj[k];
+        inv[(size_t)i * b + j] = s;
+        inv[(size_t)j * b + i] = s;
+      }
+    }
+  }, grain);
+}
+
+// ------------------------------------------------------------ validation
+void validate(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col, const double* val) {
+  if (n <= 0) fail(KATZ_EINVAL, "n must be positive");
+  if (!rp || (nnz > 0 && !col)) fail(KATZ_EINVAL, "null CSR array");
+  if (nnz < 0 || nnz >= INT32_MAX) fail(KATZ_EINVAL, "nnz must be in [0, 2^31-1)");
+  if (rp[0] != 0 || rp[n] != nnz) fail(KATZ_EINVAL, "row_ptr must start at 0 and end at nnz");
+  std::atomic<int> bad{0};
+  std::atomic<int> asym{0};
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e && !bad.load(std::memory_order_relaxed); i++) {
+      int32_t s = rp[i], t = rp[i + 1];
+      if (t < s) { bad = 1; break; }
+      int32_t last = -1;
+      for (int32_t k = s; k < t; k++) {
+        int32_t j = col[k];
+        if (j < 0 || j >= n) { bad = 2; break; }
+        if (j <= last) { bad = 3; break; }
+        if (j == i) { bad = 4; break; }
+        if (val && !(val[k] >= 0.0 && std::isfinite(val[k]))) { bad = 5; break; }
+        last = j;
+        // symmetric partner (j, i) with the same value
+        const int32_t* rb = col + rp[j];
+        const int32_t* re = col + rp[j + 1];
+        const int32_t* f = std::lower_bound(rb, re, (int32_t)i);
+        if (f == re || *f != i || (val && val[f - col] != val[k])) asym = 1;
+      }
+    }
+  }, 2048);
+  switch (bad.load()) {
+    case 1: fail(KATZ_EINVAL, "row_ptr is not non-decreasing");
+    case 2: fail(KATZ_EINVAL, "column index out of range");
+    case 3: fail(KATZ_EINVAL, "columns must be strictly increasing within a row");
+    case 4: fail(KATZ_EINVAL, "diagonal entries (self loops) are not allowed");
+    case 5: fail(KATZ_EINVAL, "values must be finite and nonnegative");
+    default: break;
+  }
+  if (asym) fail(KATZ_ENOTSYM, "adjacency matrix is not symmetric");
+}
+
+// y = A x for the caller's CSR (original order)
+void spmv(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x, double* y) {
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; i++) {
+      double s = 0;
+      if (val)
+        for (int32_t k = rp[i]; k < rp[i + 1]; k++) s += val[k] * x[col[k]];
+      else
+        for (int32_t k = rp[i]; k < rp[i + 1]; k++) s += x[col[k]];
+      y[i] = s;
+    }
+  }, 8192);
+}
+
+// Largest eigenvalue of A by Lanczos without reorthogonalisation (the top Ritz
+// value is unaffected by the loss of orthogonality, which only duplicates
+// converged values).  Stops when the Ritz residual bound is below 1e-13 of the
+// Ritz value.
+double lambda_max(int32_t n, const int32_t* rp, const int32_t* col, const double* val, uint64_t seed) {
+  if (rp[n] == 0) return 0.0;
+  std::vector<double> q(n), qp(n, 0.0), w(n);
+  Rng rng{seed ^ 0x5A5A5A5AULL};
+  for (int32_t i = 0; i < n; i++) q[i] = 0.5 + rng.unif();  // positive start: overlaps the Perron vector
+  double nq = std::sqrt(dot(q.data(), q.data(), n));
+  for (auto& v : q) v /= nq;
+  std::vector<double> al, be;
+  double theta = 0, bprev = 0;
+  const int mmax = std::min<int64_t>(600, n);
+  for (int j = 0; j < mmax; j++) {
+    spmv(n, rp, col, val, q.data(), w.data());
+    double a = dot(q.data(), w.data(), n);
+    parallel_for(n, [&](int64_t b, int64_t e) {
+      for (int64_t i = b; i < e; i++) w[i] -= a * q[i] + bprev * qp[i];
+    });
+    double bj = std::sqrt(dot(w.data(), w.data(), n));
+    al.push_back(a);
+    be.push_back(bj);
+    int m = (int)al.size();
+    if (m % 8 == 0 || bj <= 1e-14 * std::fabs(a) || j == mmax - 1) {
+      std::vector<double> d(al), z;
+      std::vector<double> e(be.begin(), be.end() - 1);
+      tridiag_eig(d, e, z, m);
+      int top = (int)(std::max_element(d.begin(), d.end()) - d.begin());
+      theta = d[top];
+      double resid = bj * std::fabs(z[(size_t)(m - 1) * m + top]);
+      if (resid <= 1e-13 * std::fabs(theta) || bj <= 1e-14 * std::fabs(a)) break;
+    }
+    if (bj == 0.0) break;
+    for (int32_t i = 0; i < n; i++) {
+      double t = w[i] / bj;
+      qp[i] = q[i];
+      q[i] = t;
+    }
+    bprev = bj;
+  }
+  return theta;
+}
+
+// ------------------------------------------------------------- partition
+struct Partition {
+  std::vector<int32_t> perm, iperm, blk_start;
+  int32_t n1 = 0, n2 = 0;
+};
+
+// BFS order of the nodes of `nodes` (a set marked by inset[v] == tag), restarting
+// from the lowest unvisited node; the first BFS of each component starts from
+// a pseudo-peripheral node (the last node reached by a BFS from the seed).
+void bfs_order(const int32_t* rp, const int32_t* col, const std::vector<int32_t>& nodes,
+               std::vector<int32_t>& mark, int32_t tag, std::vector<int32_t>& out,
+               std::vector<int32_t>& queue) {
+  out.clear();
+  // mark[v] == tag: in set, unvisited; mark[v] == tag + 1: visited
+  auto bfs = [&](int32_t s, bool record, std::vector<int32_t>& seen) -> int32_t {
+    queue.clear();
+    queue.push_back(s);
+    seen.push_back(s);
+    mark[s] = tag + 1;
+    size_t h = 0;
+    int32_t last = s;
+    while (h < queue.size()) {
+      int32_t u = queue[h++];
+      last = u;
+      if (record) out.push_back(u);
+      for (int32_t k = rp[u]; k < rp[u + 1]; k++) {
+        int32_t v = col[k];
+        if (mark[v] == tag) { mark[v] = tag + 1; queue.push_back(v); seen.push_back(v); }
+      }
+    }
+    return last;
+  };
+  std::vector<int32_t> seen;
+  for (int32_t s : nodes) {
+    if (mark[s] != tag) continue;
+    seen.clear();
+    int32_t far = bfs(s, false, seen);
+    for (int32_t v : seen) mark[v] = tag;  // unvisit the component
+    seen.clear();
+    bfs(far, true, seen);
+  }
+}
+
+Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const int32_t* labels,
+                         int32_t max_block) {
+  // (a) initial parts
+  std::vector<int32_t> part(n);
+  int32_t P = 0;
+  if (labels) {
+    std::vector<int32_t> lab(labels, labels + n);
+    std::vector<int32_t> u(lab);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    for (int32_t v = 0; v < n; v++) part[v] = (int32_t)(std::lower_bound(u.begin(), u.end(), lab[v]) - u.begin());
+    P = (int32_t)u.size();
+  } else {
+    std::fill(part.begin(), part.end(), 0);
+    P = 1;
+  }
+  // (b) BFS chunking of every part into pieces of <= max_block nodes
+  std::vector<std::vector<int32_t>> members(P);
+  for (int32_t v = 0; v < n; v++) members[part[v]].push_back(v);
+  std::vector<int32_t> mark(n, -1), order, queue;
+  std::vector<int32_t> piece(n, -1);
+  int32_t npiece = 0;
+  for (int32_t p = 0; p < P; p++) {
+    auto& mem = members[p];
+    for (int32_t v : mem) mark[v] = 2 * p;
+    bfs_order(rp, col, mem, mark, 2 * p, order, queue);
+    for (size_t k = 0; k < order.size(); k++) {
+      if (k % (size_t)max_block == 0) npiece++;
+      piece[order[k]] = npiece - 1;
+    }
+    std::vector<int32_t>().swap(mem);
+  }
+  // (c) greedy vertex cover of the cut edges (largest remaining cut degree first)
+  std::vector<int32_t> cutdeg(n, 0);
+  int32_t dmax = 0;
+  for (int32_t v = 0; v < n; v++) {
+    int32_t c = 0;
+    for (int32_t k = rp[v]; k < rp[v + 1]; k++) c += piece[col[k]] != piece[v];
+    cutdeg[v] = c;
+    dmax = std::max(dmax, c);
+  }
+  std::vector<std::vector<int32_t>> bucket(dmax + 1);
+  for (int32_t v = n - 1; v >= 0; v--)
+    if (cutdeg[v] > 0) bucket[cutdeg[v]].push_back(v);
+  std::vector<char> insep(n, 0);
+  std::vector<int32_t> sep_order;
+  for (int32_t d = dmax; d > 0;) {
+    if (bucket[d].empty()) { d--; continue; }
+    int32_t v = bucket[d].back();
+    bucket[d].pop_back();
+    if (insep[v] || cutdeg[v] != d) continue;  // stale entry
+    insep[v] = 1;
+    sep_order.push_back(v);
+    cutdeg[v] = 0;
+    for (int32_t k = rp[v]; k < rp[v + 1]; k++) {
+      int32_t u = col[k];
+      if (!insep[u] && piece[u] != piece[v]) {
+        cutdeg[u]--;
+        if (cutdeg[u] > 0) bucket[cutdeg[u]].push_back(u);
+      }
+    }
+  }
+  std::vector<std::vector<int32_t>>().swap(bucket);
+  // (d) minimality: a separator node whose non-separator neighbours all lie in
+  // one piece (with room) joins that piece; one with none becomes a singleton.
+  std::vector<int32_t> psize(npiece, 0);
+  for (int32_t v = 0; v < n; v++) if (!insep[v]) psize[piece[v]]++;
+  for (auto it = sep_order.rbegin(); it != sep_order.rend(); ++it) {
+    int32_t v = *it;
+    int32_t target = -1;
+    bool ok = true;
+    for (int32_t k = rp[v]; k < rp[v + 1] && ok; k++) {
+      int32_t u = col[k];
+      if (insep[u]) continue;
+      if (target < 0) target = piece[u];
+      else if (piece[u] != target) ok = false;
+    }
+    if (!ok) continue;
+    if (target < 0) {
+      piece[v] = npiece++;
+      psize.push_back(1);
+      insep[v] = 0;
+    } else if (psize[target] < max_block) {
+      piece[v] = target;
+      psize[target]++;
+      insep[v] = 0;
+    }
+  }
+  // (e) blocks = connected components of the graph without the separator;
+  // each lies inside one piece, so it has at most max_block nodes.
+  std::vector<int32_t> comp(n, -1);
+  std::vector<std::vector<int32_t>> blocks;
+  for (int32_t s = 0; s < n; s++) {
+    if (insep[s] || comp[s] >= 0) continue;
+    int32_t id = (int32_t)blocks.size();
+    blocks.emplace_back();
+    auto& b = blocks.back();
+    b.push_back(s);
+    comp[s] = id;
+    for (size_t h = 0; h < b.size(); h++) {
+      int32_t u = b[h];
+      for (int32_t k = rp[u]; k < rp[u + 1]; k++) {
+        int32_t v = col[k];
+        if (!insep[v] && comp[v] < 0) { comp[v] = id; b.push_back(v); }
+      }
+    }
+  }
+  // largest blocks first (the block kernel then sees a descending work list)
+  std::vector<int32_t> bo(blocks.size());
+  std::iota(bo.begin(), bo.end(), 0);
+  std::stable_sort(bo.begin(), bo.end(), [&](int32_t a, int32_t b) { return blocks[a].size() > blocks[b].size(); });
+  Partition R;
+  R.perm.assign(n, -1);
+  R.iperm.reserve(n);
+  R.blk_start.push_back(0);
+  std::vector<int32_t> blkpos(blocks.size());
+  for (size_t t = 0; t < bo.size(); t++) {
+    blkpos[bo[t]] = (int32_t)t;
+    for (int32_t v : blocks[bo[t]]) { R.perm[v] = (int32_t)R.iperm.size(); R.iperm.push_back(v); }
+    R.blk_start.push_back((int32_t)R.iperm.size());
+  }
+  R.n1 = (int32_t)R.iperm.size();
+  // separator nodes by degree, largest first, then by id: the hubs, which most
+  // adjacency entries point to, share few cache lines of every gathered panel
+  std::vector<std::pair<int64_t, int32_t>> sk;
+  for (int32_t v = 0; v < n; v++)
+    if (insep[v]) sk.emplace_back(-(int64_t)(rp[v + 1] - rp[v]), v);
+  std::sort(sk.begin(), sk.end());
+  (void)blkpos;
+  for (auto& kv : sk) { R.perm[kv.second] = (int32_t)R.iperm.size(); R.iperm.push_back(kv.second); }
+  R.n2 = n - R.n1;
+  return R;
+}
+
+// ----------------------------------------------------- separator operators
+// Applies S x = M22 x - M12^T M11^{-1} M12 x on the host (n2-vectors), using
+// the permuted CSR: with u = M11^{-1} (beta A12 x),
+//   S x = x - beta (A21 u + A22 x).
+struct SchurOp {
+  const HostIndex& H;
+  std::vector<double> t1;  // n1 scratch
+  explicit SchurOp(const HostIndex& h) : H(h), t1(h.n1) {}
+  void apply(const double* x, double* y) {
+    const int32_t n1 = H.n1, n = H.n;
+    const double beta = H.beta;
+    const bool w = H.weighted;
+    // t1 = beta * A12 x, block by block, then t1 <- M11^{-1} t1
+    int32_t nb = (int32_t)H.blk_start.size() - 1;
+    parallel_for(nb, [&](int64_t b0, int64_t b1) {
+      std::vector<double> tmp;
+      for (int64_t b = b0; b < b1; b++) {
+        int32_t s = H.blk_start[b], e = H.blk_start[b + 1], sz = e - s;
+        tmp.assign(sz, 0.0);
+        for (int32_t i = s; i < e; i++) {
+          double acc = 0;
+          for (int32_t k = H.split[i]; k < H.rp[i + 1]; k++) acc += (w ? H.val[k] : 1.0) * x[H.col[k] - n1];
+          tmp[i - s] = beta * acc;
+        }
+        const double* mi = &H.minv[H.blk_off[b]];
+        for (int32_t i = 0; i < sz; i++) {
+          double acc = 0;
+          for (int32_t k = 0; k < sz; k++) acc += mi[(size_t)i * sz + k] * tmp[k];
+          t1[s + i] = acc;
+        }
+      }
+    }, 64);
+    parallel_for(n - n1, [&](int64_t r0, int64_t r1) {
+      for (int64_t r = r0; r < r1; r++) {
+        int32_t i = n1 + (int32_t)r;
+        double acc = 0;
+        for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) {
+          int32_t j = H.col[k];
+          double xv = j < n1 ? t1[j] : x[j - n1];
+          acc += (w ? H.val[k] : 1.0) * xv;
+        }
+        y[r] = x[r] - beta * acc;
+      }
+    }, 4096);
+  }
+};
+
+// lower-triangular dense solves with L (n2 x n2 row-major)
+void lsolve(const std::vector<double>& L, int m, double* x) {  // x <- L^{-1} x
+  for (int i = 0; i < m; i++) {
+    double s = x[i];
+    const double* li = &L[(size_t)i * m];
+    for (int k = 0; k < i; k++) s -= li[k] * x[k];
+    x[i] = s / li[i];
+  }
+}
+void ltsolve(const std::vector<double>& L, int m, double* x) {  // x <- L^{-T} x
+  for (int i = m - 1; i >= 0; i--) {
+    double s = x[i];
+    for (int k = i + 1; k < m; k++) s -= L[(size_t)k * m + i] * x[k];
+    x[i] = s / L[(size_t)i * m + i];
+  }
+}
+
+// Top-r eigenpairs of R = I - L^{-1} S L^{-T} by Lanczos with full
+// reorthogonalisation (Algorithm 1, Lanczos step; R as a matrix-vector
+// product only).  An exhausted Krylov space restarts from a fresh random
+// vector orthogonal to the basis, so m = n2 steps give the whole spectrum.
+void lanczos_R(HostIndex& H, int32_t r, int32_t steps, uint64_t seed) {
+  const int32_t m2 = H.n2;
+  r = std::min(r, m2);
+  H.rank = r;
+  if (r <= 0) return;
+  int32_t m = steps > 0 ? steps : std::max(2 * r, r + 20);
+  m = std::min(m, m2);
+  SchurOp S(H);
+  const bool chol = H.l_kind == KATZ_L_CHOL;
+  std::vector<double> Q((size_t)m * m2);
+  std::vector<double> w(m2), tmp(m2);
+  std::vector<double> al, be;
+  Rng rng{seed};
+  auto random_start = [&](double* q, int32_t j) {
+    for (int32_t i = 0; i < m2; i++) q[i] = rng.normal();
+    for (int pass = 0; pass < 2; pass++)
+      for (int32_t k = 0; k < j; k++) {
+        const double* qk = &Q[(size_t)k * m2];
+        double h = dot(qk, q, m2);
+        for (int32_t i = 0; i < m2; i++) q[i] -= h * qk[i];
+      }
+    double nn = std::sqrt(dot(q, q, m2));
+    for (int32_t i = 0; i < m2; i++) q[i] /= nn;
+  };
+  random_start(&Q[0], 0);
+  auto applyR = [&](const double* x, double* y) {
+    // y = x - L^{-1} S L^{-T} x
+    std::copy(x, x + m2, tmp.begin());
+    if (chol) ltsolve(H.lchol, m2, tmp.data());
+    S.apply(tmp.data(), y);
+    if (chol) lsolve(H.lchol, m2, y);
+    for (int32_t i = 0; i < m2; i++) y[i] = x[i] - y[i];
+  };
+  double tnorm = 0;
+  for (int32_t j = 0; j < m; j++) {
+    double* qj = &Q[(size_t)j * m2];
+    applyR(qj, w.data());
+    double a = dot(qj, w.data(), m2);
+    al.push_back(a);
+    tnorm = std::max(tnorm, std::fabs(a));
+    // full reorthogonalisation, two classical Gram-Schmidt passes
+    for (int pass = 0; pass < 2; pass++) {
+      std::vector<double> h(j + 1);
+      parallel_for(j + 1, [&](int64_t k0, int64_t k1) {
+        for (int64_t k = k0; k < k1; k++) {
+          const double* qk = &Q[(size_t)k * m2];
+          double s = 0;
+          for (int32_t i = 0; i < m2; i++) s += qk[i] * w[i];
+          h[k] = s;
+        }
+      }, 1);
+      parallel_for(m2, [&](int64_t i0, int64_t i1) {
+        for (int32_t k = 0; k <= j; k++) {
+          const double* qk = &Q[(size_t)k * m2];
+          double hk = h[k];
+          for (int64_t i = i0; i < i1; i++) w[i] -= hk * qk[i];
+        }
+      }, 16384);
+    }
+    if (j + 1 == m) {
+      be.push_back(std::sqrt(dot(w.data(), w.data(), m2)));
+      break;
+    }
+    double b = std::sqrt(dot(w.data(), w.data(), m2));
+    double* qn = &Q[(size_t)(j + 1) * m2];
+    if (b <= 1e-12 * std::max(tnorm, 1e-300)) {
+      be.push_back(0.0);  // invariant subspace: T decouples, restart
+      random_start(qn, j + 1);
+    } else {
+      be.push_back(b);
+      for (int32_t i = 0; i < m2; i++) qn[i] = w[i] / b;
+    }
+    tnorm = std::max(tnorm, b);
+  }
+  int32_t mm = (int32_t)al.size();
+  std::vector<double> d(al), z;
+  std::vector<double> e(be.begin(), be.begin() + (mm - 1));
+  tridiag_eig(d, e, z, mm);
+  std::vector<int32_t> idx(mm);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return d[a] > d[b]; });
+  H.sigma.resize(r);
+  H.D.resize(r);
+  H.U.assign((size_t)m2 * r, 0.0);
+  for (int32_t t = 0; t < r; t++) {
+    int32_t col = idx[t];
+    double s = d[col];
+    if (s >= 1.0 - 1e-12) s = 1.0 - 1e-12;  // R < I exactly since S is SPD
+    H.sigma[t] = s;
+    H.D[t] = s / (1.0 - s);
+  }
+  H.sigma_next = mm > r ? d[idx[r]] : 0.0;
+  // Ritz vectors u_t = Q^T y_t, stored row-major n2 x r
+  parallel_for(m2, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; i++)
+      for (int32_t t = 0; t < r; t++) {
+        int32_t col = idx[t];
+        double s = 0;
+        for (int32_t k = 0; k < mm; k++) s += Q[(size_t)k * m2 + i] * z[(size_t)k * mm + col];
+        H.U[(size_t)i * r + t] = s;
+      }
+  }, 4096);
+  H.lanczos_steps = mm;
+  // V = L^{-T} U
+  H.V = H.U;
+  if (chol) {
+    std::vector<double> colv(m2);
+    for (int32_t t = 0; t < r; t++) {
+      for (int32_t i = 0; i < m2; i++) colv[i] = H.U[(size_t)i * r + t];
+      ltsolve(H.lchol, m2, colv.data());
+      for (int32_t i = 0; i < m2; i++) H.V[(size_t)i * r + t] = colv[i];
+    }
+  }
+}
+
+}  // namespace
+
+void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                      const double* val, const katz_build_opts& o, HostIndex& H) {
+  auto t0 = std::chrono::steady_clock::now();
+  validate(n, nnz, row_ptr, col, val);
+  if (o.rank < 0) fail(KATZ_EINVAL, "rank must be >= 0");
+  if (o.max_block < 0) fail(KATZ_EINVAL, "max_block must be >= 0");
+  if (o.l_kind < KATZ_L_AUTO || o.l_kind > KATZ_L_IDENTITY) fail(KATZ_EINVAL, "bad l_kind");
+  if (o.precision != KATZ_PREC_FP64 && o.precision != KATZ_PREC_MIXED) fail(KATZ_EINVAL, "bad precision");
+  H.n = n;
+  H.nnz = nnz;
+  H.weighted = val != nullptr;
+  H.precision = o.precision;
+  H.lambda_max = lambda_max(n, row_ptr, col, val, o.seed);
+  if (o.beta > 0) {
+    H.beta = o.beta;
+  } else {
+    if (!(o.beta_frac > 0)) fail(KATZ_EINVAL, "give beta > 0 or beta_frac > 0");
+    if (H.lambda_max <= 0) fail(KATZ_EINVAL, "graph has no edges: beta_frac needs lambda_max > 0");
+    H.beta = o.beta_frac / H.lambda_max;
+  }
+  H.c = H.beta * H.lambda_max;
+  if (!(H.c < 1.0)) fail(KATZ_EDIVERGE, "beta * lambda_max(A) >= 1: Katz series diverges and I - beta A is not positive definite");
+  if (o.labels)
+    for (int32_t v = 0; v < n; v++)
+      if (o.labels[v] < 0) fail(KATZ_EINVAL, "labels must be >= 0");
+
+  int32_t max_block = o.max_block > 0 ? o.max_block : 64;
+  Partition P = make_partition(n, row_ptr, col, o.labels, max_block);
+  H.perm = std::move(P.perm);
+  H.iperm = std::move(P.iperm);
+  H.blk_start = std::move(P.blk_start);
+  H.n1 = P.n1;
+  H.n2 = P.n2;
+
+  // permuted CSR with sorted rows and the separator split
+  H.rp.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; i++) {
+    int32_t v = H.iperm[i];
+    H.rp[i + 1] = H.rp[i] + (row_ptr[v + 1] - row_ptr[v]);
+  }
+  H.col.resize(nnz);
+  H.split.resize(n);
+  if (val) H.val.resize(nnz);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    std::vector<std::pair<int32_t, double>> tmp;
+    for (int64_t i = b; i < e; i++) {
+      int32_t v = H.iperm[i];
+      tmp.clear();
+      for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; k++) tmp.emplace_back(H.perm[col[k]], val ? val[k] : 1.0);
+      std::sort(tmp.begin(), tmp.end());
+      int32_t o2 = H.rp[i];
+      int32_t sp = H.rp[i + 1];
+      for (size_t k = 0; k < tmp.size(); k++) {
+        H.col[o2 + k] = tmp[k].first;
+        if (val) H.val[o2 + k] = tmp[k].second;
+        if (tmp[k].first >= H.n1 && sp == H.rp[i + 1]) sp = o2 + (int32_t)k;
+      }
+      H.split[i] = sp;
+    }
+  }, 4096);
+
+  // M11 block inverses
+  int32_t nb = (int32_t)H.blk_start.size() - 1;
+  H.blk_off.assign(nb + 1, 0);
+  for (int32_t b = 0; b < nb; b++) {
+    int64_t sz = H.blk_start[b + 1] - H.blk_start[b];
+    H.blk_off[b + 1] = H.blk_off[b] + sz * sz;
+  }
+  H.minv.assign(H.blk_off[nb], 0.0);
+  std::atomic<int> notpd{0};
+  parallel_for(nb, [&](int64_t b0, int64_t b1) {
+    std::vector<double> a, w;
+    for (int64_t b = b0; b < b1; b++) {
+      int32_t s = H.blk_start[b], sz = H.blk_start[b + 1] - s;
+      a.assign((size_t)sz * sz, 0.0);
+      for (int32_t i = 0; i < sz; i++) {
+        a[(size_t)i * sz + i] = 1.0;
+        for (int32_t k = H.rp[s + i]; k < H.split[s + i]; k++) {
+          int32_t j = H.col[k] - s;  // within the block by construction
+          a[(size_t)i * sz + j] -= H.beta * (H.weighted ? H.val[k] : 1.0);
+        }
+      }
+      if (!chol_lower(a.data(), sz)) { notpd = 1; continue; }
+      chol_inverse(a.data(), sz, &H.minv[H.blk_off[b]], w);
+    }
+  }, 16);
+  if (notpd) fail(KATZ_EDIVERGE, "an M11 block is not positive definite (beta too large)");
+
+  // separator factor
+  int32_t lk = o.l_kind;
+  if (lk == KATZ_L_AUTO) lk = (H.n2 > 0 && H.n2 <= 1024) ? KATZ_L_CHOL : KATZ_L_IDENTITY;
+  if (lk == KATZ_L_CHOL && H.n2 > 4096) fail(KATZ_EINVAL, "l_kind CHOL needs a separator of at most 4096 nodes");
+  H.l_kind = lk;
+  if (lk == KATZ_L_CHOL && H.n2 > 0) {
+    const int32_t m2 = H.n2, n1 = H.n1;
+    H.lchol.assign((size_t)m2 * m2, 0.0);
+    for (int32_t r = 0; r < m2; r++) {
+      H.lchol[(size_t)r * m2 + r] = 1.0;
+      int32_t i = n1 + r;
+      for (int32_t k = H.split[i]; k < H.rp[i + 1]; k++)
+        H.lchol[(size_t)r * m2 + (H.col[k] - n1)] -= H.beta * (H.weighted ? H.val[k] : 1.0);
+    }
+    if (!chol_lower(H.lchol.data(), m2)) fail(KATZ_EDIVERGE, "M22 is not positive definite (beta too large)");
+    H.ginv.assign((size_t)m2 * m2, 0.0);
+    std::vector<double> w;
+    chol_inverse(H.lchol.data(), m2, H.ginv.data(), w);
+  }
+  lanczos_R(H, std::min(o.rank, H.n2), o.lanczos_steps, o.seed);
+  H.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace katz

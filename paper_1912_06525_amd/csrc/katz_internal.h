@@ -1,0 +1,88 @@
+// Internal structures shared by the host index builder, the HIP solver and
+// the C ABI.  Not part of the public interface.
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "katz.h"
+
+namespace katz {
+
+// Error carrying a katz_status code.
+struct Error {
+  int code;
+  std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+
+// parallel_for over [0, n) in contiguous chunks on the host's cores.
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn, int64_t grain = 4096);
+int host_threads();
+
+// ------------------------------------------------------------ host index
+struct HostIndex {
+  int32_t n = 0, n1 = 0, n2 = 0;
+  int64_t nnz = 0;
+  double beta = 0, lambda_max = 0, c = 0;
+  bool weighted = false;
+  std::vector<int32_t> perm;   // perm[v]  = new position of original node v
+  std::vector<int32_t> iperm;  // iperm[i] = original node at new position i
+  // adjacency in the new order: rows sorted, split[i] = first entry of row i
+  // whose column is a separator position (>= n1)
+  std::vector<int32_t> rp, col, split;
+  std::vector<double> val;
+  // M11 blocks: block b covers new positions [blk_start[b], blk_start[b+1]);
+  // its inverse (I - beta A_bb)^{-1} is stored row-major at minv[blk_off[b]]
+  std::vector<int32_t> blk_start;
+  std::vector<int64_t> blk_off;
+  std::vector<double> minv;
+  // separator: L L^T = M22 (CHOL) or L = I (IDENTITY)
+  int32_t l_kind = KATZ_L_IDENTITY;
+  std::vector<double> ginv;    // n2 x n2 M22^{-1} (CHOL only)
+  std::vector<double> lchol;   // n2 x n2 lower factor of M22 (CHOL only)
+  // rank-r preconditioner: V = L^{-T} U (row-major n2 x r), D = s/(1-s)
+  int32_t rank = 0;
+  std::vector<double> U, V, sigma, D;
+  double sigma_next = 0;
+  int32_t lanczos_steps = 0;
+  int32_t precision = KATZ_PREC_FP64;
+  double build_seconds = 0;
+};
+
+void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                      const double* val, const katz_build_opts& o, HostIndex& H);
+
+// ------------------------------------------------------- device index
+struct DeviceIndex;            // defined in the HIP solver
+DeviceIndex* device_upload(const HostIndex& H, int device);
+void device_free(DeviceIndex* D);
+int64_t device_bytes(const DeviceIndex* D);
+int64_t device_factor_bytes(const DeviceIndex* D);
+
+struct QueryArgs {
+  const int32_t* q;
+  int32_t nq;
+  katz_query_opts opts;
+  double* scores;          // nq*n or NULL
+  int32_t topk;            // 0: no top-K
+  int32_t* ids;            // nq*topk
+  double* topk_scores;     // nq*topk or NULL
+  katz_query_stats* st;
+  void* stream;
+};
+int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& a);
+int profile_enable(int on);
+void profile_reset();
+int profile_read(katz_kernel_stat* out, int max);
+
+}  // namespace katz
+
+struct katz_index {
+  katz::HostIndex host;
+  katz::DeviceIndex* dev = nullptr;
+  int device = -1;
+};

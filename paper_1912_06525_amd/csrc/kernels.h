@@ -1,0 +1,80 @@
+// Device kernels of the query path (gfx950, wave64).  Included by solver.hip
+// only.  All panels are node-major: an m x B panel stores the B values of one
+// node contiguously (element (i, j) at [i * B + j]), so one adjacency entry
+// gathers one contiguous B-wide row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace katz {
+namespace dev {
+
+constexpr int WG = 256;   // threads per workgroup (4 wave64s)
+constexpr int MAXC = 8;   // column accumulators per lane in the SpMM (B <= 8 * CW)
+
+// Per-column solver state in device memory (B entries each).
+struct ColState {
+  double* rz;      // <r, z> (<r, r> for plain CG)
+  double* pq;      // <p, S p> or <p, M p>
+  double* alpha;   // step length
+  double* bcg;     // direction coefficient
+  double* rr;      // <r, r> of the recurrence residual
+  double* thr;     // stop when rr <= thr
+  int* active;     // 1 while the column iterates
+  int* status;     // 0 ok, 1 breakdown (<p, q> <= 0 or not finite), 2 iteration cap
+  int* iters;      // iterations taken in this solve
+  int* n_active;   // number of active columns (scalar)
+  const int* mask; // columns taking part in this solve (1) or not (0)
+  int max_iter;
+};
+
+// -------------------------------------------------------------- reduction
+// Recounts the active columns (one thread) after an epilogue changed them.
+__device__ inline void recount_active(const ColState& cs, int B) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int j = 0; j < B; j++) c += cs.active[j];
+    *cs.n_active = c;
+  }
+}
+
+__device__ inline bool finite_pos(double x) { return x > 0.0 && x < 1.0e308; }
+
+// Last-workgroup reduction: sums partials[w * nv + v] over w < nwg for every
+// v < nv with all threads (lanes over v, then over w; fixed tree order, so the
+// result is deterministic) and calls f(v, sum) once per v.
+template <typename F>
+__device__ inline void final_reduce(const double* partials, int nwg, int nv, F&& f) {
+  __shared__ double red[WG];
+  int VC = 1;
+  while (VC < nv && VC < WG) VC <<= 1;
+  const int WR = WG / VC;
+  const int tid = threadIdx.x, vl = tid % VC, wl = tid / VC;
+  for (int v0 = 0; v0 < nv; v0 += VC) {
+    const int v = v0 + vl;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (v < nv) {
+      int w = wl;
+      for (; w + 3 * WR < nwg; w += 4 * WR) {
+        s0 += partials[(int64_t)w * nv + v];
+        s1 += partials[(int64_t)(w + WR) * nv + v];
+        s2 += partials[(int64_t)(w + 2 * WR) * nv + v];
+        s3 += partials[(int64_t)(w + 3 * WR) * nv + v];
+      }
+      for (; w < nwg; w += WR) s0 += partials[(int64_t)w * nv + v];
+    }
+    red[tid] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    for (int off = WR / 2; off > 0; off >>= 1) {
+      if (wl < off) red[tid] += red[tid + off * VC];
+      __syncthreads();
+    }
+    if (wl == 0 && v < nv) f(v, red[tid]);
+    __syncthreads();
+  }
+}
+
+}  // namespace dev
+}  // namespace katz

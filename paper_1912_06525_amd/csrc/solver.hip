@@ -1,0 +1,1430 @@
+// Query path on the GPU: device index, kernels and the solve loops.
+//
+// Per query batch (B columns, node-major panels, permuted node order):
+//   a1  b = beta A e_q                           (k_rhs_scatter)
+//   a2  t = M11^{-1} b1, f = b2 - M12^T t        (k_m11_apply, k_spmm)
+//   a3  PCG on S k2 = f with S~^{-1}             (k_m11_apply + k_spmm = S p,
+//                                                 k_vt + k_lowrank = S~^{-1} r,
+//                                                 k_update_r / k_update_p)
+//   a4  k1 = M11^{-1} (b1 - M12 k2)              (k_m11_apply)
+//   a6  true residual b - M k in FP64, refine    (k_spmm, k_axpy_mask)
+//   a5  unpermute to query-major output          (k_unpermute)
+//   a8  plain CG on M: k_spmm + k_update_r + k_update_p
+// M12 = -beta A12, M22 = I - beta A22 and M11 = I - beta A11 are applied from
+// one permuted CSR of A whose rows carry a split between block columns and
+// separator columns.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <atomic>
+#include <memory>
+#include <mutex>
+
+#include "katz_internal.h"
+#include "kernels.h"
+
+#define HIPCHECK(x)                                                                     \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess) fail(KATZ_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace katz {
+using namespace dev;
+
+enum Ep { EP_NONE = 0, EP_PQ = 1, EP_RES = 2, EP_RR_INIT = 3, EP_RR = 4, EP_RZ_INIT = 5, EP_RZ = 6,
+          EP_RR_CG = 7, EP_NORM = 8, EP_VT = 9 };
+
+// ==================================================================== kernels
+// Fill a buffer with a value.
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// a1: scatter b[:, j] = beta * A[:, q_j] (rows of the permuted CSR are the
+// columns of A by symmetry).  The panel was zero-filled before.
+template <typename T>
+__global__ void k_rhs_scatter(const int32_t* qpos, int B, const int32_t* rp, const int32_t* col,
+                              const double* val, double beta, T* b) {
+  int j = blockIdx.x;
+  if (j >= B) return;
+  int32_t r = qpos[j];
+  for (int32_t k = rp[r] + threadIdx.x; k < rp[r + 1]; k += blockDim.x)
+    b[(int64_t)col[k] * B + j] = (T)(beta * (val ? val[k] : 1.0));
+}
+
+// ------------------------------------------------------------------- SpMM
+// y[i] = cv v[i] + cw w[i] + ca (A_<split x)[i] + cb (A_>=split x)[i] for the
+// rows [row0, row1) of the permuted CSR; x is a full n-row panel, v, w, y are
+// row-aligned to row0.  Short rows: teams of TS lanes per row, CW of them
+// across columns and TS/CW across the row's entries (partials combined by
+// cross-lane shuffles).  Rows longer than long_thr (hubs) get a whole
+// workgroup each (the first n_long workgroups).  Optional per-column dot
+// <d, y> (d = dotv or y) with a last-workgroup epilogue.
+template <typename T>
+struct SpmmArgs {
+  int row0, row1, rows_per_wg;
+  const int32_t* rp;
+  const int32_t* col;
+  const int32_t* split;
+  const double* val;
+  const T* x;
+  T ca, cb;
+  int parts;  // bit 0: entries left of the split, bit 1: right of it
+  const T* v;
+  T cv;
+  const T* w;
+  T cw;
+  T* y;
+  int B;
+  int ep;
+  const T* dotv;
+  double* partials;
+  double* out;  // EP_RES destination
+  ColState cs;
+  const int* n_active;       // early exit when *n_active == 0 (NULL: never)
+  const int32_t* long_rows;  // rows with more than long_thr entries, ascending
+  int n_long, long_thr;
+};
+
+// Accumulates lane (nz, cl)'s share of row i: entries kb+nz, kb+nz+NZ, ...
+// (four entries in flight per step).
+// Column groups per lane: B <= CW whenever CW < 64, so only the 64-wide
+// layout carries several column accumulators.
+template <int CW>
+struct ncm {
+  static constexpr int value = CW == 64 ? MAXC : 1;
+};
+
+template <typename T, int CW, int NZ>
+__device__ inline void row_gather(const SpmmArgs<T>& a, int i, int nz, int cl, int NC, T* acc) {
+  const int32_t s = a.rp[i], e = a.rp[i + 1], sp = a.split[i];
+  const int32_t kb = (a.parts & 1) ? s : sp;
+  const int32_t ke = (a.parts & 2) ? e : sp;
+  const int B = a.B;
+  constexpr int NCM = ncm<CW>::value;
+  int32_t k = kb + nz;
+  for (; k + 3 * NZ < ke; k += 4 * NZ) {
+    int32_t c[4];
+    T cf[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int32_t kk = k + u * NZ;
+      c[u] = a.col[kk];
+      cf[u] = (kk < sp) ? a.ca : a.cb;
+      if (a.val) cf[u] *= (T)a.val[kk];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const T* xr = a.x + (int64_t)c[u] * B;
+#pragma unroll
+      for (int cc = 0; cc < NCM; cc++) {
+        const int j = cl + CW * cc;
+        if (cc < NC && j < B) acc[cc] += cf[u] * xr[j];
+      }
+    }
+  }
+  for (; k < ke; k += NZ) {
+    const int32_t cidx = a.col[k];
+    T coef = (k < sp) ? a.ca : a.cb;
+    if (a.val) coef *= (T)a.val[k];
+    const T* xr = a.x + (int64_t)cidx * B;
+#pragma unroll
+    for (int cc = 0; cc < NCM; cc++) {
+      const int j = cl + CW * cc;
+      if (cc < NC && j < B) acc[cc] += coef * xr[j];
+    }
+  }
+}
+
+// Finishes row i for the lane owning column group cl: adds the row-aligned
+// panels, stores y and accumulates the dot.
+template <typename T, int CW>
+__device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, const T* acc, double* dacc) {
+  const int B = a.B;
+  constexpr int NCM = ncm<CW>::value;
+  const int64_t ro = (int64_t)(i - a.row0) * B;
+#pragma unroll
+  for (int cc = 0; cc < NCM; cc++) {
+    const int j = cl + CW * cc;
+    if (cc < NC && j < B) {
+      T yv = acc[cc];
+      if (a.v) yv += a.cv * a.v[ro + j];
+      if (a.w) yv += a.cw * a.w[ro + j];
+      a.y[ro + j] = yv;
+      if (a.ep != EP_NONE) {
+        double d = a.dotv ? (double)a.dotv[ro + j] : (double)yv;
+        dacc[cc] += d * (double)yv;
+      }
+    }
+  }
+}
+
+template <typename T, int TS, int CW>
+__global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
+  if (a.n_active && *a.n_active == 0) return;
+  constexpr int NZ = TS / CW;
+  constexpr int TEAMS = WG / TS;
+  constexpr int NZW = WG / CW;  // entry lanes of the long-row path
+  constexpr int NCM = ncm<CW>::value;
+  extern __shared__ double sh[];
+  const int tid = threadIdx.x;
+  const int B = a.B;
+  const int NC = (B + CW - 1) / CW;
+  double dacc[NCM];
+#pragma unroll
+  for (int c = 0; c < NCM; c++) dacc[c] = 0.0;
+  bool owner;      // this lane holds final dot values
+  int slot;        // its row of the per-workgroup dot table
+  int cl_own;
+  if ((int)blockIdx.x < a.n_long) {
+    // ---- one hub row, whole workgroup
+    const int cl = tid % CW, nz = tid / CW;
+    const int i = a.long_rows[blockIdx.x];
+    T acc[NCM];
+#pragma unroll
+    for (int c = 0; c < NCM; c++) acc[c] = (T)0;
+    row_gather<T, CW, NZW>(a, i, nz, cl, NC, acc);
+    // lanes of one wave sharing cl: xor over the wave; then across waves in LDS
+#pragma unroll
+    for (int c = 0; c < NCM; c++) {
+#pragma unroll
+      for (int off = CW; off < 64; off <<= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+    }
+    const int wave = tid / 64, lw = tid % 64;
+    if (lw < CW) {
+#pragma unroll
+      for (int c = 0; c < NCM; c++)
+        if (c < NC) sh[(wave * NCM + c) * CW + lw] = (double)acc[c];
+    }
+    __syncthreads();
+    if (tid < CW) {
+#pragma unroll
+      for (int c = 0; c < NCM; c++) {
+        if (c < NC) {
+          double t = 0.0;
+          for (int wv = 0; wv < WG / 64; wv++) t += sh[(wv * NCM + c) * CW + tid];
+          acc[c] = (T)t;
+        }
+      }
+      row_finish<T, CW>(a, i, tid, NC, acc, dacc);
+    }
+    __syncthreads();
+    owner = tid < CW;
+    slot = 0;
+    cl_own = tid;
+  } else {
+    // ---- short rows: a chunk of rows, one team per row
+    const int team = tid / TS, lane = tid % TS;
+    const int cl = lane % CW, nz = lane / CW;
+    const int rbeg = a.row0 + ((int)blockIdx.x - a.n_long) * a.rows_per_wg;
+    const int rend = min(a.row1, rbeg + a.rows_per_wg);
+    for (int i = rbeg + team; i < rend; i += TEAMS) {
+      if (a.long_rows && a.rp[i + 1] - a.rp[i] > a.long_thr) continue;  // done by its own workgroup
+      T acc[NCM];
+#pragma unroll
+      for (int c = 0; c < NCM; c++) acc[c] = (T)0;
+      row_gather<T, CW, NZ>(a, i, nz, cl, NC, acc);
+#pragma unroll
+      for (int c = 0; c < NCM; c++) {
+#pragma unroll
+        for (int off = CW; off < TS; off <<= 1) acc[c] += __shfl_xor(acc[c], off, TS);
+      }
+      if (nz == 0) row_finish<T, CW>(a, i, cl, NC, acc, dacc);
+    }
+    owner = nz == 0;
+    slot = team;
+    cl_own = cl;
+  }
+  if (a.ep == EP_NONE) return;
+  // per-column workgroup sums -> partials[blockIdx.x * B + j]
+  for (int j = tid; j < TEAMS * B; j += WG) sh[j] = 0.0;
+  __syncthreads();
+  if (owner) {
+#pragma unroll
+    for (int c = 0; c < NCM; c++) {
+      const int j = cl_own + CW * c;
+      if (c < NC && j < B) sh[slot * B + j] = dacc[c];
+    }
+  }
+  __syncthreads();
+  if (B * TEAMS <= WG) {
+    // tree over teams: thread (t, j) with t < TEAMS
+    const int t = tid / B, j = tid % B;
+    for (int off = TEAMS / 2; off > 0; off >>= 1) {
+      if (t < off) sh[t * B + j] += sh[(t + off) * B + j];
+      __syncthreads();
+    }
+    if (tid < B) a.partials[(int64_t)blockIdx.x * B + tid] = sh[tid];
+  } else {
+    for (int j = tid; j < B; j += WG) {
+      double s = 0.0;
+      for (int t = 0; t < TEAMS; t++) s += sh[t * B + j];
+      a.partials[(int64_t)blockIdx.x * B + j] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------- column-lane maps
+// Elementwise kernels over an m x B panel: CL column lanes (power of two,
+// <= WG), WG / CL row groups, each lane owning columns cl, cl + CL.
+struct ColMap {
+  int CL, RG, NCL;
+};
+__device__ inline ColMap colmap(int B) {
+  int cl = 1;
+  while (cl < B && cl < WG) cl <<= 1;
+  ColMap m;
+  m.CL = cl;
+  m.RG = WG / cl;
+  m.NCL = (B + cl - 1) / cl;
+  return m;
+}
+
+// Reduces per-lane per-column values dacc[0..NCL) over the row groups of the
+// workgroup into partials[blockIdx.x * B + j].
+__device__ inline void wg_colsum(const ColMap& m, int B, const double* dacc, double* partials) {
+  extern __shared__ double sh[];  // WG
+  const int tid = threadIdx.x, cl = tid % m.CL, rg = tid / m.CL;
+  for (int c = 0; c < m.NCL; c++) {
+    __syncthreads();
+    sh[tid] = dacc[c];
+    __syncthreads();
+    for (int off = m.RG / 2; off > 0; off >>= 1) {  // fixed-order tree over row groups
+      if (rg < off) sh[tid] += sh[tid + off * m.CL];
+      __syncthreads();
+    }
+    const int j = cl + m.CL * c;
+    if (rg == 0 && j < B) partials[(int64_t)blockIdx.x * B + j] = sh[tid];
+  }
+}
+
+// Per-column sum of squares of an m x B panel -> out[j] (FP64).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_colnorm2(const T* p, int64_t m, int B, int rows_per_wg,
+                                                 double* partials) {
+  const ColMap cm = colmap(B);
+  const int tid = threadIdx.x, cl = tid % cm.CL, rg = tid / cm.CL;
+  double dacc[2] = {0.0, 0.0};
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(m, r0 + rows_per_wg);
+  for (int64_t i = r0 + rg; i < r1; i += cm.RG)
+    for (int c = 0; c < cm.NCL; c++) {
+      const int j = cl + cm.CL * c;
+      if (j < B) {
+        double v = (double)p[i * B + j];
+        dacc[c] += v * v;
+      }
+    }
+  wg_colsum(cm, B, dacc, partials);
+}
+
+// x += alpha p; r -= alpha q (active columns), then <r, r> per column.
+// EP_RR: convergence / iteration-cap test.  EP_RR_CG: also the CG direction
+// coefficient bcg = rr_new / rz and rz = rr_new (z = r).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_update_r(int64_t m, int B, int rows_per_wg, T* x, const T* p, T* r,
+                                                 const T* q, ColState cs, double* partials) {
+  if (*cs.n_active == 0) return;
+  const ColMap cm = colmap(B);
+  const int tid = threadIdx.x, cl = tid % cm.CL, rg = tid / cm.CL;
+  double dacc[2] = {0.0, 0.0};
+  T al[2];
+  int act[2];
+  for (int c = 0; c < cm.NCL; c++) {
+    const int j = cl + cm.CL * c;
+    act[c] = (j < B) ? cs.active[j] : 0;
+    al[c] = act[c] ? (T)cs.alpha[j] : (T)0;
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(m, r0 + rows_per_wg);
+  for (int64_t i = r0 + rg; i < r1; i += cm.RG)
+    for (int c = 0; c < cm.NCL; c++) {
+      const int j = cl + cm.CL * c;
+      if (j < B && act[c]) {
+        const int64_t o = i * B + j;
+        x[o] += al[c] * p[o];
+        T rv = r[o] - al[c] * q[o];
+        r[o] = rv;
+        dacc[c] += (double)rv * (double)rv;
+      }
+    }
+  wg_colsum(cm, B, dacc, partials);
+}
+
+// p = z + bcg p (active columns); init: p = z for the columns in the mask.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_update_p(int64_t m, int B, const T* z, T* p, int init, ColState cs) {
+  if (!init && *cs.n_active == 0) return;
+  const ColMap cm = colmap(B);
+  const int tid = threadIdx.x, cl = tid % cm.CL, rg = tid / cm.CL;
+  for (int c = 0; c < cm.NCL; c++) {
+    const int j = cl + cm.CL * c;
+    if (j >= B) continue;
+    if (init ? !cs.active[j] : !cs.active[j]) continue;
+    const T b = init ? (T)0 : (T)cs.bcg[j];
+    for (int64_t i = (int64_t)blockIdx.x * cm.RG + rg; i < m; i += (int64_t)gridDim.x * cm.RG) {
+      const int64_t o = i * B + j;
+      p[o] = init ? z[o] : z[o] + b * p[o];
+    }
+  }
+}
+
+// dst[:, j] (+)= src[:, j] for columns with mask[j] (copy when add == 0).
+template <typename T, typename S>
+__global__ __launch_bounds__(WG) void k_axpy_mask(int64_t m, int B, T* dst, const S* src, const int* mask,
+                                                  const double* scale, int add) {
+  const ColMap cm = colmap(B);
+  const int tid = threadIdx.x, cl = tid % cm.CL, rg = tid / cm.CL;
+  for (int c = 0; c < cm.NCL; c++) {
+    const int j = cl + cm.CL * c;
+    if (j >= B || (mask && !mask[j])) continue;
+    const double sc = scale ? scale[j] : 1.0;
+    for (int64_t i = (int64_t)blockIdx.x * cm.RG + rg; i < m; i += (int64_t)gridDim.x * cm.RG) {
+      const int64_t o = i * B + j;
+      T v = (T)(sc * (double)src[o]);
+      dst[o] = add ? (T)(dst[o] + v) : v;
+    }
+  }
+}
+
+// ------------------------------------------------------ M11 block solves
+// out[i] = scale * M_bb^{-1} u[i] for every row i of the tile's blocks, with
+// u[i] = cv v[i] + ca (A12 x2)[i] staged in LDS (x2: separator panel indexed
+// by column - n1).  The block inverse is symmetric, so thread i reads column
+// i of row k (coalesced across the block's rows).
+template <typename T>
+struct M11Args {
+  const int32_t* tile_row0;
+  const int32_t* row_blk;
+  const int32_t* blk_start;
+  const int64_t* blk_off;
+  const T* minv;
+  const int32_t* rp;
+  const int32_t* col;
+  const int32_t* split;
+  const double* val;
+  int n1;
+  const T* v;
+  T cv;
+  const T* x2;
+  T ca;
+  T* out;
+  int B, CB;
+  const int* n_active;
+};
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_m11_apply(M11Args<T> a) {
+  if (a.n_active && *a.n_active == 0) return;
+  extern __shared__ unsigned char smem[];
+  T* u = reinterpret_cast<T*>(smem);
+  const int r0 = a.tile_row0[blockIdx.x], r1 = a.tile_row0[blockIdx.x + 1], R = r1 - r0;
+  const int B = a.B;
+  for (int jc = 0; jc < B; jc += a.CB) {
+    const int cb = min(a.CB, B - jc);
+    const int P = R * cb;
+    for (int p = threadIdx.x; p < P; p += WG) {
+      const int i = p / cb, jj = p - i * cb, gi = r0 + i, j = jc + jj;
+      T s = (T)0;
+      if (a.x2) {
+        for (int32_t k = a.split[gi]; k < a.rp[gi + 1]; k++) {
+          T xv = a.x2[(int64_t)(a.col[k] - a.n1) * B + j];
+          s += a.val ? (T)a.val[k] * xv : xv;
+        }
+        s *= a.ca;
+      }
+      if (a.v) s += a.cv * a.v[(int64_t)gi * B + j];
+      u[p] = s;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < P; p += WG) {
+      const int i = p / cb, jj = p - i * cb, gi = r0 + i, j = jc + jj;
+      const int blk = a.row_blk[gi];
+      const int bs = a.blk_start[blk], bsz = a.blk_start[blk + 1] - bs, li = gi - bs;
+      const T* mi = a.minv + a.blk_off[blk];
+      const T* ub = u + (int64_t)(bs - r0) * cb + jj;
+      T s = (T)0;
+      for (int k = 0; k < bsz; k++) s += mi[(int64_t)k * bsz + li] * ub[(int64_t)k * cb];
+      a.out[(int64_t)gi * B + j] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// z = G r with the dense symmetric G = M22^{-1} (L = chol(M22)).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_dense_apply(int m, int B, const T* g, const T* r, T* z,
+                                                    const int* n_active) {
+  if (n_active && *n_active == 0) return;
+  const int64_t P = (int64_t)m * B;
+  for (int64_t p = blockIdx.x * (int64_t)WG + threadIdx.x; p < P; p += (int64_t)gridDim.x * WG) {
+    const int i = (int)(p / B), j = (int)(p - (int64_t)i * B);
+    T s = (T)0;
+    for (int k = 0; k < m; k++) s += g[(int64_t)k * m + i] * r[(int64_t)k * B + j];
+    z[p] = s;
+  }
+}
+
+// --------------------------------------------------- low-rank correction
+// V is stored column-major (V[k * m + i]), so lanes over rows read it
+// coalesced.  W = V^T r (rank x B) is split over row chunks; the last
+// workgroup forms DW = D o W.
+//   small rank*B (<= 64): each thread owns rows and keeps all rank*B sums in
+//   registers, reduced over the workgroup by wave shuffles and LDS;
+//   otherwise lanes over (k, j) pairs loop over the rows.
+template <typename T, typename TV>
+__global__ __launch_bounds__(WG) void k_vt(int64_t m, int B, int rank, const TV* V, const T* r, int rows_per_wg,
+                                           double* partials, const int* n_active) {
+  if (n_active && *n_active == 0) return;
+  __shared__ double sh[WG];
+  const int P = rank * B;
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(m, r0 + rows_per_wg);
+  if (P <= 64) {
+    double acc[64];
+#pragma unroll
+    for (int p = 0; p < 64; p++) acc[p] = 0.0;
+    for (int64_t i = r0 + tid; i < r1; i += WG) {
+      for (int j = 0; j < B; j++) {
+        const double rv = (double)r[i * B + j];
+#pragma unroll
+        for (int k = 0; k < 64; k++)
+          if (k < rank && k * B + j < 64) acc[k * B + j] += (double)V[(int64_t)k * m + i] * rv;
+      }
+    }
+    // reduce each acc[p] over the workgroup: wave shuffles, then 4 waves in LDS
+    const int wave = tid / 64, lane = tid % 64;
+#pragma unroll
+    for (int p = 0; p < 64; p++) {
+      if (p < P) {
+        double v = acc[p];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) sh[wave * 64 + p] = v;
+      }
+    }
+    __syncthreads();
+    if (tid < P) {
+      double s = 0.0;
+      for (int wv = 0; wv < WG / 64; wv++) s += sh[wv * 64 + tid];
+      partials[(int64_t)blockIdx.x * P + tid] = s;
+    }
+  } else {
+    int G = 1;
+    while (G * 2 * P <= WG) G <<= 1;
+    for (int pb = 0; pb < P; pb += WG / G) {
+      const int pw = min(WG / G, P - pb);
+      const int pl = tid % (WG / G), g = tid / (WG / G);
+      double acc = 0.0;
+      if (pl < pw) {
+        const int p = pb + pl, k = p / B, j = p - k * B;
+        for (int64_t i = r0 + g; i < r1; i += G) acc += (double)V[(int64_t)k * m + i] * (double)r[i * B + j];
+      }
+      __syncthreads();
+      sh[tid] = acc;
+      __syncthreads();
+      if (g == 0 && pl < pw) {
+        double s = 0.0;
+        for (int gg = 0; gg < G; gg++) s += sh[gg * (WG / G) + pl];
+        partials[(int64_t)blockIdx.x * P + pb + pl] = s;
+      }
+    }
+  }
+}
+
+// z = base + V DW with base = r (L = I) or the already stored z (L = chol),
+// then <r, z> per column (EP_RZ_INIT: rz = <r,z>; EP_RZ: bcg = <r,z>_new / rz).
+template <typename T, typename TV>
+__global__ __launch_bounds__(WG) void k_lowrank(int64_t m, int B, int rank, const TV* V, const double* DW,
+                                                const T* r, T* z, int z_has_base, int rows_per_wg,
+                                                const int* n_active, double* partials) {
+  if (n_active && *n_active == 0) return;
+  const ColMap cm = colmap(B);
+  const int tid = threadIdx.x, cl = tid % cm.CL, rg = tid / cm.CL;
+  double dacc[2] = {0.0, 0.0};
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(m, r0 + rows_per_wg);
+  for (int64_t i = r0 + rg; i < r1; i += cm.RG)
+    for (int c = 0; c < cm.NCL; c++) {
+      const int j = cl + cm.CL * c;
+      if (j >= B) continue;
+      const int64_t o = i * B + j;
+      double s = z_has_base ? (double)z[o] : (double)r[o];
+      for (int k = 0; k < rank; k++) s += (double)V[(int64_t)k * m + i] * DW[k * B + j];
+      T zv = (T)s;
+      z[o] = zv;
+      dacc[c] += (double)r[o] * (double)zv;
+    }
+  wg_colsum(cm, B, dacc, partials);
+}
+
+// One workgroup: reduces the producer's per-workgroup partials (fixed order)
+// and applies the step's per-column logic.
+//   EP_PQ: pq, alpha = rz / pq, breakdown test     EP_RES / EP_NORM: out = sum
+//   EP_RR_INIT: rr, solve start                    EP_RR: rr, convergence / cap
+//   EP_RR_CG: as EP_RR plus bcg = rr_new / rz      EP_VT: DW = D o W
+//   EP_RZ_INIT: rz                                  EP_RZ: bcg = rz_new / rz
+__global__ __launch_bounds__(WG) void k_finalize(const double* partials, int nwg, int nv, int ep, ColState cs,
+                                                 int B, double* out, const double* D, const int* n_active) {
+  if (n_active && *n_active == 0) return;
+  final_reduce(partials, nwg, nv, [&](int j, double s) {
+    switch (ep) {
+      case EP_RES:
+      case EP_NORM:
+        out[j] = s;
+        break;
+      case EP_VT:
+        out[j] = D[j / B] * s;
+        break;
+      case EP_PQ:
+        if (cs.active[j]) {
+          cs.pq[j] = s;
+          if (!finite_pos(s)) {
+            cs.status[j] = 1;
+            cs.active[j] = 0;
+          } else {
+            cs.alpha[j] = cs.rz[j] / s;
+          }
+        }
+        break;
+      case EP_RR_INIT:
+        cs.rr[j] = s;
+        cs.iters[j] = 0;
+        cs.status[j] = 0;
+        cs.active[j] = (cs.mask[j] && s > cs.thr[j]) ? 1 : 0;
+        break;
+      case EP_RR:
+      case EP_RR_CG: {
+        if (!cs.active[j]) break;
+        cs.rr[j] = s;
+        const int it = ++cs.iters[j];
+        if (ep == EP_RR_CG) {
+          cs.bcg[j] = s / cs.rz[j];
+          cs.rz[j] = s;
+        }
+        if (!(s == s)) {
+          cs.status[j] = 1;
+          cs.active[j] = 0;
+        } else if (s <= cs.thr[j]) {
+          cs.active[j] = 0;
+        } else if (it >= cs.max_iter) {
+          cs.status[j] = 2;
+          cs.active[j] = 0;
+        }
+        break;
+      }
+      case EP_RZ_INIT:
+        if (cs.mask[j]) cs.rz[j] = s;
+        break;
+      case EP_RZ:
+        if (cs.active[j]) {
+          cs.bcg[j] = s / cs.rz[j];
+          cs.rz[j] = s;
+        }
+        break;
+      default:
+        break;
+    }
+  });
+  if (ep == EP_PQ || ep == EP_RR_INIT || ep == EP_RR || ep == EP_RR_CG) recount_active(cs, B);
+}
+
+// Plain-CG start: rz = rr, active = mask && rr > thr.
+__global__ void k_cg_init(int B, ColState cs) {
+  for (int j = threadIdx.x; j < B; j += blockDim.x) {
+    cs.rz[j] = cs.rr[j];
+    cs.iters[j] = 0;
+    cs.status[j] = 0;
+    cs.active[j] = (cs.mask[j] && cs.rr[j] > cs.thr[j]) ? 1 : 0;
+  }
+  recount_active(cs, B);
+}
+
+// scores[j * n + v] = K[perm[v] * B + j]
+template <typename T>
+__global__ void k_unpermute(int n, int B, const T* K, const int32_t* perm, double* out) {
+  const int j = blockIdx.y;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    out[(int64_t)j * n + v] = (double)K[(int64_t)perm[v] * B + j];
+}
+
+
+// ============================================================== profiling
+// Optional per-kernel timing: HIP events around each launch of the hot
+// kernels on the solve stream, harvested at the solver's host sync points,
+// plus the algorithmic bytes each launch moves (formulas next to the launches).
+enum ProfKind { PK_SPMM_SEP = 0, PK_SPMM_FULL, PK_M11, PK_VT, PK_LOWRANK, PK_UPDATE_R, PK_UPDATE_P, PK_TOPK,
+                PK_OTHER, PK_COUNT };
+static const char* kProfNames[PK_COUNT] = {"spmm_separator_rows", "spmm_all_rows", "m11_block_apply",
+                                           "lowrank_vt", "lowrank_apply", "update_r", "update_p", "topk_select",
+                                           "other"};
+struct ProfTable {
+  std::mutex mu;
+  int64_t launches[PK_COUNT] = {};
+  double ms[PK_COUNT] = {};
+  double bytes[PK_COUNT] = {};
+};
+static ProfTable g_prof;
+static std::atomic<int> g_prof_on{0};
+
+struct ProfEvents {
+  std::vector<hipEvent_t> ev;  // pairs
+  std::vector<int> kind;
+  std::vector<double> bytes;
+  size_t used = 0;
+  void begin(int k, double b, hipStream_t st) {
+    if (used == kind.size()) {
+      hipEvent_t a, c;
+      HIPCHECK(hipEventCreate(&a));
+      HIPCHECK(hipEventCreate(&c));
+      ev.push_back(a);
+      ev.push_back(c);
+      kind.push_back(0);
+      bytes.push_back(0);
+    }
+    kind[used] = k;
+    bytes[used] = b;
+    HIPCHECK(hipEventRecord(ev[2 * used], st));
+  }
+  void end(hipStream_t st) {
+    HIPCHECK(hipEventRecord(ev[2 * used + 1], st));
+    used++;
+  }
+  // call after the stream was synchronized
+  void harvest() {
+    if (!used) return;
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    for (size_t i = 0; i < used; i++) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
+        g_prof.launches[kind[i]]++;
+        g_prof.ms[kind[i]] += ms;
+        g_prof.bytes[kind[i]] += bytes[i];
+      }
+    }
+    used = 0;
+  }
+  ~ProfEvents() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+// ============================================================= device index
+struct Workspace {
+  int B = 0;
+  int64_t n = 0, n2 = 0;
+  double *Bp = nullptr, *Rhs = nullptr, *K = nullptr, *Dx = nullptr, *X = nullptr, *Y = nullptr,
+         *W = nullptr, *Z = nullptr;
+  double* partials = nullptr;
+  size_t partials_cap = 0;
+  double* DW = nullptr;
+  double *rz, *pq, *alpha, *bcg, *rr, *thr, *bn2, *res2, *colscale;
+  int *active, *status, *iters, *n_active, *mask;
+  int32_t* qpos = nullptr;
+  double* out_scores = nullptr;  // staging for host output
+  int64_t out_cap = 0;
+  void* tk_scratch = nullptr;    // top-K selection state and winners
+  size_t tk_cap = 0;
+  int32_t* tk_ids = nullptr;     // staging for host top-K output
+  double* tk_sc = nullptr;
+  int64_t tk_out_cap = 0;
+  void* hpin = nullptr;          // pinned host staging for small scalars
+  std::vector<void*> allocs;
+  int device = 0;
+  ProfEvents prof;
+};
+
+struct DeviceIndex {
+  int device = 0;
+  int32_t n = 0, n1 = 0, n2 = 0, rank = 0, nblocks = 0, ntiles = 0, max_tile_rows = 0;
+  int64_t nnz = 0;
+  double beta = 0, c = 0;
+  int l_kind = KATZ_L_IDENTITY;
+  int precision = KATZ_PREC_FP64;
+  int32_t *rp = nullptr, *col = nullptr, *split = nullptr, *perm = nullptr, *iperm = nullptr;
+  double* val = nullptr;
+  int32_t *tile_row0 = nullptr, *row_blk = nullptr, *blk_start = nullptr;
+  int64_t* blk_off = nullptr;
+  double* minv = nullptr;
+  double* ginv = nullptr;
+  double* V = nullptr;
+  double* D = nullptr;
+  int64_t bytes = 0, factor_bytes = 0;
+  std::vector<void*> allocs;
+  std::mutex mu;
+  std::vector<std::unique_ptr<Workspace>> pool;
+  double avg_deg = 0;
+  // sizes for the algorithmic-byte formulas
+  int64_t nnz_sep = 0, nnz_sep_left = 0, nnz_a12 = 0, cols_sep = 0, cols_sep_left = 0, cols_a12 = 0,
+          cols_all = 0, minv_elems = 0;
+  // hub rows (more than kLongRow entries) of the separator range and of all rows
+  int32_t *long_sep = nullptr, *long_all = nullptr;
+  int n_long_sep = 0, n_long_all = 0;
+};
+constexpr int kLongRow = 256;
+
+namespace {
+
+template <typename T>
+T* dalloc(std::vector<void*>& list, int64_t count, int64_t* bytes = nullptr) {
+  if (count <= 0) count = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, (size_t)count * sizeof(T));
+  if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? KATZ_ENOMEM : KATZ_EDEVICE,
+                            std::string("hipMalloc: ") + hipGetErrorString(e));
+  list.push_back(p);
+  if (bytes) *bytes += count * (int64_t)sizeof(T);
+  return (T*)p;
+}
+
+template <typename T>
+T* upload(std::vector<void*>& list, const std::vector<T>& h, int64_t* bytes) {
+  T* d = dalloc<T>(list, (int64_t)h.size(), bytes);
+  if (!h.empty()) HIPCHECK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+int grid_for(int64_t work, int per) {
+  int64_t g = (work + per - 1) / per;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65535));
+}
+
+}  // namespace
+
+DeviceIndex* device_upload(const HostIndex& H, int device) {
+  HIPCHECK(hipSetDevice(device));
+  auto D = new DeviceIndex();
+  try {
+    D->device = device;
+    D->n = H.n;
+    D->n1 = H.n1;
+    D->n2 = H.n2;
+    D->nnz = H.nnz;
+    D->beta = H.beta;
+    D->c = H.c;
+    D->l_kind = H.l_kind;
+    D->precision = H.precision;
+    D->rank = H.rank;
+    D->avg_deg = H.n ? (double)H.nnz / H.n : 0;
+    {
+      // distinct columns touched by each row range (each gathered panel row is
+      // counted once in the algorithmic bytes) and entry counts
+      std::vector<char> seen(H.n, 0), seenl(H.n, 0), seena(H.n, 0), seenall(H.n, 0);
+      for (int32_t i = 0; i < H.n; i++)
+        for (int32_t k = H.rp[i]; k < H.rp[i + 1]; k++) {
+          int32_t c = H.col[k];
+          seenall[c] = 1;
+          if (i >= H.n1) {
+            D->nnz_sep++;
+            seen[c] = 1;
+            if (k < H.split[i]) { D->nnz_sep_left++; seenl[c] = 1; }
+          } else if (k >= H.split[i]) {
+            D->nnz_a12++;
+            seena[c] = 1;
+          }
+        }
+      for (int32_t c = 0; c < H.n; c++) {
+        D->cols_sep += seen[c];
+        D->cols_sep_left += seenl[c];
+        D->cols_a12 += seena[c];
+        D->cols_all += seenall[c];
+      }
+      D->minv_elems = (int64_t)H.minv.size();
+      std::vector<int32_t> ls, la;
+      for (int32_t i = 0; i < H.n; i++)
+        if (H.rp[i + 1] - H.rp[i] > kLongRow) {
+          la.push_back(i);
+          if (i >= H.n1) ls.push_back(i);
+        }
+      D->n_long_sep = (int)ls.size();
+      D->n_long_all = (int)la.size();
+      D->long_sep = upload(D->allocs, ls, &D->bytes);
+      D->long_all = upload(D->allocs, la, &D->bytes);
+    }
+    int64_t* by = &D->bytes;
+    D->rp = upload(D->allocs, H.rp, by);
+    D->col = upload(D->allocs, H.col, by);
+    D->split = upload(D->allocs, H.split, by);
+    D->perm = upload(D->allocs, H.perm, by);
+    D->iperm = upload(D->allocs, H.iperm, by);
+    if (H.weighted) D->val = upload(D->allocs, H.val, by);
+    // tiles of consecutive blocks with at most 256 rows (a larger block is a
+    // tile of its own)
+    const int nb = (int)H.blk_start.size() - 1;
+    D->nblocks = nb;
+    std::vector<int32_t> tiles{0}, row_blk(std::max(1, H.n1));
+    int32_t cur = 0;
+    int max_rows = 0;
+    for (int b = 0; b < nb; b++) {
+      int32_t s = H.blk_start[b], e = H.blk_start[b + 1];
+      for (int32_t i = s; i < e; i++) row_blk[i] = b;
+      if (e - tiles.back() > WG && s > tiles.back()) {
+        tiles.push_back(s);
+      }
+      cur = e;
+      (void)cur;
+    }
+    if (tiles.back() != H.n1) tiles.push_back(H.n1);
+    if (H.n1 == 0) tiles.assign(1, 0);
+    for (size_t t = 0; t + 1 < tiles.size(); t++) max_rows = std::max(max_rows, tiles[t + 1] - tiles[t]);
+    D->ntiles = (int)tiles.size() - 1;
+    D->max_tile_rows = max_rows;
+    D->tile_row0 = upload(D->allocs, tiles, by);
+    D->row_blk = upload(D->allocs, row_blk, by);
+    D->blk_start = upload(D->allocs, H.blk_start, by);
+    D->blk_off = upload(D->allocs, H.blk_off, by);
+    int64_t fb0 = D->bytes;
+    D->minv = upload(D->allocs, H.minv, by);
+    D->factor_bytes = D->bytes - fb0;
+    if (H.l_kind == KATZ_L_CHOL && H.n2 > 0) D->ginv = upload(D->allocs, H.ginv, by);
+    if (H.rank > 0) {
+      std::vector<double> vc((size_t)H.n2 * H.rank);  // column-major copy
+      for (int64_t i = 0; i < H.n2; i++)
+        for (int k = 0; k < H.rank; k++) vc[(size_t)k * H.n2 + i] = H.V[(size_t)i * H.rank + k];
+      D->V = upload(D->allocs, vc, by);
+      D->D = upload(D->allocs, H.D, by);
+    }
+    HIPCHECK(hipDeviceSynchronize());
+  } catch (...) {
+    device_free(D);
+    throw;
+  }
+  return D;
+}
+
+static void free_ws(Workspace* w) {
+  for (void* p : w->allocs) (void)hipFree(p);
+  if (w->hpin) (void)hipHostFree(w->hpin);
+  w->allocs.clear();
+}
+
+void device_free(DeviceIndex* D) {
+  if (!D) return;
+  (void)hipSetDevice(D->device);
+  for (auto& w : D->pool) free_ws(w.get());
+  for (void* p : D->allocs) (void)hipFree(p);
+  delete D;
+}
+int64_t device_bytes(const DeviceIndex* D) { return D ? D->bytes : 0; }
+int64_t device_factor_bytes(const DeviceIndex* D) { return D ? D->factor_bytes : 0; }
+
+// ================================================================ workspace
+static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
+  auto w = std::make_unique<Workspace>();
+  w->B = B;
+  w->n = D->n;
+  w->n2 = D->n2;
+  w->device = D->device;
+  auto& L = w->allocs;
+  const int64_t nB = (int64_t)D->n * B;
+  w->Bp = dalloc<double>(L, nB);
+  w->Rhs = dalloc<double>(L, nB);
+  w->K = dalloc<double>(L, nB);
+  w->Dx = dalloc<double>(L, nB);
+  w->X = dalloc<double>(L, nB);
+  w->Y = dalloc<double>(L, nB);
+  w->W = dalloc<double>(L, nB);
+  w->Z = dalloc<double>(L, (int64_t)std::max(1, D->n2) * B);
+  w->partials_cap = (size_t)(4096 + std::max(D->n_long_all, D->n_long_sep)) * std::max(B, 1) +
+                    (size_t)2048 * std::max(1, D->rank) * B;
+  w->partials = dalloc<double>(L, (int64_t)w->partials_cap);
+  w->DW = dalloc<double>(L, (int64_t)std::max(1, D->rank) * B);
+  double* s = dalloc<double>(L, 9 * (int64_t)B);
+  w->rz = s; w->pq = s + B; w->alpha = s + 2 * B; w->bcg = s + 3 * B; w->rr = s + 4 * B;
+  w->thr = s + 5 * B; w->bn2 = s + 6 * B; w->res2 = s + 7 * B; w->colscale = s + 8 * B;
+  int* ip = dalloc<int>(L, 4 * (int64_t)B + 1);
+  w->active = ip; w->status = ip + B; w->iters = ip + 2 * B; w->mask = ip + 3 * B; w->n_active = ip + 4 * B;
+  HIPCHECK(hipMemset(s, 0, 9 * sizeof(double) * (size_t)B));
+  HIPCHECK(hipMemset(ip, 0, (4 * (size_t)B + 1) * sizeof(int)));
+  w->qpos = dalloc<int32_t>(L, B);
+  HIPCHECK(hipHostMalloc(&w->hpin, 64 * 1024, hipHostMallocDefault));
+  return w;
+}
+
+struct WsLease {
+  DeviceIndex* D;
+  std::unique_ptr<Workspace> w;
+  WsLease(DeviceIndex* d, int B) : D(d) {
+    {
+      std::lock_guard<std::mutex> g(D->mu);
+      for (size_t i = 0; i < D->pool.size(); i++)
+        if (D->pool[i]->B == B) {
+          w = std::move(D->pool[i]);
+          D->pool.erase(D->pool.begin() + i);
+          break;
+        }
+    }
+    if (!w) w = make_ws(D, B);
+  }
+  ~WsLease() {
+    std::lock_guard<std::mutex> g(D->mu);
+    if (D->pool.size() >= 4) {
+      free_ws(D->pool.front().get());
+      D->pool.erase(D->pool.begin());
+    }
+    D->pool.push_back(std::move(w));
+  }
+};
+
+// ============================================================ launch helpers
+struct Launcher {
+  DeviceIndex* D;
+  Workspace* w;
+  hipStream_t st;
+  int B;
+
+  ColState cs(int max_iter) const {
+    ColState c;
+    c.rz = w->rz; c.pq = w->pq; c.alpha = w->alpha; c.bcg = w->bcg; c.rr = w->rr; c.thr = w->thr;
+    c.active = w->active; c.status = w->status; c.iters = w->iters; c.n_active = w->n_active;
+    c.mask = w->mask; c.max_iter = max_iter;
+    return c;
+  }
+
+  // Runs launch(); with profiling on, brackets it with HIP events and books
+  // `bytes` algorithmic bytes to `kind`.
+  template <typename F>
+  void timed(int kind, double bytes, F&& launch) {
+    const bool on = g_prof_on.load(std::memory_order_relaxed) != 0;
+    if (on) w->prof.begin(kind, bytes, st);
+    launch();
+    if (on) w->prof.end(st);
+  }
+  void sync() {
+    HIPCHECK(hipStreamSynchronize(st));
+    w->prof.harvest();
+  }
+
+  template <typename T>
+  void fill(T* p, int64_t cnt, T v) {
+    if (cnt <= 0) return;
+    k_fill<T><<<grid_for(cnt, WG * 4), WG, 0, st>>>(p, cnt, v);
+  }
+
+  // Workgroups for the elementwise reduction kernels over m rows.
+  int rows_per_wg(int64_t m) const {
+    int64_t nwg = std::min<int64_t>(1024, std::max<int64_t>(1, (m + 255) / 256));
+    return (int)((m + nwg - 1) / nwg);
+  }
+  static int nwg_for(int64_t m, int rpw) { return (int)((m + rpw - 1) / rpw); }
+
+  // Reduces nwg x nv partials and applies the epilogue `ep` (one workgroup).
+  void finalize(int nwg, int nv, int ep, const ColState& cs, double* out, const int* nact) {
+    if ((size_t)nwg * nv > w->partials_cap) fail(KATZ_EDEVICE, "internal: partials buffer too small");
+    k_finalize<<<1, WG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact);
+  }
+
+  template <typename T>
+  void spmm(SpmmArgs<T> a) {
+    const int64_t rows = a.row1 - a.row0;
+    if (rows <= 0) {
+      if (a.ep != EP_NONE) fail(KATZ_EDEVICE, "internal: empty SpMM with a reduction");
+      return;
+    }
+    a.B = B;
+    int TS, CW;
+    if (B == 1) { TS = 8; CW = 1; }
+    else if (B == 2) { TS = 8; CW = 2; }
+    else if (B <= 4) { TS = 16; CW = 4; }
+    else if (B <= 8) { TS = 32; CW = 8; }
+    else if (B <= 16) { TS = 64; CW = 16; }
+    else if (B <= 32) { TS = 64; CW = 32; }
+    else { TS = 64; CW = 64; }
+    if (B > MAXC * CW) fail(KATZ_EINVAL, "batch too wide for one launch");
+    const int teams = WG / TS;
+    int64_t nwg = std::min<int64_t>(1024, std::max<int64_t>(1, (rows + teams * 4 - 1) / (teams * 4)));
+    a.rows_per_wg = (int)((rows + nwg - 1) / nwg);
+    nwg = (rows + a.rows_per_wg - 1) / a.rows_per_wg;
+    a.partials = w->partials;
+    a.long_thr = kLongRow;
+    if (a.row0 == D->n1 && a.row1 == D->n) { a.long_rows = D->long_sep; a.n_long = D->n_long_sep; }
+    else if (a.row0 == 0 && a.row1 == D->n) { a.long_rows = D->long_all; a.n_long = D->n_long_all; }
+    else { a.long_rows = nullptr; a.n_long = 0; }
+    if (a.n_long == 0) a.long_rows = nullptr;
+    const int nwg_all = (int)nwg + a.n_long;
+    if ((size_t)nwg_all * B > w->partials_cap) fail(KATZ_EDEVICE, "internal: partials buffer too small");
+    size_t shm = sizeof(double) * std::max<size_t>((size_t)teams * B, (size_t)(WG / 64) * MAXC * CW);
+    dim3 g((unsigned)nwg_all);
+    // algorithmic bytes: row pointers and splits, the selected entries, each
+    // gathered panel row once, the row-aligned panels read and y written
+    const bool sep = a.row0 == D->n1 && a.row1 == D->n;
+    int64_t nnz_sel, cols_sel;
+    if (sep && a.parts == 1) { nnz_sel = D->nnz_sep_left; cols_sel = D->cols_sep_left; }
+    else if (sep) { nnz_sel = D->nnz_sep; cols_sel = D->cols_sep; }
+    else { nnz_sel = D->nnz; cols_sel = D->cols_all; }
+    const double wb = (double)sizeof(T) * B;
+    int panels = 1 + (a.v ? 1 : 0) + (a.w ? 1 : 0) + ((a.dotv && a.dotv != a.v) ? 1 : 0);
+    double bytes = 8.0 * rows + 4.0 + (4.0 + (a.val ? 8.0 : 0.0)) * nnz_sel + wb * cols_sel + wb * rows * panels;
+    const int kind = sep ? PK_SPMM_SEP : PK_SPMM_FULL;
+    bool launched = false;
+#define KZ_SPMM(ts, cw)                                                                    \
+  if (!launched && TS == ts && CW == cw) {                                                 \
+    timed(kind, bytes, [&] { k_spmm<T, ts, cw><<<g, WG, shm, st>>>(a); });                 \
+    launched = true;                                                                       \
+  }
+    KZ_SPMM(8, 1) KZ_SPMM(8, 2) KZ_SPMM(16, 4) KZ_SPMM(32, 8) KZ_SPMM(64, 16) KZ_SPMM(64, 32) KZ_SPMM(64, 64)
+#undef KZ_SPMM
+    if (a.ep != EP_NONE) finalize(nwg_all, B, a.ep, a.cs, a.out, a.n_active);
+  }
+
+  // out[j] = sum of squares of column j of the m x B panel p
+  template <typename T>
+  void colnorm2(const T* p, int64_t m, double* out) {
+    const int rpw = rows_per_wg(m), nwg = nwg_for(m, rpw);
+    k_colnorm2<T><<<nwg, WG, WG * sizeof(double), st>>>(p, m, B, rpw, w->partials);
+    finalize(nwg, B, EP_NORM, cs(0), out, nullptr);
+  }
+};
+
+// ============================================================ solve sweeps
+// One correction solve M d = rhs for the columns in w->mask; d is left in
+// w->Dx (all n rows), per-column outcome in w->iters / w->status.
+template <typename T>
+static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) {
+  DeviceIndex* D = L.D;
+  Workspace* w = L.w;
+  const int B = L.B;
+  const int n = D->n, n1 = D->n1, n2 = D->n2;
+  const T beta = (T)D->beta;
+  hipStream_t st = L.st;
+  ColState cs = L.cs(max_iter);
+  T* X = (T*)w->X;      // rows < n1: block-solve output; rows >= n1: p2
+  T* P2 = X + (int64_t)n1 * B;
+  T* R2 = (T*)w->Y;     // n2 x B
+  T* Q2 = (T*)w->W;     // n2 x B
+  T* Z2 = (T*)w->Z;     // n2 x B
+  T* Dx = (T*)w->Dx;
+  T* K2 = Dx + (int64_t)n1 * B;
+
+  auto m11 = [&](const T* v, T cv, const T* x2, T ca, T* out, const int* nact) {
+    if (n1 == 0) return;
+    M11Args<T> a;
+    a.tile_row0 = D->tile_row0; a.row_blk = D->row_blk; a.blk_start = D->blk_start; a.blk_off = D->blk_off;
+    a.minv = (const T*)D->minv; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val; a.n1 = n1;
+    a.v = v; a.cv = cv; a.x2 = x2; a.ca = ca; a.out = out; a.B = B; a.n_active = nact;
+    int cb = std::max(1, std::min(B, (int)(32768 / sizeof(T) / std::max(1, D->max_tile_rows))));
+    a.CB = cb;
+    size_t shm = (size_t)D->max_tile_rows * cb * sizeof(T);
+    const double wb = (double)sizeof(T) * B;
+    double bytes = (double)sizeof(T) * D->minv_elems + 4.0 * n1 + wb * n1 + (v ? wb * n1 : 0.0) +
+                   (x2 ? 8.0 * n1 + 4.0 * D->nnz_a12 + wb * D->cols_a12 : 0.0);
+    L.timed(PK_M11, bytes, [&] { k_m11_apply<T><<<D->ntiles, WG, shm, st>>>(a); });
+  };
+  // z2 = G r2 + V (D o (V^T r2)), then <r2, z2> (EP_RZ_INIT / EP_RZ)
+  auto precond = [&](int ep) {
+    const int64_t m = n2;
+    const int rpw = L.rows_per_wg(m), nwg = Launcher::nwg_for(m, rpw);
+    const int* nact = ep == EP_RZ ? w->n_active : nullptr;
+    if (D->rank > 0) {
+      L.timed(PK_VT, 8.0 * m * D->rank + (double)sizeof(T) * B * m, [&] {
+        k_vt<T, double><<<nwg, WG, 0, st>>>(m, B, D->rank, D->V, R2, rpw, w->partials, nact);
+      });
+      L.finalize(nwg, D->rank * B, EP_VT, cs, w->DW, nact);
+    }
+    int has_base = 0;
+    if (D->ginv) {
+      L.timed(PK_OTHER, (double)sizeof(T) * (m * m + 2 * m * B), [&] {
+        k_dense_apply<T><<<grid_for(m * B, WG), WG, 0, st>>>((int)m, B, (const T*)D->ginv, R2, Z2, nact);
+      });
+      has_base = 1;
+    }
+    L.timed(PK_LOWRANK, 8.0 * m * D->rank + (double)sizeof(T) * B * m * (2 + has_base), [&] {
+      k_lowrank<T, double><<<nwg, WG, WG * sizeof(double), st>>>(m, B, D->rank, D->V, w->DW, R2, Z2, has_base,
+                                                                 rpw, nact, w->partials);
+    });
+    L.finalize(nwg, B, ep, cs, nullptr, nact);
+  };
+
+  // ---- a2: t = M11^{-1} b1 -> X[0:n1]; f = b2 + beta A21 t -> R2; rr
+  m11(rhs, (T)1, nullptr, (T)0, X, nullptr);
+  {
+    SpmmArgs<T> a{};
+    a.row0 = n1; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+    a.x = X; a.ca = beta; a.cb = (T)0; a.parts = 1;
+    a.v = rhs + (int64_t)n1 * B; a.cv = (T)1; a.w = nullptr; a.cw = (T)0; a.y = R2;
+    a.ep = EP_RR_INIT; a.dotv = nullptr; a.cs = cs; a.n_active = nullptr;
+    L.spmm(a);
+  }
+  L.fill<T>(Dx, (int64_t)n * B, (T)0);
+  precond(EP_RZ_INIT);
+  k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 1, cs);
+
+  // ---- a3: PCG iterations, polled every check_every
+  int* hflag = (int*)((char*)w->hpin + 16384);
+  const int rpw2 = L.rows_per_wg(n2), nwg2 = Launcher::nwg_for(n2, rpw2);
+  for (int it = 0; it < max_iter; it += check_every) {
+    for (int s = 0; s < check_every && it + s < max_iter; s++) {
+      m11(nullptr, (T)0, P2, beta, X, w->n_active);   // t1' = M11^{-1} (beta A12 p2)
+      SpmmArgs<T> a{};
+      a.row0 = n1; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+      a.x = X; a.ca = -beta; a.cb = -beta; a.parts = 3;
+      a.v = P2; a.cv = (T)1; a.w = nullptr; a.cw = (T)0; a.y = Q2;       // q2 = S p2
+      a.ep = EP_PQ; a.dotv = P2; a.cs = cs; a.n_active = w->n_active;
+      L.spmm(a);
+      L.timed(PK_UPDATE_R, 6.0 * sizeof(T) * B * n2, [&] {
+        k_update_r<T><<<nwg2, WG, WG * sizeof(double), st>>>(n2, B, rpw2, K2, P2, R2, Q2, cs, w->partials);
+      });
+      L.finalize(nwg2, B, EP_RR, cs, nullptr, w->n_active);
+      precond(EP_RZ);
+      L.timed(PK_UPDATE_P, 3.0 * sizeof(T) * B * n2, [&] {
+        k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 0, cs);
+      });
+    }
+    HIPCHECK(hipMemcpyAsync(hflag, w->n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+    L.sync();
+    if (*hflag == 0) break;
+  }
+  // ---- a4: k1 = M11^{-1} (b1 + beta A12 k2) -> Dx[0:n1]
+  m11(rhs, (T)1, K2, beta, Dx, nullptr);
+}
+
+template <typename T>
+static void solve_cg(Launcher& L, const T* rhs, int max_iter, int check_every) {
+  DeviceIndex* D = L.D;
+  Workspace* w = L.w;
+  const int B = L.B, n = D->n;
+  const T beta = (T)D->beta;
+  hipStream_t st = L.st;
+  ColState cs = L.cs(max_iter);
+  T* P = (T*)w->X;
+  T* R = (T*)w->Y;
+  T* Q = (T*)w->W;
+  T* Dx = (T*)w->Dx;
+  const int64_t m = n;
+  const int rpw = L.rows_per_wg(m), nwg = Launcher::nwg_for(m, rpw);
+  // r = rhs, x = 0, p = r, rz = rr = <r, r>
+  k_axpy_mask<T, T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, rhs, nullptr, nullptr, 0);
+  L.fill<T>(Dx, m * B, (T)0);
+  L.colnorm2<T>(R, m, w->rr);
+  k_cg_init<<<1, WG, 0, st>>>(B, cs);
+  k_update_p<T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, P, 1, cs);
+  int* hflag = (int*)((char*)w->hpin + 16384);
+  for (int it = 0; it < max_iter; it += check_every) {
+    for (int s = 0; s < check_every && it + s < max_iter; s++) {
+      SpmmArgs<T> a{};
+      a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+      a.x = P; a.ca = -beta; a.cb = -beta; a.parts = 3;
+      a.v = P; a.cv = (T)1; a.w = nullptr; a.cw = (T)0; a.y = Q;
+      a.ep = EP_PQ; a.dotv = P; a.cs = cs; a.n_active = w->n_active;
+      L.spmm(a);
+      L.timed(PK_UPDATE_R, 6.0 * sizeof(T) * B * m, [&] {
+        k_update_r<T><<<nwg, WG, WG * sizeof(double), st>>>(m, B, rpw, Dx, P, R, Q, cs, w->partials);
+      });
+      L.finalize(nwg, B, EP_RR_CG, cs, nullptr, w->n_active);
+      L.timed(PK_UPDATE_P, 3.0 * sizeof(T) * B * m, [&] {
+        k_update_p<T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, P, 0, cs);
+      });
+    }
+    HIPCHECK(hipMemcpyAsync(hflag, w->n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+    L.sync();
+    if (*hflag == 0) break;
+  }
+}
+
+// ============================================================ batch driver
+void device_topk(int n, int B, int K, double* Kp, const int32_t* qpos, const int32_t* rp, const int32_t* col,
+                 const int32_t* iperm, void* scratch, size_t scratch_bytes, int32_t* ids, double* scores,
+                 hipStream_t st);
+
+namespace {
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice;
+}
+
+struct ColResult {
+  int iters = 0, sweeps = 0, path = KATZ_PATH_LRC, status = KATZ_OK;
+  double rel = 0, bn = 0;
+  bool done = false, fallback = false;
+};
+
+}  // namespace
+
+// Solves one batch of B <= 512 queries; leaves K (permuted, FP64) in w->K.
+static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStream_t st, const int32_t* q,
+                      int B, const katz_query_opts& o, std::vector<ColResult>& res) {
+  Launcher L{D, w, st, B};
+  const int n = D->n;
+  const int64_t nB = (int64_t)n * B;
+  // a1: right-hand side b = beta A e_q in the permuted order
+  int32_t* hq = (int32_t*)w->hpin;
+  for (int j = 0; j < B; j++) hq[j] = H.perm[q[j]];
+  HIPCHECK(hipMemcpyAsync(w->qpos, hq, sizeof(int32_t) * B, hipMemcpyHostToDevice, st));
+  L.fill<double>(w->Bp, nB, 0.0);
+  k_rhs_scatter<double><<<B, WG, 0, st>>>(w->qpos, B, D->rp, D->col, D->val, D->beta, w->Bp);
+  L.fill<double>(w->K, nB, 0.0);
+  L.colnorm2<double>(w->Bp, n, w->bn2);
+  double* hb = (double*)((char*)w->hpin + 8192);
+  HIPCHECK(hipMemcpyAsync(hb, w->bn2, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  std::vector<double> thr(B);
+  res.assign(B, ColResult());
+  const double tol = o.rel_tol;
+  for (int j = 0; j < B; j++) {
+    res[j].bn = std::sqrt(hb[j]);
+    thr[j] = 0.25 * tol * tol * hb[j];
+    if (hb[j] == 0.0) res[j].done = true;  // isolated query node: k = 0
+    res[j].path = o.method == KATZ_METHOD_CG ? KATZ_PATH_CG : KATZ_PATH_LRC;
+  }
+  HIPCHECK(hipMemcpyAsync(w->thr, thr.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+  std::vector<int> mask(B), hstat(B), hit(B);
+  std::vector<double> hres(B);
+  for (int sweep = 0; sweep < o.max_sweeps; sweep++) {
+    bool any = false;
+    for (int j = 0; j < B; j++) any |= !res[j].done;
+    if (!any) break;
+    const double* rhs = sweep == 0 ? w->Bp : w->Rhs;
+    // each column takes one path per sweep, chosen before the sweep starts
+    std::vector<int> on_cg(B);
+    for (int j = 0; j < B; j++) on_cg[j] = o.method == KATZ_METHOD_CG || res[j].fallback || D->n2 == 0;
+    for (int pass = 0; pass < 2; pass++) {
+      // pass 0: columns on the LRC path; pass 1: plain CG (requested or fallback)
+      bool use_cg_pass = pass == 1;
+      int cnt = 0;
+      for (int j = 0; j < B; j++) {
+        mask[j] = (!res[j].done && on_cg[j] == (int)use_cg_pass) ? 1 : 0;
+        cnt += mask[j];
+      }
+      if (!cnt) continue;
+      HIPCHECK(hipMemcpyAsync(w->mask, mask.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+      if (use_cg_pass)
+        solve_cg<double>(L, rhs, o.max_iter, o.check_every);
+      else
+        solve_lrc<double>(L, rhs, o.force_fallback ? 1 : o.max_iter, o.check_every);
+      k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, w->Dx, w->mask, nullptr, 1);
+      HIPCHECK(hipMemcpyAsync(hstat.data(), w->status, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(hit.data(), w->iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+      L.sync();
+      for (int j = 0; j < B; j++) {
+        if (!mask[j]) continue;
+        res[j].iters += hit[j];
+        if (!use_cg_pass && (hstat[j] != 0 || o.force_fallback)) {
+          res[j].fallback = true;  // breakdown or cap on the LRC path
+          res[j].path = KATZ_PATH_CG_FALLBACK;
+        }
+      }
+    }
+    // a6: true FP64 residual r = b - M k, which is the next sweep's right-hand side
+    SpmmArgs<double> a{};
+    a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+    a.x = w->K; a.ca = D->beta; a.cb = D->beta; a.parts = 3;
+    a.v = w->Bp; a.cv = 1.0; a.w = w->K; a.cw = -1.0; a.y = w->Rhs;
+    a.ep = EP_RES; a.dotv = nullptr; a.out = w->res2; a.n_active = nullptr; a.cs = L.cs(0);
+    L.spmm(a);
+    HIPCHECK(hipMemcpyAsync(hres.data(), w->res2, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+    L.sync();
+    for (int j = 0; j < B; j++) {
+      if (res[j].done) continue;
+      res[j].sweeps++;
+      res[j].rel = std::sqrt(hres[j]) / res[j].bn;
+      if (res[j].rel <= tol) res[j].done = true;
+    }
+  }
+  for (int j = 0; j < B; j++)
+    if (!res[j].done) res[j].status = KATZ_ENOCONV;
+}
+
+int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa) {
+  HIPCHECK(hipSetDevice(D->device));
+  hipStream_t st = (hipStream_t)qa.stream;
+  const int n = D->n;
+  const int BMAX = 512;
+  bool dev_scores = is_device_ptr(qa.scores);
+  bool dev_ids = is_device_ptr(qa.ids);
+  if (qa.topk > 0 && qa.topk_scores && is_device_ptr(qa.topk_scores) != dev_ids)
+    fail(KATZ_EINVAL, "ids and scores must both be host or both be device buffers");
+  int rc = KATZ_OK;
+  for (int c0 = 0; c0 < qa.nq; c0 += BMAX) {
+    const int B = std::min(BMAX, qa.nq - c0);
+    WsLease lease(D, B);
+    Workspace* w = lease.w.get();
+    std::vector<ColResult> res;
+    run_batch(H, D, w, st, qa.q + c0, B, qa.opts, res);
+    if (qa.topk > 0) {
+      const int K = qa.topk;
+      size_t need = 64 * (size_t)B + 1024 * (size_t)B + 12 * (size_t)K * B + 1024;
+      if (w->tk_cap < need) {
+        w->tk_scratch = dalloc<char>(w->allocs, (int64_t)need);
+        w->tk_cap = need;
+      }
+      int32_t* ids = qa.ids + (int64_t)c0 * K;
+      double* sc = qa.topk_scores ? qa.topk_scores + (int64_t)c0 * K : nullptr;
+      int32_t* dids = ids;
+      double* dsc = sc;
+      if (!dev_ids) {
+        if (w->tk_out_cap < (int64_t)K * B) {
+          w->tk_ids = dalloc<int32_t>(w->allocs, (int64_t)K * B);
+          w->tk_sc = dalloc<double>(w->allocs, (int64_t)K * B);
+          w->tk_out_cap = (int64_t)K * B;
+        }
+        dids = w->tk_ids;
+        dsc = sc ? w->tk_sc : nullptr;
+      }
+      device_topk(n, B, K, w->K, w->qpos, D->rp, D->col, D->iperm, w->tk_scratch, w->tk_cap, dids, dsc, st);
+      if (!dev_ids) {
+        HIPCHECK(hipMemcpyAsync(ids, dids, sizeof(int32_t) * (size_t)K * B, hipMemcpyDeviceToHost, st));
+        if (sc) HIPCHECK(hipMemcpyAsync(sc, dsc, sizeof(double) * (size_t)K * B, hipMemcpyDeviceToHost, st));
+      }
+    }
+    if (qa.scores) {
+      double* dst = qa.scores + (int64_t)c0 * n;
+      double* out = dst;
+      if (!dev_scores) {
+        if (w->out_cap < (int64_t)n * B) {
+          w->out_scores = dalloc<double>(w->allocs, (int64_t)n * B);
+          w->out_cap = (int64_t)n * B;
+        }
+        out = w->out_scores;
+      }
+      dim3 g(grid_for(n, WG * 4), B);
+      k_unpermute<double><<<g, WG, 0, st>>>(n, B, w->K, D->perm, out);
+      if (!dev_scores)
+        HIPCHECK(hipMemcpyAsync(dst, out, sizeof(double) * (size_t)n * B, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    w->prof.harvest();
+    HIPCHECK(hipGetLastError());
+    for (int j = 0; j < B; j++) {
+      if (res[j].status != KATZ_OK) rc = KATZ_ENOCONV;
+      if (qa.st) {
+        katz_query_stats& s = qa.st[c0 + j];
+        s.status = res[j].status;
+        s.iters = res[j].iters;
+        s.sweeps = res[j].sweeps;
+        s.path = res[j].path;
+        s.rel_residual = res[j].rel;
+        s.err_bound = res[j].rel * (1.0 + D->c) / (1.0 - D->c);
+      }
+    }
+  }
+  return rc;
+}
+
+int profile_enable(int on) { return g_prof_on.exchange(on ? 1 : 0); }
+void profile_reset() {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  for (int k = 0; k < PK_COUNT; k++) { g_prof.launches[k] = 0; g_prof.ms[k] = 0; g_prof.bytes[k] = 0; }
+}
+int profile_read(katz_kernel_stat* out, int max) {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  int c = 0;
+  for (int k = 0; k < PK_COUNT && c < max; k++) {
+    std::memset(&out[c], 0, sizeof(out[c]));
+    std::strncpy(out[c].name, kProfNames[k], sizeof(out[c].name) - 1);
+    out[c].launches = g_prof.launches[k];
+    out[c].total_ms = g_prof.ms[k];
+    out[c].alg_bytes = g_prof.bytes[k];
+    c++;
+  }
+  return c;
+}
+
+}  // namespace katz

@@ -1,0 +1,209 @@
+"""Parity of the HIP query path (through the C ABI) against the CPU FP64
+oracle.  GPU only.
+
+Tolerances: a returned k with true relative residual rho satisfies
+||k - k*|| / ||k*|| <= rho (1 + c) / (1 - c) (kappa(M) <= (1+c)/(1-c),
+Sec. 3.1).  Tests request rho = tau (1 - c) / (1 + c) so that the error is
+below tau (norm-wise and entrywise against ||k||), with tau = 1e-6 for the
+FP64 path and 1e-9 for the small 2,000-node SBM solved to 1e-10 residual.
+"""
+import numpy as np
+import pytest
+
+import katz_inputs as ki
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+K = pytest.importorskip("paper_1912_06525_amd")
+
+
+def _accept(kh, k, tau, what=""):
+    nk = np.linalg.norm(k)
+    err = np.linalg.norm(kh - k)
+    assert err <= tau * max(nk, 1e-300), "%s: rel err %.3e > %.1e" % (what, err / max(nk, 1e-300), tau)
+    assert np.max(np.abs(kh - k)) <= tau * max(nk, 1e-300), what
+
+
+def _check(g, idx, qs, tau, method=K.KATZ_METHOD_LRC, **kw):
+    c = idx.info.c
+    tol = tau * (1 - c) / (1 + c)
+    sc, st = idx.query(qs, tol=tol, method=method, **kw)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=idx.info.beta, lam=idx.info.lambda_max,
+                             validate=False)
+    A = oracle.csr_matrix(g.n, g.row_ptr, g.col)
+    res = oracle.katz_residual(A, idx.info.beta, qs, sc.T)
+    for j, q in enumerate(qs):
+        assert st[j]["status"] == 0, st[j]
+        _accept(sc[j], ref["k"][:, j], tau, "q=%d" % q)
+        assert res[j] <= 1.05 * tol + 1e-15, (res[j], tol)
+        assert abs(st[j]["rel_residual"] - res[j]) <= 1e-3 * tol + 1e-15
+    return sc, st
+
+
+@pytest.fixture(scope="module")
+def sbm2k():
+    w = ki.workload("sbm2k")
+    return w
+
+
+@pytest.mark.parametrize("method", [K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG])
+@pytest.mark.parametrize("rank", [0, 5, 32])
+def test_sbm2k_fp64_1e10(sbm2k, method, rank):
+    g = sbm2k.graph
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=rank, labels=g.labels, max_block=200)
+    sc, st = idx.query(sbm2k.queries, tol=1e-10, method=method)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, sbm2k.queries, beta=idx.info.beta)
+    assert st[0]["status"] == 0 and st[0]["rel_residual"] <= 1e-10
+    _accept(sc[0], ref["k_direct"][:, 0], 3.1e-10, "sbm2k")
+    assert st[0]["path"] == (K.KATZ_PATH_CG if method == K.KATZ_METHOD_CG else K.KATZ_PATH_LRC)
+
+
+def test_full_rank_converges_in_one_iteration(sbm2k):
+    # Theorem 1 with r = n2 and exact eigenvectors: S S~^{-1} = I.
+    g = ki.sbm([30, 30, 30], [0.3, 0.3, 0.3], 0.05, seed=8)
+    idx0 = K.KatzIndex.from_graph(g, beta_frac=0.8, rank=0, labels=g.labels, max_block=12, device=-1)
+    n2 = idx0.info.n2
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.8, rank=n2, labels=g.labels, max_block=12,
+                                 l_kind=K.KATZ_L_CHOL, lanczos_steps=10 ** 6)
+    qs = ki.sample_queries(g, 3, 4)
+    sc, st = _check(g, idx, qs, 1e-9)
+    assert all(s["iters"] <= 2 for s in st), st
+
+
+@pytest.mark.parametrize("lk", [K.KATZ_L_CHOL, K.KATZ_L_IDENTITY])
+@pytest.mark.parametrize("c", [0.1, 0.5, 0.9, 0.99])
+def test_small_sbm_both_factors(lk, c):
+    # dense chol(M22) is for small separators: a smaller graph for CHOL
+    g = ki.workload("lnsbm4m", scale=0.0006 if lk == K.KATZ_L_CHOL else 0.002).graph
+    idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=16, labels=g.labels, max_block=32, l_kind=lk)
+    qs = ki.sample_queries(g, 5, 31)
+    _check(g, idx, qs, 1e-6)
+
+
+def test_closed_forms_through_gpu():
+    import math
+    # star with m leaves: K_c,leaf = beta/d, K_leaf,leaf' = beta^2/d, d = 1 - m beta^2
+    m = 40
+    g = ki.from_edges(m + 1, [(0, i) for i in range(1, m + 1)])
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.9, rank=1)
+    beta = idx.info.beta
+    d = 1 - m * beta ** 2
+    sc, st = idx.query([0, 5], tol=1e-12)
+    exp0 = np.full(m + 1, beta / d)
+    exp0[0] = m * beta ** 2 / d
+    exp5 = np.full(m + 1, beta ** 2 / d)
+    exp5[0] = beta / d
+    np.testing.assert_allclose(sc[0], exp0, rtol=1e-10)
+    np.testing.assert_allclose(sc[1], exp5, rtol=1e-10)
+    assert abs(idx.info.lambda_max - math.sqrt(m)) < 1e-10
+    # complete graph K_n: K_pq = beta / ((1+beta)(1-(n-1)beta))
+    n = 30
+    g = ki.from_edges(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.7, rank=2, max_block=8)
+    beta = idx.info.beta
+    den = (1 + beta) * (1 - (n - 1) * beta)
+    sc, _ = idx.query([3], tol=1e-12)
+    exp = np.full(n, beta / den)
+    exp[3] = (n - 1) * beta ** 2 / den
+    np.testing.assert_allclose(sc[0], exp, rtol=1e-10)
+    # cycle C_n
+    n, q = 101, 7
+    g = ki.from_edges(n, [(i, (i + 1) % n) for i in range(n)])
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.8, rank=4, max_block=10)
+    beta = idx.info.beta
+    s = math.sqrt(1 - 4 * beta ** 2)
+    t = (1 - s) / (2 * beta)
+    sc, _ = idx.query([q], tol=1e-12)
+    dl = (np.arange(n) - q) % n
+    exp = (t ** dl + t ** (n - dl)) / (s * (1 - t ** n)) - (dl == 0)
+    np.testing.assert_allclose(sc[0], exp, rtol=1e-9, atol=1e-12 * np.linalg.norm(exp))
+
+
+def test_isolated_and_disconnected():
+    g = ki.from_edges(12, [(0, 1), (1, 2), (2, 0), (2, 3), (5, 6), (6, 7), (7, 8), (8, 5)])
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.6, rank=2, max_block=3)
+    sc, st = idx.query([4, 1, 6], tol=1e-12)
+    assert np.all(sc[0] == 0) and st[0]["status"] == 0          # isolated node 4
+    # exact zeros across components in exact arithmetic; the rank-r
+    # preconditioner's Ritz vectors span components, so PCG leaves rounding-level
+    # values there
+    tiny = lambda x, k: np.all(np.abs(x) <= 1e-13 * np.linalg.norm(k))
+    assert tiny(sc[1][4:], sc[1]) and np.all(sc[1][:4] > 0)
+    assert tiny(sc[2][:5], sc[2]) and tiny(sc[2][9:], sc[2]) and np.all(sc[2][5:9] > 0)
+    cg, _ = idx.query([1, 6], tol=1e-12, method=K.KATZ_METHOD_CG)
+    assert np.all(cg[0][4:] == 0) and np.all(cg[1][:5] == 0) and np.all(cg[1][9:] == 0)
+
+
+def test_batch_columns_match_single_solves():
+    g = ki.workload("lnsbm4m", scale=0.003).graph
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.7, rank=8, labels=g.labels, max_block=32)
+    qs = ki.sample_queries(g, 7, 3)
+    tol = 1e-9
+    sb, _ = idx.query(qs, tol=tol)
+    for j, q in enumerate(qs):
+        s1, _ = idx.query([q], tol=tol)
+        _accept(sb[j], s1[0], 1e-7, "batch col %d" % j)
+
+
+def test_forced_fallback_to_cg():
+    g = ki.workload("lnsbm4m", scale=0.002).graph
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.9, rank=4, labels=g.labels, max_block=32)
+    qs = ki.sample_queries(g, 3, 5)
+    # fault injection from the host: the first (LRC) sweep is declared broken
+    # down, the refinement sweeps then run plain CG on the residual
+    sc, st = idx.query(qs, tol=1e-8, force_fallback=True)
+    assert all(s["path"] == K.KATZ_PATH_CG_FALLBACK for s in st)
+    assert all(s["sweeps"] >= 1 and s["status"] == 0 for s in st)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=idx.info.beta)
+    for j in range(len(qs)):
+        _accept(sc[j], ref["k"][:, j], 1e-8 * 19 * 1.05, "fallback")
+    # an iteration cap on every path ends in KATZ_ENOCONV with the best iterate
+    sc, st = idx.query(qs, tol=1e-12, max_iter=2, max_sweeps=2)
+    assert all(s["status"] == K.KATZ_ENOCONV for s in st)
+
+
+def test_device_output_buffer():
+    import torch
+    g = ki.workload("sbm2k").graph
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=8, labels=g.labels)
+    qs = ki.sample_queries(g, 3, 99)
+    out = torch.empty((3, g.n), dtype=torch.float64, device="cuda")
+    idx.query(qs, out=out, tol=1e-10)
+    torch.cuda.synchronize()
+    host, _ = idx.query(qs, tol=1e-10)
+    assert np.array_equal(out.cpu().numpy(), host)
+
+
+@pytest.mark.parametrize("K_", [1, 10, 100])
+def test_topk_matches_oracle(K_):
+    g = ki.workload("lnsbm4m", scale=0.003).graph
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=8, labels=g.labels, max_block=32)
+    qs = ki.sample_queries(g, 4, 123)
+    tau = 1e-9
+    tol = tau * (1 - idx.info.c) / (1 + idx.info.c)
+    ids, scs, st = idx.topk(qs, K_, tol=tol)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=idx.info.beta)
+    for j, q in enumerate(qs):
+        k = ref["k"][:, j]
+        oid, osc, sid, ssc = oracle.topk_links(g.n, g.row_ptr, g.col, k, q, K_)
+        ok, msg, _ = oracle.topk_accept(ids[j], sid, ssc, K_, 2 * tau * np.linalg.norm(k))
+        assert ok, msg
+        m = ids[j] >= 0
+        np.testing.assert_allclose(scs[j][m], k[ids[j][m]], rtol=0, atol=tau * np.linalg.norm(k))
+
+
+def test_topk_ties_and_padding():
+    # star: leaf query -> every other leaf ties exactly (K_leaf,leaf' = beta^2/d);
+    # fewer candidates than k -> padding with (-1, NaN)
+    m = 9
+    g = ki.from_edges(m + 1, [(0, i) for i in range(1, m + 1)])
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=1)
+    ids, scs, _ = idx.topk([4], 12, tol=1e-12)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, [4], beta=idx.info.beta)
+    k = ref["k"][:, 0]
+    _, _, sid, ssc = oracle.topk_links(g.n, g.row_ptr, g.col, k, 4, 12)
+    ok, msg, ntie = oracle.topk_accept(ids[0], sid, ssc, 12, 2e-10 * np.linalg.norm(k))
+    assert ok, msg
+    assert sorted(ids[0][:8].tolist()) == [1, 2, 3, 5, 6, 7, 8, 9] and ids[0][8:].tolist() == [-1] * 4
+    assert np.isnan(scs[0][8:]).all() and ntie == 1
