@@ -411,7 +411,7 @@ struct M11Args {
   const T* x2;
   T ca;
   T* out;
-  int B, CB;
+  int B, CB, sub;
   const int* n_active;
 };
 
@@ -422,21 +422,31 @@ __global__ __launch_bounds__(WG) void k_m11_apply(M11Args<T> a) {
   T* u = reinterpret_cast<T*>(smem);
   const int r0 = a.tile_row0[blockIdx.x], r1 = a.tile_row0[blockIdx.x + 1], R = r1 - r0;
   const int B = a.B;
+  const int SUB = a.sub, PPP = WG / SUB;  // SUB lanes share one (row, column) gather
   for (int jc = 0; jc < B; jc += a.CB) {
     const int cb = min(a.CB, B - jc);
     const int P = R * cb;
-    for (int p = threadIdx.x; p < P; p += WG) {
-      const int i = p / cb, jj = p - i * cb, gi = r0 + i, j = jc + jj;
+    for (int pb = 0; pb < P; pb += PPP) {
+      const int p = pb + (int)threadIdx.x / SUB, sl = (int)threadIdx.x % SUB;
       T s = (T)0;
-      if (a.x2) {
-        for (int32_t k = a.split[gi]; k < a.rp[gi + 1]; k++) {
-          T xv = a.x2[(int64_t)(a.col[k] - a.n1) * B + j];
-          s += a.val ? (T)a.val[k] * xv : xv;
+      int gi = 0, j = 0;
+      if (p < P) {
+        const int i = p / cb, jj = p - i * cb;
+        gi = r0 + i;
+        j = jc + jj;
+        if (a.x2) {
+          for (int32_t k = a.split[gi] + sl; k < a.rp[gi + 1]; k += SUB) {
+            T xv = a.x2[(int64_t)(a.col[k] - a.n1) * B + j];
+            s += a.val ? (T)a.val[k] * xv : xv;
+          }
         }
-        s *= a.ca;
       }
-      if (a.v) s += a.cv * a.v[(int64_t)gi * B + j];
-      u[p] = s;
+      for (int off = 1; off < SUB; off <<= 1) s += __shfl_xor(s, off, SUB);
+      if (p < P && sl == 0) {
+        s *= a.ca;
+        if (a.v) s += a.cv * a.v[(int64_t)gi * B + j];
+        u[p] = s;
+      }
     }
     __syncthreads();
     for (int p = threadIdx.x; p < P; p += WG) {
@@ -482,36 +492,7 @@ __global__ __launch_bounds__(WG) void k_vt(int64_t m, int B, int rank, const TV*
   const int P = rank * B;
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(m, r0 + rows_per_wg);
-  if (P <= 64) {
-    double acc[64];
-#pragma unroll
-    for (int p = 0; p < 64; p++) acc[p] = 0.0;
-    for (int64_t i = r0 + tid; i < r1; i += WG) {
-      for (int j = 0; j < B; j++) {
-        const double rv = (double)r[i * B + j];
-#pragma unroll
-        for (int k = 0; k < 64; k++)
-          if (k < rank && k * B + j < 64) acc[k * B + j] += (double)V[(int64_t)k * m + i] * rv;
-      }
-    }
-    // reduce each acc[p] over the workgroup: wave shuffles, then 4 waves in LDS
-    const int wave = tid / 64, lane = tid % 64;
-#pragma unroll
-    for (int p = 0; p < 64; p++) {
-      if (p < P) {
-        double v = acc[p];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) sh[wave * 64 + p] = v;
-      }
-    }
-    __syncthreads();
-    if (tid < P) {
-      double s = 0.0;
-      for (int wv = 0; wv < WG / 64; wv++) s += sh[wv * 64 + tid];
-      partials[(int64_t)blockIdx.x * P + tid] = s;
-    }
-  } else {
+  {
     int G = 1;
     while (G * 2 * P <= WG) G <<= 1;
     for (int pb = 0; pb < P; pb += WG / G) {
@@ -531,6 +512,42 @@ __global__ __launch_bounds__(WG) void k_vt(int64_t m, int B, int rank, const TV*
         partials[(int64_t)blockIdx.x * P + pb + pl] = s;
       }
     }
+  }
+}
+
+// W = V^T r for one column (B = 1): each thread owns rows and keeps the rank
+// sums in registers (compile-time indexed), reduced by wave shuffles and LDS.
+template <typename T, typename TV, int RMAX>
+__global__ __launch_bounds__(WG) void k_vt1(int64_t m, int rank, const TV* V, const T* r, int rows_per_wg,
+                                            double* partials, const int* n_active) {
+  if (n_active && *n_active == 0) return;
+  __shared__ double sh[(WG / 64) * RMAX];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(m, r0 + rows_per_wg);
+  double acc[RMAX];
+#pragma unroll
+  for (int k = 0; k < RMAX; k++) acc[k] = 0.0;
+  for (int64_t i = r0 + tid; i < r1; i += WG) {
+    const double rv = (double)r[i];
+#pragma unroll
+    for (int k = 0; k < RMAX; k++)
+      if (k < rank) acc[k] += (double)V[(int64_t)k * m + i] * rv;
+  }
+  const int wave = tid / 64, lane = tid % 64;
+#pragma unroll
+  for (int k = 0; k < RMAX; k++) {
+    if (k < rank) {
+      double v = acc[k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) sh[wave * RMAX + k] = v;
+    }
+  }
+  __syncthreads();
+  if (tid < rank) {
+    double s = 0.0;
+    for (int wv = 0; wv < WG / 64; wv++) s += sh[wv * RMAX + tid];
+    partials[(int64_t)blockIdx.x * rank + tid] = s;
   }
 }
 
@@ -628,6 +645,15 @@ __global__ __launch_bounds__(WG) void k_finalize(const double* partials, int nwg
     }
   });
   if (ep == EP_PQ || ep == EP_RR_INIT || ep == EP_RR || ep == EP_RR_CG) recount_active(cs, B);
+}
+
+// Start of a batch: stop thresholds on the recurrence residual and the first
+// sweep's column mask (columns with b = 0 are done: k = 0).
+__global__ void k_cols_setup(int B, const double* bn2, double scale, double* thr, int* mask) {
+  for (int j = threadIdx.x; j < B; j += blockDim.x) {
+    thr[j] = scale * bn2[j];
+    mask[j] = bn2[j] > 0.0 ? 1 : 0;
+  }
 }
 
 // Plain-CG start: rz = rr, active = mask && rr > thr.
@@ -909,6 +935,35 @@ void device_free(DeviceIndex* D) {
 int64_t device_bytes(const DeviceIndex* D) { return D ? D->bytes : 0; }
 int64_t device_factor_bytes(const DeviceIndex* D) { return D ? D->factor_bytes : 0; }
 
+// ================================================================== tuning
+// Launch shapes (overridable from the environment for tuning sweeps).  Every
+// partials buffer is sized from these limits.
+struct Tuning {
+  int ts1;          // lanes per row of the one-column SpMM (4, 8, 16, 32)
+  int spmm_nwg;     // max short-row workgroups of the SpMM
+  int rows_team;    // target rows per team of the SpMM
+  int ew_nwg;       // max workgroups of the row-parallel reduction kernels
+  int ew_rows;      // target rows per workgroup of those kernels
+};
+static int env_int(const char* name, int dflt, int lo, int hi) {
+  const char* e = getenv(name);
+  int v = e ? atoi(e) : dflt;
+  return (v >= lo && v <= hi) ? v : dflt;
+}
+static const Tuning& tuning() {
+  static const Tuning t = [] {
+    Tuning u;
+    u.ts1 = env_int("KATZ_SPMM_TS1", 8, 4, 32);
+    if (u.ts1 != 4 && u.ts1 != 8 && u.ts1 != 16 && u.ts1 != 32) u.ts1 = 8;
+    u.spmm_nwg = env_int("KATZ_SPMM_NWG", 8192, 64, 65536);
+    u.rows_team = env_int("KATZ_SPMM_ROWS_PER_TEAM", 1, 1, 64);
+    u.ew_nwg = env_int("KATZ_EW_NWG", 1024, 64, 65536);
+    u.ew_rows = env_int("KATZ_EW_ROWS", 256, 16, 65536);
+    return u;
+  }();
+  return t;
+}
+
 // ================================================================ workspace
 static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   auto w = std::make_unique<Workspace>();
@@ -926,8 +981,13 @@ static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   w->Y = dalloc<double>(L, nB);
   w->W = dalloc<double>(L, nB);
   w->Z = dalloc<double>(L, (int64_t)std::max(1, D->n2) * B);
-  w->partials_cap = (size_t)(4096 + std::max(D->n_long_all, D->n_long_sep)) * std::max(B, 1) +
-                    (size_t)2048 * std::max(1, D->rank) * B;
+  {
+    // largest producer: SpMM (short + hub workgroups) x B, or a row-parallel
+    // kernel x max(B, rank * B)
+    const Tuning& tu = tuning();
+    size_t wgs = std::max<size_t>((size_t)tu.spmm_nwg + std::max(D->n_long_all, D->n_long_sep), (size_t)tu.ew_nwg);
+    w->partials_cap = wgs * (size_t)std::max(1, D->rank) * (size_t)std::max(B, 1);
+  }
   w->partials = dalloc<double>(L, (int64_t)w->partials_cap);
   w->DW = dalloc<double>(L, (int64_t)std::max(1, D->rank) * B);
   double* s = dalloc<double>(L, 9 * (int64_t)B);
@@ -1004,14 +1064,19 @@ struct Launcher {
 
   // Workgroups for the elementwise reduction kernels over m rows.
   int rows_per_wg(int64_t m) const {
-    int64_t nwg = std::min<int64_t>(1024, std::max<int64_t>(1, (m + 255) / 256));
+    const Tuning& tu = tuning();
+    int64_t nwg = std::min<int64_t>(tu.ew_nwg, std::max<int64_t>(1, (m + tu.ew_rows - 1) / tu.ew_rows));
     return (int)((m + nwg - 1) / nwg);
+  }
+  // Checked before every launch that writes nwg x nv partial sums.
+  void need(int64_t nwg, int64_t nv) const {
+    if ((size_t)(nwg * nv) > w->partials_cap) fail(KATZ_EDEVICE, "internal: partials buffer too small");
   }
   static int nwg_for(int64_t m, int rpw) { return (int)((m + rpw - 1) / rpw); }
 
   // Reduces nwg x nv partials and applies the epilogue `ep` (one workgroup).
   void finalize(int nwg, int nv, int ep, const ColState& cs, double* out, const int* nact) {
-    if ((size_t)nwg * nv > w->partials_cap) fail(KATZ_EDEVICE, "internal: partials buffer too small");
+    need(nwg, nv);
     k_finalize<<<1, WG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact);
   }
 
@@ -1024,7 +1089,8 @@ struct Launcher {
     }
     a.B = B;
     int TS, CW;
-    if (B == 1) { TS = 8; CW = 1; }
+    const Tuning& tu = tuning();
+    if (B == 1) { TS = tu.ts1; CW = 1; }
     else if (B == 2) { TS = 8; CW = 2; }
     else if (B <= 4) { TS = 16; CW = 4; }
     else if (B <= 8) { TS = 32; CW = 8; }
@@ -1033,7 +1099,8 @@ struct Launcher {
     else { TS = 64; CW = 64; }
     if (B > MAXC * CW) fail(KATZ_EINVAL, "batch too wide for one launch");
     const int teams = WG / TS;
-    int64_t nwg = std::min<int64_t>(1024, std::max<int64_t>(1, (rows + teams * 4 - 1) / (teams * 4)));
+    int64_t nwg = std::min<int64_t>(tu.spmm_nwg,
+                                    std::max<int64_t>(1, (rows + teams * tu.rows_team - 1) / (teams * tu.rows_team)));
     a.rows_per_wg = (int)((rows + nwg - 1) / nwg);
     nwg = (rows + a.rows_per_wg - 1) / a.rows_per_wg;
     a.partials = w->partials;
@@ -1043,7 +1110,7 @@ struct Launcher {
     else { a.long_rows = nullptr; a.n_long = 0; }
     if (a.n_long == 0) a.long_rows = nullptr;
     const int nwg_all = (int)nwg + a.n_long;
-    if ((size_t)nwg_all * B > w->partials_cap) fail(KATZ_EDEVICE, "internal: partials buffer too small");
+    need(nwg_all, B);
     size_t shm = sizeof(double) * std::max<size_t>((size_t)teams * B, (size_t)(WG / 64) * MAXC * CW);
     dim3 g((unsigned)nwg_all);
     // algorithmic bytes: row pointers and splits, the selected entries, each
@@ -1063,7 +1130,7 @@ struct Launcher {
     timed(kind, bytes, [&] { k_spmm<T, ts, cw><<<g, WG, shm, st>>>(a); });                 \
     launched = true;                                                                       \
   }
-    KZ_SPMM(8, 1) KZ_SPMM(8, 2) KZ_SPMM(16, 4) KZ_SPMM(32, 8) KZ_SPMM(64, 16) KZ_SPMM(64, 32) KZ_SPMM(64, 64)
+    KZ_SPMM(4, 1) KZ_SPMM(8, 1) KZ_SPMM(16, 1) KZ_SPMM(32, 1) KZ_SPMM(8, 2) KZ_SPMM(16, 4) KZ_SPMM(32, 8) KZ_SPMM(64, 16) KZ_SPMM(64, 32) KZ_SPMM(64, 64)
 #undef KZ_SPMM
     if (a.ep != EP_NONE) finalize(nwg_all, B, a.ep, a.cs, a.out, a.n_active);
   }
@@ -1072,10 +1139,15 @@ struct Launcher {
   template <typename T>
   void colnorm2(const T* p, int64_t m, double* out) {
     const int rpw = rows_per_wg(m), nwg = nwg_for(m, rpw);
+    need(nwg, B);
     k_colnorm2<T><<<nwg, WG, WG * sizeof(double), st>>>(p, m, B, rpw, w->partials);
     finalize(nwg, B, EP_NORM, cs(0), out, nullptr);
   }
 };
+
+// Pinned host staging (w->hpin, 64 KiB), B <= 512:
+constexpr size_t kPinQ = 0, kPinMask0 = 2048, kPinMask1 = 4096, kPinBn2 = 8192, kPinRes = 12288,
+                 kPinFlag = 16384, kPinStat0 = 20480, kPinIter0 = 22528, kPinStat1 = 24576, kPinIter1 = 26624;
 
 // ============================================================ solve sweeps
 // One correction solve M d = rhs for the columns in w->mask; d is left in
@@ -1105,6 +1177,7 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     a.v = v; a.cv = cv; a.x2 = x2; a.ca = ca; a.out = out; a.B = B; a.n_active = nact;
     int cb = std::max(1, std::min(B, (int)(32768 / sizeof(T) / std::max(1, D->max_tile_rows))));
     a.CB = cb;
+    a.sub = cb >= 16 ? 1 : (cb >= 4 ? 2 : 4);
     size_t shm = (size_t)D->max_tile_rows * cb * sizeof(T);
     const double wb = (double)sizeof(T) * B;
     double bytes = (double)sizeof(T) * D->minv_elems + 4.0 * n1 + wb * n1 + (v ? wb * n1 : 0.0) +
@@ -1116,9 +1189,15 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     const int64_t m = n2;
     const int rpw = L.rows_per_wg(m), nwg = Launcher::nwg_for(m, rpw);
     const int* nact = ep == EP_RZ ? w->n_active : nullptr;
+    L.need(nwg, (int64_t)std::max(1, D->rank) * B);
     if (D->rank > 0) {
-      L.timed(PK_VT, 8.0 * m * D->rank + (double)sizeof(T) * B * m, [&] {
-        k_vt<T, double><<<nwg, WG, 0, st>>>(m, B, D->rank, D->V, R2, rpw, w->partials, nact);
+      const int rk = D->rank;
+      L.timed(PK_VT, 8.0 * m * rk + (double)sizeof(T) * B * m, [&] {
+        if (B == 1 && rk <= 8) k_vt1<T, double, 8><<<nwg, WG, 0, st>>>(m, rk, D->V, R2, rpw, w->partials, nact);
+        else if (B == 1 && rk <= 16) k_vt1<T, double, 16><<<nwg, WG, 0, st>>>(m, rk, D->V, R2, rpw, w->partials, nact);
+        else if (B == 1 && rk <= 32) k_vt1<T, double, 32><<<nwg, WG, 0, st>>>(m, rk, D->V, R2, rpw, w->partials, nact);
+        else if (B == 1 && rk <= 64) k_vt1<T, double, 64><<<nwg, WG, 0, st>>>(m, rk, D->V, R2, rpw, w->partials, nact);
+        else k_vt<T, double><<<nwg, WG, 0, st>>>(m, B, rk, D->V, R2, rpw, w->partials, nact);
       });
       L.finalize(nwg, D->rank * B, EP_VT, cs, w->DW, nact);
     }
@@ -1151,8 +1230,9 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
   k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 1, cs);
 
   // ---- a3: PCG iterations, polled every check_every
-  int* hflag = (int*)((char*)w->hpin + 16384);
+  int* hflag = (int*)((char*)w->hpin + kPinFlag);
   const int rpw2 = L.rows_per_wg(n2), nwg2 = Launcher::nwg_for(n2, rpw2);
+  L.need(nwg2, B);
   for (int it = 0; it < max_iter; it += check_every) {
     for (int s = 0; s < check_every && it + s < max_iter; s++) {
       m11(nullptr, (T)0, P2, beta, X, w->n_active);   // t1' = M11^{-1} (beta A12 p2)
@@ -1193,13 +1273,14 @@ static void solve_cg(Launcher& L, const T* rhs, int max_iter, int check_every) {
   T* Dx = (T*)w->Dx;
   const int64_t m = n;
   const int rpw = L.rows_per_wg(m), nwg = Launcher::nwg_for(m, rpw);
+  L.need(nwg, B);
   // r = rhs, x = 0, p = r, rz = rr = <r, r>
   k_axpy_mask<T, T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, rhs, nullptr, nullptr, 0);
   L.fill<T>(Dx, m * B, (T)0);
   L.colnorm2<T>(R, m, w->rr);
   k_cg_init<<<1, WG, 0, st>>>(B, cs);
   k_update_p<T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, P, 1, cs);
-  int* hflag = (int*)((char*)w->hpin + 16384);
+  int* hflag = (int*)((char*)w->hpin + kPinFlag);
   for (int it = 0; it < max_iter; it += check_every) {
     for (int s = 0; s < check_every && it + s < max_iter; s++) {
       SpmmArgs<T> a{};
@@ -1249,68 +1330,59 @@ struct ColResult {
 }  // namespace
 
 // Solves one batch of B <= 512 queries; leaves K (permuted, FP64) in w->K.
+
 static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStream_t st, const int32_t* q,
                       int B, const katz_query_opts& o, std::vector<ColResult>& res) {
   Launcher L{D, w, st, B};
   const int n = D->n;
   const int64_t nB = (int64_t)n * B;
+  char* pin = (char*)w->hpin;
   // a1: right-hand side b = beta A e_q in the permuted order
-  int32_t* hq = (int32_t*)w->hpin;
+  int32_t* hq = (int32_t*)(pin + kPinQ);
   for (int j = 0; j < B; j++) hq[j] = H.perm[q[j]];
   HIPCHECK(hipMemcpyAsync(w->qpos, hq, sizeof(int32_t) * B, hipMemcpyHostToDevice, st));
   L.fill<double>(w->Bp, nB, 0.0);
   k_rhs_scatter<double><<<B, WG, 0, st>>>(w->qpos, B, D->rp, D->col, D->val, D->beta, w->Bp);
   L.fill<double>(w->K, nB, 0.0);
   L.colnorm2<double>(w->Bp, n, w->bn2);
-  double* hb = (double*)((char*)w->hpin + 8192);
-  HIPCHECK(hipMemcpyAsync(hb, w->bn2, sizeof(double) * B, hipMemcpyDeviceToHost, st));
-  HIPCHECK(hipStreamSynchronize(st));
-  std::vector<double> thr(B);
-  res.assign(B, ColResult());
+  // thresholds and the first sweep's mask on the device (no host round trip)
   const double tol = o.rel_tol;
-  for (int j = 0; j < B; j++) {
-    res[j].bn = std::sqrt(hb[j]);
-    thr[j] = 0.25 * tol * tol * hb[j];
-    if (hb[j] == 0.0) res[j].done = true;  // isolated query node: k = 0
-    res[j].path = o.method == KATZ_METHOD_CG ? KATZ_PATH_CG : KATZ_PATH_LRC;
-  }
-  HIPCHECK(hipMemcpyAsync(w->thr, thr.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
-  std::vector<int> mask(B), hstat(B), hit(B);
-  std::vector<double> hres(B);
+  k_cols_setup<<<1, WG, 0, st>>>(B, w->bn2, 0.25 * tol * tol, w->thr, w->mask);
+  res.assign(B, ColResult());
+  for (int j = 0; j < B; j++) res[j].path = o.method == KATZ_METHOD_CG ? KATZ_PATH_CG : KATZ_PATH_LRC;
+  double* hb = (double*)(pin + kPinBn2);
+  double* hres = (double*)(pin + kPinRes);
+  bool have_bn = false;
   for (int sweep = 0; sweep < o.max_sweeps; sweep++) {
     bool any = false;
     for (int j = 0; j < B; j++) any |= !res[j].done;
     if (!any) break;
     const double* rhs = sweep == 0 ? w->Bp : w->Rhs;
     // each column takes one path per sweep, chosen before the sweep starts
-    std::vector<int> on_cg(B);
-    for (int j = 0; j < B; j++) on_cg[j] = o.method == KATZ_METHOD_CG || res[j].fallback || D->n2 == 0;
+    int ran[2] = {0, 0};
     for (int pass = 0; pass < 2; pass++) {
       // pass 0: columns on the LRC path; pass 1: plain CG (requested or fallback)
-      bool use_cg_pass = pass == 1;
+      const bool cg_pass = pass == 1;
+      int* hm = (int*)(pin + (pass ? kPinMask1 : kPinMask0));
       int cnt = 0;
       for (int j = 0; j < B; j++) {
-        mask[j] = (!res[j].done && on_cg[j] == (int)use_cg_pass) ? 1 : 0;
-        cnt += mask[j];
+        const bool on_cg = o.method == KATZ_METHOD_CG || res[j].fallback || D->n2 == 0;
+        hm[j] = (!res[j].done && on_cg == cg_pass) ? 1 : 0;
+        cnt += hm[j];
       }
       if (!cnt) continue;
-      HIPCHECK(hipMemcpyAsync(w->mask, mask.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
-      if (use_cg_pass)
+      ran[pass] = 1;
+      // sweep 0: the device mask (b != 0) is already in place
+      if (sweep > 0) HIPCHECK(hipMemcpyAsync(w->mask, hm, sizeof(int) * B, hipMemcpyHostToDevice, st));
+      if (cg_pass)
         solve_cg<double>(L, rhs, o.max_iter, o.check_every);
       else
         solve_lrc<double>(L, rhs, o.force_fallback ? 1 : o.max_iter, o.check_every);
       k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, w->Dx, w->mask, nullptr, 1);
-      HIPCHECK(hipMemcpyAsync(hstat.data(), w->status, sizeof(int) * B, hipMemcpyDeviceToHost, st));
-      HIPCHECK(hipMemcpyAsync(hit.data(), w->iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
-      L.sync();
-      for (int j = 0; j < B; j++) {
-        if (!mask[j]) continue;
-        res[j].iters += hit[j];
-        if (!use_cg_pass && (hstat[j] != 0 || o.force_fallback)) {
-          res[j].fallback = true;  // breakdown or cap on the LRC path
-          res[j].path = KATZ_PATH_CG_FALLBACK;
-        }
-      }
+      HIPCHECK(hipMemcpyAsync(pin + (pass ? kPinStat1 : kPinStat0), w->status, sizeof(int) * B,
+                              hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(pin + (pass ? kPinIter1 : kPinIter0), w->iters, sizeof(int) * B,
+                              hipMemcpyDeviceToHost, st));
     }
     // a6: true FP64 residual r = b - M k, which is the next sweep's right-hand side
     SpmmArgs<double> a{};
@@ -1319,8 +1391,33 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
     a.v = w->Bp; a.cv = 1.0; a.w = w->K; a.cw = -1.0; a.y = w->Rhs;
     a.ep = EP_RES; a.dotv = nullptr; a.out = w->res2; a.n_active = nullptr; a.cs = L.cs(0);
     L.spmm(a);
-    HIPCHECK(hipMemcpyAsync(hres.data(), w->res2, sizeof(double) * B, hipMemcpyDeviceToHost, st));
-    L.sync();
+    HIPCHECK(hipMemcpyAsync(hres, w->res2, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+    if (!have_bn) HIPCHECK(hipMemcpyAsync(hb, w->bn2, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+    L.sync();  // one host round trip per sweep
+    if (!have_bn) {
+      for (int j = 0; j < B; j++) {
+        res[j].bn = std::sqrt(hb[j]);
+        if (hb[j] == 0.0) {  // isolated query node: k = 0 exactly
+          res[j].done = true;
+          res[j].rel = 0.0;
+        }
+      }
+      have_bn = true;
+    }
+    for (int pass = 0; pass < 2; pass++) {
+      if (!ran[pass]) continue;
+      const int* hm = (const int*)(pin + (pass ? kPinMask1 : kPinMask0));
+      const int* hs = (const int*)(pin + (pass ? kPinStat1 : kPinStat0));
+      const int* hi = (const int*)(pin + (pass ? kPinIter1 : kPinIter0));
+      for (int j = 0; j < B; j++) {
+        if (!hm[j] || res[j].bn == 0.0) continue;
+        res[j].iters += hi[j];
+        if (pass == 0 && (hs[j] != 0 || o.force_fallback)) {
+          res[j].fallback = true;  // breakdown or cap on the LRC path
+          res[j].path = KATZ_PATH_CG_FALLBACK;
+        }
+      }
+    }
     for (int j = 0; j < B; j++) {
       if (res[j].done) continue;
       res[j].sweeps++;
