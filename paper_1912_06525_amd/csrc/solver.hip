@@ -13,6 +13,7 @@
 // M12 = -beta A12, M22 = I - beta A22 and M11 = I - beta A11 are applied from
 // one permuted CSR of A whose rows carry a split between block columns and
 // separator columns.
+#include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +22,7 @@
 #include <atomic>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 
 #include "katz_internal.h"
 #include "kernels.h"
@@ -33,6 +35,11 @@
 
 namespace katz {
 using namespace dev;
+
+typedef __hip_bfloat16 bf16;
+__device__ inline double to_d(double x) { return x; }
+__device__ inline double to_d(float x) { return (double)x; }
+__device__ inline double to_d(bf16 x) { return (double)__bfloat162float(x); }
 
 enum Ep { EP_NONE = 0, EP_PQ = 1, EP_RES = 2, EP_RR_INIT = 3, EP_RR = 4, EP_RZ_INIT = 5, EP_RZ = 6,
           EP_RR_CG = 7, EP_NORM = 8, EP_VT = 9 };
@@ -501,7 +508,7 @@ __global__ __launch_bounds__(WG) void k_vt(int64_t m, int B, int rank, const TV*
       double acc = 0.0;
       if (pl < pw) {
         const int p = pb + pl, k = p / B, j = p - k * B;
-        for (int64_t i = r0 + g; i < r1; i += G) acc += (double)V[(int64_t)k * m + i] * (double)r[i * B + j];
+        for (int64_t i = r0 + g; i < r1; i += G) acc += to_d(V[(int64_t)k * m + i]) * (double)r[i * B + j];
       }
       __syncthreads();
       sh[tid] = acc;
@@ -531,7 +538,7 @@ __global__ __launch_bounds__(WG) void k_vt1(int64_t m, int rank, const TV* V, co
     const double rv = (double)r[i];
 #pragma unroll
     for (int k = 0; k < RMAX; k++)
-      if (k < rank) acc[k] += (double)V[(int64_t)k * m + i] * rv;
+      if (k < rank) acc[k] += to_d(V[(int64_t)k * m + i]) * rv;
   }
   const int wave = tid / 64, lane = tid % 64;
 #pragma unroll
@@ -568,12 +575,161 @@ __global__ __launch_bounds__(WG) void k_lowrank(int64_t m, int B, int rank, cons
       if (j >= B) continue;
       const int64_t o = i * B + j;
       double s = z_has_base ? (double)z[o] : (double)r[o];
-      for (int k = 0; k < rank; k++) s += (double)V[(int64_t)k * m + i] * DW[k * B + j];
+      for (int k = 0; k < rank; k++) s += to_d(V[(int64_t)k * m + i]) * DW[k * B + j];
       T zv = (T)s;
       z[o] = zv;
       dacc[c] += (double)r[o] * (double)zv;
     }
   wg_colsum(cm, B, dacc, partials);
+}
+
+// ------------------------------------------- low-rank GEMMs on MFMA (bf16)
+// FP32 panels, BF16 V: v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  The
+// FP32 panel operand is split into bf16 hi + lo parts (two MFMAs), so the
+// product keeps ~16 mantissa bits; V itself is stored in BF16.
+// Operand lanes (16x16x32): a[t] = A[l % 16][8 (l / 16) + t],
+// b[t] = B[8 (l / 16) + t][l % 16]; result d[t] = D[4 (l / 16) + t][l % 16].
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// W partials: workgroup (jt, kt, s) computes the 32 (k) x 64 (j) tile of
+// V^T r over row chunk s; wave w owns columns j0 + 16 w and both k halves.
+// V16: column-major n2 x rank (bf16); r: m x B FP32.
+__global__ __launch_bounds__(WG) void k_vt_mfma(int64_t m, int B, int rank, const bf16* V16, const float* r,
+                                                int64_t rows_per_chunk, double* partials, const int* n_active) {
+  if (n_active && *n_active == 0) return;
+  const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
+  const int j0 = blockIdx.x * 64 + wave * 16;
+  const int k0 = blockIdx.y * 32;
+  const int64_t i_beg = (int64_t)blockIdx.z * rows_per_chunk;
+  const int64_t i_end = min<int64_t>(m, i_beg + rows_per_chunk);
+  const int jn = j0 + (l % 16);
+  const bool jok = jn < B;
+  const __bf16* Vb = reinterpret_cast<const __bf16*>(V16);
+  floatx4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  for (int64_t i0 = i_beg; i0 < i_end; i0 += 32) {
+    bf16x8 bh, bl, a0, a1;
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      const int64_t i = i0 + 8 * (l / 16) + t;
+      const bool iok = i < i_end;
+      const float x = (iok && jok) ? r[i * B + jn] : 0.0f;
+      __bf16 h, lo;
+      split_bf16(x, h, lo);
+      bh[t] = h;
+      bl[t] = lo;
+      const int ka = k0 + (l % 16), kb = k0 + 16 + (l % 16);
+      a0[t] = (iok && ka < rank) ? Vb[(int64_t)ka * m + i] : (__bf16)0.0f;
+      a1[t] = (iok && kb < rank) ? Vb[(int64_t)kb * m + i] : (__bf16)0.0f;
+    }
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bh, acc0, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bl, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bh, acc1, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bl, acc1, 0, 0, 0);
+  }
+  // d[t] = W[k0 + 4 (l / 16) + t][jn] (acc0), W[k0 + 16 + 4 (l / 16) + t][jn] (acc1)
+  const int64_t P = (int64_t)rank * B;
+  double* out = partials + (int64_t)blockIdx.z * P;
+  if (jok) {
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int ka = k0 + 4 * (l / 16) + t, kb = k0 + 16 + 4 * (l / 16) + t;
+      if (ka < rank) out[(int64_t)ka * B + jn] = (double)acc0[t];
+      if (kb < rank) out[(int64_t)kb * B + jn] = (double)acc1[t];
+    }
+  }
+}
+
+// z = base + V DW for 64-row x 64-column tiles (grid-stride over row tiles),
+// base = r or the stored z; plus per-column partial dots <r, z>.
+// V16r: row-major n2 x rank (bf16); DW: rank x B (FP64, split to bf16 hi/lo in LDS).
+__global__ __launch_bounds__(WG) void k_lowrank_mfma(int64_t m, int B, int rank, const bf16* V16r, const double* DW,
+                                                     const float* r, float* z, int z_has_base, double* partials,
+                                                     const int* n_active) {
+  if (n_active && *n_active == 0) return;
+  extern __shared__ unsigned char smem_lr[];
+  const int KP = (rank + 31) / 32 * 32;             // rank padded to the MFMA depth
+  __bf16* dh = reinterpret_cast<__bf16*>(smem_lr);  // [KP][64]
+  __bf16* dl = dh + KP * 64;
+  double* red = reinterpret_cast<double*>(dl + KP * 64);  // [4 waves][64]
+  const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
+  const int jb = blockIdx.y * 64;
+  for (int e = threadIdx.x; e < KP * 64; e += WG) {
+    const int k = e / 64, jj = e % 64;
+    const float v = (k < rank && jb + jj < B) ? (float)DW[(int64_t)k * B + jb + jj] : 0.0f;
+    __bf16 h, lo;
+    split_bf16(v, h, lo);
+    dh[e] = h;
+    dl[e] = lo;
+  }
+  __syncthreads();
+  const __bf16* Vb = reinterpret_cast<const __bf16*>(V16r);
+  double dacc[4] = {0.0, 0.0, 0.0, 0.0};  // column jb + 16 c + l % 16
+  const int64_t ntile = (m + 63) / 64;
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t i0 = tile * 64 + wave * 16;  // this wave's 16 rows
+    floatx4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) acc[c] = (floatx4){0, 0, 0, 0};
+    for (int k0 = 0; k0 < KP; k0 += 32) {
+      bf16x8 a;
+      const int64_t ia = i0 + (l % 16);
+#pragma unroll
+      for (int t = 0; t < 8; t++) {
+        const int k = k0 + 8 * (l / 16) + t;
+        a[t] = (ia < m && k < rank) ? Vb[ia * rank + k] : (__bf16)0.0f;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        bf16x8 bh, bl;
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+          const int e = (k0 + 8 * (l / 16) + t) * 64 + 16 * c + (l % 16);
+          bh[t] = dh[e];
+          bl[t] = dl[e];
+        }
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[c], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const int j = jb + 16 * c + (l % 16);
+      if (j >= B) continue;
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const int64_t i = i0 + 4 * (l / 16) + t;
+        if (i >= m) continue;
+        const int64_t o = i * B + j;
+        const float base = z_has_base ? z[o] : r[o];
+        const float zv = base + acc[c][t];
+        z[o] = zv;
+        dacc[c] += (double)r[o] * (double)zv;
+      }
+    }
+  }
+  // per-column sums: the 4 lanes l, l^16, l^32, l^48 share a column in a wave
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    double v = dacc[c];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (l < 16) red[wave * 64 + 16 * c + l] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int j = jb + threadIdx.x;
+    if (j < B) {
+      double sum = 0.0;
+      for (int wv = 0; wv < WG / 64; wv++) sum += red[wv * 64 + threadIdx.x];
+      partials[(int64_t)blockIdx.x * B + j] = sum;
+    }
+  }
 }
 
 // One workgroup: reduces the producer's per-workgroup partials (fixed order)
@@ -653,6 +809,21 @@ __global__ void k_cols_setup(int B, const double* bn2, double scale, double* thr
   for (int j = threadIdx.x; j < B; j += blockDim.x) {
     thr[j] = scale * bn2[j];
     mask[j] = bn2[j] > 0.0 ? 1 : 0;
+  }
+}
+
+// Precision form, per sweep: the FP64 right-hand side is scaled to unit norm
+// per column for the FP32 inner solve (inv), the correction is scaled back
+// (fwd), and the inner stop threshold is the larger of the FP32 floor and half
+// the outer tolerance relative to this right-hand side.
+__global__ void k_mixed_scales(int B, const double* rn2, const double* bn2, double tol, double eps,
+                               double* inv, double* fwd, double* thr) {
+  for (int j = threadIdx.x; j < B; j += blockDim.x) {
+    const double rn = sqrt(rn2[j]);
+    inv[j] = rn > 0.0 ? 1.0 / rn : 0.0;
+    fwd[j] = rn;
+    const double t = rn > 0.0 ? fmax(eps, 0.5 * tol * sqrt(bn2[j]) / rn) : 1.0;
+    thr[j] = t * t;
   }
 }
 
@@ -745,7 +916,8 @@ struct Workspace {
   double* partials = nullptr;
   size_t partials_cap = 0;
   double* DW = nullptr;
-  double *rz, *pq, *alpha, *bcg, *rr, *thr, *bn2, *res2, *colscale;
+  double *rz, *pq, *alpha, *bcg, *rr, *thr, *bn2, *res2, *colscale, *rn2, *inv, *fwd;
+  float* Rf = nullptr;             // scaled FP32 right-hand side (precision form)
   int *active, *status, *iters, *n_active, *mask;
   int32_t* qpos = nullptr;
   double* out_scores = nullptr;  // staging for host output
@@ -776,6 +948,11 @@ struct DeviceIndex {
   double* ginv = nullptr;
   double* V = nullptr;
   double* D = nullptr;
+  // precision form: FP32 block inverses and G, BF16 low-rank factor
+  float* minv32 = nullptr;
+  float* ginv32 = nullptr;
+  bf16* V16 = nullptr;      // column-major n2 x r
+  bf16* V16r = nullptr;     // row-major n2 x r (MFMA operand layout)
   int64_t bytes = 0, factor_bytes = 0;
   std::vector<void*> allocs;
   std::mutex mu;
@@ -809,6 +986,16 @@ T* upload(std::vector<void*>& list, const std::vector<T>& h, int64_t* bytes) {
   T* d = dalloc<T>(list, (int64_t)h.size(), bytes);
   if (!h.empty()) HIPCHECK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   return d;
+}
+
+// float -> bfloat16 bits, round to nearest even (NaN kept quiet)
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
 }
 
 int grid_for(int64_t work, int per) {
@@ -904,12 +1091,28 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
     D->minv = upload(D->allocs, H.minv, by);
     D->factor_bytes = D->bytes - fb0;
     if (H.l_kind == KATZ_L_CHOL && H.n2 > 0) D->ginv = upload(D->allocs, H.ginv, by);
+    if (H.precision == KATZ_PREC_MIXED) {
+      std::vector<float> m32(H.minv.begin(), H.minv.end());
+      D->minv32 = upload(D->allocs, m32, by);
+      if (D->ginv) {
+        std::vector<float> g32(H.ginv.begin(), H.ginv.end());
+        D->ginv32 = upload(D->allocs, g32, by);
+      }
+    }
     if (H.rank > 0) {
       std::vector<double> vc((size_t)H.n2 * H.rank);  // column-major copy
       for (int64_t i = 0; i < H.n2; i++)
         for (int k = 0; k < H.rank; k++) vc[(size_t)k * H.n2 + i] = H.V[(size_t)i * H.rank + k];
       D->V = upload(D->allocs, vc, by);
       D->D = upload(D->allocs, H.D, by);
+      if (H.precision == KATZ_PREC_MIXED) {
+        std::vector<uint16_t> vb(vc.size()), vr(vc.size());
+        for (size_t t = 0; t < vc.size(); t++) vb[t] = bf16_bits((float)vc[t]);
+        for (int64_t i = 0; i < H.n2; i++)
+          for (int k = 0; k < H.rank; k++) vr[(size_t)i * H.rank + k] = bf16_bits((float)H.V[(size_t)i * H.rank + k]);
+        D->V16 = (bf16*)upload(D->allocs, vb, by);
+        D->V16r = (bf16*)upload(D->allocs, vr, by);
+      }
     }
     HIPCHECK(hipDeviceSynchronize());
   } catch (...) {
@@ -934,6 +1137,22 @@ void device_free(DeviceIndex* D) {
 }
 int64_t device_bytes(const DeviceIndex* D) { return D ? D->bytes : 0; }
 int64_t device_factor_bytes(const DeviceIndex* D) { return D ? D->factor_bytes : 0; }
+
+// Factor storage for a panel type: FP64 panels use the FP64 factors, FP32
+// panels the FP32 block inverses and the BF16 low-rank factor.
+template <typename T> struct Factors;
+template <> struct Factors<double> {
+  typedef double TV;
+  static const double* minv(const DeviceIndex* D) { return D->minv; }
+  static const double* ginv(const DeviceIndex* D) { return D->ginv; }
+  static const double* V(const DeviceIndex* D) { return D->V; }
+};
+template <> struct Factors<float> {
+  typedef bf16 TV;
+  static const float* minv(const DeviceIndex* D) { return D->minv32; }
+  static const float* ginv(const DeviceIndex* D) { return D->ginv32; }
+  static const bf16* V(const DeviceIndex* D) { return D->V16; }
+};
 
 // ================================================================== tuning
 // Launch shapes (overridable from the environment for tuning sweeps).  Every
@@ -990,12 +1209,14 @@ static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   }
   w->partials = dalloc<double>(L, (int64_t)w->partials_cap);
   w->DW = dalloc<double>(L, (int64_t)std::max(1, D->rank) * B);
-  double* s = dalloc<double>(L, 9 * (int64_t)B);
+  double* s = dalloc<double>(L, 12 * (int64_t)B);
   w->rz = s; w->pq = s + B; w->alpha = s + 2 * B; w->bcg = s + 3 * B; w->rr = s + 4 * B;
   w->thr = s + 5 * B; w->bn2 = s + 6 * B; w->res2 = s + 7 * B; w->colscale = s + 8 * B;
+  w->rn2 = s + 9 * B; w->inv = s + 10 * B; w->fwd = s + 11 * B;
+  if (D->precision == KATZ_PREC_MIXED) w->Rf = dalloc<float>(L, nB);
   int* ip = dalloc<int>(L, 4 * (int64_t)B + 1);
   w->active = ip; w->status = ip + B; w->iters = ip + 2 * B; w->mask = ip + 3 * B; w->n_active = ip + 4 * B;
-  HIPCHECK(hipMemset(s, 0, 9 * sizeof(double) * (size_t)B));
+  HIPCHECK(hipMemset(s, 0, 12 * sizeof(double) * (size_t)B));
   HIPCHECK(hipMemset(ip, 0, (4 * (size_t)B + 1) * sizeof(int)));
   w->qpos = dalloc<int32_t>(L, B);
   HIPCHECK(hipHostMalloc(&w->hpin, 64 * 1024, hipHostMallocDefault));
@@ -1145,9 +1366,50 @@ struct Launcher {
   }
 };
 
+// Relative accuracy the FP32 inner solves are asked for (the FP64 sweeps do the rest).
+constexpr double kInnerTolFP32 = 1e-5;
+
 // Pinned host staging (w->hpin, 64 KiB), B <= 512:
 constexpr size_t kPinQ = 0, kPinMask0 = 2048, kPinMask1 = 4096, kPinBn2 = 8192, kPinRes = 12288,
                  kPinFlag = 16384, kPinStat0 = 20480, kPinIter0 = 22528, kPinStat1 = 24576, kPinIter1 = 26624;
+
+// Rank-r preconditioner on MFMA for FP32 panels: DW = D o (V^T r) by split-K
+// tiles + finalize; z = r + V DW with the <r, z> partials + finalize.
+static void precond_mfma(Launcher& L, const float* R2, float* Z2, int ep, const ColState& cs, const int* nact) {
+  DeviceIndex* D = L.D;
+  Workspace* w = L.w;
+  const int B = L.B, rank = D->rank;
+  const int64_t m = D->n2;
+  hipStream_t st = L.st;
+  const int jt = (B + 63) / 64, kt = (rank + 31) / 32;
+  int S = (int)std::max<int64_t>(1, std::min<int64_t>(512, 2048 / (jt * kt)));
+  S = (int)std::min<int64_t>(S, (m + 31) / 32);
+  int64_t rows_per_chunk = ((m + S - 1) / S + 31) / 32 * 32;
+  S = (int)((m + rows_per_chunk - 1) / rows_per_chunk);
+  L.need(S, (int64_t)rank * B);
+  L.timed(PK_VT, 2.0 * m * rank + 4.0 * B * m, [&] {
+    k_vt_mfma<<<dim3(jt, kt, S), WG, 0, st>>>(m, B, rank, D->V16, R2, rows_per_chunk, w->partials, nact);
+  });
+  L.finalize(S, rank * B, EP_VT, cs, w->DW, nact);
+  const int64_t ntile = (m + 63) / 64;
+  const int gx = (int)std::min<int64_t>(ntile, 1024);
+  L.need(gx, B);
+  const int KP = (rank + 31) / 32 * 32;
+  const size_t shm = (size_t)KP * 64 * 2 * sizeof(uint16_t) + 4 * 64 * sizeof(double);
+  if (shm > 65536) {  // rank > 224: ask for more than the default 64 KiB of LDS
+    static std::mutex mu;
+    static size_t granted = 65536;
+    std::lock_guard<std::mutex> g(mu);
+    if (shm > granted) {
+      HIPCHECK(hipFuncSetAttribute((const void*)k_lowrank_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+      granted = shm;
+    }
+  }
+  L.timed(PK_LOWRANK, 2.0 * m * rank + 4.0 * B * m * 2, [&] {
+    k_lowrank_mfma<<<dim3(gx, jt), WG, shm, st>>>(m, B, rank, D->V16r, w->DW, R2, Z2, 0, w->partials, nact);
+  });
+  L.finalize(gx, B, ep, cs, nullptr, nact);
+}
 
 // ============================================================ solve sweeps
 // One correction solve M d = rhs for the columns in w->mask; d is left in
@@ -1173,7 +1435,7 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     if (n1 == 0) return;
     M11Args<T> a;
     a.tile_row0 = D->tile_row0; a.row_blk = D->row_blk; a.blk_start = D->blk_start; a.blk_off = D->blk_off;
-    a.minv = (const T*)D->minv; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val; a.n1 = n1;
+    a.minv = Factors<T>::minv(D); a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val; a.n1 = n1;
     a.v = v; a.cv = cv; a.x2 = x2; a.ca = ca; a.out = out; a.B = B; a.n_active = nact;
     int cb = std::max(1, std::min(B, (int)(32768 / sizeof(T) / std::max(1, D->max_tile_rows))));
     a.CB = cb;
@@ -1189,27 +1451,34 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     const int64_t m = n2;
     const int rpw = L.rows_per_wg(m), nwg = Launcher::nwg_for(m, rpw);
     const int* nact = ep == EP_RZ ? w->n_active : nullptr;
+    if (std::is_same<T, float>::value && B >= 16 && D->rank > 0 && !D->ginv) {
+      precond_mfma(L, (const float*)R2, (float*)Z2, ep, cs, nact);
+      return;
+    }
     L.need(nwg, (int64_t)std::max(1, D->rank) * B);
     if (D->rank > 0) {
       const int rk = D->rank;
-      L.timed(PK_VT, 8.0 * m * rk + (double)sizeof(T) * B * m, [&] {
-        if (B == 1 && rk <= 8) k_vt1<T, double, 8><<<nwg, WG, 0, st>>>(m, rk, D->V, R2, rpw, w->partials, nact);
-        else if (B == 1 && rk <= 16) k_vt1<T, double, 16><<<nwg, WG, 0, st>>>(m, rk, D->V, R2, rpw, w->partials, nact);
-        else if (B == 1 && rk <= 32) k_vt1<T, double, 32><<<nwg, WG, 0, st>>>(m, rk, D->V, R2, rpw, w->partials, nact);
-        else if (B == 1 && rk <= 64) k_vt1<T, double, 64><<<nwg, WG, 0, st>>>(m, rk, D->V, R2, rpw, w->partials, nact);
-        else k_vt<T, double><<<nwg, WG, 0, st>>>(m, B, rk, D->V, R2, rpw, w->partials, nact);
+      L.timed(PK_VT, (double)sizeof(typename Factors<T>::TV) * m * rk + (double)sizeof(T) * B * m, [&] {
+        typedef typename Factors<T>::TV TV;
+        const TV* V = Factors<T>::V(D);
+        if (B == 1 && rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+        else if (B == 1 && rk <= 16) k_vt1<T, TV, 16><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+        else if (B == 1 && rk <= 32) k_vt1<T, TV, 32><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+        else if (B == 1 && rk <= 64) k_vt1<T, TV, 64><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+        else k_vt<T, TV><<<nwg, WG, 0, st>>>(m, B, rk, V, R2, rpw, w->partials, nact);
       });
       L.finalize(nwg, D->rank * B, EP_VT, cs, w->DW, nact);
     }
     int has_base = 0;
     if (D->ginv) {
       L.timed(PK_OTHER, (double)sizeof(T) * (m * m + 2 * m * B), [&] {
-        k_dense_apply<T><<<grid_for(m * B, WG), WG, 0, st>>>((int)m, B, (const T*)D->ginv, R2, Z2, nact);
+        k_dense_apply<T><<<grid_for(m * B, WG), WG, 0, st>>>((int)m, B, Factors<T>::ginv(D), R2, Z2, nact);
       });
       has_base = 1;
     }
-    L.timed(PK_LOWRANK, 8.0 * m * D->rank + (double)sizeof(T) * B * m * (2 + has_base), [&] {
-      k_lowrank<T, double><<<nwg, WG, WG * sizeof(double), st>>>(m, B, D->rank, D->V, w->DW, R2, Z2, has_base,
+    L.timed(PK_LOWRANK, (double)sizeof(typename Factors<T>::TV) * m * D->rank + (double)sizeof(T) * B * m * (2 + has_base), [&] {
+      k_lowrank<T, typename Factors<T>::TV><<<nwg, WG, WG * sizeof(double), st>>>(m, B, D->rank, Factors<T>::V(D),
+                                                                                w->DW, R2, Z2, has_base,
                                                                  rpw, nact, w->partials);
     });
     L.finalize(nwg, B, ep, cs, nullptr, nact);
@@ -1374,11 +1643,25 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
       ran[pass] = 1;
       // sweep 0: the device mask (b != 0) is already in place
       if (sweep > 0) HIPCHECK(hipMemcpyAsync(w->mask, hm, sizeof(int) * B, hipMemcpyHostToDevice, st));
-      if (cg_pass)
-        solve_cg<double>(L, rhs, o.max_iter, o.check_every);
-      else
-        solve_lrc<double>(L, rhs, o.force_fallback ? 1 : o.max_iter, o.check_every);
-      k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, w->Dx, w->mask, nullptr, 1);
+      const int iters = (!cg_pass && o.force_fallback) ? 1 : o.max_iter;
+      if (D->precision == KATZ_PREC_MIXED) {
+        // FP32 inner solve on the unit-norm right-hand side, FP64 accumulation
+        L.colnorm2<double>(rhs, n, w->rn2);
+        k_mixed_scales<<<1, WG, 0, st>>>(B, w->rn2, w->bn2, tol, kInnerTolFP32, w->inv, w->fwd, w->thr);
+        k_axpy_mask<float, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->Rf, rhs, nullptr, w->inv, 0);
+        if (cg_pass)
+          solve_cg<float>(L, w->Rf, iters, o.check_every);
+        else
+          solve_lrc<float>(L, w->Rf, iters, o.check_every);
+        k_axpy_mask<double, float><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const float*)w->Dx, w->mask,
+                                                                  w->fwd, 1);
+      } else {
+        if (cg_pass)
+          solve_cg<double>(L, rhs, iters, o.check_every);
+        else
+          solve_lrc<double>(L, rhs, iters, o.check_every);
+        k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, w->Dx, w->mask, nullptr, 1);
+      }
       HIPCHECK(hipMemcpyAsync(pin + (pass ? kPinStat1 : kPinStat0), w->status, sizeof(int) * B,
                               hipMemcpyDeviceToHost, st));
       HIPCHECK(hipMemcpyAsync(pin + (pass ? kPinIter1 : kPinIter0), w->iters, sizeof(int) * B,
