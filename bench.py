@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile-kernels", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--workload", type=str, default="cl1m",
+                    help="cl1m (default, one query per solve), lnsbm4m (256 FP64 RHS), cl8m (512 mixed RHS)")
+    ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -84,6 +87,8 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload != "cl1m":
+        return run_batched(args)
 
     t0 = time.time()
     w = ki.workload("cl1m", scale=args.scale)
@@ -200,6 +205,100 @@ def main():
         "cpu_baseline": head.get("cpu", {}).get("baseline"),
         "results": results,
     }
+    print(json.dumps(line), flush=True)
+
+
+def run_batched(args):
+    """Batched workloads: one step = one batch of B queries solved together."""
+    import numpy as np
+    import torch
+
+    import katz_inputs as ki
+    import paper_1912_06525_amd as K
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    w = ki.workload(args.workload, scale=args.scale)
+    g = w.graph
+    B = args.batch or w.batch
+    log("graph %s: n=%d nnz=%d (%.1fs)" % (args.workload, g.n, g.nnz, time.time() - t0))
+    cs = [float(x) for x in args.c.split(",")] if args.c != "0.1,0.5,0.9" else list(w.c)
+    prec = K.KATZ_PREC_MIXED if w.precision == "mixed" else K.KATZ_PREC_FP64
+    rank = args.rank if args.rank != 32 else w.rank
+    tol = w.tol
+    queries = ki.sample_queries(g, B * (args.steps + args.warmup), 3003)
+    out = torch.empty((B, g.n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    results = {}
+    kernel_table = None
+    for c in cs:
+        tb = time.time()
+        idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=rank, max_block=args.max_block, device=0,
+                                     labels=g.labels, precision=prec)
+        info = idx.info
+        log("c=%.2f index: n1=%d n2=%d blocks=%d sigma1=%.4f sigma_r+1=%.5f build %.1fs dev %.1f GB"
+            % (c, info.n1, info.n2, info.nblocks, info.sigma_max, info.sigma_next, time.time() - tb,
+               info.device_bytes / 1e9))
+        entry = {"n1": info.n1, "n2": info.n2, "build_s": round(info.build_seconds, 2)}
+        for name, method in (("lrc", K.KATZ_METHOD_LRC), ("cg", K.KATZ_METHOD_CG)):
+            def step(s):
+                q = queries[s * B:(s + 1) * B]
+                t = time.perf_counter()
+                _, st = idx.query(q, out=out, tol=tol, method=method, stream=stream)
+                bad = [x for x in st if x["status"] != 0]
+                if bad:
+                    raise RuntimeError("no convergence: %r" % bad[:2])
+                return time.perf_counter() - t, st
+            for s in range(args.warmup):
+                step(s)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            lat, its, sw = [], [], []
+            for s in range(args.steps):
+                dt, st = step(args.warmup + s)
+                lat.append(dt)
+                its += [x["iters"] for x in st]
+                sw += [x["sweeps"] for x in st]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            entry[name] = {"qps": B * args.steps / el, "ms_per_batch": 1e3 * el / args.steps,
+                           "iters_median": float(np.median(its)), "sweeps_median": float(np.median(sw))}
+            log("  %s: %.1f q/s, %.1f ms/batch of %d, iters median %g, sweeps %g"
+                % (name, entry[name]["qps"], entry[name]["ms_per_batch"], B, entry[name]["iters_median"],
+                   entry[name]["sweeps_median"]))
+            if not args.no_profile_kernels:
+                K.katz_profile_reset()
+                K.katz_profile_enable(True)
+                step(args.warmup)
+                torch.cuda.synchronize()
+                K.katz_profile_enable(False)
+                tab = [r for r in K.katz_profile_read() if r["launches"] > 0]
+                for r in tab:
+                    r["avg_us"] = 1e3 * r["total_ms"] / r["launches"]
+                    r["achieved_GBs"] = r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
+                    log("    %-22s %5d x %9.1f us  %8.1f GB/s" % (r["name"], r["launches"], r["avg_us"],
+                                                                r["achieved_GBs"]))
+                entry[name]["kernels"] = tab
+                if name == "lrc" and c == cs[0]:
+                    kernel_table = tab
+        results["c=%g" % c] = entry
+        idx.close()
+    head = results["c=%g" % cs[0]]
+    roofline = None
+    if kernel_table:
+        dom = max(kernel_table, key=lambda r: r["total_ms"])
+        roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["achieved_GBs"], 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                    "traffic": None, "avg_launch_us": round(dom["avg_us"], 2)}
+    line = {"metric": "Katz queries/sec at 1e-6 rel. residual, LRC-Katz vs CG, 1 MI355X; p99 ms",
+            "value": round(head["lrc"]["qps"], 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(head["lrc"]["ms_per_batch"], 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+bf16/f64" if prec == K.KATZ_PREC_MIXED else "f64", "data": "synthetic",
+            "config": {"workload": "%s, %d nodes, batch %d, rank %d, c %s" % (args.workload, g.n, B, rank, cs),
+                       "n": g.n, "nnz": g.nnz, "batch": B},
+            "cg_qps": round(head["cg"]["qps"], 2), "lrc_over_cg": round(head["lrc"]["qps"] / head["cg"]["qps"], 3),
+            "roofline": roofline, "cpu_baseline": None, "results": results}
     print(json.dumps(line), flush=True)
 
 

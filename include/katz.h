@@ -70,6 +70,12 @@ enum katz_l_kind {
 
 enum katz_method { KATZ_METHOD_LRC = 0, KATZ_METHOD_CG = 1 };
 
+enum katz_order {
+  KATZ_ORDER_AUTO = 0,     /* DEGREE */
+  KATZ_ORDER_DEGREE = 1,   /* blocks largest first; separator by degree (hubs first) */
+  KATZ_ORDER_LOCALITY = 2  /* blocks and separator in BFS visit order */
+};
+
 enum katz_path {
   KATZ_PATH_LRC = 0,        /* Schur-complement PCG with the rank-r preconditioner */
   KATZ_PATH_CG = 1,         /* plain CG on M (requested) */
@@ -88,6 +94,12 @@ typedef struct {
   int32_t device;         /* HIP device ordinal; -1 builds a host-only index
                              (inspectable, not queryable) */
   int32_t lanczos_steps;  /* 0: max(2r, r + 20) */
+  int32_t order;          /* enum katz_order: node order inside the two parts */
+  int32_t u_precision;    /* storage of the low-rank factor V on the device:
+                             0 auto (FP32 on the FP64 path, BF16 on the mixed
+                             path), 1 FP64, 2 FP32.  The preconditioner is a
+                             fixed SPD operator either way, so the solution's
+                             accuracy does not depend on it. */
 } katz_build_opts;
 
 typedef struct {

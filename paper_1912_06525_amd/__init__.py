@@ -26,6 +26,7 @@ KATZ_PREC_FP64, KATZ_PREC_MIXED = 0, 1
 KATZ_L_AUTO, KATZ_L_CHOL, KATZ_L_IDENTITY = 0, 1, 2
 KATZ_METHOD_LRC, KATZ_METHOD_CG = 0, 1
 KATZ_PATH_LRC, KATZ_PATH_CG, KATZ_PATH_CG_FALLBACK = 0, 1, 2
+KATZ_ORDER_AUTO, KATZ_ORDER_DEGREE, KATZ_ORDER_LOCALITY = 0, 1, 2
 
 _STATUS = {0: "KATZ_OK", -1: "KATZ_EINVAL", -2: "KATZ_ENOTSYM", -3: "KATZ_EDIVERGE", -4: "KATZ_ENOMEM",
            -5: "KATZ_EDEVICE", -6: "KATZ_ENOCONV", -7: "KATZ_EBUSY", -8: "KATZ_EIO"}
@@ -40,7 +41,8 @@ class katz_build_opts(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("beta_frac", ctypes.c_double), ("rank", ctypes.c_int32),
                 ("max_block", ctypes.c_int32), ("labels", ctypes.POINTER(ctypes.c_int32)),
                 ("l_kind", ctypes.c_int32), ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("device", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("u_precision", ctypes.c_int32)]
 
 
 class katz_query_opts(ctypes.Structure):
@@ -249,12 +251,14 @@ class KatzIndex:
     def __init__(self, n: int, row_ptr, col, val=None, *, beta: float = 0.0, beta_frac: float = 0.5,
                  rank: int = 32, max_block: int = 64, labels=None, l_kind: int = KATZ_L_AUTO,
                  precision: int = KATZ_PREC_FP64, seed: int = 12345, device: int = 0,
-                 lanczos_steps: int = 0):
+                 lanczos_steps: int = 0, order: int = KATZ_ORDER_AUTO, u_precision: int = 0):
         o = katz_build_opts_default()
         o.beta, o.beta_frac, o.rank, o.max_block = beta, beta_frac, rank, max_block
         self._labels = None if labels is None else np.ascontiguousarray(labels, np.int32)
         o.labels = _pi32(self._labels)
         o.l_kind, o.precision, o.seed, o.device, o.lanczos_steps = l_kind, precision, seed, device, lanczos_steps
+        o.order = order
+        o.u_precision = u_precision
         self.n = int(n)
         self.h = katz_index_build(n, row_ptr, col, val, o)
         self.info = katz_index_info(self.h)

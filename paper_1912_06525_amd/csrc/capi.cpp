@@ -67,6 +67,8 @@ void katz_build_opts_default(katz_build_opts* o) {
   o->seed = 12345;
   o->device = 0;
   o->lanczos_steps = 0;
+  o->order = KATZ_ORDER_AUTO;
+  o->u_precision = 0;
 }
 
 void katz_query_opts_default(katz_query_opts* o) {
@@ -88,6 +90,7 @@ int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
     katz_build_opts_default(&o);
     if (opts) o = *opts;
     if (o.max_block > 256) return set_error(KATZ_EINVAL, "max_block must be <= 256");
+    if (o.u_precision < 0 || o.u_precision > 2) return set_error(KATZ_EINVAL, "bad u_precision");
     auto* idx = new katz_index();
     try {
       katz::build_host_index(n, nnz, row_ptr, col_idx, val, o, idx->host);

@@ -355,7 +355,7 @@ void bfs_order(const int32_t* rp, const int32_t* col, const std::vector<int32_t>
 }
 
 Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const int32_t* labels,
-                         int32_t max_block) {
+                         int32_t max_block, int32_t order_kind) {
   // (a) initial parts
   std::vector<int32_t> part(n);
   int32_t P = 0;
@@ -375,6 +375,8 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
   for (int32_t v = 0; v < n; v++) members[part[v]].push_back(v);
   std::vector<int32_t> mark(n, -1), order, queue;
   std::vector<int32_t> piece(n, -1);
+  std::vector<int64_t> visit(n, 0);  // position in the concatenated BFS orders
+  int64_t nvisit = 0;
   int32_t npiece = 0;
   for (int32_t p = 0; p < P; p++) {
     auto& mem = members[p];
@@ -383,6 +385,7 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
     for (size_t k = 0; k < order.size(); k++) {
       if (k % (size_t)max_block == 0) npiece++;
       piece[order[k]] = npiece - 1;
+      visit[order[k]] = nvisit++;
     }
     std::vector<int32_t>().swap(mem);
   }
@@ -461,10 +464,18 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
       }
     }
   }
-  // largest blocks first (the block kernel then sees a descending work list)
+  // Block order.  DEGREE: largest blocks first (a descending work list for the
+  // block kernel).  LOCALITY: blocks and their nodes in BFS visit order, so
+  // neighbours stay close in every panel.
+  const bool locality = order_kind == KATZ_ORDER_LOCALITY;
   std::vector<int32_t> bo(blocks.size());
   std::iota(bo.begin(), bo.end(), 0);
-  std::stable_sort(bo.begin(), bo.end(), [&](int32_t a, int32_t b) { return blocks[a].size() > blocks[b].size(); });
+  if (locality) {
+    for (auto& b : blocks) std::sort(b.begin(), b.end(), [&](int32_t x, int32_t y) { return visit[x] < visit[y]; });
+    std::stable_sort(bo.begin(), bo.end(), [&](int32_t a, int32_t b) { return visit[blocks[a][0]] < visit[blocks[b][0]]; });
+  } else {
+    std::stable_sort(bo.begin(), bo.end(), [&](int32_t a, int32_t b) { return blocks[a].size() > blocks[b].size(); });
+  }
   Partition R;
   R.perm.assign(n, -1);
   R.iperm.reserve(n);
@@ -476,11 +487,12 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
     R.blk_start.push_back((int32_t)R.iperm.size());
   }
   R.n1 = (int32_t)R.iperm.size();
-  // separator nodes by degree, largest first, then by id: the hubs, which most
-  // adjacency entries point to, share few cache lines of every gathered panel
+  // separator order.  DEGREE: largest first, then by id (the hubs, which most
+  // adjacency entries point to, share few cache lines of every gathered
+  // panel).  LOCALITY: BFS visit order.
   std::vector<std::pair<int64_t, int32_t>> sk;
   for (int32_t v = 0; v < n; v++)
-    if (insep[v]) sk.emplace_back(-(int64_t)(rp[v + 1] - rp[v]), v);
+    if (insep[v]) sk.emplace_back(locality ? visit[v] : -(int64_t)(rp[v + 1] - rp[v]), v);
   std::sort(sk.begin(), sk.end());
   (void)blkpos;
   for (auto& kv : sk) { R.perm[kv.second] = (int32_t)R.iperm.size(); R.iperm.push_back(kv.second); }
@@ -681,10 +693,12 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
   if (o.max_block < 0) fail(KATZ_EINVAL, "max_block must be >= 0");
   if (o.l_kind < KATZ_L_AUTO || o.l_kind > KATZ_L_IDENTITY) fail(KATZ_EINVAL, "bad l_kind");
   if (o.precision != KATZ_PREC_FP64 && o.precision != KATZ_PREC_MIXED) fail(KATZ_EINVAL, "bad precision");
+  if (o.order < KATZ_ORDER_AUTO || o.order > KATZ_ORDER_LOCALITY) fail(KATZ_EINVAL, "bad order");
   H.n = n;
   H.nnz = nnz;
   H.weighted = val != nullptr;
   H.precision = o.precision;
+  H.u_precision = o.u_precision == 0 ? 2 : o.u_precision;
   H.lambda_max = lambda_max(n, row_ptr, col, val, o.seed);
   if (o.beta > 0) {
     H.beta = o.beta;
@@ -700,7 +714,10 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
       if (o.labels[v] < 0) fail(KATZ_EINVAL, "labels must be >= 0");
 
   int32_t max_block = o.max_block > 0 ? o.max_block : 64;
-  Partition P = make_partition(n, row_ptr, col, o.labels, max_block);
+  int32_t order_kind = o.order;
+  if (const char* e = getenv("KATZ_ORDER")) order_kind = atoi(e);
+  if (order_kind == KATZ_ORDER_AUTO) order_kind = KATZ_ORDER_DEGREE;
+  Partition P = make_partition(n, row_ptr, col, o.labels, max_block, order_kind);
   H.perm = std::move(P.perm);
   H.iperm = std::move(P.iperm);
   H.blk_start = std::move(P.blk_start);

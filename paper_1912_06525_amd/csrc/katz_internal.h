@@ -50,6 +50,7 @@ struct HostIndex {
   double sigma_next = 0;
   int32_t lanczos_steps = 0;
   int32_t precision = KATZ_PREC_FP64;
+  int32_t u_precision = 0;  // resolved: 1 FP64, 2 FP32 (FP64 path); BF16 on the mixed path
   double build_seconds = 0;
 };
 

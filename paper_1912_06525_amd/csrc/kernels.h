@@ -29,6 +29,39 @@ struct ColState {
   int max_iter;
 };
 
+// ----------------------------------------------------------- XCD slabs
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b on XCD
+// b % 8), and each XCD has its own L2.  xcd_slab gives workgroup `bid` of
+// `nwg` the chunk range of its XCD: nchunks split into 8 contiguous slabs, the
+// XCD's workgroups striding through the slab together, so rows processed at
+// the same time on one XCD are neighbours in the node order.
+struct Slab {
+  int64_t first, end, stride;
+};
+// Workgroup bid of nwg: nchunks split into nx = min(8, nwg) balanced
+// contiguous slabs; slab x is walked by the workgroups with bid % nx == x, in
+// steps of their count.  Every chunk is visited exactly once.
+// Contiguous alternative: workgroup bid takes chunks [bid * c, (bid + 1) * c).
+__device__ inline Slab contiguous_slab(int bid, int nwg, int64_t nchunks) {
+  const int64_t c = (nchunks + nwg - 1) / nwg;
+  Slab s;
+  s.first = (int64_t)bid * c;
+  s.end = min<int64_t>(nchunks, s.first + c);
+  s.stride = 1;
+  return s;
+}
+__device__ inline Slab xcd_slab(int bid, int nwg, int64_t nchunks) {
+  const int nx = nwg < 8 ? nwg : 8;
+  const int x = bid % nx;
+  const int64_t q = nchunks / nx, rem = nchunks % nx;
+  const int64_t start = (int64_t)x * q + (x < rem ? x : rem);
+  Slab s;
+  s.first = start + bid / nx;
+  s.end = start + q + (x < rem ? 1 : 0);
+  s.stride = (nwg - x + nx - 1) / nx;
+  return s;
+}
+
 // -------------------------------------------------------------- reduction
 // Recounts the active columns (one thread) after an epilogue changed them.
 __device__ inline void recount_active(const ColState& cs, int B) {

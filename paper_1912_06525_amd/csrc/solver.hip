@@ -73,7 +73,9 @@ __global__ void k_rhs_scatter(const int32_t* qpos, int B, const int32_t* rp, con
 // <d, y> (d = dotv or y) with a last-workgroup epilogue.
 template <typename T>
 struct SpmmArgs {
-  int row0, row1, rows_per_wg;
+  int row0, row1, rows_per_wg;  // rows_per_wg = rows per chunk
+  int64_t nchunks;              // short-row chunks
+  int xcd;                      // walk them in XCD slabs (1) or contiguously (0)
   const int32_t* rp;
   const int32_t* col;
   const int32_t* split;
@@ -224,12 +226,14 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
     slot = 0;
     cl_own = tid;
   } else {
-    // ---- short rows: a chunk of rows, one team per row
+    // ---- short rows: chunks of rows in XCD slabs, one team per row
     const int team = tid / TS, lane = tid % TS;
     const int cl = lane % CW, nz = lane / CW;
-    const int rbeg = a.row0 + ((int)blockIdx.x - a.n_long) * a.rows_per_wg;
-    const int rend = min(a.row1, rbeg + a.rows_per_wg);
-    for (int i = rbeg + team; i < rend; i += TEAMS) {
+    const Slab sl = a.xcd ? xcd_slab((int)blockIdx.x - a.n_long, (int)gridDim.x - a.n_long, a.nchunks)
+                          : contiguous_slab((int)blockIdx.x - a.n_long, (int)gridDim.x - a.n_long, a.nchunks);
+    for (int64_t ch = sl.first; ch < sl.end; ch += sl.stride)
+    for (int i = a.row0 + (int)ch * a.rows_per_wg + team,
+             rend = min<int64_t>(a.row1, a.row0 + (ch + 1) * a.rows_per_wg); i < rend; i += TEAMS) {
       if (a.long_rows && a.rp[i + 1] - a.rp[i] > a.long_thr) continue;  // done by its own workgroup
       T acc[NCM];
 #pragma unroll
@@ -418,7 +422,7 @@ struct M11Args {
   const T* x2;
   T ca;
   T* out;
-  int B, CB, sub;
+  int B, CB, sub, xcd;
   const int* n_active;
 };
 
@@ -427,7 +431,9 @@ __global__ __launch_bounds__(WG) void k_m11_apply(M11Args<T> a) {
   if (a.n_active && *a.n_active == 0) return;
   extern __shared__ unsigned char smem[];
   T* u = reinterpret_cast<T*>(smem);
-  const int r0 = a.tile_row0[blockIdx.x], r1 = a.tile_row0[blockIdx.x + 1], R = r1 - r0;
+  // one tile per workgroup, tiles taken in XCD slabs
+  const int tile = a.xcd ? (int)xcd_slab(blockIdx.x, gridDim.x, gridDim.x).first : (int)blockIdx.x;
+  const int r0 = a.tile_row0[tile], r1 = a.tile_row0[tile + 1], R = r1 - r0;
   const int B = a.B;
   const int SUB = a.sub, PPP = WG / SUB;  // SUB lanes share one (row, column) gather
   for (int jc = 0; jc < B; jc += a.CB) {
@@ -953,6 +959,7 @@ struct DeviceIndex {
   float* ginv32 = nullptr;
   bf16* V16 = nullptr;      // column-major n2 x r
   bf16* V16r = nullptr;     // row-major n2 x r (MFMA operand layout)
+  float* V32 = nullptr;     // column-major n2 x r, FP32 storage for the FP64 path
   int64_t bytes = 0, factor_bytes = 0;
   std::vector<void*> allocs;
   std::mutex mu;
@@ -1103,7 +1110,12 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
       std::vector<double> vc((size_t)H.n2 * H.rank);  // column-major copy
       for (int64_t i = 0; i < H.n2; i++)
         for (int k = 0; k < H.rank; k++) vc[(size_t)k * H.n2 + i] = H.V[(size_t)i * H.rank + k];
-      D->V = upload(D->allocs, vc, by);
+      if (H.precision == KATZ_PREC_FP64 && H.u_precision == 2) {
+        std::vector<float> v32(vc.begin(), vc.end());
+        D->V32 = upload(D->allocs, v32, by);
+      } else if (H.precision == KATZ_PREC_FP64) {
+        D->V = upload(D->allocs, vc, by);
+      }
       D->D = upload(D->allocs, H.D, by);
       if (H.precision == KATZ_PREC_MIXED) {
         std::vector<uint16_t> vb(vc.size()), vr(vc.size());
@@ -1145,13 +1157,11 @@ template <> struct Factors<double> {
   typedef double TV;
   static const double* minv(const DeviceIndex* D) { return D->minv; }
   static const double* ginv(const DeviceIndex* D) { return D->ginv; }
-  static const double* V(const DeviceIndex* D) { return D->V; }
 };
 template <> struct Factors<float> {
   typedef bf16 TV;
   static const float* minv(const DeviceIndex* D) { return D->minv32; }
   static const float* ginv(const DeviceIndex* D) { return D->ginv32; }
-  static const bf16* V(const DeviceIndex* D) { return D->V16; }
 };
 
 // ================================================================== tuning
@@ -1163,6 +1173,7 @@ struct Tuning {
   int rows_team;    // target rows per team of the SpMM
   int ew_nwg;       // max workgroups of the row-parallel reduction kernels
   int ew_rows;      // target rows per workgroup of those kernels
+  int xcd;          // XCD-slab chunk order for the gathering kernels
 };
 static int env_int(const char* name, int dflt, int lo, int hi) {
   const char* e = getenv(name);
@@ -1178,6 +1189,7 @@ static const Tuning& tuning() {
     u.rows_team = env_int("KATZ_SPMM_ROWS_PER_TEAM", 1, 1, 64);
     u.ew_nwg = env_int("KATZ_EW_NWG", 1024, 64, 65536);
     u.ew_rows = env_int("KATZ_EW_ROWS", 256, 16, 65536);
+    u.xcd = env_int("KATZ_XCD_SLAB", 0, 0, 1);
     return u;
   }();
   return t;
@@ -1320,10 +1332,11 @@ struct Launcher {
     else { TS = 64; CW = 64; }
     if (B > MAXC * CW) fail(KATZ_EINVAL, "batch too wide for one launch");
     const int teams = WG / TS;
-    int64_t nwg = std::min<int64_t>(tu.spmm_nwg,
-                                    std::max<int64_t>(1, (rows + teams * tu.rows_team - 1) / (teams * tu.rows_team)));
-    a.rows_per_wg = (int)((rows + nwg - 1) / nwg);
-    nwg = (rows + a.rows_per_wg - 1) / a.rows_per_wg;
+    // chunks of teams * rows_team rows; at most spmm_nwg workgroups walk them
+    a.rows_per_wg = teams * tu.rows_team;
+    a.xcd = tu.xcd;
+    a.nchunks = (rows + a.rows_per_wg - 1) / a.rows_per_wg;
+    int64_t nwg = std::min<int64_t>(tu.spmm_nwg, a.nchunks);
     a.partials = w->partials;
     a.long_thr = kLongRow;
     if (a.row0 == D->n1 && a.row1 == D->n) { a.long_rows = D->long_sep; a.n_long = D->n_long_sep; }
@@ -1411,6 +1424,40 @@ static void precond_mfma(Launcher& L, const float* R2, float* Z2, int ep, const 
   L.finalize(gx, B, ep, cs, nullptr, nact);
 }
 
+// Rank-r preconditioner with the row-parallel kernels (any B, V of type TV):
+// DW = D o (V^T r), then z = G r + V DW (G = M22^{-1} or I) with <r, z>.
+template <typename T, typename TV>
+static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, const ColState& cs,
+                           const int* nact, int rpw, int nwg) {
+  DeviceIndex* D = L.D;
+  Workspace* w = L.w;
+  const int B = L.B, rk = D->rank;
+  const int64_t m = D->n2;
+  hipStream_t st = L.st;
+  if (rk > 0) {
+    L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
+      if (B == 1 && rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+      else if (B == 1 && rk <= 16) k_vt1<T, TV, 16><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+      else if (B == 1 && rk <= 32) k_vt1<T, TV, 32><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+      else if (B == 1 && rk <= 64) k_vt1<T, TV, 64><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+      else k_vt<T, TV><<<nwg, WG, 0, st>>>(m, B, rk, V, R2, rpw, w->partials, nact);
+    });
+    L.finalize(nwg, rk * B, EP_VT, cs, w->DW, nact);
+  }
+  int has_base = 0;
+  if (Factors<T>::ginv(D)) {
+    L.timed(PK_OTHER, (double)sizeof(T) * (m * m + 2 * m * B), [&] {
+      k_dense_apply<T><<<grid_for(m * B, WG), WG, 0, st>>>((int)m, B, Factors<T>::ginv(D), R2, Z2, nact);
+    });
+    has_base = 1;
+  }
+  L.timed(PK_LOWRANK, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m * (2 + has_base), [&] {
+    k_lowrank<T, TV><<<nwg, WG, WG * sizeof(double), st>>>(m, B, rk, V, w->DW, R2, Z2, has_base, rpw, nact,
+                                                           w->partials);
+  });
+  L.finalize(nwg, B, ep, cs, nullptr, nact);
+}
+
 // ============================================================ solve sweeps
 // One correction solve M d = rhs for the columns in w->mask; d is left in
 // w->Dx (all n rows), per-column outcome in w->iters / w->status.
@@ -1437,6 +1484,7 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     a.tile_row0 = D->tile_row0; a.row_blk = D->row_blk; a.blk_start = D->blk_start; a.blk_off = D->blk_off;
     a.minv = Factors<T>::minv(D); a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val; a.n1 = n1;
     a.v = v; a.cv = cv; a.x2 = x2; a.ca = ca; a.out = out; a.B = B; a.n_active = nact;
+    a.xcd = tuning().xcd;
     int cb = std::max(1, std::min(B, (int)(32768 / sizeof(T) / std::max(1, D->max_tile_rows))));
     a.CB = cb;
     a.sub = cb >= 16 ? 1 : (cb >= 4 ? 2 : 4);
@@ -1456,32 +1504,12 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
       return;
     }
     L.need(nwg, (int64_t)std::max(1, D->rank) * B);
-    if (D->rank > 0) {
-      const int rk = D->rank;
-      L.timed(PK_VT, (double)sizeof(typename Factors<T>::TV) * m * rk + (double)sizeof(T) * B * m, [&] {
-        typedef typename Factors<T>::TV TV;
-        const TV* V = Factors<T>::V(D);
-        if (B == 1 && rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
-        else if (B == 1 && rk <= 16) k_vt1<T, TV, 16><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
-        else if (B == 1 && rk <= 32) k_vt1<T, TV, 32><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
-        else if (B == 1 && rk <= 64) k_vt1<T, TV, 64><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
-        else k_vt<T, TV><<<nwg, WG, 0, st>>>(m, B, rk, V, R2, rpw, w->partials, nact);
-      });
-      L.finalize(nwg, D->rank * B, EP_VT, cs, w->DW, nact);
-    }
-    int has_base = 0;
-    if (D->ginv) {
-      L.timed(PK_OTHER, (double)sizeof(T) * (m * m + 2 * m * B), [&] {
-        k_dense_apply<T><<<grid_for(m * B, WG), WG, 0, st>>>((int)m, B, Factors<T>::ginv(D), R2, Z2, nact);
-      });
-      has_base = 1;
-    }
-    L.timed(PK_LOWRANK, (double)sizeof(typename Factors<T>::TV) * m * D->rank + (double)sizeof(T) * B * m * (2 + has_base), [&] {
-      k_lowrank<T, typename Factors<T>::TV><<<nwg, WG, WG * sizeof(double), st>>>(m, B, D->rank, Factors<T>::V(D),
-                                                                                w->DW, R2, Z2, has_base,
-                                                                 rpw, nact, w->partials);
-    });
-    L.finalize(nwg, B, ep, cs, nullptr, nact);
+    if (std::is_same<T, double>::value && D->V32)
+      precond_simple<T, float>(L, D->V32, R2, Z2, ep, cs, nact, rpw, nwg);
+    else if (std::is_same<T, double>::value)
+      precond_simple<T, double>(L, D->V, R2, Z2, ep, cs, nact, rpw, nwg);
+    else
+      precond_simple<T, bf16>(L, D->V16, R2, Z2, ep, cs, nact, rpw, nwg);
   };
 
   // ---- a2: t = M11^{-1} b1 -> X[0:n1]; f = b2 + beta A21 t -> R2; rr

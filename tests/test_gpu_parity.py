@@ -48,10 +48,10 @@ def sbm2k():
 
 
 @pytest.mark.parametrize("method", [K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG])
-@pytest.mark.parametrize("rank", [0, 5, 32])
-def test_sbm2k_fp64_1e10(sbm2k, method, rank):
+@pytest.mark.parametrize("rank,uprec", [(0, 0), (5, 1), (32, 2)])
+def test_sbm2k_fp64_1e10(sbm2k, method, rank, uprec):
     g = sbm2k.graph
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=rank, labels=g.labels, max_block=200)
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=rank, labels=g.labels, max_block=200, u_precision=uprec)
     sc, st = idx.query(sbm2k.queries, tol=1e-10, method=method)
     ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, sbm2k.queries, beta=idx.info.beta)
     assert st[0]["status"] == 0 and st[0]["rel_residual"] <= 1e-10
@@ -65,18 +65,19 @@ def test_full_rank_converges_in_one_iteration(sbm2k):
     idx0 = K.KatzIndex.from_graph(g, beta_frac=0.8, rank=0, labels=g.labels, max_block=12, device=-1)
     n2 = idx0.info.n2
     idx = K.KatzIndex.from_graph(g, beta_frac=0.8, rank=n2, labels=g.labels, max_block=12,
-                                 l_kind=K.KATZ_L_CHOL, lanczos_steps=10 ** 6)
+                                 l_kind=K.KATZ_L_CHOL, lanczos_steps=10 ** 6, u_precision=1)
     qs = ki.sample_queries(g, 3, 4)
     sc, st = _check(g, idx, qs, 1e-9)
     assert all(s["iters"] <= 2 for s in st), st
 
 
+@pytest.mark.parametrize("order", [K.KATZ_ORDER_DEGREE, K.KATZ_ORDER_LOCALITY])
 @pytest.mark.parametrize("lk", [K.KATZ_L_CHOL, K.KATZ_L_IDENTITY])
 @pytest.mark.parametrize("c", [0.1, 0.5, 0.9, 0.99])
-def test_small_sbm_both_factors(lk, c):
+def test_small_sbm_both_factors(lk, c, order):
     # dense chol(M22) is for small separators: a smaller graph for CHOL
     g = ki.workload("lnsbm4m", scale=0.0006 if lk == K.KATZ_L_CHOL else 0.002).graph
-    idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=16, labels=g.labels, max_block=32, l_kind=lk)
+    idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=16, labels=g.labels, max_block=32, l_kind=lk, order=order)
     qs = ki.sample_queries(g, 5, 31)
     _check(g, idx, qs, 1e-6)
 
