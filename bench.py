@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--workload", type=str, default="cl1m",
                     help="cl1m (default, one query per solve), lnsbm4m (256 FP64 RHS), cl8m (512 mixed RHS)")
     ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
+    ap.add_argument("--u-precision", type=int, default=0, help="low-rank factor storage (0 auto, 1 FP64, 2 FP32, 3 BF16)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -109,7 +110,8 @@ def main():
         for s in range(steps):
             q = queries[(offset + s) % len(queries)]
             t = time.perf_counter()
-            _, st = idx.query([q], out=out, tol=tol, method=method, stream=stream)
+            _, st = idx.query([q], out=out, tol=tol, method=method, stream=stream,
+                              check_every=int(os.environ.get("KATZ_CHECK_EVERY", "0")))
             lat.append(time.perf_counter() - t)
             its.append(st[0]["iters"])
             res.append(st[0]["rel_residual"])
@@ -119,7 +121,8 @@ def main():
 
     for c in cs:
         tb = time.time()
-        idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=args.rank, max_block=args.max_block, device=0)
+        idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=args.rank, max_block=args.max_block, device=0,
+                                     u_precision=args.u_precision)
         info = idx.info
         log("c=%.2f index: n1=%d n2=%d blocks=%d sigma1=%.4f sigma_r+1=%.5f build %.1fs"
             % (c, info.n1, info.n2, info.nblocks, info.sigma_max, info.sigma_next, time.time() - tb))

@@ -97,7 +97,7 @@ typedef struct {
   int32_t order;          /* enum katz_order: node order inside the two parts */
   int32_t u_precision;    /* storage of the low-rank factor V on the device:
                              0 auto (FP32 on the FP64 path, BF16 on the mixed
-                             path), 1 FP64, 2 FP32.  The preconditioner is a
+                             path), 1 FP64, 2 FP32, 3 BF16.  The preconditioner is a
                              fixed SPD operator either way, so the solution's
                              accuracy does not depend on it. */
 } katz_build_opts;

@@ -90,7 +90,7 @@ int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
     katz_build_opts_default(&o);
     if (opts) o = *opts;
     if (o.max_block > 256) return set_error(KATZ_EINVAL, "max_block must be <= 256");
-    if (o.u_precision < 0 || o.u_precision > 2) return set_error(KATZ_EINVAL, "bad u_precision");
+    if (o.u_precision < 0 || o.u_precision > 3) return set_error(KATZ_EINVAL, "bad u_precision");
     auto* idx = new katz_index();
     try {
       katz::build_host_index(n, nnz, row_ptr, col_idx, val, o, idx->host);

@@ -42,7 +42,7 @@ __device__ inline double to_d(float x) { return (double)x; }
 __device__ inline double to_d(bf16 x) { return (double)__bfloat162float(x); }
 
 enum Ep { EP_NONE = 0, EP_PQ = 1, EP_RES = 2, EP_RR_INIT = 3, EP_RR = 4, EP_RZ_INIT = 5, EP_RZ = 6,
-          EP_RR_CG = 7, EP_NORM = 8, EP_VT = 9 };
+          EP_RR_CG = 7, EP_NORM = 8, EP_VT = 9, EP_RR_VT = 10 };
 
 // ==================================================================== kernels
 // Fill a buffer with a value.
@@ -362,6 +362,50 @@ __global__ __launch_bounds__(WG) void k_update_r(int64_t m, int B, int rows_per_
       }
     }
   wg_colsum(cm, B, dacc, partials);
+}
+
+// One column (B = 1): x += alpha p; r -= alpha q; then, in the same pass,
+// the partial sums of V^T r (rank values, registers) and <r, r>; partials
+// per workgroup: [W_0 .. W_{rank-1}, rr].  Finalized by EP_RR_VT.
+template <typename T, typename TV, int RMAX>
+__global__ __launch_bounds__(WG) void k_update_r_vt1(int64_t m, int rows_per_wg, T* x, const T* p, T* r,
+                                                     const T* q, int rank, const TV* V, ColState cs,
+                                                     double* partials) {
+  if (*cs.n_active == 0) return;
+  __shared__ double sh[(WG / 64) * (RMAX + 1)];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(m, r0 + rows_per_wg);
+  const T al = (T)cs.alpha[0];
+  double acc[RMAX + 1];
+#pragma unroll
+  for (int k = 0; k <= RMAX; k++) acc[k] = 0.0;
+  for (int64_t i = r0 + tid; i < r1; i += WG) {
+    x[i] += al * p[i];
+    const T rv = r[i] - al * q[i];
+    r[i] = rv;
+    const double rd = (double)rv;
+    acc[RMAX] += rd * rd;
+#pragma unroll
+    for (int k = 0; k < RMAX; k++)
+      if (k < rank) acc[k] += to_d(V[(int64_t)k * m + i]) * rd;
+  }
+  const int wave = tid / 64, lane = tid % 64;
+#pragma unroll
+  for (int k = 0; k <= RMAX; k++) {
+    if (k < rank || k == RMAX) {
+      double v = acc[k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) sh[wave * (RMAX + 1) + k] = v;
+    }
+  }
+  __syncthreads();
+  if (tid <= rank) {
+    const int k = tid < rank ? tid : RMAX;
+    double sum = 0.0;
+    for (int wv = 0; wv < WG / 64; wv++) sum += sh[wv * (RMAX + 1) + k];
+    partials[(int64_t)blockIdx.x * (rank + 1) + tid] = sum;
+  }
 }
 
 // p = z + bcg p (active columns); init: p = z for the columns in the mask.
@@ -773,6 +817,13 @@ __global__ __launch_bounds__(WG) void k_finalize(const double* partials, int nwg
         cs.status[j] = 0;
         cs.active[j] = (cs.mask[j] && s > cs.thr[j]) ? 1 : 0;
         break;
+      case EP_RR_VT:
+        if (j < nv - 1) {
+          out[j] = D[j] * s;  // DW (one column)
+          break;
+        }
+        j = 0;  // the last value is <r, r> of column 0
+        // fall through
       case EP_RR:
       case EP_RR_CG: {
         if (!cs.active[j]) break;
@@ -806,7 +857,7 @@ __global__ __launch_bounds__(WG) void k_finalize(const double* partials, int nwg
         break;
     }
   });
-  if (ep == EP_PQ || ep == EP_RR_INIT || ep == EP_RR || ep == EP_RR_CG) recount_active(cs, B);
+  if (ep == EP_PQ || ep == EP_RR_INIT || ep == EP_RR || ep == EP_RR_CG || ep == EP_RR_VT) recount_active(cs, B);
 }
 
 // Start of a batch: stop thresholds on the recurrence residual and the first
@@ -937,6 +988,9 @@ struct Workspace {
   std::vector<void*> allocs;
   int device = 0;
   ProfEvents prof;
+  hipStream_t stream = nullptr;          // the workspace's own stream (default priority)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;  // captured iteration chunks
 };
 
 struct DeviceIndex {
@@ -1113,6 +1167,10 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
       if (H.precision == KATZ_PREC_FP64 && H.u_precision == 2) {
         std::vector<float> v32(vc.begin(), vc.end());
         D->V32 = upload(D->allocs, v32, by);
+      } else if (H.precision == KATZ_PREC_FP64 && H.u_precision == 3) {
+        std::vector<uint16_t> vb(vc.size());
+        for (size_t t = 0; t < vc.size(); t++) vb[t] = bf16_bits((float)vc[t]);
+        D->V16 = (bf16*)upload(D->allocs, vb, by);
       } else if (H.precision == KATZ_PREC_FP64) {
         D->V = upload(D->allocs, vc, by);
       }
@@ -1135,6 +1193,13 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
 }
 
 static void free_ws(Workspace* w) {
+  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
+  w->graphs.clear();
+  if (w->stream) (void)hipStreamDestroy(w->stream);
+  if (w->ev_in) (void)hipEventDestroy(w->ev_in);
+  if (w->ev_out) (void)hipEventDestroy(w->ev_out);
+  w->stream = nullptr;
+  w->ev_in = w->ev_out = nullptr;
   for (void* p : w->allocs) (void)hipFree(p);
   if (w->hpin) (void)hipHostFree(w->hpin);
   w->allocs.clear();
@@ -1164,6 +1229,8 @@ template <> struct Factors<float> {
   static const float* ginv(const DeviceIndex* D) { return D->ginv32; }
 };
 
+constexpr size_t kPinFlagOff = 16384;  // pinned staging offset of the poll flag
+
 // ================================================================== tuning
 // Launch shapes (overridable from the environment for tuning sweeps).  Every
 // partials buffer is sized from these limits.
@@ -1174,6 +1241,8 @@ struct Tuning {
   int ew_nwg;       // max workgroups of the row-parallel reduction kernels
   int ew_rows;      // target rows per workgroup of those kernels
   int xcd;          // XCD-slab chunk order for the gathering kernels
+  int graphs;       // replay captured iteration chunks as HIP graphs
+  int fuse;         // one-column residual update fused with V^T r
 };
 static int env_int(const char* name, int dflt, int lo, int hi) {
   const char* e = getenv(name);
@@ -1190,6 +1259,8 @@ static const Tuning& tuning() {
     u.ew_nwg = env_int("KATZ_EW_NWG", 1024, 64, 65536);
     u.ew_rows = env_int("KATZ_EW_ROWS", 256, 16, 65536);
     u.xcd = env_int("KATZ_XCD_SLAB", 0, 0, 1);
+    u.graphs = env_int("KATZ_GRAPHS", 1, 0, 1);
+    u.fuse = env_int("KATZ_FUSE", 0, 0, 1);
     return u;
   }();
   return t;
@@ -1232,6 +1303,9 @@ static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   HIPCHECK(hipMemset(ip, 0, (4 * (size_t)B + 1) * sizeof(int)));
   w->qpos = dalloc<int32_t>(L, B);
   HIPCHECK(hipHostMalloc(&w->hpin, 64 * 1024, hipHostMallocDefault));
+  HIPCHECK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+  HIPCHECK(hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming));
+  HIPCHECK(hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming));
   return w;
 }
 
@@ -1369,6 +1443,47 @@ struct Launcher {
     if (a.ep != EP_NONE) finalize(nwg_all, B, a.ep, a.cs, a.out, a.n_active);
   }
 
+  // Runs one_iter() up to max_iter times in chunks of check_every, polling the
+  // active-column count after each chunk.  A full chunk is captured once per
+  // workspace and key into a HIP graph and replayed (not while profiling).
+  template <typename F>
+  void iterate(int64_t key, int max_iter, int check_every, F&& one_iter) {
+    int* hflag = (int*)((char*)w->hpin + kPinFlagOff);
+    const bool graphs = tuning().graphs && !g_prof_on.load(std::memory_order_relaxed);
+    const int64_t gkey = (key << 40) ^ ((int64_t)check_every << 20) ^ (int64_t)max_iter;
+    for (int it = 0; it < max_iter; it += check_every) {
+      const int len = std::min(check_every, max_iter - it);
+      hipGraphExec_t ex = nullptr;
+      if (graphs && len == check_every) {
+        for (auto& g : w->graphs)
+          if (g.first == gkey) ex = g.second;
+        if (!ex) {
+          hipGraph_t gr = nullptr;
+          HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          try {
+            for (int s2 = 0; s2 < len; s2++) one_iter();
+          } catch (...) {
+            (void)hipStreamEndCapture(st, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
+            throw;
+          }
+          HIPCHECK(hipStreamEndCapture(st, &gr));
+          hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          if (e != hipSuccess) fail(KATZ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+          w->graphs.emplace_back(gkey, ex);
+        }
+      }
+      if (ex)
+        HIPCHECK(hipGraphLaunch(ex, st));
+      else
+        for (int s2 = 0; s2 < len; s2++) one_iter();
+      HIPCHECK(hipMemcpyAsync(hflag, w->n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+      sync();
+      if (*hflag == 0) break;
+    }
+  }
+
   // out[j] = sum of squares of column j of the m x B panel p
   template <typename T>
   void colnorm2(const T* p, int64_t m, double* out) {
@@ -1384,7 +1499,7 @@ constexpr double kInnerTolFP32 = 1e-5;
 
 // Pinned host staging (w->hpin, 64 KiB), B <= 512:
 constexpr size_t kPinQ = 0, kPinMask0 = 2048, kPinMask1 = 4096, kPinBn2 = 8192, kPinRes = 12288,
-                 kPinFlag = 16384, kPinStat0 = 20480, kPinIter0 = 22528, kPinStat1 = 24576, kPinIter1 = 26624;
+                 kPinFlag = kPinFlagOff, kPinStat0 = 20480, kPinIter0 = 22528, kPinStat1 = 24576, kPinIter1 = 26624;
 
 // Rank-r preconditioner on MFMA for FP32 panels: DW = D o (V^T r) by split-K
 // tiles + finalize; z = r + V DW with the <r, z> partials + finalize.
@@ -1424,17 +1539,29 @@ static void precond_mfma(Launcher& L, const float* R2, float* Z2, int ep, const 
   L.finalize(gx, B, ep, cs, nullptr, nact);
 }
 
+// Calls f(V) with the low-rank factor in the storage the index holds for
+// panels of type T (FP32 panels: BF16; FP64 panels: BF16, FP32 or FP64).
+template <typename T, typename F>
+static void with_lowrank_factor(const DeviceIndex* D, F&& f) {
+  if (std::is_same<T, float>::value || D->V16)
+    f(D->V16);
+  else if (D->V32)
+    f(D->V32);
+  else
+    f(D->V);
+}
+
 // Rank-r preconditioner with the row-parallel kernels (any B, V of type TV):
 // DW = D o (V^T r), then z = G r + V DW (G = M22^{-1} or I) with <r, z>.
 template <typename T, typename TV>
 static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, const ColState& cs,
-                           const int* nact, int rpw, int nwg) {
+                           const int* nact, int rpw, int nwg, bool dw_ready = false) {
   DeviceIndex* D = L.D;
   Workspace* w = L.w;
   const int B = L.B, rk = D->rank;
   const int64_t m = D->n2;
   hipStream_t st = L.st;
-  if (rk > 0) {
+  if (rk > 0 && !dw_ready) {
     L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
       if (B == 1 && rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
       else if (B == 1 && rk <= 16) k_vt1<T, TV, 16><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
@@ -1456,6 +1583,26 @@ static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep,
                                                            w->partials);
   });
   L.finalize(nwg, B, ep, cs, nullptr, nact);
+}
+
+// x += alpha p; r -= alpha q with DW = D o (V^T r) and <r, r> in one pass and
+// one finalize (one column, rank <= 64).
+template <typename T, typename TV>
+static void update_r_vt1(Launcher& L, const TV* V, T* x, const T* p, T* r, const T* q, const ColState& cs,
+                         int rpw, int nwg) {
+  DeviceIndex* D = L.D;
+  Workspace* w = L.w;
+  const int rk = D->rank;
+  const int64_t m = D->n2;
+  hipStream_t st = L.st;
+  L.need(nwg, rk + 1);
+  L.timed(PK_UPDATE_R, 6.0 * sizeof(T) * m + (double)sizeof(TV) * m * rk, [&] {
+    if (rk <= 8) k_update_r_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
+    else if (rk <= 16) k_update_r_vt1<T, TV, 16><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
+    else if (rk <= 32) k_update_r_vt1<T, TV, 32><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
+    else k_update_r_vt1<T, TV, 64><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
+  });
+  L.finalize(nwg, rk + 1, EP_RR_VT, cs, w->DW, w->n_active);
 }
 
 // ============================================================ solve sweeps
@@ -1504,12 +1651,10 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
       return;
     }
     L.need(nwg, (int64_t)std::max(1, D->rank) * B);
-    if (std::is_same<T, double>::value && D->V32)
-      precond_simple<T, float>(L, D->V32, R2, Z2, ep, cs, nact, rpw, nwg);
-    else if (std::is_same<T, double>::value)
-      precond_simple<T, double>(L, D->V, R2, Z2, ep, cs, nact, rpw, nwg);
-    else
-      precond_simple<T, bf16>(L, D->V16, R2, Z2, ep, cs, nact, rpw, nwg);
+    with_lowrank_factor<T>(D, [&](auto* V) {
+      typedef typename std::remove_cv<typename std::remove_pointer<decltype(V)>::type>::type TV;
+      precond_simple<T, TV>(L, V, R2, Z2, ep, cs, nact, rpw, nwg);
+    });
   };
 
   // ---- a2: t = M11^{-1} b1 -> X[0:n1]; f = b2 + beta A21 t -> R2; rr
@@ -1527,11 +1672,10 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
   k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 1, cs);
 
   // ---- a3: PCG iterations, polled every check_every
-  int* hflag = (int*)((char*)w->hpin + kPinFlag);
   const int rpw2 = L.rows_per_wg(n2), nwg2 = Launcher::nwg_for(n2, rpw2);
   L.need(nwg2, B);
-  for (int it = 0; it < max_iter; it += check_every) {
-    for (int s = 0; s < check_every && it + s < max_iter; s++) {
+  const bool fuse_vt = B == 1 && D->rank > 0 && D->rank <= 64 && !D->ginv && tuning().fuse;
+  L.iterate(sizeof(T) == 8 ? 1 : 2, max_iter, check_every, [&] {
       m11(nullptr, (T)0, P2, beta, X, w->n_active);   // t1' = M11^{-1} (beta A12 p2)
       SpmmArgs<T> a{};
       a.row0 = n1; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
@@ -1539,19 +1683,24 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
       a.v = P2; a.cv = (T)1; a.w = nullptr; a.cw = (T)0; a.y = Q2;       // q2 = S p2
       a.ep = EP_PQ; a.dotv = P2; a.cs = cs; a.n_active = w->n_active;
       L.spmm(a);
-      L.timed(PK_UPDATE_R, 6.0 * sizeof(T) * B * n2, [&] {
-        k_update_r<T><<<nwg2, WG, WG * sizeof(double), st>>>(n2, B, rpw2, K2, P2, R2, Q2, cs, w->partials);
-      });
-      L.finalize(nwg2, B, EP_RR, cs, nullptr, w->n_active);
-      precond(EP_RZ);
+      if (fuse_vt) {
+        // one column: residual update and V^T r in one pass, then z = r + V DW
+        with_lowrank_factor<T>(D, [&](auto* V) {
+          typedef typename std::remove_cv<typename std::remove_pointer<decltype(V)>::type>::type TV;
+          update_r_vt1<T, TV>(L, V, K2, P2, R2, Q2, cs, rpw2, nwg2);
+          precond_simple<T, TV>(L, V, R2, Z2, EP_RZ, cs, w->n_active, rpw2, nwg2, true);
+        });
+      } else {
+        L.timed(PK_UPDATE_R, 6.0 * sizeof(T) * B * n2, [&] {
+          k_update_r<T><<<nwg2, WG, WG * sizeof(double), st>>>(n2, B, rpw2, K2, P2, R2, Q2, cs, w->partials);
+        });
+        L.finalize(nwg2, B, EP_RR, cs, nullptr, w->n_active);
+        precond(EP_RZ);
+      }
       L.timed(PK_UPDATE_P, 3.0 * sizeof(T) * B * n2, [&] {
         k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 0, cs);
       });
-    }
-    HIPCHECK(hipMemcpyAsync(hflag, w->n_active, sizeof(int), hipMemcpyDeviceToHost, st));
-    L.sync();
-    if (*hflag == 0) break;
-  }
+  });
   // ---- a4: k1 = M11^{-1} (b1 + beta A12 k2) -> Dx[0:n1]
   m11(rhs, (T)1, K2, beta, Dx, nullptr);
 }
@@ -1577,9 +1726,7 @@ static void solve_cg(Launcher& L, const T* rhs, int max_iter, int check_every) {
   L.colnorm2<T>(R, m, w->rr);
   k_cg_init<<<1, WG, 0, st>>>(B, cs);
   k_update_p<T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, P, 1, cs);
-  int* hflag = (int*)((char*)w->hpin + kPinFlag);
-  for (int it = 0; it < max_iter; it += check_every) {
-    for (int s = 0; s < check_every && it + s < max_iter; s++) {
+  L.iterate(sizeof(T) == 8 ? 3 : 4, max_iter, check_every, [&] {
       SpmmArgs<T> a{};
       a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
       a.x = P; a.ca = -beta; a.cb = -beta; a.parts = 3;
@@ -1593,11 +1740,7 @@ static void solve_cg(Launcher& L, const T* rhs, int max_iter, int check_every) {
       L.timed(PK_UPDATE_P, 3.0 * sizeof(T) * B * m, [&] {
         k_update_p<T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, P, 0, cs);
       });
-    }
-    HIPCHECK(hipMemcpyAsync(hflag, w->n_active, sizeof(int), hipMemcpyDeviceToHost, st));
-    L.sync();
-    if (*hflag == 0) break;
-  }
+  });
 }
 
 // ============================================================ batch driver
@@ -1754,6 +1897,11 @@ int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa) {
     const int B = std::min(BMAX, qa.nq - c0);
     WsLease lease(D, B);
     Workspace* w = lease.w.get();
+    // work runs on the workspace's stream, ordered after the caller's stream
+    HIPCHECK(hipEventRecord(w->ev_in, st));
+    HIPCHECK(hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    hipStream_t caller = st;
+    st = w->stream;
     std::vector<ColResult> res;
     run_batch(H, D, w, st, qa.q + c0, B, qa.opts, res);
     if (qa.topk > 0) {
@@ -1799,6 +1947,9 @@ int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa) {
     }
     HIPCHECK(hipStreamSynchronize(st));
     w->prof.harvest();
+    HIPCHECK(hipEventRecord(w->ev_out, st));
+    HIPCHECK(hipStreamWaitEvent(caller, w->ev_out, 0));
+    st = caller;
     HIPCHECK(hipGetLastError());
     for (int j = 0; j < B; j++) {
       if (res[j].status != KATZ_OK) rc = KATZ_ENOCONV;

@@ -48,7 +48,7 @@ def sbm2k():
 
 
 @pytest.mark.parametrize("method", [K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG])
-@pytest.mark.parametrize("rank,uprec", [(0, 0), (5, 1), (32, 2)])
+@pytest.mark.parametrize("rank,uprec", [(0, 0), (5, 1), (32, 2), (32, 3)])
 def test_sbm2k_fp64_1e10(sbm2k, method, rank, uprec):
     g = sbm2k.graph
     idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=rank, labels=g.labels, max_block=200, u_precision=uprec)
