@@ -35,10 +35,16 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the SpMM kernel's source (its section of solver.hip, between the
+    SpMM and column-lane-map markers) and of kernels.h."""
     h = hashlib.sha256()
-    for f in ("solver.hip", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_1912_06525_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1912_06525_amd", "csrc", "solver.hip")) as fh:
+        src = fh.read()
+    a = src.index("// ------------------------------------------------------------------- SpMM")
+    b = src.index("// ------------------------------------------------------- column-lane maps")
+    h.update(src[a:b].encode())
+    with open(os.path.join(ROOT, "paper_1912_06525_amd", "csrc", "kernels.h"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -105,13 +111,13 @@ def main():
     out = torch.empty((1, g.n), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
 
-    def run(idx, method, steps, offset):
+    def run(idx, method, steps, offset, check_every=0):
         lat, its, res = [], [], []
         for s in range(steps):
             q = queries[(offset + s) % len(queries)]
             t = time.perf_counter()
             _, st = idx.query([q], out=out, tol=tol, method=method, stream=stream,
-                              check_every=int(os.environ.get("KATZ_CHECK_EVERY", "0")))
+                              check_every=check_every or int(os.environ.get("KATZ_CHECK_EVERY", "0")))
             lat.append(time.perf_counter() - t)
             its.append(st[0]["iters"])
             res.append(st[0]["rel_residual"])
@@ -144,10 +150,12 @@ def main():
                                                                     entry[name]["ms_per_query"],
                                                                     entry[name]["iters_median"]))
             if c == head_c and not args.no_profile_kernels:
-                # repeat of the timed steps with HIP-event timing of every hot kernel launch
+                # repeat of the timed steps with HIP-event timing of every hot kernel
+                # launch; convergence is polled every iteration here so that no
+                # launch runs after a query has converged (each timed launch works)
                 K.katz_profile_reset()
                 K.katz_profile_enable(True)
-                run(idx, method, args.steps, args.warmup)
+                run(idx, method, args.steps, args.warmup, check_every=1)
                 torch.cuda.synchronize()
                 K.katz_profile_enable(False)
                 tab = [r for r in K.katz_profile_read() if r["launches"] > 0]

@@ -909,10 +909,10 @@ __global__ void k_unpermute(int n, int B, const T* K, const int32_t* perm, doubl
 // kernels on the solve stream, harvested at the solver's host sync points,
 // plus the algorithmic bytes each launch moves (formulas next to the launches).
 enum ProfKind { PK_SPMM_SEP = 0, PK_SPMM_FULL, PK_M11, PK_VT, PK_LOWRANK, PK_UPDATE_R, PK_UPDATE_P, PK_TOPK,
-                PK_OTHER, PK_COUNT };
+                PK_OTHER, PK_SPMM_RHS, PK_COUNT };
 static const char* kProfNames[PK_COUNT] = {"spmm_separator_rows", "spmm_all_rows", "m11_block_apply",
                                            "lowrank_vt", "lowrank_apply", "update_r", "update_p", "topk_select",
-                                           "other"};
+                                           "other", "spmm_schur_rhs"};
 struct ProfTable {
   std::mutex mu;
   int64_t launches[PK_COUNT] = {};
@@ -1431,7 +1431,7 @@ struct Launcher {
     const double wb = (double)sizeof(T) * B;
     int panels = 1 + (a.v ? 1 : 0) + (a.w ? 1 : 0) + ((a.dotv && a.dotv != a.v) ? 1 : 0);
     double bytes = 8.0 * rows + 4.0 + (4.0 + (a.val ? 8.0 : 0.0)) * nnz_sel + wb * cols_sel + wb * rows * panels;
-    const int kind = sep ? PK_SPMM_SEP : PK_SPMM_FULL;
+    const int kind = sep ? (a.parts == 1 ? PK_SPMM_RHS : PK_SPMM_SEP) : PK_SPMM_FULL;
     bool launched = false;
 #define KZ_SPMM(ts, cw)                                                                    \
   if (!launched && TS == ts && CW == cw) {                                                 \
