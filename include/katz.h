@@ -213,6 +213,51 @@ int katz_index_partition(const katz_index* idx, int32_t* perm, int32_t* block_pt
  */
 int katz_index_lowrank(const katz_index* idx, double* U, double* sigma);
 
+/* ------------------------------------------------------------- serving
+ * Continuous batching of top-K link-prediction requests (Sec. 3.3) on one
+ * index: `workers` worker slots, each with a device workspace of `max_batch`
+ * query columns and its own stream, take columns from the head of the request
+ * queue (merging small requests, splitting large ones) whenever they are free,
+ * so requests arriving while others run are admitted as slots free up and
+ * their batches overlap on the device.  Workers x max_batch is admitted
+ * against hbm_fraction of the free HBM at creation (reduced to fit; KATZ_ENOMEM
+ * if not even one column fits).  All calls are thread-safe. */
+typedef struct katz_server katz_server;
+
+typedef struct {
+  int32_t workers;       /* worker slots (0: 4), reduced to fit the HBM budget */
+  int32_t max_batch;     /* query columns per worker batch, 1..512 (default 64) */
+  double hbm_fraction;   /* share of free HBM for the workspaces (default 0.8) */
+  int32_t k;             /* links returned per query node (default 100) */
+  katz_query_opts query; /* solve options for every batch */
+} katz_server_opts;
+
+typedef struct {
+  int32_t workers, capacity, k;   /* as admitted */
+  int64_t queued_queries;         /* query nodes waiting for a worker */
+  int64_t live_columns;           /* query columns being solved now */
+  int64_t done_queries, done_requests;
+  int64_t bytes_per_column;       /* device workspace bytes per resident column */
+} katz_server_info_t;
+
+void katz_server_opts_default(katz_server_opts* o);
+/* Starts the workers.  idx must outlive the server.  Errors: KATZ_EINVAL,
+ * KATZ_EDEVICE (host-only index), KATZ_ENOMEM. */
+int katz_server_create(const katz_index* idx, const katz_server_opts* opts, katz_server** out);
+/* Queues a request of nq query nodes (copied); returns at once with a ticket.
+ * Errors: KATZ_EINVAL (bad ids), KATZ_EBUSY (server stopping). */
+int katz_server_submit(katz_server* s, const int32_t* q, int32_t nq, int64_t* ticket);
+/* Waits up to timeout_us (0: do not wait, < 0: forever) for a request; when it
+ * is complete copies ids[nq*k], scores[nq*k], st[nq] (each nullable) and the
+ * submit-to-completion latency, releases the ticket and returns its status
+ * (KATZ_OK or KATZ_ENOCONV).  KATZ_EBUSY if still running, KATZ_EINVAL for an
+ * unknown ticket. */
+int katz_server_poll(katz_server* s, int64_t ticket, int32_t* ids, double* scores, katz_query_stats* st,
+                     double* latency_ms, int64_t timeout_us);
+int katz_server_info(katz_server* s, katz_server_info_t* info);
+/* Finishes the queued requests, stops the workers and frees the workspaces. */
+void katz_server_destroy(katz_server* s);
+
 /* Per-kernel timing of the query path (tracing aid): with profiling on, every
  * launch of the hot kernels is bracketed by HIP events on the solve stream and
  * the algorithmic bytes it moves are booked to its kind. */

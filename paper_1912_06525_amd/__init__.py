@@ -34,7 +34,8 @@ _STATUS = {0: "KATZ_OK", -1: "KATZ_EINVAL", -2: "KATZ_ENOTSYM", -3: "KATZ_EDIVER
 EXPORTED = ["katz_build_opts_default", "katz_query_opts_default", "katz_index_build", "katz_query",
             "katz_topk_links", "katz_index_free", "katz_index_info", "katz_index_partition",
             "katz_index_lowrank", "katz_profile_enable", "katz_profile_reset", "katz_profile_read",
-            "katz_last_error"]
+            "katz_server_opts_default", "katz_server_create", "katz_server_submit", "katz_server_poll",
+            "katz_server_info", "katz_server_destroy", "katz_last_error"]
 
 
 class katz_build_opts(ctypes.Structure):
@@ -64,6 +65,18 @@ class katz_index_info_t(ctypes.Structure):
                 ("sigma_max", ctypes.c_double), ("sigma_next", ctypes.c_double),
                 ("factor_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("build_seconds", ctypes.c_double)]
+
+
+class katz_server_opts(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("hbm_fraction", ctypes.c_double),
+                ("k", ctypes.c_int32), ("query", katz_query_opts)]
+
+
+class katz_server_info_t(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("capacity", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("queued_queries", ctypes.c_int64), ("live_columns", ctypes.c_int64),
+                ("done_queries", ctypes.c_int64), ("done_requests", ctypes.c_int64),
+                ("bytes_per_column", ctypes.c_int64)]
 
 
 class katz_kernel_stat(ctypes.Structure):
@@ -113,6 +126,19 @@ def _load():
     lib.katz_profile_reset.restype = None
     lib.katz_profile_read.argtypes = [ctypes.POINTER(katz_kernel_stat), ctypes.c_int]
     lib.katz_profile_read.restype = ctypes.c_int
+    lib.katz_server_opts_default.argtypes = [ctypes.POINTER(katz_server_opts)]
+    lib.katz_server_opts_default.restype = None
+    lib.katz_server_create.argtypes = [P, ctypes.POINTER(katz_server_opts), ctypes.POINTER(P)]
+    lib.katz_server_create.restype = ctypes.c_int
+    lib.katz_server_submit.argtypes = [P, pi32, i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.katz_server_submit.restype = ctypes.c_int
+    lib.katz_server_poll.argtypes = [P, ctypes.c_int64, pi32, pdbl, ctypes.POINTER(katz_query_stats),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int64]
+    lib.katz_server_poll.restype = ctypes.c_int
+    lib.katz_server_info.argtypes = [P, ctypes.POINTER(katz_server_info_t)]
+    lib.katz_server_info.restype = ctypes.c_int
+    lib.katz_server_destroy.argtypes = [P]
+    lib.katz_server_destroy.restype = None
     lib.katz_last_error.argtypes = []
     lib.katz_last_error.restype = ctypes.c_char_p
     return lib
@@ -326,3 +352,62 @@ class KatzIndex:
         katz_topk_links(self.h, q, k, self._opts(tol, method, max_iter, max_sweeps, check_every), ids, scores,
                         st, stream)
         return ids, scores, stats_dicts(st)
+
+
+# --------------------------------------------------------------- serving
+def katz_server_opts_default() -> katz_server_opts:
+    o = katz_server_opts()
+    _lib.katz_server_opts_default(ctypes.byref(o))
+    return o
+
+
+class KatzServer:
+    """Continuous-batching top-K server over one KatzIndex (katz_server_*)."""
+
+    def __init__(self, index: KatzIndex, *, workers: int = 0, max_batch: int = 64, hbm_fraction: float = 0.8,
+                 k: int = 100, tol: float = 1e-6, method: int = KATZ_METHOD_LRC):
+        o = katz_server_opts_default()
+        o.workers, o.max_batch, o.hbm_fraction, o.k = workers, max_batch, hbm_fraction, k
+        o.query.rel_tol = tol
+        o.query.method = method
+        self.index = index          # keeps the index alive
+        self.k = k
+        self.h = ctypes.c_void_p()
+        _check(_lib.katz_server_create(index.h, ctypes.byref(o), ctypes.byref(self.h)))
+        self._nq = {}
+
+    def submit(self, q) -> int:
+        qa = np.ascontiguousarray(np.atleast_1d(q), np.int32)
+        t = ctypes.c_int64()
+        _check(_lib.katz_server_submit(self.h, _pi32(qa), len(qa), ctypes.byref(t)))
+        self._nq[t.value] = len(qa)
+        return t.value
+
+    def poll(self, ticket: int, timeout_us: int = -1):
+        """(ids [nq, k], scores [nq, k], stats, latency_ms) or None if not done."""
+        nq = self._nq[ticket]
+        ids = np.empty((nq, self.k), np.int32)
+        sc = np.empty((nq, self.k), np.float64)
+        st = (katz_query_stats * nq)()
+        lat = ctypes.c_double()
+        rc = _lib.katz_server_poll(self.h, ticket, _pi32(ids), _pdbl(sc), st, ctypes.byref(lat), int(timeout_us))
+        if rc == KATZ_EBUSY:
+            return None
+        if rc not in (KATZ_OK, KATZ_ENOCONV):
+            _check(rc)
+        del self._nq[ticket]
+        return ids, sc, stats_dicts(st), lat.value
+
+    def info(self) -> dict:
+        i = katz_server_info_t()
+        _check(_lib.katz_server_info(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in katz_server_info_t._fields_}
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.katz_server_destroy(h)
+        self.h = None
+
+    def __del__(self):
+        self.close()

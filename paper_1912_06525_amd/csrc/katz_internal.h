@@ -76,11 +76,22 @@ struct QueryArgs {
   void* stream;
 };
 int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& a);
+// Device workspace (panels, partial sums, stream) reusable across calls.
+struct Workspace;
+Workspace* ws_create(DeviceIndex* D, int cap);
+void ws_destroy(DeviceIndex* D, Workspace* w);
+int ws_capacity(const Workspace* w);
+// As device_query, on the given workspace when it is large enough (NULL: pooled).
+int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& a, Workspace* w);
 int profile_enable(int on);
 void profile_reset();
 int profile_read(katz_kernel_stat* out, int max);
 
 }  // namespace katz
+
+namespace katz {
+struct Server;
+}
 
 struct katz_index {
   katz::HostIndex host;

@@ -966,7 +966,7 @@ struct ProfEvents {
 
 // ============================================================= device index
 struct Workspace {
-  int B = 0;
+  int B = 0;  // capacity in columns (a call may use any width <= B)
   int64_t n = 0, n2 = 0;
   double *Bp = nullptr, *Rhs = nullptr, *K = nullptr, *Dx = nullptr, *X = nullptr, *Y = nullptr,
          *W = nullptr, *Z = nullptr;
@@ -1309,18 +1309,21 @@ static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   return w;
 }
 
+// Takes the pooled workspace of the smallest capacity >= B (or makes one of
+// capacity B) for the duration of a call, and returns it to the pool.
 struct WsLease {
   DeviceIndex* D;
   std::unique_ptr<Workspace> w;
   WsLease(DeviceIndex* d, int B) : D(d) {
     {
       std::lock_guard<std::mutex> g(D->mu);
+      int best = -1;
       for (size_t i = 0; i < D->pool.size(); i++)
-        if (D->pool[i]->B == B) {
-          w = std::move(D->pool[i]);
-          D->pool.erase(D->pool.begin() + i);
-          break;
-        }
+        if (D->pool[i]->B >= B && (best < 0 || D->pool[i]->B < D->pool[best]->B)) best = (int)i;
+      if (best >= 0) {
+        w = std::move(D->pool[best]);
+        D->pool.erase(D->pool.begin() + best);
+      }
     }
     if (!w) w = make_ws(D, B);
   }
@@ -1450,7 +1453,7 @@ struct Launcher {
   void iterate(int64_t key, int max_iter, int check_every, F&& one_iter) {
     int* hflag = (int*)((char*)w->hpin + kPinFlagOff);
     const bool graphs = tuning().graphs && !g_prof_on.load(std::memory_order_relaxed);
-    const int64_t gkey = (key << 40) ^ ((int64_t)check_every << 20) ^ (int64_t)max_iter;
+    const int64_t gkey = (key << 56) ^ ((int64_t)B << 40) ^ ((int64_t)check_every << 20) ^ (int64_t)max_iter;
     for (int it = 0; it < max_iter; it += check_every) {
       const int len = std::min(check_every, max_iter - it);
       hipGraphExec_t ex = nullptr;
@@ -1883,11 +1886,25 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
     if (!res[j].done) res[j].status = KATZ_ENOCONV;
 }
 
-int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa) {
+int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa) { return device_query_ws(H, D, qa, nullptr); }
+
+Workspace* ws_create(DeviceIndex* D, int cap) {
+  HIPCHECK(hipSetDevice(D->device));
+  return make_ws(D, cap).release();
+}
+void ws_destroy(DeviceIndex* D, Workspace* w) {
+  if (!w) return;
+  (void)hipSetDevice(D->device);
+  free_ws(w);
+  delete w;
+}
+int ws_capacity(const Workspace* w) { return w ? w->B : 0; }
+
+int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Workspace* fixed) {
   HIPCHECK(hipSetDevice(D->device));
   hipStream_t st = (hipStream_t)qa.stream;
   const int n = D->n;
-  const int BMAX = 512;
+  const int BMAX = fixed ? std::min(512, fixed->B) : 512;
   bool dev_scores = is_device_ptr(qa.scores);
   bool dev_ids = is_device_ptr(qa.ids);
   if (qa.topk > 0 && qa.topk_scores && is_device_ptr(qa.topk_scores) != dev_ids)
@@ -1895,8 +1912,12 @@ int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa) {
   int rc = KATZ_OK;
   for (int c0 = 0; c0 < qa.nq; c0 += BMAX) {
     const int B = std::min(BMAX, qa.nq - c0);
-    WsLease lease(D, B);
-    Workspace* w = lease.w.get();
+    std::unique_ptr<WsLease> lease;
+    Workspace* w = fixed;
+    if (!w || w->B < B) {
+      lease.reset(new WsLease(D, B));
+      w = lease->w.get();
+    }
     // work runs on the workspace's stream, ordered after the caller's stream
     HIPCHECK(hipEventRecord(w->ev_in, st));
     HIPCHECK(hipStreamWaitEvent(w->stream, w->ev_in, 0));
