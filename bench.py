@@ -77,6 +77,10 @@ def main():
                     help="cl1m (default, one query per solve), lnsbm4m (256 FP64 RHS), cl8m (512 mixed RHS)")
     ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
     ap.add_argument("--u-precision", type=int, default=0, help="low-rank factor storage (0 auto, 1 FP64, 2 FP32, 3 BF16)")
+    ap.add_argument("--serve", action="store_true", help="serving mode on --workload (default dcsbm16m)")
+    ap.add_argument("--requests", type=int, default=200, help="requests per offered-load point (serving)")
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--max-batch-cols", type=int, default=64)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -94,6 +98,8 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.serve:
+        return run_serving(args)
     if args.workload != "cl1m":
         return run_batched(args)
 
@@ -310,6 +316,94 @@ def run_batched(args):
                        "n": g.n, "nnz": g.nnz, "batch": B},
             "cg_qps": round(head["cg"]["qps"], 2), "lrc_over_cg": round(head["lrc"]["qps"] / head["cg"]["qps"], 3),
             "roofline": roofline, "cpu_baseline": None, "results": results}
+    print(json.dumps(line), flush=True)
+
+
+def run_serving(args):
+    """Serving: Poisson arrivals of top-100 link-prediction requests of
+    round(2^u) query nodes, u ~ U[0, 9]; saturation throughput, then offered
+    loads of 0.5 / 0.8 / 0.95 x saturation with p50 / p99 latency."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import katz_inputs as ki
+    import paper_1912_06525_amd as K
+
+    wl = args.workload if args.workload != "cl1m" else "dcsbm16m"
+    t0 = time.time()
+    w = ki.workload(wl, scale=args.scale)
+    g = w.graph
+    log("graph %s: n=%d nnz=%d (%.1fs)" % (wl, g.n, g.nnz, time.time() - t0))
+    c = 0.5
+    rank = args.rank if args.rank != 32 else w.rank
+    prec = K.KATZ_PREC_MIXED if w.precision == "mixed" else K.KATZ_PREC_FP64
+    tb = time.time()
+    idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=rank, max_block=args.max_block, device=0,
+                                 labels=g.labels, precision=prec)
+    log("index: n2=%d build %.1fs" % (idx.info.n2, time.time() - tb))
+    rng = np.random.default_rng(4005)
+    pool = ki.sample_queries(g, min(g.n // 2, 200000), 4006)
+    results = {}
+    for method_name, method in (("lrc", K.KATZ_METHOD_LRC), ("cg", K.KATZ_METHOD_CG)):
+        srv = K.KatzServer(idx, workers=args.workers, max_batch=args.max_batch_cols, k=100, tol=1e-6,
+                           method=method)
+        info = srv.info()
+        log("server %s: %d workers x %d columns (%.2f GB per column)" % (method_name, info["workers"], info["capacity"],
+                                                                         info["bytes_per_column"] / 1e9))
+
+        def make_req():
+            size = int(round(2 ** rng.uniform(0, 9)))
+            return pool[rng.integers(0, len(pool), size=size)]
+
+        # warm-up (workspaces, graphs)
+        for t in [srv.submit(make_req()) for _ in range(args.workers * 2)]:
+            srv.poll(t)
+        # saturation: a burst of requests, completion rate in queries/s
+        reqs = [make_req() for _ in range(args.requests)]
+        tt = time.perf_counter()
+        tks = [srv.submit(r) for r in reqs]
+        lats = [srv.poll(t)[3] for t in tks]
+        el = time.perf_counter() - tt
+        nq = sum(len(r) for r in reqs)
+        sat = nq / el
+        entry = {"saturation_qps": sat, "burst_requests": len(reqs), "mean_request_size": nq / len(reqs)}
+        log("  %s saturation: %.1f queries/s (%d requests, %d queries, %.1fs)" % (method_name, sat, len(reqs), nq, el))
+        for load in (0.5, 0.8, 0.95):
+            reqs = [make_req() for _ in range(args.requests)]
+            mean_q = np.mean([len(r) for r in reqs])
+            rate = load * sat / mean_q                       # requests per second
+            gaps = rng.exponential(1.0 / rate, size=len(reqs))
+            tks = []
+            tt = time.perf_counter()
+            nxt = tt
+            for r, gp in zip(reqs, gaps):
+                nxt += gp
+                d = nxt - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tks.append(srv.submit(r))
+            lat = np.array([srv.poll(t)[3] for t in tks])
+            el = time.perf_counter() - tt
+            nq = sum(len(r) for r in reqs)
+            entry["load_%g" % load] = {"offered_qps": load * sat, "achieved_qps": nq / el,
+                                       "p50_ms": float(np.percentile(lat, 50)),
+                                       "p99_ms": float(np.percentile(lat, 99))}
+            log("  %s load %.2f: offered %.1f q/s, achieved %.1f q/s, p50 %.1f ms, p99 %.1f ms"
+                % (method_name, load, load * sat, nq / el, np.percentile(lat, 50), np.percentile(lat, 99)))
+        results[method_name] = entry
+        srv.close()
+    head = results["lrc"]
+    line = {"metric": "Katz queries/sec at 1e-6 rel. residual, LRC-Katz vs CG, 1 MI355X; p99 ms",
+            "value": round(head["saturation_qps"], 2), "unit": "queries/s", "n_gpus": 1, "steps": args.requests,
+            "warmup": args.workers * 2, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+bf16/f64" if prec == K.KATZ_PREC_MIXED else "f64",
+            "data": "synthetic",
+            "config": {"workload": "serving, %s, %d nodes, top-100 requests of 1-512 nodes" % (wl, g.n),
+                       "n": g.n, "nnz": g.nnz, "workers": args.workers, "max_batch": args.max_batch_cols},
+            "p99_ms": round(head["load_0.8"]["p99_ms"], 3), "cg_qps": round(results["cg"]["saturation_qps"], 2),
+            "roofline": None, "cpu_baseline": None, "results": results}
     print(json.dumps(line), flush=True)
 
 

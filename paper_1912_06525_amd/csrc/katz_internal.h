@@ -81,6 +81,8 @@ struct Workspace;
 Workspace* ws_create(DeviceIndex* D, int cap);
 void ws_destroy(DeviceIndex* D, Workspace* w);
 int ws_capacity(const Workspace* w);
+// Device bytes one column of workspace capacity takes.
+int64_t ws_bytes_per_column(const DeviceIndex* D);
 // As device_query, on the given workspace when it is large enough (NULL: pooled).
 int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& a, Workspace* w);
 int profile_enable(int on);

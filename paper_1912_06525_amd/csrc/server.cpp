@@ -179,15 +179,8 @@ void katz_server_opts_default(katz_server_opts* o) {
 }  // extern "C"
 
 namespace katz {
-// Bytes of device workspace per resident query column (node-length panels of
-// the solve, FP64 plus the FP32 copy of the precision form).
-int64_t bytes_per_column(const katz_index* idx) {
-  const HostIndex& H = idx->host;
-  int64_t b = (int64_t)H.n * 8 * 7 + (int64_t)std::max(1, H.n2) * 8;
-  if (H.precision == KATZ_PREC_MIXED) b += (int64_t)H.n * 4;
-  b += (int64_t)H.n * 8 / 4;  // output staging, top-K, partial sums (approx.)
-  return b;
-}
+// Bytes of device workspace per resident query column.
+int64_t bytes_per_column(const katz_index* idx) { return ws_bytes_per_column(idx->dev); }
 }  // namespace katz
 
 extern "C" {

@@ -968,8 +968,12 @@ struct ProfEvents {
 struct Workspace {
   int B = 0;  // capacity in columns (a call may use any width <= B)
   int64_t n = 0, n2 = 0;
-  double *Bp = nullptr, *Rhs = nullptr, *K = nullptr, *Dx = nullptr, *X = nullptr, *Y = nullptr,
-         *W = nullptr, *Z = nullptr;
+  // FP64: Rhs (b, then each sweep's residual), K (accumulated solution).
+  // Solve panels in the precision of the inner solves (FP64, or FP32 for
+  // the precision form; typed at the point of use): Dx, X (n rows), Y, W
+  // (n rows for CG, n2 used by LRC), Z (n2 rows).
+  double *Rhs = nullptr, *K = nullptr;
+  void *Dx = nullptr, *X = nullptr, *Y = nullptr, *W = nullptr, *Z = nullptr;
   double* partials = nullptr;
   size_t partials_cap = 0;
   double* DW = nullptr;
@@ -977,8 +981,6 @@ struct Workspace {
   float* Rf = nullptr;             // scaled FP32 right-hand side (precision form)
   int *active, *status, *iters, *n_active, *mask;
   int32_t* qpos = nullptr;
-  double* out_scores = nullptr;  // staging for host output
-  int64_t out_cap = 0;
   void* tk_scratch = nullptr;    // top-K selection state and winners
   size_t tk_cap = 0;
   int32_t* tk_ids = nullptr;     // staging for host top-K output
@@ -991,6 +993,7 @@ struct Workspace {
   hipStream_t stream = nullptr;          // the workspace's own stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;  // captured iteration chunks
+  ~Workspace();
 };
 
 struct DeviceIndex {
@@ -1202,8 +1205,12 @@ static void free_ws(Workspace* w) {
   w->ev_in = w->ev_out = nullptr;
   for (void* p : w->allocs) (void)hipFree(p);
   if (w->hpin) (void)hipHostFree(w->hpin);
+  w->hpin = nullptr;
   w->allocs.clear();
 }
+// Frees everything still held (also a workspace whose creation failed part
+// way); free_ws is idempotent.
+Workspace::~Workspace() { free_ws(this); }
 
 void device_free(DeviceIndex* D) {
   if (!D) return;
@@ -1230,6 +1237,7 @@ template <> struct Factors<float> {
 };
 
 constexpr size_t kPinFlagOff = 16384;  // pinned staging offset of the poll flag
+constexpr size_t kPinProfOff = 28672;  // active-column count read for profiling
 
 // ================================================================== tuning
 // Launch shapes (overridable from the environment for tuning sweeps).  Every
@@ -1267,6 +1275,26 @@ static const Tuning& tuning() {
 }
 
 // ================================================================ workspace
+// Element size of the inner-solve panels: FP32 for the precision form.
+static int64_t solve_elem_bytes(const DeviceIndex* D) { return D->precision == KATZ_PREC_MIXED ? 4 : 8; }
+// Partial sums per column: the largest producer is the SpMM (short + hub
+// workgroups) or a row-parallel kernel, times max(1, rank) values.
+static size_t partials_per_column(const DeviceIndex* D) {
+  const Tuning& tu = tuning();
+  size_t wgs = std::max<size_t>((size_t)tu.spmm_nwg + std::max(D->n_long_all, D->n_long_sep), (size_t)tu.ew_nwg);
+  return wgs * (size_t)std::max(1, D->rank);
+}
+// Device bytes of a workspace per column of capacity (panels, FP32 copy of
+// the right-hand side, partial sums, top-K scratch for K <= 4096).
+int64_t ws_bytes_per_column(const DeviceIndex* D) {
+  const int64_t n = D->n, n2 = std::max(1, D->n2), esz = solve_elem_bytes(D);
+  int64_t b = 16 * n + esz * (4 * n + n2);
+  if (D->precision == KATZ_PREC_MIXED) b += 4 * n;
+  b += 8 * (int64_t)partials_per_column(D) + 8 * std::max(1, D->rank);
+  b += 64 + 1024 + 12 * 4096;
+  return b;
+}
+
 static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   auto w = std::make_unique<Workspace>();
   w->B = B;
@@ -1275,21 +1303,15 @@ static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   w->device = D->device;
   auto& L = w->allocs;
   const int64_t nB = (int64_t)D->n * B;
-  w->Bp = dalloc<double>(L, nB);
+  const int64_t esz = solve_elem_bytes(D);
   w->Rhs = dalloc<double>(L, nB);
   w->K = dalloc<double>(L, nB);
-  w->Dx = dalloc<double>(L, nB);
-  w->X = dalloc<double>(L, nB);
-  w->Y = dalloc<double>(L, nB);
-  w->W = dalloc<double>(L, nB);
-  w->Z = dalloc<double>(L, (int64_t)std::max(1, D->n2) * B);
-  {
-    // largest producer: SpMM (short + hub workgroups) x B, or a row-parallel
-    // kernel x max(B, rank * B)
-    const Tuning& tu = tuning();
-    size_t wgs = std::max<size_t>((size_t)tu.spmm_nwg + std::max(D->n_long_all, D->n_long_sep), (size_t)tu.ew_nwg);
-    w->partials_cap = wgs * (size_t)std::max(1, D->rank) * (size_t)std::max(B, 1);
-  }
+  w->Dx = dalloc<char>(L, nB * esz);
+  w->X = dalloc<char>(L, nB * esz);
+  w->Y = dalloc<char>(L, nB * esz);
+  w->W = dalloc<char>(L, nB * esz);
+  w->Z = dalloc<char>(L, (int64_t)std::max(1, D->n2) * B * esz);
+  w->partials_cap = partials_per_column(D) * (size_t)std::max(B, 1);
   w->partials = dalloc<double>(L, (int64_t)w->partials_cap);
   w->DW = dalloc<double>(L, (int64_t)std::max(1, D->rank) * B);
   double* s = dalloc<double>(L, 12 * (int64_t)B);
@@ -1360,6 +1382,20 @@ struct Launcher {
     if (on) w->prof.begin(kind, bytes, st);
     launch();
     if (on) w->prof.end(st);
+  }
+  // As timed(), for kernels that touch only the active columns: with
+  // profiling on, first reads the active-column count (a stream sync outside
+  // the timed region) and books bytes_per_col for each active column.
+  template <typename F>
+  void timed_cols(int kind, double bytes_per_col, F&& launch) {
+    double b = 0.0;
+    if (g_prof_on.load(std::memory_order_relaxed) != 0) {
+      int* h = (int*)((char*)w->hpin + kPinProfOff);
+      HIPCHECK(hipMemcpyAsync(h, w->n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      b = bytes_per_col * (double)*h;
+    }
+    timed(kind, b, launch);
   }
   void sync() {
     HIPCHECK(hipStreamSynchronize(st));
@@ -1694,13 +1730,13 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
           precond_simple<T, TV>(L, V, R2, Z2, EP_RZ, cs, w->n_active, rpw2, nwg2, true);
         });
       } else {
-        L.timed(PK_UPDATE_R, 6.0 * sizeof(T) * B * n2, [&] {
+        L.timed_cols(PK_UPDATE_R, 6.0 * sizeof(T) * n2, [&] {
           k_update_r<T><<<nwg2, WG, WG * sizeof(double), st>>>(n2, B, rpw2, K2, P2, R2, Q2, cs, w->partials);
         });
         L.finalize(nwg2, B, EP_RR, cs, nullptr, w->n_active);
         precond(EP_RZ);
       }
-      L.timed(PK_UPDATE_P, 3.0 * sizeof(T) * B * n2, [&] {
+      L.timed_cols(PK_UPDATE_P, 3.0 * sizeof(T) * n2, [&] {
         k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 0, cs);
       });
   });
@@ -1736,11 +1772,11 @@ static void solve_cg(Launcher& L, const T* rhs, int max_iter, int check_every) {
       a.v = P; a.cv = (T)1; a.w = nullptr; a.cw = (T)0; a.y = Q;
       a.ep = EP_PQ; a.dotv = P; a.cs = cs; a.n_active = w->n_active;
       L.spmm(a);
-      L.timed(PK_UPDATE_R, 6.0 * sizeof(T) * B * m, [&] {
+      L.timed_cols(PK_UPDATE_R, 6.0 * sizeof(T) * m, [&] {
         k_update_r<T><<<nwg, WG, WG * sizeof(double), st>>>(m, B, rpw, Dx, P, R, Q, cs, w->partials);
       });
       L.finalize(nwg, B, EP_RR_CG, cs, nullptr, w->n_active);
-      L.timed(PK_UPDATE_P, 3.0 * sizeof(T) * B * m, [&] {
+      L.timed_cols(PK_UPDATE_P, 3.0 * sizeof(T) * m, [&] {
         k_update_p<T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, P, 0, cs);
       });
   });
@@ -1784,10 +1820,15 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
   int32_t* hq = (int32_t*)(pin + kPinQ);
   for (int j = 0; j < B; j++) hq[j] = H.perm[q[j]];
   HIPCHECK(hipMemcpyAsync(w->qpos, hq, sizeof(int32_t) * B, hipMemcpyHostToDevice, st));
-  L.fill<double>(w->Bp, nB, 0.0);
-  k_rhs_scatter<double><<<B, WG, 0, st>>>(w->qpos, B, D->rp, D->col, D->val, D->beta, w->Bp);
+  // b is sparse (deg(q) entries per column) and is written into Rhs
+  // afresh where it is needed, instead of being kept as a dense panel
+  auto put_b = [&] {
+    L.fill<double>(w->Rhs, nB, 0.0);
+    k_rhs_scatter<double><<<B, WG, 0, st>>>(w->qpos, B, D->rp, D->col, D->val, D->beta, w->Rhs);
+  };
+  put_b();
   L.fill<double>(w->K, nB, 0.0);
-  L.colnorm2<double>(w->Bp, n, w->bn2);
+  L.colnorm2<double>(w->Rhs, n, w->bn2);
   // thresholds and the first sweep's mask on the device (no host round trip)
   const double tol = o.rel_tol;
   k_cols_setup<<<1, WG, 0, st>>>(B, w->bn2, 0.25 * tol * tol, w->thr, w->mask);
@@ -1800,7 +1841,7 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
     bool any = false;
     for (int j = 0; j < B; j++) any |= !res[j].done;
     if (!any) break;
-    const double* rhs = sweep == 0 ? w->Bp : w->Rhs;
+    const double* rhs = w->Rhs;  // b in the first sweep, then the residual
     // each column takes one path per sweep, chosen before the sweep starts
     int ran[2] = {0, 0};
     for (int pass = 0; pass < 2; pass++) {
@@ -1834,18 +1875,22 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
           solve_cg<double>(L, rhs, iters, o.check_every);
         else
           solve_lrc<double>(L, rhs, iters, o.check_every);
-        k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, w->Dx, w->mask, nullptr, 1);
+        k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const double*)w->Dx, w->mask,
+                                                                    nullptr, 1);
       }
       HIPCHECK(hipMemcpyAsync(pin + (pass ? kPinStat1 : kPinStat0), w->status, sizeof(int) * B,
                               hipMemcpyDeviceToHost, st));
       HIPCHECK(hipMemcpyAsync(pin + (pass ? kPinIter1 : kPinIter0), w->iters, sizeof(int) * B,
                               hipMemcpyDeviceToHost, st));
     }
-    // a6: true FP64 residual r = b - M k, which is the next sweep's right-hand side
+    // a6: true FP64 residual r = b - M k, which is the next sweep's right-hand
+    // side: Rhs = b, then Rhs = Rhs + beta A k - k in place (each element is
+    // read and written by the same lane)
+    put_b();
     SpmmArgs<double> a{};
     a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
     a.x = w->K; a.ca = D->beta; a.cb = D->beta; a.parts = 3;
-    a.v = w->Bp; a.cv = 1.0; a.w = w->K; a.cw = -1.0; a.y = w->Rhs;
+    a.v = w->Rhs; a.cv = 1.0; a.w = w->K; a.cw = -1.0; a.y = w->Rhs;
     a.ep = EP_RES; a.dotv = nullptr; a.out = w->res2; a.n_active = nullptr; a.cs = L.cs(0);
     L.spmm(a);
     HIPCHECK(hipMemcpyAsync(hres, w->res2, sizeof(double) * B, hipMemcpyDeviceToHost, st));
@@ -1954,13 +1999,7 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
     if (qa.scores) {
       double* dst = qa.scores + (int64_t)c0 * n;
       double* out = dst;
-      if (!dev_scores) {
-        if (w->out_cap < (int64_t)n * B) {
-          w->out_scores = dalloc<double>(w->allocs, (int64_t)n * B);
-          w->out_cap = (int64_t)n * B;
-        }
-        out = w->out_scores;
-      }
+      if (!dev_scores) out = w->Rhs;  // free once the batch is solved
       dim3 g(grid_for(n, WG * 4), B);
       k_unpermute<double><<<g, WG, 0, st>>>(n, B, w->K, D->perm, out);
       if (!dev_scores)
