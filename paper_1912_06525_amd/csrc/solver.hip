@@ -108,11 +108,27 @@ struct ncm {
   static constexpr int value = CW == 64 ? MAXC : 1;
 };
 
-template <typename T, int CW, int NZ>
-__device__ inline void row_gather(const SpmmArgs<T>& a, int i, int nz, int cl, int NC, T* acc) {
-  const int32_t s = a.rp[i], e = a.rp[i + 1], sp = a.split[i];
-  const int32_t kb = (a.parts & 1) ? s : sp;
-  const int32_t ke = (a.parts & 2) ? e : sp;
+// VAL: weighted graph (entry values in a.val).  A compile-time switch: a
+// runtime test between the loads makes the compiler wait for each one.
+// Entry range [kb, ke) of row i taken by this launch and the split point sp
+// (entries before sp take ca, the others cb); len = the row's full length.
+struct RowRange {
+  int32_t kb, ke, sp, len;
+};
+template <typename T>
+__device__ inline RowRange row_range(const SpmmArgs<T>& a, int i) {
+  RowRange r;
+  const int32_t s = a.rp[i], e = a.rp[i + 1];
+  r.len = e - s;
+  r.sp = a.split[i];
+  r.kb = (a.parts & 1) ? s : r.sp;
+  r.ke = (a.parts & 2) ? e : r.sp;
+  return r;
+}
+
+template <typename T, int CW, int NZ, bool VAL>
+__device__ inline void row_gather(const SpmmArgs<T>& a, const RowRange& rr, int nz, int cl, int NC, T* acc) {
+  const int32_t kb = rr.kb, ke = rr.ke, sp = rr.sp;
   const int B = a.B;
   constexpr int NCM = ncm<CW>::value;
   int32_t k = kb + nz;
@@ -124,7 +140,7 @@ __device__ inline void row_gather(const SpmmArgs<T>& a, int i, int nz, int cl, i
       const int32_t kk = k + u * NZ;
       c[u] = a.col[kk];
       cf[u] = (kk < sp) ? a.ca : a.cb;
-      if (a.val) cf[u] *= (T)a.val[kk];
+      if (VAL) cf[u] *= (T)a.val[kk];
     }
 #pragma unroll
     for (int u = 0; u < 4; u++) {
@@ -136,23 +152,68 @@ __device__ inline void row_gather(const SpmmArgs<T>& a, int i, int nz, int cl, i
       }
     }
   }
-  for (; k < ke; k += NZ) {
-    const int32_t cidx = a.col[k];
-    T coef = (k < sp) ? a.ca : a.cb;
-    if (a.val) coef *= (T)a.val[k];
-    const T* xr = a.x + (int64_t)cidx * B;
+  if (k < ke) {
+    // tail of at most 3 entries per lane (most rows of a sparse graph end
+    // here), branch-free so that all its loads are in flight together: an
+    // index past the row's end is clamped to its last entry (a valid load)
+    // and its product masked to 0
+    int32_t c[3];
+    T cf[3];
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+      const int32_t kk = k + u * NZ;
+      const bool ok = kk < ke;
+      const int32_t kc = ok ? kk : ke - 1;
+      c[u] = a.col[kc];
+      cf[u] = (kk < sp) ? a.ca : a.cb;
+      if (VAL) cf[u] *= (T)a.val[kc];
+    }
 #pragma unroll
     for (int cc = 0; cc < NCM; cc++) {
       const int j = cl + CW * cc;
-      if (cc < NC && j < B) acc[cc] += coef * xr[j];
+      if (cc < NC && j < B) {
+        T xv[3];
+#pragma unroll
+        for (int u = 0; u < 3; u++) xv[u] = a.x[(int64_t)c[u] * B + j];
+#pragma unroll
+        for (int u = 0; u < 3; u++) acc[cc] += (k + u * NZ < ke) ? cf[u] * xv[u] : (T)0;
+      }
+    }
+  }
+}
+
+// Row-aligned operands of row i for the lane owning column group cl,
+// loaded before they are needed (for one accumulator per lane, at the start
+// of the row, so their latency overlaps the gather).
+template <typename T, int CW>
+struct RowOps {
+  T v[ncm<CW>::value], w[ncm<CW>::value];
+  double d[ncm<CW>::value];
+};
+template <typename T, int CW>
+__device__ inline void row_load(const SpmmArgs<T>& a, int i, int cl, int NC, RowOps<T, CW>& p) {
+  const int B = a.B;
+  constexpr int NCM = ncm<CW>::value;
+  const int64_t ro = (int64_t)(i - a.row0) * B;
+#pragma unroll
+  for (int cc = 0; cc < NCM; cc++) {
+    const int j = cl + CW * cc;
+    p.v[cc] = p.w[cc] = (T)0;
+    p.d[cc] = 0.0;
+    if (cc < NC && j < B) {
+      if (a.v) p.v[cc] = a.v[ro + j];
+      if (a.w) p.w[cc] = a.w[ro + j];
+      if (a.ep != EP_NONE && a.dotv) p.d[cc] = (double)a.dotv[ro + j];
     }
   }
 }
 
 // Finishes row i for the lane owning column group cl: adds the row-aligned
-// panels, stores y and accumulates the dot.
+// operands, stores y and accumulates the dot (in place, y == v, is allowed:
+// the lane has loaded v before).
 template <typename T, int CW>
-__device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, const T* acc, double* dacc) {
+__device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, const T* acc,
+                                  const RowOps<T, CW>& p, double* dacc) {
   const int B = a.B;
   constexpr int NCM = ncm<CW>::value;
   const int64_t ro = (int64_t)(i - a.row0) * B;
@@ -161,18 +222,18 @@ __device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, c
     const int j = cl + CW * cc;
     if (cc < NC && j < B) {
       T yv = acc[cc];
-      if (a.v) yv += a.cv * a.v[ro + j];
-      if (a.w) yv += a.cw * a.w[ro + j];
+      if (a.v) yv += a.cv * p.v[cc];
+      if (a.w) yv += a.cw * p.w[cc];
       a.y[ro + j] = yv;
       if (a.ep != EP_NONE) {
-        double d = a.dotv ? (double)a.dotv[ro + j] : (double)yv;
+        double d = a.dotv ? p.d[cc] : (double)yv;
         dacc[cc] += d * (double)yv;
       }
     }
   }
 }
 
-template <typename T, int TS, int CW>
+template <typename T, int TS, int CW, bool VAL>
 __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
   if (a.n_active && *a.n_active == 0) return;
   constexpr int NZ = TS / CW;
@@ -193,10 +254,12 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
     // ---- one hub row, whole workgroup
     const int cl = tid % CW, nz = tid / CW;
     const int i = a.long_rows[blockIdx.x];
+    RowOps<T, CW> ops;
+    if (tid < CW) row_load<T, CW>(a, i, tid, NC, ops);
     T acc[NCM];
 #pragma unroll
     for (int c = 0; c < NCM; c++) acc[c] = (T)0;
-    row_gather<T, CW, NZW>(a, i, nz, cl, NC, acc);
+    row_gather<T, CW, NZW, VAL>(a, row_range(a, i), nz, cl, NC, acc);
     // lanes of one wave sharing cl: xor over the wave; then across waves in LDS
 #pragma unroll
     for (int c = 0; c < NCM; c++) {
@@ -219,7 +282,7 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
           acc[c] = (T)t;
         }
       }
-      row_finish<T, CW>(a, i, tid, NC, acc, dacc);
+      row_finish<T, CW>(a, i, tid, NC, acc, ops, dacc);
     }
     __syncthreads();
     owner = tid < CW;
@@ -234,17 +297,23 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
     for (int64_t ch = sl.first; ch < sl.end; ch += sl.stride)
     for (int i = a.row0 + (int)ch * a.rows_per_wg + team,
              rend = min<int64_t>(a.row1, a.row0 + (ch + 1) * a.rows_per_wg); i < rend; i += TEAMS) {
-      if (a.long_rows && a.rp[i + 1] - a.rp[i] > a.long_thr) continue;  // done by its own workgroup
+      RowOps<T, CW> ops;
+      if (NCM == 1) row_load<T, CW>(a, i, cl, NC, ops);  // early: overlaps the row's other loads
+      const RowRange rr = row_range(a, i);
+      if (a.long_rows && rr.len > a.long_thr) continue;  // done by its own workgroup
       T acc[NCM];
 #pragma unroll
       for (int c = 0; c < NCM; c++) acc[c] = (T)0;
-      row_gather<T, CW, NZ>(a, i, nz, cl, NC, acc);
+      row_gather<T, CW, NZ, VAL>(a, rr, nz, cl, NC, acc);
 #pragma unroll
       for (int c = 0; c < NCM; c++) {
 #pragma unroll
         for (int off = CW; off < TS; off <<= 1) acc[c] += __shfl_xor(acc[c], off, TS);
       }
-      if (nz == 0) row_finish<T, CW>(a, i, cl, NC, acc, dacc);
+      if (nz == 0) {
+        if (NCM > 1) row_load<T, CW>(a, i, cl, NC, ops);
+        row_finish<T, CW>(a, i, cl, NC, acc, ops, dacc);
+      }
     }
     owner = nz == 0;
     slot = team;
@@ -633,6 +702,147 @@ __global__ __launch_bounds__(WG) void k_lowrank(int64_t m, int B, int rank, cons
   wg_colsum(cm, B, dacc, partials);
 }
 
+// ------------------------------------- low-rank products for B >= 2 columns
+// Both kernels give thread t of a workgroup one panel column,
+// j = blockIdx.y * JW + t % JW (JW: a power of two <= 256 covering B, or 256),
+// and WG / JW row groups; blockIdx.x is a chunk of rpc rows.  The rows of V
+// (column-major n2 x rank) of a 64-row block are staged in LDS as a row-major
+// tile (stride RMAX + 2 doubles: rows of different row groups fall in
+// different banks), so each panel element is read once and each V value once
+// per workgroup.  Ranks above `rank` (up to RMAX) are staged as 0.
+constexpr int kVRows = 64;
+
+template <typename TV, int RMAX>
+__device__ inline void stage_v(double* sV, const TV* V, int64_t m, int rank, int64_t b0, int nb) {
+  constexpr int LD = RMAX + 2;
+  for (int e = threadIdx.x; e < kVRows * RMAX; e += WG) {
+    const int k = e / kVRows, ii = e % kVRows;  // consecutive threads: consecutive rows of one column
+    sV[ii * LD + k] = (k < rank && ii < nb) ? to_d(V[(int64_t)k * m + b0 + ii]) : 0.0;
+  }
+}
+
+// W partials: partials[blockIdx.x * rank * B + k * B + j] = sum over the
+// chunk's rows i of V[i][k] r[i][j] (FP64 sums).
+template <typename T, typename TV, int RMAX>
+__global__ __launch_bounds__(WG) void k_vt_rows(int64_t m, int B, int rank, int JW, const TV* V, const T* r,
+                                                int64_t rpc, double* partials, const int* n_active) {
+  if (n_active && *n_active == 0) return;
+  constexpr int LD = RMAX + 2;
+  __shared__ double sV[kVRows * LD];
+  const int tid = threadIdx.x, jl = tid % JW, rg = tid / JW, NR = WG / JW;
+  const int j = blockIdx.y * JW + jl;
+  const bool col_ok = j < B;
+  const int64_t r0 = (int64_t)blockIdx.x * rpc, r1 = min<int64_t>(m, r0 + rpc);
+  double acc[RMAX];
+#pragma unroll
+  for (int k = 0; k < RMAX; k++) acc[k] = 0.0;
+  for (int64_t b0 = r0; b0 < r1; b0 += kVRows) {
+    const int nb = (int)min<int64_t>(kVRows, r1 - b0);
+    __syncthreads();
+    stage_v<TV, RMAX>(sV, V, m, rank, b0, nb);
+    __syncthreads();
+    if (col_ok) {
+      for (int ii = rg; ii < nb; ii += NR) {
+        const double x = (double)r[(b0 + ii) * B + j];
+        const double* vr = sV + ii * LD;
+#pragma unroll
+        for (int k = 0; k < RMAX; k++) acc[k] += vr[k] * x;
+      }
+    }
+  }
+  const int64_t nv = (int64_t)rank * B;
+  double* out = partials + (int64_t)blockIdx.x * nv;
+  if (NR == 1) {
+#pragma unroll
+    for (int k = 0; k < RMAX; k++)
+      if (k < rank && col_ok) out[(int64_t)k * B + j] = acc[k];
+    return;
+  }
+  // sum over the row groups in a fixed tree order
+#pragma unroll
+  for (int k = 0; k < RMAX; k++) {
+    if (k < rank) {
+      __syncthreads();
+      sV[tid] = acc[k];
+      __syncthreads();
+      for (int off = NR / 2; off > 0; off >>= 1) {
+        if (rg < off) sV[tid] += sV[tid + off * JW];
+        __syncthreads();
+      }
+      if (rg == 0 && col_ok) out[(int64_t)k * B + j] = sV[tid];
+    }
+  }
+}
+
+// DW[v] = D[v / B] * sum over chunks c of partials[c * nv + v], nv = rank * B:
+// 64 values per workgroup, its four waves taking every fourth chunk, combined
+// in a fixed order (deterministic).
+__global__ __launch_bounds__(WG) void k_vt_reduce(const double* partials, int nchunk, int64_t nv, int B,
+                                                  const double* Dg, double* DW, const int* n_active) {
+  if (n_active && *n_active == 0) return;
+  __shared__ double sh[WG];
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int64_t v = (int64_t)blockIdx.x * 64 + lane;
+  double s0 = 0.0, s1 = 0.0;
+  if (v < nv) {
+    int c = wv;
+    for (; c + 4 < nchunk; c += 8) {
+      s0 += partials[(int64_t)c * nv + v];
+      s1 += partials[(int64_t)(c + 4) * nv + v];
+    }
+    for (; c < nchunk; c += 4) s0 += partials[(int64_t)c * nv + v];
+  }
+  sh[tid] = s0 + s1;
+  __syncthreads();
+  if (wv == 0 && v < nv) DW[v] = Dg[v / B] * ((sh[lane] + sh[64 + lane]) + (sh[128 + lane] + sh[192 + lane]));
+}
+
+// z = base + V DW (base = r, or the z already stored when L = chol), then
+// the per-column <r, z> partials[blockIdx.x * B + j] over the chunk's rows.
+template <typename T, typename TV, int RMAX>
+__global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank, int JW, const TV* V,
+                                                     const double* DW, const T* r, T* z, int z_has_base,
+                                                     int64_t rpc, const int* n_active, double* partials) {
+  if (n_active && *n_active == 0) return;
+  constexpr int LD = RMAX + 2;
+  __shared__ double sV[kVRows * LD];
+  const int tid = threadIdx.x, jl = tid % JW, rg = tid / JW, NR = WG / JW;
+  const int j = blockIdx.y * JW + jl;
+  const bool col_ok = j < B;
+  const int64_t r0 = (int64_t)blockIdx.x * rpc, r1 = min<int64_t>(m, r0 + rpc);
+  double dw[RMAX];
+#pragma unroll
+  for (int k = 0; k < RMAX; k++) dw[k] = (col_ok && k < rank) ? DW[(int64_t)k * B + j] : 0.0;
+  double dacc = 0.0;
+  for (int64_t b0 = r0; b0 < r1; b0 += kVRows) {
+    const int nb = (int)min<int64_t>(kVRows, r1 - b0);
+    __syncthreads();
+    stage_v<TV, RMAX>(sV, V, m, rank, b0, nb);
+    __syncthreads();
+    if (col_ok) {
+      for (int ii = rg; ii < nb; ii += NR) {
+        const int64_t o = (b0 + ii) * B + j;
+        const double rv = (double)r[o];
+        double sum = z_has_base ? (double)z[o] : rv;
+        const double* vr = sV + ii * LD;
+#pragma unroll
+        for (int k = 0; k < RMAX; k++) sum += vr[k] * dw[k];
+        const T zv = (T)sum;
+        z[o] = zv;
+        dacc += rv * (double)zv;
+      }
+    }
+  }
+  __syncthreads();
+  sV[tid] = dacc;
+  __syncthreads();
+  for (int off = NR / 2; off > 0; off >>= 1) {
+    if (rg < off) sV[tid] += sV[tid + off * JW];
+    __syncthreads();
+  }
+  if (rg == 0 && col_ok) partials[(int64_t)blockIdx.x * B + j] = sV[tid];
+}
+
 // ------------------------------------------- low-rank GEMMs on MFMA (bf16)
 // FP32 panels, BF16 V: v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  The
 // FP32 panel operand is split into bf16 hi + lo parts (two MFMAs), so the
@@ -964,6 +1174,41 @@ struct ProfEvents {
   }
 };
 
+// ================================================================== tuning
+// Launch shapes (overridable from the environment for tuning sweeps).  Every
+// partials buffer is sized from these limits.
+struct Tuning {
+  int ts1;          // lanes per row of the one-column SpMM (4, 8, 16, 32)
+  int spmm_nwg;     // max short-row workgroups of the SpMM
+  int rows_team;    // target rows per team of the SpMM
+  int ew_nwg;       // max workgroups of the row-parallel reduction kernels
+  int ew_rows;      // target rows per workgroup of those kernels
+  int xcd;          // XCD-slab chunk order for the gathering kernels
+  int graphs;       // replay captured iteration chunks as HIP graphs
+  int fuse;         // one-column residual update fused with V^T r
+};
+static int env_int(const char* name, int dflt, int lo, int hi) {
+  const char* e = getenv(name);
+  int v = e ? atoi(e) : dflt;
+  return (v >= lo && v <= hi) ? v : dflt;
+}
+static const Tuning& tuning() {
+  static const Tuning t = [] {
+    Tuning u;
+    u.ts1 = env_int("KATZ_SPMM_TS1", 8, 4, 32);
+    if (u.ts1 != 4 && u.ts1 != 8 && u.ts1 != 16 && u.ts1 != 32) u.ts1 = 8;
+    u.spmm_nwg = env_int("KATZ_SPMM_NWG", 8192, 64, 65536);
+    u.rows_team = env_int("KATZ_SPMM_ROWS_PER_TEAM", 1, 1, 64);
+    u.ew_nwg = env_int("KATZ_EW_NWG", 1024, 64, 65536);
+    u.ew_rows = env_int("KATZ_EW_ROWS", 256, 16, 65536);
+    u.xcd = env_int("KATZ_XCD_SLAB", 0, 0, 1);
+    u.graphs = env_int("KATZ_GRAPHS", 1, 0, 1);
+    u.fuse = env_int("KATZ_FUSE", 0, 0, 1);
+    return u;
+  }();
+  return t;
+}
+
 // ============================================================= device index
 struct Workspace {
   int B = 0;  // capacity in columns (a call may use any width <= B)
@@ -1239,41 +1484,6 @@ template <> struct Factors<float> {
 constexpr size_t kPinFlagOff = 16384;  // pinned staging offset of the poll flag
 constexpr size_t kPinProfOff = 28672;  // active-column count read for profiling
 
-// ================================================================== tuning
-// Launch shapes (overridable from the environment for tuning sweeps).  Every
-// partials buffer is sized from these limits.
-struct Tuning {
-  int ts1;          // lanes per row of the one-column SpMM (4, 8, 16, 32)
-  int spmm_nwg;     // max short-row workgroups of the SpMM
-  int rows_team;    // target rows per team of the SpMM
-  int ew_nwg;       // max workgroups of the row-parallel reduction kernels
-  int ew_rows;      // target rows per workgroup of those kernels
-  int xcd;          // XCD-slab chunk order for the gathering kernels
-  int graphs;       // replay captured iteration chunks as HIP graphs
-  int fuse;         // one-column residual update fused with V^T r
-};
-static int env_int(const char* name, int dflt, int lo, int hi) {
-  const char* e = getenv(name);
-  int v = e ? atoi(e) : dflt;
-  return (v >= lo && v <= hi) ? v : dflt;
-}
-static const Tuning& tuning() {
-  static const Tuning t = [] {
-    Tuning u;
-    u.ts1 = env_int("KATZ_SPMM_TS1", 8, 4, 32);
-    if (u.ts1 != 4 && u.ts1 != 8 && u.ts1 != 16 && u.ts1 != 32) u.ts1 = 8;
-    u.spmm_nwg = env_int("KATZ_SPMM_NWG", 8192, 64, 65536);
-    u.rows_team = env_int("KATZ_SPMM_ROWS_PER_TEAM", 1, 1, 64);
-    u.ew_nwg = env_int("KATZ_EW_NWG", 1024, 64, 65536);
-    u.ew_rows = env_int("KATZ_EW_ROWS", 256, 16, 65536);
-    u.xcd = env_int("KATZ_XCD_SLAB", 0, 0, 1);
-    u.graphs = env_int("KATZ_GRAPHS", 1, 0, 1);
-    u.fuse = env_int("KATZ_FUSE", 0, 0, 1);
-    return u;
-  }();
-  return t;
-}
-
 // ================================================================ workspace
 // Element size of the inner-solve panels: FP32 for the precision form.
 static int64_t solve_elem_bytes(const DeviceIndex* D) { return D->precision == KATZ_PREC_MIXED ? 4 : 8; }
@@ -1471,14 +1681,20 @@ struct Launcher {
     int panels = 1 + (a.v ? 1 : 0) + (a.w ? 1 : 0) + ((a.dotv && a.dotv != a.v) ? 1 : 0);
     double bytes = 8.0 * rows + 4.0 + (4.0 + (a.val ? 8.0 : 0.0)) * nnz_sel + wb * cols_sel + wb * rows * panels;
     const int kind = sep ? (a.parts == 1 ? PK_SPMM_RHS : PK_SPMM_SEP) : PK_SPMM_FULL;
-    bool launched = false;
+    auto launch = [&](const SpmmArgs<T>& aa, double by) {
+      bool launched = false;
 #define KZ_SPMM(ts, cw)                                                                    \
   if (!launched && TS == ts && CW == cw) {                                                 \
-    timed(kind, bytes, [&] { k_spmm<T, ts, cw><<<g, WG, shm, st>>>(a); });                 \
+    timed(kind, by, [&] {                                                                  \
+      if (aa.val) k_spmm<T, ts, cw, true><<<g, WG, shm, st>>>(aa);                         \
+      else k_spmm<T, ts, cw, false><<<g, WG, shm, st>>>(aa);                               \
+    });                                                                                    \
     launched = true;                                                                       \
   }
-    KZ_SPMM(4, 1) KZ_SPMM(8, 1) KZ_SPMM(16, 1) KZ_SPMM(32, 1) KZ_SPMM(8, 2) KZ_SPMM(16, 4) KZ_SPMM(32, 8) KZ_SPMM(64, 16) KZ_SPMM(64, 32) KZ_SPMM(64, 64)
+      KZ_SPMM(4, 1) KZ_SPMM(8, 1) KZ_SPMM(16, 1) KZ_SPMM(32, 1) KZ_SPMM(8, 2) KZ_SPMM(16, 4) KZ_SPMM(32, 8) KZ_SPMM(64, 16) KZ_SPMM(64, 32) KZ_SPMM(64, 64)
 #undef KZ_SPMM
+    };
+    launch(a, bytes);
     if (a.ep != EP_NONE) finalize(nwg_all, B, a.ep, a.cs, a.out, a.n_active);
   }
 
@@ -1592,6 +1808,53 @@ static void with_lowrank_factor(const DeviceIndex* D, F&& f) {
 
 // Rank-r preconditioner with the row-parallel kernels (any B, V of type TV):
 // DW = D o (V^T r), then z = G r + V DW (G = M22^{-1} or I) with <r, z>.
+// Preconditioner for B >= 2 columns and rank <= 64 with the row-blocked
+// kernels: DW = D o (V^T r) (chunk partials, then a many-workgroup fixed-order
+// reduction), then z = base + V DW with the <r, z> partials and finalize.
+template <typename T, typename TV>
+static void precond_rows(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, const ColState& cs,
+                         const int* nact) {
+  DeviceIndex* D = L.D;
+  Workspace* w = L.w;
+  const int B = L.B, rk = D->rank;
+  const int64_t m = D->n2;
+  hipStream_t st = L.st;
+  int JW = 1;
+  while (JW < B && JW < WG) JW <<= 1;
+  const int njt = (B + JW - 1) / JW;
+  const int64_t rpc = std::max<int64_t>(kVRows, (m + 1023) / 1024);
+  const int nchunk = (int)((m + rpc - 1) / rpc);
+  const int64_t nv = (int64_t)rk * B;
+  dim3 g((unsigned)nchunk, (unsigned)njt);
+  L.need(nchunk, nv);
+  L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
+    if (rk <= 8) k_vt_rows<T, TV, 8><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
+    else if (rk <= 16) k_vt_rows<T, TV, 16><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
+    else if (rk <= 32) k_vt_rows<T, TV, 32><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
+    else k_vt_rows<T, TV, 64><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
+  });
+  k_vt_reduce<<<(unsigned)((nv + 63) / 64), WG, 0, st>>>(w->partials, nchunk, nv, B, D->D, w->DW, nact);
+  int has_base = 0;
+  if (Factors<T>::ginv(D)) {
+    L.timed(PK_OTHER, (double)sizeof(T) * (m * m + 2 * m * B), [&] {
+      k_dense_apply<T><<<grid_for(m * B, WG), WG, 0, st>>>((int)m, B, Factors<T>::ginv(D), R2, Z2, nact);
+    });
+    has_base = 1;
+  }
+  L.need(nchunk, B);
+  L.timed(PK_LOWRANK, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m * (2 + has_base), [&] {
+    if (rk <= 8)
+      k_lowrank_rows<T, TV, 8><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials);
+    else if (rk <= 16)
+      k_lowrank_rows<T, TV, 16><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials);
+    else if (rk <= 32)
+      k_lowrank_rows<T, TV, 32><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials);
+    else
+      k_lowrank_rows<T, TV, 64><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials);
+  });
+  L.finalize(nchunk, B, ep, cs, nullptr, nact);
+}
+
 template <typename T, typename TV>
 static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, const ColState& cs,
                            const int* nact, int rpw, int nwg, bool dw_ready = false) {
@@ -1600,6 +1863,10 @@ static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep,
   const int B = L.B, rk = D->rank;
   const int64_t m = D->n2;
   hipStream_t st = L.st;
+  if (B >= 2 && rk > 0 && rk <= 64) {
+    precond_rows<T, TV>(L, V, R2, Z2, ep, cs, nact);
+    return;
+  }
   if (rk > 0 && !dw_ready) {
     L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
       if (B == 1 && rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
