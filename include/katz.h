@@ -71,7 +71,7 @@ enum katz_l_kind {
 enum katz_method { KATZ_METHOD_LRC = 0, KATZ_METHOD_CG = 1 };
 
 enum katz_order {
-  KATZ_ORDER_AUTO = 0,     /* DEGREE */
+  KATZ_ORDER_AUTO = 0,     /* LOCALITY */
   KATZ_ORDER_DEGREE = 1,   /* blocks largest first; separator by degree (hubs first) */
   KATZ_ORDER_LOCALITY = 2  /* blocks and separator in BFS visit order */
 };

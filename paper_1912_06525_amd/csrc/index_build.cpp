@@ -716,7 +716,7 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
   int32_t max_block = o.max_block > 0 ? o.max_block : 64;
   int32_t order_kind = o.order;
   if (const char* e = getenv("KATZ_ORDER")) order_kind = atoi(e);
-  if (order_kind == KATZ_ORDER_AUTO) order_kind = KATZ_ORDER_DEGREE;
+  if (order_kind == KATZ_ORDER_AUTO) order_kind = KATZ_ORDER_LOCALITY;
   Partition P = make_partition(n, row_ptr, col, o.labels, max_block, order_kind);
   H.perm = std::move(P.perm);
   H.iperm = std::move(P.iperm);

@@ -589,6 +589,69 @@ __global__ __launch_bounds__(WG) void k_m11_apply(M11Args<T> a) {
   }
 }
 
+// Block solve for B >= 16 columns.  Workgroup (tile, column chunk) with CBW
+// lanes per row (64 / CBW rows per wave, coalesced panel rows):
+//   phase 1: u[i][:] = ca (A12 x2)[i][:] + cv v[i][:] for the tile's rows
+//            into LDS (4 entries of the A12 gather in flight per lane);
+//   phase 2: out[i][:] = sum_k Minv_b[li][k] u[bs + k][:] with row li of the
+//            block inverse (stored symmetric, so its row is contiguous).
+template <typename T, int CBW, bool VAL>
+__global__ __launch_bounds__(WG) void k_m11_cols(M11Args<T> a) {
+  if (a.n_active && *a.n_active == 0) return;
+  extern __shared__ unsigned char smem[];
+  T* u = reinterpret_cast<T*>(smem);  // tile rows x CBW
+  constexpr int RPG = WG / CBW;       // rows in flight per workgroup
+  const int r0 = a.tile_row0[blockIdx.x], r1 = a.tile_row0[blockIdx.x + 1], R = r1 - r0;
+  const int B = a.B;
+  const int lane = threadIdx.x % CBW, rs = threadIdx.x / CBW;
+  const int j = blockIdx.y * CBW + lane;
+  const bool ok = j < B;
+  const int jc = ok ? j : B - 1;  // clamped: loads stay in bounds, results unused
+  for (int i = rs; i < R; i += RPG) {
+    const int gi = r0 + i;
+    T s = (T)0;
+    if (a.x2) {
+      const int32_t kb = a.split[gi], ke = a.rp[gi + 1];
+      for (int32_t k = kb; k < ke; k += 4) {
+        int32_t c[4];
+        T f[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const int32_t kk = k + q < ke ? k + q : ke - 1;
+          c[q] = a.col[kk];
+          f[q] = k + q < ke ? (VAL ? (T)a.val[kk] : (T)1) : (T)0;
+        }
+        T xv[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) xv[q] = a.x2[(int64_t)(c[q] - a.n1) * B + jc];
+#pragma unroll
+        for (int q = 0; q < 4; q++) s += (k + q < ke) ? f[q] * xv[q] : (T)0;
+      }
+    }
+    s *= a.ca;
+    if (a.v) s += a.cv * a.v[(int64_t)gi * B + jc];
+    u[i * CBW + lane] = s;
+  }
+  __syncthreads();
+  for (int i = rs; i < R; i += RPG) {
+    const int gi = r0 + i;
+    const int blk = a.row_blk[gi];
+    const int bs = a.blk_start[blk], bsz = a.blk_start[blk + 1] - bs, li = gi - bs;
+    const T* mi = a.minv + a.blk_off[blk] + (int64_t)li * bsz;
+    const T* ub = u + (bs - r0) * CBW + lane;
+    T s0 = (T)0, s1 = (T)0, s2 = (T)0, s3 = (T)0;
+    int k = 0;
+    for (; k + 3 < bsz; k += 4) {
+      s0 += mi[k] * ub[k * CBW];
+      s1 += mi[k + 1] * ub[(k + 1) * CBW];
+      s2 += mi[k + 2] * ub[(k + 2) * CBW];
+      s3 += mi[k + 3] * ub[(k + 3) * CBW];
+    }
+    for (; k < bsz; k++) s0 += mi[k] * ub[k * CBW];
+    if (ok) a.out[(int64_t)gi * B + j] = (s0 + s1) + (s2 + s3);
+  }
+}
+
 // z = G r with the dense symmetric G = M22^{-1} (L = chol(M22)).
 template <typename T>
 __global__ __launch_bounds__(WG) void k_dense_apply(int m, int B, const T* g, const T* r, T* z,
@@ -1945,7 +2008,25 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     const double wb = (double)sizeof(T) * B;
     double bytes = (double)sizeof(T) * D->minv_elems + 4.0 * n1 + wb * n1 + (v ? wb * n1 : 0.0) +
                    (x2 ? 8.0 * n1 + 4.0 * D->nnz_a12 + wb * D->cols_a12 : 0.0);
-    L.timed(PK_M11, bytes, [&] { k_m11_apply<T><<<D->ntiles, WG, shm, st>>>(a); });
+    if (B >= 16) {
+      // column-chunked kernel: 64 KB of LDS per workgroup at most
+      const int cbw = sizeof(T) == 8 ? (B <= 16 ? 16 : 32) : (B <= 16 ? 16 : (B <= 32 ? 32 : 64));
+      const size_t shm2 = (size_t)D->max_tile_rows * cbw * sizeof(T);
+      if (shm2 > 65536) fail(KATZ_EDEVICE, "internal: block tile too large for LDS");
+      dim3 g((unsigned)D->ntiles, (unsigned)((B + cbw - 1) / cbw));
+      L.timed(PK_M11, bytes, [&] {
+        const bool wv = a.val != nullptr;
+        if (cbw == 16) {
+          if (wv) k_m11_cols<T, 16, true><<<g, WG, shm2, st>>>(a); else k_m11_cols<T, 16, false><<<g, WG, shm2, st>>>(a);
+        } else if (cbw == 32) {
+          if (wv) k_m11_cols<T, 32, true><<<g, WG, shm2, st>>>(a); else k_m11_cols<T, 32, false><<<g, WG, shm2, st>>>(a);
+        } else {
+          if (wv) k_m11_cols<T, 64, true><<<g, WG, shm2, st>>>(a); else k_m11_cols<T, 64, false><<<g, WG, shm2, st>>>(a);
+        }
+      });
+    } else {
+      L.timed(PK_M11, bytes, [&] { k_m11_apply<T><<<D->ntiles, WG, shm, st>>>(a); });
+    }
   };
   // z2 = G r2 + V (D o (V^T r2)), then <r2, z2> (EP_RZ_INIT / EP_RZ)
   auto precond = [&](int ep) {
