@@ -299,3 +299,22 @@ def test_pins_catch_planted_mistakes(monkeypatch):
         got = series_only()
         assert not np.allclose(got, exp, rtol=1e-6), name
     monkeypatch.setattr(ko, "katz_rhs", orig_rhs)
+
+
+# ------------------------------------------------ residual (P8 support)
+@pytest.mark.parametrize("n,beta", [(6, 0.1), (9, 0.05)])
+def test_residual_closed_forms_complete_graph(n, beta):
+    """||b - (I - beta A) k|| / ||b|| on K_n, q = 0, b = beta A e_q (eq.
+    LinearSystem), for three k with hand-derived values: k = 0 gives 1;
+    k = b gives ||beta A b|| / ||b|| with A b = (n-2) on v != q and (n-1) at
+    q; the closed-form Katz vector gives 0 (to rounding)."""
+    nn, rp, col = complete(n)
+    A = ko.csr_matrix(nn, rp, col)
+    b = ko.katz_rhs(A, beta, [0])
+    assert ko.katz_residual(A, beta, [0], np.zeros((n, 1)))[0] == pytest.approx(1.0, abs=1e-15)
+    want = beta * math.sqrt((n - 1) * (n - 2) ** 2 + (n - 1) ** 2) / math.sqrt(n - 1)
+    assert ko.katz_residual(A, beta, [0], b)[0] == pytest.approx(want, rel=1e-14)
+    d = (1 + beta) * (1 - (n - 1) * beta)
+    k = np.full((n, 1), beta / d)
+    k[0, 0] = (n - 1) * beta ** 2 / d
+    assert ko.katz_residual(A, beta, [0], k)[0] < 1e-14
