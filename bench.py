@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--workload", type=str, default="cl1m",
                     help="cl1m (default, one query per solve), lnsbm4m (256 FP64 RHS), cl8m (512 mixed RHS)")
     ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
+    ap.add_argument("--host-output", action="store_true",
+                    help="one-query workload: deliver scores to pinned host memory (PCIe-inclusive rate; "
+                         "the result line then says so in config.output)")
     ap.add_argument("--u-precision", type=int, default=0, help="low-rank factor storage (0 auto, 1 FP64, 2 FP32, 3 BF16)")
     ap.add_argument("--serve", action="store_true", help="serving mode on --workload (default dcsbm16m)")
     ap.add_argument("--requests", type=int, default=200, help="requests per offered-load point (serving)")
@@ -114,7 +117,11 @@ def main():
     results = {}
     roofline = None
     kernel_table = None
-    out = torch.empty((1, g.n), dtype=torch.float64, device=dev)
+    if args.host_output:
+        # scores delivered to pinned host memory: the PCIe-inclusive rate
+        out = torch.empty((1, g.n), dtype=torch.float64, pin_memory=True)
+    else:
+        out = torch.empty((1, g.n), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
 
     def run(idx, method, steps, offset, check_every=0):
@@ -213,7 +220,8 @@ def main():
         "config": {"workload": "Chung-Lu power-law graph, %d nodes, exponent 2.5, mean degree 20, "
                                "c = beta*lambda_max = %g, rank %d, FP64, 1 query per solve"
                                % (g.n, head_c, args.rank),
-                   "n": g.n, "nnz": g.nnz, "c": head_c, "rank": args.rank, "batch": 1, "tol": tol},
+                   "n": g.n, "nnz": g.nnz, "c": head_c, "rank": args.rank, "batch": 1, "tol": tol,
+                   "output": "pinned host memory (PCIe-inclusive)" if args.host_output else "device memory"},
         "p99_ms": round(head["lrc"]["p99_ms"], 4),
         "p50_ms": round(head["lrc"]["p50_ms"], 4),
         "cg_qps": round(head["cg"]["qps"], 2),
@@ -415,8 +423,10 @@ def cpu_baseline(g, idx, queries, tol, out, stream, K):
     import oracle
     info = idx.info
     sample = [int(q) for q in queries[:4]]
+    # the oracle's own lambda_max (outside the timed region) and the same c
+    lam = oracle.lambda_max(oracle.csr_matrix(g.n, g.row_ptr, g.col))
     t = time.perf_counter()
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, sample, beta=info.beta, lam=info.lambda_max, validate=False)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, sample, c=info.c, lam=lam, validate=False)
     el = time.perf_counter() - t
     errs = []
     for j, q in enumerate(sample):

@@ -8,6 +8,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+def oracle_beta(g, c):
+    """beta = c / lambda_max(A) with the oracle's own lambda_max: tests pick
+    beta on their side and hand the same value to the index build and to the
+    oracle, so no oracle input comes from the library."""
+    import oracle
+    return c / oracle.lambda_max(oracle.csr_matrix(g.n, g.row_ptr, g.col))
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: large workload, minutes of host time")

@@ -9,17 +9,18 @@ import pytest
 
 import katz_inputs as ki
 import oracle
+from conftest import oracle_beta
 
 pytestmark = pytest.mark.gpu
 K = pytest.importorskip("paper_1912_06525_amd")
 
 
-def _run(g, idx, qs, tau, method=K.KATZ_METHOD_LRC):
+def _run(g, idx, beta, qs, tau, method=K.KATZ_METHOD_LRC):
+    # beta: the test's own value, given to the index build and to the oracle
     c = idx.info.c
     tol = tau * (1 - c) / (1 + c)
     sc, st = idx.query(qs, tol=tol, method=method)
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=idx.info.beta, lam=idx.info.lambda_max,
-                             validate=False)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta, validate=False)
     for j in range(len(qs)):
         k = ref["k"][:, j]
         assert st[j]["status"] == 0 and st[j]["rel_residual"] <= tol, st[j]
@@ -32,18 +33,20 @@ def _run(g, idx, qs, tau, method=K.KATZ_METHOD_LRC):
 @pytest.mark.parametrize("method", [K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG])
 def test_mixed_small_sbm(c, method):
     g = ki.workload("lnsbm4m", scale=0.002).graph
-    idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=16, labels=g.labels, max_block=32,
+    beta = oracle_beta(g, c)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=16, labels=g.labels, max_block=32,
                                  precision=K.KATZ_PREC_MIXED)
     qs = ki.sample_queries(g, 6, 71)
-    st = _run(g, idx, qs, 1e-6, method)
+    st = _run(g, idx, beta, qs, 1e-6, method)
     assert all(s["sweeps"] >= 2 for s in st)          # FP32 inner solve, FP64 refinement
 
 
 def test_mixed_chung_lu_batch():
     g = ki.chung_lu(30000, 2.3, 12.0, seed=1004)
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.9, rank=32, precision=K.KATZ_PREC_MIXED)
+    beta = oracle_beta(g, 0.9)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=32, precision=K.KATZ_PREC_MIXED)
     qs = ki.sample_queries(g, 20, 5)
-    _run(g, idx, qs, 1e-6)
+    _run(g, idx, beta, qs, 1e-6)
 
 
 def test_mixed_matches_fp64_path():
@@ -61,12 +64,13 @@ def test_mixed_matches_fp64_path():
 def test_mixed_batched_mfma_preconditioner(B, rank):
     # B >= 16 FP32 panels take the bf16 MFMA low-rank kernels (ragged B and rank)
     g = ki.chung_lu(20000, 2.3, 12.0, seed=11)
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.9, rank=rank, precision=K.KATZ_PREC_MIXED)
+    beta = oracle_beta(g, 0.9)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=rank, precision=K.KATZ_PREC_MIXED)
     qs = ki.sample_queries(g, B, 3)
-    st = _run(g, idx, qs, 1e-6)
+    st = _run(g, idx, beta, qs, 1e-6)
     # same queries one at a time (scalar kernels) agree within the tolerance
     one, _ = idx.query(qs[:2], tol=1e-8)
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs[:2], beta=idx.info.beta)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs[:2], beta=beta)
     for j in range(2):
         assert np.linalg.norm(one[j] - ref["k"][:, j]) <= 1e-6 * np.linalg.norm(ref["k"][:, j])
 

@@ -7,8 +7,11 @@ Sec. 3.1).  Tests request rho = tau (1 - c) / (1 + c) so that the error is
 below tau (norm-wise and entrywise against ||k||), with tau = 1e-6 for the
 FP64 path and 1e-9 for the small 2,000-node SBM solved to 1e-10 residual.
 """
+import math
+
 import numpy as np
 import pytest
+from conftest import oracle_beta
 
 import katz_inputs as ki
 import oracle
@@ -25,14 +28,14 @@ def _accept(kh, k, tau, what=""):
     assert np.max(np.abs(kh - k)) <= tau * max(nk, 1e-300), what
 
 
-def _check(g, idx, qs, tau, method=K.KATZ_METHOD_LRC, **kw):
+def _check(g, idx, beta, qs, tau, method=K.KATZ_METHOD_LRC, **kw):
+    # beta: the test's own value, given to the index build and to the oracle
     c = idx.info.c
     tol = tau * (1 - c) / (1 + c)
     sc, st = idx.query(qs, tol=tol, method=method, **kw)
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=idx.info.beta, lam=idx.info.lambda_max,
-                             validate=False)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta, validate=False)
     A = oracle.csr_matrix(g.n, g.row_ptr, g.col)
-    res = oracle.katz_residual(A, idx.info.beta, qs, sc.T)
+    res = oracle.katz_residual(A, beta, qs, sc.T)
     for j, q in enumerate(qs):
         assert st[j]["status"] == 0, st[j]
         _accept(sc[j], ref["k"][:, j], tau, "q=%d" % q)
@@ -51,9 +54,10 @@ def sbm2k():
 @pytest.mark.parametrize("rank,uprec", [(0, 0), (5, 1), (32, 2), (32, 3)])
 def test_sbm2k_fp64_1e10(sbm2k, method, rank, uprec):
     g = sbm2k.graph
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=rank, labels=g.labels, max_block=200, u_precision=uprec)
+    beta = oracle_beta(g, 0.5)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=rank, labels=g.labels, max_block=200, u_precision=uprec)
     sc, st = idx.query(sbm2k.queries, tol=1e-10, method=method)
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, sbm2k.queries, beta=idx.info.beta)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, sbm2k.queries, beta=beta)
     assert st[0]["status"] == 0 and st[0]["rel_residual"] <= 1e-10
     _accept(sc[0], ref["k_direct"][:, 0], 3.1e-10, "sbm2k")
     assert st[0]["path"] == (K.KATZ_PATH_CG if method == K.KATZ_METHOD_CG else K.KATZ_PATH_LRC)
@@ -62,12 +66,13 @@ def test_sbm2k_fp64_1e10(sbm2k, method, rank, uprec):
 def test_full_rank_converges_in_one_iteration(sbm2k):
     # Theorem 1 with r = n2 and exact eigenvectors: S S~^{-1} = I.
     g = ki.sbm([30, 30, 30], [0.3, 0.3, 0.3], 0.05, seed=8)
-    idx0 = K.KatzIndex.from_graph(g, beta_frac=0.8, rank=0, labels=g.labels, max_block=12, device=-1)
+    beta = oracle_beta(g, 0.8)
+    idx0 = K.KatzIndex.from_graph(g, beta=beta, rank=0, labels=g.labels, max_block=12, device=-1)
     n2 = idx0.info.n2
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.8, rank=n2, labels=g.labels, max_block=12,
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=n2, labels=g.labels, max_block=12,
                                  l_kind=K.KATZ_L_CHOL, lanczos_steps=10 ** 6, u_precision=1)
     qs = ki.sample_queries(g, 3, 4)
-    sc, st = _check(g, idx, qs, 1e-9)
+    sc, st = _check(g, idx, beta, qs, 1e-9)
     assert all(s["iters"] <= 2 for s in st), st
 
 
@@ -77,9 +82,10 @@ def test_full_rank_converges_in_one_iteration(sbm2k):
 def test_small_sbm_both_factors(lk, c, order):
     # dense chol(M22) is for small separators: a smaller graph for CHOL
     g = ki.workload("lnsbm4m", scale=0.0006 if lk == K.KATZ_L_CHOL else 0.002).graph
-    idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=16, labels=g.labels, max_block=32, l_kind=lk, order=order)
+    beta = oracle_beta(g, c)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=16, labels=g.labels, max_block=32, l_kind=lk, order=order)
     qs = ki.sample_queries(g, 5, 31)
-    _check(g, idx, qs, 1e-6)
+    _check(g, idx, beta, qs, 1e-6)
 
 
 def test_closed_forms_through_gpu():
@@ -87,8 +93,8 @@ def test_closed_forms_through_gpu():
     # star with m leaves: K_c,leaf = beta/d, K_leaf,leaf' = beta^2/d, d = 1 - m beta^2
     m = 40
     g = ki.from_edges(m + 1, [(0, i) for i in range(1, m + 1)])
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.9, rank=1)
-    beta = idx.info.beta
+    beta = 0.9 / math.sqrt(m)  # lambda_max of the star is sqrt(m)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=1)
     d = 1 - m * beta ** 2
     sc, st = idx.query([0, 5], tol=1e-12)
     exp0 = np.full(m + 1, beta / d)
@@ -101,8 +107,8 @@ def test_closed_forms_through_gpu():
     # complete graph K_n: K_pq = beta / ((1+beta)(1-(n-1)beta))
     n = 30
     g = ki.from_edges(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.7, rank=2, max_block=8)
-    beta = idx.info.beta
+    beta = 0.7 / (n - 1)  # lambda_max of K_n is n - 1
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=2, max_block=8)
     den = (1 + beta) * (1 - (n - 1) * beta)
     sc, _ = idx.query([3], tol=1e-12)
     exp = np.full(n, beta / den)
@@ -111,8 +117,8 @@ def test_closed_forms_through_gpu():
     # cycle C_n
     n, q = 101, 7
     g = ki.from_edges(n, [(i, (i + 1) % n) for i in range(n)])
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.8, rank=4, max_block=10)
-    beta = idx.info.beta
+    beta = 0.8 / 2  # lambda_max of a cycle is 2
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=4, max_block=10)
     s = math.sqrt(1 - 4 * beta ** 2)
     t = (1 - s) / (2 * beta)
     sc, _ = idx.query([q], tol=1e-12)
@@ -149,14 +155,15 @@ def test_batch_columns_match_single_solves():
 
 def test_forced_fallback_to_cg():
     g = ki.workload("lnsbm4m", scale=0.002).graph
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.9, rank=4, labels=g.labels, max_block=32)
+    beta = oracle_beta(g, 0.9)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=4, labels=g.labels, max_block=32)
     qs = ki.sample_queries(g, 3, 5)
     # fault injection from the host: the first (LRC) sweep is declared broken
     # down, the refinement sweeps then run plain CG on the residual
     sc, st = idx.query(qs, tol=1e-8, force_fallback=True)
     assert all(s["path"] == K.KATZ_PATH_CG_FALLBACK for s in st)
     assert all(s["sweeps"] >= 1 and s["status"] == 0 for s in st)
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=idx.info.beta)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta)
     for j in range(len(qs)):
         _accept(sc[j], ref["k"][:, j], 1e-8 * 19 * 1.05, "fallback")
     # an iteration cap on every path ends in KATZ_ENOCONV with the best iterate
@@ -179,12 +186,13 @@ def test_device_output_buffer():
 @pytest.mark.parametrize("K_", [1, 10, 100])
 def test_topk_matches_oracle(K_):
     g = ki.workload("lnsbm4m", scale=0.003).graph
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=8, labels=g.labels, max_block=32)
+    beta = oracle_beta(g, 0.5)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=8, labels=g.labels, max_block=32)
     qs = ki.sample_queries(g, 4, 123)
     tau = 1e-9
-    tol = tau * (1 - idx.info.c) / (1 + idx.info.c)
+    tol = tau * (1 - 0.5) / (1 + 0.5)
     ids, scs, st = idx.topk(qs, K_, tol=tol)
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=idx.info.beta)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta)
     for j, q in enumerate(qs):
         k = ref["k"][:, j]
         oid, osc, sid, ssc = oracle.topk_links(g.n, g.row_ptr, g.col, k, q, K_)
@@ -199,9 +207,10 @@ def test_topk_ties_and_padding():
     # fewer candidates than k -> padding with (-1, NaN)
     m = 9
     g = ki.from_edges(m + 1, [(0, i) for i in range(1, m + 1)])
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=1)
+    beta = 0.5 / math.sqrt(m)  # lambda_max of the star is sqrt(m)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=1)
     ids, scs, _ = idx.topk([4], 12, tol=1e-12)
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, [4], beta=idx.info.beta)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, [4], beta=beta)
     k = ref["k"][:, 0]
     _, _, sid, ssc = oracle.topk_links(g.n, g.row_ptr, g.col, k, 4, 12)
     ok, msg, ntie = oracle.topk_accept(ids[0], sid, ssc, 12, 2e-10 * np.linalg.norm(k))

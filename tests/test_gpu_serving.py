@@ -10,6 +10,7 @@ import pytest
 
 import katz_inputs as ki
 import oracle
+from conftest import oracle_beta
 
 pytestmark = pytest.mark.gpu
 K = pytest.importorskip("paper_1912_06525_amd")
@@ -20,16 +21,17 @@ TAU = 1e-8
 @pytest.fixture(scope="module")
 def setup():
     g = ki.workload("dcsbm16m", scale=0.002).graph
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=16, labels=g.labels)
-    return g, idx
+    beta = oracle_beta(g, 0.5)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=16, labels=g.labels)
+    return g, idx, beta
 
 
 def _tol(idx):
     return TAU * (1 - idx.info.c) / (1 + idx.info.c)
 
 
-def _check_against_oracle(g, idx, qs, ids, k):
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=idx.info.beta, validate=False)
+def _check_against_oracle(g, beta, qs, ids, k):
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta, validate=False)
     for j, q in enumerate(qs):
         kv = ref["k"][:, j]
         _, _, sid, ssc = oracle.topk_links(g.n, g.row_ptr, g.col, kv, q, k)
@@ -38,14 +40,14 @@ def _check_against_oracle(g, idx, qs, ids, k):
 
 
 def test_server_alone_vs_mix(setup):
-    g, idx = setup
+    g, idx, beta = setup
     k = 20
     srv = K.KatzServer(idx, workers=3, max_batch=16, k=k, tol=_tol(idx))
     try:
         R = ki.sample_queries(g, 8, 77)
         t = srv.submit(R)
         ids_a, sc_a, st_a, _ = srv.poll(t)
-        _check_against_oracle(g, idx, R, ids_a, k)
+        _check_against_oracle(g, beta, R, ids_a, k)
         # a mix: several requests of mixed sizes submitted from two threads,
         # with R again in the middle
         rng = np.random.default_rng(5)
@@ -71,12 +73,12 @@ def test_server_alone_vs_mix(setup):
         # same request alone and in the mix: same ranking (tie rule), scores within tolerance
         for j in range(len(R)):
             assert np.all(np.abs(sc_a[j] - sc_b[j]) <= 2 * TAU * np.abs(sc_a[j]).max())
-        _check_against_oracle(g, idx, R, ids_b, k)
+        _check_against_oracle(g, beta, R, ids_b, k)
         for tk, r in tickets:
             ids, sc, st, lat = srv.poll(tk)
             assert ids.shape == (len(r), k) and lat > 0
             assert all(s["status"] == 0 for s in st)
-        _check_against_oracle(g, idx, others[3], srv_result(srv, others[3]), k)
+        _check_against_oracle(g, beta, others[3], srv_result(srv, others[3]), k)
     finally:
         srv.close()
 
@@ -87,7 +89,7 @@ def srv_result(srv, q):
 
 
 def test_server_splits_large_request(setup):
-    g, idx = setup
+    g, idx, beta = setup
     k = 10
     srv = K.KatzServer(idx, workers=2, max_batch=8, k=k, tol=_tol(idx))
     try:
@@ -95,7 +97,7 @@ def test_server_splits_large_request(setup):
         t = srv.submit(qs)
         ids, sc, st, _ = srv.poll(t)
         assert ids.shape == (29, k)
-        _check_against_oracle(g, idx, qs, ids, k)
+        _check_against_oracle(g, beta, qs, ids, k)
         info = srv.info()
         assert info["done_queries"] >= 29 and info["queued_queries"] == 0
     finally:
@@ -103,7 +105,7 @@ def test_server_splits_large_request(setup):
 
 
 def test_server_admission_by_hbm(setup):
-    g, idx = setup
+    g, idx, beta = setup
     srv = K.KatzServer(idx, workers=4, max_batch=512, k=5, hbm_fraction=0.8)
     try:
         info = srv.info()

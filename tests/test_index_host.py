@@ -12,6 +12,7 @@ import scipy.linalg as sl
 import katz_inputs as ki
 import oracle
 import paper_1912_06525_amd as K
+from conftest import oracle_beta
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -25,7 +26,7 @@ def test_header_symbols_exported():
     assert names == set(K.EXPORTED)
 
 
-def _dense_parts(g, idx):
+def _dense_parts(g, idx, beta):
     info = idx.info
     perm, bp = idx.partition()
     n, n1 = g.n, info.n1
@@ -33,7 +34,7 @@ def _dense_parts(g, idx):
     P = np.zeros((n, n))
     P[perm, np.arange(n)] = 1.0          # P @ x puts node v at position perm[v]
     Ap = P @ A @ P.T
-    M = np.eye(n) - info.beta * Ap
+    M = np.eye(n) - beta * Ap
     return M, Ap, perm, bp, n1
 
 
@@ -59,13 +60,14 @@ def test_partition_is_block_diagonal(labels):
 
 def test_lemma1_block_elimination_exact():
     g = ki.workload("sbm2k", scale=0.4).graph
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.7, rank=0, device=-1, labels=g.labels, max_block=64)
-    M, Ap, perm, bp, n1 = _dense_parts(g, idx)
+    beta = oracle_beta(g, 0.7)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=0, device=-1, labels=g.labels, max_block=64)
+    M, Ap, perm, bp, n1 = _dense_parts(g, idx, beta)
     qs = ki.sample_queries(g, 3, 17)
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=idx.info.beta)["k_direct"]
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta)["k_direct"]
     M11, M12, M22 = M[:n1, :n1], M[:n1, n1:], M[n1:, n1:]
     for i, q in enumerate(qs):
-        b = idx.info.beta * Ap[:, perm[q]]
+        b = beta * Ap[:, perm[q]]
         b1, b2 = b[:n1], b[n1:]
         S = M22 - M12.T @ np.linalg.solve(M11, M12)
         k2 = np.linalg.solve(S, b2 - M12.T @ np.linalg.solve(M11, b1))      # eq. (5)
@@ -78,23 +80,25 @@ def test_star_centre_is_the_separator():
     m = 7
     g = ki.from_edges(m + 1, [(0, i) for i in range(1, m + 1)])
     labels = np.arange(m + 1, dtype=np.int32)
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.6, rank=1, device=-1, labels=labels, l_kind=K.KATZ_L_CHOL)
+    beta = 0.6 / np.sqrt(m)  # lambda_max of the star is sqrt(m)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=1, device=-1, labels=labels, l_kind=K.KATZ_L_CHOL)
     info = idx.info
     assert info.n2 == 1 and info.n1 == m
     perm, _ = idx.partition()
     assert perm[0] == m                     # centre placed last
     # S = 1 - m beta^2 (scalar); with L = chol(M22) = 1, R = m beta^2
     U, s = idx.lowrank()
-    assert abs(s[0] - m * info.beta ** 2) < 1e-14
+    assert abs(s[0] - m * beta ** 2) < 1e-14
 
 
 @pytest.mark.parametrize("lkind", [K.KATZ_L_CHOL, K.KATZ_L_IDENTITY])
 def test_theorem1_spectrum(lkind):
     g = ki.sbm([12, 10, 14], [0.5, 0.5, 0.5], 0.08, seed=5)
     r = 3
-    idx = K.KatzIndex.from_graph(g, beta_frac=0.8, rank=r, device=-1, labels=g.labels, max_block=8,
+    beta = oracle_beta(g, 0.8)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=r, device=-1, labels=g.labels, max_block=8,
                                  l_kind=lkind, lanczos_steps=10 ** 6)
-    M, Ap, perm, bp, n1 = _dense_parts(g, idx)
+    M, Ap, perm, bp, n1 = _dense_parts(g, idx, beta)
     n2 = idx.info.n2
     assert n2 >= r + 2
     M11, M12, M22 = M[:n1, :n1], M[:n1, n1:], M[n1:, n1:]
