@@ -192,6 +192,27 @@ int katz_topk_links(const katz_index* idx, const int32_t* q, int32_t nq, int32_t
                     const katz_query_opts* opts, int32_t* ids, double* scores,
                     katz_query_stats* st, void* stream);
 
+/*
+ * Writes the index to a file, so that the offline part of the method
+ * (Sec. 3.2 steps 1-4, Algorithm 1) is done once and later processes only
+ * run queries (Algorithm 2).  The file holds the reordering, the permuted
+ * CSR, the M11 block inverses, the M22 factor and the low-rank factors, in
+ * this host's byte order.  path: a file name; an existing file is replaced.
+ * Errors: KATZ_EINVAL (null argument), KATZ_EIO (cannot open or write).
+ */
+int katz_index_save(const katz_index* idx, const char* path);
+
+/*
+ * Reads an index written by katz_index_save and, when device >= 0, copies
+ * it to that device (device < 0: host-only, for the inspection calls).  The
+ * file is validated in full before use (sizes, CSR structure, symmetry,
+ * permutation, block structure, factor shapes).  *out receives the index
+ * (free with katz_index_free).  Errors: KATZ_EINVAL (null argument, not an
+ * index file, other version or byte order, or failed validation), KATZ_EIO
+ * (cannot open, truncated), KATZ_ENOMEM, KATZ_EDEVICE.
+ */
+int katz_index_load(const char* path, int32_t device, katz_index** out);
+
 /* Frees host and device memory of the index.  NULL is a no-op. */
 void katz_index_free(katz_index* idx);
 

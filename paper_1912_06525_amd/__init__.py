@@ -32,7 +32,7 @@ _STATUS = {0: "KATZ_OK", -1: "KATZ_EINVAL", -2: "KATZ_ENOTSYM", -3: "KATZ_EDIVER
            -5: "KATZ_EDEVICE", -6: "KATZ_ENOCONV", -7: "KATZ_EBUSY", -8: "KATZ_EIO"}
 
 EXPORTED = ["katz_build_opts_default", "katz_query_opts_default", "katz_index_build", "katz_query",
-            "katz_topk_links", "katz_index_free", "katz_index_info", "katz_index_partition",
+            "katz_topk_links", "katz_index_save", "katz_index_load", "katz_index_free", "katz_index_info", "katz_index_partition",
             "katz_index_lowrank", "katz_profile_enable", "katz_profile_reset", "katz_profile_read",
             "katz_server_opts_default", "katz_server_create", "katz_server_submit", "katz_server_poll",
             "katz_server_info", "katz_server_destroy", "katz_last_error"]
@@ -112,6 +112,10 @@ def _load():
     lib.katz_topk_links.argtypes = [P, pi32, i32, i32, ctypes.POINTER(katz_query_opts), P, P,
                                     ctypes.POINTER(katz_query_stats), P]
     lib.katz_topk_links.restype = ctypes.c_int
+    lib.katz_index_save.argtypes = [P, ctypes.c_char_p]
+    lib.katz_index_save.restype = ctypes.c_int
+    lib.katz_index_load.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(P)]
+    lib.katz_index_load.restype = ctypes.c_int
     lib.katz_index_free.argtypes = [P]
     lib.katz_index_free.restype = None
     lib.katz_index_info.argtypes = [P, ctypes.POINTER(katz_index_info_t)]
@@ -222,6 +226,16 @@ def katz_topk_links(idx, q, k: int, opts: Optional[katz_query_opts], ids, scores
     return rc
 
 
+def katz_index_save(idx, path: str) -> None:
+    _check(_lib.katz_index_save(idx, os.fsencode(path)))
+
+
+def katz_index_load(path: str, device: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(_lib.katz_index_load(os.fsencode(path), int(device), ctypes.byref(h)))
+    return h
+
+
 def katz_index_free(idx) -> None:
     _lib.katz_index_free(idx)
 
@@ -292,6 +306,19 @@ class KatzIndex:
     @classmethod
     def from_graph(cls, g, **kw):
         return cls(g.n, g.row_ptr, g.col, **kw)
+
+    @classmethod
+    def load(cls, path: str, device: int = 0) -> "KatzIndex":
+        """An index written by save(), on `device` (< 0: host only)."""
+        self = cls.__new__(cls)
+        self._labels = None
+        self.h = katz_index_load(path, device)
+        self.info = katz_index_info(self.h)
+        self.n = int(self.info.n)
+        return self
+
+    def save(self, path: str) -> None:
+        katz_index_save(self.h, path)
 
     def close(self):
         h = getattr(self, "h", None)

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["index_build.cpp", "capi.cpp", "server.cpp", "solver.hip", "topk.hip"]
+SOURCES = ["index_build.cpp", "index_io.cpp", "capi.cpp", "server.cpp", "solver.hip", "topk.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INC, "-I" + CSRC, "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable", "-Wno-unused-but-set-variable"]

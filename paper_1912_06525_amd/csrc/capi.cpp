@@ -105,6 +105,32 @@ int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
   });
 }
 
+int katz_index_save(const katz_index* idx, const char* path) {
+  return guarded([&]() -> int {
+    if (!idx || !path) return set_error(KATZ_EINVAL, "null index or path");
+    katz::save_host_index(idx->host, path);
+    return KATZ_OK;
+  });
+}
+
+int katz_index_load(const char* path, int32_t device, katz_index** out) {
+  return guarded([&]() -> int {
+    if (!out || !path) return set_error(KATZ_EINVAL, "null path or output pointer");
+    *out = nullptr;
+    auto* idx = new katz_index();
+    try {
+      katz::load_host_index(path, idx->host);
+      idx->device = device;
+      if (device >= 0) idx->dev = katz::device_upload(idx->host, device);
+    } catch (...) {
+      delete idx;
+      throw;
+    }
+    *out = idx;
+    return KATZ_OK;
+  });
+}
+
 int katz_query(const katz_index* idx, const int32_t* q, int32_t nq, const katz_query_opts* opts,
                double* scores, katz_query_stats* st, void* stream) {
   return guarded([&]() -> int {

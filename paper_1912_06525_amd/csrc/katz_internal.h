@@ -56,6 +56,9 @@ struct HostIndex {
 
 void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
                       const double* val, const katz_build_opts& o, HostIndex& H);
+// Index files (index_io.cpp): a loaded index is fully validated.
+void save_host_index(const HostIndex& H, const char* path);
+void load_host_index(const char* path, HostIndex& H);
 
 // ------------------------------------------------------- device index
 struct DeviceIndex;            // defined in the HIP solver

@@ -217,3 +217,21 @@ def test_topk_ties_and_padding():
     assert ok, msg
     assert sorted(ids[0][:8].tolist()) == [1, 2, 3, 5, 6, 7, 8, 9] and ids[0][8:].tolist() == [-1] * 4
     assert np.isnan(scs[0][8:]).all() and ntie == 1
+
+
+def test_loaded_index_answers_identically(tmp_path):
+    # an index written by save() and loaded on the device gives the same bits
+    g = ki.workload("lnsbm4m", scale=0.002).graph
+    beta = oracle_beta(g, 0.7)
+    a = K.KatzIndex.from_graph(g, beta=beta, rank=8, labels=g.labels, max_block=32)
+    p = str(tmp_path / "idx.katz")
+    a.save(p)
+    b = K.KatzIndex.load(p, device=0)
+    qs = ki.sample_queries(g, 5, 77)
+    sa, sta = a.query(qs, tol=1e-9)
+    sb, stb = b.query(qs, tol=1e-9)
+    assert np.array_equal(sa, sb)
+    assert [s["iters"] for s in sta] == [s["iters"] for s in stb]
+    ia, xa, _ = a.topk(qs, 20, tol=1e-9)
+    ib, xb, _ = b.topk(qs, 20, tol=1e-9)
+    assert np.array_equal(ia, ib) and np.array_equal(xa, xb)

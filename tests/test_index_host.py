@@ -148,3 +148,65 @@ def test_error_codes():
     with pytest.raises(K.KatzError) as e:
         idx.query([7])
     assert e.value.code == K.KATZ_EINVAL
+
+
+# ------------------------------------------------------------ index files
+def _info_tuple(info):
+    return (info.n, info.n1, info.n2, info.nnz, info.nblocks, info.max_block_size, info.rank, info.l_kind,
+            info.precision, info.beta, info.lambda_max, info.c, info.sigma_max, info.sigma_next)
+
+
+def test_index_file_round_trip(tmp_path):
+    g = ki.workload("sbm2k", scale=0.5).graph
+    for lk in (K.KATZ_L_CHOL, K.KATZ_L_IDENTITY):
+        a = K.KatzIndex.from_graph(g, beta=oracle_beta(g, 0.6), rank=6, device=-1, labels=g.labels,
+                                   max_block=40, l_kind=lk)
+        p = str(tmp_path / ("idx%d.katz" % lk))
+        a.save(p)
+        b = K.KatzIndex.load(p, device=-1)
+        assert _info_tuple(a.info) == _info_tuple(b.info)
+        pa, ba = a.partition()
+        pb, bb = b.partition()
+        assert np.array_equal(pa, pb) and np.array_equal(ba, bb)
+        ua, sa = a.lowrank()
+        ub, sb = b.lowrank()
+        assert np.array_equal(ua, ub) and np.array_equal(sa, sb)
+
+
+def test_index_file_rejects_damage(tmp_path):
+    g = ki.workload("sbm2k", scale=0.3).graph
+    a = K.KatzIndex.from_graph(g, beta=oracle_beta(g, 0.5), rank=2, device=-1, max_block=32)
+    p = tmp_path / "good.katz"
+    a.save(str(p))
+    raw = bytearray(p.read_bytes())
+    n = a.info.n
+
+    def load_code(data, name):
+        q = tmp_path / name
+        q.write_bytes(bytes(data))
+        with pytest.raises(K.KatzError) as e:
+            K.KatzIndex.load(str(q), device=-1)
+        return e.value.code
+
+    with pytest.raises(K.KatzError) as e:
+        K.KatzIndex.load(str(tmp_path / "missing.katz"), device=-1)
+    assert e.value.code == K.KATZ_EIO
+    bad = bytearray(raw)
+    bad[0] = ord("X")
+    assert load_code(bad, "magic.katz") == K.KATZ_EINVAL
+    assert load_code(raw[: len(raw) // 2], "short.katz") == K.KATZ_EIO
+    # header: magic 8, version 4, tag 4, then 84 bytes of scalars; perm's
+    # element count (u64) at 100, its elements from 108
+    perm0 = int.from_bytes(raw[108:112], "little")
+    bad = bytearray(raw)
+    bad[108:112] = raw[112:116]                       # perm[0] = perm[1]: not a permutation
+    assert perm0 != int.from_bytes(raw[112:116], "little")
+    assert load_code(bad, "perm.katz") == K.KATZ_EINVAL
+    # the first column index: after perm, iperm (n each), rp (n + 1), col's count
+    off = 108 + 4 * n + 8 + 4 * n + 8 + 4 * (n + 1) + 8
+    bad = bytearray(raw)
+    bad[off:off + 4] = (n + 5).to_bytes(4, "little")  # column out of range
+    assert load_code(bad, "col.katz") == K.KATZ_EINVAL
+    # a good file still loads after all this
+    b = K.KatzIndex.load(str(p), device=-1)
+    assert b.info.n == n
