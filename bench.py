@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--host-output", action="store_true",
                     help="one-query workload: deliver scores to pinned host memory (PCIe-inclusive rate; "
                          "the result line then says so in config.output)")
+    ap.add_argument("--precision", type=str, default="fp64", choices=["fp64", "mixed"],
+                    help="one-query workload: FP64 path (the configuration's) or the precision form")
     ap.add_argument("--u-precision", type=int, default=0, help="low-rank factor storage (0 auto, 1 FP64, 2 FP32, 3 BF16)")
     ap.add_argument("--serve", action="store_true", help="serving mode on --workload (default dcsbm16m)")
     ap.add_argument("--requests", type=int, default=200, help="requests per offered-load point (serving)")
@@ -141,7 +143,8 @@ def main():
     for c in cs:
         tb = time.time()
         idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=args.rank, max_block=args.max_block, device=0,
-                                     u_precision=args.u_precision)
+                                     u_precision=args.u_precision,
+                                     precision=K.KATZ_PREC_MIXED if args.precision == "mixed" else K.KATZ_PREC_FP64)
         info = idx.info
         log("c=%.2f index: n1=%d n2=%d blocks=%d sigma1=%.4f sigma_r+1=%.5f build %.1fs"
             % (c, info.n1, info.n2, info.nblocks, info.sigma_max, info.sigma_next, time.time() - tb))
@@ -215,11 +218,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+bf16/f64",
         "data": "synthetic",
         "config": {"workload": "Chung-Lu power-law graph, %d nodes, exponent 2.5, mean degree 20, "
-                               "c = beta*lambda_max = %g, rank %d, FP64, 1 query per solve"
-                               % (g.n, head_c, args.rank),
+                               "c = beta*lambda_max = %g, rank %d, %s, 1 query per solve"
+                               % (g.n, head_c, args.rank,
+                                  "FP64" if args.precision == "fp64" else "FP32 inner solves + FP64 refinement"),
                    "n": g.n, "nnz": g.nnz, "c": head_c, "rank": args.rank, "batch": 1, "tol": tol,
                    "output": "pinned host memory (PCIe-inclusive)" if args.host_output else "device memory"},
         "p99_ms": round(head["lrc"]["p99_ms"], 4),
