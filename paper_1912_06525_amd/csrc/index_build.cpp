@@ -14,6 +14,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -688,7 +689,17 @@ void lanczos_R(HostIndex& H, int32_t r, int32_t steps, uint64_t seed) {
 void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
                       const double* val, const katz_build_opts& o, HostIndex& H) {
   auto t0 = std::chrono::steady_clock::now();
+  // KATZ_VERBOSE=1: phase times of the build on stderr
+  const bool verbose = getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 0;
+  auto tp = t0;
+  auto phase = [&](const char* what) {
+    if (!verbose) return;
+    auto t = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "katz build: %-22s %8.3f s\n", what, std::chrono::duration<double>(t - tp).count());
+    tp = t;
+  };
   validate(n, nnz, row_ptr, col, val);
+  phase("validate");
   if (o.rank < 0) fail(KATZ_EINVAL, "rank must be >= 0");
   if (o.max_block < 0) fail(KATZ_EINVAL, "max_block must be >= 0");
   if (o.l_kind < KATZ_L_AUTO || o.l_kind > KATZ_L_IDENTITY) fail(KATZ_EINVAL, "bad l_kind");
@@ -708,6 +719,7 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
     H.beta = o.beta_frac / H.lambda_max;
   }
   H.c = H.beta * H.lambda_max;
+  phase("lambda_max");
   if (!(H.c < 1.0)) fail(KATZ_EDIVERGE, "beta * lambda_max(A) >= 1: Katz series diverges and I - beta A is not positive definite");
   if (o.labels)
     for (int32_t v = 0; v < n; v++)
@@ -723,6 +735,7 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
   H.blk_start = std::move(P.blk_start);
   H.n1 = P.n1;
   H.n2 = P.n2;
+  phase("partition");
 
   // permuted CSR with sorted rows and the separator split
   H.rp.assign(n + 1, 0);
@@ -751,6 +764,7 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
     }
   }, 4096);
 
+  phase("permuted CSR");
   // M11 block inverses
   int32_t nb = (int32_t)H.blk_start.size() - 1;
   H.blk_off.assign(nb + 1, 0);
@@ -777,6 +791,7 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
     }
   }, 16);
   if (notpd) fail(KATZ_EDIVERGE, "an M11 block is not positive definite (beta too large)");
+  phase("block inverses");
 
   // separator factor
   int32_t lk = o.l_kind;
@@ -797,7 +812,9 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
     std::vector<double> w;
     chol_inverse(H.lchol.data(), m2, H.ginv.data(), w);
   }
+  phase("M22 factor");
   lanczos_R(H, std::min(o.rank, H.n2), o.lanczos_steps, o.seed);
+  phase("Lanczos on R");
   H.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
