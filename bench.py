@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--precision", type=str, default="fp64", choices=["fp64", "mixed"],
                     help="one-query workload: FP64 path (the configuration's) or the precision form")
     ap.add_argument("--u-precision", type=int, default=0, help="low-rank factor storage (0 auto, 1 FP64, 2 FP32, 3 BF16)")
+    ap.add_argument("--pairs", type=int, default=0,
+                    help="pairwise queries on the 1M-node graph: this many distinct sources per step, "
+                         "16 destinations each")
     ap.add_argument("--serve", action="store_true", help="serving mode on --workload (default dcsbm16m)")
     ap.add_argument("--requests", type=int, default=200, help="requests per offered-load point (serving)")
     ap.add_argument("--workers", type=int, default=4)
@@ -105,6 +108,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.serve:
         return run_serving(args)
+    if args.pairs:
+        return run_pairs(args)
     if args.workload != "cl1m":
         return run_batched(args)
 
@@ -328,6 +333,49 @@ def run_batched(args):
                        "n": g.n, "nnz": g.nnz, "batch": B},
             "cg_qps": round(head["cg"]["qps"], 2), "lrc_over_cg": round(head["lrc"]["qps"] / head["cg"]["qps"], 3),
             "roofline": roofline, "cpu_baseline": None, "results": results}
+    print(json.dumps(line), flush=True)
+
+
+def run_pairs(args):
+    """Pairwise Katz scores K[dst, src] on the 1M-node Chung-Lu graph: a step is
+    `pairs` distinct sources x 16 destinations, solved as one batch."""
+    import numpy as np
+    import torch
+
+    import katz_inputs as ki
+    import paper_1912_06525_amd as K
+
+    w = ki.workload("cl1m", scale=args.scale)
+    g = w.graph
+    c = float(args.c.split(",")[0]) if args.c != "0.1,0.5,0.9" else 0.5
+    idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=args.rank, max_block=args.max_block, device=0)
+    rng = np.random.default_rng(6006)
+    S, D = args.pairs, 16
+    res = {}
+    for name, method in (("lrc", K.KATZ_METHOD_LRC), ("cg", K.KATZ_METHOD_CG)):
+        def step(s):
+            src = np.repeat(ki.sample_queries(g, S, 7000 + s), D)
+            dst = rng.integers(0, g.n, size=len(src)).astype(np.int32)
+            t = time.perf_counter()
+            _, st = idx.pair_scores(src, dst, tol=1e-6, method=method)
+            if any(x["status"] != 0 for x in st):
+                raise RuntimeError("no convergence")
+            return time.perf_counter() - t
+        for s in range(args.warmup):
+            step(s)
+        torch.cuda.synchronize()
+        lat = [step(args.warmup + s) for s in range(args.steps)]
+        el = sum(lat)
+        res[name] = {"pairs_per_s": S * D * args.steps / el, "ms_per_step": 1e3 * el / args.steps}
+        log("  %s: %.0f pairs/s (%d sources x %d destinations per step, %.1f ms)"
+            % (name, res[name]["pairs_per_s"], S, D, res[name]["ms_per_step"]))
+    line = {"metric": "pairwise Katz scores/sec at 1e-6 rel. residual, 1 MI355X", "value": round(res["lrc"]["pairs_per_s"], 1),
+            "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(res["lrc"]["ms_per_step"], 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "Chung-Lu power-law graph, %d nodes, c = %g, rank %d, %d sources x 16 "
+                                   "destinations per step" % (g.n, c, args.rank, S)},
+            "cg_pairs_per_s": round(res["cg"]["pairs_per_s"], 1)}
     print(json.dumps(line), flush=True)
 
 

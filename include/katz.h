@@ -213,6 +213,20 @@ int katz_index_save(const katz_index* idx, const char* path);
  */
 int katz_index_load(const char* path, int32_t device, katz_index** out);
 
+/*
+ * Katz scores of node pairs (the pairwise query of Sec. 3.1): scores[i] =
+ * K[dst[i], src[i]] = ((I - beta A)^{-1} - I)[dst[i], src[i]] (K is
+ * symmetric, so the roles may be swapped).  Pairs sharing a source share one
+ * solve: the distinct sources run as the columns of batched solves, and only
+ * the requested entries leave the device.
+ *   src[npairs], dst[npairs]: host arrays of node ids in [0, n).
+ *   scores: npairs FP64, host or device pointer (detected), caller-allocated.
+ *   st: nullable, npairs entries (each pair gets its source's solve stats).
+ * Errors as katz_query.
+ */
+int katz_pair_scores(const katz_index* idx, const int32_t* src, const int32_t* dst, int32_t npairs,
+                     const katz_query_opts* opts, double* scores, katz_query_stats* st, void* stream);
+
 /* Frees host and device memory of the index.  NULL is a no-op. */
 void katz_index_free(katz_index* idx);
 

@@ -32,7 +32,7 @@ _STATUS = {0: "KATZ_OK", -1: "KATZ_EINVAL", -2: "KATZ_ENOTSYM", -3: "KATZ_EDIVER
            -5: "KATZ_EDEVICE", -6: "KATZ_ENOCONV", -7: "KATZ_EBUSY", -8: "KATZ_EIO"}
 
 EXPORTED = ["katz_build_opts_default", "katz_query_opts_default", "katz_index_build", "katz_query",
-            "katz_topk_links", "katz_index_save", "katz_index_load", "katz_index_free", "katz_index_info", "katz_index_partition",
+            "katz_topk_links", "katz_pair_scores", "katz_index_save", "katz_index_load", "katz_index_free", "katz_index_info", "katz_index_partition",
             "katz_index_lowrank", "katz_profile_enable", "katz_profile_reset", "katz_profile_read",
             "katz_server_opts_default", "katz_server_create", "katz_server_submit", "katz_server_poll",
             "katz_server_info", "katz_server_destroy", "katz_last_error"]
@@ -112,6 +112,9 @@ def _load():
     lib.katz_topk_links.argtypes = [P, pi32, i32, i32, ctypes.POINTER(katz_query_opts), P, P,
                                     ctypes.POINTER(katz_query_stats), P]
     lib.katz_topk_links.restype = ctypes.c_int
+    lib.katz_pair_scores.argtypes = [P, pi32, pi32, i32, ctypes.POINTER(katz_query_opts), P,
+                                     ctypes.POINTER(katz_query_stats), P]
+    lib.katz_pair_scores.restype = ctypes.c_int
     lib.katz_index_save.argtypes = [P, ctypes.c_char_p]
     lib.katz_index_save.restype = ctypes.c_int
     lib.katz_index_load.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(P)]
@@ -221,6 +224,19 @@ def katz_topk_links(idx, q, k: int, opts: Optional[katz_query_opts], ids, scores
     st = (katz_query_stats * len(qa))() if stats is None else stats
     rc = _lib.katz_topk_links(idx, _pi32(qa), len(qa), int(k), ctypes.byref(opts) if opts is not None else None,
                               _ptr(ids), _ptr(scores), st, ctypes.c_void_p(stream) if stream else None)
+    if rc not in (KATZ_OK, KATZ_ENOCONV):
+        _check(rc)
+    return rc
+
+
+def katz_pair_scores(idx, src, dst, opts: Optional[katz_query_opts], scores, stats=None, stream=None) -> int:
+    s = np.ascontiguousarray(src, np.int32)
+    d = np.ascontiguousarray(dst, np.int32)
+    if s.shape != d.shape:
+        raise ValueError("src and dst must have the same length")
+    st = (katz_query_stats * len(s))() if stats is None else stats
+    rc = _lib.katz_pair_scores(idx, _pi32(s), _pi32(d), len(s), ctypes.byref(opts) if opts is not None else None,
+                               _ptr(scores), st, ctypes.c_void_p(stream) if stream else None)
     if rc not in (KATZ_OK, KATZ_ENOCONV):
         _check(rc)
     return rc
@@ -363,6 +379,16 @@ class KatzIndex:
         st = (katz_query_stats * len(q))()
         katz_query(self.h, q, self._opts(tol, method, max_iter, max_sweeps, check_every, force_fallback), out,
                    st, stream)
+        return out, stats_dicts(st)
+
+    def pair_scores(self, src: Sequence[int], dst: Sequence[int], out=None, *, tol: float = 1e-6,
+                    method: int = KATZ_METHOD_LRC, max_iter: int = 0, max_sweeps: int = 0, stream=None):
+        """K[dst[i], src[i]] per pair: (scores [npairs] FP64, stats list)."""
+        s = np.atleast_1d(np.asarray(src, np.int32))
+        if out is None:
+            out = np.empty(len(s), np.float64)
+        st = (katz_query_stats * len(s))()
+        katz_pair_scores(self.h, s, dst, self._opts(tol, method, max_iter, max_sweeps, 0), out, st, stream)
         return out, stats_dicts(st)
 
     def topk(self, q: Sequence[int], k: int, ids=None, scores=None, *, tol: float = 1e-6,

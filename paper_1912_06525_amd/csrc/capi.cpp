@@ -1,7 +1,10 @@
 // C ABI of the Katz library (include/katz.h): argument checks, error codes,
 // thread-local error messages; no exceptions cross the boundary.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
+#include <vector>
 #include <new>
 #include <string>
 
@@ -142,6 +145,47 @@ int katz_query(const katz_index* idx, const int32_t* q, int32_t nq, const katz_q
     a.q = q; a.nq = nq; a.opts = resolve(opts); a.scores = scores; a.topk = 0;
     a.st = st; a.stream = stream;
     rc = katz::device_query(idx->host, idx->dev, a);
+    if (rc == KATZ_ENOCONV) set_error(rc, "some queries did not reach the tolerance (see stats)");
+    return rc;
+  });
+}
+
+int katz_pair_scores(const katz_index* idx, const int32_t* src, const int32_t* dst, int32_t npairs,
+                     const katz_query_opts* opts, double* scores, katz_query_stats* st, void* stream) {
+  return guarded([&]() -> int {
+    if (!idx) return set_error(KATZ_EINVAL, "null index");
+    if (npairs < 0) return set_error(KATZ_EINVAL, "npairs must be >= 0");
+    if (npairs == 0) return KATZ_OK;
+    if (!src || !dst || !scores) return set_error(KATZ_EINVAL, "null pair or output array");
+    int rc = check_queries(idx, src, npairs);
+    if (rc) return rc;
+    rc = check_queries(idx, dst, npairs);
+    if (rc) return rc;
+    // distinct sources become the columns of the solve; pairs sorted by column
+    std::vector<int32_t> order(npairs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return src[a] < src[b]; });
+    std::vector<int32_t> q, pcol(npairs), prow(npairs);
+    for (int32_t t = 0; t < npairs; t++) {
+      const int32_t i = order[t];
+      if (q.empty() || q.back() != src[i]) q.push_back(src[i]);
+      pcol[t] = (int32_t)q.size() - 1;
+      prow[t] = idx->host.perm[dst[i]];
+    }
+    std::vector<double> out(npairs);
+    std::vector<katz_query_stats> qst(q.size());
+    katz::QueryArgs a{};
+    a.q = q.data(); a.nq = (int32_t)q.size(); a.opts = resolve(opts); a.scores = nullptr; a.topk = 0;
+    a.st = qst.data(); a.stream = stream;
+    a.npairs = npairs; a.pair_col = pcol.data(); a.pair_row = prow.data(); a.pair_out = out.data();
+    rc = katz::device_query(idx->host, idx->dev, a);
+    // back to the caller's pair order
+    std::vector<double> res(npairs);
+    for (int32_t t = 0; t < npairs; t++) {
+      res[order[t]] = out[t];
+      if (st) st[order[t]] = qst[pcol[t]];
+    }
+    katz::copy_to_caller(scores, res.data(), sizeof(double) * (size_t)npairs);
     if (rc == KATZ_ENOCONV) set_error(rc, "some queries did not reach the tolerance (see stats)");
     return rc;
   });

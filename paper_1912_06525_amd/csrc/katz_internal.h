@@ -77,8 +77,16 @@ struct QueryArgs {
   double* topk_scores;     // nq*topk or NULL
   katz_query_stats* st;
   void* stream;
+  // pair mode (npairs > 0): entries K[row, q[col]] for pairs sorted by col;
+  // pair_row in the permuted order; pair_out host FP64 [npairs]
+  int32_t npairs = 0;
+  const int32_t* pair_col = nullptr;
+  const int32_t* pair_row = nullptr;
+  double* pair_out = nullptr;
 };
 int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& a);
+// Copies host bytes to a caller buffer that may be host or device memory.
+void copy_to_caller(void* dst, const void* src, size_t bytes);
 // Device workspace (panels, partial sums, stream) reusable across calls.
 struct Workspace;
 Workspace* ws_create(DeviceIndex* D, int cap);

@@ -1169,6 +1169,13 @@ __global__ void k_cg_init(int B, ColState cs) {
 }
 
 // scores[j * n + v] = K[perm[v] * B + j]
+// out[t] = K[row[t]][col[t]] of the permuted n x B panel (pair queries).
+__global__ void k_pair_gather(int np, int B, const double* K, const int32_t* row, const int32_t* col,
+                              double* out) {
+  const int t = blockIdx.x * WG + threadIdx.x;
+  if (t < np) out[t] = K[(int64_t)row[t] * B + col[t]];
+}
+
 template <typename T>
 __global__ void k_unpermute(int n, int B, const T* K, const int32_t* perm, double* out) {
   const int j = blockIdx.y;
@@ -1292,6 +1299,9 @@ struct Workspace {
   void* tk_scratch = nullptr;    // top-K selection state and winners
   size_t tk_cap = 0;
   int32_t* tk_ids = nullptr;     // staging for host top-K output
+  int32_t *pr_rows = nullptr, *pr_cols = nullptr;  // pair queries: rows, columns, values
+  double* pr_out = nullptr;
+  int64_t pr_cap = 0;
   double* tk_sc = nullptr;
   int64_t tk_out_cap = 0;
   void* hpin = nullptr;          // pinned host staging for small scalars
@@ -2281,6 +2291,13 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
 
 int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa) { return device_query_ws(H, D, qa, nullptr); }
 
+void copy_to_caller(void* dst, const void* src, size_t bytes) {
+  if (is_device_ptr(dst))
+    HIPCHECK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+  else
+    std::memcpy(dst, src, bytes);
+}
+
 Workspace* ws_create(DeviceIndex* D, int cap) {
   HIPCHECK(hipSetDevice(D->device));
   return make_ws(D, cap).release();
@@ -2342,6 +2359,29 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
       if (!dev_ids) {
         HIPCHECK(hipMemcpyAsync(ids, dids, sizeof(int32_t) * (size_t)K * B, hipMemcpyDeviceToHost, st));
         if (sc) HIPCHECK(hipMemcpyAsync(sc, dsc, sizeof(double) * (size_t)K * B, hipMemcpyDeviceToHost, st));
+      }
+    }
+    if (qa.npairs > 0) {
+      // the pairs whose column lies in this chunk (sorted by column)
+      const int32_t* pc = qa.pair_col;
+      const int64_t p0 = std::lower_bound(pc, pc + qa.npairs, c0) - pc;
+      const int64_t p1 = std::lower_bound(pc, pc + qa.npairs, c0 + B) - pc;
+      const int64_t np = p1 - p0;
+      if (np > 0) {
+        if (w->pr_cap < np) {
+          w->pr_rows = dalloc<int32_t>(w->allocs, np);
+          w->pr_cols = dalloc<int32_t>(w->allocs, np);
+          w->pr_out = dalloc<double>(w->allocs, np);
+          w->pr_cap = np;
+        }
+        std::vector<int32_t> cols(qa.pair_col + p0, qa.pair_col + p1);
+        for (auto& x : cols) x -= c0;
+        HIPCHECK(hipMemcpyAsync(w->pr_rows, qa.pair_row + p0, sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(w->pr_cols, cols.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
+        k_pair_gather<<<(unsigned)((np + WG - 1) / WG), WG, 0, st>>>((int)np, B, w->K, w->pr_rows, w->pr_cols,
+                                                                    w->pr_out);
+        HIPCHECK(hipMemcpyAsync(qa.pair_out + p0, w->pr_out, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));  // `cols` is pageable host memory
       }
     }
     if (qa.scores) {

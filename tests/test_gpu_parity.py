@@ -235,3 +235,37 @@ def test_loaded_index_answers_identically(tmp_path):
     ia, xa, _ = a.topk(qs, 20, tol=1e-9)
     ib, xb, _ = b.topk(qs, 20, tol=1e-9)
     assert np.array_equal(ia, ib) and np.array_equal(xa, xb)
+
+
+def test_pair_scores_match_oracle():
+    # pairwise Katz K[dst, src]: repeated sources, src == dst (K_qq), an
+    # isolated source and more distinct sources than one batch holds
+    g = ki.workload("lnsbm4m", scale=0.002).graph
+    beta = oracle_beta(g, 0.6)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=8, labels=g.labels, max_block=32)
+    rng = np.random.default_rng(5)
+    deg = np.diff(g.row_ptr)
+    srcs = ki.sample_queries(g, 600, 41)               # > 512 distinct: two batches
+    src = np.concatenate([srcs, srcs[:50], [srcs[3]]])
+    dst = rng.integers(0, g.n, size=len(src)).astype(np.int32)
+    dst[-1] = srcs[3]                                  # K_qq
+    iso = np.nonzero(deg == 0)[0]
+    if len(iso):
+        src = np.append(src, iso[0])
+        dst = np.append(dst, srcs[0])
+    tau = 1e-8
+    tol = tau * (1 - 0.6) / (1 + 0.6)
+    sc, st = idx.pair_scores(src, dst, tol=tol)
+    assert all(s["status"] == 0 for s in st)
+    uq = np.unique(src)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, uq, beta=beta, validate=False)["k"]
+    col = {int(q): j for j, q in enumerate(uq)}
+    for t in range(len(src)):
+        k = ref[:, col[int(src[t])]]
+        assert abs(sc[t] - k[dst[t]]) <= tau * max(np.linalg.norm(k), 1e-300), t
+    # device output buffer gives the same values
+    import torch
+    out = torch.empty(len(src), dtype=torch.float64, device="cuda")
+    idx.pair_scores(src, dst, out=out, tol=tol)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), sc)
