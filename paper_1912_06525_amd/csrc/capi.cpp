@@ -96,11 +96,15 @@ int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
     if (o.u_precision < 0 || o.u_precision > 3) return set_error(KATZ_EINVAL, "bad u_precision");
     auto* idx = new katz_index();
     try {
-      katz::build_host_index(n, nnz, row_ptr, col_idx, val, o, idx->host);
+      // with a device, a large Lanczos on R runs there after the upload
+      katz::build_host_index(n, nnz, row_ptr, col_idx, val, o, idx->host, o.device >= 0);
       idx->device = o.device;
-      if (o.device >= 0) idx->dev = katz::device_upload(idx->host, o.device);
+      if (o.device >= 0) {
+        idx->dev = katz::device_upload(idx->host, o.device);
+        if (idx->host.lanczos_rank > 0) katz::device_lanczos_R(idx->host, idx->dev);
+      }
     } catch (...) {
-      delete idx;
+      katz_index_free(idx);
       throw;
     }
     *out = idx;
@@ -126,7 +130,7 @@ int katz_index_load(const char* path, int32_t device, katz_index** out) {
       idx->device = device;
       if (device >= 0) idx->dev = katz::device_upload(idx->host, device);
     } catch (...) {
-      delete idx;
+      katz_index_free(idx);
       throw;
     }
     *out = idx;

@@ -581,9 +581,9 @@ void lanczos_R(HostIndex& H, int32_t r, int32_t steps, uint64_t seed) {
   std::vector<double> Q((size_t)m * m2);
   std::vector<double> w(m2), tmp(m2);
   std::vector<double> al, be;
-  Rng rng{seed};
+  uint64_t rs = seed;
   auto random_start = [&](double* q, int32_t j) {
-    for (int32_t i = 0; i < m2; i++) q[i] = rng.normal();
+    lanczos_normals(rs, q, m2);
     for (int pass = 0; pass < 2; pass++)
       for (int32_t k = 0; k < j; k++) {
         const double* qk = &Q[(size_t)k * m2];
@@ -643,35 +643,18 @@ void lanczos_R(HostIndex& H, int32_t r, int32_t steps, uint64_t seed) {
     }
     tnorm = std::max(tnorm, b);
   }
-  int32_t mm = (int32_t)al.size();
-  std::vector<double> d(al), z;
-  std::vector<double> e(be.begin(), be.begin() + (mm - 1));
-  tridiag_eig(d, e, z, mm);
-  std::vector<int32_t> idx(mm);
-  std::iota(idx.begin(), idx.end(), 0);
-  std::sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return d[a] > d[b]; });
-  H.sigma.resize(r);
-  H.D.resize(r);
-  H.U.assign((size_t)m2 * r, 0.0);
-  for (int32_t t = 0; t < r; t++) {
-    int32_t col = idx[t];
-    double s = d[col];
-    if (s >= 1.0 - 1e-12) s = 1.0 - 1e-12;  // R < I exactly since S is SPD
-    H.sigma[t] = s;
-    H.D[t] = s / (1.0 - s);
-  }
-  H.sigma_next = mm > r ? d[idx[r]] : 0.0;
+  const int32_t mm = (int32_t)al.size();
+  const std::vector<double> z = lanczos_ritz(H, al, be, r);
   // Ritz vectors u_t = Q^T y_t, stored row-major n2 x r
+  H.U.assign((size_t)m2 * r, 0.0);
   parallel_for(m2, [&](int64_t i0, int64_t i1) {
     for (int64_t i = i0; i < i1; i++)
       for (int32_t t = 0; t < r; t++) {
-        int32_t col = idx[t];
         double s = 0;
-        for (int32_t k = 0; k < mm; k++) s += Q[(size_t)k * m2 + i] * z[(size_t)k * mm + col];
+        for (int32_t k = 0; k < mm; k++) s += Q[(size_t)k * m2 + i] * z[(size_t)t * mm + k];
         H.U[(size_t)i * r + t] = s;
       }
   }, 4096);
-  H.lanczos_steps = mm;
   // V = L^{-T} U
   H.V = H.U;
   if (chol) {
@@ -686,8 +669,53 @@ void lanczos_R(HostIndex& H, int32_t r, int32_t steps, uint64_t seed) {
 
 }  // namespace
 
+void lanczos_normals(uint64_t& state, double* out, int64_t n) {
+  Rng rng{state};
+  for (int64_t i = 0; i < n; i++) out[i] = rng.normal();
+  state = rng.s;
+}
+
+std::vector<double> lanczos_ritz(HostIndex& H, const std::vector<double>& al, const std::vector<double>& be,
+                                 int32_t r) {
+  const int32_t mm = (int32_t)al.size();
+  std::vector<double> d(al), z;
+  std::vector<double> e(be.begin(), be.begin() + (mm - 1));
+  tridiag_eig(d, e, z, mm);
+  std::vector<int32_t> idx(mm);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return d[a] > d[b]; });
+  H.rank = r;
+  H.sigma.resize(r);
+  H.D.resize(r);
+  std::vector<double> zr((size_t)mm * r);
+  for (int32_t t = 0; t < r; t++) {
+    const int32_t col = idx[t];
+    double s = d[col];
+    if (s >= 1.0 - 1e-12) s = 1.0 - 1e-12;  // R < I exactly since S is SPD
+    H.sigma[t] = s;
+    H.D[t] = s / (1.0 - s);
+    for (int32_t k = 0; k < mm; k++) zr[(size_t)t * mm + k] = z[(size_t)k * mm + col];
+  }
+  H.sigma_next = mm > r ? d[idx[r]] : 0.0;
+  H.lanczos_steps = mm;
+  return zr;
+}
+
+bool lanczos_on_device(const HostIndex& H, const katz_build_opts& o) {
+  if (o.device < 0 || o.rank <= 0 || H.l_kind != KATZ_L_IDENTITY) return false;
+  const int64_t r = std::min<int64_t>(o.rank, H.n2);
+  const int64_t m = o.lanczos_steps > 0 ? o.lanczos_steps : std::max<int64_t>(2 * r, r + 20);
+  if (std::min<int64_t>(m, H.n2) > 512) return false;  // the device Ritz step's limit
+  if (const char* e = getenv("KATZ_LANCZOS")) {  // 1 host, 2 device (tests and timing runs)
+    const int v = atoi(e);
+    if (v == 1) return false;
+    if (v == 2) return true;
+  }
+  return H.n2 >= 65536;
+}
+
 void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
-                      const double* val, const katz_build_opts& o, HostIndex& H) {
+                      const double* val, const katz_build_opts& o, HostIndex& H, bool defer_lanczos) {
   auto t0 = std::chrono::steady_clock::now();
   // KATZ_VERBOSE=1: phase times of the build on stderr
   const bool verbose = getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 0;
@@ -813,8 +841,15 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
     chol_inverse(H.lchol.data(), m2, H.ginv.data(), w);
   }
   phase("M22 factor");
-  lanczos_R(H, std::min(o.rank, H.n2), o.lanczos_steps, o.seed);
-  phase("Lanczos on R");
+  if (defer_lanczos && lanczos_on_device(H, o)) {
+    H.rank = 0;
+    H.lanczos_rank = std::min(o.rank, H.n2);
+    H.lanczos_steps_req = o.lanczos_steps;
+    H.lanczos_seed = o.seed;
+  } else {
+    lanczos_R(H, std::min(o.rank, H.n2), o.lanczos_steps, o.seed);
+    phase("Lanczos on R");
+  }
   H.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 

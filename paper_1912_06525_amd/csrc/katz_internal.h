@@ -49,13 +49,27 @@ struct HostIndex {
   std::vector<double> U, V, sigma, D;
   double sigma_next = 0;
   int32_t lanczos_steps = 0;
+  int32_t lanczos_rank = 0, lanczos_steps_req = 0;  // a deferred Lanczos run
+  uint64_t lanczos_seed = 0;
   int32_t precision = KATZ_PREC_FP64;
   int32_t u_precision = 0;  // resolved: 1 FP64, 2 FP32 (FP64 path); BF16 on the mixed path
   double build_seconds = 0;
 };
 
+// defer_lanczos: leave the low-rank factor out (rank 0) and record what it
+// needs in H.lanczos_rank / lanczos_steps_req / lanczos_seed, for a Lanczos
+// run on the device (device_lanczos_R).
 void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
-                      const double* val, const katz_build_opts& o, HostIndex& H);
+                      const double* val, const katz_build_opts& o, HostIndex& H, bool defer_lanczos = false);
+// Lanczos pieces shared by the host and device runs: the seeded normal
+// stream of the start / restart vectors, and the Ritz pairs of the
+// tridiagonal (fills rank, sigma, D, sigma_next, lanczos_steps; returns the
+// coefficients z, Ritz vector t = sum_k z[t * mm + k] q_k).
+void lanczos_normals(uint64_t& state, double* out, int64_t n);
+std::vector<double> lanczos_ritz(HostIndex& H, const std::vector<double>& al, const std::vector<double>& be,
+                                 int32_t r);
+// Whether the Lanczos on R should run on the device for these options.
+bool lanczos_on_device(const HostIndex& H, const katz_build_opts& o);
 // Index files (index_io.cpp): a loaded index is fully validated.
 void save_host_index(const HostIndex& H, const char* path);
 void load_host_index(const char* path, HostIndex& H);
@@ -63,6 +77,9 @@ void load_host_index(const char* path, HostIndex& H);
 // ------------------------------------------------------- device index
 struct DeviceIndex;            // defined in the HIP solver
 DeviceIndex* device_upload(const HostIndex& H, int device);
+// Top eigenpairs of R on the device (L = I), as the host Lanczos computes
+// them; fills the low-rank fields of H and uploads the factors.
+void device_lanczos_R(HostIndex& H, DeviceIndex* D);
 void device_free(DeviceIndex* D);
 int64_t device_bytes(const DeviceIndex* D);
 int64_t device_factor_bytes(const DeviceIndex* D);

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <atomic>
@@ -837,9 +838,9 @@ __global__ __launch_bounds__(WG) void k_vt_rows(int64_t m, int B, int rank, int 
   }
 }
 
-// DW[v] = D[v / B] * sum over chunks c of partials[c * nv + v], nv = rank * B:
-// 64 values per workgroup, its four waves taking every fourth chunk, combined
-// in a fixed order (deterministic).
+// DW[v] = D[v / B] * sum over chunks c of partials[c * nv + v], nv = rank * B
+// (D NULL: the plain sums): 64 values per workgroup, its four waves taking
+// every fourth chunk, combined in a fixed order (deterministic).
 __global__ __launch_bounds__(WG) void k_vt_reduce(const double* partials, int nchunk, int64_t nv, int B,
                                                   const double* Dg, double* DW, const int* n_active) {
   if (n_active && *n_active == 0) return;
@@ -857,7 +858,8 @@ __global__ __launch_bounds__(WG) void k_vt_reduce(const double* partials, int nc
   }
   sh[tid] = s0 + s1;
   __syncthreads();
-  if (wv == 0 && v < nv) DW[v] = Dg[v / B] * ((sh[lane] + sh[64 + lane]) + (sh[128 + lane] + sh[192 + lane]));
+  if (wv == 0 && v < nv)
+    DW[v] = (Dg ? Dg[v / B] : 1.0) * ((sh[lane] + sh[64 + lane]) + (sh[128 + lane] + sh[192 + lane]));
 }
 
 // z = base + V DW (base = r, or the z already stored when L = chol), then
@@ -1387,6 +1389,36 @@ int grid_for(int64_t work, int per) {
 
 }  // namespace
 
+// The low-rank factor's device copies (in the storage the index's precision
+// and u_precision call for) and D.
+static void upload_factors(const HostIndex& H, DeviceIndex* D) {
+  D->rank = H.rank;
+  if (H.rank <= 0) return;
+  int64_t* by = &D->bytes;
+  std::vector<double> vc((size_t)H.n2 * H.rank);  // column-major copy
+  for (int64_t i = 0; i < H.n2; i++)
+    for (int k = 0; k < H.rank; k++) vc[(size_t)k * H.n2 + i] = H.V[(size_t)i * H.rank + k];
+  if (H.precision == KATZ_PREC_FP64 && H.u_precision == 2) {
+    std::vector<float> v32(vc.begin(), vc.end());
+    D->V32 = upload(D->allocs, v32, by);
+  } else if (H.precision == KATZ_PREC_FP64 && H.u_precision == 3) {
+    std::vector<uint16_t> vb(vc.size());
+    for (size_t t = 0; t < vc.size(); t++) vb[t] = bf16_bits((float)vc[t]);
+    D->V16 = (bf16*)upload(D->allocs, vb, by);
+  } else if (H.precision == KATZ_PREC_FP64) {
+    D->V = upload(D->allocs, vc, by);
+  }
+  D->D = upload(D->allocs, H.D, by);
+  if (H.precision == KATZ_PREC_MIXED) {
+    std::vector<uint16_t> vb(vc.size()), vr(vc.size());
+    for (size_t t = 0; t < vc.size(); t++) vb[t] = bf16_bits((float)vc[t]);
+    for (int64_t i = 0; i < H.n2; i++)
+      for (int k = 0; k < H.rank; k++) vr[(size_t)i * H.rank + k] = bf16_bits((float)H.V[(size_t)i * H.rank + k]);
+    D->V16 = (bf16*)upload(D->allocs, vb, by);
+    D->V16r = (bf16*)upload(D->allocs, vr, by);
+  }
+}
+
 DeviceIndex* device_upload(const HostIndex& H, int device) {
   HIPCHECK(hipSetDevice(device));
   auto D = new DeviceIndex();
@@ -1481,30 +1513,7 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
         D->ginv32 = upload(D->allocs, g32, by);
       }
     }
-    if (H.rank > 0) {
-      std::vector<double> vc((size_t)H.n2 * H.rank);  // column-major copy
-      for (int64_t i = 0; i < H.n2; i++)
-        for (int k = 0; k < H.rank; k++) vc[(size_t)k * H.n2 + i] = H.V[(size_t)i * H.rank + k];
-      if (H.precision == KATZ_PREC_FP64 && H.u_precision == 2) {
-        std::vector<float> v32(vc.begin(), vc.end());
-        D->V32 = upload(D->allocs, v32, by);
-      } else if (H.precision == KATZ_PREC_FP64 && H.u_precision == 3) {
-        std::vector<uint16_t> vb(vc.size());
-        for (size_t t = 0; t < vc.size(); t++) vb[t] = bf16_bits((float)vc[t]);
-        D->V16 = (bf16*)upload(D->allocs, vb, by);
-      } else if (H.precision == KATZ_PREC_FP64) {
-        D->V = upload(D->allocs, vc, by);
-      }
-      D->D = upload(D->allocs, H.D, by);
-      if (H.precision == KATZ_PREC_MIXED) {
-        std::vector<uint16_t> vb(vc.size()), vr(vc.size());
-        for (size_t t = 0; t < vc.size(); t++) vb[t] = bf16_bits((float)vc[t]);
-        for (int64_t i = 0; i < H.n2; i++)
-          for (int k = 0; k < H.rank; k++) vr[(size_t)i * H.rank + k] = bf16_bits((float)H.V[(size_t)i * H.rank + k]);
-        D->V16 = (bf16*)upload(D->allocs, vb, by);
-        D->V16r = (bf16*)upload(D->allocs, vr, by);
-      }
-    }
+    upload_factors(H, D);
     HIPCHECK(hipDeviceSynchronize());
   } catch (...) {
     device_free(D);
@@ -2413,6 +2422,216 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
     }
   }
   return rc;
+}
+
+// ------------------------------------------------ Lanczos on R (device)
+// The top eigenpairs of R = I - S (L = I) by Lanczos with full
+// reorthogonalisation, as the host index build computes them (Algorithm 1,
+// Lanczos step), with the basis Q (column-major n2 x m, FP64) in HBM.
+
+// partials[blockIdx.x * nv + k] = sum over the chunk's rows i of Q[k][i] w[i]
+// for k in the workgroup's tile of kQT vectors (blockIdx.y).
+constexpr int kQT = 16;
+__global__ __launch_bounds__(WG) void k_qtw(int64_t m, int nv, const double* Q, const double* w, int64_t rpc,
+                                            double* partials) {
+  __shared__ double sh[(WG / 64) * kQT];
+  const int tid = threadIdx.x, k0 = blockIdx.y * kQT;
+  const int64_t r0 = (int64_t)blockIdx.x * rpc, r1 = min<int64_t>(m, r0 + rpc);
+  double acc[kQT];
+#pragma unroll
+  for (int t = 0; t < kQT; t++) acc[t] = 0.0;
+  for (int64_t i = r0 + tid; i < r1; i += WG) {
+    const double x = w[i];
+#pragma unroll
+    for (int t = 0; t < kQT; t++)
+      if (k0 + t < nv) acc[t] += Q[(int64_t)(k0 + t) * m + i] * x;
+  }
+  const int wave = tid / 64, lane = tid % 64;
+#pragma unroll
+  for (int t = 0; t < kQT; t++) {
+    double v = acc[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) sh[wave * kQT + t] = v;
+  }
+  __syncthreads();
+  if (tid < kQT && k0 + tid < nv) {
+    double s = 0.0;
+    for (int wv = 0; wv < WG / 64; wv++) s += sh[wv * kQT + tid];
+    partials[(int64_t)blockIdx.x * nv + k0 + tid] = s;
+  }
+}
+
+// w[i] -= sum_k Q[k][i] h[k], k < nv (h staged in LDS, nv <= kMaxBasis).
+constexpr int kMaxBasis = 4096;
+constexpr int kMaxRitzSteps = 512;  // k_ritz stages kQT x steps doubles in 64 KB of LDS
+__global__ __launch_bounds__(WG) void k_sub_qh(int64_t m, int nv, const double* Q, const double* h, double* w) {
+  __shared__ double hs[kMaxBasis];
+  for (int k = threadIdx.x; k < nv; k += WG) hs[k] = h[k];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= m) return;
+  double s = 0.0;
+  for (int k = 0; k < nv; k++) s += Q[(int64_t)k * m + i] * hs[k];
+  w[i] -= s;
+}
+
+// dst[i] = a * src[i]
+__global__ void k_scale(int64_t m, double a, const double* src, double* dst) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < m) dst[i] = a * src[i];
+}
+
+// U[i][t] (row-major m x r) = sum_k Q[k][i] Z[t * mm + k] for the tile of
+// kQT Ritz vectors t (blockIdx.y); Z staged in LDS.
+__global__ __launch_bounds__(WG) void k_ritz(int64_t m, int mm, int r, const double* Q, const double* Z, double* U) {
+  extern __shared__ double zs[];  // kQT x mm
+  const int t0 = blockIdx.y * kQT;
+  for (int e = threadIdx.x; e < kQT * mm; e += WG) {
+    const int t = e / mm, k = e % mm;
+    zs[e] = t0 + t < r ? Z[(int64_t)(t0 + t) * mm + k] : 0.0;
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= m) return;
+  double acc[kQT];
+#pragma unroll
+  for (int t = 0; t < kQT; t++) acc[t] = 0.0;
+  for (int k = 0; k < mm; k++) {
+    const double q = Q[(int64_t)k * m + i];
+#pragma unroll
+    for (int t = 0; t < kQT; t++) acc[t] += q * zs[t * mm + k];
+  }
+#pragma unroll
+  for (int t = 0; t < kQT; t++)
+    if (t0 + t < r) U[i * r + t0 + t] = acc[t];
+}
+
+void device_lanczos_R(HostIndex& H, DeviceIndex* D) {
+  auto t0 = std::chrono::steady_clock::now();
+  HIPCHECK(hipSetDevice(D->device));
+  const int32_t m2 = H.n2, n1 = H.n1, n = H.n;
+  const int32_t r = std::min(H.lanczos_rank, m2);
+  if (r <= 0 || H.l_kind != KATZ_L_IDENTITY) fail(KATZ_EDEVICE, "internal: device Lanczos needs L = I and r > 0");
+  int32_t m = H.lanczos_steps_req > 0 ? H.lanczos_steps_req : std::max(2 * r, r + 20);
+  m = std::min(m, m2);
+  if (m > kMaxRitzSteps) fail(KATZ_EINVAL, "more than 512 Lanczos steps run on the host");
+  std::unique_ptr<Workspace> wsp = make_ws(D, 1);
+  Workspace* w = wsp.get();
+  hipStream_t st = w->stream;
+  Launcher L{D, w, st, 1};
+  std::vector<void*> tmp;
+  struct Freer {
+    std::vector<void*>& v;
+    ~Freer() { for (void* p : v) (void)hipFree(p); }
+  } freer{tmp};
+  double* Q = dalloc<double>(tmp, (int64_t)m * m2);
+  double* wv = dalloc<double>(tmp, m2);
+  const int64_t rpc = std::max<int64_t>(WG * 4, (m2 + 1023) / 1024);
+  const int nchunk = (int)((m2 + rpc - 1) / rpc);
+  double* part = dalloc<double>(tmp, (int64_t)nchunk * kMaxBasis);
+  double* hv = dalloc<double>(tmp, kMaxBasis);
+  // rows < n1: t1 = M11^{-1} (beta A12 q); rows >= n1: q (its own FP64 buffer:
+  // the workspace panels are FP32 for the precision form)
+  double* X = dalloc<double>(tmp, n);
+  std::vector<double> hh(kMaxBasis);
+  const unsigned g1 = (unsigned)((m2 + WG - 1) / WG);
+
+  // h[0..nv) = Q[:, 0..nv)^T x (device), and a copy on the host
+  auto qtx = [&](const double* Qb, int nv, const double* x) {
+    dim3 g((unsigned)nchunk, (unsigned)((nv + kQT - 1) / kQT));
+    k_qtw<<<g, WG, 0, st>>>(m2, nv, Qb, x, rpc, part);
+    k_vt_reduce<<<(unsigned)((nv + 63) / 64), WG, 0, st>>>(part, nchunk, nv, 1, nullptr, hv, nullptr);
+    HIPCHECK(hipMemcpyAsync(hh.data(), hv, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+  };
+  auto norm = [&](const double* x) {
+    qtx(x, 1, x);
+    return std::sqrt(hh[0]);
+  };
+  // q_j <- random, orthogonal to q_0..q_{j-1} (two passes), unit norm
+  uint64_t rs = H.lanczos_seed;
+  std::vector<double> hq(m2);
+  auto random_start = [&](int j) {
+    lanczos_normals(rs, hq.data(), m2);
+    double* qj = Q + (int64_t)j * m2;
+    HIPCHECK(hipMemcpyAsync(qj, hq.data(), sizeof(double) * m2, hipMemcpyHostToDevice, st));
+    for (int pass = 0; pass < 2 && j > 0; pass++) {
+      qtx(Q, j, qj);
+      k_sub_qh<<<g1, WG, 0, st>>>(m2, j, Q, hv, qj);
+    }
+    const double nn = norm(qj);
+    k_scale<<<g1, WG, 0, st>>>(m2, 1.0 / nn, qj, qj);
+  };
+  // y = R q = beta (A21 t1 + A22 q), t1 = M11^{-1} (beta A12 q)
+  auto applyR = [&](const double* q, double* y) {
+    HIPCHECK(hipMemcpyAsync(X + n1, q, sizeof(double) * m2, hipMemcpyDeviceToDevice, st));
+    if (n1 > 0) {
+      M11Args<double> a;
+      a.tile_row0 = D->tile_row0; a.row_blk = D->row_blk; a.blk_start = D->blk_start; a.blk_off = D->blk_off;
+      a.minv = D->minv; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val; a.n1 = n1;
+      a.v = nullptr; a.cv = 0.0; a.x2 = X + n1; a.ca = D->beta; a.out = X; a.B = 1; a.n_active = nullptr;
+      a.xcd = 0;
+      a.CB = 1;
+      a.sub = 4;
+      const size_t shm = (size_t)D->max_tile_rows * sizeof(double);
+      k_m11_apply<double><<<D->ntiles, WG, shm, st>>>(a);
+    }
+    SpmmArgs<double> s{};
+    s.row0 = n1; s.row1 = n; s.rp = D->rp; s.col = D->col; s.split = D->split; s.val = D->val;
+    s.x = X; s.ca = D->beta; s.cb = D->beta; s.parts = 3;
+    s.v = nullptr; s.cv = 0.0; s.w = nullptr; s.cw = 0.0; s.y = y;
+    s.ep = EP_NONE; s.dotv = nullptr; s.cs = L.cs(0); s.n_active = nullptr;
+    L.spmm(s);
+  };
+
+  std::vector<double> al, be;
+  random_start(0);
+  double tnorm = 0.0;
+  for (int j = 0; j < m; j++) {
+    const double* qj = Q + (int64_t)j * m2;
+    applyR(qj, wv);
+    qtx(qj, 1, wv);
+    const double a = hh[0];
+    al.push_back(a);
+    tnorm = std::max(tnorm, std::fabs(a));
+    for (int pass = 0; pass < 2; pass++) {  // full reorthogonalisation
+      qtx(Q, j + 1, wv);
+      k_sub_qh<<<g1, WG, 0, st>>>(m2, j + 1, Q, hv, wv);
+    }
+    const double b = norm(wv);
+    if (j + 1 == m) {
+      be.push_back(b);
+      break;
+    }
+    if (b <= 1e-12 * std::max(tnorm, 1e-300)) {
+      be.push_back(0.0);  // invariant subspace: T decouples, restart
+      random_start(j + 1);
+    } else {
+      be.push_back(b);
+      k_scale<<<g1, WG, 0, st>>>(m2, 1.0 / b, wv, Q + (int64_t)(j + 1) * m2);
+    }
+    tnorm = std::max(tnorm, b);
+  }
+  const int32_t mm = (int32_t)al.size();
+  const std::vector<double> z = lanczos_ritz(H, al, be, r);
+  double* Zd = dalloc<double>(tmp, (int64_t)mm * r);
+  double* Ud = dalloc<double>(tmp, (int64_t)m2 * r);
+  HIPCHECK(hipMemcpyAsync(Zd, z.data(), sizeof(double) * z.size(), hipMemcpyHostToDevice, st));
+  {
+    dim3 g(g1, (unsigned)((r + kQT - 1) / kQT));
+    const size_t shm = sizeof(double) * kQT * mm;
+    if (shm > 65536) fail(KATZ_EINVAL, "lanczos_steps too large for the device Ritz step");
+    k_ritz<<<g, WG, shm, st>>>(m2, mm, r, Q, Zd, Ud);
+  }
+  H.U.resize((size_t)m2 * r);
+  HIPCHECK(hipMemcpyAsync(H.U.data(), Ud, sizeof(double) * H.U.size(), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  HIPCHECK(hipGetLastError());
+  H.V = H.U;  // L = I
+  upload_factors(H, D);
+  HIPCHECK(hipDeviceSynchronize());
+  H.build_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 int profile_enable(int on) { return g_prof_on.exchange(on ? 1 : 0); }

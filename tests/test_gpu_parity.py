@@ -269,3 +269,50 @@ def test_pair_scores_match_oracle():
     idx.pair_scores(src, dst, out=out, tol=tol)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), sc)
+
+
+def test_device_lanczos_matches_host(monkeypatch):
+    # the index build's Lanczos on R run on the device (forced) reproduces
+    # the host run: same Ritz values, Ritz vectors up to sign, same answers
+    g = ki.workload("lnsbm4m", scale=0.004).graph
+    beta = oracle_beta(g, 0.9)
+    monkeypatch.setenv("KATZ_LANCZOS", "1")
+    a = K.KatzIndex.from_graph(g, beta=beta, rank=12, labels=g.labels, max_block=32)
+    monkeypatch.setenv("KATZ_LANCZOS", "2")
+    b = K.KatzIndex.from_graph(g, beta=beta, rank=12, labels=g.labels, max_block=32)
+    assert a.info.l_kind == K.KATZ_L_IDENTITY and b.info.rank == a.info.rank == 12
+    ua, sa = a.lowrank()
+    ub, sb = b.lowrank()
+    np.testing.assert_allclose(sb, sa, rtol=0, atol=1e-10)
+    for t in range(len(sa) - 1):
+        if sa[t] - sa[t + 1] > 1e-6 and (t == 0 or sa[t - 1] - sa[t] > 1e-6):  # simple, separated pairs
+            assert abs(abs(ua[:, t] @ ub[:, t]) - 1.0) < 1e-6, t
+    qs = ki.sample_queries(g, 4, 9)
+    tol = 1e-9
+    ka, sta = a.query(qs, tol=tol)
+    kb, stb = b.query(qs, tol=tol)
+    for j in range(len(qs)):
+        assert np.linalg.norm(ka[j] - kb[j]) <= 20 * tol * np.linalg.norm(ka[j])
+
+
+def test_device_lanczos_full_spectrum(monkeypatch):
+    # Theorem 1 on the device path: with m = n2 steps the device Lanczos
+    # returns the top eigenvalues of the dense R = I - S
+    g = ki.sbm([40, 35, 45, 30], [0.3, 0.3, 0.3, 0.3], 0.04, seed=13)
+    beta = oracle_beta(g, 0.8)
+    monkeypatch.setenv("KATZ_LANCZOS", "2")
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=6, labels=g.labels, max_block=8, l_kind=K.KATZ_L_IDENTITY,
+                                 lanczos_steps=10 ** 6)
+    info = idx.info
+    perm, _ = idx.partition()
+    A = oracle.csr_matrix(g.n, g.row_ptr, g.col).toarray()
+    P = np.zeros((g.n, g.n))
+    P[perm, np.arange(g.n)] = 1.0
+    M = np.eye(g.n) - beta * (P @ A @ P.T)
+    n1 = info.n1
+    M11, M12, M22 = M[:n1, :n1], M[:n1, n1:], M[n1:, n1:]
+    S = M22 - M12.T @ np.linalg.solve(M11, M12)
+    sig = np.sort(np.linalg.eigvalsh(np.eye(info.n2) - S))[::-1]
+    U, s = idx.lowrank()
+    np.testing.assert_allclose(s, sig[:6], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(U.T @ U, np.eye(6), atol=1e-10)
