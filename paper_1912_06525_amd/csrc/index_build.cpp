@@ -357,6 +357,14 @@ void bfs_order(const int32_t* rp, const int32_t* col, const std::vector<int32_t>
 
 Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const int32_t* labels,
                          int32_t max_block, int32_t order_kind) {
+  const bool verbose = getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 1;
+  auto tp = std::chrono::steady_clock::now();
+  auto phase = [&](const char* what) {
+    if (!verbose) return;
+    auto t = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "katz partition: %-20s %8.3f s\n", what, std::chrono::duration<double>(t - tp).count());
+    tp = t;
+  };
   // (a) initial parts
   std::vector<int32_t> part(n);
   int32_t P = 0;
@@ -390,6 +398,7 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
     }
     std::vector<int32_t>().swap(mem);
   }
+  phase("BFS chunks");
   // (c) greedy vertex cover of the cut edges (largest remaining cut degree first)
   std::vector<int32_t> cutdeg(n, 0);
   int32_t dmax = 0;
@@ -421,6 +430,7 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
     }
   }
   std::vector<std::vector<int32_t>>().swap(bucket);
+  phase("vertex cover");
   // (d) minimality: a separator node whose non-separator neighbours all lie in
   // one piece (with room) joins that piece; one with none becomes a singleton.
   std::vector<int32_t> psize(npiece, 0);
@@ -446,6 +456,7 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
       insep[v] = 0;
     }
   }
+  phase("minimality");
   // (e) blocks = connected components of the graph without the separator;
   // each lies inside one piece, so it has at most max_block nodes.
   std::vector<int32_t> comp(n, -1);
@@ -465,27 +476,54 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
       }
     }
   }
+  phase("components");
   // Block order.  DEGREE: largest blocks first (a descending work list for the
   // block kernel).  LOCALITY: blocks and their nodes in BFS visit order, so
   // neighbours stay close in every panel.
   const bool locality = order_kind == KATZ_ORDER_LOCALITY;
-  std::vector<int32_t> bo(blocks.size());
+  const int32_t nbk = (int32_t)blocks.size();
+  std::vector<int32_t> bo(nbk);
   std::iota(bo.begin(), bo.end(), 0);
-  if (locality) {
-    for (auto& b : blocks) std::sort(b.begin(), b.end(), [&](int32_t x, int32_t y) { return visit[x] < visit[y]; });
-    std::stable_sort(bo.begin(), bo.end(), [&](int32_t a, int32_t b) { return visit[blocks[a][0]] < visit[blocks[b][0]]; });
-  } else {
-    std::stable_sort(bo.begin(), bo.end(), [&](int32_t a, int32_t b) { return blocks[a].size() > blocks[b].size(); });
-  }
   Partition R;
   R.perm.assign(n, -1);
-  R.iperm.reserve(n);
   R.blk_start.push_back(0);
-  std::vector<int32_t> blkpos(blocks.size());
-  for (size_t t = 0; t < bo.size(); t++) {
-    blkpos[bo[t]] = (int32_t)t;
-    for (int32_t v : blocks[bo[t]]) { R.perm[v] = (int32_t)R.iperm.size(); R.iperm.push_back(v); }
-    R.blk_start.push_back((int32_t)R.iperm.size());
+  if (locality) {
+    // blocks by their first node in visit order, nodes within a block in
+    // visit order: sort the blocks by that key, then place the nodes while
+    // walking the visit order (O(n) apart from the sort of the block keys)
+    std::vector<int32_t> ord(n, -1);
+    for (int32_t v = 0; v < n; v++) {
+      if (visit[v] < 0 || visit[v] >= n || ord[visit[v]] >= 0) fail(KATZ_EDEVICE, "internal: BFS visit order");
+      ord[visit[v]] = v;
+    }
+    std::vector<std::pair<int64_t, int32_t>> kb(nbk, {INT64_MAX, 0});
+    for (int32_t b = 0; b < nbk; b++) kb[b].second = b;
+    for (int32_t v = 0; v < n; v++)
+      if (!insep[v]) kb[comp[v]].first = std::min(kb[comp[v]].first, visit[v]);
+    std::sort(kb.begin(), kb.end());
+    std::vector<int32_t> slot(nbk);
+    int32_t run = 0;
+    for (int32_t t = 0; t < nbk; t++) {
+      bo[t] = kb[t].second;
+      slot[bo[t]] = run;
+      run += (int32_t)blocks[bo[t]].size();
+      R.blk_start.push_back(run);
+    }
+    R.iperm.assign(run, -1);
+    for (int32_t pos = 0; pos < n; pos++) {
+      const int32_t v = ord[pos];
+      if (insep[v]) continue;
+      const int32_t at = slot[comp[v]]++;
+      R.perm[v] = at;
+      R.iperm[at] = v;
+    }
+  } else {
+    std::stable_sort(bo.begin(), bo.end(), [&](int32_t a, int32_t b) { return blocks[a].size() > blocks[b].size(); });
+    R.iperm.reserve(n);
+    for (size_t t = 0; t < bo.size(); t++) {
+      for (int32_t v : blocks[bo[t]]) { R.perm[v] = (int32_t)R.iperm.size(); R.iperm.push_back(v); }
+      R.blk_start.push_back((int32_t)R.iperm.size());
+    }
   }
   R.n1 = (int32_t)R.iperm.size();
   // separator order.  DEGREE: largest first, then by id (the hubs, which most
@@ -495,9 +533,9 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
   for (int32_t v = 0; v < n; v++)
     if (insep[v]) sk.emplace_back(locality ? visit[v] : -(int64_t)(rp[v + 1] - rp[v]), v);
   std::sort(sk.begin(), sk.end());
-  (void)blkpos;
   for (auto& kv : sk) { R.perm[kv.second] = (int32_t)R.iperm.size(); R.iperm.push_back(kv.second); }
   R.n2 = n - R.n1;
+  phase("order");
   return R;
 }
 
