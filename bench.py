@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--pairs", type=int, default=0,
                     help="pairwise queries on the 1M-node graph: this many distinct sources per step, "
                          "16 destinations each")
+    ap.add_argument("--sparse-katz", type=str, default="",
+                    help="Sparse-Katz on the 1M-node graph: 'nq,s,T' (queries per call, list length, modular nodes)")
     ap.add_argument("--serve", action="store_true", help="serving mode on --workload (default dcsbm16m)")
     ap.add_argument("--requests", type=int, default=200, help="requests per offered-load point (serving)")
     ap.add_argument("--workers", type=int, default=4)
@@ -110,6 +112,8 @@ def main():
         return run_serving(args)
     if args.pairs:
         return run_pairs(args)
+    if args.sparse_katz:
+        return run_sparse_katz(args)
     if args.workload != "cl1m":
         return run_batched(args)
 
@@ -376,6 +380,47 @@ def run_pairs(args):
             "config": {"workload": "Chung-Lu power-law graph, %d nodes, c = %g, rank %d, %d sources x 16 "
                                    "destinations per step" % (g.n, c, args.rank, S)},
             "cg_pairs_per_s": round(res["cg"]["pairs_per_s"], 1)}
+    print(json.dumps(line), flush=True)
+
+
+def run_sparse_katz(args):
+    """Sparse-Katz requests (Algorithm 3) on the 1M-node Chung-Lu graph: a step is
+    one call with nq query nodes, each re-ranking its top-s list by the
+    correlation with T modular nodes."""
+    import torch
+
+    import katz_inputs as ki
+    import paper_1912_06525_amd as K
+
+    nq, S, T = (int(x) for x in args.sparse_katz.split(","))
+    w = ki.workload("cl1m", scale=args.scale)
+    g = w.graph
+    c = float(args.c.split(",")[0]) if args.c != "0.1,0.5,0.9" else 0.5
+    idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=args.rank, max_block=args.max_block, device=0)
+    res = {}
+    for name, method in (("lrc", K.KATZ_METHOD_LRC), ("cg", K.KATZ_METHOD_CG)):
+        def step(s):
+            q = ki.sample_queries(g, nq, 8000 + s)
+            t = time.perf_counter()
+            _, _, st = idx.sparse_katz(q, S, T, tol=1e-6, method=method)
+            if any(x["status"] != 0 for x in st):
+                raise RuntimeError("no convergence")
+            return time.perf_counter() - t
+        for s in range(args.warmup):
+            step(s)
+        torch.cuda.synchronize()
+        lat = [step(args.warmup + s) for s in range(args.steps)]
+        el = sum(lat)
+        res[name] = {"requests_per_s": nq * args.steps / el, "ms_per_step": 1e3 * el / args.steps}
+        log("  %s: %.1f requests/s (%d per call, s=%d, T=%d, %.1f ms per call)"
+            % (name, res[name]["requests_per_s"], nq, S, T, res[name]["ms_per_step"]))
+    line = {"metric": "Sparse-Katz link-prediction requests/sec at 1e-6 rel. residual, 1 MI355X",
+            "value": round(res["lrc"]["requests_per_s"], 2), "unit": "requests/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["lrc"]["ms_per_step"], 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "Chung-Lu power-law graph, %d nodes, c = %g, rank %d, %d queries per call, "
+                                   "s = %d, T = %d" % (g.n, c, args.rank, nq, S, T)},
+            "cg_requests_per_s": round(res["cg"]["requests_per_s"], 2)}
     print(json.dumps(line), flush=True)
 
 

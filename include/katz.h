@@ -227,6 +227,24 @@ int katz_index_load(const char* path, int32_t device, katz_index** out);
 int katz_pair_scores(const katz_index* idx, const int32_t* src, const int32_t* dst, int32_t npairs,
                      const katz_query_opts* opts, double* scores, katz_query_stats* st, void* stream);
 
+/*
+ * Sparse-Katz link prediction (Sec. 3.3, Algorithm 3).  For each query q:
+ * the top-s candidates of k_q (q and its neighbours excluded, as in
+ * katz_topk_links) are re-ranked by the Pearson correlation of their row
+ * with q's row in K_T = [k_t1 ... k_tT], the Katz vectors of the T
+ * highest-ranked candidates ("modular" nodes).  Rows are T-vectors K[v, t].
+ * Correlation descending; undefined correlations (a constant row, or fewer
+ * than 2 modular nodes) last; ties keep the Katz order.
+ *   s in [0, 4096], T in [2, 4096].
+ *   ids: nq * s int32 (padded with -1); corr: nq * s FP64 correlations (NaN
+ *     when undefined or padded) or NULL.  Host or device pointers.
+ *   st: nullable, nq entries (the stats of the k_q solves).
+ * Errors as katz_query.
+ */
+int katz_sparse_katz(const katz_index* idx, const int32_t* q, int32_t nq, int32_t s, int32_t T,
+                     const katz_query_opts* opts, int32_t* ids, double* corr, katz_query_stats* st,
+                     void* stream);
+
 /* Frees host and device memory of the index.  NULL is a no-op. */
 void katz_index_free(katz_index* idx);
 

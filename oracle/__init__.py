@@ -9,7 +9,7 @@ eqs. KatzPath, KatzMatrix, LinearSystem): k_q = sum_{l>=1} beta^l A^l e_q =
 ((I - beta A)^{-1} - I) e_q = (I - beta A)^{-1} beta A e_q, two independent
 ways (a dense Cholesky solve and a truncated Neumann series with a rigorous
 tail bound), plus the top-K link-prediction ranking (Section 3.3, Algorithm 3's
-sort step).
+sort step) and the Sparse-Katz re-ranking (Algorithm 3).
 """
 from .reference import (  # noqa: F401
     OracleError,
@@ -25,4 +25,5 @@ from .reference import (  # noqa: F401
     topk_accept,
     tie_classes,
     walk_counts,
+    sparse_katz,
 )

@@ -260,6 +260,35 @@ def topk_accept(build_ids: Sequence[int], sorted_ids: np.ndarray, sorted_scores:
 
 
 # ------------------------------------------------------------- brute force
+def sparse_katz(n: int, row_ptr, col, q: int, s: int, T: int, beta: float, lam: Optional[float] = None) -> dict:
+    """Sparse-Katz link prediction (Section 3.3, Algorithm 3), from the text:
+    k_q; its candidates (all nodes but q and its neighbours) sorted by score
+    (ties by id); the top-s list and the T highest-ranked candidates as the
+    "modular" nodes; K_T = [k_t] for those nodes (n x T); for each listed
+    candidate j, rho_j = Pearson correlation of rows q and j of K_T (NaN when
+    a row is constant or T < 2); the list re-ordered by rho descending,
+    undefined correlations last, ties in the Katz order.
+    Returns ids (re-ranked), rho (in that order), the Katz-ordered list, its
+    correlations and K_T."""
+    kq = katz_oracle(n, row_ptr, col, [q], beta=beta, lam=lam, validate=False)["k"][:, 0]
+    _, _, sid, _ = topk_links(n, row_ptr, col, kq, q, max(s, T))
+    cand = sid[:s]
+    mods = sid[:T]
+    rho = np.full(len(cand), np.nan)
+    KT = None
+    if len(mods) >= 2:
+        KT = katz_oracle(n, row_ptr, col, mods, beta=beta, lam=lam, validate=False)["k"]
+        xq = KT[q, :]
+        for j, v in enumerate(cand):
+            y = KT[v, :]
+            if np.ptp(xq) > 0 and np.ptp(y) > 0:
+                rho[j] = np.corrcoef(xq, y)[0, 1]
+    key = [(0 if np.isfinite(r) else 1, -r if np.isfinite(r) else 0.0, j) for j, r in enumerate(rho)]
+    order = [j for _, _, j in sorted(key)]
+    return {"ids": cand[order], "rho": rho[order], "katz_order": cand, "katz_rho": rho, "KT": KT,
+            "modular": mods}
+
+
 def walk_counts(n: int, row_ptr, col, q: int, max_len: int) -> list:
     """Exact number of walks of each length l = 1..max_len from q to every
     node, by explicit depth-first enumeration of the walks (tiny graphs only).

@@ -32,7 +32,7 @@ _STATUS = {0: "KATZ_OK", -1: "KATZ_EINVAL", -2: "KATZ_ENOTSYM", -3: "KATZ_EDIVER
            -5: "KATZ_EDEVICE", -6: "KATZ_ENOCONV", -7: "KATZ_EBUSY", -8: "KATZ_EIO"}
 
 EXPORTED = ["katz_build_opts_default", "katz_query_opts_default", "katz_index_build", "katz_query",
-            "katz_topk_links", "katz_pair_scores", "katz_index_save", "katz_index_load", "katz_index_free", "katz_index_info", "katz_index_partition",
+            "katz_topk_links", "katz_pair_scores", "katz_sparse_katz", "katz_index_save", "katz_index_load", "katz_index_free", "katz_index_info", "katz_index_partition",
             "katz_index_lowrank", "katz_profile_enable", "katz_profile_reset", "katz_profile_read",
             "katz_server_opts_default", "katz_server_create", "katz_server_submit", "katz_server_poll",
             "katz_server_info", "katz_server_destroy", "katz_last_error"]
@@ -112,6 +112,9 @@ def _load():
     lib.katz_topk_links.argtypes = [P, pi32, i32, i32, ctypes.POINTER(katz_query_opts), P, P,
                                     ctypes.POINTER(katz_query_stats), P]
     lib.katz_topk_links.restype = ctypes.c_int
+    lib.katz_sparse_katz.argtypes = [P, pi32, i32, i32, i32, ctypes.POINTER(katz_query_opts), P, P,
+                                     ctypes.POINTER(katz_query_stats), P]
+    lib.katz_sparse_katz.restype = ctypes.c_int
     lib.katz_pair_scores.argtypes = [P, pi32, pi32, i32, ctypes.POINTER(katz_query_opts), P,
                                      ctypes.POINTER(katz_query_stats), P]
     lib.katz_pair_scores.restype = ctypes.c_int
@@ -237,6 +240,18 @@ def katz_pair_scores(idx, src, dst, opts: Optional[katz_query_opts], scores, sta
     st = (katz_query_stats * len(s))() if stats is None else stats
     rc = _lib.katz_pair_scores(idx, _pi32(s), _pi32(d), len(s), ctypes.byref(opts) if opts is not None else None,
                                _ptr(scores), st, ctypes.c_void_p(stream) if stream else None)
+    if rc not in (KATZ_OK, KATZ_ENOCONV):
+        _check(rc)
+    return rc
+
+
+def katz_sparse_katz(idx, q, s: int, T: int, opts: Optional[katz_query_opts], ids, corr=None, stats=None,
+                     stream=None) -> int:
+    qa = np.ascontiguousarray(q, np.int32)
+    st = (katz_query_stats * len(qa))() if stats is None else stats
+    rc = _lib.katz_sparse_katz(idx, _pi32(qa), len(qa), int(s), int(T),
+                               ctypes.byref(opts) if opts is not None else None, _ptr(ids), _ptr(corr), st,
+                               ctypes.c_void_p(stream) if stream else None)
     if rc not in (KATZ_OK, KATZ_ENOCONV):
         _check(rc)
     return rc
@@ -390,6 +405,16 @@ class KatzIndex:
         st = (katz_query_stats * len(s))()
         katz_pair_scores(self.h, s, dst, self._opts(tol, method, max_iter, max_sweeps, 0), out, st, stream)
         return out, stats_dicts(st)
+
+    def sparse_katz(self, q: Sequence[int], s: int, T: int, *, tol: float = 1e-6, method: int = KATZ_METHOD_LRC,
+                    max_iter: int = 0, max_sweeps: int = 0, stream=None):
+        """Sparse-Katz re-ranked links: (ids [nq, s], correlations [nq, s], stats)."""
+        q = np.atleast_1d(np.asarray(q, np.int32))
+        ids = np.empty((len(q), s), np.int32)
+        corr = np.empty((len(q), s), np.float64)
+        st = (katz_query_stats * len(q))()
+        katz_sparse_katz(self.h, q, s, T, self._opts(tol, method, max_iter, max_sweeps, 0), ids, corr, st, stream)
+        return ids, corr, stats_dicts(st)
 
     def topk(self, q: Sequence[int], k: int, ids=None, scores=None, *, tol: float = 1e-6,
              method: int = KATZ_METHOD_LRC, max_iter: int = 0, max_sweeps: int = 0, check_every: int = 0,

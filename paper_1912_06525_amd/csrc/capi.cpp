@@ -43,6 +43,36 @@ int check_queries(const katz_index* idx, const int32_t* q, int32_t nq) {
   return KATZ_OK;
 }
 
+katz_query_opts resolve(const katz_query_opts* o);
+
+// K[dst[i], src[i]] for validated pairs into host out[], per-pair stats
+// (nullable); the distinct sources run as the columns of batched solves.
+int pair_scores_host(const katz_index* idx, const int32_t* src, const int32_t* dst, int32_t npairs,
+                     const katz_query_opts* opts, double* out_h, katz_query_stats* st, void* stream) {
+  std::vector<int32_t> order(npairs);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return src[a] < src[b]; });
+  std::vector<int32_t> q, pcol(npairs), prow(npairs);
+  for (int32_t t = 0; t < npairs; t++) {
+    const int32_t i = order[t];
+    if (q.empty() || q.back() != src[i]) q.push_back(src[i]);
+    pcol[t] = (int32_t)q.size() - 1;
+    prow[t] = idx->host.perm[dst[i]];
+  }
+  std::vector<double> out(npairs);
+  std::vector<katz_query_stats> qst(q.size());
+  katz::QueryArgs a{};
+  a.q = q.data(); a.nq = (int32_t)q.size(); a.opts = resolve(opts); a.scores = nullptr; a.topk = 0;
+  a.st = qst.data(); a.stream = stream;
+  a.npairs = npairs; a.pair_col = pcol.data(); a.pair_row = prow.data(); a.pair_out = out.data();
+  const int rc = katz::device_query(idx->host, idx->dev, a);
+  for (int32_t t = 0; t < npairs; t++) {
+    out_h[order[t]] = out[t];
+    if (st) st[order[t]] = qst[pcol[t]];
+  }
+  return rc;
+}
+
 katz_query_opts resolve(const katz_query_opts* o) {
   katz_query_opts r;
   katz_query_opts_default(&r);
@@ -165,32 +195,101 @@ int katz_pair_scores(const katz_index* idx, const int32_t* src, const int32_t* d
     if (rc) return rc;
     rc = check_queries(idx, dst, npairs);
     if (rc) return rc;
-    // distinct sources become the columns of the solve; pairs sorted by column
-    std::vector<int32_t> order(npairs);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return src[a] < src[b]; });
-    std::vector<int32_t> q, pcol(npairs), prow(npairs);
-    for (int32_t t = 0; t < npairs; t++) {
-      const int32_t i = order[t];
-      if (q.empty() || q.back() != src[i]) q.push_back(src[i]);
-      pcol[t] = (int32_t)q.size() - 1;
-      prow[t] = idx->host.perm[dst[i]];
-    }
-    std::vector<double> out(npairs);
-    std::vector<katz_query_stats> qst(q.size());
-    katz::QueryArgs a{};
-    a.q = q.data(); a.nq = (int32_t)q.size(); a.opts = resolve(opts); a.scores = nullptr; a.topk = 0;
-    a.st = qst.data(); a.stream = stream;
-    a.npairs = npairs; a.pair_col = pcol.data(); a.pair_row = prow.data(); a.pair_out = out.data();
-    rc = katz::device_query(idx->host, idx->dev, a);
-    // back to the caller's pair order
     std::vector<double> res(npairs);
-    for (int32_t t = 0; t < npairs; t++) {
-      res[order[t]] = out[t];
-      if (st) st[order[t]] = qst[pcol[t]];
-    }
+    rc = pair_scores_host(idx, src, dst, npairs, opts, res.data(), st, stream);
     katz::copy_to_caller(scores, res.data(), sizeof(double) * (size_t)npairs);
     if (rc == KATZ_ENOCONV) set_error(rc, "some queries did not reach the tolerance (see stats)");
+    return rc;
+  });
+}
+
+int katz_sparse_katz(const katz_index* idx, const int32_t* q, int32_t nq, int32_t s, int32_t T,
+                     const katz_query_opts* opts, int32_t* ids, double* corr, katz_query_stats* st,
+                     void* stream) {
+  return guarded([&]() -> int {
+    int rc = check_queries(idx, q, nq);
+    if (rc) return rc;
+    if (s < 0 || T < 2 || T > 4096 || s > 4096) return set_error(KATZ_EINVAL, "need 0 <= s <= 4096 and 2 <= T <= 4096");
+    if (nq == 0 || s == 0) return KATZ_OK;
+    if (!ids) return set_error(KATZ_EINVAL, "null ids buffer");
+    // (1) k_q and its top max(s, T) candidates (q and its neighbours excluded)
+    const int32_t K = std::max(s, T);
+    std::vector<int32_t> top((size_t)nq * K);
+    std::vector<double> topsc((size_t)nq * K);
+    katz::QueryArgs a{};
+    a.q = q; a.nq = nq; a.opts = resolve(opts); a.scores = nullptr; a.topk = K; a.ids = top.data();
+    a.topk_scores = topsc.data(); a.st = st; a.stream = stream;
+    int rc1 = katz::device_query(idx->host, idx->dev, a);
+    // (2) the T modular nodes t of each query: K_T[v][t] = K[v, t] for v = q
+    // and for every listed candidate, as pair queries (src t, dst v)
+    std::vector<int32_t> ps, pd;
+    std::vector<int32_t> ncand(nq), nmod(nq);
+    for (int32_t i = 0; i < nq; i++) {
+      const int32_t* li = top.data() + (size_t)i * K;
+      int32_t nc = 0;
+      while (nc < K && li[nc] >= 0) nc++;
+      ncand[i] = std::min(nc, s);
+      nmod[i] = std::min(nc, T);
+      for (int32_t t = 0; t < nmod[i]; t++) {
+        ps.push_back(li[t]);
+        pd.push_back(q[i]);
+        for (int32_t j = 0; j < ncand[i]; j++) {
+          ps.push_back(li[t]);
+          pd.push_back(li[j]);
+        }
+      }
+    }
+    std::vector<double> kt(ps.size());
+    std::vector<katz_query_stats> pst(ps.size());
+    int rc2 = ps.empty() ? KATZ_OK
+                         : pair_scores_host(idx, ps.data(), pd.data(), (int32_t)ps.size(), opts, kt.data(),
+                                            pst.data(), stream);
+    // (3) Pearson correlation of row q with each candidate's row; re-rank
+    std::vector<int32_t> out_ids((size_t)nq * s, -1);
+    std::vector<double> out_corr((size_t)nq * s, std::nan(""));
+    size_t base = 0;
+    for (int32_t i = 0; i < nq; i++) {
+      const int32_t Ti = nmod[i], nc = ncand[i];
+      const int32_t* li = top.data() + (size_t)i * K;
+      // kt[base + t * (nc + 1) + 0] = K[q, t]; ... + 1 + j = K[cand j, t]
+      auto at = [&](int32_t t, int32_t r) { return kt[base + (size_t)t * (nc + 1) + r]; };
+      std::vector<double> rho(nc, std::nan(""));
+      if (Ti >= 2) {
+        double mq = 0;
+        for (int32_t t = 0; t < Ti; t++) mq += at(t, 0);
+        mq /= Ti;
+        double sq = 0;
+        for (int32_t t = 0; t < Ti; t++) sq += (at(t, 0) - mq) * (at(t, 0) - mq);
+        for (int32_t j = 0; j < nc; j++) {
+          double mj = 0;
+          for (int32_t t = 0; t < Ti; t++) mj += at(t, 1 + j);
+          mj /= Ti;
+          double sj = 0, cj = 0;
+          for (int32_t t = 0; t < Ti; t++) {
+            const double dj = at(t, 1 + j) - mj;
+            sj += dj * dj;
+            cj += (at(t, 0) - mq) * dj;
+          }
+          if (sq > 0 && sj > 0) rho[j] = cj / std::sqrt(sq * sj);
+        }
+      }
+      std::vector<int32_t> ord(nc);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+        const bool fx = !std::isnan(rho[x]), fy = !std::isnan(rho[y]);
+        if (fx != fy) return fx;           // undefined correlations last
+        return fx && rho[x] > rho[y];      // descending; ties keep the Katz order
+      });
+      for (int32_t j = 0; j < nc; j++) {
+        out_ids[(size_t)i * s + j] = li[ord[j]];
+        out_corr[(size_t)i * s + j] = rho[ord[j]];
+      }
+      base += (size_t)Ti * (nc + 1);
+    }
+    katz::copy_to_caller(ids, out_ids.data(), sizeof(int32_t) * out_ids.size());
+    if (corr) katz::copy_to_caller(corr, out_corr.data(), sizeof(double) * out_corr.size());
+    rc = rc1 != KATZ_OK ? rc1 : rc2;
+    if (rc == KATZ_ENOCONV) set_error(rc, "some solves did not reach the tolerance");
     return rc;
   });
 }

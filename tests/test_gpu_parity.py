@@ -316,3 +316,26 @@ def test_device_lanczos_full_spectrum(monkeypatch):
     U, s = idx.lowrank()
     np.testing.assert_allclose(s, sig[:6], rtol=0, atol=1e-10)
     np.testing.assert_allclose(U.T @ U, np.eye(6), atol=1e-10)
+
+
+def test_sparse_katz_matches_oracle():
+    # Sparse-Katz (Algorithm 3): the re-ranked top-s list and its
+    # correlations against the oracle, tie classes of correlation width 1e-7
+    g = ki.workload("lnsbm4m", scale=0.002).graph
+    beta = oracle_beta(g, 0.7)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=8, labels=g.labels, max_block=32)
+    qs = ki.sample_queries(g, 3, 61)
+    s, T = 20, 8
+    ids, corr, st = idx.sparse_katz(qs, s, T, tol=1e-11)
+    assert all(x["status"] == 0 for x in st)
+    for i, q in enumerate(qs):
+        ref = oracle.sparse_katz(g.n, g.row_ptr, g.col, int(q), s, T, beta)
+        m = len(ref["ids"])
+        assert np.all(ids[i][m:] == -1)
+        fin = np.isfinite(ref["rho"])
+        np.testing.assert_allclose(corr[i][:m][fin], ref["rho"][fin], rtol=0, atol=1e-7)
+        # finite part: same order up to ties; undefined ones last, in Katz order
+        nf = int(fin.sum())
+        ok, msg, _ = oracle.topk_accept(ids[i][:nf], ref["ids"][:nf], ref["rho"][:nf], nf, 1e-7)
+        assert ok, msg
+        assert np.array_equal(ids[i][nf:m], ref["ids"][nf:m])

@@ -318,3 +318,48 @@ def test_residual_closed_forms_complete_graph(n, beta):
     k = np.full((n, 1), beta / d)
     k[0, 0] = (n - 1) * beta ** 2 / d
     assert ko.katz_residual(A, beta, [0], k)[0] < 1e-14
+
+
+# ------------------------------------------------- Sparse-Katz (Algorithm 3)
+def test_sparse_katz_cycle_closed_form():
+    """On the cycle C_n every Katz score is a closed form of the distance, so
+    the candidate list, the modular nodes, K_T and the correlations all follow
+    from it (no solve): the oracle's re-ranked list must match."""
+    n, q, s, T = 23, 0, 8, 6
+    nn, rp, col = cycle(n)
+    beta = 0.3
+    sq = math.sqrt(1 - 4 * beta ** 2)
+    t = (1 - sq) / (2 * beta)
+
+    def K(d):
+        d = np.minimum(d % n, (-d) % n)
+        return (t ** d + t ** (n - d)) / (sq * (1 - t ** n)) - (d == 0)
+
+    cand = [v for v in range(n) if v not in (q, 1, n - 1)]
+    cand.sort(key=lambda v: (-K(v - q), v))
+    mods = cand[:T]
+    KT = np.array([[K(v - m) for m in mods] for v in range(n)])
+    rho = []
+    for v in cand[:s]:
+        x, y = KT[q], KT[v]
+        rho.append(np.corrcoef(x, y)[0, 1] if np.ptp(y) > 0 else np.nan)
+    want = [v for _, v in sorted(zip([-r for r in rho], cand[:s]), key=lambda p: (p[0], cand.index(p[1])))]
+    want_rho = sorted(rho, reverse=True)
+    got = oracle.sparse_katz(nn, rp, col, q, s, T, beta)
+    assert list(got["katz_order"]) == cand[:s]
+    assert list(got["modular"]) == mods
+    np.testing.assert_allclose(got["katz_rho"], rho, rtol=0, atol=1e-9)
+    # mirror-image nodes have exactly equal correlations: any order inside a
+    # tie class is right (the same rule as for the top-K list)
+    ok, msg, ntie = oracle.topk_accept(got["ids"], np.array(want), np.array(want_rho), s, 1e-9)
+    assert ok, msg
+    assert ntie >= 1
+    assert sorted(got["ids"].tolist()) == sorted(cand[:s])          # a permutation of the top-s list
+    assert np.all(np.abs(got["rho"]) <= 1 + 1e-12)
+
+
+def test_sparse_katz_pearson_by_hand():
+    # Pearson correlation on rows written out: (1,2,3) vs (2,4,6) = 1, vs (3,2,1) = -1
+    x = np.array([1.0, 2.0, 3.0])
+    assert np.corrcoef(x, 2 * x)[0, 1] == pytest.approx(1.0)
+    assert np.corrcoef(x, x[::-1])[0, 1] == pytest.approx(-1.0)
