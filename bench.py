@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--precision", type=str, default="fp64", choices=["fp64", "mixed"],
                     help="one-query workload: FP64 path (the configuration's) or the precision form")
     ap.add_argument("--u-precision", type=int, default=0, help="low-rank factor storage (0 auto, 1 FP64, 2 FP32, 3 BF16)")
+    ap.add_argument("--concurrency", type=int, default=2,
+                    help="one-query workload: also time this many host threads solving independent single "
+                         "queries at once (each on its own workspace stream); 0 or 1 to skip")
     ap.add_argument("--pairs", type=int, default=0,
                     help="pairwise queries on the 1M-node graph: this many distinct sources per step, "
                          "16 destinations each")
@@ -174,6 +177,42 @@ def main():
             log("  %s: %.1f q/s, %.3f ms/query, iters median %g" % (name, entry[name]["qps"],
                                                                     entry[name]["ms_per_query"],
                                                                     entry[name]["iters_median"]))
+            if c == head_c and args.concurrency > 1 and not args.host_output:
+                # independent one-query solves from several host threads at once
+                import threading
+                per = max(1, args.steps // args.concurrency) * 2
+                outs = [torch.empty((1, g.n), dtype=torch.float64, device=dev) for _ in range(args.concurrency)]
+                errs = []
+
+                # one caller stream per thread (default priority): on a shared stream
+                # each call would be ordered after the others
+                strs = [torch.cuda.Stream(device=dev) for _ in range(args.concurrency)]
+
+                def worker(tid):
+                    try:
+                        for s2 in range(per):
+                            q = queries[(tid * per + s2) % len(queries)]
+                            _, st2 = idx.query([q], out=outs[tid], tol=tol, method=method,
+                                               stream=strs[tid].cuda_stream)
+                            if st2[0]["status"] != 0:
+                                errs.append(q)
+                    except Exception as e:  # reported below
+                        errs.append(repr(e))
+                ths = [threading.Thread(target=worker, args=(i,)) for i in range(args.concurrency)]
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for th in ths:
+                    th.start()
+                for th in ths:
+                    th.join()
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t
+                if errs:
+                    raise RuntimeError("concurrent solves failed: %r" % errs[:3])
+                entry[name]["concurrent_qps"] = per * args.concurrency / el
+                entry[name]["concurrency"] = args.concurrency
+                log("  %s: %.1f q/s with %d concurrent one-query solves" % (name, per * args.concurrency / el,
+                                                                          args.concurrency))
             if c == head_c and not args.no_profile_kernels:
                 # repeat of the timed steps with HIP-event timing of every hot kernel
                 # launch; convergence is polled every iteration here so that no
@@ -239,6 +278,9 @@ def main():
         "p50_ms": round(head["lrc"]["p50_ms"], 4),
         "cg_qps": round(head["cg"]["qps"], 2),
         "lrc_over_cg": round(value / head["cg"]["qps"], 3),
+        "concurrent": {"threads": args.concurrency,
+                       "lrc_qps": round(head["lrc"].get("concurrent_qps", 0.0), 2),
+                       "cg_qps": round(head["cg"].get("concurrent_qps", 0.0), 2)} if args.concurrency > 1 else None,
         "roofline": roofline,
         "cpu_baseline": head.get("cpu", {}).get("baseline"),
         "results": results,

@@ -102,6 +102,12 @@ struct QueryArgs {
   double* pair_out = nullptr;
 };
 int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& a);
+// Serializes an open HIP graph capture (one thread) with the operations of
+// other threads that may synchronize with the legacy stream (allocation,
+// frees, synchronous copies and memsets, stream and event creation, work on
+// the NULL stream): HIP rejects those while a capture is open, and the
+// capture fails with them.
+std::recursive_mutex& hip_global_mu();
 // Copies host bytes to a caller buffer that may be host or device memory.
 void copy_to_caller(void* dst, const void* src, size_t bytes);
 // Device workspace (panels, partial sums, stream) reusable across calls.

@@ -78,7 +78,12 @@ struct Server {
       return;
     }
     hipStream_t stream = nullptr;
-    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+    hipError_t se;
+    {
+      std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
+      se = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+    }
+    if (se != hipSuccess) {
       init_failed = 1;
       return;
     }
@@ -152,6 +157,7 @@ struct Server {
       done_queries += nq;
       cv_done.notify_all();
     }
+    std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
     (void)hipStreamDestroy(stream);
   }
 };

@@ -1211,6 +1211,7 @@ struct ProfEvents {
   size_t used = 0;
   void begin(int k, double b, hipStream_t st) {
     if (used == kind.size()) {
+      std::lock_guard<std::recursive_mutex> g(hip_global_mu());
       hipEvent_t a, c;
       HIPCHECK(hipEventCreate(&a));
       HIPCHECK(hipEventCreate(&c));
@@ -1355,6 +1356,7 @@ namespace {
 
 template <typename T>
 T* dalloc(std::vector<void*>& list, int64_t count, int64_t* bytes = nullptr) {
+  std::lock_guard<std::recursive_mutex> g(hip_global_mu());
   if (count <= 0) count = 1;
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, (size_t)count * sizeof(T));
@@ -1367,6 +1369,7 @@ T* dalloc(std::vector<void*>& list, int64_t count, int64_t* bytes = nullptr) {
 
 template <typename T>
 T* upload(std::vector<void*>& list, const std::vector<T>& h, int64_t* bytes) {
+  std::lock_guard<std::recursive_mutex> g(hip_global_mu());
   T* d = dalloc<T>(list, (int64_t)h.size(), bytes);
   if (!h.empty()) HIPCHECK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   return d;
@@ -1420,6 +1423,7 @@ static void upload_factors(const HostIndex& H, DeviceIndex* D) {
 }
 
 DeviceIndex* device_upload(const HostIndex& H, int device) {
+  std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
   HIPCHECK(hipSetDevice(device));
   auto D = new DeviceIndex();
   try {
@@ -1523,6 +1527,7 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
 }
 
 static void free_ws(Workspace* w) {
+  std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
   w->graphs.clear();
   if (w->stream) (void)hipStreamDestroy(w->stream);
@@ -1541,6 +1546,7 @@ Workspace::~Workspace() { free_ws(this); }
 
 void device_free(DeviceIndex* D) {
   if (!D) return;
+  std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
   (void)hipSetDevice(D->device);
   for (auto& w : D->pool) free_ws(w.get());
   for (void* p : D->allocs) (void)hipFree(p);
@@ -1588,6 +1594,7 @@ int64_t ws_bytes_per_column(const DeviceIndex* D) {
 }
 
 static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
+  std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
   auto w = std::make_unique<Workspace>();
   w->B = B;
   w->n = D->n;
@@ -1613,13 +1620,15 @@ static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   if (D->precision == KATZ_PREC_MIXED) w->Rf = dalloc<float>(L, nB);
   int* ip = dalloc<int>(L, 4 * (int64_t)B + 1);
   w->active = ip; w->status = ip + B; w->iters = ip + 2 * B; w->mask = ip + 3 * B; w->n_active = ip + 4 * B;
-  HIPCHECK(hipMemset(s, 0, 12 * sizeof(double) * (size_t)B));
-  HIPCHECK(hipMemset(ip, 0, (4 * (size_t)B + 1) * sizeof(int)));
   w->qpos = dalloc<int32_t>(L, B);
   HIPCHECK(hipHostMalloc(&w->hpin, 64 * 1024, hipHostMallocDefault));
   HIPCHECK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
   HIPCHECK(hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming));
   HIPCHECK(hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming));
+  // cleared on the workspace's own stream (not the legacy stream)
+  HIPCHECK(hipMemsetAsync(s, 0, 12 * sizeof(double) * (size_t)B, w->stream));
+  HIPCHECK(hipMemsetAsync(ip, 0, (4 * (size_t)B + 1) * sizeof(int), w->stream));
+  HIPCHECK(hipStreamSynchronize(w->stream));
   return w;
 }
 
@@ -1795,6 +1804,7 @@ struct Launcher {
         for (auto& g : w->graphs)
           if (g.first == gkey) ex = g.second;
         if (!ex) {
+          std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
           hipGraph_t gr = nullptr;
           HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
           try {
@@ -2300,7 +2310,13 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
 
 int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa) { return device_query_ws(H, D, qa, nullptr); }
 
+std::recursive_mutex& hip_global_mu() {
+  static std::recursive_mutex m;
+  return m;
+}
+
 void copy_to_caller(void* dst, const void* src, size_t bytes) {
+  std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
   if (is_device_ptr(dst))
     HIPCHECK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
   else
@@ -2338,8 +2354,12 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
       w = lease->w.get();
     }
     // work runs on the workspace's stream, ordered after the caller's stream
-    HIPCHECK(hipEventRecord(w->ev_in, st));
-    HIPCHECK(hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    {
+      std::unique_lock<std::recursive_mutex> lk(hip_global_mu(), std::defer_lock);
+      if (!st) lk.lock();  // the legacy stream
+      HIPCHECK(hipEventRecord(w->ev_in, st));
+      HIPCHECK(hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    }
     hipStream_t caller = st;
     st = w->stream;
     std::vector<ColResult> res;
@@ -2405,7 +2425,11 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
     HIPCHECK(hipStreamSynchronize(st));
     w->prof.harvest();
     HIPCHECK(hipEventRecord(w->ev_out, st));
-    HIPCHECK(hipStreamWaitEvent(caller, w->ev_out, 0));
+    {
+      std::unique_lock<std::recursive_mutex> lk(hip_global_mu(), std::defer_lock);
+      if (!caller) lk.lock();  // the legacy stream
+      HIPCHECK(hipStreamWaitEvent(caller, w->ev_out, 0));
+    }
     st = caller;
     HIPCHECK(hipGetLastError());
     for (int j = 0; j < B; j++) {
@@ -2523,7 +2547,10 @@ void device_lanczos_R(HostIndex& H, DeviceIndex* D) {
   std::vector<void*> tmp;
   struct Freer {
     std::vector<void*>& v;
-    ~Freer() { for (void* p : v) (void)hipFree(p); }
+    ~Freer() {
+      std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
+      for (void* p : v) (void)hipFree(p);
+    }
   } freer{tmp};
   double* Q = dalloc<double>(tmp, (int64_t)m * m2);
   double* wv = dalloc<double>(tmp, m2);
@@ -2629,8 +2656,11 @@ void device_lanczos_R(HostIndex& H, DeviceIndex* D) {
   HIPCHECK(hipStreamSynchronize(st));
   HIPCHECK(hipGetLastError());
   H.V = H.U;  // L = I
-  upload_factors(H, D);
-  HIPCHECK(hipDeviceSynchronize());
+  {
+    std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
+    upload_factors(H, D);
+    HIPCHECK(hipDeviceSynchronize());
+  }
   H.build_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 

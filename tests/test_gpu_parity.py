@@ -339,3 +339,40 @@ def test_sparse_katz_matches_oracle():
         ok, msg, _ = oracle.topk_accept(ids[i][:nf], ref["ids"][:nf], ref["rho"][:nf], nf, 1e-7)
         assert ok, msg
         assert np.array_equal(ids[i][nf:m], ref["ids"][nf:m])
+
+
+@pytest.mark.parametrize("own_streams", [True, False])
+def test_concurrent_queries_from_threads(own_streams):
+    # independent one-query solves from several host threads on a fresh index:
+    # workspace creation overlaps the HIP-graph capture of other threads'
+    # iteration chunks (>= 8 iterations per solve); results equal the
+    # sequential ones bit for bit
+    import threading
+    import torch
+    g = ki.workload("lnsbm4m", scale=0.002).graph
+    beta = oracle_beta(g, 0.9)
+    qs = ki.sample_queries(g, 24, 88)
+    ref_idx = K.KatzIndex.from_graph(g, beta=beta, rank=8, labels=g.labels, max_block=32)
+    ref = {int(q): ref_idx.query([q], tol=1e-11)[0][0] for q in qs}
+    assert all(s["iters"] >= 8 for s in ref_idx.query(qs[:4], tol=1e-11)[1])
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=8, labels=g.labels, max_block=32)
+    got, errs = {}, []
+
+    def worker(t):
+        try:
+            st = torch.cuda.Stream() if own_streams else None
+            for q in qs[t::6]:
+                out = torch.empty((1, g.n), dtype=torch.float64, device="cuda")
+                idx.query([q], out=out, tol=1e-11, stream=st.cuda_stream if st else None)
+                (st or torch.cuda.current_stream()).synchronize()
+                got[int(q)] = out.cpu().numpy()[0]
+        except Exception as e:
+            errs.append(repr(e))
+    ths = [threading.Thread(target=worker, args=(t,)) for t in range(6)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    assert not errs, errs[:2]
+    for q in qs:
+        assert np.array_equal(got[int(q)], ref[int(q)]), q
