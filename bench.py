@@ -246,6 +246,8 @@ def main():
         torch.cuda.synchronize()
 
     head = results["c=%g" % head_c]
+    copy_gbs = measured_copy_bandwidth(torch, dev)
+    log("measured device copy bandwidth: %.0f GB/s (read + write of a 1 GiB copy)" % copy_gbs)
     if kernel_table:
         dom = max(kernel_table, key=lambda r: r["total_ms"])
         wl = "cl1m" if args.scale == 1.0 else "cl1m_s%g" % args.scale
@@ -253,7 +255,10 @@ def main():
         roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["achieved_GBs"], 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4),
                     "traffic": traffic, "avg_launch_us": round(dom["avg_us"], 2),
-                    "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
+                    "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
+                    "measured_copy_GBs": round(copy_gbs, 1),
+                    "frac_of_measured_copy": round(dom["achieved_GBs"] / copy_gbs, 4),
+                    "traffic_GBs": round(traffic / (dom["avg_us"] * 1e-6) / 1e9, 1) if traffic else None}
     value = head["lrc"]["qps"]
     line = {
         "metric": "Katz queries/sec at 1e-6 rel. residual, LRC-Katz vs CG, 1 MI355X; p99 ms",
@@ -552,6 +557,26 @@ def run_serving(args):
             "p99_ms": round(head["load_0.8"]["p99_ms"], 3), "cg_qps": round(results["cg"]["saturation_qps"], 2),
             "roofline": None, "cpu_baseline": None, "results": results}
     print(json.dumps(line), flush=True)
+
+
+def measured_copy_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + written per second, GB/s) of
+    a plain 1 GiB copy, best of `reps`, timed with HIP events."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = 0.0
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        best = max(best, 2 * nbytes / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del x, y
+    torch.cuda.empty_cache()
+    return best
 
 
 def cpu_baseline(g, idx, queries, tol, out, stream, K):

@@ -455,9 +455,11 @@ __global__ __launch_bounds__(WG) void k_update_r_vt1(int64_t m, int rows_per_wg,
     r[i] = rv;
     const double rd = (double)rv;
     acc[RMAX] += rd * rd;
+    TV vv[RMAX];
 #pragma unroll
-    for (int k = 0; k < RMAX; k++)
-      if (k < rank) acc[k] += to_d(V[(int64_t)k * m + i]) * rd;
+    for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+#pragma unroll
+    for (int k = 0; k < RMAX; k++) acc[k] += to_d(vv[k]) * rd;
   }
   const int wave = tid / 64, lane = tid % 64;
 #pragma unroll
@@ -562,9 +564,22 @@ __global__ __launch_bounds__(WG) void k_m11_apply(M11Args<T> a) {
         gi = r0 + i;
         j = jc + jj;
         if (a.x2) {
-          for (int32_t k = a.split[gi] + sl; k < a.rp[gi + 1]; k += SUB) {
-            T xv = a.x2[(int64_t)(a.col[k] - a.n1) * B + j];
-            s += a.val ? (T)a.val[k] * xv : xv;
+          // four entries per lane in flight (indices past the row end clamped
+          // to its last entry, products masked); same order of the sums
+          const int32_t ke = a.rp[gi + 1];
+          for (int32_t k = a.split[gi] + sl; k < ke; k += 4 * SUB) {
+            int32_t c[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) c[q] = a.col[k + q * SUB < ke ? k + q * SUB : ke - 1];
+            T xv[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) xv[q] = a.x2[(int64_t)(c[q] - a.n1) * B + j];
+            __builtin_amdgcn_sched_barrier(0);  // keep the gathers together
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+              const int32_t kk = k + q * SUB;
+              if (kk < ke) s += a.val ? (T)a.val[kk] * xv[q] : xv[q];
+            }
           }
         }
       }
@@ -718,10 +733,16 @@ __global__ __launch_bounds__(WG) void k_vt1(int64_t m, int rank, const TV* V, co
 #pragma unroll
   for (int k = 0; k < RMAX; k++) acc[k] = 0.0;
   for (int64_t i = r0 + tid; i < r1; i += WG) {
-    const double rv = (double)r[i];
+    // all factor loads first, unconditionally (columns past the rank repeat
+    // the last one and their sums are never used), so they are in flight
+    // together instead of one latency each
+    TV vv[RMAX];
 #pragma unroll
-    for (int k = 0; k < RMAX; k++)
-      if (k < rank) acc[k] += to_d(V[(int64_t)k * m + i]) * rv;
+    for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+    const double rv = (double)r[i];
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the FMAs
+#pragma unroll
+    for (int k = 0; k < RMAX; k++) acc[k] += to_d(vv[k]) * rv;
   }
   const int wave = tid / 64, lane = tid % 64;
 #pragma unroll
@@ -764,6 +785,34 @@ __global__ __launch_bounds__(WG) void k_lowrank(int64_t m, int B, int rank, cons
       dacc[c] += (double)r[o] * (double)zv;
     }
   wg_colsum(cm, B, dacc, partials);
+}
+
+// One column (B = 1) of k_lowrank with the rank known at compile time (<=
+// RMAX): DW in registers (0 past the rank) and all factor loads of a row
+// issued together.  Same sums, same order.
+template <typename T, typename TV, int RMAX>
+__global__ __launch_bounds__(WG) void k_lowrank1(int64_t m, int rank, const TV* V, const double* DW, const T* r,
+                                                 T* z, int z_has_base, int rows_per_wg, const int* n_active,
+                                                 double* partials) {
+  if (n_active && *n_active == 0) return;
+  double dw[RMAX];
+#pragma unroll
+  for (int k = 0; k < RMAX; k++) dw[k] = k < rank ? DW[k] : 0.0;
+  double dacc[1] = {0.0};
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(m, r0 + rows_per_wg);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += WG) {
+    TV vv[RMAX];
+#pragma unroll
+    for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+    const double rv = (double)r[i];
+    double s = z_has_base ? (double)z[i] : rv;
+#pragma unroll
+    for (int k = 0; k < RMAX; k++) s += to_d(vv[k]) * dw[k];
+    const T zv = (T)s;
+    z[i] = zv;
+    dacc[0] += rv * (double)zv;
+  }
+  wg_colsum(colmap(1), 1, dacc, partials);
 }
 
 // ------------------------------------- low-rank products for B >= 2 columns
@@ -1259,6 +1308,7 @@ struct Tuning {
   int xcd;          // XCD-slab chunk order for the gathering kernels
   int graphs;       // replay captured iteration chunks as HIP graphs
   int fuse;         // one-column residual update fused with V^T r
+  int lr_nwg;       // max workgroups of the one-column low-rank kernels
 };
 static int env_int(const char* name, int dflt, int lo, int hi) {
   const char* e = getenv(name);
@@ -1277,6 +1327,7 @@ static const Tuning& tuning() {
     u.xcd = env_int("KATZ_XCD_SLAB", 0, 0, 1);
     u.graphs = env_int("KATZ_GRAPHS", 1, 0, 1);
     u.fuse = env_int("KATZ_FUSE", 0, 0, 1);
+    u.lr_nwg = env_int("KATZ_LR_NWG", 512, 64, 65536);
     return u;
   }();
   return t;
@@ -1959,6 +2010,14 @@ static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep,
     precond_rows<T, TV>(L, V, R2, Z2, ep, cs, nact);
     return;
   }
+  if (B == 1) {
+    // the one-column low-rank kernels amortize their per-workgroup rank-wide
+    // reduction over more rows than the update kernels do
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(tuning().lr_nwg, (m + 63) / 64));
+    rpw = (int)((m + want - 1) / want);
+    nwg = Launcher::nwg_for(m, rpw);
+    L.need(nwg, std::max(1, rk));
+  }
   if (rk > 0 && !dw_ready) {
     L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
       if (B == 1 && rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
@@ -1977,8 +2036,17 @@ static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep,
     has_base = 1;
   }
   L.timed(PK_LOWRANK, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m * (2 + has_base), [&] {
-    k_lowrank<T, TV><<<nwg, WG, WG * sizeof(double), st>>>(m, B, rk, V, w->DW, R2, Z2, has_base, rpw, nact,
-                                                           w->partials);
+    const size_t shm = WG * sizeof(double);
+    if (B == 1 && rk >= 1 && rk <= 8)
+      k_lowrank1<T, TV, 8><<<nwg, WG, shm, st>>>(m, rk, V, w->DW, R2, Z2, has_base, rpw, nact, w->partials);
+    else if (B == 1 && rk >= 1 && rk <= 16)
+      k_lowrank1<T, TV, 16><<<nwg, WG, shm, st>>>(m, rk, V, w->DW, R2, Z2, has_base, rpw, nact, w->partials);
+    else if (B == 1 && rk >= 1 && rk <= 32)
+      k_lowrank1<T, TV, 32><<<nwg, WG, shm, st>>>(m, rk, V, w->DW, R2, Z2, has_base, rpw, nact, w->partials);
+    else if (B == 1 && rk >= 1 && rk <= 64)
+      k_lowrank1<T, TV, 64><<<nwg, WG, shm, st>>>(m, rk, V, w->DW, R2, Z2, has_base, rpw, nact, w->partials);
+    else
+      k_lowrank<T, TV><<<nwg, WG, shm, st>>>(m, B, rk, V, w->DW, R2, Z2, has_base, rpw, nact, w->partials);
   });
   L.finalize(nwg, B, ep, cs, nullptr, nact);
 }
@@ -2465,10 +2533,14 @@ __global__ __launch_bounds__(WG) void k_qtw(int64_t m, int nv, const double* Q, 
 #pragma unroll
   for (int t = 0; t < kQT; t++) acc[t] = 0.0;
   for (int64_t i = r0 + tid; i < r1; i += WG) {
+    // unconditional loads (vectors past nv repeat the last; their sums are
+    // never used), in flight together
+    double qv[kQT];
+#pragma unroll
+    for (int t = 0; t < kQT; t++) qv[t] = Q[(int64_t)(k0 + t < nv ? k0 + t : nv - 1) * m + i];
     const double x = w[i];
 #pragma unroll
-    for (int t = 0; t < kQT; t++)
-      if (k0 + t < nv) acc[t] += Q[(int64_t)(k0 + t) * m + i] * x;
+    for (int t = 0; t < kQT; t++) acc[t] += qv[t] * x;
   }
   const int wave = tid / 64, lane = tid % 64;
 #pragma unroll
