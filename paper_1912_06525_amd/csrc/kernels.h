@@ -75,15 +75,15 @@ __device__ inline void recount_active(const ColState& cs, int B) {
 
 __device__ inline bool finite_pos(double x) { return x > 0.0 && x < 1.0e308; }
 
-// Last-workgroup reduction: sums partials[w * nv + v] over w < nwg for every
-// v < nv with all threads (lanes over v, then over w; fixed tree order, so the
-// result is deterministic) and calls f(v, sum) once per v.
-template <typename F>
+// One-workgroup reduction of NT threads: sums partials[w * nv + v] over
+// w < nwg for every v < nv with all threads (lanes over v, then over w; fixed
+// tree order, so the result is deterministic) and calls f(v, sum) once per v.
+template <int NT, typename F>
 __device__ inline void final_reduce(const double* partials, int nwg, int nv, F&& f) {
-  __shared__ double red[WG];
+  __shared__ double red[NT];
   int VC = 1;
-  while (VC < nv && VC < WG) VC <<= 1;
-  const int WR = WG / VC;
+  while (VC < nv && VC < NT) VC <<= 1;
+  const int WR = NT / VC;
   const int tid = threadIdx.x, vl = tid % VC, wl = tid / VC;
   for (int v0 = 0; v0 < nv; v0 += VC) {
     const int v = v0 + vl;

@@ -1112,10 +1112,13 @@ __global__ __launch_bounds__(WG) void k_lowrank_mfma(int64_t m, int B, int rank,
 //   EP_RR_INIT: rr, solve start                    EP_RR: rr, convergence / cap
 //   EP_RR_CG: as EP_RR plus bcg = rr_new / rz      EP_VT: DW = D o W
 //   EP_RZ_INIT: rz                                  EP_RZ: bcg = rz_new / rz
-__global__ __launch_bounds__(WG) void k_finalize(const double* partials, int nwg, int nv, int ep, ColState cs,
-                                                 int B, double* out, const double* D, const int* n_active) {
+// One workgroup of kFinWG threads: the partials are read kFinWG wide (fewer
+// dependent rounds than a 256-thread workgroup).
+constexpr int kFinWG = 1024;
+__global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int nwg, int nv, int ep, ColState cs,
+                                                     int B, double* out, const double* D, const int* n_active) {
   if (n_active && *n_active == 0) return;
-  final_reduce(partials, nwg, nv, [&](int j, double s) {
+  final_reduce<kFinWG>(partials, nwg, nv, [&](int j, double s) {
     switch (ep) {
       case EP_RES:
       case EP_NORM:
@@ -1775,7 +1778,7 @@ struct Launcher {
   // Reduces nwg x nv partials and applies the epilogue `ep` (one workgroup).
   void finalize(int nwg, int nv, int ep, const ColState& cs, double* out, const int* nact) {
     need(nwg, nv);
-    k_finalize<<<1, WG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact);
+    k_finalize<<<1, kFinWG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact);
   }
 
   template <typename T>
