@@ -102,12 +102,9 @@ struct SpmmArgs {
 
 // Accumulates lane (nz, cl)'s share of row i: entries kb+nz, kb+nz+NZ, ...
 // (four entries in flight per step).
-// Column groups per lane: B <= CW whenever CW < 64, so only the 64-wide
-// layout carries several column accumulators.
-template <int CW>
-struct ncm {
-  static constexpr int value = CW == 64 ? MAXC : 1;
-};
+// NCM: column groups per lane (CW = 64 takes B up to 64 * NCM; narrower
+// layouts have B <= CW and NCM = 1), a compile-time count so that every
+// gather of an entry is issued at once.
 
 // VAL: weighted graph (entry values in a.val).  A compile-time switch: a
 // runtime test between the loads makes the compiler wait for each one.
@@ -127,11 +124,22 @@ __device__ inline RowRange row_range(const SpmmArgs<T>& a, int i) {
   return r;
 }
 
-template <typename T, int CW, int NZ, bool VAL>
+template <typename T, int CW, int NZ, bool VAL, int NCM>
 __device__ inline void row_gather(const SpmmArgs<T>& a, const RowRange& rr, int nz, int cl, int NC, T* acc) {
   const int32_t kb = rr.kb, ke = rr.ke, sp = rr.sp;
   const int B = a.B;
-  constexpr int NCM = ncm<CW>::value;
+  // the lane's column in each group, clamped into [0, B) for a ragged last
+  // group: every gather is an in-bounds load issued unconditionally (so the
+  // loads of an entry are in flight together) and only the accumulation is
+  // masked
+  int jc[NCM];
+  bool jok[NCM];
+#pragma unroll
+  for (int cc = 0; cc < NCM; cc++) {
+    const int j = cl + CW * cc;
+    jok[cc] = cc < NC && j < B;
+    jc[cc] = j < B ? j : B - 1;
+  }
   int32_t k = kb + nz;
   for (; k + 3 * NZ < ke; k += 4 * NZ) {
     int32_t c[4];
@@ -143,14 +151,18 @@ __device__ inline void row_gather(const SpmmArgs<T>& a, const RowRange& rr, int 
       cf[u] = (kk < sp) ? a.ca : a.cb;
       if (VAL) cf[u] *= (T)a.val[kk];
     }
+    T xv[4][NCM];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
       const T* xr = a.x + (int64_t)c[u] * B;
 #pragma unroll
-      for (int cc = 0; cc < NCM; cc++) {
-        const int j = cl + CW * cc;
-        if (cc < NC && j < B) acc[cc] += cf[u] * xr[j];
-      }
+      for (int cc = 0; cc < NCM; cc++) xv[u][cc] = xr[jc[cc]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+#pragma unroll
+      for (int cc = 0; cc < NCM; cc++)
+        if (jok[cc]) acc[cc] += cf[u] * xv[u][cc];
     }
   }
   if (k < ke) {
@@ -169,15 +181,18 @@ __device__ inline void row_gather(const SpmmArgs<T>& a, const RowRange& rr, int 
       cf[u] = (kk < sp) ? a.ca : a.cb;
       if (VAL) cf[u] *= (T)a.val[kc];
     }
+    T xv[3][NCM];
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+      const T* xr = a.x + (int64_t)c[u] * B;
+#pragma unroll
+      for (int cc = 0; cc < NCM; cc++) xv[u][cc] = xr[jc[cc]];
+    }
 #pragma unroll
     for (int cc = 0; cc < NCM; cc++) {
-      const int j = cl + CW * cc;
-      if (cc < NC && j < B) {
-        T xv[3];
+      if (jok[cc]) {
 #pragma unroll
-        for (int u = 0; u < 3; u++) xv[u] = a.x[(int64_t)c[u] * B + j];
-#pragma unroll
-        for (int u = 0; u < 3; u++) acc[cc] += (k + u * NZ < ke) ? cf[u] * xv[u] : (T)0;
+        for (int u = 0; u < 3; u++) acc[cc] += (k + u * NZ < ke) ? cf[u] * xv[u][cc] : (T)0;
       }
     }
   }
@@ -186,15 +201,14 @@ __device__ inline void row_gather(const SpmmArgs<T>& a, const RowRange& rr, int 
 // Row-aligned operands of row i for the lane owning column group cl,
 // loaded before they are needed (for one accumulator per lane, at the start
 // of the row, so their latency overlaps the gather).
-template <typename T, int CW>
+template <typename T, int NCM>
 struct RowOps {
-  T v[ncm<CW>::value], w[ncm<CW>::value];
-  double d[ncm<CW>::value];
+  T v[NCM], w[NCM];
+  double d[NCM];
 };
-template <typename T, int CW>
-__device__ inline void row_load(const SpmmArgs<T>& a, int i, int cl, int NC, RowOps<T, CW>& p) {
+template <typename T, int CW, int NCM>
+__device__ inline void row_load(const SpmmArgs<T>& a, int i, int cl, int NC, RowOps<T, NCM>& p) {
   const int B = a.B;
-  constexpr int NCM = ncm<CW>::value;
   const int64_t ro = (int64_t)(i - a.row0) * B;
 #pragma unroll
   for (int cc = 0; cc < NCM; cc++) {
@@ -212,11 +226,10 @@ __device__ inline void row_load(const SpmmArgs<T>& a, int i, int cl, int NC, Row
 // Finishes row i for the lane owning column group cl: adds the row-aligned
 // operands, stores y and accumulates the dot (in place, y == v, is allowed:
 // the lane has loaded v before).
-template <typename T, int CW>
+template <typename T, int CW, int NCM>
 __device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, const T* acc,
-                                  const RowOps<T, CW>& p, double* dacc) {
+                                  const RowOps<T, NCM>& p, double* dacc) {
   const int B = a.B;
-  constexpr int NCM = ncm<CW>::value;
   const int64_t ro = (int64_t)(i - a.row0) * B;
 #pragma unroll
   for (int cc = 0; cc < NCM; cc++) {
@@ -234,13 +247,12 @@ __device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, c
   }
 }
 
-template <typename T, int TS, int CW, bool VAL>
+template <typename T, int TS, int CW, bool VAL, int NCM>
 __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
   if (a.n_active && *a.n_active == 0) return;
   constexpr int NZ = TS / CW;
   constexpr int TEAMS = WG / TS;
   constexpr int NZW = WG / CW;  // entry lanes of the long-row path
-  constexpr int NCM = ncm<CW>::value;
   extern __shared__ double sh[];
   const int tid = threadIdx.x;
   const int B = a.B;
@@ -255,12 +267,12 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
     // ---- one hub row, whole workgroup
     const int cl = tid % CW, nz = tid / CW;
     const int i = a.long_rows[blockIdx.x];
-    RowOps<T, CW> ops;
-    if (tid < CW) row_load<T, CW>(a, i, tid, NC, ops);
+    RowOps<T, NCM> ops;
+    if (tid < CW) row_load<T, CW, NCM>(a, i, tid, NC, ops);
     T acc[NCM];
 #pragma unroll
     for (int c = 0; c < NCM; c++) acc[c] = (T)0;
-    row_gather<T, CW, NZW, VAL>(a, row_range(a, i), nz, cl, NC, acc);
+    row_gather<T, CW, NZW, VAL, NCM>(a, row_range(a, i), nz, cl, NC, acc);
     // lanes of one wave sharing cl: xor over the wave; then across waves in LDS
 #pragma unroll
     for (int c = 0; c < NCM; c++) {
@@ -283,7 +295,7 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
           acc[c] = (T)t;
         }
       }
-      row_finish<T, CW>(a, i, tid, NC, acc, ops, dacc);
+      row_finish<T, CW, NCM>(a, i, tid, NC, acc, ops, dacc);
     }
     __syncthreads();
     owner = tid < CW;
@@ -298,22 +310,22 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
     for (int64_t ch = sl.first; ch < sl.end; ch += sl.stride)
     for (int i = a.row0 + (int)ch * a.rows_per_wg + team,
              rend = min<int64_t>(a.row1, a.row0 + (ch + 1) * a.rows_per_wg); i < rend; i += TEAMS) {
-      RowOps<T, CW> ops;
-      if (NCM == 1) row_load<T, CW>(a, i, cl, NC, ops);  // early: overlaps the row's other loads
+      RowOps<T, NCM> ops;
+      if (NCM == 1) row_load<T, CW, NCM>(a, i, cl, NC, ops);  // early: overlaps the row's other loads
       const RowRange rr = row_range(a, i);
       if (a.long_rows && rr.len > a.long_thr) continue;  // done by its own workgroup
       T acc[NCM];
 #pragma unroll
       for (int c = 0; c < NCM; c++) acc[c] = (T)0;
-      row_gather<T, CW, NZ, VAL>(a, rr, nz, cl, NC, acc);
+      row_gather<T, CW, NZ, VAL, NCM>(a, rr, nz, cl, NC, acc);
 #pragma unroll
       for (int c = 0; c < NCM; c++) {
 #pragma unroll
         for (int off = CW; off < TS; off <<= 1) acc[c] += __shfl_xor(acc[c], off, TS);
       }
       if (nz == 0) {
-        if (NCM > 1) row_load<T, CW>(a, i, cl, NC, ops);
-        row_finish<T, CW>(a, i, cl, NC, acc, ops, dacc);
+        if (NCM > 1) row_load<T, CW, NCM>(a, i, cl, NC, ops);
+        row_finish<T, CW, NCM>(a, i, cl, NC, acc, ops, dacc);
       }
     }
     owner = nz == 0;
@@ -1828,16 +1840,20 @@ struct Launcher {
     const int kind = sep ? (a.parts == 1 ? PK_SPMM_RHS : PK_SPMM_SEP) : PK_SPMM_FULL;
     auto launch = [&](const SpmmArgs<T>& aa, double by) {
       bool launched = false;
-#define KZ_SPMM(ts, cw)                                                                    \
-  if (!launched && TS == ts && CW == cw) {                                                 \
+      const int nc = (B + CW - 1) / CW;  // column groups per lane
+#define KZ_SPMM_N(ts, cw, ncm)                                                             \
+  if (!launched && TS == ts && CW == cw && (ncm == 1 || nc <= ncm)) {                      \
     timed(kind, by, [&] {                                                                  \
-      if (aa.val) k_spmm<T, ts, cw, true><<<g, WG, shm, st>>>(aa);                         \
-      else k_spmm<T, ts, cw, false><<<g, WG, shm, st>>>(aa);                               \
+      if (aa.val) k_spmm<T, ts, cw, true, ncm><<<g, WG, shm, st>>>(aa);                    \
+      else k_spmm<T, ts, cw, false, ncm><<<g, WG, shm, st>>>(aa);                          \
     });                                                                                    \
     launched = true;                                                                       \
   }
-      KZ_SPMM(4, 1) KZ_SPMM(8, 1) KZ_SPMM(16, 1) KZ_SPMM(32, 1) KZ_SPMM(8, 2) KZ_SPMM(16, 4) KZ_SPMM(32, 8) KZ_SPMM(64, 16) KZ_SPMM(64, 32) KZ_SPMM(64, 64)
-#undef KZ_SPMM
+      KZ_SPMM_N(4, 1, 1) KZ_SPMM_N(8, 1, 1) KZ_SPMM_N(16, 1, 1) KZ_SPMM_N(32, 1, 1) KZ_SPMM_N(8, 2, 1)
+      KZ_SPMM_N(16, 4, 1) KZ_SPMM_N(32, 8, 1) KZ_SPMM_N(64, 16, 1) KZ_SPMM_N(64, 32, 1)
+      KZ_SPMM_N(64, 64, 2) KZ_SPMM_N(64, 64, 4) KZ_SPMM_N(64, 64, 8)
+#undef KZ_SPMM_N
+      if (!launched) fail(KATZ_EDEVICE, "internal: no SpMM variant for this batch width");
     };
     launch(a, bytes);
     if (a.ep != EP_NONE) finalize(nwg_all, B, a.ep, a.cs, a.out, a.n_active);
