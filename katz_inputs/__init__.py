@@ -174,6 +174,23 @@ def from_edges(n: int, edges) -> Graph:
     return Graph(n, rp, v.astype(np.int32), None, "edges")
 
 
+def edge_weights(g: Graph, seed: int, lo: float = 0.25, hi: float = 2.0) -> np.ndarray:
+    """Positive FP64 weights for the CSR entries of g, one value per undirected
+    edge so that the weighted matrix stays symmetric: uniform in [lo, hi) from
+    the splitmix64 finaliser of (min(u, v) * n + max(u, v)) xor the seed."""
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), g.degrees())
+    c = g.col.astype(np.int64)
+    key = (np.minimum(rows, c) * np.int64(g.n) + np.maximum(rows, c)).astype(np.uint64)
+    with np.errstate(over="ignore"):
+        z = key ^ (np.uint64(seed) * np.uint64(0x9E3779B97F4A7C15))
+        z = z + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    u01 = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return lo + (hi - lo) * u01
+
+
 def sample_queries(g: Graph, k: int, seed: int) -> np.ndarray:
     """k distinct nodes of degree >= 1, uniform, seeded (draw order kept)."""
     lib = _load()

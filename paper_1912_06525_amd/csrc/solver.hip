@@ -124,8 +124,9 @@ __device__ inline RowRange row_range(const SpmmArgs<T>& a, int i) {
   return r;
 }
 
-template <typename T, int CW, int NZ, bool VAL, int NCM>
-__device__ inline void row_gather(const SpmmArgs<T>& a, const RowRange& rr, int nz, int cl, int NC, T* acc) {
+// Args: any argument struct with col, val, x, B, ca and cb.
+template <typename T, int CW, int NZ, bool VAL, int NCM, typename Args>
+__device__ inline void row_gather(const Args& a, const RowRange& rr, int nz, int cl, int NC, T* acc) {
   const int32_t kb = rr.kb, ke = rr.ke, sp = rr.sp;
   const int B = a.B;
   // the lane's column in each group, clamped into [0, B) for a ragged last
@@ -552,6 +553,7 @@ struct M11Args {
   T* out;
   int B, CB, sub, xcd;
   const int* n_active;
+  const int32_t* tile_row1;  // k_m11_cols: tile ends when tiles are not adjacent (NULL: tile_row0[t + 1])
 };
 
 template <typename T>
@@ -629,7 +631,8 @@ __global__ __launch_bounds__(WG) void k_m11_cols(M11Args<T> a) {
   extern __shared__ unsigned char smem[];
   T* u = reinterpret_cast<T*>(smem);  // tile rows x CBW
   constexpr int RPG = WG / CBW;       // rows in flight per workgroup
-  const int r0 = a.tile_row0[blockIdx.x], r1 = a.tile_row0[blockIdx.x + 1], R = r1 - r0;
+  const int r0 = a.tile_row0[blockIdx.x];
+  const int r1 = a.tile_row1 ? a.tile_row1[blockIdx.x] : a.tile_row0[blockIdx.x + 1], R = r1 - r0;
   const int B = a.B;
   const int lane = threadIdx.x % CBW, rs = threadIdx.x / CBW;
   const int j = blockIdx.y * CBW + lane;
@@ -677,6 +680,112 @@ __global__ __launch_bounds__(WG) void k_m11_cols(M11Args<T> a) {
     }
     for (; k < bsz; k++) s0 += mi[k] * ub[k * CBW];
     if (ok) a.out[(int64_t)gi * B + j] = (s0 + s1) + (s2 + s3);
+  }
+}
+
+// Block solve for blocks of at most S rows and B > 32 columns.  A wave takes
+// consecutive blocks (chunks of blocks_per_chunk, in XCD slabs) and all
+// columns, 64 * NCM of them per wave, lane = column within each group.  For
+// each block the lane keeps the block's rows of
+//   u = ca (A12 x2) + cv v
+// in registers (the A12 part is the SpMM row gather over the entries right of
+// the split, summed with weight 1 and scaled by ca after), then writes
+// out = Minv_b u with row i of the symmetric block inverse read at
+// wave-uniform addresses.  No LDS and no per-row index chain: blocks are
+// almost all 1-4 rows, so this is an SpMM over the A12 rows with a tiny
+// epilogue.  Blocks with more than S rows are skipped here and solved by
+// k_m11_cols over tiles of their own.
+template <typename T>
+struct M11SmallArgs {
+  const int32_t* blk_start;
+  const int64_t* blk_off;
+  const T* minv;
+  const int32_t* rp;
+  const int32_t* col;
+  const int32_t* split;
+  const double* val;
+  const T* x;  // full n-row panel whose rows >= n1 are x2 (NULL: no A12 term)
+  T ca, cb;    // row_gather coefficients: ca unused (no entries left of the split), cb = 1
+  T cu;        // scale of the A12 sum
+  const T* v;
+  T cv;
+  T* out;
+  int B, nblocks, blocks_per_chunk, xcd;
+  int64_t nchunks;
+  const int* n_active;
+};
+
+template <typename T, int NCM, int S, bool VAL>
+__global__ __launch_bounds__(WG) void k_m11_small(M11SmallArgs<T> a) {
+  if (a.n_active && *a.n_active == 0) return;
+  constexpr int CW = 64, TEAMS = WG / 64;
+  const int team = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64), cl = (int)threadIdx.x % 64;
+  const int B = a.B, NC = (B + CW - 1) / CW;
+  int jc[NCM];
+  bool jok[NCM];
+#pragma unroll
+  for (int cc = 0; cc < NCM; cc++) {
+    const int j = cl + CW * cc;
+    jok[cc] = cc < NC && j < B;
+    jc[cc] = j < B ? j : B - 1;
+  }
+  const Slab sl = a.xcd ? xcd_slab((int)blockIdx.x, (int)gridDim.x, a.nchunks)
+                        : contiguous_slab((int)blockIdx.x, (int)gridDim.x, a.nchunks);
+  for (int64_t ch = sl.first; ch < sl.end; ch += sl.stride) {
+    const int bend = (int)min<int64_t>(a.nblocks, (ch + 1) * a.blocks_per_chunk);
+    for (int b = (int)(ch * a.blocks_per_chunk) + team; b < bend; b += TEAMS) {
+      const int bs = __builtin_amdgcn_readfirstlane(a.blk_start[b]);
+      const int bsz = __builtin_amdgcn_readfirstlane(a.blk_start[b + 1]) - bs;
+      if (bsz > S) continue;
+      const T* mi = a.minv + a.blk_off[b];
+      T u[S][NCM];
+#pragma unroll
+      for (int k = 0; k < S; k++) {
+        if (k < bsz) {
+          const int gi = bs + k;
+          const int64_t ro = (int64_t)gi * B;
+          T vv[NCM], acc[NCM];
+#pragma unroll
+          for (int cc = 0; cc < NCM; cc++) vv[cc] = acc[cc] = (T)0;
+          if (a.v) {  // one uniform branch: the row's loads issued together
+#pragma unroll
+            for (int cc = 0; cc < NCM; cc++) vv[cc] = a.v[ro + jc[cc]];
+          }
+          if (a.x) {
+            RowRange rr;
+            rr.kb = rr.sp = a.split[gi];
+            rr.ke = a.rp[gi + 1];
+            rr.len = rr.ke - rr.kb;
+            row_gather<T, CW, 1, VAL, NCM>(a, rr, 0, cl, NC, acc);
+          }
+#pragma unroll
+          for (int cc = 0; cc < NCM; cc++) u[k][cc] = a.cu * acc[cc] + a.cv * vv[cc];
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < NCM; cc++) u[k][cc] = (T)0;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < S; i++) {
+        if (i < bsz) {
+          // row i of the inverse: every load issued (index clamped into the
+          // row), entries past the block masked to 0
+          T m[S];
+#pragma unroll
+          for (int k = 0; k < S; k++) m[k] = mi[i * bsz + (k < bsz ? k : bsz - 1)];
+#pragma unroll
+          for (int k = 0; k < S; k++) m[k] = k < bsz ? m[k] : (T)0;
+          const int64_t ro = (int64_t)(bs + i) * B;
+#pragma unroll
+          for (int cc = 0; cc < NCM; cc++) {
+            T o = m[0] * u[0][cc];
+#pragma unroll
+            for (int k = 1; k < S; k++) o += m[k] * u[k][cc];
+            if (jok[cc]) a.out[ro + cl + CW * cc] = o;
+          }
+        }
+      }
+    }
   }
 }
 
@@ -1255,10 +1364,10 @@ __global__ void k_unpermute(int n, int B, const T* K, const int32_t* perm, doubl
 // kernels on the solve stream, harvested at the solver's host sync points,
 // plus the algorithmic bytes each launch moves (formulas next to the launches).
 enum ProfKind { PK_SPMM_SEP = 0, PK_SPMM_FULL, PK_M11, PK_VT, PK_LOWRANK, PK_UPDATE_R, PK_UPDATE_P, PK_TOPK,
-                PK_OTHER, PK_SPMM_RHS, PK_COUNT };
+                PK_OTHER, PK_SPMM_RHS, PK_M11_BIG, PK_COUNT };
 static const char* kProfNames[PK_COUNT] = {"spmm_separator_rows", "spmm_all_rows", "m11_block_apply",
                                            "lowrank_vt", "lowrank_apply", "update_r", "update_p", "topk_select",
-                                           "other", "spmm_schur_rhs"};
+                                           "other", "spmm_schur_rhs", "m11_big_blocks"};
 struct ProfTable {
   std::mutex mu;
   int64_t launches[PK_COUNT] = {};
@@ -1324,6 +1433,7 @@ struct Tuning {
   int graphs;       // replay captured iteration chunks as HIP graphs
   int fuse;         // one-column residual update fused with V^T r
   int lr_nwg;       // max workgroups of the one-column low-rank kernels
+  int m11_bpt;      // blocks per team and chunk of the batched small-block solve
 };
 static int env_int(const char* name, int dflt, int lo, int hi) {
   const char* e = getenv(name);
@@ -1343,6 +1453,7 @@ static const Tuning& tuning() {
     u.graphs = env_int("KATZ_GRAPHS", 1, 0, 1);
     u.fuse = env_int("KATZ_FUSE", 0, 0, 1);
     u.lr_nwg = env_int("KATZ_LR_NWG", 512, 64, 65536);
+    u.m11_bpt = env_int("KATZ_M11_BLOCKS_PER_TEAM", 1, 1, 64);
     return u;
   }();
   return t;
@@ -1394,6 +1505,10 @@ struct DeviceIndex {
   double* val = nullptr;
   int32_t *tile_row0 = nullptr, *row_blk = nullptr, *blk_start = nullptr;
   int64_t* blk_off = nullptr;
+  // blocks with more than kSmallBlock rows: one tile each, [big_row0, big_row1)
+  int32_t *big_row0 = nullptr, *big_row1 = nullptr;
+  int n_big = 0, max_big_rows = 0;
+  int64_t big_rows = 0;
   double* minv = nullptr;
   double* ginv = nullptr;
   double* V = nullptr;
@@ -1417,6 +1532,8 @@ struct DeviceIndex {
   int n_long_sep = 0, n_long_all = 0;
 };
 constexpr int kLongRow = 256;
+// Batched block solves keep a block's rows in registers up to this size.
+constexpr int kSmallBlock = 4;
 
 namespace {
 
@@ -1571,6 +1688,22 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
     D->row_blk = upload(D->allocs, row_blk, by);
     D->blk_start = upload(D->allocs, H.blk_start, by);
     D->blk_off = upload(D->allocs, H.blk_off, by);
+    {
+      std::vector<int32_t> b0, b1;
+      for (int b = 0; b < nb; b++) {
+        const int32_t sz = H.blk_start[b + 1] - H.blk_start[b];
+        if (sz <= kSmallBlock) continue;
+        b0.push_back(H.blk_start[b]);
+        b1.push_back(H.blk_start[b + 1]);
+        D->max_big_rows = std::max(D->max_big_rows, (int)sz);
+        D->big_rows += sz;
+      }
+      D->n_big = (int)b0.size();
+      if (D->n_big) {
+        D->big_row0 = upload(D->allocs, b0, by);
+        D->big_row1 = upload(D->allocs, b1, by);
+      }
+    }
     int64_t fb0 = D->bytes;
     D->minv = upload(D->allocs, H.minv, by);
     D->factor_bytes = D->bytes - fb0;
@@ -2117,6 +2250,7 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     a.minv = Factors<T>::minv(D); a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val; a.n1 = n1;
     a.v = v; a.cv = cv; a.x2 = x2; a.ca = ca; a.out = out; a.B = B; a.n_active = nact;
     a.xcd = tuning().xcd;
+    a.tile_row1 = nullptr;
     int cb = std::max(1, std::min(B, (int)(32768 / sizeof(T) / std::max(1, D->max_tile_rows))));
     a.CB = cb;
     a.sub = cb >= 16 ? 1 : (cb >= 4 ? 2 : 4);
@@ -2124,7 +2258,47 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     const double wb = (double)sizeof(T) * B;
     double bytes = (double)sizeof(T) * D->minv_elems + 4.0 * n1 + wb * n1 + (v ? wb * n1 : 0.0) +
                    (x2 ? 8.0 * n1 + 4.0 * D->nnz_a12 + wb * D->cols_a12 : 0.0);
-    if (B >= 16) {
+    if (B > 32) {
+      if (B > 512) fail(KATZ_EINVAL, "batch too wide for one launch");
+      // blocks of <= kSmallBlock rows in registers; larger ones by the tile
+      // kernel below (bytes split by row share)
+      const Tuning& tu = tuning();
+      M11SmallArgs<T> s;
+      s.blk_start = D->blk_start; s.blk_off = D->blk_off; s.minv = a.minv;
+      s.rp = D->rp; s.col = D->col; s.split = D->split; s.val = D->val;
+      s.x = x2 ? x2 - (int64_t)n1 * B : nullptr;  // x2 is rows >= n1 of a full panel
+      s.ca = (T)0; s.cb = (T)1; s.cu = ca; s.v = v; s.cv = cv; s.out = out;
+      s.B = B; s.nblocks = D->nblocks; s.blocks_per_chunk = (WG / 64) * tu.m11_bpt; s.xcd = tu.xcd;
+      s.nchunks = (D->nblocks + s.blocks_per_chunk - 1) / s.blocks_per_chunk;
+      s.n_active = nact;
+      const dim3 g((unsigned)std::min<int64_t>(tu.spmm_nwg, s.nchunks));
+      const double fb = n1 > 0 ? (double)D->big_rows / n1 : 0.0;
+      L.timed(PK_M11, bytes * (1.0 - fb), [&] {
+        const bool wv = s.val != nullptr;
+#define KZ_M11S(ncm)                                                                        \
+  if (wv) k_m11_small<T, ncm, kSmallBlock, true><<<g, WG, 0, st>>>(s);                      \
+  else k_m11_small<T, ncm, kSmallBlock, false><<<g, WG, 0, st>>>(s);
+        if (B <= 64) { KZ_M11S(1) } else if (B <= 128) { KZ_M11S(2) } else if (B <= 256) { KZ_M11S(4) }
+        else { KZ_M11S(8) }
+#undef KZ_M11S
+      });
+      if (D->n_big > 0) {
+        a.tile_row0 = D->big_row0;
+        a.tile_row1 = D->big_row1;
+        const int cbw = sizeof(T) == 8 ? 32 : 64;
+        const size_t shm2 = (size_t)D->max_big_rows * cbw * sizeof(T);
+        if (shm2 > 65536) fail(KATZ_EDEVICE, "internal: block too large for LDS");
+        const dim3 gb((unsigned)D->n_big, (unsigned)((B + cbw - 1) / cbw));
+        L.timed(PK_M11_BIG, bytes * fb, [&] {
+          const bool wv = a.val != nullptr;
+          if (cbw == 32) {
+            if (wv) k_m11_cols<T, 32, true><<<gb, WG, shm2, st>>>(a); else k_m11_cols<T, 32, false><<<gb, WG, shm2, st>>>(a);
+          } else {
+            if (wv) k_m11_cols<T, 64, true><<<gb, WG, shm2, st>>>(a); else k_m11_cols<T, 64, false><<<gb, WG, shm2, st>>>(a);
+          }
+        });
+      }
+    } else if (B >= 16) {
       // column-chunked kernel: 64 KB of LDS per workgroup at most
       const int cbw = sizeof(T) == 8 ? (B <= 16 ? 16 : 32) : (B <= 16 ? 16 : (B <= 32 ? 32 : 64));
       const size_t shm2 = (size_t)D->max_tile_rows * cbw * sizeof(T);
@@ -2692,6 +2866,7 @@ void device_lanczos_R(HostIndex& H, DeviceIndex* D) {
       a.xcd = 0;
       a.CB = 1;
       a.sub = 4;
+      a.tile_row1 = nullptr;
       const size_t shm = (size_t)D->max_tile_rows * sizeof(double);
       k_m11_apply<double><<<D->ntiles, WG, shm, st>>>(a);
     }

@@ -376,3 +376,30 @@ def test_concurrent_queries_from_threads(own_streams):
     assert not errs, errs[:2]
     for q in qs:
         assert np.array_equal(got[int(q)], ref[int(q)]), q
+
+
+@pytest.mark.parametrize("prec", [K.KATZ_PREC_FP64, K.KATZ_PREC_MIXED])
+@pytest.mark.parametrize("B", [1, 8, 40, 130])
+def test_weighted_graph_matches_oracle(prec, B):
+    # weighted adjacency (every kernel's weighted variant): one column, the
+    # narrow and the 64-wide SpMM layouts, and blocks larger than the batched
+    # block solve keeps in registers (tile kernel beside it)
+    g = ki.workload("lnsbm4m", scale=0.002).graph
+    val = ki.edge_weights(g, seed=3)
+    A = oracle.csr_matrix(g.n, g.row_ptr, g.col, val)
+    beta = 0.7 / oracle.lambda_max(A)
+    idx = K.KatzIndex.from_graph(g, val=val, beta=beta, rank=8, labels=g.labels, max_block=32, precision=prec)
+    _, bp = idx.partition()
+    assert np.diff(bp).max() > 4
+    qs = ki.sample_queries(g, B, 17)
+    tau = 1e-6
+    c = idx.info.c
+    tol = tau * (1 - c) / (1 + c)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta, val=val, validate=False)["k"]
+    for method in (K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG):
+        sc, st = idx.query(qs, tol=tol, method=method)
+        res = oracle.katz_residual(A, beta, qs, sc.T)
+        for j, q in enumerate(qs):
+            assert st[j]["status"] == 0, st[j]
+            _accept(sc[j], ref[:, j], tau, "method %d q=%d" % (method, q))
+            assert res[j] <= 1.05 * tol + 1e-15, (res[j], tol)
