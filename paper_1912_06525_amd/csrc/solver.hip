@@ -211,38 +211,61 @@ template <typename T, int CW, int NCM>
 __device__ inline void row_load(const SpmmArgs<T>& a, int i, int cl, int NC, RowOps<T, NCM>& p) {
   const int B = a.B;
   const int64_t ro = (int64_t)(i - a.row0) * B;
+  // clamped columns (a ragged last group reads column B - 1, unused): one
+  // uniform branch per operand with all of its loads, none per column group,
+  // so the loads are in flight together and no later store waits on them
+  int jc[NCM];
 #pragma unroll
   for (int cc = 0; cc < NCM; cc++) {
     const int j = cl + CW * cc;
+    jc[cc] = j < B ? j : B - 1;
     p.v[cc] = p.w[cc] = (T)0;
     p.d[cc] = 0.0;
-    if (cc < NC && j < B) {
-      if (a.v) p.v[cc] = a.v[ro + j];
-      if (a.w) p.w[cc] = a.w[ro + j];
-      if (a.ep != EP_NONE && a.dotv) p.d[cc] = (double)a.dotv[ro + j];
+  }
+  (void)NC;
+  if (a.v) {
+#pragma unroll
+    for (int cc = 0; cc < NCM; cc++) p.v[cc] = a.v[ro + jc[cc]];
+  }
+  if (a.w) {
+#pragma unroll
+    for (int cc = 0; cc < NCM; cc++) p.w[cc] = a.w[ro + jc[cc]];
+  }
+  if (a.ep != EP_NONE && a.dotv) {
+    if (a.dotv == a.v) {
+#pragma unroll
+      for (int cc = 0; cc < NCM; cc++) p.d[cc] = (double)p.v[cc];
+    } else {
+#pragma unroll
+      for (int cc = 0; cc < NCM; cc++) p.d[cc] = (double)a.dotv[ro + jc[cc]];
     }
   }
 }
 
 // Finishes row i for the lane owning column group cl: adds the row-aligned
 // operands, stores y and accumulates the dot (in place, y == v, is allowed:
-// the lane has loaded v before).
+// the lane has loaded v before).  Every group's value is formed before the
+// first store.
 template <typename T, int CW, int NCM>
 __device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, const T* acc,
                                   const RowOps<T, NCM>& p, double* dacc) {
   const int B = a.B;
   const int64_t ro = (int64_t)(i - a.row0) * B;
+  T yv[NCM];
+#pragma unroll
+  for (int cc = 0; cc < NCM; cc++) {
+    yv[cc] = acc[cc];
+    if (a.v) yv[cc] += a.cv * p.v[cc];
+    if (a.w) yv[cc] += a.cw * p.w[cc];
+  }
 #pragma unroll
   for (int cc = 0; cc < NCM; cc++) {
     const int j = cl + CW * cc;
     if (cc < NC && j < B) {
-      T yv = acc[cc];
-      if (a.v) yv += a.cv * p.v[cc];
-      if (a.w) yv += a.cw * p.w[cc];
-      a.y[ro + j] = yv;
+      a.y[ro + j] = yv[cc];
       if (a.ep != EP_NONE) {
-        double d = a.dotv ? p.d[cc] : (double)yv;
-        dacc[cc] += d * (double)yv;
+        double d = a.dotv ? p.d[cc] : (double)yv[cc];
+        dacc[cc] += d * (double)yv[cc];
       }
     }
   }
@@ -312,7 +335,9 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
     for (int i = a.row0 + (int)ch * a.rows_per_wg + team,
              rend = min<int64_t>(a.row1, a.row0 + (ch + 1) * a.rows_per_wg); i < rend; i += TEAMS) {
       RowOps<T, NCM> ops;
-      if (NCM == 1) row_load<T, CW, NCM>(a, i, cl, NC, ops);  // early: overlaps the row's other loads
+      // one column group: row operands early, overlapping the gather (wider
+      // lanes load them after it; loading them early measured no faster)
+      if (NCM == 1) row_load<T, CW, NCM>(a, i, cl, NC, ops);
       const RowRange rr = row_range(a, i);
       if (a.long_rows && rr.len > a.long_thr) continue;  // done by its own workgroup
       T acc[NCM];
