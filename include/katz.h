@@ -96,10 +96,15 @@ typedef struct {
   int32_t lanczos_steps;  /* 0: max(2r, r + 20) */
   int32_t order;          /* enum katz_order: node order inside the two parts */
   int32_t u_precision;    /* storage of the low-rank factor V on the device:
-                             0 auto (FP32 on the FP64 path, BF16 on the mixed
-                             path), 1 FP64, 2 FP32, 3 BF16.  The preconditioner is a
-                             fixed SPD operator either way, so the solution's
-                             accuracy does not depend on it. */
+                             0 auto, 1 FP64, 2 FP32, 3 BF16 (FP64 path; the
+                             mixed path always stores BF16).  Auto takes BF16
+                             when every weight D_i = sigma_i / (1 - sigma_i) of
+                             the correction is at most 16, else FP32: the
+                             preconditioner's error from rounding V grows like
+                             D_max times the storage precision.  The
+                             preconditioner is a fixed symmetric operator either
+                             way, so the solution's accuracy does not depend on
+                             it, only the iteration count. */
 } katz_build_opts;
 
 typedef struct {
@@ -134,10 +139,13 @@ typedef struct {
   int32_t device;          /* -1 for a host-only index */
   double beta, lambda_max, c;
   double sigma_max;        /* largest kept eigenvalue of R (0 if r = 0) */
-  double sigma_next;       /* Ritz estimate of sigma_{r+1} (0 if unknown) */
+  double sigma_next;       /* Ritz value r+1 of the Lanczos run: a lower bound
+                              of sigma_{r+1} (interlacing), tight only when the
+                              run has converged that far (0 if unknown) */
   int64_t factor_bytes;    /* M11 block inverses as stored on the device */
   int64_t device_bytes;    /* total resident index bytes on the device */
   double build_seconds;
+  int32_t u_precision;     /* storage of V as resolved (1 FP64, 2 FP32, 3 BF16) */
 } katz_index_info_t;
 
 /* Sets the documented defaults. */

@@ -345,6 +345,7 @@ int katz_index_info(const katz_index* idx, katz_index_info_t* info) {
   info->factor_bytes = idx->dev ? katz::device_factor_bytes(idx->dev) : (int64_t)H.minv.size() * 8;
   info->device_bytes = katz::device_bytes(idx->dev);
   info->build_seconds = H.build_seconds;
+  info->u_precision = H.u_precision;
   return KATZ_OK;
 }
 

@@ -713,6 +713,9 @@ void lanczos_normals(uint64_t& state, double* out, int64_t n) {
   state = rng.s;
 }
 
+// Largest correction weight D_i for which auto stores V in BF16.
+constexpr double kBf16MaxWeight = 16.0;
+
 std::vector<double> lanczos_ritz(HostIndex& H, const std::vector<double>& al, const std::vector<double>& be,
                                  int32_t r) {
   const int32_t mm = (int32_t)al.size();
@@ -736,6 +739,12 @@ std::vector<double> lanczos_ritz(HostIndex& H, const std::vector<double>& al, co
   }
   H.sigma_next = mm > r ? d[idx[r]] : 0.0;
   H.lanczos_steps = mm;
+  if (H.u_precision_req == 0) {
+    // auto storage of V: BF16 unless a large weight would amplify its rounding
+    double dmax = 0.0;
+    for (double x : H.D) dmax = std::max(dmax, std::fabs(x));
+    H.u_precision = dmax <= kBf16MaxWeight ? 3 : 2;
+  }
   return zr;
 }
 
@@ -775,7 +784,8 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
   H.nnz = nnz;
   H.weighted = val != nullptr;
   H.precision = o.precision;
-  H.u_precision = o.u_precision == 0 ? 2 : o.u_precision;
+  H.u_precision_req = o.u_precision;
+  H.u_precision = o.u_precision == 0 ? 2 : o.u_precision;  // auto: settled in lanczos_ritz
   H.lambda_max = lambda_max(n, row_ptr, col, val, o.seed);
   if (o.beta > 0) {
     H.beta = o.beta;

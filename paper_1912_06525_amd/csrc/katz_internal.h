@@ -52,7 +52,8 @@ struct HostIndex {
   int32_t lanczos_rank = 0, lanczos_steps_req = 0;  // a deferred Lanczos run
   uint64_t lanczos_seed = 0;
   int32_t precision = KATZ_PREC_FP64;
-  int32_t u_precision = 0;  // resolved: 1 FP64, 2 FP32 (FP64 path); BF16 on the mixed path
+  int32_t u_precision = 0;  // resolved: 1 FP64, 2 FP32, 3 BF16 (FP64 path); BF16 on the mixed path
+  int32_t u_precision_req = 0;  // as requested (0: auto, resolved once the Ritz values are known)
   double build_seconds = 0;
 };
 

@@ -153,7 +153,23 @@ def test_error_codes():
 # ------------------------------------------------------------ index files
 def _info_tuple(info):
     return (info.n, info.n1, info.n2, info.nnz, info.nblocks, info.max_block_size, info.rank, info.l_kind,
-            info.precision, info.beta, info.lambda_max, info.c, info.sigma_max, info.sigma_next)
+            info.precision, info.beta, info.lambda_max, info.c, info.sigma_max, info.sigma_next, info.u_precision)
+
+
+@pytest.mark.parametrize("c,req", [(0.5, 0), (0.995, 0), (0.5, 2), (0.995, 3), (0.5, 1)])
+def test_lowrank_storage_resolution(c, req):
+    # auto (0): BF16 (3) when every weight sigma / (1 - sigma) <= 16, else
+    # FP32 (2); an explicit request is kept as given
+    g = ki.chung_lu(3000, 2.5, 8.0, seed=4)
+    idx = K.KatzIndex.from_graph(g, beta=oracle_beta(g, c), rank=6, device=-1, u_precision=req)
+    _, s = idx.lowrank()
+    dmax = np.max(np.abs(s / (1 - s)))
+    if req:
+        assert idx.info.u_precision == req
+    else:
+        assert idx.info.u_precision == (3 if dmax <= 16 else 2), (dmax, idx.info.u_precision)
+    if c > 0.99:
+        assert dmax > 16   # the case exercises the FP32 branch
 
 
 def test_index_file_round_trip(tmp_path):
