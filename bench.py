@@ -312,6 +312,14 @@ def run_batched(args):
     rank = args.rank if args.rank != 32 else w.rank
     tol = w.tol
     queries = ki.sample_queries(g, B * (args.steps + args.warmup), 3003)
+    if args.copy_calib:
+        # plain 1 GiB copies: the reference that scales the PMC byte counters
+        x = torch.empty(2 ** 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     out = torch.empty((B, g.n), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
     results = {}
@@ -361,6 +369,7 @@ def run_batched(args):
                 for r in tab:
                     r["avg_us"] = 1e3 * r["total_ms"] / r["launches"]
                     r["achieved_GBs"] = r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
+                    r["alg_bytes_per_launch"] = r["alg_bytes"] / r["launches"]
                     log("    %-22s %5d x %9.1f us  %8.1f GB/s" % (r["name"], r["launches"], r["avg_us"],
                                                                 r["achieved_GBs"]))
                 entry[name]["kernels"] = tab
@@ -372,9 +381,13 @@ def run_batched(args):
     roofline = None
     if kernel_table:
         dom = max(kernel_table, key=lambda r: r["total_ms"])
+        wl = args.workload if args.scale == 1.0 else "%s_s%g" % (args.workload, args.scale)
+        traffic = load_traffic(dom["name"], "%s_b%d_c%g" % (wl, B, cs[0]), dom["alg_bytes_per_launch"])
         roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["achieved_GBs"], 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                    "traffic": None, "avg_launch_us": round(dom["avg_us"], 2)}
+                    "traffic": traffic, "avg_launch_us": round(dom["avg_us"], 2),
+                    "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
+                    "traffic_GBs": round(traffic / (dom["avg_us"] * 1e-6) / 1e9, 1) if traffic else None}
     line = {"metric": "Katz queries/sec at 1e-6 rel. residual, LRC-Katz vs CG, 1 MI355X; p99 ms",
             "value": round(head["lrc"]["qps"], 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(head["lrc"]["ms_per_batch"], 3),

@@ -19,8 +19,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <atomic>
+#include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <type_traits>
@@ -1459,6 +1463,7 @@ struct Tuning {
   int fuse;         // one-column residual update fused with V^T r
   int lr_nwg;       // max workgroups of the one-column low-rank kernels
   int m11_bpt;      // blocks per team and chunk of the batched small-block solve
+  int autotune;     // tune the SpMM chunk walk per index (off when pinned by the environment)
 };
 static int env_int(const char* name, int dflt, int lo, int hi) {
   const char* e = getenv(name);
@@ -1479,9 +1484,34 @@ static const Tuning& tuning() {
     u.fuse = env_int("KATZ_FUSE", 0, 0, 1);
     u.lr_nwg = env_int("KATZ_LR_NWG", 512, 64, 65536);
     u.m11_bpt = env_int("KATZ_M11_BLOCKS_PER_TEAM", 1, 1, 64);
+    u.autotune = env_int("KATZ_AUTOTUNE", 1, 0, 1) && !getenv("KATZ_XCD_SLAB") && !getenv("KATZ_SPMM_NWG");
     return u;
   }();
   return t;
+}
+
+// SpMM chunk walk, packed as xcd << 24 | workgroups (at most 65536).
+inline int32_t walk_pack(int xcd, int nwg) { return (int32_t)((xcd ? 1 : 0) << 24 | (nwg & 0xffffff)); }
+inline int walk_xcd(int32_t w) { return (w >> 24) & 1; }
+inline int walk_nwg(int32_t w) { return w & 0xffffff; }
+// SpMM variants x panel precisions x weights (Launcher::spmm_variant).
+constexpr int kWalkSlots = 12 * 2 * 2;
+// Tuned walks of this process by graph shape (n, nnz, n1) and variant slot.
+struct WalkKey {
+  int64_t n, nnz, n1;
+  int slot;
+  bool operator<(const WalkKey& o) const {
+    return std::tie(n, nnz, n1, slot) < std::tie(o.n, o.nnz, o.n1, o.slot);
+  }
+};
+static std::map<WalkKey, int32_t>& walk_cache() {
+  static std::map<WalkKey, int32_t> m;
+  return m;
+}
+// Held while tuning; taken before hip_global_mu, never while holding it.
+static std::mutex& walk_mu() {
+  static std::mutex m;
+  return m;
 }
 
 // ============================================================= device index
@@ -1555,6 +1585,8 @@ struct DeviceIndex {
   // hub rows (more than kLongRow entries) of the separator range and of all rows
   int32_t *long_sep = nullptr, *long_all = nullptr;
   int n_long_sep = 0, n_long_all = 0;
+  // autotuned SpMM chunk walk per variant (-1: not tuned, the default applies)
+  std::atomic<int32_t> walk[kWalkSlots];
 };
 constexpr int kLongRow = 256;
 // Batched block solves keep a block's rows in registers up to this size.
@@ -1634,6 +1666,7 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
   std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
   HIPCHECK(hipSetDevice(device));
   auto D = new DeviceIndex();
+  for (auto& x : D->walk) x.store(-1);
   try {
     D->device = device;
     D->n = H.n;
@@ -1951,16 +1984,18 @@ struct Launcher {
     k_finalize<<<1, kFinWG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact);
   }
 
+  // SpMM kernel variant for this batch width: team size TS, column lanes CW,
+  // compile-time column groups NCM and weights; `slot` numbers the variant
+  // (with the panel precision) for the autotuned chunk walk.
   template <typename T>
-  void spmm(SpmmArgs<T> a) {
-    const int64_t rows = a.row1 - a.row0;
-    if (rows <= 0) {
-      if (a.ep != EP_NONE) fail(KATZ_EDEVICE, "internal: empty SpMM with a reduction");
-      return;
-    }
-    a.B = B;
-    int TS, CW;
+  struct SpmmVariant {
+    void (*fn)(SpmmArgs<T>);
+    int TS, CW, slot;
+  };
+  template <typename T>
+  SpmmVariant<T> spmm_variant(bool weighted) const {
     const Tuning& tu = tuning();
+    int TS, CW;
     if (B == 1) { TS = tu.ts1; CW = 1; }
     else if (B == 2) { TS = 8; CW = 2; }
     else if (B <= 4) { TS = 16; CW = 4; }
@@ -1969,22 +2004,60 @@ struct Launcher {
     else if (B <= 32) { TS = 64; CW = 32; }
     else { TS = 64; CW = 64; }
     if (B > MAXC * CW) fail(KATZ_EINVAL, "batch too wide for one launch");
-    const int teams = WG / TS;
-    // chunks of teams * rows_team rows; at most spmm_nwg workgroups walk them
+    const int nc = (B + CW - 1) / CW;  // column groups per lane
+    SpmmVariant<T> v{nullptr, TS, CW, -1};
+    int idx = 0;
+#define KZ_SPMM_V(ts, cw, ncm)                                                              \
+  if (!v.fn && TS == ts && CW == cw && (ncm == 1 || nc <= ncm)) {                          \
+    v.fn = weighted ? k_spmm<T, ts, cw, true, ncm> : k_spmm<T, ts, cw, false, ncm>;        \
+    v.slot = idx;                                                                           \
+  }                                                                                         \
+  idx++;
+    KZ_SPMM_V(4, 1, 1) KZ_SPMM_V(8, 1, 1) KZ_SPMM_V(16, 1, 1) KZ_SPMM_V(32, 1, 1) KZ_SPMM_V(8, 2, 1)
+    KZ_SPMM_V(16, 4, 1) KZ_SPMM_V(32, 8, 1) KZ_SPMM_V(64, 16, 1) KZ_SPMM_V(64, 32, 1)
+    KZ_SPMM_V(64, 64, 2) KZ_SPMM_V(64, 64, 4) KZ_SPMM_V(64, 64, 8)
+#undef KZ_SPMM_V
+    if (!v.fn) fail(KATZ_EDEVICE, "internal: no SpMM variant for this batch width");
+    v.slot = (v.slot * 2 + (sizeof(T) == 8 ? 1 : 0)) * 2 + (weighted ? 1 : 0);
+    return v;
+  }
+
+  // Fills in the launch shape of `a` (chunking, walk, hub rows, partials)
+  // and returns the grid and LDS size.
+  template <typename T>
+  void spmm_shape(SpmmArgs<T>& a, const SpmmVariant<T>& v, int32_t walk, dim3& g, size_t& shm) const {
+    const Tuning& tu = tuning();
+    const int64_t rows = a.row1 - a.row0;
+    const int teams = WG / v.TS;
+    // chunks of teams * rows_team rows, walked contiguously or in XCD slabs
     a.rows_per_wg = teams * tu.rows_team;
-    a.xcd = tu.xcd;
+    a.xcd = walk_xcd(walk);
     a.nchunks = (rows + a.rows_per_wg - 1) / a.rows_per_wg;
-    int64_t nwg = std::min<int64_t>(tu.spmm_nwg, a.nchunks);
+    const int64_t nwg = std::min<int64_t>(walk_nwg(walk), a.nchunks);
     a.partials = w->partials;
     a.long_thr = kLongRow;
     if (a.row0 == D->n1 && a.row1 == D->n) { a.long_rows = D->long_sep; a.n_long = D->n_long_sep; }
     else if (a.row0 == 0 && a.row1 == D->n) { a.long_rows = D->long_all; a.n_long = D->n_long_all; }
     else { a.long_rows = nullptr; a.n_long = 0; }
     if (a.n_long == 0) a.long_rows = nullptr;
-    const int nwg_all = (int)nwg + a.n_long;
+    g = dim3((unsigned)(nwg + a.n_long));
+    shm = sizeof(double) * std::max<size_t>((size_t)teams * B, (size_t)(WG / 64) * MAXC * v.CW);
+  }
+
+  template <typename T>
+  void spmm(SpmmArgs<T> a) {
+    const int64_t rows = a.row1 - a.row0;
+    if (rows <= 0) {
+      if (a.ep != EP_NONE) fail(KATZ_EDEVICE, "internal: empty SpMM with a reduction");
+      return;
+    }
+    a.B = B;
+    const SpmmVariant<T> v = spmm_variant<T>(a.val != nullptr);
+    dim3 g;
+    size_t shm;
+    spmm_shape(a, v, walk_for(v.slot), g, shm);
+    const int nwg_all = (int)g.x;
     need(nwg_all, B);
-    size_t shm = sizeof(double) * std::max<size_t>((size_t)teams * B, (size_t)(WG / 64) * MAXC * CW);
-    dim3 g((unsigned)nwg_all);
     // algorithmic bytes: row pointers and splits, the selected entries, each
     // gathered panel row once, the row-aligned panels read and y written
     const bool sep = a.row0 == D->n1 && a.row1 == D->n;
@@ -1996,25 +2069,88 @@ struct Launcher {
     int panels = 1 + (a.v ? 1 : 0) + (a.w ? 1 : 0) + ((a.dotv && a.dotv != a.v) ? 1 : 0);
     double bytes = 8.0 * rows + 4.0 + (4.0 + (a.val ? 8.0 : 0.0)) * nnz_sel + wb * cols_sel + wb * rows * panels;
     const int kind = sep ? (a.parts == 1 ? PK_SPMM_RHS : PK_SPMM_SEP) : PK_SPMM_FULL;
-    auto launch = [&](const SpmmArgs<T>& aa, double by) {
-      bool launched = false;
-      const int nc = (B + CW - 1) / CW;  // column groups per lane
-#define KZ_SPMM_N(ts, cw, ncm)                                                             \
-  if (!launched && TS == ts && CW == cw && (ncm == 1 || nc <= ncm)) {                      \
-    timed(kind, by, [&] {                                                                  \
-      if (aa.val) k_spmm<T, ts, cw, true, ncm><<<g, WG, shm, st>>>(aa);                    \
-      else k_spmm<T, ts, cw, false, ncm><<<g, WG, shm, st>>>(aa);                          \
-    });                                                                                    \
-    launched = true;                                                                       \
-  }
-      KZ_SPMM_N(4, 1, 1) KZ_SPMM_N(8, 1, 1) KZ_SPMM_N(16, 1, 1) KZ_SPMM_N(32, 1, 1) KZ_SPMM_N(8, 2, 1)
-      KZ_SPMM_N(16, 4, 1) KZ_SPMM_N(32, 8, 1) KZ_SPMM_N(64, 16, 1) KZ_SPMM_N(64, 32, 1)
-      KZ_SPMM_N(64, 64, 2) KZ_SPMM_N(64, 64, 4) KZ_SPMM_N(64, 64, 8)
-#undef KZ_SPMM_N
-      if (!launched) fail(KATZ_EDEVICE, "internal: no SpMM variant for this batch width");
-    };
-    launch(a, bytes);
+    timed(kind, bytes, [&] { v.fn<<<g, WG, shm, st>>>(a); });
     if (a.ep != EP_NONE) finalize(nwg_all, B, a.ep, a.cs, a.out, a.n_active);
+  }
+
+  // Chunk walk of an SpMM variant: the one tuned for this index, else the
+  // default (contiguous chunks over spmm_nwg workgroups, or as pinned by
+  // KATZ_XCD_SLAB / KATZ_SPMM_NWG).
+  int32_t walk_for(int slot) const {
+    const int32_t t = D->walk[slot].load(std::memory_order_acquire);
+    if (t >= 0) return t;
+    const Tuning& tu = tuning();
+    return walk_pack(tu.xcd, tu.spmm_nwg);
+  }
+
+  // Autotuner of the SpMM chunk walk (the launch shape that decides which
+  // rows run together, and so how well the gathered panel rows are reused in
+  // the L2 and the last-level cache).  Candidates: the default (contiguous
+  // chunks over spmm_nwg workgroups, which balances power-law row lengths)
+  // and XCD slabs over the resident workgroup count R and 2R (each XCD walks
+  // its own slab in a narrow sliding window, which suits community-ordered
+  // graphs).  Each is timed on the launch `a` describes (one warm-up and two
+  // timed launches; `a.y` must be a panel the caller overwrites afterwards)
+  // and the fastest kept, a non-default only when 3% faster.  The choice is
+  // kept per index and variant, and per process for the graph's shape, so
+  // indexes of one graph in one process compute bit-identical results.  Not
+  // run under HIP-graph capture or when the walk is pinned by the environment.
+  template <typename T>
+  void tune_spmm(SpmmArgs<T> a) {
+    const Tuning& tu = tuning();
+    if (a.row1 <= a.row0) return;
+    a.B = B;
+    const SpmmVariant<T> v = spmm_variant<T>(a.val != nullptr);
+    if (!tu.autotune || D->walk[v.slot].load(std::memory_order_acquire) >= 0) return;
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    HIPCHECK(hipStreamIsCapturing(st, &cst));
+    if (cst != hipStreamCaptureStatusNone) return;
+    std::lock_guard<std::mutex> lk(walk_mu());
+    if (D->walk[v.slot].load(std::memory_order_acquire) >= 0) return;
+    // no other thread captures a graph or allocates while the candidates run
+    std::lock_guard<std::recursive_mutex> lg(hip_global_mu());
+    const WalkKey key{D->n, D->nnz, D->n1, v.slot};
+    auto& cache = walk_cache();
+    const auto it = cache.find(key);
+    if (it != cache.end()) {
+      D->walk[v.slot].store(it->second, std::memory_order_release);
+      return;
+    }
+    a.ep = EP_NONE; a.v = nullptr; a.w = nullptr; a.dotv = nullptr; a.n_active = nullptr;
+    dim3 g;
+    size_t shm;
+    spmm_shape(a, v, walk_pack(tu.xcd, tu.spmm_nwg), g, shm);
+    int per_cu = 0, cus = 0;
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, WG, shm));
+    HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, D->device));
+    const int R = std::max(1, per_cu) * std::max(1, cus);
+    const int32_t cand[3] = {walk_pack(tu.xcd, tu.spmm_nwg), walk_pack(1, std::min(R, 65536)),
+                             walk_pack(1, std::min(2 * R, 65536))};
+    float ms[3] = {0.f, 0.f, 0.f};
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    for (int c = 0; c < 3; c++) {
+      spmm_shape(a, v, cand[c], g, shm);
+      v.fn<<<g, WG, shm, st>>>(a);
+      HIPCHECK(hipEventRecord(e0, st));
+      for (int r = 0; r < 2; r++) v.fn<<<g, WG, shm, st>>>(a);
+      HIPCHECK(hipEventRecord(e1, st));
+      HIPCHECK(hipEventSynchronize(e1));
+      HIPCHECK(hipEventElapsedTime(&ms[c], e0, e1));
+    }
+    HIPCHECK(hipEventDestroy(e0));
+    HIPCHECK(hipEventDestroy(e1));
+    HIPCHECK(hipGetLastError());
+    int best = 0;
+    for (int c = 1; c < 3; c++)
+      if (ms[c] < 0.97f * ms[best]) best = c;
+    if (getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 0)
+      fprintf(stderr, "[katz] SpMM walk, variant %d, rows %d..%d, B %d: default %.3f ms, xcd slabs x%d %.3f ms, "
+                      "x%d %.3f ms -> %s\n", v.slot, a.row0, a.row1, B, ms[0] / 2, R, ms[1] / 2, 2 * R, ms[2] / 2,
+              best == 0 ? "default" : (best == 1 ? "xcd slabs R" : "xcd slabs 2R"));
+    cache[key] = cand[best];
+    D->walk[v.slot].store(cand[best], std::memory_order_release);
   }
 
   // Runs one_iter() up to max_iter times in chunks of check_every, polling the
@@ -2377,6 +2513,13 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
   const int rpw2 = L.rows_per_wg(n2), nwg2 = Launcher::nwg_for(n2, rpw2);
   L.need(nwg2, B);
   const bool fuse_vt = B == 1 && D->rank > 0 && D->rank <= 64 && !D->ginv && tuning().fuse;
+  {
+    // chunk walk of the iteration's S p launch (Q2 is rewritten by every iteration)
+    SpmmArgs<T> a{};
+    a.row0 = n1; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+    a.x = X; a.ca = -beta; a.cb = -beta; a.parts = 3; a.y = Q2; a.cs = cs;
+    L.tune_spmm(a);
+  }
   L.iterate(sizeof(T) == 8 ? 1 : 2, max_iter, check_every, [&] {
       m11(nullptr, (T)0, P2, beta, X, w->n_active);   // t1' = M11^{-1} (beta A12 p2)
       SpmmArgs<T> a{};
@@ -2428,6 +2571,13 @@ static void solve_cg(Launcher& L, const T* rhs, int max_iter, int check_every) {
   L.colnorm2<T>(R, m, w->rr);
   k_cg_init<<<1, WG, 0, st>>>(B, cs);
   k_update_p<T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, P, 1, cs);
+  {
+    // chunk walk of the iteration's A p launch (Q is rewritten by every iteration)
+    SpmmArgs<T> a{};
+    a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+    a.x = P; a.ca = -beta; a.cb = -beta; a.parts = 3; a.y = Q; a.cs = cs;
+    L.tune_spmm(a);
+  }
   L.iterate(sizeof(T) == 8 ? 3 : 4, max_iter, check_every, [&] {
       SpmmArgs<T> a{};
       a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
