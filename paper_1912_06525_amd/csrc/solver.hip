@@ -940,11 +940,17 @@ __global__ __launch_bounds__(WG) void k_lowrank(int64_t m, int B, int rank, cons
 // One column (B = 1) of k_lowrank with the rank known at compile time (<=
 // RMAX): DW in registers (0 past the rank) and all factor loads of a row
 // issued together.  Same sums, same order.
-template <typename T, typename TV, int RMAX>
+// PUPD: z is not stored; the search direction is updated in place instead,
+// z[i] <- z_new + b z[i] (z holds p; b = bcg, 0 at init), when the column is
+// active, and no partials are written.
+template <typename T, typename TV, int RMAX, bool PUPD = false>
 __global__ __launch_bounds__(WG) void k_lowrank1(int64_t m, int rank, const TV* V, const double* DW, const T* r,
                                                  T* z, int z_has_base, int rows_per_wg, const int* n_active,
-                                                 double* partials) {
+                                                 double* partials, const double* bcg = nullptr,
+                                                 const int* active = nullptr, int init = 0) {
   if (n_active && *n_active == 0) return;
+  if (PUPD && !active[0]) return;
+  const double b = PUPD && !init ? bcg[0] : 0.0;
   double dw[RMAX];
 #pragma unroll
   for (int k = 0; k < RMAX; k++) dw[k] = k < rank ? DW[k] : 0.0;
@@ -955,14 +961,19 @@ __global__ __launch_bounds__(WG) void k_lowrank1(int64_t m, int rank, const TV* 
 #pragma unroll
     for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
     const double rv = (double)r[i];
-    double s = z_has_base ? (double)z[i] : rv;
+    const double pv = PUPD && !init ? (double)z[i] : 0.0;
+    double s = !PUPD && z_has_base ? (double)z[i] : rv;
 #pragma unroll
     for (int k = 0; k < RMAX; k++) s += to_d(vv[k]) * dw[k];
-    const T zv = (T)s;
-    z[i] = zv;
-    dacc[0] += rv * (double)zv;
+    if (PUPD) {
+      z[i] = (T)(s + b * pv);
+    } else {
+      const T zv = (T)s;
+      z[i] = zv;
+      dacc[0] += rv * (double)zv;
+    }
   }
-  wg_colsum(colmap(1), 1, dacc, partials);
+  if (!PUPD) wg_colsum(colmap(1), 1, dacc, partials);
 }
 
 // ------------------------------------- low-rank products for B >= 2 columns
@@ -1041,7 +1052,8 @@ __global__ __launch_bounds__(WG) void k_vt_rows(int64_t m, int B, int rank, int 
 // (D NULL: the plain sums): 64 values per workgroup, its four waves taking
 // every fourth chunk, combined in a fixed order (deterministic).
 __global__ __launch_bounds__(WG) void k_vt_reduce(const double* partials, int nchunk, int64_t nv, int B,
-                                                  const double* Dg, double* DW, const int* n_active) {
+                                                  const double* Dg, double* DW, const int* n_active,
+                                                  double* DW2 = nullptr) {
   if (n_active && *n_active == 0) return;
   __shared__ double sh[WG];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
@@ -1057,22 +1069,31 @@ __global__ __launch_bounds__(WG) void k_vt_reduce(const double* partials, int nc
   }
   sh[tid] = s0 + s1;
   __syncthreads();
-  if (wv == 0 && v < nv)
-    DW[v] = (Dg ? Dg[v / B] : 1.0) * ((sh[lane] + sh[64 + lane]) + (sh[128 + lane] + sh[192 + lane]));
+  if (wv == 0 && v < nv) {
+    const double sw = (sh[lane] + sh[64 + lane]) + (sh[128 + lane] + sh[192 + lane]);
+    const double d = Dg ? Dg[v / B] : 1.0;
+    DW[v] = d * sw;
+    if (DW2) DW2[v] = d * sw * sw;  // this (k, j)'s term of <r, z>
+  }
 }
 
 // z = base + V DW (base = r, or the z already stored when L = chol), then
 // the per-column <r, z> partials[blockIdx.x * B + j] over the chunk's rows.
-template <typename T, typename TV, int RMAX>
+// PUPD: as in k_lowrank1, z holds the search direction p, updated in place
+// (p <- z_new + bcg p, p <- z_new at init) for the active columns, no partials.
+template <typename T, typename TV, int RMAX, bool PUPD = false>
 __global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank, int JW, const TV* V,
                                                      const double* DW, const T* r, T* z, int z_has_base,
-                                                     int64_t rpc, const int* n_active, double* partials) {
+                                                     int64_t rpc, const int* n_active, double* partials,
+                                                     const double* bcg = nullptr, const int* active = nullptr,
+                                                     int init = 0) {
   if (n_active && *n_active == 0) return;
   constexpr int LD = RMAX + 2;
   __shared__ double sV[kVRows * LD];
   const int tid = threadIdx.x, jl = tid % JW, rg = tid / JW, NR = WG / JW;
   const int j = blockIdx.y * JW + jl;
-  const bool col_ok = j < B;
+  const bool col_ok = j < B && (!PUPD || active[j]);
+  const double b = PUPD && !init && col_ok ? bcg[j] : 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * rpc, r1 = min<int64_t>(m, r0 + rpc);
   double dw[RMAX];
 #pragma unroll
@@ -1087,16 +1108,22 @@ __global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank,
       for (int ii = rg; ii < nb; ii += NR) {
         const int64_t o = (b0 + ii) * B + j;
         const double rv = (double)r[o];
-        double sum = z_has_base ? (double)z[o] : rv;
+        const double pv = PUPD && !init ? (double)z[o] : 0.0;
+        double sum = !PUPD && z_has_base ? (double)z[o] : rv;
         const double* vr = sV + ii * LD;
 #pragma unroll
         for (int k = 0; k < RMAX; k++) sum += vr[k] * dw[k];
-        const T zv = (T)sum;
-        z[o] = zv;
-        dacc += rv * (double)zv;
+        if (PUPD) {
+          z[o] = (T)(sum + b * pv);
+        } else {
+          const T zv = (T)sum;
+          z[o] = zv;
+          dacc += rv * (double)zv;
+        }
       }
     }
   }
+  if (PUPD) return;
   __syncthreads();
   sV[tid] = dacc;
   __syncthreads();
@@ -1266,7 +1293,8 @@ __global__ __launch_bounds__(WG) void k_lowrank_mfma(int64_t m, int B, int rank,
 // dependent rounds than a 256-thread workgroup).
 constexpr int kFinWG = 1024;
 __global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int nwg, int nv, int ep, ColState cs,
-                                                     int B, double* out, const double* D, const int* n_active) {
+                                                     int B, double* out, const double* D, const int* n_active,
+                                                     double* out2) {
   if (n_active && *n_active == 0) return;
   final_reduce<kFinWG>(partials, nwg, nv, [&](int j, double s) {
     switch (ep) {
@@ -1276,6 +1304,7 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int
         break;
       case EP_VT:
         out[j] = D[j / B] * s;
+        if (out2) out2[j] = D[j / B] * s * s;
         break;
       case EP_PQ:
         if (cs.active[j]) {
@@ -1335,6 +1364,21 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int
     }
   });
   if (ep == EP_PQ || ep == EP_RR_INIT || ep == EP_RR || ep == EP_RR_CG || ep == EP_RR_VT) recount_active(cs, B);
+}
+
+// <r, z> of the preconditioned residual z = r + V (D o W), W = V^T r, without
+// forming z: <r, r> + sum_k D_k W_k^2 (exact for the stored V; DW2 holds the
+// terms D_k W_kj^2, rank x B), summed in a fixed order; then the PCG step
+// logic of EP_RZ_INIT / EP_RZ (rz, and bcg = rz_new / rz_old).
+__global__ void k_rz_lowrank(int rank, int B, const double* DW2, int init, ColState cs, const int* n_active) {
+  if (!init && n_active && *n_active == 0) return;
+  for (int j = threadIdx.x; j < B; j += blockDim.x) {
+    if (init ? !cs.mask[j] : !cs.active[j]) continue;
+    double s = cs.rr[j];
+    for (int k = 0; k < rank; k++) s += DW2[(int64_t)k * B + j];
+    if (!init) cs.bcg[j] = s / cs.rz[j];
+    cs.rz[j] = s;
+  }
 }
 
 // Start of a batch: stop thresholds on the recurrence residual and the first
@@ -1527,6 +1571,7 @@ struct Workspace {
   double* partials = nullptr;
   size_t partials_cap = 0;
   double* DW = nullptr;
+  double* DW2 = nullptr;  // terms D_k W_kj^2 of <r, z> (rank x B)
   double *rz, *pq, *alpha, *bcg, *rr, *thr, *bn2, *res2, *colscale, *rn2, *inv, *fwd;
   float* Rf = nullptr;             // scaled FP32 right-hand side (precision form)
   int *active, *status, *iters, *n_active, *mask;
@@ -1845,7 +1890,7 @@ int64_t ws_bytes_per_column(const DeviceIndex* D) {
   const int64_t n = D->n, n2 = std::max(1, D->n2), esz = solve_elem_bytes(D);
   int64_t b = 16 * n + esz * (4 * n + n2);
   if (D->precision == KATZ_PREC_MIXED) b += 4 * n;
-  b += 8 * (int64_t)partials_per_column(D) + 8 * std::max(1, D->rank);
+  b += 8 * (int64_t)partials_per_column(D) + 16 * std::max(1, D->rank);  // partials, DW, DW2
   b += 64 + 1024 + 12 * 4096;
   return b;
 }
@@ -1870,6 +1915,7 @@ static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   w->partials_cap = partials_per_column(D) * (size_t)std::max(B, 1);
   w->partials = dalloc<double>(L, (int64_t)w->partials_cap);
   w->DW = dalloc<double>(L, (int64_t)std::max(1, D->rank) * B);
+  w->DW2 = dalloc<double>(L, (int64_t)std::max(1, D->rank) * B);
   double* s = dalloc<double>(L, 12 * (int64_t)B);
   w->rz = s; w->pq = s + B; w->alpha = s + 2 * B; w->bcg = s + 3 * B; w->rr = s + 4 * B;
   w->thr = s + 5 * B; w->bn2 = s + 6 * B; w->res2 = s + 7 * B; w->colscale = s + 8 * B;
@@ -1979,9 +2025,10 @@ struct Launcher {
   static int nwg_for(int64_t m, int rpw) { return (int)((m + rpw - 1) / rpw); }
 
   // Reduces nwg x nv partials and applies the epilogue `ep` (one workgroup).
-  void finalize(int nwg, int nv, int ep, const ColState& cs, double* out, const int* nact) {
+  void finalize(int nwg, int nv, int ep, const ColState& cs, double* out, const int* nact,
+                double* out2 = nullptr) {
     need(nwg, nv);
-    k_finalize<<<1, kFinWG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact);
+    k_finalize<<<1, kFinWG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact, out2);
   }
 
   // SpMM kernel variant for this batch width: team size TS, column lanes CW,
@@ -2364,6 +2411,81 @@ static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep,
   L.finalize(nwg, B, ep, cs, nullptr, nact);
 }
 
+// Preconditioner and search-direction update in one pass (L = I, 1 <= rank
+// <= 64): W = V^T r and DW = D o W as in precond_rows / precond_simple, then
+// <r, z> = <r, r> + sum_k D_k W_k^2 gives bcg before z exists (k_rz_lowrank),
+// and one pass writes p = r + V DW + bcg p (init: p = r + V DW) for the
+// active columns.  Saves writing and re-reading z and one launch per
+// iteration.
+template <typename T, typename TV>
+static void precond_fused(Launcher& L, const TV* V, const T* R2, T* P2, int init, const ColState& cs,
+                          const int* nact) {
+  DeviceIndex* D = L.D;
+  Workspace* w = L.w;
+  const int B = L.B, rk = D->rank;
+  const int64_t m = D->n2;
+  hipStream_t st = L.st;
+  const double pbytes = (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m * (init ? 2 : 3);
+  if (B == 1) {
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(tuning().lr_nwg, (m + 63) / 64));
+    const int rpw = (int)((m + want - 1) / want), nwg = Launcher::nwg_for(m, rpw);
+    L.need(nwg, rk);
+    L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * m, [&] {
+      if (rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+      else if (rk <= 16) k_vt1<T, TV, 16><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+      else if (rk <= 32) k_vt1<T, TV, 32><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+      else k_vt1<T, TV, 64><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+    });
+    L.finalize(nwg, rk, EP_VT, cs, w->DW, nact, w->DW2);
+    k_rz_lowrank<<<1, WG, 0, st>>>(rk, B, w->DW2, init, cs, nact);
+    L.timed(PK_LOWRANK, pbytes, [&] {
+      if (rk <= 8)
+        k_lowrank1<T, TV, 8, true><<<nwg, WG, 0, st>>>(m, rk, V, w->DW, R2, P2, 0, rpw, nact, nullptr, cs.bcg,
+                                                         cs.active, init);
+      else if (rk <= 16)
+        k_lowrank1<T, TV, 16, true><<<nwg, WG, 0, st>>>(m, rk, V, w->DW, R2, P2, 0, rpw, nact, nullptr, cs.bcg,
+                                                          cs.active, init);
+      else if (rk <= 32)
+        k_lowrank1<T, TV, 32, true><<<nwg, WG, 0, st>>>(m, rk, V, w->DW, R2, P2, 0, rpw, nact, nullptr, cs.bcg,
+                                                          cs.active, init);
+      else
+        k_lowrank1<T, TV, 64, true><<<nwg, WG, 0, st>>>(m, rk, V, w->DW, R2, P2, 0, rpw, nact, nullptr, cs.bcg,
+                                                          cs.active, init);
+    });
+    return;
+  }
+  int JW = 1;
+  while (JW < B && JW < WG) JW <<= 1;
+  const int njt = (B + JW - 1) / JW;
+  const int64_t rpc = std::max<int64_t>(kVRows, (m + 1023) / 1024);
+  const int nchunk = (int)((m + rpc - 1) / rpc);
+  const int64_t nv = (int64_t)rk * B;
+  dim3 g((unsigned)nchunk, (unsigned)njt);
+  L.need(nchunk, nv);
+  L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
+    if (rk <= 8) k_vt_rows<T, TV, 8><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
+    else if (rk <= 16) k_vt_rows<T, TV, 16><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
+    else if (rk <= 32) k_vt_rows<T, TV, 32><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
+    else k_vt_rows<T, TV, 64><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
+  });
+  k_vt_reduce<<<(unsigned)((nv + 63) / 64), WG, 0, st>>>(w->partials, nchunk, nv, B, D->D, w->DW, nact, w->DW2);
+  k_rz_lowrank<<<1, WG, 0, st>>>(rk, B, w->DW2, init, cs, nact);
+  L.timed(PK_LOWRANK, pbytes, [&] {
+    if (rk <= 8)
+      k_lowrank_rows<T, TV, 8, true><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr,
+                                                         cs.bcg, cs.active, init);
+    else if (rk <= 16)
+      k_lowrank_rows<T, TV, 16, true><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr,
+                                                          cs.bcg, cs.active, init);
+    else if (rk <= 32)
+      k_lowrank_rows<T, TV, 32, true><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr,
+                                                          cs.bcg, cs.active, init);
+    else
+      k_lowrank_rows<T, TV, 64, true><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr,
+                                                          cs.bcg, cs.active, init);
+  });
+}
+
 // x += alpha p; r -= alpha q with DW = D o (V^T r) and <r, r> in one pass and
 // one finalize (one column, rank <= 64).
 template <typename T, typename TV>
@@ -2495,6 +2617,43 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     });
   };
 
+  // z = S~^{-1} r2 and p2 = z + bcg p2 (init: p2 = z).  With L = I and a
+  // rank of at most 64 (or none), precond_fused updates p2 without forming z;
+  // otherwise z is formed (with <r2, z>) and p2 updated after.
+  const bool fuse_p = !D->ginv && D->rank <= 64 && !(std::is_same<T, float>::value && B >= 16 && D->rank > 0);
+  auto precond_p = [&](int init) {
+    if (!fuse_p) {
+      precond(init ? EP_RZ_INIT : EP_RZ);
+      L.timed_cols(PK_UPDATE_P, 3.0 * sizeof(T) * n2, [&] {
+        k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, init, cs);
+      });
+      return;
+    }
+    const int* nact = init ? nullptr : w->n_active;
+    if (D->rank == 0) {
+      // z = r: <r, z> = <r, r>
+      k_rz_lowrank<<<1, WG, 0, st>>>(0, B, nullptr, init, cs, nact);
+      L.timed_cols(PK_UPDATE_P, 3.0 * sizeof(T) * n2, [&] {
+        k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, R2, P2, init, cs);
+      });
+      return;
+    }
+    with_lowrank_factor<T>(D, [&](auto* V) {
+      typedef typename std::remove_cv<typename std::remove_pointer<decltype(V)>::type>::type TV;
+      precond_fused<T, TV>(L, V, R2, P2, init, cs, nact);
+    });
+  };
+
+  {
+    // chunk walk of the iteration's S p launch, tuned before any SpMM of the
+    // solve so that every launch of this variant uses the same walk (Q2 is
+    // first written by the iterations)
+    SpmmArgs<T> a{};
+    a.row0 = n1; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+    a.x = X; a.ca = -beta; a.cb = -beta; a.parts = 3; a.y = Q2; a.cs = cs;
+    L.tune_spmm(a);
+  }
+
   // ---- a2: t = M11^{-1} b1 -> X[0:n1]; f = b2 + beta A21 t -> R2; rr
   m11(rhs, (T)1, nullptr, (T)0, X, nullptr);
   {
@@ -2506,20 +2665,12 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     L.spmm(a);
   }
   L.fill<T>(Dx, (int64_t)n * B, (T)0);
-  precond(EP_RZ_INIT);
-  k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 1, cs);
+  precond_p(1);
 
   // ---- a3: PCG iterations, polled every check_every
   const int rpw2 = L.rows_per_wg(n2), nwg2 = Launcher::nwg_for(n2, rpw2);
   L.need(nwg2, B);
   const bool fuse_vt = B == 1 && D->rank > 0 && D->rank <= 64 && !D->ginv && tuning().fuse;
-  {
-    // chunk walk of the iteration's S p launch (Q2 is rewritten by every iteration)
-    SpmmArgs<T> a{};
-    a.row0 = n1; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
-    a.x = X; a.ca = -beta; a.cb = -beta; a.parts = 3; a.y = Q2; a.cs = cs;
-    L.tune_spmm(a);
-  }
   L.iterate(sizeof(T) == 8 ? 1 : 2, max_iter, check_every, [&] {
       m11(nullptr, (T)0, P2, beta, X, w->n_active);   // t1' = M11^{-1} (beta A12 p2)
       SpmmArgs<T> a{};
@@ -2540,7 +2691,8 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
           k_update_r<T><<<nwg2, WG, WG * sizeof(double), st>>>(n2, B, rpw2, K2, P2, R2, Q2, cs, w->partials);
         });
         L.finalize(nwg2, B, EP_RR, cs, nullptr, w->n_active);
-        precond(EP_RZ);
+        precond_p(0);
+        return;
       }
       L.timed_cols(PK_UPDATE_P, 3.0 * sizeof(T) * n2, [&] {
         k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 0, cs);
@@ -2565,19 +2717,20 @@ static void solve_cg(Launcher& L, const T* rhs, int max_iter, int check_every) {
   const int64_t m = n;
   const int rpw = L.rows_per_wg(m), nwg = Launcher::nwg_for(m, rpw);
   L.need(nwg, B);
+  {
+    // chunk walk of the iteration's A p launch (Q is first written by the
+    // iterations)
+    SpmmArgs<T> a{};
+    a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+    a.x = P; a.ca = -beta; a.cb = -beta; a.parts = 3; a.y = Q; a.cs = cs;
+    L.tune_spmm(a);
+  }
   // r = rhs, x = 0, p = r, rz = rr = <r, r>
   k_axpy_mask<T, T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, rhs, nullptr, nullptr, 0);
   L.fill<T>(Dx, m * B, (T)0);
   L.colnorm2<T>(R, m, w->rr);
   k_cg_init<<<1, WG, 0, st>>>(B, cs);
   k_update_p<T><<<grid_for(m, 64), WG, 0, st>>>(m, B, R, P, 1, cs);
-  {
-    // chunk walk of the iteration's A p launch (Q is rewritten by every iteration)
-    SpmmArgs<T> a{};
-    a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
-    a.x = P; a.ca = -beta; a.cb = -beta; a.parts = 3; a.y = Q; a.cs = cs;
-    L.tune_spmm(a);
-  }
   L.iterate(sizeof(T) == 8 ? 3 : 4, max_iter, check_every, [&] {
       SpmmArgs<T> a{};
       a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
