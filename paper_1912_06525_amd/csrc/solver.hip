@@ -1292,9 +1292,22 @@ __global__ __launch_bounds__(WG) void k_lowrank_mfma(int64_t m, int B, int rank,
 // One workgroup of kFinWG threads: the partials are read kFinWG wide (fewer
 // dependent rounds than a 256-thread workgroup).
 constexpr int kFinWG = 1024;
+// <r, z> = <r, r> + sum_k DW2[k][j] (the terms D_k W_kj^2 of z = r + V (D o W),
+// summed in a fixed order) and the PCG step: init sets rz for the masked
+// columns, an iteration sets bcg = rz_new / rz_old for the active ones.
+__device__ inline void rz_from_terms(int rank, int B, const double* DW2, int init, const ColState& cs) {
+  for (int j = threadIdx.x; j < B; j += blockDim.x) {
+    if (init ? !cs.mask[j] : !cs.active[j]) continue;
+    double s = cs.rr[j];
+    for (int k = 0; k < rank; k++) s += DW2[(int64_t)k * B + j];
+    if (!init) cs.bcg[j] = s / cs.rz[j];
+    cs.rz[j] = s;
+  }
+}
+
 __global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int nwg, int nv, int ep, ColState cs,
                                                      int B, double* out, const double* D, const int* n_active,
-                                                     double* out2) {
+                                                     double* out2, int rz_mode) {
   if (n_active && *n_active == 0) return;
   final_reduce<kFinWG>(partials, nwg, nv, [&](int j, double s) {
     switch (ep) {
@@ -1364,6 +1377,12 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int
     }
   });
   if (ep == EP_PQ || ep == EP_RR_INIT || ep == EP_RR || ep == EP_RR_CG || ep == EP_RR_VT) recount_active(cs, B);
+  if (ep == EP_VT && rz_mode) {
+    // the <r, z> terms just written by this workgroup (out2), then the PCG
+    // step: 1 = iteration, 2 = initial step
+    __syncthreads();
+    rz_from_terms(nv / B, B, out2, rz_mode == 2, cs);
+  }
 }
 
 // <r, z> of the preconditioned residual z = r + V (D o W), W = V^T r, without
@@ -1372,13 +1391,7 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int
 // logic of EP_RZ_INIT / EP_RZ (rz, and bcg = rz_new / rz_old).
 __global__ void k_rz_lowrank(int rank, int B, const double* DW2, int init, ColState cs, const int* n_active) {
   if (!init && n_active && *n_active == 0) return;
-  for (int j = threadIdx.x; j < B; j += blockDim.x) {
-    if (init ? !cs.mask[j] : !cs.active[j]) continue;
-    double s = cs.rr[j];
-    for (int k = 0; k < rank; k++) s += DW2[(int64_t)k * B + j];
-    if (!init) cs.bcg[j] = s / cs.rz[j];
-    cs.rz[j] = s;
-  }
+  rz_from_terms(rank, B, DW2, init, cs);
 }
 
 // Start of a batch: stop thresholds on the recurrence residual and the first
@@ -2026,9 +2039,9 @@ struct Launcher {
 
   // Reduces nwg x nv partials and applies the epilogue `ep` (one workgroup).
   void finalize(int nwg, int nv, int ep, const ColState& cs, double* out, const int* nact,
-                double* out2 = nullptr) {
+                double* out2 = nullptr, int rz_mode = 0) {
     need(nwg, nv);
-    k_finalize<<<1, kFinWG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact, out2);
+    k_finalize<<<1, kFinWG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact, out2, rz_mode);
   }
 
   // SpMM kernel variant for this batch width: team size TS, column lanes CW,
@@ -2436,8 +2449,7 @@ static void precond_fused(Launcher& L, const TV* V, const T* R2, T* P2, int init
       else if (rk <= 32) k_vt1<T, TV, 32><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
       else k_vt1<T, TV, 64><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
     });
-    L.finalize(nwg, rk, EP_VT, cs, w->DW, nact, w->DW2);
-    k_rz_lowrank<<<1, WG, 0, st>>>(rk, B, w->DW2, init, cs, nact);
+    L.finalize(nwg, rk, EP_VT, cs, w->DW, nact, w->DW2, init ? 2 : 1);  // with <r, z> and the step
     L.timed(PK_LOWRANK, pbytes, [&] {
       if (rk <= 8)
         k_lowrank1<T, TV, 8, true><<<nwg, WG, 0, st>>>(m, rk, V, w->DW, R2, P2, 0, rpw, nact, nullptr, cs.bcg,
