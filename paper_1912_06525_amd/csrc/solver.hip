@@ -1521,6 +1521,7 @@ struct Tuning {
   int lr_nwg;       // max workgroups of the one-column low-rank kernels
   int m11_bpt;      // blocks per team and chunk of the batched small-block solve
   int autotune;     // tune the SpMM chunk walk per index (off when pinned by the environment)
+  int m11_sub1;     // lanes per row of the A12 gather in the 1-3 column block solve
 };
 static int env_int(const char* name, int dflt, int lo, int hi) {
   const char* e = getenv(name);
@@ -1542,6 +1543,8 @@ static const Tuning& tuning() {
     u.lr_nwg = env_int("KATZ_LR_NWG", 512, 64, 65536);
     u.m11_bpt = env_int("KATZ_M11_BLOCKS_PER_TEAM", 1, 1, 64);
     u.autotune = env_int("KATZ_AUTOTUNE", 1, 0, 1) && !getenv("KATZ_XCD_SLAB") && !getenv("KATZ_SPMM_NWG");
+    u.m11_sub1 = env_int("KATZ_M11_SUB", 4, 1, 16);
+    if (u.m11_sub1 & (u.m11_sub1 - 1)) u.m11_sub1 = 4;  // a power of two (shuffle reduction)
     return u;
   }();
   return t;
@@ -2548,7 +2551,7 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     a.tile_row1 = nullptr;
     int cb = std::max(1, std::min(B, (int)(32768 / sizeof(T) / std::max(1, D->max_tile_rows))));
     a.CB = cb;
-    a.sub = cb >= 16 ? 1 : (cb >= 4 ? 2 : 4);
+    a.sub = cb >= 16 ? 1 : (cb >= 4 ? 2 : tuning().m11_sub1);
     size_t shm = (size_t)D->max_tile_rows * cb * sizeof(T);
     const double wb = (double)sizeof(T) * B;
     double bytes = (double)sizeof(T) * D->minv_elems + 4.0 * n1 + wb * n1 + (v ? wb * n1 : 0.0) +
