@@ -22,8 +22,8 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests need a visible device; on a CPU-only host they are skipped
-    # (the driver selects them with -m gpu on the GPU machine).
+    # GPU tests need a visible device; on a host without one they are
+    # skipped (select them with -m gpu).
     try:
         import torch
         have_gpu = torch.cuda.is_available()

@@ -403,3 +403,17 @@ def test_weighted_graph_matches_oracle(prec, B):
             assert st[j]["status"] == 0, st[j]
             _accept(sc[j], ref[:, j], tau, "method %d q=%d" % (method, q))
             assert res[j] <= 1.05 * tol + 1e-15, (res[j], tol)
+
+
+@pytest.mark.parametrize("prec", [K.KATZ_PREC_FP64, K.KATZ_PREC_MIXED])
+@pytest.mark.parametrize("B", [1, 7, 40])
+def test_rank0_identity_preconditioner(prec, B):
+    # L = I without a low-rank part: S~^{-1} = I, so <r, z> = <r, r> and the
+    # search direction is p = r + bcg p (no preconditioner pass)
+    g = ki.workload("lnsbm4m", scale=0.002).graph
+    beta = oracle_beta(g, 0.8)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=0, labels=g.labels, max_block=32, precision=prec,
+                                 l_kind=K.KATZ_L_IDENTITY)
+    assert idx.info.rank == 0 and idx.info.l_kind == K.KATZ_L_IDENTITY
+    qs = ki.sample_queries(g, B, 23)
+    _check(g, idx, beta, qs, 1e-6)
