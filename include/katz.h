@@ -112,7 +112,12 @@ typedef struct {
   int32_t max_iter;    /* inner iterations per refinement sweep (default 1000) */
   int32_t method;      /* enum katz_method (default LRC) */
   int32_t max_sweeps;  /* FP64 refinement sweeps (default 6) */
-  int32_t check_every; /* inner iterations between host convergence polls (default 8) */
+  int32_t check_every; /* inner iterations between host convergence polls;
+                          0 (default): adaptive, the first poll after as many
+                          iterations as the previous solve of the same kind on
+                          this index needed (8 if none), then after 1, 1, 2, 2,
+                          4, 4, 8, 8, ... more.  Iterations after convergence
+                          change nothing, so results do not depend on it. */
   int32_t force_fallback; /* fault injection for tests: every LRC solve stops after
                              one iteration and counts as broken down, so the
                              refinement sweeps run plain CG (default 0) */

@@ -80,7 +80,7 @@ katz_query_opts resolve(const katz_query_opts* o) {
   if (!(r.rel_tol > 0)) r.rel_tol = 1e-6;
   if (r.max_iter <= 0) r.max_iter = 1000;
   if (r.max_sweeps <= 0) r.max_sweeps = 6;
-  if (r.check_every <= 0) r.check_every = 8;
+  if (r.check_every < 0) r.check_every = 0;  // 0: adaptive polling
   return r;
 }
 }  // namespace
@@ -110,7 +110,7 @@ void katz_query_opts_default(katz_query_opts* o) {
   o->max_iter = 1000;
   o->method = KATZ_METHOD_LRC;
   o->max_sweeps = 6;
-  o->check_every = 8;
+  o->check_every = 0;
   o->force_fallback = 0;
 }
 

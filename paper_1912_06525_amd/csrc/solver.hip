@@ -1648,8 +1648,13 @@ struct DeviceIndex {
   int n_long_sep = 0, n_long_all = 0;
   // autotuned SpMM chunk walk per variant (-1: not tuned, the default applies)
   std::atomic<int32_t> walk[kWalkSlots];
+  // iterations the last solve of each kind needed (method x precision x first
+  // or later sweep; 0: none yet), the first poll of the adaptive schedule
+  std::atomic<int32_t> iter_hint[8];
 };
 constexpr int kLongRow = 256;
+// HIP graphs of iteration chunks kept per workspace.
+constexpr size_t kMaxGraphs = 64;
 // Batched block solves keep a block's rows in registers up to this size.
 constexpr int kSmallBlock = 4;
 
@@ -1728,6 +1733,7 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
   HIPCHECK(hipSetDevice(device));
   auto D = new DeviceIndex();
   for (auto& x : D->walk) x.store(-1);
+  for (auto& x : D->iter_hint) x.store(0);
   try {
     D->device = device;
     D->n = H.n;
@@ -1985,6 +1991,7 @@ struct Launcher {
   Workspace* w;
   hipStream_t st;
   int B;
+  int iter_hint = 0;  // first poll of the adaptive schedule (0: default)
 
   ColState cs(int max_iter) const {
     ColState c;
@@ -2216,21 +2223,32 @@ struct Launcher {
     D->walk[v.slot].store(cand[best], std::memory_order_release);
   }
 
-  // Runs one_iter() up to max_iter times in chunks of check_every, polling the
-  // active-column count after each chunk.  A full chunk is captured once per
-  // workspace and key into a HIP graph and replayed (not while profiling).
+  // Runs one_iter() up to max_iter times in chunks, polling the active-column
+  // count after each chunk.  check_every > 0: chunks of that length.
+  // check_every == 0 (adaptive): the first chunk is iter_hint (what the last
+  // solve of this kind needed; 8 if none), then 1, 1, 2, 2, 4, 4, 8, 8, ...:
+  // iterations after convergence still launch every kernel (which exits at
+  // once) and each poll is a host round trip, so the schedule keeps both few
+  // when consecutive solves need similar counts.  A chunk is captured once per
+  // workspace, key and length into a HIP graph and replayed (not while
+  // profiling; at most kMaxGraphs per workspace, further lengths run eagerly).
   template <typename F>
   void iterate(int64_t key, int max_iter, int check_every, F&& one_iter) {
     int* hflag = (int*)((char*)w->hpin + kPinFlagOff);
     const bool graphs = tuning().graphs && !g_prof_on.load(std::memory_order_relaxed);
-    const int64_t gkey = (key << 56) ^ ((int64_t)B << 40) ^ ((int64_t)check_every << 20) ^ (int64_t)max_iter;
-    for (int it = 0; it < max_iter; it += check_every) {
-      const int len = std::min(check_every, max_iter - it);
+    int it = 0;
+    for (int chunk = 0; it < max_iter; chunk++) {
+      int want;
+      if (check_every > 0) want = check_every;
+      else if (chunk == 0) want = iter_hint > 0 ? iter_hint : 8;
+      else want = std::min(8, 1 << ((chunk - 1) / 2));
+      const int len = std::min(want, max_iter - it);
+      const int64_t gkey = (key << 56) ^ ((int64_t)B << 40) ^ ((int64_t)len << 20) ^ (int64_t)max_iter;
       hipGraphExec_t ex = nullptr;
-      if (graphs && len == check_every) {
+      if (graphs) {
         for (auto& g : w->graphs)
           if (g.first == gkey) ex = g.second;
-        if (!ex) {
+        if (!ex && w->graphs.size() < kMaxGraphs) {
           std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
           hipGraph_t gr = nullptr;
           HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -2252,6 +2270,7 @@ struct Launcher {
         HIPCHECK(hipGraphLaunch(ex, st));
       else
         for (int s2 = 0; s2 < len; s2++) one_iter();
+      it += len;
       HIPCHECK(hipMemcpyAsync(hflag, w->n_active, sizeof(int), hipMemcpyDeviceToHost, st));
       sync();
       if (*hflag == 0) break;
@@ -2840,6 +2859,8 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
       // sweep 0: the device mask (b != 0) is already in place
       if (sweep > 0) HIPCHECK(hipMemcpyAsync(w->mask, hm, sizeof(int) * B, hipMemcpyHostToDevice, st));
       const int iters = (!cg_pass && o.force_fallback) ? 1 : o.max_iter;
+      const int hslot = (cg_pass ? 4 : 0) + (D->precision == KATZ_PREC_MIXED ? 2 : 0) + (sweep > 0 ? 1 : 0);
+      L.iter_hint = D->iter_hint[hslot].load(std::memory_order_relaxed);
       if (D->precision == KATZ_PREC_MIXED) {
         // FP32 inner solve on the unit-norm right-hand side, FP64 accumulation
         L.colnorm2<double>(rhs, n, w->rn2);
@@ -2892,6 +2913,14 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
       const int* hm = (const int*)(pin + (pass ? kPinMask1 : kPinMask0));
       const int* hs = (const int*)(pin + (pass ? kPinStat1 : kPinStat0));
       const int* hi = (const int*)(pin + (pass ? kPinIter1 : kPinIter0));
+      // the iterations this solve needed: the first poll of the next one
+      int most = 0;
+      for (int j = 0; j < B; j++)
+        if (hm[j] && res[j].bn != 0.0) most = std::max(most, hi[j]);
+      if (most > 0) {
+        const int hslot = (pass ? 4 : 0) + (D->precision == KATZ_PREC_MIXED ? 2 : 0) + (sweep > 0 ? 1 : 0);
+        D->iter_hint[hslot].store(most, std::memory_order_relaxed);
+      }
       for (int j = 0; j < B; j++) {
         if (!hm[j] || res[j].bn == 0.0) continue;
         res[j].iters += hi[j];
