@@ -2827,7 +2827,7 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
     k_rhs_scatter<double><<<B, WG, 0, st>>>(w->qpos, B, D->rp, D->col, D->val, D->beta, w->Rhs);
   };
   put_b();
-  L.fill<double>(w->K, nB, 0.0);
+  // K is not cleared: the first sweep writes it whole (below)
   L.colnorm2<double>(w->Rhs, n, w->bn2);
   // thresholds and the first sweep's mask on the device (no host round trip)
   const double tol = o.rel_tol;
@@ -2870,15 +2870,26 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
           solve_cg<float>(L, w->Rf, iters, o.check_every);
         else
           solve_lrc<float>(L, w->Rf, iters, o.check_every);
-        k_axpy_mask<double, float><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const float*)w->Dx, w->mask,
-                                                                  w->fwd, 1);
+        // first sweep (one path for all columns): K = correction for every
+        // column (those outside the mask are exactly 0: each solve clears Dx
+        // and never touches inactive columns); later sweeps add
+        if (sweep == 0)
+          k_axpy_mask<double, float><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const float*)w->Dx, nullptr,
+                                                                    w->fwd, 0);
+        else
+          k_axpy_mask<double, float><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const float*)w->Dx, w->mask,
+                                                                    w->fwd, 1);
       } else {
         if (cg_pass)
           solve_cg<double>(L, rhs, iters, o.check_every);
         else
           solve_lrc<double>(L, rhs, iters, o.check_every);
-        k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const double*)w->Dx, w->mask,
-                                                                    nullptr, 1);
+        if (sweep == 0)
+          k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const double*)w->Dx, nullptr,
+                                                                      nullptr, 0);
+        else
+          k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const double*)w->Dx, w->mask,
+                                                                      nullptr, 1);
       }
       HIPCHECK(hipMemcpyAsync(pin + (pass ? kPinStat1 : kPinStat0), w->status, sizeof(int) * B,
                               hipMemcpyDeviceToHost, st));
@@ -2887,8 +2898,9 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
     }
     // a6: true FP64 residual r = b - M k, which is the next sweep's right-hand
     // side: Rhs = b, then Rhs = Rhs + beta A k - k in place (each element is
-    // read and written by the same lane)
-    put_b();
+    // read and written by the same lane).  The first sweep's solve only read
+    // Rhs, which still holds b.
+    if (sweep > 0) put_b();
     SpmmArgs<double> a{};
     a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
     a.x = w->K; a.ca = D->beta; a.cb = D->beta; a.parts = 3;

@@ -417,3 +417,18 @@ def test_rank0_identity_preconditioner(prec, B):
     assert idx.info.rank == 0 and idx.info.l_kind == K.KATZ_L_IDENTITY
     qs = ki.sample_queries(g, B, 23)
     _check(g, idx, beta, qs, 1e-6)
+
+
+@pytest.mark.parametrize("method", [K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG])
+def test_poll_schedule_does_not_change_results(method):
+    # iterations after convergence change nothing, so every polling schedule
+    # (adaptive with and without a hint, fixed intervals) gives the same bits
+    g = ki.workload("lnsbm4m", scale=0.002).graph
+    beta = oracle_beta(g, 0.8)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=8, labels=g.labels, max_block=32)
+    qs = ki.sample_queries(g, 3, 29)
+    ref, st_ref = idx.query(qs, tol=1e-9, method=method, check_every=1)
+    for ce in (0, 0, 3, 8):   # the first adaptive call polls from a hint left by the previous one
+        sc, st = idx.query(qs, tol=1e-9, method=method, check_every=ce)
+        assert np.array_equal(sc, ref), ce
+        assert [s["iters"] for s in st] == [s["iters"] for s in st_ref], ce
