@@ -432,3 +432,14 @@ def test_poll_schedule_does_not_change_results(method):
         sc, st = idx.query(qs, tol=1e-9, method=method, check_every=ce)
         assert np.array_equal(sc, ref), ce
         assert [s["iters"] for s in st] == [s["iters"] for s in st_ref], ce
+
+
+def test_query_wider_than_one_launch():
+    # 530 queries: one launch of 512 columns (8 column groups per lane) and
+    # one of 18, both against the oracle
+    g = ki.workload("sbm2k").graph
+    beta = oracle_beta(g, 0.5)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=8, labels=g.labels, max_block=64)
+    qs = ki.sample_queries(g, 530, 31)
+    assert len(qs) == 530
+    _check(g, idx, beta, qs, 1e-6)
