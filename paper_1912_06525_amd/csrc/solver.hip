@@ -1655,6 +1655,8 @@ struct DeviceIndex {
 constexpr int kLongRow = 256;
 // HIP graphs of iteration chunks kept per workspace.
 constexpr size_t kMaxGraphs = 64;
+// Partial sums (workgroups x values) above which finalize reduces in two stages.
+constexpr int64_t kFinTwoStage = 1 << 20;
 // Batched block solves keep a block's rows in registers up to this size.
 constexpr int kSmallBlock = 4;
 
@@ -2051,6 +2053,14 @@ struct Launcher {
   void finalize(int nwg, int nv, int ep, const ColState& cs, double* out, const int* nact,
                 double* out2 = nullptr, int rz_mode = 0) {
     need(nwg, nv);
+    if ((int64_t)nwg * nv > kFinTwoStage && nwg > 1) {
+      // many partial rows: a many-workgroup first stage sums each value's
+      // column (fixed order) into row 0, then the one-workgroup step runs on
+      // that row; each value's column is read and written by one workgroup
+      k_vt_reduce<<<(unsigned)((nv + 63) / 64), WG, 0, st>>>(w->partials, nwg, nv, B, nullptr, w->partials,
+                                                             nact);
+      nwg = 1;
+    }
     k_finalize<<<1, kFinWG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact, out2, rz_mode);
   }
 
