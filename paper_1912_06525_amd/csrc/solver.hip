@@ -1555,7 +1555,7 @@ inline int32_t walk_pack(int xcd, int nwg) { return (int32_t)((xcd ? 1 : 0) << 2
 inline int walk_xcd(int32_t w) { return (w >> 24) & 1; }
 inline int walk_nwg(int32_t w) { return w & 0xffffff; }
 // SpMM variants x panel precisions x weights (Launcher::spmm_variant).
-constexpr int kWalkSlots = 12 * 2 * 2;
+constexpr int kWalkSlots = 13 * 2 * 2;
 // Tuned walks of this process by graph shape (n, nnz, n1) and variant slot.
 struct WalkKey {
   int64_t n, nnz, n1;
@@ -2088,14 +2088,14 @@ struct Launcher {
     SpmmVariant<T> v{nullptr, TS, CW, -1};
     int idx = 0;
 #define KZ_SPMM_V(ts, cw, ncm)                                                              \
-  if (!v.fn && TS == ts && CW == cw && (ncm == 1 || nc <= ncm)) {                          \
+  if (!v.fn && TS == ts && CW == cw && nc <= ncm) {                                         \
     v.fn = weighted ? k_spmm<T, ts, cw, true, ncm> : k_spmm<T, ts, cw, false, ncm>;        \
     v.slot = idx;                                                                           \
   }                                                                                         \
   idx++;
     KZ_SPMM_V(4, 1, 1) KZ_SPMM_V(8, 1, 1) KZ_SPMM_V(16, 1, 1) KZ_SPMM_V(32, 1, 1) KZ_SPMM_V(8, 2, 1)
     KZ_SPMM_V(16, 4, 1) KZ_SPMM_V(32, 8, 1) KZ_SPMM_V(64, 16, 1) KZ_SPMM_V(64, 32, 1)
-    KZ_SPMM_V(64, 64, 2) KZ_SPMM_V(64, 64, 4) KZ_SPMM_V(64, 64, 8)
+    KZ_SPMM_V(64, 64, 1) KZ_SPMM_V(64, 64, 2) KZ_SPMM_V(64, 64, 4) KZ_SPMM_V(64, 64, 8)
 #undef KZ_SPMM_V
     if (!v.fn) fail(KATZ_EDEVICE, "internal: no SpMM variant for this batch width");
     v.slot = (v.slot * 2 + (sizeof(T) == 8 ? 1 : 0)) * 2 + (weighted ? 1 : 0);
