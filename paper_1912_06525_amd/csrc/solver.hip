@@ -712,9 +712,10 @@ __global__ __launch_bounds__(WG) void k_m11_cols(M11Args<T> a) {
   }
 }
 
-// Block solve for blocks of at most S rows and B > 32 columns.  A wave takes
-// consecutive blocks (chunks of blocks_per_chunk, in XCD slabs) and all
-// columns, 64 * NCM of them per wave, lane = column within each group.  For
+// Block solve for blocks of at most S rows and B >= 5 columns.  A team of CW
+// lanes (8, 16, 32 or 64; WG / CW teams per workgroup) takes consecutive
+// blocks (chunks of blocks_per_chunk, in XCD slabs) and all columns, CW * NCM
+// of them per team, lane = column within each group.  For
 // each block the lane keeps the block's rows of
 //   u = ca (A12 x2) + cv v
 // in registers (the A12 part is the SpMM row gather over the entries right of
@@ -744,11 +745,13 @@ struct M11SmallArgs {
   const int* n_active;
 };
 
-template <typename T, int NCM, int S, bool VAL>
+template <typename T, int CW, int NCM, int S, bool VAL>
 __global__ __launch_bounds__(WG) void k_m11_small(M11SmallArgs<T> a) {
   if (a.n_active && *a.n_active == 0) return;
-  constexpr int CW = 64, TEAMS = WG / 64;
-  const int team = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64), cl = (int)threadIdx.x % 64;
+  constexpr int TEAMS = WG / CW;
+  // a 64-lane team is a wave: its block indices are wave-uniform (scalar loads)
+  const int team = CW == 64 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64) : (int)threadIdx.x / CW;
+  const int cl = (int)threadIdx.x % CW;
   const int B = a.B, NC = (B + CW - 1) / CW;
   int jc[NCM];
   bool jok[NCM];
@@ -763,8 +766,8 @@ __global__ __launch_bounds__(WG) void k_m11_small(M11SmallArgs<T> a) {
   for (int64_t ch = sl.first; ch < sl.end; ch += sl.stride) {
     const int bend = (int)min<int64_t>(a.nblocks, (ch + 1) * a.blocks_per_chunk);
     for (int b = (int)(ch * a.blocks_per_chunk) + team; b < bend; b += TEAMS) {
-      const int bs = __builtin_amdgcn_readfirstlane(a.blk_start[b]);
-      const int bsz = __builtin_amdgcn_readfirstlane(a.blk_start[b + 1]) - bs;
+      const int bs = CW == 64 ? __builtin_amdgcn_readfirstlane(a.blk_start[b]) : a.blk_start[b];
+      const int bsz = (CW == 64 ? __builtin_amdgcn_readfirstlane(a.blk_start[b + 1]) : a.blk_start[b + 1]) - bs;
       if (bsz > S) continue;
       const T* mi = a.minv + a.blk_off[b];
       T u[S][NCM];
@@ -1522,6 +1525,7 @@ struct Tuning {
   int m11_bpt;      // blocks per team and chunk of the batched small-block solve
   int autotune;     // tune the SpMM chunk walk per index (off when pinned by the environment)
   int m11_sub1;     // lanes per row of the A12 gather in the 1-3 column block solve
+  int m11_small_min;  // narrowest batch taking the register block solve (5..513; default 16)
 };
 static int env_int(const char* name, int dflt, int lo, int hi) {
   const char* e = getenv(name);
@@ -1544,6 +1548,7 @@ static const Tuning& tuning() {
     u.m11_bpt = env_int("KATZ_M11_BLOCKS_PER_TEAM", 1, 1, 64);
     u.autotune = env_int("KATZ_AUTOTUNE", 1, 0, 1) && !getenv("KATZ_XCD_SLAB") && !getenv("KATZ_SPMM_NWG");
     u.m11_sub1 = env_int("KATZ_M11_SUB", 4, 1, 16);
+    u.m11_small_min = env_int("KATZ_M11_SMALL_MIN", 16, 5, 513);
     if (u.m11_sub1 & (u.m11_sub1 - 1)) u.m11_sub1 = 4;  // a power of two (shuffle reduction)
     return u;
   }();
@@ -2585,40 +2590,44 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     const double wb = (double)sizeof(T) * B;
     double bytes = (double)sizeof(T) * D->minv_elems + 4.0 * n1 + wb * n1 + (v ? wb * n1 : 0.0) +
                    (x2 ? 8.0 * n1 + 4.0 * D->nnz_a12 + wb * D->cols_a12 : 0.0);
-    if (B > 32) {
+    if (B >= tuning().m11_small_min) {
       if (B > 512) fail(KATZ_EINVAL, "batch too wide for one launch");
-      // blocks of <= kSmallBlock rows in registers; larger ones by the tile
-      // kernel below (bytes split by row share)
+      // blocks of <= kSmallBlock rows in registers, a team of CW lanes per
+      // block; larger ones by the tile kernel below (bytes split by row share)
+      const int cw = B <= 8 ? 8 : (B <= 16 ? 16 : (B <= 32 ? 32 : 64));
       const Tuning& tu = tuning();
       M11SmallArgs<T> s;
       s.blk_start = D->blk_start; s.blk_off = D->blk_off; s.minv = a.minv;
       s.rp = D->rp; s.col = D->col; s.split = D->split; s.val = D->val;
       s.x = x2 ? x2 - (int64_t)n1 * B : nullptr;  // x2 is rows >= n1 of a full panel
       s.ca = (T)0; s.cb = (T)1; s.cu = ca; s.v = v; s.cv = cv; s.out = out;
-      s.B = B; s.nblocks = D->nblocks; s.blocks_per_chunk = (WG / 64) * tu.m11_bpt; s.xcd = tu.xcd;
+      s.B = B; s.nblocks = D->nblocks; s.blocks_per_chunk = (WG / cw) * tu.m11_bpt; s.xcd = tu.xcd;
       s.nchunks = (D->nblocks + s.blocks_per_chunk - 1) / s.blocks_per_chunk;
       s.n_active = nact;
       const dim3 g((unsigned)std::min<int64_t>(tu.spmm_nwg, s.nchunks));
       const double fb = n1 > 0 ? (double)D->big_rows / n1 : 0.0;
       L.timed(PK_M11, bytes * (1.0 - fb), [&] {
         const bool wv = s.val != nullptr;
-#define KZ_M11S(ncm)                                                                        \
-  if (wv) k_m11_small<T, ncm, kSmallBlock, true><<<g, WG, 0, st>>>(s);                      \
-  else k_m11_small<T, ncm, kSmallBlock, false><<<g, WG, 0, st>>>(s);
-        if (B <= 64) { KZ_M11S(1) } else if (B <= 128) { KZ_M11S(2) } else if (B <= 256) { KZ_M11S(4) }
-        else { KZ_M11S(8) }
+#define KZ_M11S(cw, ncm)                                                                    \
+  if (wv) k_m11_small<T, cw, ncm, kSmallBlock, true><<<g, WG, 0, st>>>(s);                  \
+  else k_m11_small<T, cw, ncm, kSmallBlock, false><<<g, WG, 0, st>>>(s);
+        if (cw == 8) { KZ_M11S(8, 1) } else if (cw == 16) { KZ_M11S(16, 1) } else if (cw == 32) { KZ_M11S(32, 1) }
+        else if (B <= 64) { KZ_M11S(64, 1) } else if (B <= 128) { KZ_M11S(64, 2) } else if (B <= 256) { KZ_M11S(64, 4) }
+        else { KZ_M11S(64, 8) }
 #undef KZ_M11S
       });
       if (D->n_big > 0) {
         a.tile_row0 = D->big_row0;
         a.tile_row1 = D->big_row1;
-        const int cbw = sizeof(T) == 8 ? 32 : 64;
+        const int cbw = B <= 16 ? 16 : ((B <= 32 || sizeof(T) == 8) ? 32 : 64);
         const size_t shm2 = (size_t)D->max_big_rows * cbw * sizeof(T);
         if (shm2 > 65536) fail(KATZ_EDEVICE, "internal: block too large for LDS");
         const dim3 gb((unsigned)D->n_big, (unsigned)((B + cbw - 1) / cbw));
         L.timed(PK_M11_BIG, bytes * fb, [&] {
           const bool wv = a.val != nullptr;
-          if (cbw == 32) {
+          if (cbw == 16) {
+            if (wv) k_m11_cols<T, 16, true><<<gb, WG, shm2, st>>>(a); else k_m11_cols<T, 16, false><<<gb, WG, shm2, st>>>(a);
+          } else if (cbw == 32) {
             if (wv) k_m11_cols<T, 32, true><<<gb, WG, shm2, st>>>(a); else k_m11_cols<T, 32, false><<<gb, WG, shm2, st>>>(a);
           } else {
             if (wv) k_m11_cols<T, 64, true><<<gb, WG, shm2, st>>>(a); else k_m11_cols<T, 64, false><<<gb, WG, shm2, st>>>(a);
