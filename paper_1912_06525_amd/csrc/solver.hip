@@ -1447,6 +1447,28 @@ __global__ void k_unpermute(int n, int B, const T* K, const int32_t* perm, doubl
     out[(int64_t)j * n + v] = (double)K[(int64_t)perm[v] * B + j];
 }
 
+// The same for wide batches, as a tiled transpose: a workgroup moves 64
+// nodes x 64 columns, reading 64 contiguous values of each node's (permuted)
+// row and writing 64 consecutive nodes of each column, through LDS (rows
+// padded by one element against bank conflicts).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_unpermute_tiled(int n, int B, const T* K, const int32_t* perm,
+                                                        double* out) {
+  constexpr int TV = 64, TJ = 64, RS = WG / 64;
+  __shared__ double tile[TV][TJ + 1];
+  const int v0 = blockIdx.x * TV, j0 = blockIdx.y * TJ;
+  const int tx = (int)threadIdx.x % 64, ty = (int)threadIdx.x / 64;
+  for (int r = ty; r < TV; r += RS) {
+    const int v = v0 + r, j = j0 + tx;
+    if (v < n && j < B) tile[r][tx] = (double)K[(int64_t)perm[v] * B + j];
+  }
+  __syncthreads();
+  for (int c = ty; c < TJ; c += RS) {
+    const int j = j0 + c, v = v0 + tx;
+    if (v < n && j < B) out[(int64_t)j * n + v] = tile[tx][c];
+  }
+}
+
 
 // ============================================================== profiling
 // Optional per-kernel timing: HIP events around each launch of the hot
@@ -3081,8 +3103,13 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
       double* dst = qa.scores + (int64_t)c0 * n;
       double* out = dst;
       if (!dev_scores) out = w->Rhs;  // free once the batch is solved
-      dim3 g(grid_for(n, WG * 4), B);
-      k_unpermute<double><<<g, WG, 0, st>>>(n, B, w->K, D->perm, out);
+      if (B >= 32) {
+        dim3 g((unsigned)((n + 63) / 64), (unsigned)((B + 63) / 64));
+        k_unpermute_tiled<double><<<g, WG, 0, st>>>(n, B, w->K, D->perm, out);
+      } else {
+        dim3 g(grid_for(n, WG * 4), B);
+        k_unpermute<double><<<g, WG, 0, st>>>(n, B, w->K, D->perm, out);
+      }
       if (!dev_scores)
         HIPCHECK(hipMemcpyAsync(dst, out, sizeof(double) * (size_t)n * B, hipMemcpyDeviceToHost, st));
     }
