@@ -226,3 +226,11 @@ def test_index_file_rejects_damage(tmp_path):
     # a good file still loads after all this
     b = K.KatzIndex.load(str(p), device=-1)
     assert b.info.n == n
+
+
+def test_query_option_defaults():
+    # documented defaults of katz_query_opts (the adaptive polling schedule
+    # is check_every = 0)
+    o = K.katz_query_opts_default()
+    assert o.rel_tol == 1e-6 and o.max_iter == 1000 and o.max_sweeps == 6
+    assert o.check_every == 0 and o.force_fallback == 0
