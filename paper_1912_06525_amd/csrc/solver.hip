@@ -68,6 +68,22 @@ __global__ void k_rhs_scatter(const int32_t* qpos, int B, const int32_t* rp, con
     b[(int64_t)col[k] * B + j] = (T)(beta * (val ? val[k] : 1.0));
 }
 
+// ||b_j||^2 from the query row itself (its entries are distinct columns): the
+// sum of (beta a_k)^2, one wave per column, instead of a pass over the panel.
+__global__ void k_rhs_norm2(const int32_t* qpos, int B, const int32_t* rp, const double* val, double beta,
+                            double* out) {
+  const int j = blockIdx.x;
+  if (j >= B) return;
+  const int32_t r = qpos[j];
+  double s = 0.0;
+  for (int32_t k = rp[r] + (int)threadIdx.x; k < rp[r + 1]; k += (int)blockDim.x) {
+    const double v = beta * (val ? val[k] : 1.0);
+    s += v * v;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
 // ------------------------------------------------------------------- SpMM
 // y[i] = cv v[i] + cw w[i] + ca (A_<split x)[i] + cb (A_>=split x)[i] for the
 // rows [row0, row1) of the permuted CSR; x is a full n-row panel, v, w, y are
@@ -2739,7 +2755,9 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     a.ep = EP_RR_INIT; a.dotv = nullptr; a.cs = cs; a.n_active = nullptr;
     L.spmm(a);
   }
-  L.fill<T>(Dx, (int64_t)n * B, (T)0);
+  // x2 (rows >= n1 of Dx) starts at 0; rows < n1 are written whole by the
+  // back-solve (a4) before anything reads them
+  L.fill<T>(K2, (int64_t)n2 * B, (T)0);
   precond_p(1);
 
   // ---- a3: PCG iterations, polled every check_every
@@ -2869,7 +2887,7 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
   };
   put_b();
   // K is not cleared: the first sweep writes it whole (below)
-  L.colnorm2<double>(w->Rhs, n, w->bn2);
+  k_rhs_norm2<<<B, 64, 0, st>>>(w->qpos, B, D->rp, D->val, D->beta, w->bn2);
   // thresholds and the first sweep's mask on the device (no host round trip)
   const double tol = o.rel_tol;
   k_cols_setup<<<1, WG, 0, st>>>(B, w->bn2, 0.25 * tol * tol, w->thr, w->mask);
