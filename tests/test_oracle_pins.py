@@ -1,7 +1,8 @@
 """Pins for the CPU oracle: each check compares it with something other than
-itself -- brute-force walk enumeration, closed forms derived by hand for
-complete, star and cycle graphs, symmetry, reachability, relabelling and the
-convergence condition (Section 3.1).  CPU only."""
+itself -- brute-force walk enumeration (plain and edge-weighted), closed
+forms derived by hand for complete, star, weighted star and cycle graphs,
+symmetry, reachability, relabelling and the convergence condition
+(Section 3.1).  CPU only."""
 import math
 
 import numpy as np
@@ -164,6 +165,83 @@ def test_walk_counts_golden():
         assert list(x) == gold["counts"][l]
 
 
+# ------------------------------------------------ weighted adjacency (P1, P2)
+def weighted_star(w):
+    """Star whose centre 0 joins leaf i (1..m) with weight w[i-1]; the CSR
+    values in entry order (row 0: leaves 1..m; row i: the centre)."""
+    m = len(w)
+    n, rp, col = star(m)
+    val = np.concatenate([np.asarray(w, np.float64), np.asarray(w, np.float64)])
+    return n, rp, col, val
+
+
+def _weighted_star_expected(w, c):
+    # A e_0 = w on the leaves and lambda_max = ||w||, so beta^2 sum w_i^2 = c^2.
+    # Centre query: k_i = beta w_i (1 + k_0), k_0 = beta sum w_i k_i
+    #   => k_0 = c^2 / (1 - c^2), k_i = beta w_i / (1 - c^2).
+    # Leaf query j: k_i = beta w_i k_0, k_0 = beta w_j + beta sum w_i k_i
+    #   => k_0 = beta w_j / (1 - c^2), k_i = beta^2 w_i w_j / (1 - c^2).
+    w = np.asarray(w, np.float64)
+    beta = c / np.linalg.norm(w)
+    d = 1 - c * c
+    centre = np.concatenate([[c * c / d], beta * w / d])
+    j = 2
+    leaf = np.concatenate([[beta * w[j - 1] / d], beta * beta * w * w[j - 1] / d])
+    return beta, centre, j, leaf
+
+
+@pytest.mark.parametrize("w,c", [([0.5, 1.7, 0.3, 2.0, 1.1], 0.5),
+                                 ([3.0, 0.25, 0.75], 0.9),
+                                 ([1.0, 1.0, 1.0, 1.0], 0.3)])
+def test_weighted_star_closed_form(w, c):
+    n, rp, col, val = weighted_star(w)
+    beta, centre, j, leaf = _weighted_star_expected(w, c)
+    out = oracle.katz_oracle(n, rp, col, [0, j], c=c, val=val, direct=True)
+    assert out["lambda_max"] == pytest.approx(np.linalg.norm(w), rel=1e-13)
+    assert out["beta"] == pytest.approx(beta, rel=1e-13)
+    for k in (out["k"], out["k_direct"]):
+        np.testing.assert_allclose(k[:, 0], centre, rtol=1e-12)
+        np.testing.assert_allclose(k[:, 1], leaf, rtol=1e-12)
+
+
+def _weighted_walk_sums(n, rp, col, val, q, L):
+    """sums[l][v] = sum over the walks q -> v with l edges of the product of
+    their edge weights, by depth-first enumeration of every walk (tiny graphs
+    only; no matrix products)."""
+    sums = [[0.0] * n for _ in range(L + 1)]
+
+    def walk(u, l, prod):
+        for e in range(rp[u], rp[u + 1]):
+            v, p = int(col[e]), prod * float(val[e])
+            sums[l + 1][v] += p
+            if l + 1 < L:
+                walk(v, l + 1, p)
+
+    walk(q, 0, 1.0)
+    return sums
+
+
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_weighted_walk_sum_matches_solver(name):
+    # eq. KatzPath with each walk counted by the product of its edge weights.
+    # Entrywise |(beta A)^l e_q| <= ||beta A||^l = c^l, so the terms beyond L
+    # add at most c^(L+1) / (1 - c) to any entry (and nothing negative).
+    n, edges = SMALL[name]
+    g = ki.from_edges(n, edges)
+    val = ki.edge_weights(g, seed=11)
+    L = 9
+    for c in (0.05, 0.5):
+        for q in range(n):
+            out = oracle.katz_oracle(g.n, g.row_ptr, g.col, [q], c=c, val=val, direct=True)
+            beta = out["beta"]
+            sums = _weighted_walk_sums(g.n, g.row_ptr, g.col, val, q, L)
+            trunc = np.array([sum(beta ** l * sums[l][v] for l in range(1, L + 1)) for v in range(n)])
+            bound = c ** (L + 1) / (1 - c)
+            for k in (out["k"][:, 0], out["k_direct"][:, 0]):
+                assert np.all(k >= trunc - 1e-14)
+                assert np.all(k - trunc <= bound + 1e-14)
+
+
 # ----------------------------------------------------------- P3, P4, P9
 def _small_sbm():
     return ki.sbm([40, 30, 50], [0.2, 0.25, 0.15], 0.02, seed=77)
@@ -299,6 +377,43 @@ def test_pins_catch_planted_mistakes(monkeypatch):
         got = series_only()
         assert not np.allclose(got, exp, rtol=1e-6), name
     monkeypatch.setattr(ko, "katz_rhs", orig_rhs)
+
+
+def test_weighted_pins_catch_planted_mistakes(monkeypatch):
+    """Plants mistakes in the oracle's handling of edge weights (on the CPU)
+    and checks that the weighted star closed form rejects each one."""
+    w = [0.5, 1.7, 0.3, 2.0, 1.1]
+    n, rp, col, val = weighted_star(w)
+    _, centre, j, leaf = _weighted_star_expected(w, 0.5)
+
+    def run():
+        out = oracle.katz_oracle(n, rp, col, [0, j], c=0.5, val=val, direct=False)
+        return out["k"]
+
+    good = run()
+    np.testing.assert_allclose(good[:, 0], centre, rtol=1e-12)
+    orig_csr, orig_lam = ko.csr_matrix, ko.lambda_max
+
+    def pattern_lambda(A):
+        B = A.copy()
+        B.data[:] = 1.0
+        return orig_lam(B)
+
+    mistakes = {
+        "weights dropped": (
+            "csr_matrix", lambda n_, rp_, col_, val_=None: orig_csr(n_, rp_, col_, None)),
+        "weights in reverse entry order": (
+            "csr_matrix", lambda n_, rp_, col_, val_=None: orig_csr(
+                n_, rp_, col_, None if val_ is None else np.asarray(val_)[::-1])),
+        "lambda_max of the unweighted pattern": ("lambda_max", pattern_lambda),
+    }
+    for name, (attr, bad) in mistakes.items():
+        monkeypatch.setattr(ko, attr, bad)
+        got = run()
+        assert not (np.allclose(got[:, 0], centre, rtol=1e-6)
+                    and np.allclose(got[:, 1], leaf, rtol=1e-6)), name
+        monkeypatch.setattr(ko, "csr_matrix", orig_csr)
+        monkeypatch.setattr(ko, "lambda_max", orig_lam)
 
 
 # ------------------------------------------------ residual (P8 support)
