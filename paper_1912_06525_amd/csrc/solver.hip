@@ -1016,7 +1016,12 @@ __device__ inline void stage_v(double* sV, const TV* V, int64_t m, int rank, int
 
 // W partials: partials[blockIdx.x * rank * B + k * B + j] = sum over the
 // chunk's rows i of V[i][k] r[i][j] (FP64 sums).
-template <typename T, typename TV, int RMAX>
+// DIRECT (narrow batches, JW <= 8): no LDS tile; each thread issues all the
+// factor loads of its row at once (columns past the rank repeat the last
+// one, their sums unused), so many loads are in flight per wave instead of
+// one block's staging per barrier pair.  A thread visits rows r0 + rg,
+// r0 + rg + NR, ... as the staged form does when NR divides the block height.
+template <typename T, typename TV, int RMAX, bool DIRECT = false>
 __global__ __launch_bounds__(WG) void k_vt_rows(int64_t m, int B, int rank, int JW, const TV* V, const T* r,
                                                 int64_t rpc, double* partials, const int* n_active) {
   if (n_active && *n_active == 0) return;
@@ -1029,17 +1034,31 @@ __global__ __launch_bounds__(WG) void k_vt_rows(int64_t m, int B, int rank, int 
   double acc[RMAX];
 #pragma unroll
   for (int k = 0; k < RMAX; k++) acc[k] = 0.0;
-  for (int64_t b0 = r0; b0 < r1; b0 += kVRows) {
-    const int nb = (int)min<int64_t>(kVRows, r1 - b0);
-    __syncthreads();
-    stage_v<TV, RMAX>(sV, V, m, rank, b0, nb);
-    __syncthreads();
+  if (DIRECT) {
     if (col_ok) {
-      for (int ii = rg; ii < nb; ii += NR) {
-        const double x = (double)r[(b0 + ii) * B + j];
-        const double* vr = sV + ii * LD;
+      for (int64_t i = r0 + rg; i < r1; i += NR) {
+        TV vv[RMAX];
 #pragma unroll
-        for (int k = 0; k < RMAX; k++) acc[k] += vr[k] * x;
+        for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+        const double x = (double)r[i * B + j];
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the FMAs
+#pragma unroll
+        for (int k = 0; k < RMAX; k++) acc[k] += to_d(vv[k]) * x;
+      }
+    }
+  } else {
+    for (int64_t b0 = r0; b0 < r1; b0 += kVRows) {
+      const int nb = (int)min<int64_t>(kVRows, r1 - b0);
+      __syncthreads();
+      stage_v<TV, RMAX>(sV, V, m, rank, b0, nb);
+      __syncthreads();
+      if (col_ok) {
+        for (int ii = rg; ii < nb; ii += NR) {
+          const double x = (double)r[(b0 + ii) * B + j];
+          const double* vr = sV + ii * LD;
+#pragma unroll
+          for (int k = 0; k < RMAX; k++) acc[k] += vr[k] * x;
+        }
       }
     }
   }
@@ -1100,7 +1119,9 @@ __global__ __launch_bounds__(WG) void k_vt_reduce(const double* partials, int nc
 // the per-column <r, z> partials[blockIdx.x * B + j] over the chunk's rows.
 // PUPD: as in k_lowrank1, z holds the search direction p, updated in place
 // (p <- z_new + bcg p, p <- z_new at init) for the active columns, no partials.
-template <typename T, typename TV, int RMAX, bool PUPD = false>
+// DIRECT: as in k_vt_rows (factor loads of a row issued together, no LDS
+// tile); the same value per element (DW is 0 past the rank).
+template <typename T, typename TV, int RMAX, bool PUPD = false, bool DIRECT = false>
 __global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank, int JW, const TV* V,
                                                      const double* DW, const T* r, T* z, int z_has_base,
                                                      int64_t rpc, const int* n_active, double* partials,
@@ -1118,26 +1139,50 @@ __global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank,
 #pragma unroll
   for (int k = 0; k < RMAX; k++) dw[k] = (col_ok && k < rank) ? DW[(int64_t)k * B + j] : 0.0;
   double dacc = 0.0;
-  for (int64_t b0 = r0; b0 < r1; b0 += kVRows) {
-    const int nb = (int)min<int64_t>(kVRows, r1 - b0);
-    __syncthreads();
-    stage_v<TV, RMAX>(sV, V, m, rank, b0, nb);
-    __syncthreads();
+  if (DIRECT) {
     if (col_ok) {
-      for (int ii = rg; ii < nb; ii += NR) {
-        const int64_t o = (b0 + ii) * B + j;
+      for (int64_t i = r0 + rg; i < r1; i += NR) {
+        TV vv[RMAX];
+#pragma unroll
+        for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+        const int64_t o = i * B + j;
         const double rv = (double)r[o];
         const double pv = PUPD && !init ? (double)z[o] : 0.0;
         double sum = !PUPD && z_has_base ? (double)z[o] : rv;
-        const double* vr = sV + ii * LD;
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the FMAs
 #pragma unroll
-        for (int k = 0; k < RMAX; k++) sum += vr[k] * dw[k];
+        for (int k = 0; k < RMAX; k++) sum += to_d(vv[k]) * dw[k];
         if (PUPD) {
           z[o] = (T)(sum + b * pv);
         } else {
           const T zv = (T)sum;
           z[o] = zv;
           dacc += rv * (double)zv;
+        }
+      }
+    }
+  } else {
+    for (int64_t b0 = r0; b0 < r1; b0 += kVRows) {
+      const int nb = (int)min<int64_t>(kVRows, r1 - b0);
+      __syncthreads();
+      stage_v<TV, RMAX>(sV, V, m, rank, b0, nb);
+      __syncthreads();
+      if (col_ok) {
+        for (int ii = rg; ii < nb; ii += NR) {
+          const int64_t o = (b0 + ii) * B + j;
+          const double rv = (double)r[o];
+          const double pv = PUPD && !init ? (double)z[o] : 0.0;
+          double sum = !PUPD && z_has_base ? (double)z[o] : rv;
+          const double* vr = sV + ii * LD;
+#pragma unroll
+          for (int k = 0; k < RMAX; k++) sum += vr[k] * dw[k];
+          if (PUPD) {
+            z[o] = (T)(sum + b * pv);
+          } else {
+            const T zv = (T)sum;
+            z[o] = zv;
+            dacc += rv * (double)zv;
+          }
         }
       }
     }
@@ -1564,6 +1609,7 @@ struct Tuning {
   int autotune;     // tune the SpMM chunk walk per index (off when pinned by the environment)
   int m11_sub1;     // lanes per row of the A12 gather in the 1-3 column block solve
   int m11_small_min;  // narrowest batch taking the register block solve (5..513; default 16)
+  int lr_direct;    // widest column group (JW) of the unstaged narrow low-rank kernels (0: never)
 };
 static int env_int(const char* name, int dflt, int lo, int hi) {
   const char* e = getenv(name);
@@ -1587,6 +1633,7 @@ static const Tuning& tuning() {
     u.autotune = env_int("KATZ_AUTOTUNE", 1, 0, 1) && !getenv("KATZ_XCD_SLAB") && !getenv("KATZ_SPMM_NWG");
     u.m11_sub1 = env_int("KATZ_M11_SUB", 4, 1, 16);
     u.m11_small_min = env_int("KATZ_M11_SMALL_MIN", 16, 5, 513);
+    u.lr_direct = env_int("KATZ_LR_DIRECT_MAX", 8, 0, 16);
     if (u.m11_sub1 & (u.m11_sub1 - 1)) u.m11_sub1 = 4;  // a power of two (shuffle reduction)
     return u;
   }();
@@ -1694,6 +1741,9 @@ struct DeviceIndex {
   // iterations the last solve of each kind needed (method x precision x first
   // or later sweep; 0: none yet), the first poll of the adaptive schedule
   std::atomic<int32_t> iter_hint[8];
+  // workgroups of the unstaged narrow V^T r kernel resident at once, per
+  // panel precision (FP64, FP32; 0: not sized, the default grid applies)
+  std::atomic<int32_t> lr_resident[2];
 };
 constexpr int kLongRow = 256;
 // HIP graphs of iteration chunks kept per workspace.
@@ -1779,6 +1829,7 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
   auto D = new DeviceIndex();
   for (auto& x : D->walk) x.store(-1);
   for (auto& x : D->iter_hint) x.store(0);
+  for (auto& x : D->lr_resident) x.store(0);
   try {
     D->device = device;
     D->n = H.n;
@@ -2397,6 +2448,90 @@ static void with_lowrank_factor(const DeviceIndex* D, F&& f) {
     f(D->V);
 }
 
+// The row-blocked low-rank kernels for rank <= 64 (RMAX from the rank).
+template <typename T, typename TV, bool DIRECT>
+static void launch_vt_rows(dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V, const T* R2,
+                           int64_t rpc, double* partials, const int* nact) {
+  if (rk <= 8) k_vt_rows<T, TV, 8, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
+  else if (rk <= 16) k_vt_rows<T, TV, 16, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
+  else if (rk <= 32) k_vt_rows<T, TV, 32, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
+  else k_vt_rows<T, TV, 64, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
+}
+template <typename T, typename TV, bool PUPD, bool DIRECT>
+static void launch_lowrank_rows(dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V,
+                                const double* DW, const T* R2, T* Z2, int has_base, int64_t rpc, const int* nact,
+                                double* partials, const double* bcg, const int* active, int init) {
+  if (rk <= 8)
+    k_lowrank_rows<T, TV, 8, PUPD, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
+                                                             partials, bcg, active, init);
+  else if (rk <= 16)
+    k_lowrank_rows<T, TV, 16, PUPD, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
+                                                              partials, bcg, active, init);
+  else if (rk <= 32)
+    k_lowrank_rows<T, TV, 32, PUPD, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
+                                                              partials, bcg, active, init);
+  else
+    k_lowrank_rows<T, TV, 64, PUPD, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
+                                                              partials, bcg, active, init);
+}
+template <typename T, typename TV>
+static void vt_rows(bool direct, dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V,
+                    const T* R2, int64_t rpc, double* partials, const int* nact) {
+  if (direct) launch_vt_rows<T, TV, true>(g, st, m, B, rk, JW, V, R2, rpc, partials, nact);
+  else launch_vt_rows<T, TV, false>(g, st, m, B, rk, JW, V, R2, rpc, partials, nact);
+}
+template <typename T, typename TV, bool PUPD>
+static void lowrank_rows(bool direct, dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V,
+                         const double* DW, const T* R2, T* Z2, int has_base, int64_t rpc, const int* nact,
+                         double* partials, const double* bcg = nullptr, const int* active = nullptr,
+                         int init = 0) {
+  if (direct)
+    launch_lowrank_rows<T, TV, PUPD, true>(g, st, m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact, partials, bcg,
+                                           active, init);
+  else
+    launch_lowrank_rows<T, TV, PUPD, false>(g, st, m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact, partials,
+                                            bcg, active, init);
+}
+
+// Narrow batches run the unstaged kernels over one resident round of
+// workgroups (so no chunk waits for a second round): the count is queried
+// once per index and panel precision, outside HIP-graph capture, at the start
+// of a solve; until then the default grid applies.
+template <typename T, typename TV>
+static const void* vt_rows_direct_fn(int rk) {
+  if (rk <= 8) return (const void*)k_vt_rows<T, TV, 8, true>;
+  if (rk <= 16) return (const void*)k_vt_rows<T, TV, 16, true>;
+  if (rk <= 32) return (const void*)k_vt_rows<T, TV, 32, true>;
+  return (const void*)k_vt_rows<T, TV, 64, true>;
+}
+template <typename T>
+static void size_lowrank_rows(DeviceIndex* D, hipStream_t st) {
+  const int slot = std::is_same<T, float>::value ? 1 : 0;
+  if (!tuning().lr_direct || D->rank <= 0 || D->rank > 64) return;
+  if (D->lr_resident[slot].load(std::memory_order_acquire) > 0) return;
+  hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+  HIPCHECK(hipStreamIsCapturing(st, &cst));
+  if (cst != hipStreamCaptureStatusNone) return;
+  with_lowrank_factor<T>(D, [&](auto* V) {
+    typedef typename std::remove_cv<typename std::remove_pointer<decltype(V)>::type>::type TV;
+    int per_cu = 0, cus = 0;
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, vt_rows_direct_fn<T, TV>(D->rank), WG, 0));
+    HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, D->device));
+    D->lr_resident[slot].store(std::min(4096, std::max(1, per_cu) * std::max(1, cus)), std::memory_order_release);
+  });
+}
+// Rows per chunk of the row-blocked low-rank kernels: 1024 chunks, or one
+// resident round for the unstaged form once sized.
+template <typename T>
+static int64_t lowrank_rows_rpc(const DeviceIndex* D, int64_t m, bool direct) {
+  int64_t chunks = 1024;
+  if (direct) {
+    const int res = D->lr_resident[std::is_same<T, float>::value ? 1 : 0].load(std::memory_order_acquire);
+    if (res > 0) chunks = res;
+  }
+  return std::max<int64_t>(kVRows, (m + chunks - 1) / chunks);
+}
+
 // Rank-r preconditioner with the row-parallel kernels (any B, V of type TV):
 // DW = D o (V^T r), then z = G r + V DW (G = M22^{-1} or I) with <r, z>.
 // Preconditioner for B >= 2 columns and rank <= 64 with the row-blocked
@@ -2413,16 +2548,14 @@ static void precond_rows(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, c
   int JW = 1;
   while (JW < B && JW < WG) JW <<= 1;
   const int njt = (B + JW - 1) / JW;
-  const int64_t rpc = std::max<int64_t>(kVRows, (m + 1023) / 1024);
+  const bool direct = JW <= tuning().lr_direct;
+  const int64_t rpc = lowrank_rows_rpc<T>(D, m, direct);
   const int nchunk = (int)((m + rpc - 1) / rpc);
   const int64_t nv = (int64_t)rk * B;
   dim3 g((unsigned)nchunk, (unsigned)njt);
   L.need(nchunk, nv);
   L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
-    if (rk <= 8) k_vt_rows<T, TV, 8><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
-    else if (rk <= 16) k_vt_rows<T, TV, 16><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
-    else if (rk <= 32) k_vt_rows<T, TV, 32><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
-    else k_vt_rows<T, TV, 64><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
+    vt_rows<T, TV>(direct, g, st, m, B, rk, JW, V, R2, rpc, w->partials, nact);
   });
   k_vt_reduce<<<(unsigned)((nv + 63) / 64), WG, 0, st>>>(w->partials, nchunk, nv, B, D->D, w->DW, nact);
   int has_base = 0;
@@ -2434,14 +2567,7 @@ static void precond_rows(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, c
   }
   L.need(nchunk, B);
   L.timed(PK_LOWRANK, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m * (2 + has_base), [&] {
-    if (rk <= 8)
-      k_lowrank_rows<T, TV, 8><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials);
-    else if (rk <= 16)
-      k_lowrank_rows<T, TV, 16><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials);
-    else if (rk <= 32)
-      k_lowrank_rows<T, TV, 32><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials);
-    else
-      k_lowrank_rows<T, TV, 64><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials);
+    lowrank_rows<T, TV, false>(direct, g, st, m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials);
   });
   L.finalize(nchunk, B, ep, cs, nullptr, nact);
 }
@@ -2544,32 +2670,20 @@ static void precond_fused(Launcher& L, const TV* V, const T* R2, T* P2, int init
   int JW = 1;
   while (JW < B && JW < WG) JW <<= 1;
   const int njt = (B + JW - 1) / JW;
-  const int64_t rpc = std::max<int64_t>(kVRows, (m + 1023) / 1024);
+  const bool direct = JW <= tuning().lr_direct;
+  const int64_t rpc = lowrank_rows_rpc<T>(D, m, direct);
   const int nchunk = (int)((m + rpc - 1) / rpc);
   const int64_t nv = (int64_t)rk * B;
   dim3 g((unsigned)nchunk, (unsigned)njt);
   L.need(nchunk, nv);
   L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
-    if (rk <= 8) k_vt_rows<T, TV, 8><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
-    else if (rk <= 16) k_vt_rows<T, TV, 16><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
-    else if (rk <= 32) k_vt_rows<T, TV, 32><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
-    else k_vt_rows<T, TV, 64><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, w->partials, nact);
+    vt_rows<T, TV>(direct, g, st, m, B, rk, JW, V, R2, rpc, w->partials, nact);
   });
   k_vt_reduce<<<(unsigned)((nv + 63) / 64), WG, 0, st>>>(w->partials, nchunk, nv, B, D->D, w->DW, nact, w->DW2);
   k_rz_lowrank<<<1, WG, 0, st>>>(rk, B, w->DW2, init, cs, nact);
   L.timed(PK_LOWRANK, pbytes, [&] {
-    if (rk <= 8)
-      k_lowrank_rows<T, TV, 8, true><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr,
-                                                         cs.bcg, cs.active, init);
-    else if (rk <= 16)
-      k_lowrank_rows<T, TV, 16, true><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr,
-                                                          cs.bcg, cs.active, init);
-    else if (rk <= 32)
-      k_lowrank_rows<T, TV, 32, true><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr,
-                                                          cs.bcg, cs.active, init);
-    else
-      k_lowrank_rows<T, TV, 64, true><<<g, WG, 0, st>>>(m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr,
-                                                          cs.bcg, cs.active, init);
+    lowrank_rows<T, TV, true>(direct, g, st, m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr, cs.bcg,
+                              cs.active, init);
   });
 }
 
@@ -2744,6 +2858,7 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     a.x = X; a.ca = -beta; a.cb = -beta; a.parts = 3; a.y = Q2; a.cs = cs;
     L.tune_spmm(a);
   }
+  size_lowrank_rows<T>(D, st);  // grid of the narrow low-rank kernels, before their first launch
 
   // ---- a2: t = M11^{-1} b1 -> X[0:n1]; f = b2 + beta A21 t -> R2; rr
   m11(rhs, (T)1, nullptr, (T)0, X, nullptr);
