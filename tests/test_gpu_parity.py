@@ -88,6 +88,21 @@ def test_small_sbm_both_factors(lk, c, order):
     _check(g, idx, beta, qs, 1e-6)
 
 
+@pytest.mark.parametrize("prec", [K.KATZ_PREC_FP64, K.KATZ_PREC_MIXED])
+@pytest.mark.parametrize("lk", [K.KATZ_L_CHOL, K.KATZ_L_IDENTITY])
+@pytest.mark.parametrize("B", [2, 3])
+def test_narrow_batches_match_oracle(B, lk, prec):
+    # 2 and 3 columns through the narrow low-rank kernels: 128 row groups per
+    # workgroup (2 columns) and a column lane past the batch (3 of 4), with the
+    # unfused (CHOL) and fused (identity) preconditioner in both precisions
+    g = ki.workload("lnsbm4m", scale=0.0006 if lk == K.KATZ_L_CHOL else 0.002).graph
+    beta = oracle_beta(g, 0.9)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=16, labels=g.labels, max_block=32, l_kind=lk,
+                                 precision=prec)
+    qs = ki.sample_queries(g, B, 41)
+    _check(g, idx, beta, qs, 1e-6)
+
+
 def test_closed_forms_through_gpu():
     import math
     # star with m leaves: K_c,leaf = beta/d, K_leaf,leaf' = beta^2/d, d = 1 - m beta^2
