@@ -998,11 +998,13 @@ __global__ __launch_bounds__(WG) void k_lowrank1(int64_t m, int rank, const TV* 
 // ------------------------------------- low-rank products for B >= 2 columns
 // Both kernels give thread t of a workgroup one panel column,
 // j = blockIdx.y * JW + t % JW (JW: a power of two <= 256 covering B, or 256),
-// and WG / JW row groups; blockIdx.x is a chunk of rpc rows.  The rows of V
-// (column-major n2 x rank) of a 64-row block are staged in LDS as a row-major
-// tile (stride RMAX + 2 doubles: rows of different row groups fall in
-// different banks), so each panel element is read once and each V value once
-// per workgroup.  Ranks above `rank` (up to RMAX) are staged as 0.
+// and WG / JW row groups; blockIdx.x is a chunk of rpc rows.  In the staged
+// form (16 columns and more) the rows of V (column-major n2 x rank) of a
+// 64-row block are staged in LDS as a row-major tile (stride RMAX + 2
+// doubles: rows of different row groups fall in different banks), so each
+// panel element is read once and each V value once per workgroup.  Ranks
+// above `rank` (up to RMAX) are staged as 0.  Narrower batches take the
+// unstaged form (DIRECT below).
 constexpr int kVRows = 64;
 
 template <typename TV, int RMAX>
