@@ -79,10 +79,14 @@ void validate_index(const HostIndex& H) {
   if ((int64_t)H.rp.size() != n + 1 || (int64_t)H.col.size() != H.nnz || (int64_t)H.split.size() != n)
     bad("CSR sizes");
   if (H.weighted ? (int64_t)H.val.size() != H.nnz : !H.val.empty()) bad("value array size");
+  // row pointers non-decreasing from 0 to nnz (all of them before any row's
+  // entries are read: a pointer past the entries with a smaller one after it
+  // would otherwise be followed first)
   if (H.rp[0] != 0 || H.rp[n] != H.nnz) bad("row pointers");
+  for (int64_t i = 0; i < n; i++)
+    if (H.rp[i + 1] < H.rp[i]) bad("row pointers");
   for (int64_t i = 0; i < n; i++) {
     const int32_t s = H.rp[i], e = H.rp[i + 1];
-    if (e < s) bad("row pointers");
     if (H.split[i] < s || H.split[i] > e) bad("split points");
     for (int32_t k = s; k < e; k++) {
       const int32_t c = H.col[k];
@@ -109,12 +113,16 @@ void validate_index(const HostIndex& H) {
   }
   // blocks: contiguous, at most kMaxBlockRows rows, covering [0, n1), no
   // entries between different blocks, inverses of b x b each
+  // (block sizes first, so every block lies in [0, n1) before its rows are read)
   const size_t nb1 = H.blk_start.size();
   if (nb1 < 1 || H.blk_start[0] != 0 || H.blk_start[nb1 - 1] != H.n1) bad("block starts");
   if (H.blk_off.size() != nb1 || H.blk_off[0] != 0) bad("block offsets");
   for (size_t b = 0; b + 1 < nb1; b++) {
     const int64_t sz = (int64_t)H.blk_start[b + 1] - H.blk_start[b];
     if (sz < 1 || sz > kMaxBlockRows) bad("block size");
+  }
+  for (size_t b = 0; b + 1 < nb1; b++) {
+    const int64_t sz = (int64_t)H.blk_start[b + 1] - H.blk_start[b];
     if (H.blk_off[b + 1] - H.blk_off[b] != sz * sz) bad("block offsets");
     for (int32_t i = H.blk_start[b]; i < H.blk_start[b + 1]; i++)
       for (int32_t k = H.rp[i]; k < H.split[i]; k++)

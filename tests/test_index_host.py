@@ -223,9 +223,40 @@ def test_index_file_rejects_damage(tmp_path):
     bad = bytearray(raw)
     bad[off:off + 4] = (n + 5).to_bytes(4, "little")  # column out of range
     assert load_code(bad, "col.katz") == K.KATZ_EINVAL
+    # row pointers out of order: one past the entries with the last in place
+    # (must be rejected before any row is read through it)
+    arr = _index_arrays(raw)
+    rp_at, nb1 = arr["rp"][0], arr["blk_start"][1]
+    bad = bytearray(raw)
+    nnz = int.from_bytes(raw[rp_at + 4 * n:rp_at + 4 * n + 4], "little")
+    bad[rp_at + 4 * (n - 1):rp_at + 4 * n] = (nnz + 5).to_bytes(4, "little")
+    assert load_code(bad, "rowptr.katz") == K.KATZ_EINVAL
+    # a block start past the last block's end (block sizes must be checked
+    # before any block's rows are read)
+    bs_at = arr["blk_start"][0]
+    n1 = int.from_bytes(raw[bs_at + 4 * (nb1 - 1):bs_at + 4 * nb1], "little")
+    bad = bytearray(raw)
+    bad[bs_at + 4 * (nb1 - 2):bs_at + 4 * (nb1 - 1)] = (n1 + 3).to_bytes(4, "little")
+    assert load_code(bad, "blkstart.katz") == K.KATZ_EINVAL
     # a good file still loads after all this
     b = K.KatzIndex.load(str(p), device=-1)
     assert b.info.n == n
+
+
+def _index_arrays(raw):
+    """name -> (offset of the first element, element count) of every array of
+    an index file: 100 header bytes, then each array as a u64 count and its
+    elements, in the order the writer puts them."""
+    order = [("perm", 4), ("iperm", 4), ("rp", 4), ("col", 4), ("split", 4), ("val", 8),
+             ("blk_start", 4), ("blk_off", 8), ("minv", 8), ("ginv", 8), ("lchol", 8),
+             ("U", 8), ("V", 8), ("sigma", 8), ("D", 8)]
+    out, at = {}, 100
+    for name, esz in order:
+        cnt = int.from_bytes(raw[at:at + 8], "little")
+        out[name] = (at + 8, cnt)
+        at += 8 + esz * cnt
+    assert at == len(raw)
+    return out
 
 
 def test_query_option_defaults():
