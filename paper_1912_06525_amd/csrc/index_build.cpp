@@ -221,12 +221,18 @@ void validate(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col, con
   if (!rp || (nnz > 0 && !col)) fail(KATZ_EINVAL, "null CSR array");
   if (nnz < 0 || nnz >= INT32_MAX) fail(KATZ_EINVAL, "nnz must be in [0, 2^31-1)");
   if (rp[0] != 0 || rp[n] != nnz) fail(KATZ_EINVAL, "row_ptr must start at 0 and end at nnz");
+  // every row pointer first: non-decreasing from 0 to nnz keeps each row's
+  // range, and the partner rows the symmetry check searches, inside col
   std::atomic<int> bad{0};
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; i++)
+      if (rp[i + 1] < rp[i]) { bad = 1; break; }
+  }, 8192);
+  if (bad.load()) fail(KATZ_EINVAL, "row_ptr is not non-decreasing");
   std::atomic<int> asym{0};
   parallel_for(n, [&](int64_t b, int64_t e) {
     for (int64_t i = b; i < e && !bad.load(std::memory_order_relaxed); i++) {
       int32_t s = rp[i], t = rp[i + 1];
-      if (t < s) { bad = 1; break; }
       int32_t last = -1;
       for (int32_t k = s; k < t; k++) {
         int32_t j = col[k];
@@ -244,7 +250,6 @@ void validate(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col, con
     }
   }, 2048);
   switch (bad.load()) {
-    case 1: fail(KATZ_EINVAL, "row_ptr is not non-decreasing");
     case 2: fail(KATZ_EINVAL, "column index out of range");
     case 3: fail(KATZ_EINVAL, "columns must be strictly increasing within a row");
     case 4: fail(KATZ_EINVAL, "diagonal entries (self loops) are not allowed");

@@ -141,6 +141,12 @@ def test_error_codes():
     with pytest.raises(K.KatzError) as e:
         K.KatzIndex(3, [0, 2, 3, 4], [2, 1, 0, 0], beta=0.1, device=-1)
     assert e.value.code == K.KATZ_EINVAL
+    # a row pointer past the entries with a smaller one after it: rejected by
+    # the row-pointer pass before any row (or symmetric partner) is read
+    with pytest.raises(K.KatzError) as e:
+        K.KatzIndex(8, [0, 1, 2, 3, 4, 5, 6, 14, 12], [6, 6, 6, 6, 6, 6, 0, 1, 2, 3, 4, 5], beta=0.1,
+                    device=-1)
+    assert e.value.code == K.KATZ_EINVAL
     idx = K.KatzIndex.from_graph(g, beta_frac=0.5, device=-1, rank=0)
     with pytest.raises(K.KatzError) as e:
         idx.query([0])
