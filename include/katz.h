@@ -311,7 +311,8 @@ void katz_server_opts_default(katz_server_opts* o);
  * KATZ_EDEVICE (host-only index), KATZ_ENOMEM. */
 int katz_server_create(const katz_index* idx, const katz_server_opts* opts, katz_server** out);
 /* Queues a request of nq query nodes (copied); returns at once with a ticket.
- * Errors: KATZ_EINVAL (bad ids), KATZ_EBUSY (server stopping). */
+ * Errors: KATZ_EINVAL (bad ids), KATZ_EBUSY (server stopping), KATZ_ENOMEM
+ * (host memory for the request's nq x k result slots). */
 int katz_server_submit(katz_server* s, const int32_t* q, int32_t nq, int64_t* ticket);
 /* Waits up to timeout_us (0: do not wait, < 0: forever) for a request; when it
  * is complete copies ids[nq*k], scores[nq*k], st[nq] (each nullable) and the

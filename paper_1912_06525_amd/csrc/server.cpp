@@ -241,20 +241,33 @@ int katz_server_submit(katz_server* S, const int32_t* q, int32_t nq, int64_t* ti
   const int32_t n = s.idx->host.n;
   for (int32_t i = 0; i < nq; i++)
     if (q[i] < 0 || q[i] >= n) return KATZ_EINVAL;
-  auto r = std::make_shared<katz::Request>();
-  r->q.assign(q, q + nq);
-  r->ids.assign((size_t)nq * s.k, -1);
-  r->scores.assign((size_t)nq * s.k, 0.0);
-  r->st.assign(nq, katz_query_stats{});
-  r->remaining = nq;
-  r->t_submit = Clock::now();
-  {
-    std::lock_guard<std::mutex> g(s.mu);
-    if (s.stop) return KATZ_EBUSY;
-    r->ticket = s.next_ticket++;
-    s.live[r->ticket] = r;
-    s.queue.push_back(r);
-    *ticket = r->ticket;
+  try {
+    // the request's result slots (nq x k) are allocated here: a host
+    // allocation failure is reported, never thrown across the C ABI
+    auto r = std::make_shared<katz::Request>();
+    r->q.assign(q, q + nq);
+    r->ids.assign((size_t)nq * s.k, -1);
+    r->scores.assign((size_t)nq * s.k, 0.0);
+    r->st.assign(nq, katz_query_stats{});
+    r->remaining = nq;
+    r->t_submit = Clock::now();
+    {
+      std::lock_guard<std::mutex> g(s.mu);
+      if (s.stop) return KATZ_EBUSY;
+      r->ticket = s.next_ticket++;
+      s.live[r->ticket] = r;
+      try {
+        s.queue.push_back(r);
+      } catch (...) {
+        s.live.erase(r->ticket);
+        throw;
+      }
+      *ticket = r->ticket;
+    }
+  } catch (const std::bad_alloc&) {
+    return KATZ_ENOMEM;
+  } catch (...) {
+    return KATZ_EDEVICE;
   }
   s.cv_work.notify_one();
   return KATZ_OK;
