@@ -52,7 +52,7 @@ enum katz_status {
   KATZ_ENOMEM = -4,   /* host or device allocation failed */
   KATZ_EDEVICE = -5,  /* HIP error, or index built without a device */
   KATZ_ENOCONV = -6,  /* some query missed the tolerance (see stats) */
-  KATZ_EBUSY = -7,    /* server queue full */
+  KATZ_EBUSY = -7,    /* server: request still running (poll), server stopping (submit) */
   KATZ_EIO = -8       /* file error or corrupt index file */
 };
 
@@ -317,8 +317,9 @@ int katz_server_submit(katz_server* s, const int32_t* q, int32_t nq, int64_t* ti
 /* Waits up to timeout_us (0: do not wait, < 0: forever) for a request; when it
  * is complete copies ids[nq*k], scores[nq*k], st[nq] (each nullable) and the
  * submit-to-completion latency, releases the ticket and returns its status
- * (KATZ_OK or KATZ_ENOCONV).  KATZ_EBUSY if still running, KATZ_EINVAL for an
- * unknown ticket. */
+ * (KATZ_OK, KATZ_ENOCONV, or the error of a batch that failed, e.g.
+ * KATZ_EDEVICE).  KATZ_EBUSY if still running, KATZ_EINVAL for an unknown
+ * ticket. */
 int katz_server_poll(katz_server* s, int64_t ticket, int32_t* ids, double* scores, katz_query_stats* st,
                      double* latency_ms, int64_t timeout_us);
 int katz_server_info(katz_server* s, katz_server_info_t* info);
