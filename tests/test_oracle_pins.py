@@ -320,6 +320,28 @@ def test_series_and_direct_agree_on_sbm(c):
     assert np.all(out["k"] >= 0)
 
 
+@pytest.mark.parametrize("c", [0.3, 0.8, 0.97])
+def test_series_tail_bound_holds(c):
+    # With a loose stopping tolerance the truncation error is far above
+    # rounding, so the reported tail bound ||v_L|| c / (1 - c) is tested for
+    # real against the dense solve: the dropped tail lies below it and is a
+    # real fraction of it, and (every term >= 0) the truncated sum lies below
+    # the exact solution entrywise.  A wrong ratio (c in place of c / (1 - c))
+    # breaks the first check at every c here (error 1.3x to 33x the bound).
+    g = ki.workload("sbm2k", scale=0.3).graph
+    qs = ki.sample_queries(g, 3, 5)
+    A = ko.csr_matrix(g.n, g.row_ptr, g.col)
+    beta = c / ko.lambda_max(A)
+    kd = ko.katz_direct(A, beta, qs)
+    ks, terms, tail = ko.katz_series(A, beta, qs, c, tol=1e-4)
+    err = np.linalg.norm(kd - ks, axis=0)
+    nk = np.linalg.norm(kd, axis=0)
+    assert np.all(err <= tail + 1e-12 * nk), (err, tail)
+    assert np.all(err >= 0.05 * tail), (err, tail)
+    assert np.all(ks <= kd + 1e-12 * np.abs(kd).max())
+    assert np.all(tail <= 1e-4 * np.linalg.norm(ks, axis=0) * (1 + 1e-12))
+
+
 # ------------------------------------------------------------------ top-K
 def test_topk_star_leaf_query_ties_by_id():
     n, rp, col = star(6)
