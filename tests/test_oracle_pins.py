@@ -320,6 +320,19 @@ def test_series_and_direct_agree_on_sbm(c):
     assert np.all(out["k"] >= 0)
 
 
+def test_lambda_max_sparse_branch_closed_forms():
+    # lambda_max above 4000 nodes runs the sparse (ARPACK) branch: K(2, 4000)
+    # has sqrt(2 * 4000), its Perron vector is not the constant start vector;
+    # a weighted star has ||w||; a 6000-node cycle (2-regular) has 2
+    n, rp, col = _graph(4002, [(u, 2 + v) for u in range(2) for v in range(4000)])
+    assert ko.lambda_max(ko.csr_matrix(n, rp, col)) == pytest.approx(math.sqrt(8000), rel=1e-11)
+    w = 0.5 + (np.arange(4500) % 7) * 0.25
+    n, rp, col, val = weighted_star(w)
+    assert ko.lambda_max(ko.csr_matrix(n, rp, col, val)) == pytest.approx(np.linalg.norm(w), rel=1e-11)
+    n, rp, col = cycle(6000)
+    assert ko.lambda_max(ko.csr_matrix(n, rp, col)) == pytest.approx(2.0, rel=1e-11)
+
+
 @pytest.mark.parametrize("c", [0.3, 0.8, 0.97])
 def test_series_tail_bound_holds(c):
     # With a loose stopping tolerance the truncation error is far above
