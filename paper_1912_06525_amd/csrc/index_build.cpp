@@ -406,13 +406,14 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
   phase("BFS chunks");
   // (c) greedy vertex cover of the cut edges (largest remaining cut degree first)
   std::vector<int32_t> cutdeg(n, 0);
-  int32_t dmax = 0;
-  for (int32_t v = 0; v < n; v++) {
-    int32_t c = 0;
-    for (int32_t k = rp[v]; k < rp[v + 1]; k++) c += piece[col[k]] != piece[v];
-    cutdeg[v] = c;
-    dmax = std::max(dmax, c);
-  }
+  parallel_for(n, [&](int64_t b, int64_t e) {  // independent per node
+    for (int64_t v = b; v < e; v++) {
+      int32_t c = 0;
+      for (int32_t k = rp[v]; k < rp[v + 1]; k++) c += piece[col[k]] != piece[v];
+      cutdeg[v] = c;
+    }
+  }, 16384);
+  const int32_t dmax = n > 0 ? *std::max_element(cutdeg.begin(), cutdeg.end()) : 0;
   std::vector<std::vector<int32_t>> bucket(dmax + 1);
   for (int32_t v = n - 1; v >= 0; v--)
     if (cutdeg[v] > 0) bucket[cutdeg[v]].push_back(v);
