@@ -195,6 +195,38 @@ def test_index_file_round_trip(tmp_path):
         assert np.array_equal(ua, ub) and np.array_equal(sa, sb)
 
 
+@pytest.mark.parametrize("prec,uprec", [(K.KATZ_PREC_FP64, 1), (K.KATZ_PREC_FP64, 2), (K.KATZ_PREC_MIXED, 0)])
+def test_weighted_index_file_round_trip(tmp_path, prec, uprec):
+    # weighted adjacency, both precisions and explicit storage of V: the file
+    # keeps the weights and every option; one weight changed in the file
+    # breaks symmetry and is rejected
+    g = ki.workload("sbm2k", scale=0.4).graph
+    val = ki.edge_weights(g, seed=9)
+    A = oracle.csr_matrix(g.n, g.row_ptr, g.col, val)
+    beta = 0.6 / oracle.lambda_max(A)
+    a = K.KatzIndex.from_graph(g, val=val, beta=beta, rank=5, device=-1, max_block=32, precision=prec,
+                               u_precision=uprec)
+    p = tmp_path / "w.katz"
+    a.save(str(p))
+    b = K.KatzIndex.load(str(p), device=-1)
+    assert _info_tuple(a.info) == _info_tuple(b.info)
+    assert b.info.precision == prec and (uprec == 0 or b.info.u_precision == uprec)
+    raw = bytearray(p.read_bytes())
+    at, cnt = _index_arrays(raw)["val"]
+    assert cnt == len(val)
+    # the stored weights are the caller's, in the permuted CSR order
+    stored = np.frombuffer(bytes(raw[at:at + 8 * cnt]), dtype="<f8")
+    assert np.array_equal(np.sort(stored), np.sort(val))
+    bad = bytearray(raw)
+    w0 = np.frombuffer(bytes(bad[at:at + 8]), dtype="<f8")[0]
+    bad[at:at + 8] = np.array([w0 * 1.5], dtype="<f8").tobytes()
+    q = tmp_path / "w_bad.katz"
+    q.write_bytes(bytes(bad))
+    with pytest.raises(K.KatzError) as e:
+        K.KatzIndex.load(str(q), device=-1)
+    assert e.value.code == K.KATZ_EINVAL
+
+
 def test_index_file_rejects_damage(tmp_path):
     g = ki.workload("sbm2k", scale=0.3).graph
     a = K.KatzIndex.from_graph(g, beta=oracle_beta(g, 0.5), rank=2, device=-1, max_block=32)
