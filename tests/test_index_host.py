@@ -26,11 +26,11 @@ def test_header_symbols_exported():
     assert names == set(K.EXPORTED)
 
 
-def _dense_parts(g, idx, beta):
+def _dense_parts(g, idx, beta, val=None):
     info = idx.info
     perm, bp = idx.partition()
     n, n1 = g.n, info.n1
-    A = oracle.csr_matrix(g.n, g.row_ptr, g.col).toarray()
+    A = oracle.csr_matrix(g.n, g.row_ptr, g.col, val).toarray()
     P = np.zeros((n, n))
     P[perm, np.arange(n)] = 1.0          # P @ x puts node v at position perm[v]
     Ap = P @ A @ P.T
@@ -115,6 +115,34 @@ def test_theorem1_spectrum(lkind):
     Dg = np.diag(s / (1 - s))
     St_inv = Li.T @ (np.eye(n2) + U @ Dg @ U.T) @ Li       # eq. inverseTildeS
     ev = np.sort(np.linalg.eigvals(S @ St_inv).real)
+    expect = np.sort(np.concatenate([np.ones(r), 1 - sig_all[r:]]))
+    np.testing.assert_allclose(ev, expect, atol=1e-9)
+
+
+@pytest.mark.parametrize("lkind", [K.KATZ_L_CHOL, K.KATZ_L_IDENTITY])
+def test_theorem1_spectrum_weighted(lkind):
+    # Theorem 1 on a weighted adjacency: the index's Ritz values are the top of
+    # the dense spectrum of R, and the preconditioned Schur complement has
+    # eigenvalues 1 (r times) and 1 - sigma_i for the rest
+    g = ki.sbm([12, 10, 14], [0.5, 0.5, 0.5], 0.08, seed=6)
+    val = ki.edge_weights(g, seed=21)
+    r = 3
+    beta = 0.8 / oracle.lambda_max(oracle.csr_matrix(g.n, g.row_ptr, g.col, val))
+    idx = K.KatzIndex.from_graph(g, val=val, beta=beta, rank=r, device=-1, labels=g.labels, max_block=8,
+                                 l_kind=lkind, lanczos_steps=10 ** 6)
+    M, Ap, perm, bp, n1 = _dense_parts(g, idx, beta, val)
+    n2 = idx.info.n2
+    assert n2 >= r + 2
+    M11, M12, M22 = M[:n1, :n1], M[:n1, n1:], M[n1:, n1:]
+    S = M22 - M12.T @ np.linalg.solve(M11, M12)
+    L = np.linalg.cholesky(M22) if lkind == K.KATZ_L_CHOL else np.eye(n2)
+    Li = np.linalg.inv(L)
+    R = np.eye(n2) - Li @ S @ Li.T
+    sig_all = np.sort(np.linalg.eigvalsh(R))[::-1]
+    U, s = idx.lowrank()
+    np.testing.assert_allclose(s, sig_all[:r], rtol=0, atol=1e-10)
+    Dg = np.diag(s / (1 - s))
+    ev = np.sort(np.linalg.eigvals(S @ (Li.T @ (np.eye(n2) + U @ Dg @ U.T) @ Li)).real)
     expect = np.sort(np.concatenate([np.ones(r), 1 - sig_all[r:]]))
     np.testing.assert_allclose(ev, expect, atol=1e-9)
 
