@@ -58,13 +58,15 @@ def test_partition_is_block_diagonal(labels):
     assert info.n1 + info.n2 == g.n
 
 
-def test_lemma1_block_elimination_exact():
+@pytest.mark.parametrize("weighted", [False, True])
+def test_lemma1_block_elimination_exact(weighted):
     g = ki.workload("sbm2k", scale=0.4).graph
-    beta = oracle_beta(g, 0.7)
-    idx = K.KatzIndex.from_graph(g, beta=beta, rank=0, device=-1, labels=g.labels, max_block=64)
-    M, Ap, perm, bp, n1 = _dense_parts(g, idx, beta)
+    val = ki.edge_weights(g, seed=13) if weighted else None
+    beta = 0.7 / oracle.lambda_max(oracle.csr_matrix(g.n, g.row_ptr, g.col, val))
+    idx = K.KatzIndex.from_graph(g, val=val, beta=beta, rank=0, device=-1, labels=g.labels, max_block=64)
+    M, Ap, perm, bp, n1 = _dense_parts(g, idx, beta, val)
     qs = ki.sample_queries(g, 3, 17)
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta)["k_direct"]
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta, val=val)["k_direct"]
     M11, M12, M22 = M[:n1, :n1], M[:n1, n1:], M[n1:, n1:]
     for i, q in enumerate(qs):
         b = beta * Ap[:, perm[q]]
