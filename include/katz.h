@@ -323,7 +323,9 @@ int katz_server_submit(katz_server* s, const int32_t* q, int32_t nq, int64_t* ti
 int katz_server_poll(katz_server* s, int64_t ticket, int32_t* ids, double* scores, katz_query_stats* st,
                      double* latency_ms, int64_t timeout_us);
 int katz_server_info(katz_server* s, katz_server_info_t* info);
-/* Finishes the queued requests, stops the workers and frees the workspaces. */
+/* Finishes the queued requests, stops the workers and frees the workspaces
+ * and the server.  No other call on s may be in progress or follow (a thread
+ * still waiting in katz_server_poll must have returned first). */
 void katz_server_destroy(katz_server* s);
 
 /* Per-kernel timing of the query path (tracing aid): with profiling on, every
