@@ -26,4 +26,7 @@ from .reference import (  # noqa: F401
     tie_classes,
     walk_counts,
     sparse_katz,
+    pearson,
+    correlation_rerank,
 )
+from .cpu import katz_series_mt, cg_mt  # noqa: F401,E402

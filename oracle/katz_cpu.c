@@ -1,0 +1,315 @@
+/*
+ * Multi-core FP64 CPU tools for query-time Katz -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Called (through oracle/cpu.py) by the test suite and by the benchmark's CPU
+ * leg, never by the library's product path.  Shares no code, header, table or
+ * helper with the HIP library; it reads the same CSR arrays the generators
+ * produce.
+ *
+ * Paper: Coskun, Baggag, Koyuturk, "Fast Computation of Katz Index for
+ * Efficient Processing of Link Prediction Queries" (arXiv:1912.06525).
+ * Notation: beta is the damping factor (alpha in Sec. 3.1), A the symmetric
+ * nonnegative adjacency matrix, c = beta * lambda_max(A) < 1.
+ *
+ * ko_series -- the oracle at benchmark sizes: the Katz vector of query q,
+ *   k_q = sum_{l >= 1} (beta A)^l e_q                     (Sec. 3.1, eq. KatzMatrix
+ *   applied to e_q; the walk sum of eq. KatzPath), as a truncated Neumann
+ *   series.  Term l is v_l = beta A v_{l-1}, v_0 = e_q, a plain CSR product in
+ *   a fixed entry order.  Column j stops after term L when the rigorous tail
+ *   bound ||sum_{l > L} v_l|| <= ||v_L|| c / (1 - c) (||beta A||_2 = c) is at
+ *   most tol * ||s_L||.  Every term is >= 0, so the sum has no cancellation.
+ *
+ * ko_cg -- the CPU baseline: plain conjugate gradients (the paper's
+ *   comparison method, Sec. 4) on M k = beta A e_q with M = I - beta A
+ *   (eq. LinearSystem), several right-hand sides at once, each with its own
+ *   step lengths and stop test, OpenMP over rows.  Stop rule as the GPU path:
+ *   recurrence residual <= tol/2 ||b||, then the true residual ||b - M k|| /
+ *   ||b|| is recomputed and CG restarts from k on the columns above tol.
+ *
+ * Layout: panels are node-major, n x B, element (i, j) at [i * B + j].
+ * Reductions over rows sum fixed blocks of kRowBlock rows and then the blocks
+ * in order, so results do not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <omp.h>
+
+enum { kRowBlock = 4096 };
+
+/* y = beta A x (n x B panels). */
+static void spmm_beta(int32_t n, const int64_t* rp, const int32_t* col, const double* val, double beta, int B,
+                      const double* x, double* y) {
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; i++) {
+    double* yi = y + (int64_t)i * B;
+    for (int j = 0; j < B; j++) yi[j] = 0.0;
+    for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+      const double a = beta * (val ? val[k] : 1.0);
+      const double* xc = x + (int64_t)col[k] * B;
+      for (int j = 0; j < B; j++) yi[j] += a * xc[j];
+    }
+  }
+}
+
+/* Column sums over fixed row blocks: part[blk * B + j]; reduce_blocks sums
+ * them in block order into out[j]. */
+static void reduce_blocks(const double* part, int64_t nblk, int B, double* out) {
+  for (int j = 0; j < B; j++) out[j] = 0.0;
+  for (int64_t b = 0; b < nblk; b++)
+    for (int j = 0; j < B; j++) out[j] += part[b * B + j];
+}
+
+static int64_t nblocks(int32_t n) { return ((int64_t)n + kRowBlock - 1) / kRowBlock; }
+
+static void set_threads(int threads) {
+  if (threads > 0) omp_set_num_threads(threads);
+}
+
+/*
+ * k[n*B]: Katz vectors of q[0..B) (node-major).  terms[B]: terms summed per
+ * column; tail[B]: its final tail bound ||v_L|| c / (1 - c) (absolute).
+ * threads: OpenMP threads (0: the runtime's default); *threads_used receives
+ * the count.  Returns 0, -1 for bad arguments, -2 if some column needed more
+ * than max_terms (its k is the partial sum).
+ */
+int ko_series(int32_t n, const int64_t* rp, const int32_t* col, const double* val, double beta, double c, int32_t B,
+              const int32_t* q, double tol, int32_t max_terms, int32_t threads, double* k, int32_t* terms,
+              double* tail, int32_t* threads_used) {
+  if (n <= 0 || B <= 0 || !(c > 0.0 && c < 1.0) || !(beta > 0.0)) return -1;
+  for (int j = 0; j < B; j++)
+    if (q[j] < 0 || q[j] >= n) return -1;
+  set_threads(threads);
+  if (threads_used) *threads_used = omp_get_max_threads();
+  const int64_t nB = (int64_t)n * B, nblk = nblocks(n);
+  double* v = (double*)calloc((size_t)nB, sizeof(double));
+  double* w = (double*)malloc((size_t)nB * sizeof(double));
+  double* pv = (double*)malloc((size_t)nblk * B * sizeof(double));
+  double* ps = (double*)malloc((size_t)nblk * B * sizeof(double));
+  double* nv = (double*)malloc((size_t)B * sizeof(double));
+  double* ns = (double*)malloc((size_t)B * sizeof(double));
+  unsigned char* live = (unsigned char*)malloc((size_t)B);
+  if (!v || !w || !pv || !ps || !nv || !ns || !live) {
+    free(v); free(w); free(pv); free(ps); free(nv); free(ns); free(live);
+    return -1;
+  }
+  memset(k, 0, (size_t)nB * sizeof(double));
+  for (int j = 0; j < B; j++) {
+    v[(int64_t)q[j] * B + j] = 1.0; /* v_0 = e_q */
+    live[j] = 1;
+    terms[j] = 0;
+    tail[j] = 0.0;
+  }
+  const double ratio = c / (1.0 - c);
+  int remaining = B, rc = 0;
+  for (int32_t L = 1; remaining > 0; L++) {
+    if (L > max_terms) {
+      rc = -2;
+      break;
+    }
+    spmm_beta(n, rp, col, val, beta, B, v, w); /* v_L = beta A v_{L-1} */
+    double* t = v;
+    v = w;
+    w = t;
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < nblk; b++) {
+      double* pvb = pv + b * B;
+      double* psb = ps + b * B;
+      for (int j = 0; j < B; j++) pvb[j] = psb[j] = 0.0;
+      const int64_t i1 = (b + 1) * kRowBlock < n ? (b + 1) * kRowBlock : n;
+      for (int64_t i = b * kRowBlock; i < i1; i++) {
+        const double* vi = v + i * B;
+        double* ki = k + i * B;
+        for (int j = 0; j < B; j++) {
+          if (live[j]) ki[j] += vi[j];
+          pvb[j] += vi[j] * vi[j];
+          psb[j] += ki[j] * ki[j];
+        }
+      }
+    }
+    reduce_blocks(pv, nblk, B, nv);
+    reduce_blocks(ps, nblk, B, ns);
+    for (int j = 0; j < B; j++) {
+      if (!live[j]) continue;
+      const double bound = sqrt(nv[j]) * ratio;
+      terms[j] = L;
+      tail[j] = bound;
+      if (bound <= tol * sqrt(ns[j])) {
+        live[j] = 0;
+        remaining--;
+      }
+    }
+  }
+  free(v); free(w); free(pv); free(ps); free(nv); free(ns); free(live);
+  return rc;
+}
+
+/* q = p - beta A p on the active columns, and block partials of <p, q>. */
+static void apply_m(int32_t n, const int64_t* rp, const int32_t* col, const double* val, double beta, int B,
+                    const double* p, double* qv, const unsigned char* act, double* part) {
+  const int64_t nblk = nblocks(n);
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < nblk; b++) {
+    double* pb = part + b * B;
+    for (int j = 0; j < B; j++) pb[j] = 0.0;
+    const int64_t i1 = (b + 1) * kRowBlock < n ? (b + 1) * kRowBlock : n;
+    for (int64_t i = b * kRowBlock; i < i1; i++) {
+      double* qi = qv + i * B;
+      const double* pi = p + i * B;
+      for (int j = 0; j < B; j++) qi[j] = 0.0;
+      for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+        const double a = val ? val[e] : 1.0;
+        const double* pc = p + (int64_t)col[e] * B;
+        for (int j = 0; j < B; j++) qi[j] += a * pc[j];
+      }
+      for (int j = 0; j < B; j++) {
+        if (!act[j]) continue;
+        qi[j] = pi[j] - beta * qi[j];
+        pb[j] += pi[j] * qi[j];
+      }
+    }
+  }
+}
+
+/*
+ * x[n*B]: solutions of (I - beta A) x = beta A e_q for q[0..B), node-major.
+ * iters[B]: CG iterations per column (over all restarts); relres[B]: true
+ * FP64 ||b - M x|| / ||b|| of the returned x (0 for an isolated query).
+ * Returns 0, -1 for bad arguments, -2 if some column missed tol within
+ * max_iter iterations.
+ */
+int ko_cg(int32_t n, const int64_t* rp, const int32_t* col, const double* val, double beta, int32_t B,
+          const int32_t* q, double tol, int32_t max_iter, int32_t threads, double* x, int32_t* iters,
+          double* relres, int32_t* threads_used) {
+  if (n <= 0 || B <= 0 || !(beta > 0.0)) return -1;
+  for (int j = 0; j < B; j++)
+    if (q[j] < 0 || q[j] >= n) return -1;
+  set_threads(threads);
+  if (threads_used) *threads_used = omp_get_max_threads();
+  const int64_t nB = (int64_t)n * B, nblk = nblocks(n);
+  double* b = (double*)calloc((size_t)nB, sizeof(double));
+  double* r = (double*)malloc((size_t)nB * sizeof(double));
+  double* p = (double*)malloc((size_t)nB * sizeof(double));
+  double* qv = (double*)malloc((size_t)nB * sizeof(double));
+  double* part = (double*)malloc((size_t)nblk * B * sizeof(double));
+  double* s = (double*)malloc((size_t)B * 6 * sizeof(double));
+  unsigned char* act = (unsigned char*)malloc((size_t)B);
+  unsigned char* todo = (unsigned char*)malloc((size_t)B);
+  if (!b || !r || !p || !qv || !part || !s || !act || !todo) {
+    free(b); free(r); free(p); free(qv); free(part); free(s); free(act); free(todo);
+    return -1;
+  }
+  double *bn = s, *rr = s + B, *pq = s + 2 * B, *al = s + 3 * B, *rr2 = s + 4 * B, *tr = s + 5 * B;
+  /* b = beta A e_q: the product of the CSR with the unit panel */
+  memset(p, 0, (size_t)nB * sizeof(double));
+  for (int j = 0; j < B; j++) p[(int64_t)q[j] * B + j] = 1.0;
+  spmm_beta(n, rp, col, val, beta, B, p, b);
+  memset(x, 0, (size_t)nB * sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int64_t b0 = 0; b0 < nblk; b0++) {
+    double* pb = part + b0 * B;
+    for (int j = 0; j < B; j++) pb[j] = 0.0;
+    const int64_t i1 = (b0 + 1) * kRowBlock < n ? (b0 + 1) * kRowBlock : n;
+    for (int64_t i = b0 * kRowBlock; i < i1; i++)
+      for (int j = 0; j < B; j++) pb[j] += b[i * B + j] * b[i * B + j];
+  }
+  reduce_blocks(part, nblk, B, bn);
+  for (int j = 0; j < B; j++) {
+    bn[j] = sqrt(bn[j]);
+    iters[j] = 0;
+    relres[j] = 0.0;
+    todo[j] = bn[j] > 0.0;
+  }
+  memcpy(r, b, (size_t)nB * sizeof(double)); /* r = b - M x with x = 0 */
+  int rc = 0;
+  int total = 0;
+  for (int restart = 0;; restart++) {
+    int any = 0;
+    for (int j = 0; j < B; j++) any |= todo[j];
+    if (!any) break;
+    if (total >= max_iter || restart >= 50) {
+      rc = -2;
+      break;
+    }
+    /* (re)start on the columns above tolerance: p = r, rr = <r, r> */
+    memcpy(p, r, (size_t)nB * sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int64_t b0 = 0; b0 < nblk; b0++) {
+      double* pb = part + b0 * B;
+      for (int j = 0; j < B; j++) pb[j] = 0.0;
+      const int64_t i1 = (b0 + 1) * kRowBlock < n ? (b0 + 1) * kRowBlock : n;
+      for (int64_t i = b0 * kRowBlock; i < i1; i++)
+        for (int j = 0; j < B; j++) pb[j] += r[i * B + j] * r[i * B + j];
+    }
+    reduce_blocks(part, nblk, B, rr);
+    for (int j = 0; j < B; j++) act[j] = todo[j] && sqrt(rr[j]) > 0.5 * tol * bn[j];
+    for (; total < max_iter; total++) {
+      int na = 0;
+      for (int j = 0; j < B; j++) na += act[j];
+      if (!na) break;
+      apply_m(n, rp, col, val, beta, B, p, qv, act, part);
+      reduce_blocks(part, nblk, B, pq);
+      for (int j = 0; j < B; j++) {
+        al[j] = 0.0;
+        if (!act[j]) continue;
+        if (!(pq[j] > 0.0)) { /* breakdown: leave the column to the residual check */
+          act[j] = 0;
+          continue;
+        }
+        al[j] = rr[j] / pq[j];
+        iters[j]++;
+      }
+#pragma omp parallel for schedule(static)
+      for (int64_t b0 = 0; b0 < nblk; b0++) {
+        double* pb = part + b0 * B;
+        for (int j = 0; j < B; j++) pb[j] = 0.0;
+        const int64_t i1 = (b0 + 1) * kRowBlock < n ? (b0 + 1) * kRowBlock : n;
+        for (int64_t i = b0 * kRowBlock; i < i1; i++)
+          for (int j = 0; j < B; j++) {
+            if (!act[j]) continue;
+            const int64_t o = i * B + j;
+            x[o] += al[j] * p[o];
+            r[o] -= al[j] * qv[o];
+            pb[j] += r[o] * r[o];
+          }
+      }
+      reduce_blocks(part, nblk, B, rr2);
+      for (int j = 0; j < B; j++) {
+        tr[j] = 0.0;
+        if (!act[j]) continue;
+        tr[j] = rr2[j] / rr[j];
+        rr[j] = rr2[j];
+        if (sqrt(rr2[j]) <= 0.5 * tol * bn[j]) act[j] = 0;
+      }
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < n; i++)
+        for (int j = 0; j < B; j++)
+          if (act[j]) p[i * B + j] = r[i * B + j] + tr[j] * p[i * B + j];
+    }
+    /* true residual r = b - (x - beta A x) */
+    for (int j = 0; j < B; j++) act[j] = 1;
+    apply_m(n, rp, col, val, beta, B, x, qv, act, part);
+#pragma omp parallel for schedule(static)
+    for (int64_t b0 = 0; b0 < nblk; b0++) {
+      double* pb = part + b0 * B;
+      for (int j = 0; j < B; j++) pb[j] = 0.0;
+      const int64_t i1 = (b0 + 1) * kRowBlock < n ? (b0 + 1) * kRowBlock : n;
+      for (int64_t i = b0 * kRowBlock; i < i1; i++)
+        for (int j = 0; j < B; j++) {
+          const int64_t o = i * B + j;
+          r[o] = b[o] - qv[o];
+          pb[j] += r[o] * r[o];
+        }
+    }
+    reduce_blocks(part, nblk, B, rr);
+    for (int j = 0; j < B; j++) {
+      if (!(bn[j] > 0.0)) continue;
+      relres[j] = sqrt(rr[j]) / bn[j];
+      todo[j] = relres[j] > tol;
+    }
+  }
+  free(b); free(r); free(p); free(qv); free(part); free(s); free(act); free(todo);
+  return rc;
+}

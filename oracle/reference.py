@@ -274,19 +274,40 @@ def sparse_katz(n: int, row_ptr, col, q: int, s: int, T: int, beta: float, lam: 
     _, _, sid, _ = topk_links(n, row_ptr, col, kq, q, max(s, T))
     cand = sid[:s]
     mods = sid[:T]
-    rho = np.full(len(cand), np.nan)
     KT = None
     if len(mods) >= 2:
         KT = katz_oracle(n, row_ptr, col, mods, beta=beta, lam=lam, validate=False)["k"]
-        xq = KT[q, :]
-        for j, v in enumerate(cand):
-            y = KT[v, :]
-            if np.ptp(xq) > 0 and np.ptp(y) > 0:
-                rho[j] = np.corrcoef(xq, y)[0, 1]
-    key = [(0 if np.isfinite(r) else 1, -r if np.isfinite(r) else 0.0, j) for j, r in enumerate(rho)]
-    order = [j for _, _, j in sorted(key)]
+        order, rho = correlation_rerank(KT[q, :], KT[cand, :])
+    else:
+        order, rho = list(range(len(cand))), np.full(len(cand), np.nan)
     return {"ids": cand[order], "rho": rho[order], "katz_order": cand, "katz_rho": rho, "KT": KT,
             "modular": mods}
+
+
+def pearson(x, y) -> float:
+    """Pearson correlation of two equal-length vectors, written out:
+    sum (x - mean x)(y - mean y) / sqrt(sum (x - mean x)^2 sum (y - mean y)^2);
+    NaN when either vector is constant."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    dx = x - x.sum() / x.size
+    dy = y - y.sum() / y.size
+    sxx = float((dx * dx).sum())
+    syy = float((dy * dy).sum())
+    if not (sxx > 0 and syy > 0):
+        return float("nan")
+    return float((dx * dy).sum()) / math.sqrt(sxx * syy)
+
+
+def correlation_rerank(xq, rows):
+    """The last step of Algorithm 3: rho_j = Pearson correlation of the query's
+    row xq of K_T with candidate j's row rows[j]; returns (order, rho) where
+    order lists the candidates (given in Katz order) by rho descending,
+    undefined correlations last, ties in the Katz order."""
+    rows = np.atleast_2d(np.asarray(rows, np.float64))
+    rho = np.array([pearson(xq, rows[j]) for j in range(rows.shape[0])]) if rows.size else np.zeros(0)
+    key = [(0 if np.isfinite(r) else 1, -r if np.isfinite(r) else 0.0, j) for j, r in enumerate(rho)]
+    return [j for _, _, j in sorted(key)], rho
 
 
 def walk_counts(n: int, row_ptr, col, q: int, max_len: int) -> list:

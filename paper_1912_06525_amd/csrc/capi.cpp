@@ -224,12 +224,19 @@ int katz_sparse_katz(const katz_index* idx, const int32_t* q, int32_t nq, int32_
     // and for every listed candidate, as pair queries (src t, dst v)
     std::vector<int32_t> ps, pd;
     std::vector<int32_t> ncand(nq), nmod(nq);
+    int64_t total = 0;
     for (int32_t i = 0; i < nq; i++) {
       const int32_t* li = top.data() + (size_t)i * K;
       int32_t nc = 0;
       while (nc < K && li[nc] >= 0) nc++;
       ncand[i] = std::min(nc, s);
       nmod[i] = std::min(nc, T);
+      total += (int64_t)nmod[i] * (ncand[i] + 1);
+    }
+    if (total > INT32_MAX)
+      return set_error(KATZ_EINVAL, "too many correlation entries in one call (nq * T * (s + 1) > 2^31 - 1)");
+    for (int32_t i = 0; i < nq; i++) {
+      const int32_t* li = top.data() + (size_t)i * K;
       for (int32_t t = 0; t < nmod[i]; t++) {
         ps.push_back(li[t]);
         pd.push_back(q[i]);

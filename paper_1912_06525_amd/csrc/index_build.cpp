@@ -95,62 +95,74 @@ double dot(const double* a, const double* b, int64_t n) {
 }
 
 // ------------------------------------------------ symmetric tridiagonal
-// Eigen-decomposition of the symmetric tridiagonal matrix with diagonal d[0..m)
-// and off-diagonal e[0..m-1) by the implicitly shifted QL iteration with
-// Wilkinson-type shifts.  On return d holds the eigenvalues (unsorted) and
-// z (m x m, row-major, z[row*m + k]) the orthonormal eigenvectors as columns.
+// Eigen-decomposition of the symmetric tridiagonal T with diagonal d[0..m)
+// and off-diagonal e[0..m-1) by the symmetric QR algorithm: implicit QR
+// steps with the Wilkinson shift, applied as a chase of the bulge down the
+// unreduced window by plane rotations, with deflation of negligible
+// off-diagonal entries (Golub & Van Loan, Matrix Computations, 4th ed.,
+// Sec. 8.3, Algorithms 8.3.2 and 8.3.3).  On return d holds the eigenvalues
+// (unsorted) and z (m x m, row-major, z[row*m + k]) the orthonormal
+// eigenvectors as columns (the product of all rotations).
+namespace {
+
+// Negligible off-diagonal entry: |e_i| <= u (|d_i| + |d_{i+1}|).
+inline bool negligible(const std::vector<double>& d, const std::vector<double>& e, int i) {
+  return std::fabs(e[i]) <= 2.220446049250313e-16 * (std::fabs(d[i]) + std::fabs(d[i + 1]));
+}
+
+// One implicit QR step on the unreduced window [lo, hi] of (d, e).  The shift
+// mu is the eigenvalue of the trailing 2x2 block closer to its last diagonal
+// entry.  The first rotation takes (d_lo - mu, e_lo) to (r, 0); each later
+// rotation in plane (k, k+1) removes the bulge at T(k-1, k+1) that the
+// previous one created, until the bulge leaves the window.  Every rotation
+// R = [[c, s], [-s, c]] acts as T <- R T R^T and is accumulated as z <- z R^T.
+void qr_step(std::vector<double>& d, std::vector<double>& e, std::vector<double>& z, int m, int lo, int hi) {
+  const double t = e[hi - 1];
+  const double delta = 0.5 * (d[hi - 1] - d[hi]);
+  const double root = std::hypot(delta, t);
+  const double mu = d[hi] - t * t / (delta + (delta >= 0.0 ? root : -root));
+  double x = d[lo] - mu, y = e[lo];
+  for (int k = lo; k < hi; k++) {
+    const double r = std::hypot(x, y);
+    const double c = r > 0.0 ? x / r : 1.0, s = r > 0.0 ? y / r : 0.0;
+    if (k > lo) e[k - 1] = r;  // T(k-1, k) = r, the bulge T(k-1, k+1) = 0
+    const double a0 = d[k], a1 = d[k + 1], b = e[k];
+    d[k] = c * c * a0 + 2.0 * c * s * b + s * s * a1;
+    d[k + 1] = s * s * a0 - 2.0 * c * s * b + c * c * a1;
+    e[k] = c * s * (a1 - a0) + (c * c - s * s) * b;
+    if (k + 1 < hi) {
+      // rows k and k+1 mixed into column k+2: a new bulge at T(k, k+2)
+      x = e[k];
+      y = s * e[k + 1];
+      e[k + 1] *= c;
+    }
+    for (int i = 0; i < m; i++) {
+      double* zi = &z[(size_t)i * m];
+      const double u = zi[k], v = zi[k + 1];
+      zi[k] = c * u + s * v;
+      zi[k + 1] = c * v - s * u;
+    }
+  }
+}
+
+}  // namespace
+
 void tridiag_eig(std::vector<double>& d, std::vector<double> e, std::vector<double>& z, int m) {
   z.assign((size_t)m * m, 0.0);
   for (int i = 0; i < m; i++) z[(size_t)i * m + i] = 1.0;
-  e.resize(m, 0.0);
-  if (m > 0) e[m - 1] = 0.0;
-  const double eps = 2.220446049250313e-16;
-  for (int l = 0; l < m; l++) {
-    int iter = 0;
-    for (;;) {
-      int mm = l;
-      for (; mm < m - 1; mm++) {
-        double dd = std::fabs(d[mm]) + std::fabs(d[mm + 1]);
-        if (std::fabs(e[mm]) <= eps * dd) break;
-      }
-      if (mm == l) break;
-      if (++iter > 200) fail(KATZ_EINVAL, "tridiagonal eigensolver did not converge");
-      // shift from the trailing 2x2 of the active window's top
-      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = std::hypot(g, 1.0);
-      g = d[mm] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-      double s = 1.0, c = 1.0, p = 0.0;
-      int i = mm - 1;
-      bool deflated = false;
-      for (; i >= l; i--) {
-        double f = s * e[i], b = c * e[i];
-        r = std::hypot(f, g);
-        e[i + 1] = r;
-        if (r == 0.0) {  // underflow: split here
-          d[i + 1] -= p;
-          e[mm] = 0.0;
-          deflated = true;
-          break;
-        }
-        s = f / r;
-        c = g / r;
-        g = d[i + 1] - p;
-        r = (d[i] - g) * s + 2.0 * c * b;
-        p = s * r;
-        d[i + 1] = g + p;
-        g = c * r - b;
-        for (int k = 0; k < m; k++) {  // accumulate the rotation in z
-          double* zk = &z[(size_t)k * m];
-          double t = zk[i + 1];
-          zk[i + 1] = s * zk[i] + c * t;
-          zk[i] = c * zk[i] - s * t;
-        }
-      }
-      if (deflated) continue;
-      d[l] -= p;
-      e[l] = g;
-      e[mm] = 0.0;
+  e.resize(std::max(m, 1), 0.0);
+  int hi = m - 1, steps = 0;
+  while (hi > 0) {
+    if (negligible(d, e, hi - 1)) {  // d[hi] has converged
+      e[hi - 1] = 0.0;
+      hi--;
+      continue;
     }
+    int lo = hi - 1;
+    while (lo > 0 && !negligible(d, e, lo - 1)) lo--;
+    if (lo > 0) e[lo - 1] = 0.0;
+    if (++steps > 60 * std::max(m, 1)) fail(KATZ_EINVAL, "tridiagonal eigensolver did not converge");
+    qr_step(d, e, z, m, lo, hi);
   }
 }
 

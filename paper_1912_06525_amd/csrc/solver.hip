@@ -538,7 +538,8 @@ __global__ __launch_bounds__(WG) void k_update_r_vt1(int64_t m, int rows_per_wg,
   }
 }
 
-// p = z + bcg p (active columns); init: p = z for the columns in the mask.
+// p = z + bcg p on the active columns; init: p = z on them (a column whose
+// start residual already meets its threshold is inactive and keeps its p).
 template <typename T>
 __global__ __launch_bounds__(WG) void k_update_p(int64_t m, int B, const T* z, T* p, int init, ColState cs) {
   if (!init && *cs.n_active == 0) return;
@@ -546,8 +547,7 @@ __global__ __launch_bounds__(WG) void k_update_p(int64_t m, int B, const T* z, T
   const int tid = threadIdx.x, cl = tid % cm.CL, rg = tid / cm.CL;
   for (int c = 0; c < cm.NCL; c++) {
     const int j = cl + cm.CL * c;
-    if (j >= B) continue;
-    if (init ? !cs.active[j] : !cs.active[j]) continue;
+    if (j >= B || !cs.active[j]) continue;
     const T b = init ? (T)0 : (T)cs.bcg[j];
     for (int64_t i = (int64_t)blockIdx.x * cm.RG + rg; i < m; i += (int64_t)gridDim.x * cm.RG) {
       const int64_t o = i * B + j;
@@ -3185,32 +3185,6 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
     st = w->stream;
     std::vector<ColResult> res;
     run_batch(H, D, w, st, qa.q + c0, B, qa.opts, res);
-    if (qa.topk > 0) {
-      const int K = qa.topk;
-      size_t need = 64 * (size_t)B + 1024 * (size_t)B + 12 * (size_t)K * B + 1024;
-      if (w->tk_cap < need) {
-        w->tk_scratch = dalloc<char>(w->allocs, (int64_t)need);
-        w->tk_cap = need;
-      }
-      int32_t* ids = qa.ids + (int64_t)c0 * K;
-      double* sc = qa.topk_scores ? qa.topk_scores + (int64_t)c0 * K : nullptr;
-      int32_t* dids = ids;
-      double* dsc = sc;
-      if (!dev_ids) {
-        if (w->tk_out_cap < (int64_t)K * B) {
-          w->tk_ids = dalloc<int32_t>(w->allocs, (int64_t)K * B);
-          w->tk_sc = dalloc<double>(w->allocs, (int64_t)K * B);
-          w->tk_out_cap = (int64_t)K * B;
-        }
-        dids = w->tk_ids;
-        dsc = sc ? w->tk_sc : nullptr;
-      }
-      device_topk(n, B, K, w->K, w->qpos, D->rp, D->col, D->iperm, w->tk_scratch, w->tk_cap, dids, dsc, st);
-      if (!dev_ids) {
-        HIPCHECK(hipMemcpyAsync(ids, dids, sizeof(int32_t) * (size_t)K * B, hipMemcpyDeviceToHost, st));
-        if (sc) HIPCHECK(hipMemcpyAsync(sc, dsc, sizeof(double) * (size_t)K * B, hipMemcpyDeviceToHost, st));
-      }
-    }
     if (qa.npairs > 0) {
       // the pairs whose column lies in this chunk (sorted by column)
       const int32_t* pc = qa.pair_col;
@@ -3247,6 +3221,34 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
       }
       if (!dev_scores)
         HIPCHECK(hipMemcpyAsync(dst, out, sizeof(double) * (size_t)n * B, hipMemcpyDeviceToHost, st));
+    }
+    // top-K last: the selection overwrites q and its neighbours in K with -inf,
+    // after the pair gather and the score output have read K
+    if (qa.topk > 0) {
+      const int K = qa.topk;
+      size_t need = 64 * (size_t)B + 1024 * (size_t)B + 12 * (size_t)K * B + 1024;
+      if (w->tk_cap < need) {
+        w->tk_scratch = dalloc<char>(w->allocs, (int64_t)need);
+        w->tk_cap = need;
+      }
+      int32_t* ids = qa.ids + (int64_t)c0 * K;
+      double* sc = qa.topk_scores ? qa.topk_scores + (int64_t)c0 * K : nullptr;
+      int32_t* dids = ids;
+      double* dsc = sc;
+      if (!dev_ids) {
+        if (w->tk_out_cap < (int64_t)K * B) {
+          w->tk_ids = dalloc<int32_t>(w->allocs, (int64_t)K * B);
+          w->tk_sc = dalloc<double>(w->allocs, (int64_t)K * B);
+          w->tk_out_cap = (int64_t)K * B;
+        }
+        dids = w->tk_ids;
+        dsc = sc ? w->tk_sc : nullptr;
+      }
+      device_topk(n, B, K, w->K, w->qpos, D->rp, D->col, D->iperm, w->tk_scratch, w->tk_cap, dids, dsc, st);
+      if (!dev_ids) {
+        HIPCHECK(hipMemcpyAsync(ids, dids, sizeof(int32_t) * (size_t)K * B, hipMemcpyDeviceToHost, st));
+        if (sc) HIPCHECK(hipMemcpyAsync(sc, dsc, sizeof(double) * (size_t)K * B, hipMemcpyDeviceToHost, st));
+      }
     }
     HIPCHECK(hipStreamSynchronize(st));
     w->prof.harvest();

@@ -508,8 +508,21 @@ def test_sparse_katz_cycle_closed_form():
     assert np.all(np.abs(got["rho"]) <= 1 + 1e-12)
 
 
-def test_sparse_katz_pearson_by_hand():
-    # Pearson correlation on rows written out: (1,2,3) vs (2,4,6) = 1, vs (3,2,1) = -1
-    x = np.array([1.0, 2.0, 3.0])
-    assert np.corrcoef(x, 2 * x)[0, 1] == pytest.approx(1.0)
-    assert np.corrcoef(x, x[::-1])[0, 1] == pytest.approx(-1.0)
+def test_sparse_katz_correlation_step_by_hand():
+    """The oracle's correlation and re-rank step (Algorithm 3, last step) on
+    rows whose correlations are worked out by hand: x = (1, 2, 3, 4) has
+    deviations (-1.5, -0.5, 0.5, 1.5), sum of squares 5.
+      (2, 4, 6, 8): rho = 1;   (4, 3, 2, 1): rho = -1;
+      (1, 3, 2, 4): deviations (-1.5, 0.5, -0.5, 1.5), cross sum 4, rho = 0.8;
+      (2, 1, 4, 3): deviations (-0.5, -1.5, 1.5, 0.5), cross sum 3, rho = 0.6;
+      (5, 5, 5, 5): constant, undefined (last);  (3, 6, 9, 12): rho = 1 (tie,
+      keeps the Katz order after (2, 4, 6, 8))."""
+    x = [1.0, 2.0, 3.0, 4.0]
+    rows = [[5, 5, 5, 5], [4, 3, 2, 1], [2, 1, 4, 3], [2, 4, 6, 8], [1, 3, 2, 4], [3, 6, 9, 12]]
+    order, rho = oracle.correlation_rerank(x, rows)
+    want = [float("nan"), -1.0, 0.6, 1.0, 0.8, 1.0]
+    assert np.isnan(rho[0])
+    np.testing.assert_allclose(rho[1:], want[1:], rtol=0, atol=1e-15)
+    assert order == [3, 5, 4, 2, 1, 0]
+    assert np.isnan(oracle.pearson([1.0, 2.0], [7.0, 7.0]))
+    assert oracle.pearson([0.0, 1.0, 0.0], [0.0, 0.0, 1.0]) == pytest.approx(-0.5, abs=1e-15)
