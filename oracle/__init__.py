@@ -29,4 +29,4 @@ from .reference import (  # noqa: F401
     pearson,
     correlation_rerank,
 )
-from .cpu import katz_series_mt, cg_mt  # noqa: F401,E402
+from .cpu import katz_series_mt, cg_mt, lambda_max_mt  # noqa: F401,E402

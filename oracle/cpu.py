@@ -1,6 +1,6 @@
 """Multi-core FP64 CPU tools (``katz_cpu.c``) -- TEST INFRASTRUCTURE ONLY.
 
-Imported by the test suite and the benchmark's CPU leg only.  Two tools:
+Imported by the test suite and the benchmark's CPU leg only.  Three tools:
 
 * :func:`katz_series_mt` -- the oracle at benchmark sizes: the truncated
   Neumann series k_q = sum_{l>=1} (beta A)^l e_q (Section 3.1, eq.
@@ -10,7 +10,11 @@ Imported by the test suite and the benchmark's CPU leg only.  Two tools:
   (I - beta A) k = beta A e_q (eq. LinearSystem; the paper's comparison
   method), multi-RHS, same stop rule as the GPU path (true FP64 residual).
 
-Both return node-major results as an (n, B) array (column j = query j).
+* :func:`lambda_max_mt` -- lambda_max(A) by Lanczos with an OpenMP SpMV,
+  for graphs where the single-threaded scipy eigensolve takes minutes
+  (Sec. 3.1: beta < 1 / lambda_max; c = beta * lambda_max).
+
+The first two return node-major results as an (n, B) array (column j = query j).
 """
 from __future__ import annotations
 
@@ -47,6 +51,8 @@ def _load():
     i32, dbl, P = ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
     lib.ko_series.restype = ctypes.c_int
     lib.ko_series.argtypes = [i32, P, P, P, dbl, dbl, i32, P, dbl, i32, i32, P, P, P, P]
+    lib.ko_lambda_max.restype = ctypes.c_int
+    lib.ko_lambda_max.argtypes = [i32, P, P, P, i32, dbl, i32, P, P, P]
     lib.ko_cg.restype = ctypes.c_int
     lib.ko_cg.argtypes = [i32, P, P, P, dbl, i32, P, dbl, i32, i32, P, P, P, P]
     _lib = lib
@@ -103,3 +109,23 @@ def cg_mt(n, row_ptr, col, qs, beta, val=None, tol=1e-6, max_iter=1000, threads=
     if rc == -1:
         raise ValueError("ko_cg: bad arguments")
     return {"k": x, "iters": iters, "rel_residual": rel, "threads": int(used[0]), "converged": rc == 0}
+
+
+def lambda_max_mt(n, row_ptr, col, val=None, tol=1e-12, max_steps=400, threads=0):
+    """lambda_max(A) of a symmetric nonnegative CSR matrix by the Lanczos
+    iteration from the all-ones vector (see the module docstring).  Stops when
+    the largest Ritz value changes by at most `tol` (relative) in two
+    consecutive steps.  Returns {"lambda": float, "steps": int, "threads":
+    int}; raises if max_steps ended the run first."""
+    lib = _load()
+    rp, cl, vv = _csr(row_ptr, col, val)
+    lam = np.zeros(1, dtype=np.float64)
+    steps = np.zeros(1, dtype=np.int32)
+    used = np.zeros(1, dtype=np.int32)
+    rc = lib.ko_lambda_max(int(n), _ptr(rp), _ptr(cl), _ptr(vv), int(max_steps), float(tol), int(threads),
+                           _ptr(lam), _ptr(steps), _ptr(used))
+    if rc == -1:
+        raise ValueError("ko_lambda_max: bad arguments")
+    if rc == -2:
+        raise RuntimeError("ko_lambda_max: not converged in %d steps (last %.17g)" % (max_steps, lam[0]))
+    return {"lambda": float(lam[0]), "steps": int(steps[0]), "threads": int(used[0])}

@@ -26,30 +26,65 @@
  *   recurrence residual <= tol/2 ||b||, then the true residual ||b - M k|| /
  *   ||b|| is recomputed and CG restarts from k on the columns above tol.
  *
+ * ko_lambda_max -- lambda_max(A), which sets the convergence condition
+ *   beta < 1 / lambda_max (Sec. 3.1) and c = beta * lambda_max: the Lanczos
+ *   iteration on A from the all-ones vector (it overlaps the nonnegative
+ *   Perron vector of a nonnegative A), without reorthogonalisation (the
+ *   largest Ritz value is the first to converge and is not disturbed by the
+ *   loss of orthogonality), the largest eigenvalue of each tridiagonal by
+ *   Sturm-sequence bisection.
+ *
  * Layout: panels are node-major, n x B, element (i, j) at [i * B + j].
  * Reductions over rows sum fixed blocks of kRowBlock rows and then the blocks
  * in order, so results do not depend on the thread count.
  */
+#define _GNU_SOURCE
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sys/mman.h>
 
 #include <omp.h>
 
-enum { kRowBlock = 4096 };
+enum { kRowBlock = 4096, kAccMax = 64 };
 
-/* y = beta A x (n x B panels). */
+/* n x B panels: 2 MiB aligned and advised for transparent huge pages, since
+ * the products gather panel rows at random (fewer TLB misses; the arithmetic
+ * is unchanged).  Zero-filled.  Freed with free(). */
+static double* panel_alloc(int64_t elems) {
+  void* p = NULL;
+  const size_t bytes = (size_t)(elems > 0 ? elems : 1) * sizeof(double);
+  if (posix_memalign(&p, (size_t)1 << 21, bytes) != 0) return NULL;
+  (void)madvise(p, bytes, MADV_HUGEPAGE);
+  memset(p, 0, bytes);
+  return (double*)p;
+}
+
+/* y = beta A x (n x B panels).  Row i accumulates its entries in CSR order
+ * from 0, one running sum per column (held in registers up to kAccMax
+ * columns). */
 static void spmm_beta(int32_t n, const int64_t* rp, const int32_t* col, const double* val, double beta, int B,
-                      const double* x, double* y) {
-#pragma omp parallel for schedule(static)
+                      const double* restrict x, double* restrict y) {
+#pragma omp parallel for schedule(dynamic, 1024)
   for (int32_t i = 0; i < n; i++) {
     double* yi = y + (int64_t)i * B;
-    for (int j = 0; j < B; j++) yi[j] = 0.0;
-    for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
-      const double a = beta * (val ? val[k] : 1.0);
-      const double* xc = x + (int64_t)col[k] * B;
-      for (int j = 0; j < B; j++) yi[j] += a * xc[j];
+    if (B <= kAccMax) {
+      double acc[kAccMax];
+      for (int j = 0; j < B; j++) acc[j] = 0.0;
+      for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+        const double a = beta * (val ? val[k] : 1.0);
+        const double* xc = x + (int64_t)col[k] * B;
+        for (int j = 0; j < B; j++) acc[j] += a * xc[j];
+      }
+      for (int j = 0; j < B; j++) yi[j] = acc[j];
+    } else {
+      for (int j = 0; j < B; j++) yi[j] = 0.0;
+      for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+        const double a = beta * (val ? val[k] : 1.0);
+        const double* xc = x + (int64_t)col[k] * B;
+        for (int j = 0; j < B; j++) yi[j] += a * xc[j];
+      }
     }
   }
 }
@@ -84,8 +119,8 @@ int ko_series(int32_t n, const int64_t* rp, const int32_t* col, const double* va
   set_threads(threads);
   if (threads_used) *threads_used = omp_get_max_threads();
   const int64_t nB = (int64_t)n * B, nblk = nblocks(n);
-  double* v = (double*)calloc((size_t)nB, sizeof(double));
-  double* w = (double*)malloc((size_t)nB * sizeof(double));
+  double* v = panel_alloc(nB);
+  double* w = panel_alloc(nB);
   double* pv = (double*)malloc((size_t)nblk * B * sizeof(double));
   double* ps = (double*)malloc((size_t)nblk * B * sizeof(double));
   double* nv = (double*)malloc((size_t)B * sizeof(double));
@@ -146,23 +181,148 @@ int ko_series(int32_t n, const int64_t* rp, const int32_t* col, const double* va
   return rc;
 }
 
-/* q = p - beta A p on the active columns, and block partials of <p, q>. */
-static void apply_m(int32_t n, const int64_t* rp, const int32_t* col, const double* val, double beta, int B,
-                    const double* p, double* qv, const unsigned char* act, double* part) {
+/* Number of eigenvalues of the symmetric tridiagonal (a[0..m), b[0..m-1))
+ * below x: negative pivots of the LDL^T factorisation of T - x I (Sturm
+ * sequence).  A zero pivot is nudged to a tiny negative value. */
+static int sturm_below(int m, const double* a, const double* b, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  for (int i = 0; i < m; i++) {
+    const double off = i > 0 ? b[i - 1] * b[i - 1] / d : 0.0;
+    d = a[i] - x - off;
+    if (d == 0.0) d = -1e-300;
+    if (d < 0.0) cnt++;
+  }
+  return cnt;
+}
+
+/* Largest eigenvalue of the tridiagonal by bisection inside its Gershgorin
+ * interval, to a relative width of 4 ulp. */
+static double tridiag_max_eig(int m, const double* a, const double* b) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; i++) {
+    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < m - 1 ? fabs(b[i]) : 0.0);
+    if (a[i] - r < lo) lo = a[i] - r;
+    if (a[i] + r > hi) hi = a[i] + r;
+  }
+  for (int it = 0; it < 200; it++) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi))) break;
+    if (sturm_below(m, a, b, mid) == m) hi = mid; /* every eigenvalue is below mid */
+    else lo = mid;
+  }
+  return hi;
+}
+
+/* Fixed-order dot product of two n-vectors (row blocks, then blocks in
+ * order). */
+static double dot_blocks(int32_t n, const double* x, const double* y, double* part) {
   const int64_t nblk = nblocks(n);
 #pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < nblk; b++) {
+    const int64_t i1 = (b + 1) * kRowBlock < n ? (b + 1) * kRowBlock : n;
+    double s = 0.0;
+    for (int64_t i = b * kRowBlock; i < i1; i++) s += x[i] * y[i];
+    part[b] = s;
+  }
+  double s = 0.0;
+  for (int64_t b = 0; b < nblk; b++) s += part[b];
+  return s;
+}
+
+/*
+ * *lam: lambda_max(A) (0 for a graph with no edges).  Runs Lanczos steps
+ * until the largest Ritz value changes by at most tol (relative) over two
+ * consecutive steps, the Krylov space is exhausted, or max_steps.  *steps
+ * receives the steps taken.  Returns 0, -1 for bad arguments or memory, -2
+ * when max_steps ended the run (*lam is then the last Ritz value, a lower
+ * bound).
+ */
+int ko_lambda_max(int32_t n, const int64_t* rp, const int32_t* col, const double* val, int32_t max_steps, double tol,
+                  int32_t threads, double* lam, int32_t* steps, int32_t* threads_used) {
+  if (n <= 0 || max_steps < 1 || !lam) return -1;
+  set_threads(threads);
+  if (threads_used) *threads_used = omp_get_max_threads();
+  const int64_t nblk = nblocks(n);
+  double* q0 = panel_alloc(n);
+  double* q1 = panel_alloc(n);
+  double* w = panel_alloc(n);
+  double* part = (double*)malloc((size_t)nblk * sizeof(double));
+  double* a = (double*)malloc((size_t)max_steps * sizeof(double));
+  double* b = (double*)malloc((size_t)max_steps * sizeof(double));
+  if (!q0 || !q1 || !w || !part || !a || !b) {
+    free(q0); free(q1); free(w); free(part); free(a); free(b);
+    return -1;
+  }
+  const double inv = 1.0 / sqrt((double)n);
+  for (int32_t i = 0; i < n; i++) q1[i] = inv;
+  double theta = 0.0, prev = -1.0;
+  int stable = 0, rc = -2, m = 0;
+  for (int j = 0; j < max_steps; j++) {
+    /* w = A q1 - b_{j-1} q0 */
+    spmm_beta(n, rp, col, val, 1.0, 1, q1, w);
+    if (j > 0) {
+#pragma omp parallel for schedule(static)
+      for (int32_t i = 0; i < n; i++) w[i] -= b[j - 1] * q0[i];
+    }
+    a[j] = dot_blocks(n, w, q1, part);
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; i++) w[i] -= a[j] * q1[i];
+    const double bj = sqrt(dot_blocks(n, w, w, part));
+    b[j] = bj;
+    m = j + 1;
+    theta = tridiag_max_eig(m, a, b);
+    if (bj <= 1e-14 * fmax(fabs(theta), 1e-300)) { /* invariant subspace: theta is exact */
+      rc = 0;
+      break;
+    }
+    stable = (prev >= 0.0 && fabs(theta - prev) <= tol * fabs(theta)) ? stable + 1 : 0;
+    if (stable >= 2) {
+      rc = 0;
+      break;
+    }
+    prev = theta;
+    double* t = q0;
+    q0 = q1;
+    q1 = t;
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; i++) q1[i] = w[i] / bj;
+  }
+  *lam = theta;
+  if (steps) *steps = m;
+  free(q0); free(q1); free(w); free(part); free(a); free(b);
+  return rc;
+}
+
+/* q = p - beta A p on the active columns, and block partials of <p, q>. */
+static void apply_m(int32_t n, const int64_t* rp, const int32_t* col, const double* val, double beta, int B,
+                    const double* restrict p, double* restrict qv, const unsigned char* act, double* part) {
+  const int64_t nblk = nblocks(n);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t b = 0; b < nblk; b++) {
     double* pb = part + b * B;
     for (int j = 0; j < B; j++) pb[j] = 0.0;
     const int64_t i1 = (b + 1) * kRowBlock < n ? (b + 1) * kRowBlock : n;
+    double acc[kAccMax];
     for (int64_t i = b * kRowBlock; i < i1; i++) {
       double* qi = qv + i * B;
       const double* pi = p + i * B;
-      for (int j = 0; j < B; j++) qi[j] = 0.0;
-      for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
-        const double a = val ? val[e] : 1.0;
-        const double* pc = p + (int64_t)col[e] * B;
-        for (int j = 0; j < B; j++) qi[j] += a * pc[j];
+      if (B <= kAccMax) {
+        for (int j = 0; j < B; j++) acc[j] = 0.0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+          const double a = val ? val[e] : 1.0;
+          const double* pc = p + (int64_t)col[e] * B;
+          for (int j = 0; j < B; j++) acc[j] += a * pc[j];
+        }
+        for (int j = 0; j < B; j++) qi[j] = acc[j];
+      } else {
+        for (int j = 0; j < B; j++) qi[j] = 0.0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+          const double a = val ? val[e] : 1.0;
+          const double* pc = p + (int64_t)col[e] * B;
+          for (int j = 0; j < B; j++) qi[j] += a * pc[j];
+        }
       }
       for (int j = 0; j < B; j++) {
         if (!act[j]) continue;
@@ -189,10 +349,10 @@ int ko_cg(int32_t n, const int64_t* rp, const int32_t* col, const double* val, d
   set_threads(threads);
   if (threads_used) *threads_used = omp_get_max_threads();
   const int64_t nB = (int64_t)n * B, nblk = nblocks(n);
-  double* b = (double*)calloc((size_t)nB, sizeof(double));
-  double* r = (double*)malloc((size_t)nB * sizeof(double));
-  double* p = (double*)malloc((size_t)nB * sizeof(double));
-  double* qv = (double*)malloc((size_t)nB * sizeof(double));
+  double* b = panel_alloc(nB);
+  double* r = panel_alloc(nB);
+  double* p = panel_alloc(nB);
+  double* qv = panel_alloc(nB);
   double* part = (double*)malloc((size_t)nblk * B * sizeof(double));
   double* s = (double*)malloc((size_t)B * 6 * sizeof(double));
   unsigned char* act = (unsigned char*)malloc((size_t)B);

@@ -234,3 +234,76 @@ def test_cg_isolated_query_and_star():
     d = 1 - 3 * beta ** 2
     want = np.array([3 * beta ** 2 / d, beta / d, beta / d, beta / d, 0, 0])
     np.testing.assert_allclose(r["k"][:, 1], want, rtol=1e-11, atol=1e-15)
+
+
+# ---------------------------------------------------------------- lambda_max
+def _path(n):
+    return _graph(n, [(i, i + 1) for i in range(n - 1)])
+
+
+def _bipartite(a, b):
+    return _graph(a + b, [(i, a + j) for i in range(a) for j in range(b)])
+
+
+def _petersen():
+    outer = [(i, (i + 1) % 5) for i in range(5)]
+    spokes = [(i, i + 5) for i in range(5)]
+    inner = [(5 + i, 5 + (i + 2) % 5) for i in range(5)]
+    return _graph(10, outer + spokes + inner)
+
+
+@pytest.mark.parametrize("name,gr,expected", [
+    ("K6", lambda: complete(6), 5.0),
+    ("K40", lambda: complete(40), 39.0),
+    ("star50", lambda: star(50), math.sqrt(50)),
+    ("star4000", lambda: star(4000), math.sqrt(4000)),
+    ("K(2,4000)", lambda: _bipartite(2, 4000), math.sqrt(8000)),
+    ("cycle6000", lambda: cycle(6000), 2.0),
+    ("cycle7", lambda: cycle(7), 2.0),
+    ("path50", lambda: _path(50), 2 * math.cos(math.pi / 51)),
+    ("petersen", _petersen, 3.0),
+])
+def test_lambda_max_closed_forms(name, gr, expected):
+    """lambda_max of graphs whose spectrum is known: K_n (n - 1), a star and
+    K(a, b) (sqrt(m), sqrt(ab)), regular graphs (the degree), a path
+    (2 cos(pi / (n + 1)))."""
+    n, rp, col = gr()
+    r = cpu.lambda_max_mt(n, rp, col)
+    assert abs(r["lambda"] - expected) <= 1e-11 * expected, (name, r, expected)
+
+
+def test_lambda_max_weighted_star_and_union():
+    """A weighted star has lambda_max = ||w||; a disjoint union takes the
+    larger component's value (star of 9 leaves: 3, beside K_5: 4)."""
+    m = 7
+    w = np.array([0.5, 1.5, 2.0, 0.25, 3.0, 1.0, 0.75])
+    g = ki.from_edges(m + 1, [(0, i) for i in range(1, m + 1)])
+    val = np.empty(g.row_ptr[-1])
+    for i in range(g.n):
+        for e in range(g.row_ptr[i], g.row_ptr[i + 1]):
+            j = g.col[e]
+            val[e] = w[max(i, j) - 1]
+    r = cpu.lambda_max_mt(g.n, g.row_ptr, g.col, val=val)
+    assert abs(r["lambda"] - np.linalg.norm(w)) <= 1e-12 * np.linalg.norm(w)
+    edges = [(0, i) for i in range(1, 10)] + [(10 + i, 10 + j) for i in range(5) for j in range(i + 1, 5)]
+    n, rp, col = _graph(15, edges)
+    r = cpu.lambda_max_mt(n, rp, col)
+    assert abs(r["lambda"] - 4.0) <= 1e-11 * 4
+    # no edges: 0
+    r = cpu.lambda_max_mt(5, np.zeros(6, np.int64), np.zeros(0, np.int32))
+    assert r["lambda"] == 0.0
+
+
+def test_lambda_max_random_graphs_vs_dense_and_threads():
+    """Random community graphs: equal to the dense eigensolve of A, and
+    bit-identical for 1 and 4 threads (fixed-order reductions)."""
+    for seed in (1, 2, 3):
+        g = ki.sbm([40, 60, 25], 0.2, 0.02, seed=seed)
+        A = np.zeros((g.n, g.n))
+        for i in range(g.n):
+            A[i, g.col[g.row_ptr[i]:g.row_ptr[i + 1]]] = 1.0
+        ev = np.linalg.eigvalsh(A)[-1]
+        r1 = cpu.lambda_max_mt(g.n, g.row_ptr, g.col, threads=1)
+        r4 = cpu.lambda_max_mt(g.n, g.row_ptr, g.col, threads=4)
+        assert abs(r1["lambda"] - ev) <= 1e-11 * ev, (seed, r1, ev)
+        assert r1["lambda"] == r4["lambda"]
