@@ -1,20 +1,34 @@
 """Parity at the full benchmark sizes, in the launch configuration the
 benchmark times.  GPU only.
 
+Every test compares sampled result columns element by element with the
+oracle (Sec. 3.1, eqs. KatzMatrix and LinearSystem):
+
 * 1M-node Chung-Lu, one query per solve, FP64 (the single-GPU headline
-  workload): sampled queries against the oracle's Neumann series, with beta
-  fixed from the oracle's own lambda_max and handed to the index build.
-* 4M-node lognormal SBM (256 queries per solve, FP64) and 8M-node Chung-Lu
-  (512 queries per solve, precision form, c = 0.9): the oracle needs minutes
-  per query there, so properties that hold at any size are checked on sampled
-  columns instead:
-  - the residual ||b - (I - beta A) k|| / ||b|| recomputed here with scipy in
-    FP64 from the returned scores meets the tolerance and matches the
-    reported one;
-  - Katz scores are symmetric, K_pq = K_qp, checked across pairs of columns
-    of the batch to the accuracy the residual implies;
-  - every score is nonnegative up to the same accuracy (A >= 0, beta > 0).
+  workload): the Python oracle's Neumann series, beta from the oracle's own
+  lambda_max;
+* the same graph at 200 columns per solve, FP64 (the 129-256-column SpMM
+  variant, and the whole-workgroup hub rows of a power-law graph at B > 1);
+* 4M-node lognormal SBM, 256 columns per solve, FP64: 8 sampled columns;
+* 8M-node Chung-Lu, 512 columns per solve, precision form, c = 0.9: 8 sampled
+  columns, tau = 1e-4 (the precision form's tolerance) at the timed residual;
+* the serving form on the 16M-node DC-SBM at 1/4 scale: the top-100 lists of
+  4 requests under the tie rule.
+
+Above 1M nodes the oracle is the multi-core series tool (oracle/katz_cpu.c),
+and beta = c / lambda with lambda from the tool's Lanczos (converged to
+1e-12; scipy's single-threaded eigensolve takes minutes there).  A Ritz value
+is a lower bound on lambda_max, so the series' tail bound is given the upper
+bound c (1 + 1e-6) on beta * lambda_max.
+
+Accuracy: a result with true relative residual rho has error at most
+rho (1 + c) / (1 - c) times ||k|| (||M^-1|| = 1 / (1 - c), ||b|| <= (1 + c)
+||k||).  The FP64 tests request rho = tau (1 - c) / (1 + c) and accept
+||k^ - k|| <= tau ||k|| and max |k^ - k| <= tau ||k||, widened by the
+oracle's own tail bound.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -25,9 +39,52 @@ pytestmark = pytest.mark.gpu
 K = pytest.importorskip("paper_1912_06525_amd")
 
 
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _host():
+    model = "?"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return "%d cpus (%s)" % (os.cpu_count() or 0, model)
+
+
 def _err_ok(kh, k, tau):
     nk = np.linalg.norm(k)
-    return np.linalg.norm(kh - k) <= tau * nk and np.max(np.abs(kh - k)) <= tau * nk
+    e2 = np.linalg.norm(kh - k)
+    em = np.max(np.abs(kh - k))
+    return e2 <= tau * nk and em <= tau * nk, (e2 / nk, em / nk)
+
+
+def _lambda(g):
+    """lambda_max(A) from the oracle's multi-core Lanczos: beta is chosen on
+    the test's side and handed to the index build and to the oracle."""
+    r = oracle.lambda_max_mt(g.n, g.row_ptr, g.col)
+    _say("  lambda_max %.12g (%d Lanczos steps)" % (r["lambda"], r["steps"]))
+    return r["lambda"]
+
+
+def _series(g, qs, beta, c, tail):
+    """Oracle columns (n, len(qs)) by the multi-core series; tail-bound
+    fraction `tail`."""
+    r = oracle.katz_series_mt(g.n, g.row_ptr, g.col, [int(q) for q in qs], beta, c * (1 + 1e-6),
+                              tol=tail)
+    _say("  oracle series: terms %s on %d threads" % ([int(t) for t in r["terms"]], r["threads"]))
+    return r["k"]
+
+
+def _pick(B, m, seed):
+    """m seeded column positions of a B-column batch (first and last included)."""
+    rng = np.random.default_rng(seed)
+    mid = rng.choice(np.arange(1, B - 1), size=m - 2, replace=False)
+    return sorted({0, B - 1, *[int(x) for x in mid]})
 
 
 @pytest.mark.timeout(300)
@@ -38,7 +95,7 @@ def test_cl1m_one_query_fp64_vs_oracle():
     lam = oracle.lambda_max(A)
     beta = 0.5 / lam
     qs = [int(x) for x in w.queries[:3]]
-    print("cl1m: n=%d nnz=%d lambda_max=%.6f queries=%s" % (g.n, g.row_ptr[-1], lam, qs), flush=True)
+    _say("cl1m: n=%d nnz=%d lambda_max=%.6f queries=%s" % (g.n, g.row_ptr[-1], lam, qs))
     ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta, lam=lam, validate=False)
     idx = K.KatzIndex.from_graph(g, beta=beta, rank=32, max_block=64)
     assert idx.info.beta == beta
@@ -48,75 +105,142 @@ def test_cl1m_one_query_fp64_vs_oracle():
         for method in (K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG):
             sc, st = idx.query([q], tol=tau * (1 - c) / (1 + c), method=method)
             assert st[0]["status"] == 0
-            assert _err_ok(sc[0], ref["k"][:, j], tau), (q, method)
+            ok, e = _err_ok(sc[0], ref["k"][:, j], tau)
+            assert ok, (q, method, e)
     idx.close()
 
 
-def _test_beta(A, c):
-    """beta = c / lambda_max(A) with lambda_max from scipy's Lanczos to 1e-6
-    (the residual properties hold for any beta with c < 1, so the test picks
-    its own beta; the 1e-12 eigensolve takes minutes at these sizes)."""
-    import scipy.sparse.linalg
-    lam = scipy.sparse.linalg.eigsh(A.astype(np.float64), k=1, which="LA", tol=1e-6,
-                                    return_eigenvectors=False, v0=np.ones(A.shape[0]))[-1]
-    return c / float(lam)
-
-
-def _batch_properties(g, A, beta, c, qs, out, st, tol, pick):
-    assert all(s["status"] == 0 and s["rel_residual"] <= tol for s in st)
+def _batch_vs_oracle(g, idx, qs, tol, pick, method):
+    """Solves the batch qs in one call (device output) and returns the picked
+    columns (n, len(pick)) and every column's stats."""
+    import torch
+    B = len(qs)
+    out = torch.empty((B, g.n), dtype=torch.float64, device="cuda")
+    _, st = idx.query(qs, out=out, tol=tol, method=method)
+    torch.cuda.synchronize()
+    assert all(s["status"] == 0 and s["rel_residual"] <= tol for s in st), [s for s in st if s["status"]][:3]
     kk = np.stack([out[j].cpu().numpy() for j in pick], axis=1)
-    res = oracle.katz_residual(A, beta, [int(qs[j]) for j in pick], kk)
+    del out
+    torch.cuda.empty_cache()
+    return kk, st
+
+
+def _check_cols(kk, ref, pick, qs, tau, tail, label):
+    worst = (0.0, 0.0)
     for t, j in enumerate(pick):
-        assert res[t] <= 1.05 * tol, (j, res[t], st[j]["rel_residual"])
-        assert abs(res[t] - st[j]["rel_residual"]) <= 0.05 * tol, (j, res[t], st[j]["rel_residual"])
-    # ||k - k*|| <= ||r|| / (1 - c) with ||r|| <= tol ||b|| and ||b|| <= (1 + c) ||k*||
-    rel_err = tol * (1 + c) / (1 - c)
-    norms = {j: float(np.linalg.norm(kk[:, t])) for t, j in enumerate(pick)}
-    for t, j in enumerate(pick):
-        assert kk[:, t].min() >= -rel_err * norms[j]
-    for a in pick:
-        for b in pick:
-            if a < b:
-                kab = kk[int(qs[a]), pick.index(b)]
-                kba = kk[int(qs[b]), pick.index(a)]
-                assert abs(kab - kba) <= rel_err * (norms[a] + norms[b]), (a, b, kab, kba)
+        ok, e = _err_ok(kk[:, t], ref[:, t], tau + 2 * tail)
+        worst = (max(worst[0], e[0]), max(worst[1], e[1]))
+        assert ok, (label, j, int(qs[j]), e)
+    _say("  %s: %d columns, max rel 2-norm error %.2e, max entry error / ||k|| %.2e (tau %.0e)"
+         % (label, len(pick), worst[0], worst[1], tau))
 
 
 @pytest.mark.timeout(300)
-def test_lnsbm4m_batch256_fp64_properties():
-    import torch
+def test_cl1m_batch200_fp64_vs_oracle():
+    """200 columns per launch on the power-law graph: the FP64 SpMM variant of
+    129-256 columns and its whole-workgroup hub rows (rows above 256 entries)
+    at B > 1, both methods, against the oracle's series."""
+    w = ki.workload("cl1m", nq=200)
+    g = w.graph
+    A = oracle.csr_matrix(g.n, g.row_ptr, g.col)
+    lam = oracle.lambda_max(A)
+    c, tau, tail = 0.5, 1e-6, 1e-10
+    beta = c / lam
+    qs = w.queries[:200]
+    assert int(np.max(np.diff(g.row_ptr))) > 256  # hub rows exist
+    _say("cl1m batch 200: %s" % _host())
+    pick = _pick(200, 8, 11)
+    ref = _series(g, qs[pick], beta, c, tail)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=32, max_block=64)
+    for method, name in ((K.KATZ_METHOD_LRC, "lrc"), (K.KATZ_METHOD_CG, "cg")):
+        kk, _ = _batch_vs_oracle(g, idx, qs, tau * (1 - c) / (1 + c), pick, method)
+        _check_cols(kk, ref, pick, qs, tau, tail, "cl1m B=200 " + name)
+    idx.close()
+
+
+@pytest.mark.timeout(300)
+def test_lnsbm4m_batch256_fp64_vs_oracle():
+    """The 4M-node lognormal SBM, 256 columns per solve, FP64, c = 0.5
+    (planted communities as the partition): 8 sampled columns against the
+    oracle, residual requested at tau (1 - c) / (1 + c), tau = 1e-6."""
     w = ki.workload("lnsbm4m")
     g = w.graph
-    print("lnsbm4m: n=%d nnz=%d" % (g.n, g.row_ptr[-1]), flush=True)
-    A = oracle.csr_matrix(g.n, g.row_ptr, g.col)
-    beta = _test_beta(A, 0.5)
-    idx = K.KatzIndex.from_graph(g, beta=beta, rank=32, max_block=64, labels=g.labels)
-    tol = 1e-6
+    _say("lnsbm4m: n=%d nnz=%d; %s" % (g.n, g.row_ptr[-1], _host()))
+    c, tau, tail = 0.5, 1e-6, 1e-10
+    beta = c / _lambda(g)
     qs = w.queries[:256]
-    out = torch.empty((256, g.n), dtype=torch.float64, device="cuda")
-    _, st = idx.query(qs, out=out, tol=tol)
-    torch.cuda.synchronize()
-    _batch_properties(g, A, beta, 0.5, qs, out, st, tol, [0, 77, 131, 255])
-    del out
+    pick = _pick(256, 8, 3)
+    ref = _series(g, qs[pick], beta, c, tail)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=32, max_block=64, labels=g.labels)
+    kk, _ = _batch_vs_oracle(g, idx, qs, tau * (1 - c) / (1 + c), pick, K.KATZ_METHOD_LRC)
+    _check_cols(kk, ref, pick, qs, tau, tail, "lnsbm4m B=256 lrc")
     idx.close()
-    torch.cuda.empty_cache()
 
 
-@pytest.mark.timeout(300)
-def test_cl8m_batch512_mixed_properties():
-    import torch
+@pytest.mark.timeout(420)
+def test_cl8m_batch512_mixed_vs_oracle():
+    """The 8M-node Chung-Lu graph, 512 columns per solve in the precision form
+    (FP32 SpMM and block solves, BF16 low-rank factor, FP64 refinement), c =
+    0.9, rank 64, at the benchmark's residual 1e-6: 8 sampled columns against
+    the oracle at the precision form's tau = 1e-4 (the residual's bound is
+    1e-6 * 19 = 1.9e-5)."""
     w = ki.workload("cl8m")
     g = w.graph
-    print("cl8m: n=%d nnz=%d" % (g.n, g.row_ptr[-1]), flush=True)
-    A = oracle.csr_matrix(g.n, g.row_ptr, g.col)
-    beta = _test_beta(A, 0.9)
-    idx = K.KatzIndex.from_graph(g, beta=beta, rank=64, max_block=64, precision=K.KATZ_PREC_MIXED)
-    tol = 1e-6
+    _say("cl8m: n=%d nnz=%d; %s" % (g.n, g.row_ptr[-1], _host()))
+    c, tau, tail = 0.9, 1e-4, 1e-7
+    beta = c / _lambda(g)
     qs = w.queries[:512]
-    out = torch.empty((512, g.n), dtype=torch.float64, device="cuda")
-    _, st = idx.query(qs, out=out, tol=tol)
-    torch.cuda.synchronize()
-    _batch_properties(g, A, beta, 0.9, qs, out, st, tol, [3, 200, 511])
-    del out
+    pick = _pick(512, 8, 4)
+    ref = _series(g, qs[pick], beta, c, tail)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=64, max_block=64, precision=K.KATZ_PREC_MIXED)
+    kk, st = _batch_vs_oracle(g, idx, qs, 1e-6, pick, K.KATZ_METHOD_LRC)
+    _check_cols(kk, ref, pick, qs, tau, tail, "cl8m B=512 mixed lrc")
+    # the residual bound of every column of the batch, as the library reports it
+    bound = max(s["rel_residual"] for s in st) * (1 + c) / (1 - c)
+    assert bound <= 1.9e-5 * 1.0001
     idx.close()
-    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(420)
+def test_dcsbm_quarter_serving_top100_vs_oracle():
+    """The serving form on the degree-corrected SBM hybrid at 1/4 scale (4M
+    nodes, mean degree 25), precision form, rank 64, c = 0.5: 4 requests of
+    round(2^u) nodes (u ~ U[0, 9], the benchmark's request recipe) served
+    together; for 2 sampled query nodes of each request the top-100
+    non-neighbour list must equal the oracle's under the tie rule (classes of
+    width 2 tau ||k||, tau = 3e-6 from the residual 1e-6)."""
+    w = ki.workload("dcsbm16m", scale=0.25)
+    g = w.graph
+    _say("dcsbm16m/4: n=%d nnz=%d; %s" % (g.n, g.row_ptr[-1], _host()))
+    c = 0.5
+    tau = 1e-6 * (1 + c) / (1 - c)
+    beta = c / _lambda(g)
+    rng = np.random.default_rng(4005)
+    pool = ki.sample_queries(g, 200000, 4006)
+    reqs = [pool[rng.integers(0, len(pool), size=int(round(2 ** rng.uniform(0, 9))))] for _ in range(4)]
+    _say("  request sizes %s" % [len(r) for r in reqs])
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=64, max_block=64, labels=g.labels,
+                                 precision=K.KATZ_PREC_MIXED)
+    srv = K.KatzServer(idx, workers=4, max_batch=64, k=100, tol=1e-6)
+    try:
+        tks = [srv.submit(r) for r in reqs]
+        res = [srv.poll(t) for t in tks]
+    finally:
+        srv.close()
+    checks = []
+    for i, r in enumerate(reqs):
+        ids, sc, st, lat = res[i]
+        assert ids.shape == (len(r), 100)
+        assert all(s["status"] == 0 and s["rel_residual"] <= 1e-6 for s in st)
+        sel = list(range(len(r))) if len(r) <= 2 else sorted(
+            np.random.default_rng(100 + i).choice(len(r), size=2, replace=False).tolist())
+        checks += [(i, j) for j in sel]
+    qn = [int(reqs[i][j]) for i, j in checks]
+    ref = _series(g, qn, beta, c, 1e-10)
+    for t, (i, j) in enumerate(checks):
+        kv = ref[:, t]
+        _, _, sid, ssc = oracle.topk_links(g.n, g.row_ptr, g.col, kv, qn[t], 100)
+        ok, msg, ncls = oracle.topk_accept(res[i][0][j], sid, ssc, 100, 2 * (tau + 1e-10) * np.linalg.norm(kv))
+        assert ok, (i, j, qn[t], msg)
+    _say("  %d top-100 lists equal the oracle's under the tie rule" % len(checks))
+    idx.close()
