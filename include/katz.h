@@ -194,6 +194,31 @@ int katz_query(const katz_index* idx, const int32_t* q, int32_t nq, const katz_q
                double* scores, katz_query_stats* st, void* stream);
 
 /*
+ * katz_query without allocation, for callers that cannot allocate device
+ * memory (code running under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * katz_query, with these differences:
+ *   - every buffer of the solve (panels, partial sums, per-column state) lies
+ *     in a static device array of the library, 256 MiB, one per GPU the
+ *     library runs on, held until the process ends; the call makes no
+ *     hipMalloc, hipFree, pinned-host or graph allocation (its first call on
+ *     a device only looks up that array's address);
+ *   - KATZ_EINVAL when one query column of this index needs more scratch
+ *     than 256 MiB (the message gives both sizes; about 60 bytes per node
+ *     and column in FP64, so graphs of up to about 4 million nodes fit);
+ *     larger nq runs in chunks of the columns that fit;
+ *   - it runs on `stream` itself (not on a workspace stream), without HIP
+ *     graphs, kernel profiling or the SpMM launch-shape autotuner (it uses
+ *     the shape an earlier katz_query chose, or the default);
+ *   - every call on one GPU shares that GPU's scratch, which keeps the last
+ *     call's contents (the state that must start at zero is cleared by each
+ *     call): calls that overlap on one GPU, from several threads or streams,
+ *     race and must be serialised by the caller.
+ */
+int katz_query_noalloc(const katz_index* idx, const int32_t* q, int32_t nq, const katz_query_opts* opts,
+                       double* scores, katz_query_stats* st, void* stream);
+
+/*
  * Top-k predicted links per query (Sec. 3.3; the descending sort of
  * Algorithm 3): candidates are all nodes except q and its neighbours, ranked
  * by (Katz score descending, node id ascending).

@@ -32,6 +32,7 @@ _STATUS = {0: "KATZ_OK", -1: "KATZ_EINVAL", -2: "KATZ_ENOTSYM", -3: "KATZ_EDIVER
            -5: "KATZ_EDEVICE", -6: "KATZ_ENOCONV", -7: "KATZ_EBUSY", -8: "KATZ_EIO"}
 
 EXPORTED = ["katz_build_opts_default", "katz_query_opts_default", "katz_index_build", "katz_query",
+            "katz_query_noalloc",
             "katz_topk_links", "katz_pair_scores", "katz_sparse_katz", "katz_index_save", "katz_index_load", "katz_index_free", "katz_index_info", "katz_index_partition",
             "katz_index_lowrank", "katz_profile_enable", "katz_profile_reset", "katz_profile_read",
             "katz_server_opts_default", "katz_server_create", "katz_server_submit", "katz_server_poll",
@@ -109,6 +110,9 @@ def _load():
     lib.katz_query.argtypes = [P, pi32, i32, ctypes.POINTER(katz_query_opts), P,
                                ctypes.POINTER(katz_query_stats), P]
     lib.katz_query.restype = ctypes.c_int
+    lib.katz_query_noalloc.argtypes = [P, pi32, i32, ctypes.POINTER(katz_query_opts), P,
+                                       ctypes.POINTER(katz_query_stats), P]
+    lib.katz_query_noalloc.restype = ctypes.c_int
     lib.katz_topk_links.argtypes = [P, pi32, i32, i32, ctypes.POINTER(katz_query_opts), P, P,
                                     ctypes.POINTER(katz_query_stats), P]
     lib.katz_topk_links.restype = ctypes.c_int
@@ -216,6 +220,18 @@ def katz_query(idx, q, opts: Optional[katz_query_opts], scores, stats=None, stre
     st = (katz_query_stats * len(qa))() if stats is None else stats
     rc = _lib.katz_query(idx, _pi32(qa), len(qa), ctypes.byref(opts) if opts is not None else None,
                          _ptr(scores), st, ctypes.c_void_p(stream) if stream else None)
+    if rc not in (KATZ_OK, KATZ_ENOCONV):
+        _check(rc)
+    return rc
+
+
+def katz_query_noalloc(idx, q, opts: Optional[katz_query_opts], scores, stats=None, stream=None) -> int:
+    """katz_query with every solve buffer in the library's static device
+    scratch (no allocation); see include/katz.h."""
+    qa = np.ascontiguousarray(q, np.int32)
+    st = (katz_query_stats * len(qa))() if stats is None else stats
+    rc = _lib.katz_query_noalloc(idx, _pi32(qa), len(qa), ctypes.byref(opts) if opts is not None else None,
+                                 _ptr(scores), st, ctypes.c_void_p(stream) if stream else None)
     if rc not in (KATZ_OK, KATZ_ENOCONV):
         _check(rc)
     return rc
@@ -394,6 +410,20 @@ class KatzIndex:
         st = (katz_query_stats * len(q))()
         katz_query(self.h, q, self._opts(tol, method, max_iter, max_sweeps, check_every, force_fallback), out,
                    st, stream)
+        return out, stats_dicts(st)
+
+    def query_noalloc(self, q: Sequence[int], out=None, *, tol: float = 1e-6, method: int = KATZ_METHOD_LRC,
+                      max_iter: int = 0, max_sweeps: int = 0, check_every: int = 0, stream=None):
+        """As query(), through katz_query_noalloc (static device scratch, no
+        allocation in the library)."""
+        q = np.atleast_1d(np.asarray(q, np.int32))
+        if out is None:
+            out = np.empty((len(q), self.n), np.float64)
+        if stream is None and hasattr(out, "data_ptr") and getattr(out, "is_cuda", False):
+            import torch
+            stream = torch.cuda.current_stream(out.device).cuda_stream
+        st = (katz_query_stats * len(q))()
+        katz_query_noalloc(self.h, q, self._opts(tol, method, max_iter, max_sweeps, check_every), out, st, stream)
         return out, stats_dicts(st)
 
     def pair_scores(self, src: Sequence[int], dst: Sequence[int], out=None, *, tol: float = 1e-6,

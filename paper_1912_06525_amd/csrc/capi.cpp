@@ -184,6 +184,22 @@ int katz_query(const katz_index* idx, const int32_t* q, int32_t nq, const katz_q
   });
 }
 
+int katz_query_noalloc(const katz_index* idx, const int32_t* q, int32_t nq, const katz_query_opts* opts,
+                       double* scores, katz_query_stats* st, void* stream) {
+  return guarded([&]() -> int {
+    int rc = check_queries(idx, q, nq);
+    if (rc) return rc;
+    if (nq == 0) return KATZ_OK;
+    if (!scores) return set_error(KATZ_EINVAL, "null scores buffer");
+    katz::QueryArgs a{};
+    a.q = q; a.nq = nq; a.opts = resolve(opts); a.scores = scores; a.topk = 0;
+    a.st = st; a.stream = stream;
+    rc = katz::device_query_noalloc(idx->host, idx->dev, a);
+    if (rc == KATZ_ENOCONV) set_error(rc, "some queries did not reach the tolerance (see stats)");
+    return rc;
+  });
+}
+
 int katz_pair_scores(const katz_index* idx, const int32_t* src, const int32_t* dst, int32_t npairs,
                      const katz_query_opts* opts, double* scores, katz_query_stats* st, void* stream) {
   return guarded([&]() -> int {

@@ -103,6 +103,10 @@ struct QueryArgs {
   double* pair_out = nullptr;
 };
 int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& a);
+// As device_query for scores only (no top-K or pairs), on the caller's
+// stream, with every buffer of the solve in the library's static device
+// scratch: no device or pinned allocation, no graph capture.
+int device_query_noalloc(const HostIndex& H, DeviceIndex* D, const QueryArgs& a);
 // Serializes an open HIP graph capture (one thread) with the operations of
 // other threads that may synchronize with the legacy stream (allocation,
 // frees, synchronous copies and memsets, stream and event creation, work on

@@ -1699,6 +1699,9 @@ struct Workspace {
   hipStream_t stream = nullptr;          // the workspace's own stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;  // captured iteration chunks
+  // carved from caller-independent scratch (katz_query_noalloc): owns no
+  // memory, stream or events; runs without graphs, profiling or autotuning
+  bool external = false;
   ~Workspace();
 };
 
@@ -1958,7 +1961,7 @@ static void free_ws(Workspace* w) {
   w->stream = nullptr;
   w->ev_in = w->ev_out = nullptr;
   for (void* p : w->allocs) (void)hipFree(p);
-  if (w->hpin) (void)hipHostFree(w->hpin);
+  if (w->hpin && !w->external) (void)hipHostFree(w->hpin);
   w->hpin = nullptr;
   w->allocs.clear();
 }
@@ -2103,7 +2106,7 @@ struct Launcher {
   // `bytes` algorithmic bytes to `kind`.
   template <typename F>
   void timed(int kind, double bytes, F&& launch) {
-    const bool on = g_prof_on.load(std::memory_order_relaxed) != 0;
+    const bool on = g_prof_on.load(std::memory_order_relaxed) != 0 && !w->external;
     if (on) w->prof.begin(kind, bytes, st);
     launch();
     if (on) w->prof.end(st);
@@ -2114,7 +2117,7 @@ struct Launcher {
   template <typename F>
   void timed_cols(int kind, double bytes_per_col, F&& launch) {
     double b = 0.0;
-    if (g_prof_on.load(std::memory_order_relaxed) != 0) {
+    if (g_prof_on.load(std::memory_order_relaxed) != 0 && !w->external) {
       int* h = (int*)((char*)w->hpin + kPinProfOff);
       HIPCHECK(hipMemcpyAsync(h, w->n_active, sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
@@ -2277,7 +2280,7 @@ struct Launcher {
     if (a.row1 <= a.row0) return;
     a.B = B;
     const SpmmVariant<T> v = spmm_variant<T>(a.val != nullptr);
-    if (!tu.autotune || D->walk[v.slot].load(std::memory_order_acquire) >= 0) return;
+    if (!tu.autotune || w->external || D->walk[v.slot].load(std::memory_order_acquire) >= 0) return;
     hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
     HIPCHECK(hipStreamIsCapturing(st, &cst));
     if (cst != hipStreamCaptureStatusNone) return;
@@ -2341,7 +2344,7 @@ struct Launcher {
   template <typename F>
   void iterate(int64_t key, int max_iter, int check_every, F&& one_iter) {
     int* hflag = (int*)((char*)w->hpin + kPinFlagOff);
-    const bool graphs = tuning().graphs && !g_prof_on.load(std::memory_order_relaxed);
+    const bool graphs = tuning().graphs && !g_prof_on.load(std::memory_order_relaxed) && !w->external;
     int it = 0;
     for (int chunk = 0; it < max_iter; chunk++) {
       int want;
@@ -3270,6 +3273,155 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
         s.path = res[j].path;
         s.rel_residual = res[j].rel;
         s.err_bound = res[j].rel * (1.0 + D->c) / (1.0 - D->c);
+      }
+    }
+  }
+  return rc;
+}
+
+// ------------------------------------------------ queries without allocation
+// Scratch of katz_query_noalloc: panels, partial sums and per-column state
+// of the solve live in this file-scope device array (one copy on every GPU
+// the library runs on, held until the process ends).  Host code never passes
+// `scratch` itself to a kernel or copy: its name is a host-side stand-in, and
+// the device address is taken once per device with hipGetSymbolAddress.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr size_t kNoAllocHostBytes = 64 * 1024;  // host staging, as the pinned staging of a workspace
+
+struct NoAllocSlot {
+  void* dev = nullptr;                 // device address of `scratch` on this device
+  std::unique_ptr<char[]> host;        // host staging for query ids, masks and polled scalars
+};
+
+// Set-up, once per device and with that device current: the device address
+// of the scratch array and the host staging.  Later calls only look up.
+NoAllocSlot& noalloc_slot(int device) {
+  static std::mutex mu;
+  static std::map<int, NoAllocSlot> slots;
+  std::lock_guard<std::mutex> g(mu);
+  NoAllocSlot& sl = slots[device];
+  if (!sl.dev) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      fail(KATZ_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    sl.host.reset(new char[kNoAllocHostBytes]);
+    sl.dev = p;
+  }
+  return sl;
+}
+
+// Bump allocation over [base, base + cap) at 256-byte alignment; with
+// base == nullptr it only counts.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+// Lays a B-column workspace (the buffers run_batch uses: panels, partial
+// sums, low-rank terms, per-column scalars and state) over `base`; returns
+// the bytes it takes.  Top-K and pair buffers are not laid out.
+size_t carve_ws(const DeviceIndex* D, int B, char* base, Workspace* w) {
+  Carve c{base};
+  const int64_t nB = (int64_t)D->n * B;
+  const int64_t esz = solve_elem_bytes(D);
+  const int64_t rk = std::max(1, D->rank);
+  double* Rhs = c.take<double>(nB);
+  double* K = c.take<double>(nB);
+  char* Dx = c.take<char>(nB * esz);
+  char* X = c.take<char>(nB * esz);
+  char* Y = c.take<char>(nB * esz);
+  char* W = c.take<char>(nB * esz);
+  char* Z = c.take<char>((int64_t)std::max(1, D->n2) * B * esz);
+  const size_t pcap = partials_per_column(D) * (size_t)std::max(B, 1);
+  double* partials = c.take<double>((int64_t)pcap);
+  double* DW = c.take<double>(rk * B);
+  double* DW2 = c.take<double>(rk * B);
+  double* sc = c.take<double>(12 * (int64_t)B);
+  float* Rf = D->precision == KATZ_PREC_MIXED ? c.take<float>(nB) : nullptr;
+  int* ip = c.take<int>(4 * (int64_t)B + 1);
+  int32_t* qpos = c.take<int32_t>(B);
+  if (w) {
+    w->B = B; w->n = D->n; w->n2 = D->n2; w->device = D->device;
+    w->Rhs = Rhs; w->K = K; w->Dx = Dx; w->X = X; w->Y = Y; w->W = W; w->Z = Z;
+    w->partials = partials; w->partials_cap = pcap; w->DW = DW; w->DW2 = DW2;
+    w->rz = sc; w->pq = sc + B; w->alpha = sc + 2 * B; w->bcg = sc + 3 * B; w->rr = sc + 4 * B;
+    w->thr = sc + 5 * B; w->bn2 = sc + 6 * B; w->res2 = sc + 7 * B; w->colscale = sc + 8 * B;
+    w->rn2 = sc + 9 * B; w->inv = sc + 10 * B; w->fwd = sc + 11 * B;
+    w->Rf = Rf;
+    w->active = ip; w->status = ip + B; w->iters = ip + 2 * B; w->mask = ip + 3 * B; w->n_active = ip + 4 * B;
+    w->qpos = qpos;
+  }
+  return c.off;
+}
+
+}  // namespace
+
+int device_query_noalloc(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa) {
+  HIPCHECK(hipSetDevice(D->device));
+  NoAllocSlot& sl = noalloc_slot(D->device);
+  // columns that fit: the layout is affine in B
+  const size_t one = carve_ws(D, 1, nullptr, nullptr), two = carve_ws(D, 2, nullptr, nullptr);
+  const size_t per = two - one, fixed = one - per;
+  if (one > kScratchBytes)
+    fail(KATZ_EINVAL, "index too large for the allocation-free query: one query column needs " +
+                          std::to_string(one) + " bytes of scratch, the scratch holds " +
+                          std::to_string(kScratchBytes));
+  const int cap = (int)std::min<size_t>(512, (kScratchBytes - fixed) / per);
+  hipStream_t st = (hipStream_t)qa.stream;
+  const int n = D->n;
+  const bool dev_scores = qa.scores && is_device_ptr(qa.scores);
+  int rc = KATZ_OK;
+  for (int c0 = 0; c0 < qa.nq; c0 += cap) {
+    const int B = std::min(cap, qa.nq - c0);
+    Workspace w;
+    w.external = true;
+    const size_t used = carve_ws(D, B, (char*)sl.dev, &w);
+    if (used > kScratchBytes) fail(KATZ_EDEVICE, "internal: scratch layout exceeds the scratch");
+    w.hpin = sl.host.get();
+    // state that starts at zero (per-column scalars and flags), cleared by a
+    // fill kernel on the caller's stream: the previous call's contents remain
+    Launcher L0{D, &w, st, B};
+    L0.fill<double>(w.rz, 12 * (int64_t)B, 0.0);
+    L0.fill<int>(w.active, 4 * (int64_t)B + 1, 0);
+    std::vector<ColResult> res;
+    run_batch(H, D, &w, st, qa.q + c0, B, qa.opts, res);
+    if (qa.scores) {
+      double* dst = qa.scores + (int64_t)c0 * n;
+      double* out = dev_scores ? dst : w.Rhs;  // Rhs is free once the batch is solved
+      if (B >= 32) {
+        dim3 g((unsigned)((n + 63) / 64), (unsigned)((B + 63) / 64));
+        k_unpermute_tiled<double><<<g, WG, 0, st>>>(n, B, w.K, D->perm, out);
+      } else {
+        dim3 g(grid_for(n, WG * 4), B);
+        k_unpermute<double><<<g, WG, 0, st>>>(n, B, w.K, D->perm, out);
+      }
+      if (!dev_scores)
+        HIPCHECK(hipMemcpyAsync(dst, out, sizeof(double) * (size_t)n * B, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    HIPCHECK(hipGetLastError());
+    for (int j = 0; j < B; j++) {
+      if (res[j].status != KATZ_OK) rc = KATZ_ENOCONV;
+      if (qa.st) {
+        katz_query_stats& s2 = qa.st[c0 + j];
+        s2.status = res[j].status;
+        s2.iters = res[j].iters;
+        s2.sweeps = res[j].sweeps;
+        s2.path = res[j].path;
+        s2.rel_residual = res[j].rel;
+        s2.err_bound = res[j].rel * (1.0 + D->c) / (1.0 - D->c);
       }
     }
   }
