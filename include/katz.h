@@ -65,10 +65,18 @@ enum katz_precision {
 enum katz_l_kind {
   KATZ_L_AUTO = 0,    /* CHOL when the separator is small (<= 1024), else IDENTITY */
   KATZ_L_CHOL = 1,    /* L = dense Cholesky factor of M22 (eq. RMatrix as printed); n2 <= 4096 */
-  KATZ_L_IDENTITY = 2 /* L = I: R = I - S, preconditioner I + U~ D U~^T */
+  KATZ_L_IDENTITY = 2, /* L = I: R = I - S, preconditioner I + U~ D U~^T */
+  KATZ_L_IC0 = 3      /* L = incomplete Cholesky factor of M22 with zero fill (an SPD L of
+                         M22's own sparsity; the preconditioner ablation); n2 <= 4096 */
 };
 
-enum katz_method { KATZ_METHOD_LRC = 0, KATZ_METHOD_CG = 1 };
+enum katz_method {
+  KATZ_METHOD_LRC = 0,   /* PCG on the Schur complement S, preconditioned by S~ (Sec. 3.2 step 5) */
+  KATZ_METHOD_CG = 1,    /* plain CG on M, the comparison method and the fallback */
+  KATZ_METHOD_PCGNR = 2  /* ablation: Algorithm 2's recurrence with the step gamma = s^T S~^{-1} s
+                            for s = S r, i.e. preconditioned CG on the normal equations of S
+                            (two S-applies per iteration); results as LRC */
+};
 
 enum katz_order {
   KATZ_ORDER_AUTO = 0,     /* LOCALITY */
@@ -139,7 +147,7 @@ typedef struct {
   int32_t nblocks;         /* M11 blocks */
   int32_t max_block_size;  /* largest M11 block */
   int32_t rank;            /* r actually kept */
-  int32_t l_kind;          /* resolved katz_l_kind (CHOL or IDENTITY) */
+  int32_t l_kind;          /* resolved katz_l_kind (CHOL, IDENTITY or IC0) */
   int32_t precision;
   int32_t device;          /* -1 for a host-only index */
   double beta, lambda_max, c;
@@ -161,7 +169,8 @@ void katz_query_opts_default(katz_query_opts* o);
  * Builds the index (Algorithm 1): validates the CSR, computes lambda_max(A)
  * by Lanczos, partitions the graph into blocks of at most max_block nodes
  * plus a vertex separator (Sec. 3.2 steps 2-3), inverts every M11 block
- * through its Cholesky factor (step 4), factors M22 when l_kind is CHOL, and
+ * through its Cholesky factor (step 4), factors M22 when l_kind is CHOL (or
+ * takes its zero-fill incomplete factor for IC0), and
  * runs Lanczos on R for the top `rank` eigenpairs (eq. RMatrix).  Then the
  * index is copied to the device once.
  *   n, nnz, row_ptr[n+1], col_idx[nnz]: host CSR, int32, strictly increasing

@@ -23,8 +23,8 @@ LIB_PATH = os.path.join(_HERE, "libkatz_hip.so")
 KATZ_OK, KATZ_EINVAL, KATZ_ENOTSYM, KATZ_EDIVERGE, KATZ_ENOMEM = 0, -1, -2, -3, -4
 KATZ_EDEVICE, KATZ_ENOCONV, KATZ_EBUSY, KATZ_EIO = -5, -6, -7, -8
 KATZ_PREC_FP64, KATZ_PREC_MIXED = 0, 1
-KATZ_L_AUTO, KATZ_L_CHOL, KATZ_L_IDENTITY = 0, 1, 2
-KATZ_METHOD_LRC, KATZ_METHOD_CG = 0, 1
+KATZ_L_AUTO, KATZ_L_CHOL, KATZ_L_IDENTITY, KATZ_L_IC0 = 0, 1, 2, 3
+KATZ_METHOD_LRC, KATZ_METHOD_CG, KATZ_METHOD_PCGNR = 0, 1, 2
 KATZ_PATH_LRC, KATZ_PATH_CG, KATZ_PATH_CG_FALLBACK = 0, 1, 2
 KATZ_ORDER_AUTO, KATZ_ORDER_DEGREE, KATZ_ORDER_LOCALITY = 0, 1, 2
 

@@ -81,6 +81,8 @@ katz_query_opts resolve(const katz_query_opts* o) {
   if (r.max_iter <= 0) r.max_iter = 1000;
   if (r.max_sweeps <= 0) r.max_sweeps = 6;
   if (r.check_every < 0) r.check_every = 0;  // 0: adaptive polling
+  if (r.method != KATZ_METHOD_LRC && r.method != KATZ_METHOD_CG && r.method != KATZ_METHOD_PCGNR)
+    katz::fail(KATZ_EINVAL, "bad method");
   return r;
 }
 }  // namespace

@@ -195,6 +195,40 @@ bool chol_lower(double* a, int b) {
   return true;
 }
 
+// Incomplete Cholesky with zero fill, IC(0), of the m x m row-major
+// symmetric matrix a (lower triangle read), in place: the lower factor keeps
+// the sparsity pattern of a's lower triangle, and fill outside it is dropped
+// instead of stored.  Row i: l[i][k] = (a[i][k] - sum_j l[i][j] l[k][j]) /
+// l[k][k] for k in the row's pattern (j over the pattern entries before k;
+// entries of row k outside its own pattern are zero), then l[i][i] =
+// sqrt(a[i][i] - sum_j l[i][j]^2).  The factor exists for symmetric
+// M-matrices such as M22 = I - beta A22 (Meijerink and van der Vorst, 1977).
+// Returns false on a nonpositive pivot.
+bool ic0_lower(double* a, int m) {
+  std::vector<std::vector<int>> pat(m);
+  for (int i = 0; i < m; i++)
+    for (int j = 0; j < i; j++)
+      if (a[(size_t)i * m + j] != 0.0) pat[i].push_back(j);
+  for (int i = 0; i < m; i++) {
+    double* ai = &a[(size_t)i * m];
+    const std::vector<int>& pi = pat[i];
+    for (size_t t = 0; t < pi.size(); t++) {
+      const int k = pi[t];
+      const double* ak = &a[(size_t)k * m];
+      double s = ai[k];
+      for (size_t u = 0; u < t; u++) s -= ai[pi[u]] * ak[pi[u]];
+      ai[k] = s / ak[k];
+    }
+    double d = ai[i];
+    for (int j : pi) d -= ai[j] * ai[j];
+    if (!(d > 0.0)) return false;
+    ai[i] = std::sqrt(d);
+  }
+  for (int j = 0; j < m; j++)
+    for (int k = j + 1; k < m; k++) a[(size_t)j * m + k] = 0.0;
+  return true;
+}
+
 // Given the lower factor l (b x b), writes inv = (l l^T)^{-1} (full,
 // symmetric): column j of l^{-1} is stored as row j of w (forward
 // substitution on contiguous rows), then inv[i][j] = <w row i, w row j>.
@@ -335,40 +369,105 @@ struct Partition {
   int32_t n1 = 0, n2 = 0;
 };
 
-// BFS order of the nodes of `nodes` (a set marked by inset[v] == tag), restarting
-// from the lowest unvisited node; the first BFS of each component starts from
-// a pseudo-peripheral node (the last node reached by a BFS from the seed).
+// Node marks are read across the parts that the BFS orders of different
+// parts visit at once (a neighbour in another part never carries this part's
+// tag, whichever of its two values a concurrent BFS leaves there): relaxed
+// atomic accesses.
+inline int32_t mark_get(const std::vector<int32_t>& m, int32_t v) { return __atomic_load_n(&m[v], __ATOMIC_RELAXED); }
+inline void mark_set(std::vector<int32_t>& m, int32_t v, int32_t x) { __atomic_store_n(&m[v], x, __ATOMIC_RELAXED); }
+
+// Frontiers at least this large are expanded on all host cores.
+constexpr size_t kParFrontier = 16384;
+
+// Appends to `out` the BFS order from s over the nodes with mark == tag (and
+// marks them tag + 1): frontier by frontier, each frontier node in order
+// appends its unreached neighbours in CSR order, and a node adjacent to
+// several frontier nodes goes to the first of them -- the order of a FIFO
+// queue.  Large frontiers run in parallel with that rule made explicit:
+// claim[v] = the smallest frontier position that reaches v (claim holds
+// INT32_MAX outside a call), then each frontier node writes the nodes it
+// claimed at its prefix-sum offset.  `par`: whether parallel expansion is
+// allowed (false inside a parallel loop over parts).
+void bfs_levels(const int32_t* rp, const int32_t* col, std::vector<int32_t>& mark, int32_t tag, int32_t s,
+                std::vector<int32_t>& out, std::vector<int32_t>& claim, bool par) {
+  size_t f0 = out.size();
+  out.push_back(s);
+  mark_set(mark, s, tag + 1);
+  std::vector<int64_t> off;
+  while (f0 < out.size()) {
+    const size_t f1 = out.size(), fn = f1 - f0;
+    if (!par || fn < kParFrontier || host_threads() <= 1) {
+      for (size_t h = f0; h < f1; h++) {
+        const int32_t u = out[h];
+        for (int32_t k = rp[u]; k < rp[u + 1]; k++) {
+          const int32_t v = col[k];
+          if (mark_get(mark, v) == tag) { mark_set(mark, v, tag + 1); out.push_back(v); }
+        }
+      }
+      f0 = f1;
+      continue;
+    }
+    // claim: the first frontier position reaching each unreached node
+    parallel_for((int64_t)fn, [&](int64_t b, int64_t e) {
+      for (int64_t t = b; t < e; t++) {
+        const int32_t u = out[f0 + t];
+        for (int32_t k = rp[u]; k < rp[u + 1]; k++) {
+          const int32_t v = col[k];
+          if (mark_get(mark, v) != tag) continue;
+          int32_t cur = __atomic_load_n(&claim[v], __ATOMIC_RELAXED);
+          while ((int32_t)t < cur &&
+                 !__atomic_compare_exchange_n(&claim[v], &cur, (int32_t)t, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+          }
+        }
+      }
+    }, 1024);
+    // count and place each frontier node's claims in CSR order
+    off.assign(fn + 1, 0);
+    parallel_for((int64_t)fn, [&](int64_t b, int64_t e) {
+      for (int64_t t = b; t < e; t++) {
+        const int32_t u = out[f0 + t];
+        int64_t c = 0;
+        for (int32_t k = rp[u]; k < rp[u + 1]; k++) c += claim[col[k]] == (int32_t)t;
+        off[t + 1] = c;
+      }
+    }, 1024);
+    for (size_t t = 0; t < fn; t++) off[t + 1] += off[t];
+    out.resize(f1 + (size_t)off[fn]);
+    parallel_for((int64_t)fn, [&](int64_t b, int64_t e) {
+      for (int64_t t = b; t < e; t++) {
+        const int32_t u = out[f0 + t];
+        size_t at = f1 + (size_t)off[t];
+        for (int32_t k = rp[u]; k < rp[u + 1]; k++)
+          if (claim[col[k]] == (int32_t)t) out[at++] = col[k];
+      }
+    }, 1024);
+    parallel_for((int64_t)(out.size() - f1), [&](int64_t b, int64_t e) {
+      for (int64_t t = b; t < e; t++) {
+        const int32_t v = out[f1 + t];
+        mark_set(mark, v, tag + 1);
+        claim[v] = INT32_MAX;
+      }
+    }, 16384);
+    f0 = f1;
+  }
+}
+
+// BFS order of the nodes of `nodes` (a set marked by mark[v] == tag),
+// restarting from the lowest unvisited node; the BFS of each component starts
+// from a pseudo-peripheral node (the last node reached by a BFS from the
+// seed).  Visited nodes end with mark tag + 1.
 void bfs_order(const int32_t* rp, const int32_t* col, const std::vector<int32_t>& nodes,
                std::vector<int32_t>& mark, int32_t tag, std::vector<int32_t>& out,
-               std::vector<int32_t>& queue) {
+               std::vector<int32_t>& claim, bool par) {
   out.clear();
-  // mark[v] == tag: in set, unvisited; mark[v] == tag + 1: visited
-  auto bfs = [&](int32_t s, bool record, std::vector<int32_t>& seen) -> int32_t {
-    queue.clear();
-    queue.push_back(s);
-    seen.push_back(s);
-    mark[s] = tag + 1;
-    size_t h = 0;
-    int32_t last = s;
-    while (h < queue.size()) {
-      int32_t u = queue[h++];
-      last = u;
-      if (record) out.push_back(u);
-      for (int32_t k = rp[u]; k < rp[u + 1]; k++) {
-        int32_t v = col[k];
-        if (mark[v] == tag) { mark[v] = tag + 1; queue.push_back(v); seen.push_back(v); }
-      }
-    }
-    return last;
-  };
   std::vector<int32_t> seen;
   for (int32_t s : nodes) {
-    if (mark[s] != tag) continue;
+    if (mark_get(mark, s) != tag) continue;
     seen.clear();
-    int32_t far = bfs(s, false, seen);
-    for (int32_t v : seen) mark[v] = tag;  // unvisit the component
-    seen.clear();
-    bfs(far, true, seen);
+    bfs_levels(rp, col, mark, tag, s, seen, claim, par);
+    const int32_t far = seen.back();
+    for (int32_t v : seen) mark_set(mark, v, tag);  // unvisit the component
+    bfs_levels(rp, col, mark, tag, far, out, claim, par);
   }
 }
 
@@ -396,25 +495,43 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
     std::fill(part.begin(), part.end(), 0);
     P = 1;
   }
-  // (b) BFS chunking of every part into pieces of <= max_block nodes
+  // (b) BFS chunking of every part into pieces of <= max_block nodes.  Parts
+  // run in parallel (one BFS each) when there are several; one part runs
+  // its large frontiers in parallel.  The orders, and so the pieces, are the
+  // serial ones.
   std::vector<std::vector<int32_t>> members(P);
   for (int32_t v = 0; v < n; v++) members[part[v]].push_back(v);
-  std::vector<int32_t> mark(n, -1), order, queue;
+  std::vector<int32_t> mark(n), claim(n, INT32_MAX);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t v = b; v < e; v++) mark[v] = 2 * part[v];
+  }, 65536);
+  std::vector<std::vector<int32_t>> orders(P);
+  if (P == 1) {
+    bfs_order(rp, col, members[0], mark, 0, orders[0], claim, true);
+  } else {
+    parallel_for(P, [&](int64_t b, int64_t e) {
+      for (int64_t p = b; p < e; p++) bfs_order(rp, col, members[p], mark, 2 * (int32_t)p, orders[p], claim, false);
+    }, 1);
+  }
+  std::vector<std::vector<int32_t>>().swap(members);
   std::vector<int32_t> piece(n, -1);
   std::vector<int64_t> visit(n, 0);  // position in the concatenated BFS orders
-  int64_t nvisit = 0;
-  int32_t npiece = 0;
+  std::vector<int64_t> vbase(P + 1, 0), pbase(P + 1, 0);
   for (int32_t p = 0; p < P; p++) {
-    auto& mem = members[p];
-    for (int32_t v : mem) mark[v] = 2 * p;
-    bfs_order(rp, col, mem, mark, 2 * p, order, queue);
-    for (size_t k = 0; k < order.size(); k++) {
-      if (k % (size_t)max_block == 0) npiece++;
-      piece[order[k]] = npiece - 1;
-      visit[order[k]] = nvisit++;
-    }
-    std::vector<int32_t>().swap(mem);
+    vbase[p + 1] = vbase[p] + (int64_t)orders[p].size();
+    pbase[p + 1] = pbase[p] + ((int64_t)orders[p].size() + max_block - 1) / max_block;
   }
+  parallel_for(P, [&](int64_t b, int64_t e) {
+    for (int64_t p = b; p < e; p++) {
+      const auto& ord = orders[p];
+      for (size_t k = 0; k < ord.size(); k++) {
+        piece[ord[k]] = (int32_t)(pbase[p] + (int64_t)(k / (size_t)max_block));
+        visit[ord[k]] = vbase[p] + (int64_t)k;
+      }
+      std::vector<int32_t>().swap(orders[p]);
+    }
+  }, P > 1 ? 16 : 1);
+  int32_t npiece = (int32_t)pbase[P];
   phase("BFS chunks");
   // (c) greedy vertex cover of the cut edges (largest remaining cut degree first)
   std::vector<int32_t> cutdeg(n, 0);
@@ -633,7 +750,7 @@ void lanczos_R(HostIndex& H, int32_t r, int32_t steps, uint64_t seed) {
   int32_t m = steps > 0 ? steps : std::max(2 * r, r + 20);
   m = std::min(m, m2);
   SchurOp S(H);
-  const bool chol = H.l_kind == KATZ_L_CHOL;
+  const bool chol = H.l_kind != KATZ_L_IDENTITY;  // a dense lower factor L (CHOL or IC0)
   std::vector<double> Q((size_t)m * m2);
   std::vector<double> w(m2), tmp(m2);
   std::vector<double> al, be;
@@ -795,7 +912,7 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
   phase("validate");
   if (o.rank < 0) fail(KATZ_EINVAL, "rank must be >= 0");
   if (o.max_block < 0) fail(KATZ_EINVAL, "max_block must be >= 0");
-  if (o.l_kind < KATZ_L_AUTO || o.l_kind > KATZ_L_IDENTITY) fail(KATZ_EINVAL, "bad l_kind");
+  if (o.l_kind < KATZ_L_AUTO || o.l_kind > KATZ_L_IC0) fail(KATZ_EINVAL, "bad l_kind");
   if (o.precision != KATZ_PREC_FP64 && o.precision != KATZ_PREC_MIXED) fail(KATZ_EINVAL, "bad precision");
   if (o.order < KATZ_ORDER_AUTO || o.order > KATZ_ORDER_LOCALITY) fail(KATZ_EINVAL, "bad order");
   H.n = n;
@@ -890,9 +1007,10 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
   // separator factor
   int32_t lk = o.l_kind;
   if (lk == KATZ_L_AUTO) lk = (H.n2 > 0 && H.n2 <= 1024) ? KATZ_L_CHOL : KATZ_L_IDENTITY;
-  if (lk == KATZ_L_CHOL && H.n2 > 4096) fail(KATZ_EINVAL, "l_kind CHOL needs a separator of at most 4096 nodes");
+  if ((lk == KATZ_L_CHOL || lk == KATZ_L_IC0) && H.n2 > 4096)
+    fail(KATZ_EINVAL, "l_kind CHOL and IC0 need a separator of at most 4096 nodes");
   H.l_kind = lk;
-  if (lk == KATZ_L_CHOL && H.n2 > 0) {
+  if ((lk == KATZ_L_CHOL || lk == KATZ_L_IC0) && H.n2 > 0) {
     const int32_t m2 = H.n2, n1 = H.n1;
     H.lchol.assign((size_t)m2 * m2, 0.0);
     for (int32_t r = 0; r < m2; r++) {
@@ -901,7 +1019,8 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
       for (int32_t k = H.split[i]; k < H.rp[i + 1]; k++)
         H.lchol[(size_t)r * m2 + (H.col[k] - n1)] -= H.beta * (H.weighted ? H.val[k] : 1.0);
     }
-    if (!chol_lower(H.lchol.data(), m2)) fail(KATZ_EDIVERGE, "M22 is not positive definite (beta too large)");
+    const bool ok = lk == KATZ_L_CHOL ? chol_lower(H.lchol.data(), m2) : ic0_lower(H.lchol.data(), m2);
+    if (!ok) fail(KATZ_EDIVERGE, "M22 is not positive definite (beta too large)");
     H.ginv.assign((size_t)m2 * m2, 0.0);
     std::vector<double> w;
     chol_inverse(H.lchol.data(), m2, H.ginv.data(), w);

@@ -132,7 +132,7 @@ void validate_index(const HostIndex& H) {
   for (double x : H.minv)
     if (!std::isfinite(x)) bad("block inverse values");
   const int64_t n2 = H.n2;
-  if (H.l_kind == KATZ_L_CHOL) {
+  if (H.l_kind == KATZ_L_CHOL || H.l_kind == KATZ_L_IC0) {
     if ((int64_t)H.ginv.size() != n2 * n2 || (int64_t)H.lchol.size() != n2 * n2) bad("M22 factor size");
   } else if (H.l_kind == KATZ_L_IDENTITY) {
     if (!H.ginv.empty() || !H.lchol.empty()) bad("M22 factor present with L = I");

@@ -98,6 +98,24 @@ __device__ inline void final_reduce(const double* partials, int nwg, int nv, F&&
       }
       for (; w < nwg; w += WR) s0 += partials[(int64_t)w * nv + v];
     }
+    if (VC < 64) {
+      // lanes of a wave that share a value (tid % VC) first combine by a
+      // fixed shuffle tree, then the NT / 64 wave sums in order: two
+      // barriers instead of one per tree level
+      double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+      for (int off = VC; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
+      const int wave = tid / 64, lane = tid % 64;
+      if (lane < VC) red[wave * VC + lane] = s;
+      __syncthreads();
+      if (tid < VC) {
+        double t = 0.0;
+        for (int wv = 0; wv < NT / 64; wv++) t += red[wv * VC + tid];
+        if (v < nv) f(v, t);
+      }
+      __syncthreads();
+      continue;
+    }
     red[tid] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     for (int off = WR / 2; off > 0; off >>= 1) {

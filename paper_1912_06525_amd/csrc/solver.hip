@@ -1702,6 +1702,9 @@ struct Workspace {
   // carved from caller-independent scratch (katz_query_noalloc): owns no
   // memory, stream or events; runs without graphs, profiling or autotuning
   bool external = false;
+  // PCGNR ablation only (allocated on its first use): an n-row panel [t1 | r]
+  // and an n2-row panel s = S r
+  void *ab1 = nullptr, *ab2 = nullptr;
   ~Workspace();
 };
 
@@ -1933,7 +1936,7 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
     int64_t fb0 = D->bytes;
     D->minv = upload(D->allocs, H.minv, by);
     D->factor_bytes = D->bytes - fb0;
-    if (H.l_kind == KATZ_L_CHOL && H.n2 > 0) D->ginv = upload(D->allocs, H.ginv, by);
+    if (H.l_kind != KATZ_L_IDENTITY && H.n2 > 0) D->ginv = upload(D->allocs, H.ginv, by);
     if (H.precision == KATZ_PREC_MIXED) {
       std::vector<float> m32(H.minv.begin(), H.minv.end());
       D->minv32 = upload(D->allocs, m32, by);
@@ -2716,7 +2719,7 @@ static void update_r_vt1(Launcher& L, const TV* V, T* x, const T* p, T* r, const
 // One correction solve M d = rhs for the columns in w->mask; d is left in
 // w->Dx (all n rows), per-column outcome in w->iters / w->status.
 template <typename T>
-static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) {
+static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, bool pcgnr = false) {
   DeviceIndex* D = L.D;
   Workspace* w = L.w;
   const int B = L.B;
@@ -2864,6 +2867,68 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every) 
     L.tune_spmm(a);
   }
   size_lowrank_rows<T>(D, st);  // grid of the narrow low-rank kernels, before their first launch
+
+  if (pcgnr) {
+    // Ablation: the recurrence of Algorithm 2 as printed, with the step
+    // gamma = s^T (S~^{-1} s) for s = S r (the printed y^T s matches neither
+    // PCG nor PCGNR and diverges): preconditioned CG on the normal equations
+    // S^2 k2 = S f, two S-applies per iteration, k2 starting at 0.
+    if (w->external) fail(KATZ_EINVAL, "the PCGNR ablation is not available without allocation");
+    if (!w->ab1) {
+      w->ab1 = dalloc<char>(w->allocs, (int64_t)n * w->B * (int64_t)sizeof(T));
+      w->ab2 = dalloc<char>(w->allocs, (int64_t)std::max(1, n2) * w->B * (int64_t)sizeof(T));
+    }
+    T* RF = (T*)w->ab1;            // rows < n1: block-solve output; rows >= n1: r
+    T* Rn = RF + (int64_t)n1 * B;  // r = f - S k2 (n2 x B)
+    T* S2 = (T*)w->ab2;            // s = S r
+    // out2 = S in2 with in2 the separator rows of the full panel `full`
+    auto sapply = [&](T* full, T* in2, T* out2, int ep, const int* nact) {
+      m11(nullptr, (T)0, in2, beta, full, nact);   // t1 = M11^{-1} (beta A12 in2)
+      SpmmArgs<T> a{};
+      a.row0 = n1; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+      a.x = full; a.ca = -beta; a.cb = -beta; a.parts = 3;
+      a.v = in2; a.cv = (T)1; a.w = nullptr; a.cw = (T)0; a.y = out2;
+      a.ep = ep; a.dotv = nullptr; a.cs = cs; a.n_active = nact;  // EP_PQ: <q, q>
+      L.spmm(a);
+    };
+    auto precond_in = [&](const T* in, int ep, const int* nact) {  // Z2 = S~^{-1} in, <in, Z2>
+      const int rpw = L.rows_per_wg(n2), nwg = Launcher::nwg_for(n2, rpw);
+      L.need(nwg, (int64_t)std::max(1, D->rank) * B);
+      with_lowrank_factor<T>(D, [&](auto* V) {
+        typedef typename std::remove_cv<typename std::remove_pointer<decltype(V)>::type>::type TV;
+        precond_simple<T, TV>(L, V, in, Z2, ep, cs, nact, rpw, nwg);
+      });
+    };
+    m11(rhs, (T)1, nullptr, (T)0, X, nullptr);
+    {
+      SpmmArgs<T> a{};
+      a.row0 = n1; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+      a.x = X; a.ca = beta; a.cb = (T)0; a.parts = 1;
+      a.v = rhs + (int64_t)n1 * B; a.cv = (T)1; a.w = nullptr; a.cw = (T)0; a.y = Rn;
+      a.ep = EP_RR_INIT; a.dotv = nullptr; a.cs = cs; a.n_active = nullptr;
+      L.spmm(a);   // r = f, <r, r>, the active columns
+    }
+    L.fill<T>(K2, (int64_t)n2 * B, (T)0);
+    sapply(RF, Rn, S2, EP_NONE, nullptr);          // s = S r
+    precond_in(S2, EP_RZ_INIT, nullptr);           // w = S~^{-1} s, gamma = <s, w>
+    k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 1, cs);  // p = w
+    const int rpw2 = L.rows_per_wg(n2), nwg2 = Launcher::nwg_for(n2, rpw2);
+    L.need(nwg2, B);
+    L.iterate(sizeof(T) == 8 ? 5 : 6, max_iter, check_every, [&] {
+      sapply(X, P2, Q2, EP_PQ, w->n_active);      // q = S p; alpha = gamma / <q, q>
+      L.timed_cols(PK_UPDATE_R, 6.0 * sizeof(T) * n2, [&] {
+        k_update_r<T><<<nwg2, WG, WG * sizeof(double), st>>>(n2, B, rpw2, K2, P2, Rn, Q2, cs, w->partials);
+      });
+      L.finalize(nwg2, B, EP_RR, cs, nullptr, w->n_active);   // k2 += alpha p, r -= alpha q
+      sapply(RF, Rn, S2, EP_NONE, w->n_active);   // s = S r
+      precond_in(S2, EP_RZ, w->n_active);         // w, gamma', ratio gamma' / gamma
+      L.timed_cols(PK_UPDATE_P, 3.0 * sizeof(T) * n2, [&] {
+        k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 0, cs);  // p = w + ratio p
+      });
+    });
+    m11(rhs, (T)1, K2, beta, Dx, nullptr);
+    return;
+  }
 
   // ---- a2: t = M11^{-1} b1 -> X[0:n1]; f = b2 + beta A21 t -> R2; rr
   m11(rhs, (T)1, nullptr, (T)0, X, nullptr);
@@ -3048,7 +3113,7 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
         if (cg_pass)
           solve_cg<float>(L, w->Rf, iters, o.check_every);
         else
-          solve_lrc<float>(L, w->Rf, iters, o.check_every);
+          solve_lrc<float>(L, w->Rf, iters, o.check_every, o.method == KATZ_METHOD_PCGNR);
         // first sweep (one path for all columns): K = correction for every
         // column (those outside the mask are exactly 0: each solve clears Dx
         // and never touches inactive columns); later sweeps add
@@ -3062,7 +3127,7 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
         if (cg_pass)
           solve_cg<double>(L, rhs, iters, o.check_every);
         else
-          solve_lrc<double>(L, rhs, iters, o.check_every);
+          solve_lrc<double>(L, rhs, iters, o.check_every, o.method == KATZ_METHOD_PCGNR);
         if (sweep == 0)
           k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const double*)w->Dx, nullptr,
                                                                       nullptr, 0);

@@ -458,3 +458,43 @@ def test_query_wider_than_one_launch():
     qs = ki.sample_queries(g, 530, 31)
     assert len(qs) == 530
     _check(g, idx, beta, qs, 1e-6)
+
+
+@pytest.mark.parametrize("c", [0.5, 0.9, 0.99])
+@pytest.mark.parametrize("B", [1, 4, 40])
+def test_ic0_factor_matches_oracle(c, B):
+    """L = the zero-fill incomplete Cholesky factor of M22 (the preconditioner
+    ablation, any SPD L serves Theorem 1): results equal the oracle's at 1,
+    4 and 40 columns (the dense G apply with the unfused low-rank kernels)."""
+    g = ki.workload("lnsbm4m", scale=0.0006).graph
+    beta = oracle_beta(g, c)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=16, labels=g.labels, max_block=32, l_kind=K.KATZ_L_IC0)
+    assert idx.info.l_kind == K.KATZ_L_IC0
+    qs = ki.sample_queries(g, B, 61)
+    _check(g, idx, beta, qs, 1e-6)
+
+
+@pytest.mark.parametrize("prec", [K.KATZ_PREC_FP64, K.KATZ_PREC_MIXED])
+@pytest.mark.parametrize("lk", [K.KATZ_L_CHOL, K.KATZ_L_IDENTITY, K.KATZ_L_IC0])
+@pytest.mark.parametrize("B", [1, 6])
+def test_pcgnr_ablation_matches_oracle(lk, B, prec):
+    """The PCGNR ablation (Algorithm 2's recurrence with gamma = s^T S~^{-1} s)
+    reaches the same Katz vectors as the oracle, with every L, both
+    precisions, one and several columns; it needs at least as many
+    iterations as PCG on these graphs."""
+    g = ki.workload("lnsbm4m", scale=0.0006 if lk != K.KATZ_L_IDENTITY else 0.002).graph
+    beta = oracle_beta(g, 0.9)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=16, labels=g.labels, max_block=32, l_kind=lk, precision=prec)
+    qs = ki.sample_queries(g, B, 71)
+    _, st = _check(g, idx, beta, qs, 1e-6, method=K.KATZ_METHOD_PCGNR)
+    _, st2 = _check(g, idx, beta, qs, 1e-6, method=K.KATZ_METHOD_LRC)
+    assert all(s["path"] == K.KATZ_PATH_LRC for s in st)
+    assert sum(s["iters"] for s in st) >= sum(s["iters"] for s in st2)
+
+
+def test_bad_method_rejected():
+    g = ki.workload("sbm2k").graph
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=4, labels=g.labels, max_block=200)
+    with pytest.raises(K.KatzError) as e:
+        idx.query([3], method=7)
+    assert e.value.code == K.KATZ_EINVAL

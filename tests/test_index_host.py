@@ -93,7 +93,34 @@ def test_star_centre_is_the_separator():
     assert abs(s[0] - m * beta ** 2) < 1e-14
 
 
-@pytest.mark.parametrize("lkind", [K.KATZ_L_CHOL, K.KATZ_L_IDENTITY])
+def _ic0(A):
+    """Zero-fill incomplete Cholesky of the dense SPD M-matrix A, written out
+    for the test: L keeps the pattern of A's lower triangle and L L^T equals
+    A on that pattern and the diagonal (the defining property, asserted)."""
+    n = len(A)
+    pat = np.tril(A, -1) != 0
+    L = np.zeros_like(A)
+    for i in range(n):
+        for k in range(i):
+            if pat[i, k]:
+                L[i, k] = (A[i, k] - L[i, :k] @ L[k, :k]) / L[k, k]
+        L[i, i] = np.sqrt(A[i, i] - L[i, :i] @ L[i, :i])
+    P = L @ L.T
+    on = pat | pat.T | np.eye(n, dtype=bool)
+    np.testing.assert_allclose(P[on], A[on], rtol=0, atol=1e-13)
+    assert np.all(L[np.triu(np.ones((n, n), bool), 1)] == 0) and np.all(L[np.tril(~pat, -1)] == 0)
+    return L
+
+
+def _factor(lkind, M22):
+    if lkind == K.KATZ_L_CHOL:
+        return np.linalg.cholesky(M22)
+    if lkind == K.KATZ_L_IC0:
+        return _ic0(M22)
+    return np.eye(len(M22))
+
+
+@pytest.mark.parametrize("lkind", [K.KATZ_L_CHOL, K.KATZ_L_IDENTITY, K.KATZ_L_IC0])
 def test_theorem1_spectrum(lkind):
     g = ki.sbm([12, 10, 14], [0.5, 0.5, 0.5], 0.08, seed=5)
     r = 3
@@ -105,7 +132,7 @@ def test_theorem1_spectrum(lkind):
     assert n2 >= r + 2
     M11, M12, M22 = M[:n1, :n1], M[:n1, n1:], M[n1:, n1:]
     S = M22 - M12.T @ np.linalg.solve(M11, M12)
-    L = np.linalg.cholesky(M22) if lkind == K.KATZ_L_CHOL else np.eye(n2)
+    L = _factor(lkind, M22)
     Li = np.linalg.inv(L)
     R = np.eye(n2) - Li @ S @ Li.T
     sig_all = np.sort(np.linalg.eigvalsh(R))[::-1]
@@ -121,7 +148,7 @@ def test_theorem1_spectrum(lkind):
     np.testing.assert_allclose(ev, expect, atol=1e-9)
 
 
-@pytest.mark.parametrize("lkind", [K.KATZ_L_CHOL, K.KATZ_L_IDENTITY])
+@pytest.mark.parametrize("lkind", [K.KATZ_L_CHOL, K.KATZ_L_IDENTITY, K.KATZ_L_IC0])
 def test_theorem1_spectrum_weighted(lkind):
     # Theorem 1 on a weighted adjacency: the index's Ritz values are the top of
     # the dense spectrum of R, and the preconditioned Schur complement has
@@ -137,7 +164,7 @@ def test_theorem1_spectrum_weighted(lkind):
     assert n2 >= r + 2
     M11, M12, M22 = M[:n1, :n1], M[:n1, n1:], M[n1:, n1:]
     S = M22 - M12.T @ np.linalg.solve(M11, M12)
-    L = np.linalg.cholesky(M22) if lkind == K.KATZ_L_CHOL else np.eye(n2)
+    L = _factor(lkind, M22)
     Li = np.linalg.inv(L)
     R = np.eye(n2) - Li @ S @ Li.T
     sig_all = np.sort(np.linalg.eigvalsh(R))[::-1]
