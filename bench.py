@@ -9,11 +9,25 @@ back-solve, FP64 residual check, unpermute into a device buffer).  The headline
 value is LRC queries/sec at c = 0.5; CG at the same c, latency percentiles,
 iterations and the other c values are reported beside it.
 
+Two batched legs follow in the same run and are reported inside `results`
+(`legs`): the 4M-node lognormal SBM with 256 queries per solve in FP64
+(c = 0.5, rank 32) and the 8M-node Chung-Lu graph with 512 queries per solve
+in the precision form (c = 0.9, rank 64).  Each reports LRC and CG
+queries/sec, its dominant kernel's roofline and the error of sampled columns
+against the oracle.
+
+CPU side (rank 0 only): the oracle's multi-core Neumann series and a
+multi-core FP64 CPU CG (oracle/katz_cpu.c) on bounded samples of each
+workload, with the host's core count, CPU model and thread placement.  The
+GPU's sampled errors must lie within the residual's bound; the line carries
+`parity_ok` and the run exits with status 3 when it is false.
+
 Prints ONE JSON line.  Options: --gpus (1 only), --steps, --warmup, --c,
---scale (node-count factor for quick runs), --no-cpu (skip the oracle leg),
---copy-calib (adds a plain 1 GiB device copy, to calibrate rocprofv3 byte
-counters), --profile-kernels (HIP-event kernel timing in a repeat of the timed
-steps; on by default).
+--scale (node-count factor for quick runs), --no-cpu (skip the CPU legs),
+--legs (batched legs to run, default "c3,c4"; "" for none), --copy-calib
+(adds a plain 1 GiB device copy, to calibrate rocprofv3 byte counters),
+--no-profile-kernels (skip the HIP-event kernel timing in a repeat of the
+timed steps).
 """
 from __future__ import annotations
 
@@ -23,6 +37,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -94,6 +110,15 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="requests per offered-load point (serving)")
     ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--max-batch-cols", type=int, default=64)
+    ap.add_argument("--legs", type=str, default="c3,c4",
+                    help="batched legs after the one-query headline: c3 (4M-node SBM, 256 FP64 columns), "
+                         "c4 (8M-node Chung-Lu, 512 columns, precision form); empty for none")
+    ap.add_argument("--ablation", action="store_true",
+                    help="the paper's regime and ablations: Table 1-shaped Chung-Lu graphs at alpha = "
+                         "1/(lambda_max + 1) (LRC, the PCGNR recurrence, CG; ranks 5 and 25), and L = chol / "
+                         "IC(0) / I on community graphs where the dense factor fits")
+    ap.add_argument("--latency-queries", type=int, default=100,
+                    help="one-query workload: queries per c and method in the latency pass (p50/p99)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -113,6 +138,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.serve:
         return run_serving(args)
+    if args.ablation:
+        return run_ablation(args)
     if args.pairs:
         return run_pairs(args)
     if args.sparse_katz:
@@ -127,7 +154,7 @@ def main():
     cs = [float(x) for x in args.c.split(",")]
     head_c = 0.5 if 0.5 in cs else cs[0]
     tol = 1e-6
-    queries = w.queries
+    queries = ki.sample_queries(g, max(100, args.latency_queries, args.steps + args.warmup), 2002)
     results = {}
     roofline = None
     kernel_table = None
@@ -169,14 +196,18 @@ def main():
             lat, its, res = run(idx, method, args.steps, args.warmup)
             torch.cuda.synchronize()
             el = time.perf_counter() - t
-            lat_ms = np.array(lat) * 1e3
+            # latency pass: p50 / p99 over at least 100 queries (outside the timed steps)
+            nl = max(args.latency_queries, args.steps)
+            lat2, its2, res2 = run(idx, method, nl, args.warmup + args.steps)
+            lat_ms = np.array(lat2) * 1e3
             entry[name] = {"qps": args.steps / el, "ms_per_query": el * 1e3 / args.steps,
                            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-                           "iters_median": float(np.median(its)), "iters_max": int(np.max(its)),
-                           "max_rel_residual": float(np.max(res))}
-            log("  %s: %.1f q/s, %.3f ms/query, iters median %g" % (name, entry[name]["qps"],
-                                                                    entry[name]["ms_per_query"],
-                                                                    entry[name]["iters_median"]))
+                           "latency_queries": nl,
+                           "iters_median": float(np.median(its + its2)), "iters_max": int(np.max(its + its2)),
+                           "max_rel_residual": float(np.max(res + res2))}
+            log("  %s: %.1f q/s, %.3f ms/query, p50 %.3f p99 %.3f ms over %d, iters median %g"
+                % (name, entry[name]["qps"], entry[name]["ms_per_query"], entry[name]["p50_ms"],
+                   entry[name]["p99_ms"], nl, entry[name]["iters_median"]))
             if c == head_c and args.concurrency > 1 and not args.host_output:
                 # independent one-query solves from several host threads at once
                 import threading
@@ -222,19 +253,12 @@ def main():
                 run(idx, method, args.steps, args.warmup, check_every=1)
                 torch.cuda.synchronize()
                 K.katz_profile_enable(False)
-                tab = [r for r in K.katz_profile_read() if r["launches"] > 0]
-                for r in tab:
-                    r["avg_us"] = 1e3 * r["total_ms"] / r["launches"]
-                    r["alg_bytes_per_launch"] = r["alg_bytes"] / r["launches"]
-                    r["achieved_GBs"] = r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
+                tab = kernel_rows(K)
                 entry[name]["kernels"] = tab
                 if name == "lrc":
                     kernel_table = tab
-        if c == head_c:
-            head_idx_info = entry
-            if not args.no_cpu:
-                cpu = cpu_baseline(g, idx, queries, tol, out, stream, K)
-                entry["cpu"] = cpu
+        if c == head_c and not args.no_cpu:
+            entry["cpu"] = cpu_leg_one_query(g, idx, queries, tol, K)
         results["c=%g" % c] = entry
         idx.close()
 
@@ -244,22 +268,27 @@ def main():
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
+        del x, y
 
     head = results["c=%g" % head_c]
+    del out
+    torch.cuda.empty_cache()
     copy_gbs = measured_copy_bandwidth(torch, dev)
     log("measured device copy bandwidth: %.0f GB/s (read + write of a 1 GiB copy)" % copy_gbs)
     if kernel_table:
-        dom = max(kernel_table, key=lambda r: r["total_ms"])
         wl = "cl1m" if args.scale == 1.0 else "cl1m_s%g" % args.scale
-        traffic = load_traffic(dom["name"], wl, dom["alg_bytes_per_launch"])
-        roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["achieved_GBs"], 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "avg_launch_us": round(dom["avg_us"], 2),
-                    "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
-                    "measured_copy_GBs": round(copy_gbs, 1),
-                    "frac_of_measured_copy": round(dom["achieved_GBs"] / copy_gbs, 4),
-                    "traffic_GBs": round(traffic / (dom["avg_us"] * 1e-6) / 1e9, 1) if traffic else None}
+        roofline = roofline_of(kernel_table, wl, copy_gbs)
+
+    legs = {}
+    for leg in [x for x in args.legs.split(",") if x]:
+        legs[leg] = run_leg(leg, args, torch, K, ki, dev, copy_gbs)
+    if legs:
+        results["legs"] = legs
+
     value = head["lrc"]["qps"]
+    cpu = head.get("cpu")
+    parity = [head["cpu"]["parity_ok"]] if cpu else []
+    parity += [lg["parity_ok"] for lg in legs.values() if "parity_ok" in lg]
     line = {
         "metric": "Katz queries/sec at 1e-6 rel. residual, LRC-Katz vs CG, 1 MI355X; p99 ms",
         "value": round(value, 2),
@@ -281,16 +310,47 @@ def main():
                    "output": "pinned host memory (PCIe-inclusive)" if args.host_output else "device memory"},
         "p99_ms": round(head["lrc"]["p99_ms"], 4),
         "p50_ms": round(head["lrc"]["p50_ms"], 4),
+        "latency_queries": head["lrc"]["latency_queries"],
         "cg_qps": round(head["cg"]["qps"], 2),
         "lrc_over_cg": round(value / head["cg"]["qps"], 3),
         "concurrent": {"threads": args.concurrency,
                        "lrc_qps": round(head["lrc"].get("concurrent_qps", 0.0), 2),
                        "cg_qps": round(head["cg"].get("concurrent_qps", 0.0), 2)} if args.concurrency > 1 else None,
         "roofline": roofline,
-        "cpu_baseline": head.get("cpu", {}).get("baseline"),
+        "cpu_baseline": cpu["baseline"] if cpu else None,
+        "parity_ok": all(parity) if parity else None,
+        "legs": {k: {"lrc_qps": v["lrc"]["qps"], "cg_qps": v["cg"]["qps"], "lrc_over_cg": v["lrc_over_cg"],
+                     "roofline_frac": (v.get("roofline") or {}).get("frac"),
+                     "max_rel_err_vs_oracle": v.get("max_rel_err_vs_oracle")} for k, v in legs.items()},
         "results": results,
     }
     print(json.dumps(line), flush=True)
+    if parity and not all(parity):
+        log("PARITY FAILURE: a sampled GPU result lies outside its residual bound against the oracle")
+        sys.exit(3)
+
+
+def kernel_rows(K):
+    """The profiled kernel table (HIP events) with per-launch figures."""
+    tab = [r for r in K.katz_profile_read() if r["launches"] > 0]
+    for r in tab:
+        r["avg_us"] = 1e3 * r["total_ms"] / r["launches"]
+        r["alg_bytes_per_launch"] = r["alg_bytes"] / r["launches"]
+        r["achieved_GBs"] = r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
+    return tab
+
+
+def roofline_of(tab, workload_key, copy_gbs):
+    """Roofline object of the kernel with the largest total time."""
+    dom = max(tab, key=lambda r: r["total_ms"])
+    traffic = load_traffic(dom["name"], workload_key, dom["alg_bytes_per_launch"])
+    return {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["achieved_GBs"], 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "avg_launch_us": round(dom["avg_us"], 2),
+            "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
+            "measured_copy_GBs": round(copy_gbs, 1) if copy_gbs else None,
+            "frac_of_measured_copy": round(dom["achieved_GBs"] / copy_gbs, 4) if copy_gbs else None,
+            "traffic_GBs": round(traffic / (dom["avg_us"] * 1e-6) / 1e9, 1) if traffic else None}
 
 
 def run_batched(args):
@@ -397,6 +457,105 @@ def run_batched(args):
                        "n": g.n, "nnz": g.nnz, "batch": B},
             "cg_qps": round(head["cg"]["qps"], 2), "lrc_over_cg": round(head["lrc"]["qps"] / head["cg"]["qps"], 3),
             "roofline": roofline, "cpu_baseline": None, "results": results}
+    print(json.dumps(line), flush=True)
+
+
+# Table 1 of the paper: network, nodes, average degree (the stand-ins are
+# Chung-Lu graphs with exponent 2.5 and these sizes; the networks themselves
+# are not available).
+TABLE1 = [("DBLP_lcc", 93156, 3.82), ("Arxiv_lcc", 86376, 11.98), ("Email-Enron", 36692, 10.02),
+          ("Gowalla", 196591, 9.67), ("Flickr", 513969, 12.41), ("Hollywood-2009", 1139905, 99.13),
+          ("PPI_Data", 12976, 7.6916), ("DBLP_2006-2008", 179266, 4.2693)]
+
+
+def run_ablation(args):
+    """NEXT-3: (1) Table 1-shaped Chung-Lu graphs at the paper's damping
+    alpha = 1 / (lambda_max + 1), one query per solve, FP64, L = I, ranks 5
+    and 25: PCG on S (LRC-Katz), the PCGNR recurrence of Algorithm 2 (step
+    corrected) and plain CG; iterations and queries/s.  (2) The factor L of
+    the preconditioner (eq. RMatrix): dense chol(M22), its zero-fill
+    incomplete factor IC(0) and I, on community graphs whose separator fits
+    the dense factor (2,000 and 5,000 nodes), c in {0.5, 0.9, 0.99}, ranks 0
+    and 16."""
+    import torch
+
+    import katz_inputs as ki
+    import paper_1912_06525_amd as K
+
+    dev = torch.device("cuda:0")
+    steps = max(4, min(args.steps, 20))
+    tol = 1e-6
+
+    def measure(idx, g, method, qs):
+        out = torch.empty((1, g.n), dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        for q in qs[:3]:   # warm-up (autotuned launch shape, captured iteration chunks)
+            idx.query([int(q)], out=out, tol=tol, method=method, stream=stream)
+        torch.cuda.synchronize()
+        its = []
+        t = time.perf_counter()
+        for q in qs:
+            _, st = idx.query([int(q)], out=out, tol=tol, method=method, stream=stream)
+            if st[0]["status"] != 0:
+                raise RuntimeError("no convergence: %r" % st[0])
+            its.append(st[0]["iters"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        return {"qps": round(len(qs) / el, 1), "iters_median": float(np.median(its)), "iters_max": int(max(its))}
+
+    regime = {}
+    for name, n, deg in TABLE1:
+        n = max(1000, int(round(n * args.scale)))
+        t0 = time.time()
+        g = ki.chung_lu(n, 2.5, deg, seed=1100)
+        # lambda_max from a host-only index of the same graph (the library's own Lanczos)
+        lam = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=0, max_block=args.max_block, device=-1).info.lambda_max
+        beta = 1.0 / (lam + 1.0)
+        qs = ki.sample_queries(g, steps, 1200)
+        entry = {"n": g.n, "nnz": g.nnz, "mean_degree": round(g.nnz / g.n, 2), "lambda_max": lam,
+                 "alpha": beta, "c": lam / (lam + 1.0)}
+        for rank in (5, 25):
+            idx = K.KatzIndex.from_graph(g, beta=beta, rank=rank, max_block=args.max_block, device=0,
+                                         l_kind=K.KATZ_L_IDENTITY)
+            e = {"n2": idx.info.n2, "sigma_r": idx.info.sigma_max, "build_s": round(idx.info.build_seconds, 2)}
+            for mname, m in (("lrc", K.KATZ_METHOD_LRC), ("pcgnr", K.KATZ_METHOD_PCGNR), ("cg", K.KATZ_METHOD_CG)):
+                if mname == "cg" and rank != 5:
+                    continue
+                e[mname] = measure(idx, g, m, qs)
+            entry["rank%d" % rank] = e
+            idx.close()
+        entry["cg"] = entry["rank5"].pop("cg")
+        log("%-15s n=%d nnz=%d c=%.5f: LRC r5 %s / r25 %s, PCGNR r5 %s, CG %s (%.0fs)"
+            % (name, g.n, g.nnz, entry["c"], entry["rank5"]["lrc"], entry["rank25"]["lrc"],
+               entry["rank5"]["pcgnr"], entry["cg"], time.time() - t0))
+        regime[name] = entry
+        torch.cuda.empty_cache()
+
+    factors = {}
+    for nblk in (10, 25):
+        g = ki.sbm([200] * nblk, 0.05, 0.001, seed=1001)
+        qs = ki.sample_queries(g, steps, 2001)
+        for c in (0.5, 0.9, 0.99):
+            key = "sbm%dk_c%g" % (nblk * 200 // 1000, c)
+            factors[key] = {"n": g.n, "nnz": g.nnz}
+            for lname, lk in (("chol", K.KATZ_L_CHOL), ("ic0", K.KATZ_L_IC0), ("identity", K.KATZ_L_IDENTITY)):
+                for rank in (0, 16):
+                    idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=rank, labels=g.labels, max_block=200,
+                                                 device=0, l_kind=lk)
+                    e = measure(idx, g, K.KATZ_METHOD_LRC, qs)
+                    e["n2"] = idx.info.n2
+                    factors[key]["%s_r%d" % (lname, rank)] = e
+                    idx.close()
+            factors[key]["cg"] = measure(K.KatzIndex.from_graph(g, beta_frac=c, rank=0, labels=g.labels,
+                                                                max_block=200, device=0), g, K.KATZ_METHOD_CG, qs)
+            log("%s: %s" % (key, {k: (v["iters_median"], v["qps"]) for k, v in factors[key].items()
+                                  if isinstance(v, dict)}))
+    line = {"metric": "ablations: iterations and Katz queries/sec at 1e-6 rel. residual, 1 MI355X",
+            "value": None, "unit": "queries/s", "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": None,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "Table 1-shaped Chung-Lu graphs (exponent 2.5) at alpha = 1/(lambda_max+1); "
+                                   "SBMs of 200-node communities for the factor comparison", "scale": args.scale},
+            "paper_regime": regime, "factor_comparison": factors}
     print(json.dumps(line), flush=True)
 
 
@@ -592,30 +751,238 @@ def measured_copy_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
     return best
 
 
-def cpu_baseline(g, idx, queries, tol, out, stream, K):
-    """Times the CPU oracle (never tuned) on a bounded sample of the queries and
-    checks the GPU's scores for those queries against it (full-size parity)."""
-    import numpy as np
+def host_info():
+    """Host cores, CPU model and thread placement of the CPU legs."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count()
+    bind = os.environ.get("OMP_PROC_BIND"), os.environ.get("OMP_PLACES"), os.environ.get("GOMP_CPU_AFFINITY")
+    pin = ("OMP_PROC_BIND=%s OMP_PLACES=%s GOMP_CPU_AFFINITY=%s" % bind) if any(bind) else \
+        "none: OpenMP threads placed by the OS scheduler"
+    return {"nproc": os.cpu_count(), "affinity_cpus": aff, "cpu_model": model,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"), "pinning": pin}
 
+
+def cpu_threads():
+    """OpenMP threads for the CPU legs: every CPU this process may use."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
+
+
+def _errs(kh, k):
+    nk = float(np.linalg.norm(k))
+    return float(np.linalg.norm(kh - k)) / nk, float(np.max(np.abs(kh - k))) / nk
+
+
+def cpu_leg_one_query(g, idx, queries, tol, K, nsample=8):
+    """CPU side of the one-query workload, after the GPU timing: the oracle's
+    multi-core series and the multi-core CPU CG, each on `nsample` queries of
+    the same graph and c, and the GPU's error on those queries against the
+    oracle.  The oracle is evaluated at the index's beta; its tail bound uses
+    c from the oracle's own lambda_max (which must agree with the index's)."""
     import oracle
     info = idx.info
-    sample = [int(q) for q in queries[:4]]
-    # the oracle's own lambda_max (outside the timed region) and the same c
-    lam = oracle.lambda_max(oracle.csr_matrix(g.n, g.row_ptr, g.col))
+    sample = [int(q) for q in queries[:nsample]]
+    thr = cpu_threads()
+    lam = oracle.lambda_max_mt(g.n, g.row_ptr, g.col, threads=thr)["lambda"]
+    c_or = info.beta * lam
     t = time.perf_counter()
-    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, sample, c=info.c, lam=lam, validate=False)
-    el = time.perf_counter() - t
+    ser = oracle.katz_series_mt(g.n, g.row_ptr, g.col, sample, info.beta, c_or * (1 + 1e-6), tol=1e-13, threads=thr)
+    el_or = time.perf_counter() - t
+    # the single-threaded Python oracle (scipy SpMV) on 2 of the queries, as an extra
+    t = time.perf_counter()
+    ref1 = oracle.katz_oracle(g.n, g.row_ptr, g.col, sample[:2], beta=info.beta, lam=lam, validate=False)
+    el_1 = time.perf_counter() - t
+    # CPU CG, one query per solve like the GPU headline
+    t = time.perf_counter()
+    cg_its = []
+    for q in sample:
+        r = oracle.cg_mt(g.n, g.row_ptr, g.col, [q], info.beta, tol=tol, threads=thr)
+        if not r["converged"]:
+            raise RuntimeError("CPU CG did not converge on query %d" % q)
+        cg_its.append(int(r["iters"][0]))
+    el_cg = time.perf_counter() - t
     errs = []
     for j, q in enumerate(sample):
-        sc, st = idx.query([q], tol=tol)
-        k = ref["k"][:, j]
-        errs.append(float(np.linalg.norm(sc[0] - k) / np.linalg.norm(k)))
-    bound = tol * (1 + info.c) / (1 - info.c)
-    log("  cpu oracle: %d queries in %.1fs; GPU rel err max %.2e (bound %.2e)" % (len(sample), el, max(errs), bound))
-    return {"baseline": {"value": round(len(sample) / el, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
-                         "sample": "%d queries of the same graph and c, truncated Neumann series to a 1e-13 tail "
-                                   "bound (scipy CSR SpMV, single thread)" % len(sample)},
-            "gpu_rel_err_max": max(errs), "err_bound": bound, "oracle_terms": ref["terms"].tolist()}
+        for method in (K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG):
+            sc, st = idx.query([q], tol=tol, method=method)
+            errs.append(_errs(sc[0], ser["k"][:, j]))
+    e1 = max(_errs(ref1["k"][:, j], ser["k"][:, j])[0] for j in range(2))
+    bound = tol * (1 + c_or) / (1 - c_or) + 1e-13
+    ok = all(e[0] <= bound and e[1] <= bound for e in errs)
+    log("  cpu: oracle series %d queries in %.1fs (%d threads), 1-core oracle 2 in %.1fs, CPU CG %d in %.1fs "
+        "(iters %s); GPU rel err max %.2e (bound %.2e)" % (len(sample), el_or, ser["threads"], el_1, len(sample),
+                                                           el_cg, cg_its, max(e[0] for e in errs), bound))
+    hi = host_info()
+    base = {"value": round(len(sample) / el_or, 4), "unit": "queries/s", "cores": ser["threads"], "kind": "oracle",
+            "sample": "%d queries of the same graph and c in one multi-column truncated Neumann series to a "
+                      "1e-13 tail bound (oracle/katz_cpu.c, OpenMP)" % len(sample),
+            "host": hi,
+            "cpu_cg": {"value": round(len(sample) / el_cg, 4), "unit": "queries/s", "cores": thr,
+                       "kind": "FP64 CG, one query per solve, OpenMP CSR SpMV, stop at true residual %g" % tol,
+                       "iters": cg_its},
+            "oracle_1core": {"value": round(2 / el_1, 4), "unit": "queries/s", "cores": 1,
+                             "kind": "Python oracle (scipy CSR SpMV), truncated series to a 1e-13 tail bound",
+                             "max_rel_diff_vs_multicore_oracle": e1},
+            "gpu_err_vs_oracle": [{"query": q, "lrc_rel_err": errs[2 * j][0], "lrc_max_entry_err": errs[2 * j][1],
+                                   "cg_rel_err": errs[2 * j + 1][0], "cg_max_entry_err": errs[2 * j + 1][1]}
+                                  for j, q in enumerate(sample)],
+            "err_bound": bound, "lambda_rel_diff": abs(lam - info.lambda_max) / lam}
+    return {"baseline": base, "parity_ok": ok and base["lambda_rel_diff"] <= 1e-9}
+
+
+LEGS = {
+    # name: workload, columns per solve, c, rank, precision, oracle tail fraction
+    "c3": ("lnsbm4m", 256, 0.5, 32, "fp64", 1e-10),
+    "c4": ("cl8m", 512, 0.9, 64, "mixed", 1e-7),
+}
+
+
+def run_leg(leg, args, torch, K, ki, dev, copy_gbs):
+    """One batched leg: LRC and CG queries/sec on B columns per solve, the
+    dominant kernel's roofline, and (unless --no-cpu) the oracle's series
+    and the CPU CG on 8 sampled columns, run on the host cores in a thread
+    while the GPU is timed."""
+    import threading
+
+    import oracle
+    wl, B, c, rank, precision, tail = LEGS[leg]
+    t0 = time.time()
+    w = ki.workload(wl, scale=args.scale)
+    g = w.graph
+    log("leg %s: %s n=%d nnz=%d (%.1fs)" % (leg, wl, g.n, g.nnz, time.time() - t0))
+    prec = K.KATZ_PREC_MIXED if precision == "mixed" else K.KATZ_PREC_FP64
+    tb = time.time()
+    idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=rank, max_block=args.max_block, device=0,
+                                 labels=g.labels, precision=prec)
+    info = idx.info
+    log("  index: n1=%d n2=%d blocks=%d build %.1fs, %.1f GB on the device"
+        % (info.n1, info.n2, info.nblocks, time.time() - tb, info.device_bytes / 1e9))
+    steps, warm = max(2, min(args.steps, 4)), 1
+    queries = ki.sample_queries(g, B * (steps + warm), 3003)
+    pick = sorted({0, B - 1, *[int(x) for x in np.random.default_rng(7).choice(np.arange(1, B - 1), 6, False)]})
+    sample = [int(queries[warm * B + j]) for j in pick]
+    tol = 1e-6
+    cpu = {}
+
+    def cpu_work():
+        try:
+            thr = max(1, cpu_threads() - 2)   # two cores stay with the GPU-driving thread
+            lam = oracle.lambda_max_mt(g.n, g.row_ptr, g.col, threads=thr)["lambda"]
+            cpu["lambda"] = lam
+            t = time.perf_counter()
+            cpu["series"] = oracle.katz_series_mt(g.n, g.row_ptr, g.col, sample, info.beta, info.beta * lam * (1 + 1e-6),
+                                                  tol=tail, threads=thr)
+            cpu["series_s"] = time.perf_counter() - t
+            t = time.perf_counter()
+            r = oracle.cg_mt(g.n, g.row_ptr, g.col, sample, info.beta, tol=tol, threads=thr)
+            cpu["cg_s"] = time.perf_counter() - t
+            cpu["cg_iters"] = [int(x) for x in r["iters"]]
+            cpu["cg_ok"] = bool(r["converged"])
+            cpu["threads"] = thr
+        except Exception as e:  # reported in the result
+            cpu["error"] = repr(e)
+
+    th = None
+    if not args.no_cpu:
+        th = threading.Thread(target=cpu_work)
+        th.start()
+    out = torch.empty((B, g.n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    entry = {"workload": wl, "n": g.n, "nnz": g.nnz, "batch": B, "c": c, "rank": rank, "precision": precision,
+             "n1": info.n1, "n2": info.n2, "build_s": round(info.build_seconds, 2), "steps": steps, "warmup": warm}
+    picked = None
+    for name, method in (("lrc", K.KATZ_METHOD_LRC), ("cg", K.KATZ_METHOD_CG)):
+        def step(s):
+            q = queries[s * B:(s + 1) * B]
+            _, st = idx.query(q, out=out, tol=tol, method=method, stream=stream)
+            bad = [x for x in st if x["status"] != 0]
+            if bad:
+                raise RuntimeError("no convergence: %r" % bad[:2])
+            return st
+        for s in range(warm):
+            step(s)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its, sw, res = [], [], []
+        for s in range(steps):
+            st = step(warm + s)
+            its += [x["iters"] for x in st]
+            sw += [x["sweeps"] for x in st]
+            res += [x["rel_residual"] for x in st]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        entry[name] = {"qps": B * steps / el, "ms_per_batch": 1e3 * el / steps,
+                       "iters_median": float(np.median(its)), "sweeps_median": float(np.median(sw)),
+                       "max_rel_residual": float(np.max(res))}
+        log("  %s: %.1f q/s, %.1f ms per batch of %d, iters median %g, sweeps %g"
+            % (name, entry[name]["qps"], entry[name]["ms_per_batch"], B, entry[name]["iters_median"],
+               entry[name]["sweeps_median"]))
+        # sampled columns of the first timed batch (re-solved: the timed steps overwrote the panel)
+        step(warm)
+        torch.cuda.synchronize()
+        cols = np.stack([out[j].cpu().numpy() for j in pick], axis=1)
+        if name == "lrc":
+            picked = {"lrc": cols}
+        else:
+            picked["cg"] = cols
+        if not args.no_profile_kernels:
+            K.katz_profile_reset()
+            K.katz_profile_enable(True)
+            step(warm)
+            torch.cuda.synchronize()
+            K.katz_profile_enable(False)
+            tab = kernel_rows(K)
+            entry[name]["kernels"] = tab
+            if name == "lrc":
+                wk = wl if args.scale == 1.0 else "%s_s%g" % (wl, args.scale)
+                entry["roofline"] = roofline_of(tab, "%s_b%d_c%g" % (wk, B, c), copy_gbs)
+    entry["lrc_over_cg"] = round(entry["lrc"]["qps"] / entry["cg"]["qps"], 3)
+    del out
+    idx.close()
+    torch.cuda.empty_cache()
+    if th is not None:
+        th.join()
+        if "error" in cpu:
+            raise RuntimeError("CPU leg failed: %s" % cpu["error"])
+        lam = cpu["lambda"]
+        c_or = info.beta * lam
+        bound = tol * (1 + c_or) / (1 - c_or) + 2 * tail
+        errs = {m: [_errs(picked[m][:, t], cpu["series"]["k"][:, t]) for t in range(len(pick))] for m in picked}
+        worst = max(e[0] for m in errs for e in errs[m])
+        entry["max_rel_err_vs_oracle"] = worst
+        entry["err_bound"] = bound
+        entry["oracle_sample"] = {"columns": pick, "queries": sample,
+                                  "terms": [int(x) for x in cpu["series"]["terms"]],
+                                  "lrc_rel_err": [e[0] for e in errs["lrc"]], "cg_rel_err": [e[0] for e in errs["cg"]],
+                                  "lrc_max_entry_err": [e[1] for e in errs["lrc"]]}
+        entry["lambda_rel_diff"] = abs(lam - info.lambda_max) / lam
+        entry["parity_ok"] = bool(all(e[0] <= bound and e[1] <= bound for m in errs for e in errs[m])
+                                  and entry["lambda_rel_diff"] <= 1e-9 and cpu["cg_ok"])
+        entry["cpu"] = {"oracle": {"value": round(len(sample) / cpu["series_s"], 4), "unit": "queries/s",
+                                   "cores": cpu["threads"], "kind": "oracle",
+                                   "sample": "%d sampled columns of the first timed batch, one multi-column "
+                                             "series to a %g tail bound" % (len(sample), tail)},
+                        "cpu_cg": {"value": round(len(sample) / cpu["cg_s"], 4), "unit": "queries/s",
+                                   "cores": cpu["threads"], "iters": cpu["cg_iters"],
+                                   "kind": "FP64 CG, the %d sampled queries as one multi-RHS block, stop at true "
+                                           "residual %g" % (len(sample), tol)},
+                        "host": host_info()}
+        log("  cpu: oracle %d columns in %.1fs, CPU CG in %.1fs (%d threads); GPU rel err max %.2e (bound %.2e)"
+            % (len(sample), cpu["series_s"], cpu["cg_s"], cpu["threads"], worst, bound))
+    return entry
 
 
 if __name__ == "__main__":
