@@ -159,6 +159,12 @@ typedef struct {
   int64_t device_bytes;    /* total resident index bytes on the device */
   double build_seconds;
   int32_t u_precision;     /* storage of V as resolved (1 FP64, 2 FP32, 3 BF16) */
+  /* wall seconds of the build's phases (0 for an index loaded from a file):
+     [0] validation, [1] lambda_max, [2]-[6] partition (BFS chunking, vertex
+     cover, minimality, components, node order), [7] permuted CSR, [8] M11
+     block inverses, [9] M22 factor, [10] Lanczos on R (host or device),
+     [11] upload to the device */
+  double build_phase_seconds[12];
 } katz_index_info_t;
 
 /* Sets the documented defaults. */

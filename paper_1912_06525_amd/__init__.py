@@ -65,7 +65,8 @@ class katz_index_info_t(ctypes.Structure):
                 ("beta", ctypes.c_double), ("lambda_max", ctypes.c_double), ("c", ctypes.c_double),
                 ("sigma_max", ctypes.c_double), ("sigma_next", ctypes.c_double),
                 ("factor_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("build_seconds", ctypes.c_double), ("u_precision", ctypes.c_int32)]
+                ("build_seconds", ctypes.c_double), ("u_precision", ctypes.c_int32),
+                ("build_phase_seconds", ctypes.c_double * 12)]
 
 
 class katz_server_opts(ctypes.Structure):

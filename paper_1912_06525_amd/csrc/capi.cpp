@@ -1,6 +1,7 @@
 // C ABI of the Katz library (include/katz.h): argument checks, error codes,
 // thread-local error messages; no exceptions cross the boundary.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -132,7 +133,10 @@ int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
       katz::build_host_index(n, nnz, row_ptr, col_idx, val, o, idx->host, o.device >= 0);
       idx->device = o.device;
       if (o.device >= 0) {
+        const auto t0 = std::chrono::steady_clock::now();
         idx->dev = katz::device_upload(idx->host, o.device);
+        idx->host.phase_seconds[11] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        idx->host.build_seconds += idx->host.phase_seconds[11];
         if (idx->host.lanczos_rank > 0) katz::device_lanczos_R(idx->host, idx->dev);
       }
     } catch (...) {
@@ -238,10 +242,11 @@ int katz_sparse_katz(const katz_index* idx, const int32_t* q, int32_t nq, int32_
     a.q = q; a.nq = nq; a.opts = resolve(opts); a.scores = nullptr; a.topk = K; a.ids = top.data();
     a.topk_scores = topsc.data(); a.st = st; a.stream = stream;
     int rc1 = katz::device_query(idx->host, idx->dev, a);
-    // (2) the T modular nodes t of each query: K_T[v][t] = K[v, t] for v = q
-    // and for every listed candidate, as pair queries (src t, dst v)
-    std::vector<int32_t> ps, pd;
+    // (2) the T modular nodes t of each query: K_T[v][t] = K[v, t] = K[t, v]
+    // for v = q and every listed candidate, gathered from the Katz vectors of
+    // the t (pair entries, batched over the distinct t)
     std::vector<int32_t> ncand(nq), nmod(nq);
+    std::vector<int64_t> base(nq);
     int64_t total = 0;
     for (int32_t i = 0; i < nq; i++) {
       const int32_t* li = top.data() + (size_t)i * K;
@@ -249,12 +254,18 @@ int katz_sparse_katz(const katz_index* idx, const int32_t* q, int32_t nq, int32_
       while (nc < K && li[nc] >= 0) nc++;
       ncand[i] = std::min(nc, s);
       nmod[i] = std::min(nc, T);
+      base[i] = total;
       total += (int64_t)nmod[i] * (ncand[i] + 1);
     }
     if (total > INT32_MAX)
       return set_error(KATZ_EINVAL, "too many correlation entries in one call (nq * T * (s + 1) > 2^31 - 1)");
+    std::vector<int32_t> ps, pd;
+    ps.reserve((size_t)total);
+    pd.reserve((size_t)total);
+    std::vector<int32_t> cand((size_t)nq * s, -1);
     for (int32_t i = 0; i < nq; i++) {
       const int32_t* li = top.data() + (size_t)i * K;
+      for (int32_t j = 0; j < ncand[i]; j++) cand[(size_t)i * s + j] = li[j];
       for (int32_t t = 0; t < nmod[i]; t++) {
         ps.push_back(li[t]);
         pd.push_back(q[i]);
@@ -264,55 +275,23 @@ int katz_sparse_katz(const katz_index* idx, const int32_t* q, int32_t nq, int32_
         }
       }
     }
-    std::vector<double> kt(ps.size());
-    std::vector<katz_query_stats> pst(ps.size());
-    int rc2 = ps.empty() ? KATZ_OK
-                         : pair_scores_host(idx, ps.data(), pd.data(), (int32_t)ps.size(), opts, kt.data(),
-                                            pst.data(), stream);
-    // (3) Pearson correlation of row q with each candidate's row; re-rank
-    std::vector<int32_t> out_ids((size_t)nq * s, -1);
-    std::vector<double> out_corr((size_t)nq * s, std::nan(""));
-    size_t base = 0;
-    for (int32_t i = 0; i < nq; i++) {
-      const int32_t Ti = nmod[i], nc = ncand[i];
-      const int32_t* li = top.data() + (size_t)i * K;
-      // kt[base + t * (nc + 1) + 0] = K[q, t]; ... + 1 + j = K[cand j, t]
-      auto at = [&](int32_t t, int32_t r) { return kt[base + (size_t)t * (nc + 1) + r]; };
-      std::vector<double> rho(nc, std::nan(""));
-      if (Ti >= 2) {
-        double mq = 0;
-        for (int32_t t = 0; t < Ti; t++) mq += at(t, 0);
-        mq /= Ti;
-        double sq = 0;
-        for (int32_t t = 0; t < Ti; t++) sq += (at(t, 0) - mq) * (at(t, 0) - mq);
-        for (int32_t j = 0; j < nc; j++) {
-          double mj = 0;
-          for (int32_t t = 0; t < Ti; t++) mj += at(t, 1 + j);
-          mj /= Ti;
-          double sj = 0, cj = 0;
-          for (int32_t t = 0; t < Ti; t++) {
-            const double dj = at(t, 1 + j) - mj;
-            sj += dj * dj;
-            cj += (at(t, 0) - mq) * dj;
-          }
-          if (sq > 0 && sj > 0) rho[j] = cj / std::sqrt(sq * sj);
-        }
-      }
-      std::vector<int32_t> ord(nc);
-      std::iota(ord.begin(), ord.end(), 0);
-      std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
-        const bool fx = !std::isnan(rho[x]), fy = !std::isnan(rho[y]);
-        if (fx != fy) return fx;           // undefined correlations last
-        return fx && rho[x] > rho[y];      // descending; ties keep the Katz order
-      });
-      for (int32_t j = 0; j < nc; j++) {
-        out_ids[(size_t)i * s + j] = li[ord[j]];
-        out_corr[(size_t)i * s + j] = rho[ord[j]];
-      }
-      base += (size_t)Ti * (nc + 1);
+    // pairs sorted by their source (stable), one batch column per distinct source
+    const int32_t np = (int32_t)ps.size();
+    std::vector<int32_t> order(np), inv(np), qsrc, pcol(np), prow(np);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return ps[x] < ps[y]; });
+    for (int32_t t = 0; t < np; t++) {
+      const int32_t p = order[t];
+      if (qsrc.empty() || qsrc.back() != ps[p]) qsrc.push_back(ps[p]);
+      pcol[t] = (int32_t)qsrc.size() - 1;
+      prow[t] = idx->host.perm[pd[p]];
+      inv[p] = t;
     }
-    katz::copy_to_caller(ids, out_ids.data(), sizeof(int32_t) * out_ids.size());
-    if (corr) katz::copy_to_caller(corr, out_corr.data(), sizeof(double) * out_corr.size());
+    std::vector<katz_query_stats> pst(qsrc.size());
+    // (3) Pearson correlation of row q with each candidate's row and the
+    // re-ranking, on the device; only the lists return
+    int rc2 = katz::device_sparse_katz(idx->host, idx->dev, resolve(opts), stream, qsrc, pcol, prow, inv, base,
+                                       ncand, nmod, cand, nq, s, pst.data(), ids, corr);
     rc = rc1 != KATZ_OK ? rc1 : rc2;
     if (rc == KATZ_ENOCONV) set_error(rc, "some solves did not reach the tolerance");
     return rc;
@@ -371,6 +350,7 @@ int katz_index_info(const katz_index* idx, katz_index_info_t* info) {
   info->device_bytes = katz::device_bytes(idx->dev);
   info->build_seconds = H.build_seconds;
   info->u_precision = H.u_precision;
+  for (int t = 0; t < 12; t++) info->build_phase_seconds[t] = H.phase_seconds[t];
   return KATZ_OK;
 }
 

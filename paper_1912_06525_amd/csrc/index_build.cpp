@@ -367,6 +367,7 @@ double lambda_max(int32_t n, const int32_t* rp, const int32_t* col, const double
 struct Partition {
   std::vector<int32_t> perm, iperm, blk_start;
   int32_t n1 = 0, n2 = 0;
+  double seconds[5] = {0};  // BFS chunks, vertex cover, minimality, components, order
 };
 
 // Node marks are read across the parts that the BFS orders of different
@@ -475,10 +476,13 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
                          int32_t max_block, int32_t order_kind) {
   const bool verbose = getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 1;
   auto tp = std::chrono::steady_clock::now();
+  double ph[5] = {0};
+  int nph = 0;
   auto phase = [&](const char* what) {
-    if (!verbose) return;
     auto t = std::chrono::steady_clock::now();
-    std::fprintf(stderr, "katz partition: %-20s %8.3f s\n", what, std::chrono::duration<double>(t - tp).count());
+    const double sec = std::chrono::duration<double>(t - tp).count();
+    if (nph < 5) ph[nph++] = sec;
+    if (verbose) std::fprintf(stderr, "katz partition: %-20s %8.3f s\n", what, sec);
     tp = t;
   };
   // (a) initial parts
@@ -671,6 +675,7 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
   for (auto& kv : sk) { R.perm[kv.second] = (int32_t)R.iperm.size(); R.iperm.push_back(kv.second); }
   R.n2 = n - R.n1;
   phase("order");
+  for (int t = 0; t < 5; t++) R.seconds[t] = ph[t];
   return R;
 }
 
@@ -902,10 +907,14 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
   // KATZ_VERBOSE=1: phase times of the build on stderr
   const bool verbose = getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 0;
   auto tp = t0;
+  int slot = 0;
   auto phase = [&](const char* what) {
-    if (!verbose) return;
     auto t = std::chrono::steady_clock::now();
-    std::fprintf(stderr, "katz build: %-22s %8.3f s\n", what, std::chrono::duration<double>(t - tp).count());
+    const double sec = std::chrono::duration<double>(t - tp).count();
+    // phase slots: validate 0, lambda_max 1, (partition 2-6), CSR 7, inverses 8, M22 9, Lanczos 10
+    if (slot < 12) H.phase_seconds[slot] = sec;
+    slot = slot == 1 ? 7 : slot + 1;
+    if (verbose) std::fprintf(stderr, "katz build: %-22s %8.3f s\n", what, sec);
     tp = t;
   };
   validate(n, nnz, row_ptr, col, val);
@@ -946,7 +955,10 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
   H.blk_start = std::move(P.blk_start);
   H.n1 = P.n1;
   H.n2 = P.n2;
-  phase("partition");
+  for (int t = 0; t < 5; t++) H.phase_seconds[2 + t] = P.seconds[t];
+  if (verbose) std::fprintf(stderr, "katz build: %-22s %8.3f s\n", "partition",
+                            std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count());
+  tp = std::chrono::steady_clock::now();
 
   // permuted CSR with sorted rows and the separator split
   H.rp.assign(n + 1, 0);

@@ -55,6 +55,7 @@ struct HostIndex {
   int32_t u_precision = 0;  // resolved: 1 FP64, 2 FP32, 3 BF16 (FP64 path); BF16 on the mixed path
   int32_t u_precision_req = 0;  // as requested (0: auto, resolved once the Ritz values are known)
   double build_seconds = 0;
+  double phase_seconds[12] = {0};  // see katz_index_info_t::build_phase_seconds
 };
 
 // defer_lanczos: leave the low-rank factor out (rank 0) and record what it
@@ -100,9 +101,27 @@ struct QueryArgs {
   int32_t npairs = 0;
   const int32_t* pair_col = nullptr;
   const int32_t* pair_row = nullptr;
-  double* pair_out = nullptr;
+  double* pair_out = nullptr;   // host or device
 };
 int device_query(const HostIndex& H, DeviceIndex* D, const QueryArgs& a);
+// Algorithm 3 after the k_q solve: the modular nodes' Katz vectors as one
+// batched solve of the distinct sources q_src with device pair gathers
+// (pair p: row prow[p], column pcol[p], sorted by column), then the
+// correlation and re-ranking on the device (device_sparse_rerank).
+int device_sparse_katz(const HostIndex& H, DeviceIndex* D, const katz_query_opts& opts, void* stream,
+                       const std::vector<int32_t>& q_src, const std::vector<int32_t>& pcol,
+                       const std::vector<int32_t>& prow, const std::vector<int32_t>& inv,
+                       const std::vector<int64_t>& base, const std::vector<int32_t>& ncand,
+                       const std::vector<int32_t>& nmod, const std::vector<int32_t>& cand, int nq, int s,
+                       katz_query_stats* pst, int32_t* ids, double* corr);
+// Algorithm 3's correlation and re-ranking on the device: kt_dev holds the
+// gathered K_T entries, inv maps (query base + t (nc + 1) + row) to their
+// position in kt_dev; cand[nq * s] the listed candidates; ids/corr [nq * s]
+// host or device outputs.
+void device_sparse_rerank(int device, int nq, int s, const double* kt_dev, const std::vector<int32_t>& inv,
+                          const std::vector<int64_t>& base, const std::vector<int32_t>& ncand,
+                          const std::vector<int32_t>& nmod, const std::vector<int32_t>& cand, int32_t* ids,
+                          double* corr, void* stream);
 // As device_query for scores only (no top-K or pairs), on the caller's
 // stream, with every buffer of the solve in the library's static device
 // scratch: no device or pinned allocation, no graph capture.

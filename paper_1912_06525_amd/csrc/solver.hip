@@ -109,7 +109,8 @@ struct SpmmArgs {
   const T* w;
   T cw;
   T* y;
-  int B;
+  int B;       // columns this launch computes
+  int ld, j0;  // row stride of every panel (the batch width) and this launch's first column
   int ep;
   const T* dotv;
   double* partials;
@@ -175,7 +176,7 @@ __device__ inline void row_gather(const Args& a, const RowRange& rr, int nz, int
     T xv[4][NCM];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      const T* xr = a.x + (int64_t)c[u] * B;
+      const T* xr = a.x + (int64_t)c[u] * a.ld + a.j0;
 #pragma unroll
       for (int cc = 0; cc < NCM; cc++) xv[u][cc] = xr[jc[cc]];
     }
@@ -205,7 +206,7 @@ __device__ inline void row_gather(const Args& a, const RowRange& rr, int nz, int
     T xv[3][NCM];
 #pragma unroll
     for (int u = 0; u < 3; u++) {
-      const T* xr = a.x + (int64_t)c[u] * B;
+      const T* xr = a.x + (int64_t)c[u] * a.ld + a.j0;
 #pragma unroll
       for (int cc = 0; cc < NCM; cc++) xv[u][cc] = xr[jc[cc]];
     }
@@ -230,7 +231,7 @@ struct RowOps {
 template <typename T, int CW, int NCM>
 __device__ inline void row_load(const SpmmArgs<T>& a, int i, int cl, int NC, RowOps<T, NCM>& p) {
   const int B = a.B;
-  const int64_t ro = (int64_t)(i - a.row0) * B;
+  const int64_t ro = (int64_t)(i - a.row0) * a.ld + a.j0;
   // clamped columns (a ragged last group reads column B - 1, unused): one
   // uniform branch per operand with all of its loads, none per column group,
   // so the loads are in flight together and no later store waits on them
@@ -270,7 +271,7 @@ template <typename T, int CW, int NCM>
 __device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, const T* acc,
                                   const RowOps<T, NCM>& p, double* dacc) {
   const int B = a.B;
-  const int64_t ro = (int64_t)(i - a.row0) * B;
+  const int64_t ro = (int64_t)(i - a.row0) * a.ld + a.j0;
   T yv[NCM];
 #pragma unroll
   for (int cc = 0; cc < NCM; cc++) {
@@ -291,6 +292,42 @@ __device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, c
   }
 }
 
+// Per-column sums of the owners' dacc over the workgroup's teams (a fixed
+// tree), stored as partial row `prow`: partials[prow * ld + j0 + j].  Called
+// by every thread of the workgroup.
+template <typename T, int TEAMS, int CW, int NCM>
+__device__ inline void spmm_store_partials(const SpmmArgs<T>& a, double* sh, const double* dacc, bool owner,
+                                           int slot, int cl_own, int64_t prow) {
+  const int tid = threadIdx.x, B = a.B, NC = (B + CW - 1) / CW;
+  for (int j = tid; j < TEAMS * B; j += WG) sh[j] = 0.0;
+  __syncthreads();
+  if (owner) {
+#pragma unroll
+    for (int c = 0; c < NCM; c++) {
+      const int j = cl_own + CW * c;
+      if (c < NC && j < B) sh[slot * B + j] = dacc[c];
+    }
+  }
+  __syncthreads();
+  double* out = a.partials + prow * a.ld + a.j0;
+  if (B * TEAMS <= WG) {
+    // tree over teams: thread (t, j) with t < TEAMS
+    const int t = tid / B, j = tid % B;
+    for (int off = TEAMS / 2; off > 0; off >>= 1) {
+      if (t < off) sh[t * B + j] += sh[(t + off) * B + j];
+      __syncthreads();
+    }
+    if (tid < B) out[tid] = sh[tid];
+  } else {
+    for (int j = tid; j < B; j += WG) {
+      double s = 0.0;
+      for (int t = 0; t < TEAMS; t++) s += sh[t * B + j];
+      out[j] = s;
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T, int TS, int CW, bool VAL, int NCM>
 __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
   if (a.n_active && *a.n_active == 0) return;
@@ -301,14 +338,12 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
   const int tid = threadIdx.x;
   const int B = a.B;
   const int NC = (B + CW - 1) / CW;
+  const bool ep = a.ep != EP_NONE;
   double dacc[NCM];
 #pragma unroll
   for (int c = 0; c < NCM; c++) dacc[c] = 0.0;
-  bool owner;      // this lane holds final dot values
-  int slot;        // its row of the per-workgroup dot table
-  int cl_own;
   if ((int)blockIdx.x < a.n_long) {
-    // ---- one hub row, whole workgroup
+    // ---- one hub row, whole workgroup; its dot terms are partial row blockIdx.x
     const int cl = tid % CW, nz = tid / CW;
     const int i = a.long_rows[blockIdx.x];
     RowOps<T, NCM> ops;
@@ -342,16 +377,18 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
       row_finish<T, CW, NCM>(a, i, tid, NC, acc, ops, dacc);
     }
     __syncthreads();
-    owner = tid < CW;
-    slot = 0;
-    cl_own = tid;
-  } else {
-    // ---- short rows: chunks of rows in XCD slabs, one team per row
-    const int team = tid / TS, lane = tid % TS;
-    const int cl = lane % CW, nz = lane / CW;
-    const Slab sl = a.xcd ? xcd_slab((int)blockIdx.x - a.n_long, (int)gridDim.x - a.n_long, a.nchunks)
-                          : contiguous_slab((int)blockIdx.x - a.n_long, (int)gridDim.x - a.n_long, a.nchunks);
-    for (int64_t ch = sl.first; ch < sl.end; ch += sl.stride)
+    if (ep) spmm_store_partials<T, TEAMS, CW, NCM>(a, sh, dacc, tid < CW, 0, tid, blockIdx.x);
+    return;
+  }
+  // ---- short rows: chunks of rows in XCD slabs or contiguously, one team per
+  // row.  The dot terms of chunk ch are partial row n_long + ch, summed in the
+  // same order whichever workgroup takes the chunk, so the reductions do not
+  // depend on the chunk walk.
+  const int team = tid / TS, lane = tid % TS;
+  const int cl = lane % CW, nz = lane / CW;
+  const Slab sl = a.xcd ? xcd_slab((int)blockIdx.x - a.n_long, (int)gridDim.x - a.n_long, a.nchunks)
+                        : contiguous_slab((int)blockIdx.x - a.n_long, (int)gridDim.x - a.n_long, a.nchunks);
+  for (int64_t ch = sl.first; ch < sl.end; ch += sl.stride) {
     for (int i = a.row0 + (int)ch * a.rows_per_wg + team,
              rend = min<int64_t>(a.row1, a.row0 + (ch + 1) * a.rows_per_wg); i < rend; i += TEAMS) {
       RowOps<T, NCM> ops;
@@ -374,35 +411,10 @@ __global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
         row_finish<T, CW, NCM>(a, i, cl, NC, acc, ops, dacc);
       }
     }
-    owner = nz == 0;
-    slot = team;
-    cl_own = cl;
-  }
-  if (a.ep == EP_NONE) return;
-  // per-column workgroup sums -> partials[blockIdx.x * B + j]
-  for (int j = tid; j < TEAMS * B; j += WG) sh[j] = 0.0;
-  __syncthreads();
-  if (owner) {
+    if (ep) {
+      spmm_store_partials<T, TEAMS, CW, NCM>(a, sh, dacc, nz == 0, team, cl, a.n_long + ch);
 #pragma unroll
-    for (int c = 0; c < NCM; c++) {
-      const int j = cl_own + CW * c;
-      if (c < NC && j < B) sh[slot * B + j] = dacc[c];
-    }
-  }
-  __syncthreads();
-  if (B * TEAMS <= WG) {
-    // tree over teams: thread (t, j) with t < TEAMS
-    const int t = tid / B, j = tid % B;
-    for (int off = TEAMS / 2; off > 0; off >>= 1) {
-      if (t < off) sh[t * B + j] += sh[(t + off) * B + j];
-      __syncthreads();
-    }
-    if (tid < B) a.partials[(int64_t)blockIdx.x * B + tid] = sh[tid];
-  } else {
-    for (int j = tid; j < B; j += WG) {
-      double s = 0.0;
-      for (int t = 0; t < TEAMS; t++) s += sh[t * B + j];
-      a.partials[(int64_t)blockIdx.x * B + j] = s;
+      for (int c = 0; c < NCM; c++) dacc[c] = 0.0;
     }
   }
 }
@@ -757,6 +769,7 @@ struct M11SmallArgs {
   T cv;
   T* out;
   int B, nblocks, blocks_per_chunk, xcd;
+  int ld, j0;  // panel row stride and first column (row_gather); B and 0 here
   int64_t nchunks;
   const int* n_active;
 };
@@ -1355,6 +1368,31 @@ __global__ __launch_bounds__(WG) void k_lowrank_mfma(int64_t m, int B, int rank,
 //   EP_RR_INIT: rr, solve start                    EP_RR: rr, convergence / cap
 //   EP_RR_CG: as EP_RR plus bcg = rr_new / rz      EP_VT: DW = D o W
 //   EP_RZ_INIT: rz                                  EP_RZ: bcg = rz_new / rz
+// First stage of a reduction over many partial rows: segment y of `seg`
+// consecutive rows of partials[rows x nv] (the last one shorter), summed per
+// value in row order by four row lanes combined in a fixed order, into
+// out[y * nv + v].  Grid: (ceil(nv / 64), number of segments).
+__global__ __launch_bounds__(WG) void k_seg_reduce(const double* partials, int64_t rows, int64_t nv, int64_t seg,
+                                                   double* out, const int* n_active) {
+  if (n_active && *n_active == 0) return;
+  __shared__ double sh[WG];
+  const int tid = threadIdx.x, lane = tid % 64, q = tid / 64;
+  const int64_t v = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t r0 = (int64_t)blockIdx.y * seg, r1 = min<int64_t>(rows, r0 + seg);
+  double s0 = 0.0, s1 = 0.0;
+  if (v < nv) {
+    int64_t r = r0 + q;
+    for (; r + 4 < r1; r += 8) {
+      s0 += partials[r * nv + v];
+      s1 += partials[(r + 4) * nv + v];
+    }
+    for (; r < r1; r += 4) s0 += partials[r * nv + v];
+  }
+  sh[tid] = s0 + s1;
+  __syncthreads();
+  if (q == 0 && v < nv) out[(int64_t)blockIdx.y * nv + v] = (sh[lane] + sh[64 + lane]) + (sh[128 + lane] + sh[192 + lane]);
+}
+
 // One workgroup of kFinWG threads: the partials are read kFinWG wide (fewer
 // dependent rounds than a 256-thread workgroup).
 constexpr int kFinWG = 1024;
@@ -1612,6 +1650,7 @@ struct Tuning {
   int m11_sub1;     // lanes per row of the A12 gather in the 1-3 column block solve
   int m11_small_min;  // narrowest batch taking the register block solve (5..513; default 16)
   int lr_direct;    // widest column group (JW) of the unstaged narrow low-rank kernels (0: never)
+  int spmm_slice;   // SpMM column-slice width for wider batches (0: one launch over all columns)
 };
 static int env_int(const char* name, int dflt, int lo, int hi) {
   const char* e = getenv(name);
@@ -1636,6 +1675,7 @@ static const Tuning& tuning() {
     u.m11_sub1 = env_int("KATZ_M11_SUB", 4, 1, 16);
     u.m11_small_min = env_int("KATZ_M11_SMALL_MIN", 16, 5, 513);
     u.lr_direct = env_int("KATZ_LR_DIRECT_MAX", 8, 0, 16);
+    u.spmm_slice = env_int("KATZ_SPMM_SLICE", 0, 0, 512);
     if (u.m11_sub1 & (u.m11_sub1 - 1)) u.m11_sub1 = 4;  // a power of two (shuffle reduction)
     return u;
   }();
@@ -1678,6 +1718,7 @@ struct Workspace {
   void *Dx = nullptr, *X = nullptr, *Y = nullptr, *W = nullptr, *Z = nullptr;
   double* partials = nullptr;
   size_t partials_cap = 0;
+  double* seg = nullptr;  // first-stage sums of a reduction over many partial rows (kSegValues)
   double* DW = nullptr;
   double* DW2 = nullptr;  // terms D_k W_kj^2 of <r, z> (rank x B)
   double *rz, *pq, *alpha, *bcg, *rr, *thr, *bn2, *res2, *colscale, *rn2, *inv, *fwd;
@@ -1756,8 +1797,13 @@ struct DeviceIndex {
 constexpr int kLongRow = 256;
 // HIP graphs of iteration chunks kept per workspace.
 constexpr size_t kMaxGraphs = 64;
-// Partial sums (workgroups x values) above which finalize reduces in two stages.
+// Partial sums (rows x values) above which finalize reduces in two stages,
+// and the size of the first stage's output.
 constexpr int64_t kFinTwoStage = 1 << 20;
+constexpr int64_t kSegValues = 1 << 16;
+// Bound on an SpMM launch's chunk partials (chunks x batch width): wider
+// batches take more rows per chunk.
+constexpr int64_t kSpmmPartials = (int64_t)1 << 26;
 // Batched block solves keep a block's rows in registers up to this size.
 constexpr int kSmallBlock = 4;
 
@@ -2010,13 +2056,47 @@ static size_t partials_per_column(const DeviceIndex* D) {
   size_t wgs = std::max<size_t>((size_t)tu.spmm_nwg + std::max(D->n_long_all, D->n_long_sep), (size_t)tu.ew_nwg);
   return wgs * (size_t)std::max(1, D->rank);
 }
+// Lanes per row (team size) of the SpMM for a launch of B columns.
+static int spmm_team_size(int B) {
+  if (B == 1) return tuning().ts1;
+  if (B == 2) return 8;
+  if (B <= 4) return 16;
+  if (B <= 8) return 32;
+  return 64;
+}
+// Rows per chunk of an SpMM launch of B columns over `rows` rows with n_long
+// hub rows, whose partial rows are ld values apart: teams x rows_team, with
+// rows_team raised until (n_long + chunks) x ld fits kSpmmPartials.
+static int spmm_chunk_rows(int B, int ld, int64_t rows, int n_long) {
+  const int64_t teams = WG / spmm_team_size(B);
+  int64_t rt = tuning().rows_team;
+  const int64_t cap = std::max<int64_t>(1, kSpmmPartials / std::max(1, ld) - n_long);
+  if ((rows + teams * rt - 1) / (teams * rt) > cap) rt = (rows + teams * cap - 1) / (teams * cap);
+  return (int)(teams * rt);
+}
+// Partial sums a B-column workspace needs for its largest SpMM (all rows).
+static size_t spmm_partials_need(const DeviceIndex* D, int B) {
+  size_t need = 0;
+  const int W = tuning().spmm_slice;
+  for (int bw : {B, (W > 0 && B > W && B % W == 0) ? W : B}) {
+    const int64_t cr = spmm_chunk_rows(bw, B, D->n, D->n_long_all);
+    need = std::max(need, (size_t)(D->n_long_all + (D->n + cr - 1) / cr) * (size_t)B);
+  }
+  return need;
+}
+// First-stage sums of a two-stage reduction: at most kSegValues, or one row
+// of nv values.
+static size_t seg_values(const DeviceIndex* D, int B) {
+  return std::max<size_t>({(size_t)kSegValues, (size_t)std::max(1, D->rank) * B, (size_t)B});
+}
 // Device bytes of a workspace per column of capacity (panels, FP32 copy of
 // the right-hand side, partial sums, top-K scratch for K <= 4096).
 int64_t ws_bytes_per_column(const DeviceIndex* D) {
   const int64_t n = D->n, n2 = std::max(1, D->n2), esz = solve_elem_bytes(D);
   int64_t b = 16 * n + esz * (4 * n + n2);
   if (D->precision == KATZ_PREC_MIXED) b += 4 * n;
-  b += 8 * (int64_t)partials_per_column(D) + 16 * std::max(1, D->rank);  // partials, DW, DW2
+  b += 8 * (int64_t)std::max(partials_per_column(D), spmm_partials_need(D, 1)) + 16 * std::max(1, D->rank);  // partials, DW, DW2
+  b += 8 * (int64_t)std::max(1, D->rank) + 8;  // first-stage sums
   b += 64 + 1024 + 12 * 4096;
   return b;
 }
@@ -2038,8 +2118,9 @@ static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   w->Y = dalloc<char>(L, nB * esz);
   w->W = dalloc<char>(L, nB * esz);
   w->Z = dalloc<char>(L, (int64_t)std::max(1, D->n2) * B * esz);
-  w->partials_cap = partials_per_column(D) * (size_t)std::max(B, 1);
+  w->partials_cap = std::max(partials_per_column(D) * (size_t)std::max(B, 1), spmm_partials_need(D, std::max(B, 1)));
   w->partials = dalloc<double>(L, (int64_t)w->partials_cap);
+  w->seg = dalloc<double>(L, (int64_t)seg_values(D, std::max(B, 1)));
   w->DW = dalloc<double>(L, (int64_t)std::max(1, D->rank) * B);
   w->DW2 = dalloc<double>(L, (int64_t)std::max(1, D->rank) * B);
   double* s = dalloc<double>(L, 12 * (int64_t)B);
@@ -2155,15 +2236,20 @@ struct Launcher {
   void finalize(int nwg, int nv, int ep, const ColState& cs, double* out, const int* nact,
                 double* out2 = nullptr, int rz_mode = 0) {
     need(nwg, nv);
+    const double* src = w->partials;
     if ((int64_t)nwg * nv > kFinTwoStage && nwg > 1) {
-      // many partial rows: a many-workgroup first stage sums each value's
-      // column (fixed order) into row 0, then the one-workgroup step runs on
-      // that row; each value's column is read and written by one workgroup
-      k_vt_reduce<<<(unsigned)((nv + 63) / 64), WG, 0, st>>>(w->partials, nwg, nv, B, nullptr, w->partials,
-                                                             nact);
-      nwg = 1;
+      // many partial rows: segments of consecutive rows summed in row order
+      // by many workgroups into w->seg, then the one-workgroup step over the
+      // segment sums (both stages in a fixed order)
+      const int64_t nseg0 = std::max<int64_t>(1, std::min<int64_t>(1024, kSegValues / nv));
+      const int64_t seg = (nwg + nseg0 - 1) / nseg0;
+      const int64_t nseg = (nwg + seg - 1) / seg;
+      k_seg_reduce<<<dim3((unsigned)((nv + 63) / 64), (unsigned)nseg), WG, 0, st>>>(w->partials, nwg, nv, seg,
+                                                                                   w->seg, nact);
+      src = w->seg;
+      nwg = (int)nseg;
     }
-    k_finalize<<<1, kFinWG, 0, st>>>(w->partials, nwg, nv, ep, cs, B, out, D->D, nact, out2, rz_mode);
+    k_finalize<<<1, kFinWG, 0, st>>>(src, nwg, nv, ep, cs, B, out, D->D, nact, out2, rz_mode);
   }
 
   // SpMM kernel variant for this batch width: team size TS, column lanes CW,
@@ -2175,16 +2261,11 @@ struct Launcher {
     int TS, CW, slot;
   };
   template <typename T>
-  SpmmVariant<T> spmm_variant(bool weighted) const {
+  SpmmVariant<T> spmm_variant(bool weighted, int B) const {
     const Tuning& tu = tuning();
-    int TS, CW;
-    if (B == 1) { TS = tu.ts1; CW = 1; }
-    else if (B == 2) { TS = 8; CW = 2; }
-    else if (B <= 4) { TS = 16; CW = 4; }
-    else if (B <= 8) { TS = 32; CW = 8; }
-    else if (B <= 16) { TS = 64; CW = 16; }
-    else if (B <= 32) { TS = 64; CW = 32; }
-    else { TS = 64; CW = 64; }
+    (void)tu;
+    const int TS = spmm_team_size(B);
+    const int CW = B <= 1 ? 1 : (B <= 2 ? 2 : (B <= 4 ? 4 : (B <= 8 ? 8 : (B <= 16 ? 16 : (B <= 32 ? 32 : 64)))));
     if (B > MAXC * CW) fail(KATZ_EINVAL, "batch too wide for one launch");
     const int nc = (B + CW - 1) / CW;  // column groups per lane
     SpmmVariant<T> v{nullptr, TS, CW, -1};
@@ -2208,20 +2289,23 @@ struct Launcher {
   // and returns the grid and LDS size.
   template <typename T>
   void spmm_shape(SpmmArgs<T>& a, const SpmmVariant<T>& v, int32_t walk, dim3& g, size_t& shm) const {
+    const int B = a.B;
     const Tuning& tu = tuning();
     const int64_t rows = a.row1 - a.row0;
     const int teams = WG / v.TS;
-    // chunks of teams * rows_team rows, walked contiguously or in XCD slabs
-    a.rows_per_wg = teams * tu.rows_team;
-    a.xcd = walk_xcd(walk);
-    a.nchunks = (rows + a.rows_per_wg - 1) / a.rows_per_wg;
-    const int64_t nwg = std::min<int64_t>(walk_nwg(walk), a.nchunks);
+    (void)tu;
     a.partials = w->partials;
     a.long_thr = kLongRow;
     if (a.row0 == D->n1 && a.row1 == D->n) { a.long_rows = D->long_sep; a.n_long = D->n_long_sep; }
     else if (a.row0 == 0 && a.row1 == D->n) { a.long_rows = D->long_all; a.n_long = D->n_long_all; }
     else { a.long_rows = nullptr; a.n_long = 0; }
     if (a.n_long == 0) a.long_rows = nullptr;
+    // chunks of teams x rows_team rows, walked contiguously or in XCD slabs;
+    // chunk ch's dot terms are partial row n_long + ch
+    a.rows_per_wg = spmm_chunk_rows(B, a.ld, rows, a.n_long);
+    a.xcd = walk_xcd(walk);
+    a.nchunks = (rows + a.rows_per_wg - 1) / a.rows_per_wg;
+    const int64_t nwg = std::min<int64_t>(walk_nwg(walk), a.nchunks);
     g = dim3((unsigned)(nwg + a.n_long));
     shm = sizeof(double) * std::max<size_t>((size_t)teams * B, (size_t)(WG / 64) * MAXC * v.CW);
   }
@@ -2233,13 +2317,20 @@ struct Launcher {
       if (a.ep != EP_NONE) fail(KATZ_EDEVICE, "internal: empty SpMM with a reduction");
       return;
     }
-    a.B = B;
-    const SpmmVariant<T> v = spmm_variant<T>(a.val != nullptr);
+    // column slices: launches of W columns each over the same rows (every
+    // slice has the same launch shape, so the partial sums line up for one
+    // finalize over all B columns)
+    const int W = tuning().spmm_slice;
+    const int nsl = (W > 0 && B > W && B % W == 0) ? B / W : 1;
+    const int bw = B / nsl;
+    a.ld = B;
+    a.B = bw;
+    const SpmmVariant<T> v = spmm_variant<T>(a.val != nullptr, bw);
     dim3 g;
     size_t shm;
     spmm_shape(a, v, walk_for(v.slot), g, shm);
-    const int nwg_all = (int)g.x;
-    need(nwg_all, B);
+    const int prows = (int)(a.n_long + a.nchunks);  // partial rows (walk-independent)
+    need(prows, B);
     // algorithmic bytes: row pointers and splits, the selected entries, each
     // gathered panel row once, the row-aligned panels read and y written
     const bool sep = a.row0 == D->n1 && a.row1 == D->n;
@@ -2251,8 +2342,13 @@ struct Launcher {
     int panels = 1 + (a.v ? 1 : 0) + (a.w ? 1 : 0) + ((a.dotv && a.dotv != a.v) ? 1 : 0);
     double bytes = 8.0 * rows + 4.0 + (4.0 + (a.val ? 8.0 : 0.0)) * nnz_sel + wb * cols_sel + wb * rows * panels;
     const int kind = sep ? (a.parts == 1 ? PK_SPMM_RHS : PK_SPMM_SEP) : PK_SPMM_FULL;
-    timed(kind, bytes, [&] { v.fn<<<g, WG, shm, st>>>(a); });
-    if (a.ep != EP_NONE) finalize(nwg_all, B, a.ep, a.cs, a.out, a.n_active);
+    timed(kind, bytes, [&] {
+      for (int sl = 0; sl < nsl; sl++) {
+        a.j0 = sl * bw;
+        v.fn<<<g, WG, shm, st>>>(a);
+      }
+    });
+    if (a.ep != EP_NONE) finalize(prows, B, a.ep, a.cs, a.out, a.n_active);
   }
 
   // Chunk walk of an SpMM variant: the one tuned for this index, else the
@@ -2274,15 +2370,19 @@ struct Launcher {
   // graphs).  Each is timed on the launch `a` describes (one warm-up and two
   // timed launches; `a.y` must be a panel the caller overwrites afterwards)
   // and the fastest kept, a non-default only when 3% faster.  The choice is
-  // kept per index and variant, and per process for the graph's shape, so
-  // indexes of one graph in one process compute bit-identical results.  Not
-  // run under HIP-graph capture or when the walk is pinned by the environment.
+  // kept per index and variant, and per process for the graph's shape.  It
+  // changes no result bit: the reductions are indexed by chunk, not by
+  // workgroup.  Not run under HIP-graph capture or when the walk is pinned by
+  // the environment.
   template <typename T>
   void tune_spmm(SpmmArgs<T> a) {
     const Tuning& tu = tuning();
     if (a.row1 <= a.row0) return;
-    a.B = B;
-    const SpmmVariant<T> v = spmm_variant<T>(a.val != nullptr);
+    const int W = tu.spmm_slice;
+    a.B = (W > 0 && B > W && B % W == 0) ? W : B;   // the launch width spmm() uses
+    a.ld = B;
+    a.j0 = 0;
+    const SpmmVariant<T> v = spmm_variant<T>(a.val != nullptr, a.B);
     if (!tu.autotune || w->external || D->walk[v.slot].load(std::memory_order_acquire) >= 0) return;
     hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
     HIPCHECK(hipStreamIsCapturing(st, &cst));
@@ -2762,6 +2862,7 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
       s.x = x2 ? x2 - (int64_t)n1 * B : nullptr;  // x2 is rows >= n1 of a full panel
       s.ca = (T)0; s.cb = (T)1; s.cu = ca; s.v = v; s.cv = cv; s.out = out;
       s.B = B; s.nblocks = D->nblocks; s.blocks_per_chunk = (WG / cw) * tu.m11_bpt; s.xcd = tu.xcd;
+      s.ld = B; s.j0 = 0;
       s.nchunks = (D->nblocks + s.blocks_per_chunk - 1) / s.blocks_per_chunk;
       s.n_active = nact;
       const dim3 g((unsigned)std::min<int64_t>(tu.spmm_nwg, s.nchunks));
@@ -3272,7 +3373,7 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
         HIPCHECK(hipMemcpyAsync(w->pr_cols, cols.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
         k_pair_gather<<<(unsigned)((np + WG - 1) / WG), WG, 0, st>>>((int)np, B, w->K, w->pr_rows, w->pr_cols,
                                                                     w->pr_out);
-        HIPCHECK(hipMemcpyAsync(qa.pair_out + p0, w->pr_out, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipMemcpyAsync(qa.pair_out + p0, w->pr_out, sizeof(double) * np, hipMemcpyDefault, st));
         HIPCHECK(hipStreamSynchronize(st));  // `cols` is pageable host memory
       }
     }
@@ -3344,6 +3445,158 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
   return rc;
 }
 
+// ------------------------------------------------ Sparse-Katz re-ranking
+// Algorithm 3, last step, one workgroup per query i: with K_T the Katz scores
+// K[v, t] of the query (row r = 0) and its nc listed candidates (rows
+// r = 1..nc) at its T modular nodes t, rho_j is the Pearson correlation of
+// rows 0 and j + 1 over t (undefined when either row is constant); the list
+// is re-ordered by rho descending, undefined correlations last, equal ones in
+// the Katz order.  kt[inv[base_i + t (nc + 1) + r]] holds K_T[r][t].  Means
+// and sums run in t order; the order is a bitonic sort in LDS.
+constexpr int kRerankMax = 4096;
+__device__ inline bool rerank_before(double ka, int32_t pa, double kb, int32_t pb) {
+  const bool fa = ka == ka, fb = kb == kb;
+  if (fa != fb) return fa;
+  if (fa && ka != kb) return ka > kb;
+  return pa < pb;
+}
+__global__ __launch_bounds__(WG) void k_sparse_rerank(const double* kt, const int32_t* inv, const int64_t* base,
+                                                      const int32_t* ncand, const int32_t* nmod, const int32_t* cand,
+                                                      int s, int32_t* ids, double* corr) {
+  __shared__ double key[kRerankMax];
+  __shared__ int32_t pos[kRerankMax];
+  __shared__ double qs[2];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int nc = ncand[i], T = nmod[i];
+  const int64_t b0 = base[i];
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
+  if (tid == 0) {
+    double mq = 0.0, sq = 0.0;
+    if (T >= 2) {
+      for (int t = 0; t < T; t++) mq += kt[inv[b0 + (int64_t)t * (nc + 1)]];
+      mq /= T;
+      for (int t = 0; t < T; t++) {
+        const double d = kt[inv[b0 + (int64_t)t * (nc + 1)]] - mq;
+        sq = __fma_rn(d, d, sq);
+      }
+    }
+    qs[0] = mq;
+    qs[1] = sq;
+  }
+  __syncthreads();
+  int P = 1;
+  while (P < nc) P <<= 1;
+  for (int j = tid; j < P; j += WG) {
+    double rho = nan;
+    if (j < nc && T >= 2) {
+      double mj = 0.0;
+      for (int t = 0; t < T; t++) mj += kt[inv[b0 + (int64_t)t * (nc + 1) + 1 + j]];
+      mj /= T;
+      double sj = 0.0, cj = 0.0;
+      for (int t = 0; t < T; t++) {
+        const double dq = kt[inv[b0 + (int64_t)t * (nc + 1)]] - qs[0];
+        const double dj = kt[inv[b0 + (int64_t)t * (nc + 1) + 1 + j]] - mj;
+        sj = __fma_rn(dj, dj, sj);
+        cj = __fma_rn(dq, dj, cj);
+      }
+      if (qs[1] > 0.0 && sj > 0.0) rho = cj / sqrt(qs[1] * sj);
+    }
+    key[j] = rho;
+    pos[j] = j;  // padding (j >= nc) is undefined and sorts after every candidate
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int h = k >> 1; h > 0; h >>= 1) {
+      for (int a = tid; a < P; a += WG) {
+        const int b = a ^ h;
+        if (b > a) {
+          const bool up = (a & k) == 0;  // this pair's run ascends in the order
+          const bool swap = up ? rerank_before(key[b], pos[b], key[a], pos[a])
+                               : rerank_before(key[a], pos[a], key[b], pos[b]);
+          if (swap) {
+            const double tk = key[a]; key[a] = key[b]; key[b] = tk;
+            const int32_t tp = pos[a]; pos[a] = pos[b]; pos[b] = tp;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int p = tid; p < s; p += WG) {
+    const bool in = p < nc;
+    ids[(int64_t)i * s + p] = in ? cand[(int64_t)i * s + pos[p]] : -1;
+    corr[(int64_t)i * s + p] = in ? key[p] : nan;
+  }
+}
+
+// Solves the modular nodes' Katz vectors (the distinct sources q_src, as one
+// batched query with pair gathers K[row, q_src[col]] into a device buffer),
+// then re-ranks on the device (k_sparse_rerank).  Returns the status of the
+// solves; pst receives their stats.
+int device_sparse_katz(const HostIndex& H, DeviceIndex* D, const katz_query_opts& opts, void* stream,
+                       const std::vector<int32_t>& q_src, const std::vector<int32_t>& pcol,
+                       const std::vector<int32_t>& prow, const std::vector<int32_t>& inv,
+                       const std::vector<int64_t>& base, const std::vector<int32_t>& ncand,
+                       const std::vector<int32_t>& nmod, const std::vector<int32_t>& cand, int nq, int s,
+                       katz_query_stats* pst, int32_t* ids, double* corr) {
+  HIPCHECK(hipSetDevice(D->device));
+  std::vector<void*> tmp;
+  struct Free {
+    std::vector<void*>& t;
+    ~Free() {
+      std::lock_guard<std::recursive_mutex> g(hip_global_mu());
+      for (void* p : t) (void)hipFree(p);
+    }
+  } fr{tmp};
+  const int64_t np = (int64_t)pcol.size();
+  double* kt = dalloc<double>(tmp, std::max<int64_t>(1, np));
+  int rc = KATZ_OK;
+  if (np > 0) {
+    QueryArgs a{};
+    a.q = q_src.data(); a.nq = (int32_t)q_src.size(); a.opts = opts; a.scores = nullptr; a.topk = 0;
+    a.st = pst; a.stream = stream;
+    a.npairs = (int32_t)np; a.pair_col = pcol.data(); a.pair_row = prow.data(); a.pair_out = kt;
+    rc = device_query(H, D, a);
+  }
+  device_sparse_rerank(D->device, nq, s, kt, inv, base, ncand, nmod, cand, ids, corr, stream);
+  return rc;
+}
+
+void device_sparse_rerank(int device, int nq, int s, const double* kt_dev, const std::vector<int32_t>& inv,
+                          const std::vector<int64_t>& base, const std::vector<int32_t>& ncand,
+                          const std::vector<int32_t>& nmod, const std::vector<int32_t>& cand, int32_t* ids,
+                          double* corr, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (s > kRerankMax) fail(KATZ_EINVAL, "Sparse-Katz list longer than 4096");
+  HIPCHECK(hipSetDevice(device));
+  std::vector<void*> tmp;
+  struct Free {
+    std::vector<void*>& t;
+    ~Free() {
+      std::lock_guard<std::recursive_mutex> g(hip_global_mu());
+      for (void* p : t) (void)hipFree(p);
+    }
+  } fr{tmp};
+  auto up = [&](const auto& v) {
+    typedef typename std::decay<decltype(v[0])>::type E;
+    E* d = dalloc<E>(tmp, (int64_t)std::max<size_t>(1, v.size()));
+    if (!v.empty()) HIPCHECK(hipMemcpyAsync(d, v.data(), sizeof(E) * v.size(), hipMemcpyHostToDevice, st));
+    return d;
+  };
+  const int32_t* d_inv = up(inv);
+  const int64_t* d_base = up(base);
+  const int32_t* d_nc = up(ncand);
+  const int32_t* d_nm = up(nmod);
+  const int32_t* d_cand = up(cand);
+  int32_t* d_ids = dalloc<int32_t>(tmp, (int64_t)nq * s);
+  double* d_corr = dalloc<double>(tmp, (int64_t)nq * s);
+  k_sparse_rerank<<<nq, WG, 0, st>>>(kt_dev, d_inv, d_base, d_nc, d_nm, d_cand, s, d_ids, d_corr);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(ids, d_ids, sizeof(int32_t) * (size_t)nq * s, hipMemcpyDefault, st));
+  if (corr) HIPCHECK(hipMemcpyAsync(corr, d_corr, sizeof(double) * (size_t)nq * s, hipMemcpyDefault, st));
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
 // ------------------------------------------------ queries without allocation
 // Scratch of katz_query_noalloc: panels, partial sums and per-column state
 // of the solve live in this file-scope device array (one copy on every GPU
@@ -3409,8 +3662,9 @@ size_t carve_ws(const DeviceIndex* D, int B, char* base, Workspace* w) {
   char* Y = c.take<char>(nB * esz);
   char* W = c.take<char>(nB * esz);
   char* Z = c.take<char>((int64_t)std::max(1, D->n2) * B * esz);
-  const size_t pcap = partials_per_column(D) * (size_t)std::max(B, 1);
+  const size_t pcap = std::max(partials_per_column(D) * (size_t)std::max(B, 1), spmm_partials_need(D, std::max(B, 1)));
   double* partials = c.take<double>((int64_t)pcap);
+  double* seg = c.take<double>((int64_t)seg_values(D, std::max(B, 1)));
   double* DW = c.take<double>(rk * B);
   double* DW2 = c.take<double>(rk * B);
   double* sc = c.take<double>(12 * (int64_t)B);
@@ -3420,7 +3674,7 @@ size_t carve_ws(const DeviceIndex* D, int B, char* base, Workspace* w) {
   if (w) {
     w->B = B; w->n = D->n; w->n2 = D->n2; w->device = D->device;
     w->Rhs = Rhs; w->K = K; w->Dx = Dx; w->X = X; w->Y = Y; w->W = W; w->Z = Z;
-    w->partials = partials; w->partials_cap = pcap; w->DW = DW; w->DW2 = DW2;
+    w->partials = partials; w->partials_cap = pcap; w->seg = seg; w->DW = DW; w->DW2 = DW2;
     w->rz = sc; w->pq = sc + B; w->alpha = sc + 2 * B; w->bcg = sc + 3 * B; w->rr = sc + 4 * B;
     w->thr = sc + 5 * B; w->bn2 = sc + 6 * B; w->res2 = sc + 7 * B; w->colscale = sc + 8 * B;
     w->rn2 = sc + 9 * B; w->inv = sc + 10 * B; w->fwd = sc + 11 * B;
@@ -3711,7 +3965,8 @@ void device_lanczos_R(HostIndex& H, DeviceIndex* D) {
     upload_factors(H, D);
     HIPCHECK(hipDeviceSynchronize());
   }
-  H.build_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  H.phase_seconds[10] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  H.build_seconds += H.phase_seconds[10];
 }
 
 int profile_enable(int on) { return g_prof_on.exchange(on ? 1 : 0); }

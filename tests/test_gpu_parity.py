@@ -333,14 +333,16 @@ def test_device_lanczos_full_spectrum(monkeypatch):
     np.testing.assert_allclose(U.T @ U, np.eye(6), atol=1e-10)
 
 
-def test_sparse_katz_matches_oracle():
+@pytest.mark.parametrize("s,T", [(20, 8), (300, 5)])
+def test_sparse_katz_matches_oracle(s, T):
     # Sparse-Katz (Algorithm 3): the re-ranked top-s list and its
-    # correlations against the oracle, tie classes of correlation width 1e-7
+    # correlations (computed and sorted on the device) against the oracle,
+    # tie classes of correlation width 1e-7; a list longer than a workgroup
+    # (300) takes several sort elements per thread
     g = ki.workload("lnsbm4m", scale=0.002).graph
     beta = oracle_beta(g, 0.7)
     idx = K.KatzIndex.from_graph(g, beta=beta, rank=8, labels=g.labels, max_block=32)
     qs = ki.sample_queries(g, 3, 61)
-    s, T = 20, 8
     ids, corr, st = idx.sparse_katz(qs, s, T, tol=1e-11)
     assert all(x["status"] == 0 for x in st)
     for i, q in enumerate(qs):
@@ -498,3 +500,48 @@ def test_bad_method_rejected():
     with pytest.raises(K.KatzError) as e:
         idx.query([3], method=7)
     assert e.value.code == K.KATZ_EINVAL
+
+
+_WALK_SCRIPT = r"""
+import sys, numpy as np
+sys.path.insert(0, sys.argv[2])
+import katz_inputs as ki, paper_1912_06525_amd as K
+g = ki.workload("lnsbm4m", scale=0.004).graph
+out = {}
+for prec in (K.KATZ_PREC_FP64, K.KATZ_PREC_MIXED):
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.9, rank=16, labels=g.labels, max_block=32, precision=prec)
+    for B in (1, 40, 130):
+        qs = ki.sample_queries(g, B, 90 + B)
+        for m in (K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG):
+            sc, st = idx.query(qs, tol=1e-8, method=m)
+            out["p%d_b%d_m%d" % (prec, B, m)] = sc
+            out["p%d_b%d_m%d_it" % (prec, B, m)] = np.array([x["iters"] for x in st])
+    idx.close()
+np.savez(sys.argv[1], **out)
+"""
+
+
+def test_results_independent_of_chunk_walk(tmp_path):
+    """The SpMM chunk walk (contiguous or XCD slabs, any workgroup count) is
+    a timing choice: scores and iteration counts must be bit-identical under
+    every walk, since each chunk's reduction terms have a fixed slot.  Each
+    walk runs in a child process (the walk is pinned by the environment)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    walks = [{}, {"KATZ_XCD_SLAB": "1"}, {"KATZ_SPMM_NWG": "1000"},
+             {"KATZ_XCD_SLAB": "1", "KATZ_SPMM_NWG": "3000"}]
+    res = []
+    for t, extra in enumerate(walks):
+        env = dict(os.environ)
+        for k in ("KATZ_XCD_SLAB", "KATZ_SPMM_NWG"):
+            env.pop(k, None)
+        env.update(extra)
+        f = str(tmp_path / ("walk%d.npz" % t))
+        print("walk", extra, flush=True)
+        subprocess.run([sys.executable, "-c", _WALK_SCRIPT, f, root], env=env, check=True, timeout=300)
+        res.append(np.load(f))
+    for t in range(1, len(walks)):
+        for k in res[0].files:
+            assert np.array_equal(res[0][k], res[t][k]), (walks[t], k)
