@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving mode on --workload (default dcsbm16m)")
     ap.add_argument("--requests", type=int, default=200, help="requests per offered-load point (serving)")
     ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--methods", type=str, default="lrc,cg", help="serving: methods to run (lrc, cg)")
+    ap.add_argument("--burst", type=int, default=0, help="serving: requests of the saturation burst (default --requests)")
     ap.add_argument("--max-batch-cols", type=int, default=64)
     ap.add_argument("--legs", type=str, default="c3,c4",
                     help="batched legs after the one-query headline: c3 (4M-node SBM, 256 FP64 columns), "
@@ -188,7 +190,7 @@ def main():
         log("c=%.2f index: n1=%d n2=%d blocks=%d sigma1=%.4f sigma_r+1=%.5f build %.1fs"
             % (c, info.n1, info.n2, info.nblocks, info.sigma_max, info.sigma_next, time.time() - tb))
         entry = {"n1": info.n1, "n2": info.n2, "nblocks": info.nblocks, "build_s": round(info.build_seconds, 2),
-                 "beta": info.beta, "lambda_max": info.lambda_max}
+                 "build_phases": build_phases(info), "beta": info.beta, "lambda_max": info.lambda_max}
         for name, method in (("lrc", K.KATZ_METHOD_LRC), ("cg", K.KATZ_METHOD_CG)):
             run(idx, method, args.warmup, 0)
             torch.cuda.synchronize()
@@ -229,6 +231,13 @@ def main():
                                 errs.append(q)
                     except Exception as e:  # reported below
                         errs.append(repr(e))
+                # an untimed round first: each thread's workspace, its captured
+                # iteration graphs and the device caches are in place before timing
+                ths = [threading.Thread(target=worker, args=(i,)) for i in range(args.concurrency)]
+                for th in ths:
+                    th.start()
+                for th in ths:
+                    th.join()
                 ths = [threading.Thread(target=worker, args=(i,)) for i in range(args.concurrency)]
                 torch.cuda.synchronize()
                 t = time.perf_counter()
@@ -666,11 +675,13 @@ def run_serving(args):
     tb = time.time()
     idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=rank, max_block=args.max_block, device=0,
                                  labels=g.labels, precision=prec)
-    log("index: n2=%d build %.1fs" % (idx.info.n2, time.time() - tb))
+    log("index: n2=%d build %.1fs %s" % (idx.info.n2, time.time() - tb, build_phases(idx.info)))
     rng = np.random.default_rng(4005)
     pool = ki.sample_queries(g, min(g.n // 2, 200000), 4006)
     results = {}
     for method_name, method in (("lrc", K.KATZ_METHOD_LRC), ("cg", K.KATZ_METHOD_CG)):
+        if method_name not in args.methods.split(","):
+            continue
         srv = K.KatzServer(idx, workers=args.workers, max_batch=args.max_batch_cols, k=100, tol=1e-6,
                            method=method)
         info = srv.info()
@@ -685,7 +696,7 @@ def run_serving(args):
         for t in [srv.submit(make_req()) for _ in range(args.workers * 2)]:
             srv.poll(t)
         # saturation: a burst of requests, completion rate in queries/s
-        reqs = [make_req() for _ in range(args.requests)]
+        reqs = [make_req() for _ in range(args.burst or args.requests)]
         tt = time.perf_counter()
         tks = [srv.submit(r) for r in reqs]
         lats = [srv.poll(t)[3] for t in tks]
@@ -718,15 +729,18 @@ def run_serving(args):
                 % (method_name, load, load * sat, nq / el, np.percentile(lat, 50), np.percentile(lat, 99)))
         results[method_name] = entry
         srv.close()
-    head = results["lrc"]
+    head = results.get("lrc") or results["cg"]
     line = {"metric": "Katz queries/sec at 1e-6 rel. residual, LRC-Katz vs CG, 1 MI355X; p99 ms",
             "value": round(head["saturation_qps"], 2), "unit": "queries/s", "n_gpus": 1, "steps": args.requests,
             "warmup": args.workers * 2, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32+bf16/f64" if prec == K.KATZ_PREC_MIXED else "f64",
             "data": "synthetic",
             "config": {"workload": "serving, %s, %d nodes, top-100 requests of 1-512 nodes" % (wl, g.n),
-                       "n": g.n, "nnz": g.nnz, "workers": args.workers, "max_batch": args.max_batch_cols},
-            "p99_ms": round(head["load_0.8"]["p99_ms"], 3), "cg_qps": round(results["cg"]["saturation_qps"], 2),
+                       "n": g.n, "nnz": g.nnz, "workers": args.workers, "max_batch": args.max_batch_cols,
+                       "requests_per_load_point": args.requests},
+            "build_s": round(idx.info.build_seconds, 2), "build_phases": build_phases(idx.info),
+            "p99_ms": round(head["load_0.8"]["p99_ms"], 3),
+            "cg_qps": round(results["cg"]["saturation_qps"], 2) if "cg" in results else None,
             "roofline": None, "cpu_baseline": None, "results": results}
     print(json.dumps(line), flush=True)
 
@@ -843,6 +857,16 @@ def cpu_leg_one_query(g, idx, queries, tol, K, nsample=8):
     return {"baseline": base, "parity_ok": ok and base["lambda_rel_diff"] <= 1e-9}
 
 
+PHASES = ["validate", "lambda_max", "partition_bfs_chunks", "partition_vertex_cover", "partition_minimality",
+          "partition_components", "partition_order", "permuted_csr", "block_inverses", "m22_factor",
+          "lanczos_on_R", "device_upload"]
+
+
+def build_phases(info):
+    """The index build's wall seconds per phase (katz_index_info_t)."""
+    return {k: round(v, 3) for k, v in zip(PHASES, info.build_phase_seconds)}
+
+
 LEGS = {
     # name: workload, columns per solve, c, rank, precision, oracle tail fraction
     "c3": ("lnsbm4m", 256, 0.5, 32, "fp64", 1e-10),
@@ -902,7 +926,8 @@ def run_leg(leg, args, torch, K, ki, dev, copy_gbs):
     out = torch.empty((B, g.n), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
     entry = {"workload": wl, "n": g.n, "nnz": g.nnz, "batch": B, "c": c, "rank": rank, "precision": precision,
-             "n1": info.n1, "n2": info.n2, "build_s": round(info.build_seconds, 2), "steps": steps, "warmup": warm}
+             "n1": info.n1, "n2": info.n2, "build_s": round(info.build_seconds, 2), "build_phases": build_phases(info),
+             "steps": steps, "warmup": warm}
     picked = None
     for name, method in (("lrc", K.KATZ_METHOD_LRC), ("cg", K.KATZ_METHOD_CG)):
         def step(s):

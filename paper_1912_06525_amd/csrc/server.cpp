@@ -3,9 +3,14 @@
 //
 // Continuous batching over worker slots: every worker owns a device workspace
 // of fixed column capacity and its own stream.  An idle worker takes query
-// columns from the head of the request queue -- a whole small request, several
-// small requests merged, or a slice of a large one -- up to its capacity, and
-// solves them as one batch (Algorithm 2 with the top-K selection).  Requests
+// columns from the request queue -- a whole small request, several small
+// requests merged, or a slice of a large one -- and solves them as one batch
+// (Algorithm 2 with the top-K selection).  Two rules keep latency low:
+//   - the queued columns are spread over the idle workers (a batch takes
+//     ceil(queued / idle) columns, at least kMinSlice and at most the
+//     capacity), so a lone request runs on every free slot at once;
+//   - while other requests wait, one request holds at most W - 1 of the W
+//     workers, so a large request does not block the small ones behind it.  Requests
 // that arrive while others are on the GPU start as soon as a worker slot is
 // free; the workers' batches run concurrently on the device.  The number of
 // workers and their capacity are admitted against free HBM at creation (each
@@ -19,6 +24,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -37,6 +43,10 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Narrowest batch the spreading rule makes (narrower LRC batches lose more
+// per column than the extra parallel slot gains).
+constexpr int kMinSlice = 16;
+
 struct Request {
   int64_t ticket;
   std::vector<int32_t> q;
@@ -45,6 +55,7 @@ struct Request {
   std::vector<katz_query_stats> st;
   int32_t next = 0;               // first query not yet taken by a worker
   int32_t remaining = 0;          // queries not yet finished
+  int32_t inflight = 0;           // slices of this request being solved
   int status = KATZ_OK;
   Clock::time_point t_submit, t_done;
   bool done = false;
@@ -65,6 +76,11 @@ struct Server {
   std::vector<std::thread> workers;
   std::vector<Workspace*> ws;
   std::atomic<int64_t> live_columns{0}, done_queries{0}, done_requests{0};
+  int busy = 0;                                              // workers solving a batch (under mu)
+  // KATZ_SERVE_FIFO=1 (measurements only): full batches from the queue head,
+  // no spreading over idle workers and no per-request share
+  const bool fifo_only = getenv("KATZ_SERVE_FIFO") && atoi(getenv("KATZ_SERVE_FIFO")) > 0;
+  int64_t queued_cols = 0;                                   // untaken columns in the queue (under mu)
   std::vector<double> latencies_ms;                          // completed requests
   int64_t max_latency_samples = 1 << 20;
   std::string init_error;
@@ -100,17 +116,34 @@ struct Server {
       q.clear();
       {
         std::unique_lock<std::mutex> g(mu);
-        cv_work.wait(g, [&] { return stop || !queue.empty(); });
+        const int W = (int)ws.size();
+        // the first request this worker may take from: FIFO, skipping one
+        // that already holds W - 1 workers while others wait
+        auto pick = [&]() -> int {
+          const int share = (queue.size() > 1 && !fifo_only) ? std::max(1, W - 1) : W;
+          for (size_t t = 0; t < queue.size(); t++)
+            if (queue[t]->inflight < share) return (int)t;
+          return -1;
+        };
+        cv_work.wait(g, [&] { return (stop && queue.empty()) || pick() >= 0; });
         if (stop && queue.empty()) break;
-        // take columns from the head of the queue up to the capacity
-        while (!queue.empty() && (int)q.size() < cap) {
-          auto r = queue.front();
-          const int32_t take = std::min<int32_t>(cap - (int32_t)q.size(), (int32_t)r->q.size() - r->next);
+        const int idle = std::max(1, W - busy);
+        const int64_t spread = (queued_cols + idle - 1) / idle;
+        const int want = fifo_only ? cap
+                                   : (int)std::min<int64_t>(cap, std::max<int64_t>(std::min(kMinSlice, cap), spread));
+        for (int t = pick(); t >= 0 && t < (int)queue.size() && (int)q.size() < want;) {
+          auto r = queue[t];
+          const int32_t take = std::min<int32_t>(want - (int32_t)q.size(), (int32_t)r->q.size() - r->next);
           slices.push_back({r, r->next, take});
           q.insert(q.end(), r->q.begin() + r->next, r->q.begin() + r->next + take);
           r->next += take;
-          if (r->next == (int32_t)r->q.size()) queue.pop_front();
+          r->inflight++;
+          queued_cols -= take;
+          if (r->next == (int32_t)r->q.size()) queue.erase(queue.begin() + t);
+          else t++;
         }
+        if (q.empty()) continue;
+        busy++;
       }
       const int nq = (int)q.size();
       live_columns += nq;
@@ -145,6 +178,7 @@ struct Server {
         std::memcpy(&r.st[s.off], &st[pos], sizeof(katz_query_stats) * s.cnt);
         if (rc != KATZ_OK && r.status == KATZ_OK) r.status = rc;
         r.remaining -= s.cnt;
+        r.inflight--;
         pos += s.cnt;
         if (r.remaining == 0) {
           r.done = true;
@@ -155,7 +189,9 @@ struct Server {
         }
       }
       done_queries += nq;
+      busy--;
       cv_done.notify_all();
+      cv_work.notify_all();  // a slot is free, and a request may be below its share again
     }
     std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
     (void)hipStreamDestroy(stream);
@@ -262,6 +298,7 @@ int katz_server_submit(katz_server* S, const int32_t* q, int32_t nq, int64_t* ti
         s.live.erase(r->ticket);
         throw;
       }
+      s.queued_cols += nq;
       *ticket = r->ticket;
     }
   } catch (const std::bad_alloc&) {

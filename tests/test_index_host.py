@@ -360,3 +360,17 @@ def test_query_option_defaults():
     o = K.katz_query_opts_default()
     assert o.rel_tol == 1e-6 and o.max_iter == 1000 and o.max_sweeps == 6
     assert o.check_every == 0 and o.force_fallback == 0
+
+
+def test_build_phase_times():
+    """katz_index_info_t reports the build's wall time per phase: every phase
+    is nonnegative, a host-only build has no upload, and the phases account
+    for the build time."""
+    g = ki.workload("lnsbm4m", scale=0.01).graph
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=8, max_block=32, device=-1, labels=g.labels)
+    ph = list(idx.info.build_phase_seconds)
+    assert len(ph) == 12 and all(x >= 0 for x in ph)
+    assert ph[11] == 0.0
+    assert ph[2] > 0 and ph[10] > 0            # partition and the host Lanczos ran
+    assert sum(ph) <= idx.info.build_seconds * 1.01 + 1e-3
+    assert sum(ph) >= 0.5 * idx.info.build_seconds
