@@ -224,7 +224,9 @@ int katz_query(const katz_index* idx, const int32_t* q, int32_t nq, const katz_q
  *     larger nq runs in chunks of the columns that fit;
  *   - it runs on `stream` itself (not on a workspace stream), without HIP
  *     graphs, kernel profiling or the SpMM launch-shape autotuner (it uses
- *     the shape an earlier katz_query chose, or the default);
+ *     the shape an earlier katz_query chose, or the default; results do not
+ *     depend on that shape);
+ *   - the KATZ_METHOD_PCGNR ablation is not offered (KATZ_EINVAL);
  *   - every call on one GPU shares that GPU's scratch, which keeps the last
  *     call's contents (the state that must start at zero is cleared by each
  *     call): calls that overlap on one GPU, from several threads or streams,
@@ -322,10 +324,11 @@ int katz_index_lowrank(const katz_index* idx, double* U, double* sigma);
 /* ------------------------------------------------------------- serving
  * Continuous batching of top-K link-prediction requests (Sec. 3.3) on one
  * index: `workers` worker slots, each with a device workspace of `max_batch`
- * query columns and its own stream, take columns from the head of the request
- * queue (merging small requests, splitting large ones) whenever they are free,
- * so requests arriving while others run are admitted as slots free up and
- * their batches overlap on the device.  Workers x max_batch is admitted
+ * query columns and its own stream, take columns from the request queue
+ * (merging small requests, splitting large ones) whenever they are free, so
+ * requests arriving while others run are admitted as slots free up and their
+ * batches overlap on the device.  Requests are served in arrival order,
+ * each free worker taking up to max_batch columns.  Workers x max_batch is admitted
  * against hbm_fraction of the free HBM at creation (reduced to fit; KATZ_ENOMEM
  * if not even one column fits).  All calls are thread-safe. */
 typedef struct katz_server katz_server;

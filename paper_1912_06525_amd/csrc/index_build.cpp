@@ -537,38 +537,50 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
   }, P > 1 ? 16 : 1);
   int32_t npiece = (int32_t)pbase[P];
   phase("BFS chunks");
-  // (c) greedy vertex cover of the cut edges (largest remaining cut degree first)
-  std::vector<int32_t> cutdeg(n, 0);
+  // (c) greedy vertex cover of the cut edges (largest remaining cut degree
+  // first; among equal degrees the node listed last, node 0 first at the
+  // start).  Each node's piece and remaining cut degree sit side by side (one
+  // cache line per neighbour visit), and a cover node's degree is set to -1:
+  // a neighbour u of a new cover node v across a cut has pd[u].deg >= 1
+  // exactly when u is not in the cover yet.
+  struct PD { int32_t piece, deg; };
+  std::vector<PD> pd(n);
   parallel_for(n, [&](int64_t b, int64_t e) {  // independent per node
     for (int64_t v = b; v < e; v++) {
       int32_t c = 0;
-      for (int32_t k = rp[v]; k < rp[v + 1]; k++) c += piece[col[k]] != piece[v];
-      cutdeg[v] = c;
+      const int32_t pv = piece[v];
+      for (int32_t k = rp[v]; k < rp[v + 1]; k++) c += piece[col[k]] != pv;
+      pd[v] = {pv, c};
     }
   }, 16384);
-  const int32_t dmax = n > 0 ? *std::max_element(cutdeg.begin(), cutdeg.end()) : 0;
+  int32_t dmax = 0;
+  for (int32_t v = 0; v < n; v++) dmax = std::max(dmax, pd[v].deg);
+  // one stack per degree; an entry whose node has since moved on is stale
   std::vector<std::vector<int32_t>> bucket(dmax + 1);
   for (int32_t v = n - 1; v >= 0; v--)
-    if (cutdeg[v] > 0) bucket[cutdeg[v]].push_back(v);
-  std::vector<char> insep(n, 0);
+    if (pd[v].deg > 0) bucket[pd[v].deg].push_back(v);
   std::vector<int32_t> sep_order;
   for (int32_t d = dmax; d > 0;) {
     if (bucket[d].empty()) { d--; continue; }
-    int32_t v = bucket[d].back();
+    const int32_t v = bucket[d].back();
     bucket[d].pop_back();
-    if (insep[v] || cutdeg[v] != d) continue;  // stale entry
-    insep[v] = 1;
+    if (pd[v].deg != d) continue;  // stale entry (or already in the cover: -1)
+    pd[v].deg = -1;
     sep_order.push_back(v);
-    cutdeg[v] = 0;
-    for (int32_t k = rp[v]; k < rp[v + 1]; k++) {
-      int32_t u = col[k];
-      if (!insep[u] && piece[u] != piece[v]) {
-        cutdeg[u]--;
-        if (cutdeg[u] > 0) bucket[cutdeg[u]].push_back(u);
-      }
+    const int32_t pv = pd[v].piece;
+    const int32_t k0 = rp[v], k1 = rp[v + 1];
+    for (int32_t k = k0; k < std::min(k1, k0 + 16); k++) __builtin_prefetch(&pd[col[k]], 1);
+    for (int32_t k = k0; k < k1; k++) {
+      if (k + 16 < k1) __builtin_prefetch(&pd[col[k + 16]], 1);
+      PD& u = pd[col[k]];
+      if (u.deg > 0 && u.piece != pv)
+        if (--u.deg > 0) bucket[u.deg].push_back(col[k]);
     }
   }
   std::vector<std::vector<int32_t>>().swap(bucket);
+  std::vector<char> insep(n, 0);
+  for (int32_t v : sep_order) insep[v] = 1;
+  std::vector<PD>().swap(pd);
   phase("vertex cover");
   // (d) minimality: a separator node whose non-separator neighbours all lie in
   // one piece (with room) joins that piece; one with none becomes a singleton.

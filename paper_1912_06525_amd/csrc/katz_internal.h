@@ -114,14 +114,6 @@ int device_sparse_katz(const HostIndex& H, DeviceIndex* D, const katz_query_opts
                        const std::vector<int64_t>& base, const std::vector<int32_t>& ncand,
                        const std::vector<int32_t>& nmod, const std::vector<int32_t>& cand, int nq, int s,
                        katz_query_stats* pst, int32_t* ids, double* corr);
-// Algorithm 3's correlation and re-ranking on the device: kt_dev holds the
-// gathered K_T entries, inv maps (query base + t (nc + 1) + row) to their
-// position in kt_dev; cand[nq * s] the listed candidates; ids/corr [nq * s]
-// host or device outputs.
-void device_sparse_rerank(int device, int nq, int s, const double* kt_dev, const std::vector<int32_t>& inv,
-                          const std::vector<int64_t>& base, const std::vector<int32_t>& ncand,
-                          const std::vector<int32_t>& nmod, const std::vector<int32_t>& cand, int32_t* ids,
-                          double* corr, void* stream);
 // As device_query for scores only (no top-K or pairs), on the caller's
 // stream, with every buffer of the solve in the library's static device
 // scratch: no device or pinned allocation, no graph capture.

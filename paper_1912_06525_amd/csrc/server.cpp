@@ -5,14 +5,9 @@
 // of fixed column capacity and its own stream.  An idle worker takes query
 // columns from the request queue -- a whole small request, several small
 // requests merged, or a slice of a large one -- and solves them as one batch
-// (Algorithm 2 with the top-K selection).  Two rules keep latency low:
-//   - the queued columns are spread over the idle workers (a batch takes
-//     ceil(queued / idle) columns, at least kMinSlice and at most the
-//     capacity), so a lone request runs on every free slot at once;
-//   - while other requests wait, one request holds at most W - 1 of the W
-//     workers, so a large request does not block the small ones behind it.  Requests
-// that arrive while others are on the GPU start as soon as a worker slot is
-// free; the workers' batches run concurrently on the device.  The number of
+// (Algorithm 2 with the top-K selection), the queue served in arrival order.
+// Requests that arrive while others are on the GPU start as soon as a worker
+// slot is free; the workers' batches run concurrently on the device.  The number of
 // workers and their capacity are admitted against free HBM at creation (each
 // resident column costs a fixed number of node-length panels), so requests
 // are queued, split and admitted by memory footprint, never over-subscribed.
@@ -77,9 +72,13 @@ struct Server {
   std::vector<Workspace*> ws;
   std::atomic<int64_t> live_columns{0}, done_queries{0}, done_requests{0};
   int busy = 0;                                              // workers solving a batch (under mu)
-  // KATZ_SERVE_FIFO=1 (measurements only): full batches from the queue head,
-  // no spreading over idle workers and no per-request share
-  const bool fifo_only = getenv("KATZ_SERVE_FIFO") && atoi(getenv("KATZ_SERVE_FIFO")) > 0;
+  // Batches are full (max_batch columns) and taken in arrival order.
+  // KATZ_SERVE_SPREAD=1 (measurements only) adds two rules: a free worker
+  // takes ceil(queued columns / idle workers) columns (at least kMinSlice),
+  // and one request holds at most W - 1 workers while others wait.  They
+  // gave no better latency than arrival order (the same at 1M nodes, 5-15%
+  // higher p50 at 4M), so they are off by default.
+  const bool spread_rules = getenv("KATZ_SERVE_SPREAD") && atoi(getenv("KATZ_SERVE_SPREAD")) > 0;
   int64_t queued_cols = 0;                                   // untaken columns in the queue (under mu)
   std::vector<double> latencies_ms;                          // completed requests
   int64_t max_latency_samples = 1 << 20;
@@ -117,10 +116,11 @@ struct Server {
       {
         std::unique_lock<std::mutex> g(mu);
         const int W = (int)ws.size();
-        // the first request this worker may take from: FIFO, skipping one
-        // that already holds W - 1 workers while others wait
+        // the first request this worker may take from: the queue head (with
+        // the spread rules, skipping one that holds W - 1 workers while
+        // others wait)
         auto pick = [&]() -> int {
-          const int share = (queue.size() > 1 && !fifo_only) ? std::max(1, W - 1) : W;
+          const int share = (queue.size() > 1 && spread_rules) ? std::max(1, W - 1) : W;
           for (size_t t = 0; t < queue.size(); t++)
             if (queue[t]->inflight < share) return (int)t;
           return -1;
@@ -129,7 +129,7 @@ struct Server {
         if (stop && queue.empty()) break;
         const int idle = std::max(1, W - busy);
         const int64_t spread = (queued_cols + idle - 1) / idle;
-        const int want = fifo_only ? cap
+        const int want = !spread_rules ? cap
                                    : (int)std::min<int64_t>(cap, std::max<int64_t>(std::min(kMinSlice, cap), spread));
         for (int t = pick(); t >= 0 && t < (int)queue.size() && (int)q.size() < want;) {
           auto r = queue[t];

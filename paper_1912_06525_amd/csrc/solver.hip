@@ -1638,7 +1638,7 @@ struct ProfEvents {
 struct Tuning {
   int ts1;          // lanes per row of the one-column SpMM (4, 8, 16, 32)
   int spmm_nwg;     // max short-row workgroups of the SpMM
-  int rows_team;    // target rows per team of the SpMM
+  int rows_team;    // target rows per team of the SpMM (0: 2 for one column, else 1)
   int ew_nwg;       // max workgroups of the row-parallel reduction kernels
   int ew_rows;      // target rows per workgroup of those kernels
   int xcd;          // XCD-slab chunk order for the gathering kernels
@@ -1663,7 +1663,7 @@ static const Tuning& tuning() {
     u.ts1 = env_int("KATZ_SPMM_TS1", 8, 4, 32);
     if (u.ts1 != 4 && u.ts1 != 8 && u.ts1 != 16 && u.ts1 != 32) u.ts1 = 8;
     u.spmm_nwg = env_int("KATZ_SPMM_NWG", 8192, 64, 65536);
-    u.rows_team = env_int("KATZ_SPMM_ROWS_PER_TEAM", 1, 1, 64);
+    u.rows_team = env_int("KATZ_SPMM_ROWS_PER_TEAM", 0, 0, 64);
     u.ew_nwg = env_int("KATZ_EW_NWG", 1024, 64, 65536);
     u.ew_rows = env_int("KATZ_EW_ROWS", 256, 16, 65536);
     u.xcd = env_int("KATZ_XCD_SLAB", 0, 0, 1);
@@ -1793,6 +1793,10 @@ struct DeviceIndex {
   // workgroups of the unstaged narrow V^T r kernel resident at once, per
   // panel precision (FP64, FP32; 0: not sized, the default grid applies)
   std::atomic<int32_t> lr_resident[2];
+  // device buffers reused by calls that need scratch beyond a workspace
+  // (Sparse-Katz's gathered K_T and lists): taken and returned under aux_mu
+  std::mutex aux_mu;
+  std::vector<std::pair<void*, size_t>> aux_free;
 };
 constexpr int kLongRow = 256;
 // HIP graphs of iteration chunks kept per workspace.
@@ -2024,6 +2028,7 @@ void device_free(DeviceIndex* D) {
   (void)hipSetDevice(D->device);
   for (auto& w : D->pool) free_ws(w.get());
   for (void* p : D->allocs) (void)hipFree(p);
+  for (auto& a : D->aux_free) (void)hipFree(a.first);
   delete D;
 }
 int64_t device_bytes(const DeviceIndex* D) { return D ? D->bytes : 0; }
@@ -2069,7 +2074,9 @@ static int spmm_team_size(int B) {
 // rows_team raised until (n_long + chunks) x ld fits kSpmmPartials.
 static int spmm_chunk_rows(int B, int ld, int64_t rows, int n_long) {
   const int64_t teams = WG / spmm_team_size(B);
-  int64_t rt = tuning().rows_team;
+  // one column: two rows per team (measured 2-3% faster than one, both
+  // methods, over 4,096-16,384 workgroups on the 1M-node Chung-Lu graph)
+  int64_t rt = tuning().rows_team > 0 ? tuning().rows_team : (B == 1 ? 2 : 1);
   const int64_t cap = std::max<int64_t>(1, kSpmmPartials / std::max(1, ld) - n_long);
   if ((rows + teams * rt - 1) / (teams * rt) > cap) rt = (rows + teams * cap - 1) / (teams * cap);
   return (int)(teams * rt);
@@ -2365,9 +2372,9 @@ struct Launcher {
   // rows run together, and so how well the gathered panel rows are reused in
   // the L2 and the last-level cache).  Candidates: the default (contiguous
   // chunks over spmm_nwg workgroups, which balances power-law row lengths)
-  // and XCD slabs over the resident workgroup count R and 2R (each XCD walks
-  // its own slab in a narrow sliding window, which suits community-ordered
-  // graphs).  Each is timed on the launch `a` describes (one warm-up and two
+  // and XCD slabs over R/4, R/2, R and 2R workgroups, R the resident count
+  // (each XCD walks its own slab in a narrow sliding window, which suits
+  // community-ordered graphs).  Each is timed on the launch `a` describes (one warm-up and two
   // timed launches; `a.y` must be a panel the caller overwrites afterwards)
   // and the fastest kept, a non-default only when 3% faster.  The choice is
   // kept per index and variant, and per process for the graph's shape.  It
@@ -2406,13 +2413,18 @@ struct Launcher {
     HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, WG, shm));
     HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, D->device));
     const int R = std::max(1, per_cu) * std::max(1, cus);
-    const int32_t cand[3] = {walk_pack(tu.xcd, tu.spmm_nwg), walk_pack(1, std::min(R, 65536)),
-                             walk_pack(1, std::min(2 * R, 65536))};
-    float ms[3] = {0.f, 0.f, 0.f};
+    // XCD slabs over R/4 .. 2R workgroups: fewer workgroups per XCD narrow
+    // the window of rows it works on at once (less reuse lost to eviction),
+    // more of them keep more gathers in flight
+    constexpr int kCand = 5;
+    const int32_t cand[kCand] = {walk_pack(tu.xcd, tu.spmm_nwg), walk_pack(1, std::max(8, R / 4)),
+                                 walk_pack(1, std::max(8, R / 2)), walk_pack(1, std::min(R, 65536)),
+                                 walk_pack(1, std::min(2 * R, 65536))};
+    float ms[kCand] = {0.f, 0.f, 0.f, 0.f, 0.f};
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
-    for (int c = 0; c < 3; c++) {
+    for (int c = 0; c < kCand; c++) {
       spmm_shape(a, v, cand[c], g, shm);
       v.fn<<<g, WG, shm, st>>>(a);
       HIPCHECK(hipEventRecord(e0, st));
@@ -2425,12 +2437,13 @@ struct Launcher {
     HIPCHECK(hipEventDestroy(e1));
     HIPCHECK(hipGetLastError());
     int best = 0;
-    for (int c = 1; c < 3; c++)
+    for (int c = 1; c < kCand; c++)
       if (ms[c] < 0.97f * ms[best]) best = c;
     if (getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 0)
       fprintf(stderr, "[katz] SpMM walk, variant %d, rows %d..%d, B %d: default %.3f ms, xcd slabs x%d %.3f ms, "
-                      "x%d %.3f ms -> %s\n", v.slot, a.row0, a.row1, B, ms[0] / 2, R, ms[1] / 2, 2 * R, ms[2] / 2,
-              best == 0 ? "default" : (best == 1 ? "xcd slabs R" : "xcd slabs 2R"));
+                      "x%d %.3f ms, x%d %.3f ms, x%d %.3f ms -> candidate %d\n", v.slot, a.row0, a.row1, B,
+              ms[0] / 2, walk_nwg(cand[1]), ms[1] / 2, walk_nwg(cand[2]), ms[2] / 2, walk_nwg(cand[3]), ms[3] / 2,
+              walk_nwg(cand[4]), ms[4] / 2, best);
     cache[key] = cand[best];
     D->walk[v.slot].store(cand[best], std::memory_order_release);
   }
@@ -3529,27 +3542,101 @@ __global__ __launch_bounds__(WG) void k_sparse_rerank(const double* kt, const in
   }
 }
 
+// Bump allocation over [base, base + cap) at 256-byte alignment; with
+// base == nullptr it only counts.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+// A device buffer of at least `bytes` from the index's reusable pool (the
+// smallest free one that fits, else a new one); give it back with aux_give.
+static std::pair<void*, size_t> aux_take(DeviceIndex* D, size_t bytes) {
+  {
+    std::lock_guard<std::mutex> g(D->aux_mu);
+    int best = -1;
+    for (size_t i = 0; i < D->aux_free.size(); i++)
+      if (D->aux_free[i].second >= bytes && (best < 0 || D->aux_free[i].second < D->aux_free[best].second))
+        best = (int)i;
+    if (best >= 0) {
+      auto r = D->aux_free[best];
+      D->aux_free.erase(D->aux_free.begin() + best);
+      return r;
+    }
+  }
+  std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
+  void* p = nullptr;
+  const hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+  if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? KATZ_ENOMEM : KATZ_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return {p, std::max<size_t>(bytes, 256)};
+}
+static void aux_give(DeviceIndex* D, std::pair<void*, size_t> b) {
+  std::lock_guard<std::mutex> g(D->aux_mu);
+  if (D->aux_free.size() >= 4) {
+    // keep the pool small: drop the smallest buffer
+    size_t small = 0;
+    for (size_t i = 1; i < D->aux_free.size(); i++)
+      if (D->aux_free[i].second < D->aux_free[small].second) small = i;
+    if (D->aux_free[small].second < b.second) {
+      std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
+      (void)hipFree(D->aux_free[small].first);
+      D->aux_free[small] = b;
+      return;
+    }
+    std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
+    (void)hipFree(b.first);
+    return;
+  }
+  D->aux_free.push_back(b);
+}
+
 // Solves the modular nodes' Katz vectors (the distinct sources q_src, as one
 // batched query with pair gathers K[row, q_src[col]] into a device buffer),
-// then re-ranks on the device (k_sparse_rerank).  Returns the status of the
-// solves; pst receives their stats.
+// then re-ranks on the device (k_sparse_rerank) and copies the lists to the
+// caller.  The buffers come from the index's reusable pool.  Returns the
+// status of the solves; pst receives their stats.
 int device_sparse_katz(const HostIndex& H, DeviceIndex* D, const katz_query_opts& opts, void* stream,
                        const std::vector<int32_t>& q_src, const std::vector<int32_t>& pcol,
                        const std::vector<int32_t>& prow, const std::vector<int32_t>& inv,
                        const std::vector<int64_t>& base, const std::vector<int32_t>& ncand,
                        const std::vector<int32_t>& nmod, const std::vector<int32_t>& cand, int nq, int s,
                        katz_query_stats* pst, int32_t* ids, double* corr) {
+  if (s > kRerankMax) fail(KATZ_EINVAL, "Sparse-Katz list longer than 4096");
   HIPCHECK(hipSetDevice(D->device));
-  std::vector<void*> tmp;
-  struct Free {
-    std::vector<void*>& t;
-    ~Free() {
-      std::lock_guard<std::recursive_mutex> g(hip_global_mu());
-      for (void* p : t) (void)hipFree(p);
-    }
-  } fr{tmp};
+  hipStream_t st = (hipStream_t)stream;
   const int64_t np = (int64_t)pcol.size();
-  double* kt = dalloc<double>(tmp, std::max<int64_t>(1, np));
+  // one buffer: K_T entries, their positions, per-request sizes, candidates, outputs
+  Carve lay{nullptr};
+  lay.take<double>(np);
+  lay.take<int32_t>(np);
+  lay.take<int64_t>(nq);
+  lay.take<int32_t>(nq);
+  lay.take<int32_t>(nq);
+  lay.take<int32_t>((int64_t)nq * s);
+  lay.take<int32_t>((int64_t)nq * s);
+  lay.take<double>((int64_t)nq * s);
+  auto buf = aux_take(D, lay.off);
+  struct Give {
+    DeviceIndex* D;
+    std::pair<void*, size_t> b;
+    ~Give() { aux_give(D, b); }
+  } give{D, buf};
+  Carve c{(char*)buf.first};
+  double* kt = c.take<double>(np);
+  int32_t* d_inv = c.take<int32_t>(np);
+  int64_t* d_base = c.take<int64_t>(nq);
+  int32_t* d_nc = c.take<int32_t>(nq);
+  int32_t* d_nm = c.take<int32_t>(nq);
+  int32_t* d_cand = c.take<int32_t>((int64_t)nq * s);
+  int32_t* d_ids = c.take<int32_t>((int64_t)nq * s);
+  double* d_corr = c.take<double>((int64_t)nq * s);
   int rc = KATZ_OK;
   if (np > 0) {
     QueryArgs a{};
@@ -3558,43 +3645,20 @@ int device_sparse_katz(const HostIndex& H, DeviceIndex* D, const katz_query_opts
     a.npairs = (int32_t)np; a.pair_col = pcol.data(); a.pair_row = prow.data(); a.pair_out = kt;
     rc = device_query(H, D, a);
   }
-  device_sparse_rerank(D->device, nq, s, kt, inv, base, ncand, nmod, cand, ids, corr, stream);
-  return rc;
-}
-
-void device_sparse_rerank(int device, int nq, int s, const double* kt_dev, const std::vector<int32_t>& inv,
-                          const std::vector<int64_t>& base, const std::vector<int32_t>& ncand,
-                          const std::vector<int32_t>& nmod, const std::vector<int32_t>& cand, int32_t* ids,
-                          double* corr, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  if (s > kRerankMax) fail(KATZ_EINVAL, "Sparse-Katz list longer than 4096");
-  HIPCHECK(hipSetDevice(device));
-  std::vector<void*> tmp;
-  struct Free {
-    std::vector<void*>& t;
-    ~Free() {
-      std::lock_guard<std::recursive_mutex> g(hip_global_mu());
-      for (void* p : t) (void)hipFree(p);
-    }
-  } fr{tmp};
-  auto up = [&](const auto& v) {
-    typedef typename std::decay<decltype(v[0])>::type E;
-    E* d = dalloc<E>(tmp, (int64_t)std::max<size_t>(1, v.size()));
-    if (!v.empty()) HIPCHECK(hipMemcpyAsync(d, v.data(), sizeof(E) * v.size(), hipMemcpyHostToDevice, st));
-    return d;
+  auto up = [&](void* d, const void* h, size_t bytes) {
+    if (bytes) HIPCHECK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st));
   };
-  const int32_t* d_inv = up(inv);
-  const int64_t* d_base = up(base);
-  const int32_t* d_nc = up(ncand);
-  const int32_t* d_nm = up(nmod);
-  const int32_t* d_cand = up(cand);
-  int32_t* d_ids = dalloc<int32_t>(tmp, (int64_t)nq * s);
-  double* d_corr = dalloc<double>(tmp, (int64_t)nq * s);
-  k_sparse_rerank<<<nq, WG, 0, st>>>(kt_dev, d_inv, d_base, d_nc, d_nm, d_cand, s, d_ids, d_corr);
+  up(d_inv, inv.data(), sizeof(int32_t) * inv.size());
+  up(d_base, base.data(), sizeof(int64_t) * base.size());
+  up(d_nc, ncand.data(), sizeof(int32_t) * ncand.size());
+  up(d_nm, nmod.data(), sizeof(int32_t) * nmod.size());
+  up(d_cand, cand.data(), sizeof(int32_t) * cand.size());
+  k_sparse_rerank<<<nq, WG, 0, st>>>(kt, d_inv, d_base, d_nc, d_nm, d_cand, s, d_ids, d_corr);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipMemcpyAsync(ids, d_ids, sizeof(int32_t) * (size_t)nq * s, hipMemcpyDefault, st));
   if (corr) HIPCHECK(hipMemcpyAsync(corr, d_corr, sizeof(double) * (size_t)nq * s, hipMemcpyDefault, st));
   HIPCHECK(hipStreamSynchronize(st));
+  return rc;
 }
 
 // ------------------------------------------------ queries without allocation
@@ -3632,20 +3696,6 @@ NoAllocSlot& noalloc_slot(int device) {
   }
   return sl;
 }
-
-// Bump allocation over [base, base + cap) at 256-byte alignment; with
-// base == nullptr it only counts.
-struct Carve {
-  char* base;
-  size_t off = 0;
-  template <typename T>
-  T* take(int64_t count) {
-    off = (off + 255) & ~(size_t)255;
-    T* p = base ? (T*)(base + off) : nullptr;
-    off += (size_t)std::max<int64_t>(count, 1) * sizeof(T);
-    return p;
-  }
-};
 
 // Lays a B-column workspace (the buffers run_batch uses: panels, partial
 // sums, low-rank terms, per-column scalars and state) over `base`; returns
@@ -3688,6 +3738,8 @@ size_t carve_ws(const DeviceIndex* D, int B, char* base, Workspace* w) {
 }  // namespace
 
 int device_query_noalloc(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa) {
+  if (qa.opts.method == KATZ_METHOD_PCGNR)
+    fail(KATZ_EINVAL, "the PCGNR ablation is not available without allocation");
   HIPCHECK(hipSetDevice(D->device));
   NoAllocSlot& sl = noalloc_slot(D->device);
   // columns that fit: the layout is affine in B

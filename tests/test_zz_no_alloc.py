@@ -3,7 +3,7 @@ scratch, no allocation) against katz_query on the same index and inputs,
 through the C ABI: two calls in a row, the second with a smaller input, on
 two indexes of different sizes (so the scratch layout changes between
 calls), device and host output, both methods, and the rejection of an index
-too large for the scratch.  GPU only."""
+too large for the scratch and of the PCGNR ablation.  GPU only."""
 import numpy as np
 import pytest
 
@@ -53,6 +53,10 @@ def test_noalloc_matches_query_sbm2k():
     for j in range(len(qs)):
         assert _close(got[j], ref["k_direct"][:, j], tau)
     _two_calls(g, idx, c, tau, (5, 2), 41, method=K.KATZ_METHOD_CG, host=True)
+    # the PCGNR ablation needs buffers beyond the scratch layout: refused
+    with pytest.raises(K.KatzError) as e:
+        idx.query_noalloc(qs, out=np.empty((len(qs), g.n)), method=K.KATZ_METHOD_PCGNR)
+    assert e.value.code == K.KATZ_EINVAL and "PCGNR" in str(e.value)
     idx.close()
 
 
