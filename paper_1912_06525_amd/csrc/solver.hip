@@ -504,6 +504,31 @@ __global__ __launch_bounds__(WG) void k_update_r(int64_t m, int B, int rows_per_
   wg_colsum(cm, B, dacc, partials);
 }
 
+// Wave sums of R per-lane values (R a power of two, at most 64) by halving
+// exchanges: at each step a lane keeps one half of its remaining values (the
+// half picked by its lane bit O), adds the partner's copy of that half and
+// hands the other half over, so R - 1 exchanges (plus log2(64 / R) for the
+// last value) replace the 6 R of one butterfly per value.  On return a[0] of
+// lane l holds the wave sum of value l / (64 / R).  The order is fixed, so the
+// sums are deterministic.
+template <int C, int R>
+__device__ inline void wave_sum_spread(double (&a)[R], int lane) {
+  if constexpr (C > 1) {
+    constexpr int H = C / 2, O = 64 * H / R;
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int h = 0; h < H; h++) {
+      const double send = up ? a[h] : a[h + H];
+      const double keep = up ? a[h + H] : a[h];
+      a[h] = keep + __shfl_xor(send, O, 64);
+    }
+    wave_sum_spread<H, R>(a, lane);
+  } else {
+#pragma unroll
+    for (int o = 32 / R; o > 0; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
+  }
+}
+
 // One column (B = 1): x += alpha p; r -= alpha q; then, in the same pass,
 // the partial sums of V^T r (rank values, registers) and <r, r>; partials
 // per workgroup: [W_0 .. W_{rank-1}, rr].  Finalized by EP_RR_VT.
@@ -532,15 +557,15 @@ __global__ __launch_bounds__(WG) void k_update_r_vt1(int64_t m, int rows_per_wg,
     for (int k = 0; k < RMAX; k++) acc[k] += to_d(vv[k]) * rd;
   }
   const int wave = tid / 64, lane = tid % 64;
+  double rr = acc[RMAX];
 #pragma unroll
-  for (int k = 0; k <= RMAX; k++) {
-    if (k < rank || k == RMAX) {
-      double v = acc[k];
+  for (int off = 32; off > 0; off >>= 1) rr += __shfl_xor(rr, off, 64);
+  if (lane == 0) sh[wave * (RMAX + 1) + RMAX] = rr;
+  double vs[RMAX];
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0) sh[wave * (RMAX + 1) + k] = v;
-    }
-  }
+  for (int k = 0; k < RMAX; k++) vs[k] = acc[k];
+  wave_sum_spread<RMAX, RMAX>(vs, lane);
+  if (lane % (64 / RMAX) == 0) sh[wave * (RMAX + 1) + lane / (64 / RMAX)] = vs[0];
   __syncthreads();
   if (tid <= rank) {
     const int k = tid < rank ? tid : RMAX;
@@ -904,7 +929,27 @@ __global__ __launch_bounds__(WG) void k_vt(int64_t m, int B, int rank, const TV*
 
 // W = V^T r for one column (B = 1): each thread owns rows and keeps the rank
 // sums in registers (compile-time indexed), reduced by wave shuffles and LDS.
-template <typename T, typename TV, int RMAX>
+// One row of a row-major BF16 factor with RMAX columns (RMAX * 2 bytes, 16-byte
+// aligned) in 16-byte loads, as floats (a BF16 value is the top half of its
+// float).
+template <int RMAX>
+__device__ inline void load_vrow(const bf16* Vr, int64_t i, float (&v)[RMAX]) {
+  const uint4* p = reinterpret_cast<const uint4*>(Vr + i * RMAX);
+#pragma unroll
+  for (int c = 0; c < RMAX / 8; c++) {
+    const uint4 u = p[c];
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+      v[8 * c + 2 * h] = __uint_as_float(w[h] << 16);
+      v[8 * c + 2 * h + 1] = __uint_as_float(w[h] & 0xFFFF0000u);
+    }
+  }
+}
+
+// VR: V is the row-major BF16 copy with exactly RMAX columns (rank == RMAX),
+// read one 16-byte vector at a time instead of one 2-byte load per column.
+template <typename T, typename TV, int RMAX, bool VR = false>
 __global__ __launch_bounds__(WG) void k_vt1(int64_t m, int rank, const TV* V, const T* r, int rows_per_wg,
                                             double* partials, const int* n_active) {
   if (n_active && *n_active == 0) return;
@@ -918,24 +963,27 @@ __global__ __launch_bounds__(WG) void k_vt1(int64_t m, int rank, const TV* V, co
     // all factor loads first, unconditionally (columns past the rank repeat
     // the last one and their sums are never used), so they are in flight
     // together instead of one latency each
-    TV vv[RMAX];
+    double vd[RMAX];
+    if constexpr (VR) {
+      float vf[RMAX];
+      load_vrow<RMAX>((const bf16*)V, i, vf);
 #pragma unroll
-    for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+      for (int k = 0; k < RMAX; k++) vd[k] = (double)vf[k];
+    } else {
+      TV vv[RMAX];
+#pragma unroll
+      for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+#pragma unroll
+      for (int k = 0; k < RMAX; k++) vd[k] = to_d(vv[k]);
+    }
     const double rv = (double)r[i];
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the FMAs
 #pragma unroll
-    for (int k = 0; k < RMAX; k++) acc[k] += to_d(vv[k]) * rv;
+    for (int k = 0; k < RMAX; k++) acc[k] += vd[k] * rv;
   }
   const int wave = tid / 64, lane = tid % 64;
-#pragma unroll
-  for (int k = 0; k < RMAX; k++) {
-    if (k < rank) {
-      double v = acc[k];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0) sh[wave * RMAX + k] = v;
-    }
-  }
+  wave_sum_spread<RMAX, RMAX>(acc, lane);  // sums past the rank are never read
+  if (lane % (64 / RMAX) == 0) sh[wave * RMAX + lane / (64 / RMAX)] = acc[0];
   __syncthreads();
   if (tid < rank) {
     double s = 0.0;
@@ -975,7 +1023,7 @@ __global__ __launch_bounds__(WG) void k_lowrank(int64_t m, int B, int rank, cons
 // PUPD: z is not stored; the search direction is updated in place instead,
 // z[i] <- z_new + b z[i] (z holds p; b = bcg, 0 at init), when the column is
 // active, and no partials are written.
-template <typename T, typename TV, int RMAX, bool PUPD = false>
+template <typename T, typename TV, int RMAX, bool PUPD = false, bool VR = false>
 __global__ __launch_bounds__(WG) void k_lowrank1(int64_t m, int rank, const TV* V, const double* DW, const T* r,
                                                  T* z, int z_has_base, int rows_per_wg, const int* n_active,
                                                  double* partials, const double* bcg = nullptr,
@@ -989,14 +1037,24 @@ __global__ __launch_bounds__(WG) void k_lowrank1(int64_t m, int rank, const TV* 
   double dacc[1] = {0.0};
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(m, r0 + rows_per_wg);
   for (int64_t i = r0 + threadIdx.x; i < r1; i += WG) {
-    TV vv[RMAX];
+    double vd[RMAX];
+    if constexpr (VR) {
+      float vf[RMAX];
+      load_vrow<RMAX>((const bf16*)V, i, vf);
 #pragma unroll
-    for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+      for (int k = 0; k < RMAX; k++) vd[k] = (double)vf[k];
+    } else {
+      TV vv[RMAX];
+#pragma unroll
+      for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+#pragma unroll
+      for (int k = 0; k < RMAX; k++) vd[k] = to_d(vv[k]);
+    }
     const double rv = (double)r[i];
     const double pv = PUPD && !init ? (double)z[i] : 0.0;
     double s = !PUPD && z_has_base ? (double)z[i] : rv;
 #pragma unroll
-    for (int k = 0; k < RMAX; k++) s += to_d(vv[k]) * dw[k];
+    for (int k = 0; k < RMAX; k++) s += vd[k] * dw[k];
     if (PUPD) {
       z[i] = (T)(s + b * pv);
     } else {
@@ -1645,6 +1703,7 @@ struct Tuning {
   int graphs;       // replay captured iteration chunks as HIP graphs
   int fuse;         // one-column residual update fused with V^T r
   int lr_nwg;       // max workgroups of the one-column low-rank kernels
+  int vrow;         // one-column low-rank kernels read the row-major BF16 factor
   int m11_bpt;      // blocks per team and chunk of the batched small-block solve
   int autotune;     // tune the SpMM chunk walk per index (off when pinned by the environment)
   int m11_sub1;     // lanes per row of the A12 gather in the 1-3 column block solve
@@ -1670,6 +1729,7 @@ static const Tuning& tuning() {
     u.graphs = env_int("KATZ_GRAPHS", 1, 0, 1);
     u.fuse = env_int("KATZ_FUSE", 0, 0, 1);
     u.lr_nwg = env_int("KATZ_LR_NWG", 512, 64, 65536);
+    u.vrow = env_int("KATZ_VROW", 1, 0, 1);
     u.m11_bpt = env_int("KATZ_M11_BLOCKS_PER_TEAM", 1, 1, 64);
     u.autotune = env_int("KATZ_AUTOTUNE", 1, 0, 1) && !getenv("KATZ_XCD_SLAB") && !getenv("KATZ_SPMM_NWG");
     u.m11_sub1 = env_int("KATZ_M11_SUB", 4, 1, 16);
@@ -1867,6 +1927,12 @@ static void upload_factors(const HostIndex& H, DeviceIndex* D) {
     std::vector<uint16_t> vb(vc.size());
     for (size_t t = 0; t < vc.size(); t++) vb[t] = bf16_bits((float)vc[t]);
     D->V16 = (bf16*)upload(D->allocs, vb, by);
+    // the row-major copy for the one-column kernels (16-byte row loads)
+    if (H.rank == 8 || H.rank == 16 || H.rank == 32 || H.rank == 64) {
+      std::vector<uint16_t> vr(vc.size());
+      for (size_t t = 0; t < vc.size(); t++) vr[t] = bf16_bits((float)H.V[t]);
+      D->V16r = (bf16*)upload(D->allocs, vr, by);
+    }
   } else if (H.precision == KATZ_PREC_FP64) {
     D->V = upload(D->allocs, vc, by);
   }
@@ -2658,6 +2724,51 @@ static int64_t lowrank_rows_rpc(const DeviceIndex* D, int64_t m, bool direct) {
 // Preconditioner for B >= 2 columns and rank <= 64 with the row-blocked
 // kernels: DW = D o (V^T r) (chunk partials, then a many-workgroup fixed-order
 // reduction), then z = base + V DW with the <r, z> partials and finalize.
+// The row-major BF16 factor for the one-column kernels, when V is the BF16
+// factor and the index holds a row-major copy of it (rank 8, 16, 32 or 64).
+template <typename TV>
+static const bf16* vrow_factor(const DeviceIndex* D, const TV* V) {
+  if (!std::is_same<TV, bf16>::value || !tuning().vrow || !D->V16r || (const void*)V != (const void*)D->V16)
+    return nullptr;
+  const int rk = D->rank;
+  return (rk == 8 || rk == 16 || rk == 32 || rk == 64) ? D->V16r : nullptr;
+}
+
+// k_vt1 / k_lowrank1 over the row-major BF16 factor (RMAX = rank).
+template <typename T>
+static void vt1_vrow(hipStream_t st, int nwg, int64_t m, int rk, const bf16* Vr, const T* R2, int rpw,
+                     double* partials, const int* nact) {
+  switch (rk) {
+    case 8: k_vt1<T, bf16, 8, true><<<nwg, WG, 0, st>>>(m, rk, Vr, R2, rpw, partials, nact); break;
+    case 16: k_vt1<T, bf16, 16, true><<<nwg, WG, 0, st>>>(m, rk, Vr, R2, rpw, partials, nact); break;
+    case 32: k_vt1<T, bf16, 32, true><<<nwg, WG, 0, st>>>(m, rk, Vr, R2, rpw, partials, nact); break;
+    default: k_vt1<T, bf16, 64, true><<<nwg, WG, 0, st>>>(m, rk, Vr, R2, rpw, partials, nact); break;
+  }
+}
+template <typename T, bool PUPD>
+static void lowrank1_vrow(hipStream_t st, int nwg, size_t shm, int64_t m, int rk, const bf16* Vr, const double* DW,
+                          const T* R2, T* Z2, int has_base, int rpw, const int* nact, double* partials,
+                          const double* bcg, const int* active, int init) {
+  switch (rk) {
+    case 8:
+      k_lowrank1<T, bf16, 8, PUPD, true><<<nwg, WG, shm, st>>>(m, rk, Vr, DW, R2, Z2, has_base, rpw, nact,
+                                                               partials, bcg, active, init);
+      break;
+    case 16:
+      k_lowrank1<T, bf16, 16, PUPD, true><<<nwg, WG, shm, st>>>(m, rk, Vr, DW, R2, Z2, has_base, rpw, nact,
+                                                                partials, bcg, active, init);
+      break;
+    case 32:
+      k_lowrank1<T, bf16, 32, PUPD, true><<<nwg, WG, shm, st>>>(m, rk, Vr, DW, R2, Z2, has_base, rpw, nact,
+                                                                partials, bcg, active, init);
+      break;
+    default:
+      k_lowrank1<T, bf16, 64, PUPD, true><<<nwg, WG, shm, st>>>(m, rk, Vr, DW, R2, Z2, has_base, rpw, nact,
+                                                                partials, bcg, active, init);
+      break;
+  }
+}
+
 template <typename T, typename TV>
 static void precond_rows(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, const ColState& cs,
                          const int* nact) {
@@ -2713,9 +2824,11 @@ static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep,
     nwg = Launcher::nwg_for(m, rpw);
     L.need(nwg, std::max(1, rk));
   }
+  const bf16* Vr = B == 1 ? vrow_factor(D, V) : nullptr;
   if (rk > 0 && !dw_ready) {
     L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
-      if (B == 1 && rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+      if (Vr) vt1_vrow<T>(st, nwg, m, rk, Vr, R2, rpw, w->partials, nact);
+      else if (B == 1 && rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
       else if (B == 1 && rk <= 16) k_vt1<T, TV, 16><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
       else if (B == 1 && rk <= 32) k_vt1<T, TV, 32><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
       else if (B == 1 && rk <= 64) k_vt1<T, TV, 64><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
@@ -2732,7 +2845,10 @@ static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep,
   }
   L.timed(PK_LOWRANK, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m * (2 + has_base), [&] {
     const size_t shm = WG * sizeof(double);
-    if (B == 1 && rk >= 1 && rk <= 8)
+    if (Vr)
+      lowrank1_vrow<T, false>(st, nwg, shm, m, rk, Vr, w->DW, R2, Z2, has_base, rpw, nact, w->partials, nullptr,
+                              nullptr, 0);
+    else if (B == 1 && rk >= 1 && rk <= 8)
       k_lowrank1<T, TV, 8><<<nwg, WG, shm, st>>>(m, rk, V, w->DW, R2, Z2, has_base, rpw, nact, w->partials);
     else if (B == 1 && rk >= 1 && rk <= 16)
       k_lowrank1<T, TV, 16><<<nwg, WG, shm, st>>>(m, rk, V, w->DW, R2, Z2, has_base, rpw, nact, w->partials);
@@ -2765,15 +2881,19 @@ static void precond_fused(Launcher& L, const TV* V, const T* R2, T* P2, int init
     const int64_t want = std::max<int64_t>(1, std::min<int64_t>(tuning().lr_nwg, (m + 63) / 64));
     const int rpw = (int)((m + want - 1) / want), nwg = Launcher::nwg_for(m, rpw);
     L.need(nwg, rk);
+    const bf16* Vr = vrow_factor(D, V);
     L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * m, [&] {
-      if (rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
+      if (Vr) vt1_vrow<T>(st, nwg, m, rk, Vr, R2, rpw, w->partials, nact);
+      else if (rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
       else if (rk <= 16) k_vt1<T, TV, 16><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
       else if (rk <= 32) k_vt1<T, TV, 32><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
       else k_vt1<T, TV, 64><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
     });
     L.finalize(nwg, rk, EP_VT, cs, w->DW, nact, w->DW2, init ? 2 : 1);  // with <r, z> and the step
     L.timed(PK_LOWRANK, pbytes, [&] {
-      if (rk <= 8)
+      if (Vr)
+        lowrank1_vrow<T, true>(st, nwg, 0, m, rk, Vr, w->DW, R2, P2, 0, rpw, nact, nullptr, cs.bcg, cs.active, init);
+      else if (rk <= 8)
         k_lowrank1<T, TV, 8, true><<<nwg, WG, 0, st>>>(m, rk, V, w->DW, R2, P2, 0, rpw, nact, nullptr, cs.bcg,
                                                          cs.active, init);
       else if (rk <= 16)

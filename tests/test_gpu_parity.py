@@ -545,3 +545,46 @@ def test_results_independent_of_chunk_walk(tmp_path):
     for t in range(1, len(walks)):
         for k in res[0].files:
             assert np.array_equal(res[0][k], res[t][k]), (walks[t], k)
+
+
+_VROW_SCRIPT = r"""
+import sys, numpy as np
+sys.path.insert(0, sys.argv[2])
+import katz_inputs as ki, paper_1912_06525_amd as K
+g = ki.workload("lnsbm4m", scale=0.004).graph
+out = {}
+for prec, up, rank in ((K.KATZ_PREC_FP64, 3, 16), (K.KATZ_PREC_FP64, 3, 32), (K.KATZ_PREC_MIXED, 0, 8),
+                       (K.KATZ_PREC_FP64, 3, 20)):
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.9, rank=rank, labels=g.labels, max_block=32, precision=prec,
+                                 u_precision=up)
+    qs = ki.sample_queries(g, 6, 7 + rank)
+    for j, q in enumerate(qs):
+        sc, st = idx.query([q], tol=1e-8)
+        out["p%d_r%d_q%d" % (prec, rank, j)] = sc
+        out["p%d_r%d_q%d_it" % (prec, rank, j)] = np.array([st[0]["iters"], st[0]["sweeps"]])
+    idx.close()
+np.savez(sys.argv[1], **out)
+"""
+
+
+def test_row_major_factor_gives_identical_results(tmp_path):
+    """One-column solves read the BF16 low-rank factor from a row-major copy
+    (16-byte row loads) when the rank is 8, 16, 32 or 64; the column-major
+    reads (KATZ_VROW=0) take the same values in the same order, so scores and
+    iteration counts must be bit-identical.  Rank 20 has no row-major copy
+    and checks the fallback.  Each setting runs in a child process."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = []
+    for t, vrow in enumerate(("1", "0")):
+        env = dict(os.environ)
+        env["KATZ_VROW"] = vrow
+        f = str(tmp_path / ("vrow%d.npz" % t))
+        print("KATZ_VROW", vrow, flush=True)
+        subprocess.run([sys.executable, "-c", _VROW_SCRIPT, f, root], env=env, check=True, timeout=300)
+        res.append(np.load(f))
+    assert res[0].files == res[1].files
+    for k in res[0].files:
+        assert np.array_equal(res[0][k], res[1][k]), k
