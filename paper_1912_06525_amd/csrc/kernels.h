@@ -90,6 +90,20 @@ __device__ inline void final_reduce(const double* partials, int nwg, int nv, F&&
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (v < nv) {
       int w = wl;
+      // 16 loads in flight per lane (the partials come from other XCDs' L2s,
+      // so each round trip is long), combined in a fixed order
+      for (; w + 15 * WR < nwg; w += 16 * WR) {
+        double t[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) t[u] = partials[(int64_t)(w + u * WR) * nv + v];
+#pragma unroll
+        for (int u = 0; u < 16; u += 4) {
+          s0 += t[u];
+          s1 += t[u + 1];
+          s2 += t[u + 2];
+          s3 += t[u + 3];
+        }
+      }
       for (; w + 3 * WR < nwg; w += 4 * WR) {
         s0 += partials[(int64_t)w * nv + v];
         s1 += partials[(int64_t)(w + WR) * nv + v];

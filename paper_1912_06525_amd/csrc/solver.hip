@@ -504,6 +504,24 @@ __global__ __launch_bounds__(WG) void k_update_r(int64_t m, int B, int rows_per_
   wg_colsum(cm, B, dacc, partials);
 }
 
+// One row of a row-major BF16 factor with RMAX columns (RMAX * 2 bytes, 16-byte
+// aligned) in 16-byte loads, as floats (a BF16 value is the top half of its
+// float).
+template <int RMAX>
+__device__ inline void load_vrow(const bf16* Vr, int64_t i, float (&v)[RMAX]) {
+  const uint4* p = reinterpret_cast<const uint4*>(Vr + i * RMAX);
+#pragma unroll
+  for (int c = 0; c < RMAX / 8; c++) {
+    const uint4 u = p[c];
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+      v[8 * c + 2 * h] = __uint_as_float(w[h] << 16);
+      v[8 * c + 2 * h + 1] = __uint_as_float(w[h] & 0xFFFF0000u);
+    }
+  }
+}
+
 // Wave sums of R per-lane values (R a power of two, at most 64) by halving
 // exchanges: at each step a lane keeps one half of its remaining values (the
 // half picked by its lane bit O), adds the partner's copy of that half and
@@ -532,7 +550,8 @@ __device__ inline void wave_sum_spread(double (&a)[R], int lane) {
 // One column (B = 1): x += alpha p; r -= alpha q; then, in the same pass,
 // the partial sums of V^T r (rank values, registers) and <r, r>; partials
 // per workgroup: [W_0 .. W_{rank-1}, rr].  Finalized by EP_RR_VT.
-template <typename T, typename TV, int RMAX>
+// VR: V is the row-major BF16 copy with rank == RMAX (16-byte row loads).
+template <typename T, typename TV, int RMAX, bool VR = false>
 __global__ __launch_bounds__(WG) void k_update_r_vt1(int64_t m, int rows_per_wg, T* x, const T* p, T* r,
                                                      const T* q, int rank, const TV* V, ColState cs,
                                                      double* partials) {
@@ -545,16 +564,28 @@ __global__ __launch_bounds__(WG) void k_update_r_vt1(int64_t m, int rows_per_wg,
 #pragma unroll
   for (int k = 0; k <= RMAX; k++) acc[k] = 0.0;
   for (int64_t i = r0 + tid; i < r1; i += WG) {
-    x[i] += al * p[i];
-    const T rv = r[i] - al * q[i];
+    // the factor row first (it does not depend on the update), then the update
+    double vd[RMAX];
+    if constexpr (VR) {
+      float vf[RMAX];
+      load_vrow<RMAX>((const bf16*)V, i, vf);
+#pragma unroll
+      for (int k = 0; k < RMAX; k++) vd[k] = (double)vf[k];
+    } else {
+      TV vv[RMAX];
+#pragma unroll
+      for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+#pragma unroll
+      for (int k = 0; k < RMAX; k++) vd[k] = to_d(vv[k]);
+    }
+    const T pv = p[i], qv = q[i], xv = x[i], r0v = r[i];
+    x[i] = xv + al * pv;
+    const T rv = r0v - al * qv;
     r[i] = rv;
     const double rd = (double)rv;
     acc[RMAX] += rd * rd;
-    TV vv[RMAX];
 #pragma unroll
-    for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
-#pragma unroll
-    for (int k = 0; k < RMAX; k++) acc[k] += to_d(vv[k]) * rd;
+    for (int k = 0; k < RMAX; k++) acc[k] += vd[k] * rd;
   }
   const int wave = tid / 64, lane = tid % 64;
   double rr = acc[RMAX];
@@ -929,24 +960,6 @@ __global__ __launch_bounds__(WG) void k_vt(int64_t m, int B, int rank, const TV*
 
 // W = V^T r for one column (B = 1): each thread owns rows and keeps the rank
 // sums in registers (compile-time indexed), reduced by wave shuffles and LDS.
-// One row of a row-major BF16 factor with RMAX columns (RMAX * 2 bytes, 16-byte
-// aligned) in 16-byte loads, as floats (a BF16 value is the top half of its
-// float).
-template <int RMAX>
-__device__ inline void load_vrow(const bf16* Vr, int64_t i, float (&v)[RMAX]) {
-  const uint4* p = reinterpret_cast<const uint4*>(Vr + i * RMAX);
-#pragma unroll
-  for (int c = 0; c < RMAX / 8; c++) {
-    const uint4 u = p[c];
-    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-    for (int h = 0; h < 4; h++) {
-      v[8 * c + 2 * h] = __uint_as_float(w[h] << 16);
-      v[8 * c + 2 * h + 1] = __uint_as_float(w[h] & 0xFFFF0000u);
-    }
-  }
-}
-
 // VR: V is the row-major BF16 copy with exactly RMAX columns (rank == RMAX),
 // read one 16-byte vector at a time instead of one 2-byte load per column.
 template <typename T, typename TV, int RMAX, bool VR = false>
@@ -1501,6 +1514,7 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int
       case EP_RR_VT:
         if (j < nv - 1) {
           out[j] = D[j] * s;  // DW (one column)
+          if (out2) out2[j] = D[j] * s * s;
           break;
         }
         j = 0;  // the last value is <r, r> of column 0
@@ -1544,6 +1558,11 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int
     // step: 1 = iteration, 2 = initial step
     __syncthreads();
     rz_from_terms(nv / B, B, out2, rz_mode == 2, cs);
+  }
+  if (ep == EP_RR_VT && rz_mode) {
+    // one column: the same from <r, r> (just stored) and the rank terms
+    __syncthreads();
+    rz_from_terms(nv - 1, 1, out2, 0, cs);
   }
 }
 
@@ -1727,7 +1746,7 @@ static const Tuning& tuning() {
     u.ew_rows = env_int("KATZ_EW_ROWS", 256, 16, 65536);
     u.xcd = env_int("KATZ_XCD_SLAB", 0, 0, 1);
     u.graphs = env_int("KATZ_GRAPHS", 1, 0, 1);
-    u.fuse = env_int("KATZ_FUSE", 0, 0, 1);
+    u.fuse = env_int("KATZ_FUSE", 1, 0, 1);
     u.lr_nwg = env_int("KATZ_LR_NWG", 512, 64, 65536);
     u.vrow = env_int("KATZ_VROW", 1, 0, 1);
     u.m11_bpt = env_int("KATZ_M11_BLOCKS_PER_TEAM", 1, 1, 64);
@@ -2928,24 +2947,57 @@ static void precond_fused(Launcher& L, const TV* V, const T* R2, T* P2, int init
   });
 }
 
-// x += alpha p; r -= alpha q with DW = D o (V^T r) and <r, r> in one pass and
-// one finalize (one column, rank <= 64).
+// One column, L = I, rank <= 64: x += alpha p; r -= alpha q with W = V^T r
+// and <r, r> in one pass; one finalize gives DW = D o W, the convergence test
+// and the PCG step (<r, z> = <r, r> + sum_k D_k W_k^2, bcg); then p = r +
+// V DW + bcg p in one pass.  Two launches and one finalize per iteration
+// fewer than update, V^T r and the fused apply as separate passes.
 template <typename T, typename TV>
-static void update_r_vt1(Launcher& L, const TV* V, T* x, const T* p, T* r, const T* q, const ColState& cs,
-                         int rpw, int nwg) {
+static void update_r_precond1(Launcher& L, const TV* V, T* x, T* p, T* r, const T* q, const ColState& cs) {
   DeviceIndex* D = L.D;
   Workspace* w = L.w;
   const int rk = D->rank;
   const int64_t m = D->n2;
   hipStream_t st = L.st;
+  const int64_t want = std::max<int64_t>(1, std::min<int64_t>(tuning().lr_nwg, (m + 63) / 64));
+  const int rpw = (int)((m + want - 1) / want), nwg = Launcher::nwg_for(m, rpw);
   L.need(nwg, rk + 1);
+  const bf16* Vr = vrow_factor(D, V);
   L.timed(PK_UPDATE_R, 6.0 * sizeof(T) * m + (double)sizeof(TV) * m * rk, [&] {
-    if (rk <= 8) k_update_r_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
-    else if (rk <= 16) k_update_r_vt1<T, TV, 16><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
-    else if (rk <= 32) k_update_r_vt1<T, TV, 32><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
-    else k_update_r_vt1<T, TV, 64><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
+    if (Vr) {
+      switch (rk) {
+        case 8: k_update_r_vt1<T, bf16, 8, true><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, Vr, cs, w->partials); break;
+        case 16: k_update_r_vt1<T, bf16, 16, true><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, Vr, cs, w->partials); break;
+        case 32: k_update_r_vt1<T, bf16, 32, true><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, Vr, cs, w->partials); break;
+        default: k_update_r_vt1<T, bf16, 64, true><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, Vr, cs, w->partials); break;
+      }
+    } else if (rk <= 8) {
+      k_update_r_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
+    } else if (rk <= 16) {
+      k_update_r_vt1<T, TV, 16><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
+    } else if (rk <= 32) {
+      k_update_r_vt1<T, TV, 32><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
+    } else {
+      k_update_r_vt1<T, TV, 64><<<nwg, WG, 0, st>>>(m, rpw, x, p, r, q, rk, V, cs, w->partials);
+    }
   });
-  L.finalize(nwg, rk + 1, EP_RR_VT, cs, w->DW, w->n_active);
+  L.finalize(nwg, rk + 1, EP_RR_VT, cs, w->DW, w->n_active, w->DW2, 1);
+  L.timed(PK_LOWRANK, (double)sizeof(TV) * m * rk + 3.0 * sizeof(T) * m, [&] {
+    if (Vr)
+      lowrank1_vrow<T, true>(st, nwg, 0, m, rk, Vr, w->DW, r, p, 0, rpw, w->n_active, nullptr, cs.bcg, cs.active, 0);
+    else if (rk <= 8)
+      k_lowrank1<T, TV, 8, true><<<nwg, WG, 0, st>>>(m, rk, V, w->DW, r, p, 0, rpw, w->n_active, nullptr, cs.bcg,
+                                                       cs.active, 0);
+    else if (rk <= 16)
+      k_lowrank1<T, TV, 16, true><<<nwg, WG, 0, st>>>(m, rk, V, w->DW, r, p, 0, rpw, w->n_active, nullptr, cs.bcg,
+                                                        cs.active, 0);
+    else if (rk <= 32)
+      k_lowrank1<T, TV, 32, true><<<nwg, WG, 0, st>>>(m, rk, V, w->DW, r, p, 0, rpw, w->n_active, nullptr, cs.bcg,
+                                                        cs.active, 0);
+    else
+      k_lowrank1<T, TV, 64, true><<<nwg, WG, 0, st>>>(m, rk, V, w->DW, r, p, 0, rpw, w->n_active, nullptr, cs.bcg,
+                                                        cs.active, 0);
+  });
 }
 
 // ============================================================ solve sweeps
@@ -3182,7 +3234,7 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
   // ---- a3: PCG iterations, polled every check_every
   const int rpw2 = L.rows_per_wg(n2), nwg2 = Launcher::nwg_for(n2, rpw2);
   L.need(nwg2, B);
-  const bool fuse_vt = B == 1 && D->rank > 0 && D->rank <= 64 && !D->ginv && tuning().fuse;
+  const bool fuse_vt = B == 1 && D->rank > 0 && D->rank <= 64 && !D->ginv && fuse_p && tuning().fuse;
   L.iterate(sizeof(T) == 8 ? 1 : 2, max_iter, check_every, [&] {
       m11(nullptr, (T)0, P2, beta, X, w->n_active);   // t1' = M11^{-1} (beta A12 p2)
       SpmmArgs<T> a{};
@@ -3192,23 +3244,18 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
       a.ep = EP_PQ; a.dotv = P2; a.cs = cs; a.n_active = w->n_active;
       L.spmm(a);
       if (fuse_vt) {
-        // one column: residual update and V^T r in one pass, then z = r + V DW
+        // one column: update and V^T r in one pass, then p = r + V DW + bcg p
         with_lowrank_factor<T>(D, [&](auto* V) {
           typedef typename std::remove_cv<typename std::remove_pointer<decltype(V)>::type>::type TV;
-          update_r_vt1<T, TV>(L, V, K2, P2, R2, Q2, cs, rpw2, nwg2);
-          precond_simple<T, TV>(L, V, R2, Z2, EP_RZ, cs, w->n_active, rpw2, nwg2, true);
+          update_r_precond1<T, TV>(L, V, K2, P2, R2, Q2, cs);
         });
-      } else {
-        L.timed_cols(PK_UPDATE_R, 6.0 * sizeof(T) * n2, [&] {
-          k_update_r<T><<<nwg2, WG, WG * sizeof(double), st>>>(n2, B, rpw2, K2, P2, R2, Q2, cs, w->partials);
-        });
-        L.finalize(nwg2, B, EP_RR, cs, nullptr, w->n_active);
-        precond_p(0);
         return;
       }
-      L.timed_cols(PK_UPDATE_P, 3.0 * sizeof(T) * n2, [&] {
-        k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, 0, cs);
+      L.timed_cols(PK_UPDATE_R, 6.0 * sizeof(T) * n2, [&] {
+        k_update_r<T><<<nwg2, WG, WG * sizeof(double), st>>>(n2, B, rpw2, K2, P2, R2, Q2, cs, w->partials);
       });
+      L.finalize(nwg2, B, EP_RR, cs, nullptr, w->n_active);
+      precond_p(0);
   });
   // ---- a4: k1 = M11^{-1} (b1 + beta A12 k2) -> Dx[0:n1]
   m11(rhs, (T)1, K2, beta, Dx, nullptr);
