@@ -91,8 +91,10 @@ __global__ void k_rhs_norm2(const int32_t* qpos, int B, const int32_t* rp, const
 // across columns and TS/CW across the row's entries (partials combined by
 // cross-lane shuffles).  Rows longer than long_thr (hubs) get a whole
 // workgroup each (the first n_long workgroups).  Optional per-column dot
-// <d, y> (d = dotv or y) with a last-workgroup epilogue.
-template <typename T>
+// <d, y> (d = dotv or y) with a last-workgroup epilogue.  TX: the element
+// type of x and w (FP32 for the precision form's residual update, whose sums
+// and output stay FP64).
+template <typename T, typename TX = T>
 struct SpmmArgs {
   int row0, row1, rows_per_wg;  // rows_per_wg = rows per chunk
   int64_t nchunks;              // short-row chunks
@@ -101,12 +103,12 @@ struct SpmmArgs {
   const int32_t* col;
   const int32_t* split;
   const double* val;
-  const T* x;
+  const TX* x;
   T ca, cb;
   int parts;  // bit 0: entries left of the split, bit 1: right of it
   const T* v;
   T cv;
-  const T* w;
+  const TX* w;
   T cw;
   T* y;
   int B;       // columns this launch computes
@@ -134,8 +136,8 @@ struct SpmmArgs {
 struct RowRange {
   int32_t kb, ke, sp, len;
 };
-template <typename T>
-__device__ inline RowRange row_range(const SpmmArgs<T>& a, int i) {
+template <typename T, typename TX>
+__device__ inline RowRange row_range(const SpmmArgs<T, TX>& a, int i) {
   RowRange r;
   const int32_t s = a.rp[i], e = a.rp[i + 1];
   r.len = e - s;
@@ -176,9 +178,9 @@ __device__ inline void row_gather(const Args& a, const RowRange& rr, int nz, int
     T xv[4][NCM];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      const T* xr = a.x + (int64_t)c[u] * a.ld + a.j0;
+      const auto* xr = a.x + (int64_t)c[u] * a.ld + a.j0;
 #pragma unroll
-      for (int cc = 0; cc < NCM; cc++) xv[u][cc] = xr[jc[cc]];
+      for (int cc = 0; cc < NCM; cc++) xv[u][cc] = (T)xr[jc[cc]];
     }
 #pragma unroll
     for (int u = 0; u < 4; u++) {
@@ -206,9 +208,9 @@ __device__ inline void row_gather(const Args& a, const RowRange& rr, int nz, int
     T xv[3][NCM];
 #pragma unroll
     for (int u = 0; u < 3; u++) {
-      const T* xr = a.x + (int64_t)c[u] * a.ld + a.j0;
+      const auto* xr = a.x + (int64_t)c[u] * a.ld + a.j0;
 #pragma unroll
-      for (int cc = 0; cc < NCM; cc++) xv[u][cc] = xr[jc[cc]];
+      for (int cc = 0; cc < NCM; cc++) xv[u][cc] = (T)xr[jc[cc]];
     }
 #pragma unroll
     for (int cc = 0; cc < NCM; cc++) {
@@ -228,8 +230,8 @@ struct RowOps {
   T v[NCM], w[NCM];
   double d[NCM];
 };
-template <typename T, int CW, int NCM>
-__device__ inline void row_load(const SpmmArgs<T>& a, int i, int cl, int NC, RowOps<T, NCM>& p) {
+template <typename T, int CW, int NCM, typename TX>
+__device__ inline void row_load(const SpmmArgs<T, TX>& a, int i, int cl, int NC, RowOps<T, NCM>& p) {
   const int B = a.B;
   const int64_t ro = (int64_t)(i - a.row0) * a.ld + a.j0;
   // clamped columns (a ragged last group reads column B - 1, unused): one
@@ -250,7 +252,7 @@ __device__ inline void row_load(const SpmmArgs<T>& a, int i, int cl, int NC, Row
   }
   if (a.w) {
 #pragma unroll
-    for (int cc = 0; cc < NCM; cc++) p.w[cc] = a.w[ro + jc[cc]];
+    for (int cc = 0; cc < NCM; cc++) p.w[cc] = (T)a.w[ro + jc[cc]];
   }
   if (a.ep != EP_NONE && a.dotv) {
     if (a.dotv == a.v) {
@@ -267,8 +269,8 @@ __device__ inline void row_load(const SpmmArgs<T>& a, int i, int cl, int NC, Row
 // operands, stores y and accumulates the dot (in place, y == v, is allowed:
 // the lane has loaded v before).  Every group's value is formed before the
 // first store.
-template <typename T, int CW, int NCM>
-__device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, const T* acc,
+template <typename T, int CW, int NCM, typename TX>
+__device__ inline void row_finish(const SpmmArgs<T, TX>& a, int i, int cl, int NC, const T* acc,
                                   const RowOps<T, NCM>& p, double* dacc) {
   const int B = a.B;
   const int64_t ro = (int64_t)(i - a.row0) * a.ld + a.j0;
@@ -295,8 +297,8 @@ __device__ inline void row_finish(const SpmmArgs<T>& a, int i, int cl, int NC, c
 // Per-column sums of the owners' dacc over the workgroup's teams (a fixed
 // tree), stored as partial row `prow`: partials[prow * ld + j0 + j].  Called
 // by every thread of the workgroup.
-template <typename T, int TEAMS, int CW, int NCM>
-__device__ inline void spmm_store_partials(const SpmmArgs<T>& a, double* sh, const double* dacc, bool owner,
+template <typename T, int TEAMS, int CW, int NCM, typename TX>
+__device__ inline void spmm_store_partials(const SpmmArgs<T, TX>& a, double* sh, const double* dacc, bool owner,
                                            int slot, int cl_own, int64_t prow) {
   const int tid = threadIdx.x, B = a.B, NC = (B + CW - 1) / CW;
   for (int j = tid; j < TEAMS * B; j += WG) sh[j] = 0.0;
@@ -328,8 +330,8 @@ __device__ inline void spmm_store_partials(const SpmmArgs<T>& a, double* sh, con
   __syncthreads();
 }
 
-template <typename T, int TS, int CW, bool VAL, int NCM>
-__global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T> a) {
+template <typename T, int TS, int CW, bool VAL, int NCM, typename TX = T>
+__global__ __launch_bounds__(WG) void k_spmm(SpmmArgs<T, TX> a) {
   if (a.n_active && *a.n_active == 0) return;
   constexpr int NZ = TS / CW;
   constexpr int TEAMS = WG / TS;
@@ -642,6 +644,30 @@ __global__ __launch_bounds__(WG) void k_axpy_mask(int64_t m, int B, T* dst, cons
   }
 }
 
+// Precision form, after a sweep's FP32 solve of the scaled system: the
+// correction d = fl32(fwd_j x_j) on the sweep's columns (mask; every column
+// when NULL) and 0 on the others, written back to x for the residual update
+// r -= M d, and K = d (add == 0) or K += d on those columns.  d is exactly an
+// FP32 value, so M d summed in FP64 is the FP64 residual change of the K
+// actually stored, up to the rounding of K + d.
+__global__ __launch_bounds__(WG) void k_take_correction(int64_t m, int B, float* x, double* K, const int* mask,
+                                                        const double* fwd, int add) {
+  const ColMap cm = colmap(B);
+  const int tid = threadIdx.x, cl = tid % cm.CL, rg = tid / cm.CL;
+  for (int c = 0; c < cm.NCL; c++) {
+    const int j = cl + cm.CL * c;
+    if (j >= B) continue;
+    const bool on = !mask || mask[j];
+    const double sc = fwd[j];
+    for (int64_t i = (int64_t)blockIdx.x * cm.RG + rg; i < m; i += (int64_t)gridDim.x * cm.RG) {
+      const int64_t o = i * B + j;
+      const float d = on ? (float)(sc * (double)x[o]) : 0.0f;
+      x[o] = d;
+      if (on) K[o] = add ? K[o] + (double)d : (double)d;
+    }
+  }
+}
+
 // ------------------------------------------------------ M11 block solves
 // out[i] = scale * M_bb^{-1} u[i] for every row i of the tile's blocks, with
 // u[i] = cv v[i] + ca (A12 x2)[i] staged in LDS (x2: separator panel indexed
@@ -730,6 +756,57 @@ __global__ __launch_bounds__(WG) void k_m11_apply(M11Args<T> a) {
     }
     __syncthreads();
   }
+}
+
+// One column, first sweep: the Schur right-hand side f = b2 + beta A21 t,
+// t = M11^{-1} b1, when b = beta A e_q reaches few rows.  The lists (from
+// the host, structure only): rows[0, nt) the rows of the blocks that hold a
+// neighbour of q (t there, into x1, which is zero elsewhere); rows[nt, nt +
+// ns) the separator rows next to q or to those blocks, ascending; for
+// separator row s, the block-row entries that reach it, off[s] .. off[s + 1]
+// of (pj: the block row, pk: its CSR entry), in block-row order.  f there
+// into f2 (zero elsewhere), <f, f> in a fixed order and the column's start
+// state as EP_RR_INIT sets it.  One workgroup; every loop is short (hub rows
+// never appear whole: only their entries towards the listed blocks do).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_schur_rhs1(const int32_t* rows, int nt, int ns, const int32_t* off,
+                                                   const int32_t* pj, const int32_t* pk, const T* rhs, int32_t n1,
+                                                   const int32_t* row_blk, const int32_t* blk_start,
+                                                   const int64_t* blk_off, const T* minv, const double* val,
+                                                   T beta, T* x1, T* f2, ColState cs) {
+  __shared__ double sh[WG / 64];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < nt; t += WG) {
+    const int gi = rows[t];
+    const int blk = row_blk[gi], bs = blk_start[blk], bsz = blk_start[blk + 1] - bs, li = gi - bs;
+    const T* mi = minv + blk_off[blk];
+    T u = (T)0;
+    for (int k = 0; k < bsz; k++) u += mi[(int64_t)k * bsz + li] * rhs[bs + k];
+    x1[gi] = u;
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int t = tid; t < ns; t += WG) {
+    const int i = rows[nt + t];
+    T g = (T)0;
+    for (int p = off[t]; p < off[t + 1]; p++) g += (val ? (T)val[pk[p]] : (T)1) * x1[pj[p]];
+    const T f = rhs[i] + beta * g;
+    f2[i - n1] = f;
+    acc += (double)f * (double)f;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (tid % 64 == 0) sh[tid / 64] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double rr = 0.0;
+    for (int wv = 0; wv < WG / 64; wv++) rr += sh[wv];
+    cs.rr[0] = rr;
+    cs.iters[0] = 0;
+    cs.status[0] = 0;
+    cs.active[0] = (cs.mask[0] && rr > cs.thr[0]) ? 1 : 0;
+  }
+  recount_active(cs, 1);
 }
 
 // Block solve for B >= 16 columns.  Workgroup (tile, column chunk) with CBW
@@ -1726,6 +1803,8 @@ struct Tuning {
   int m11_bpt;      // blocks per team and chunk of the batched small-block solve
   int autotune;     // tune the SpMM chunk walk per index (off when pinned by the environment)
   int m11_sub1;     // lanes per row of the A12 gather in the 1-3 column block solve
+  int sparse_rhs;   // one-column Schur right-hand side from the rows b reaches
+  int rec_res;      // precision form: residual updated by M d (FP32 d) per sweep
   int m11_small_min;  // narrowest batch taking the register block solve (5..513; default 16)
   int lr_direct;    // widest column group (JW) of the unstaged narrow low-rank kernels (0: never)
   int spmm_slice;   // SpMM column-slice width for wider batches (0: one launch over all columns)
@@ -1752,6 +1831,8 @@ static const Tuning& tuning() {
     u.m11_bpt = env_int("KATZ_M11_BLOCKS_PER_TEAM", 1, 1, 64);
     u.autotune = env_int("KATZ_AUTOTUNE", 1, 0, 1) && !getenv("KATZ_XCD_SLAB") && !getenv("KATZ_SPMM_NWG");
     u.m11_sub1 = env_int("KATZ_M11_SUB", 4, 1, 16);
+    u.sparse_rhs = env_int("KATZ_SPARSE_RHS", 1, 0, 1);
+    u.rec_res = env_int("KATZ_REC_RES", 1, 0, 1);
     u.m11_small_min = env_int("KATZ_M11_SMALL_MIN", 16, 5, 513);
     u.lr_direct = env_int("KATZ_LR_DIRECT_MAX", 8, 0, 16);
     u.spmm_slice = env_int("KATZ_SPMM_SLICE", 0, 0, 512);
@@ -2346,26 +2427,30 @@ struct Launcher {
 
   // SpMM kernel variant for this batch width: team size TS, column lanes CW,
   // compile-time column groups NCM and weights; `slot` numbers the variant
-  // (with the panel precision) for the autotuned chunk walk.
-  template <typename T>
+  // (with the panel precision) for the autotuned chunk walk.  FP32 x with
+  // FP64 sums (TX = float, T = double) exists for 16 columns and more and
+  // shares the FP64 variant's walk.
+  template <typename T, typename TX = T>
   struct SpmmVariant {
-    void (*fn)(SpmmArgs<T>);
+    void (*fn)(SpmmArgs<T, TX>);
     int TS, CW, slot;
   };
-  template <typename T>
-  SpmmVariant<T> spmm_variant(bool weighted, int B) const {
+  template <typename T, typename TX = T>
+  SpmmVariant<T, TX> spmm_variant(bool weighted, int B) const {
     const Tuning& tu = tuning();
     (void)tu;
     const int TS = spmm_team_size(B);
     const int CW = B <= 1 ? 1 : (B <= 2 ? 2 : (B <= 4 ? 4 : (B <= 8 ? 8 : (B <= 16 ? 16 : (B <= 32 ? 32 : 64)))));
     if (B > MAXC * CW) fail(KATZ_EINVAL, "batch too wide for one launch");
     const int nc = (B + CW - 1) / CW;  // column groups per lane
-    SpmmVariant<T> v{nullptr, TS, CW, -1};
+    SpmmVariant<T, TX> v{nullptr, TS, CW, -1};
     int idx = 0;
 #define KZ_SPMM_V(ts, cw, ncm)                                                              \
-  if (!v.fn && TS == ts && CW == cw && nc <= ncm) {                                         \
-    v.fn = weighted ? k_spmm<T, ts, cw, true, ncm> : k_spmm<T, ts, cw, false, ncm>;        \
-    v.slot = idx;                                                                           \
+  if constexpr (std::is_same<T, TX>::value || cw >= 16) {                                   \
+    if (!v.fn && TS == ts && CW == cw && nc <= ncm) {                                       \
+      v.fn = weighted ? k_spmm<T, ts, cw, true, ncm, TX> : k_spmm<T, ts, cw, false, ncm, TX>; \
+      v.slot = idx;                                                                         \
+    }                                                                                       \
   }                                                                                         \
   idx++;
     KZ_SPMM_V(4, 1, 1) KZ_SPMM_V(8, 1, 1) KZ_SPMM_V(16, 1, 1) KZ_SPMM_V(32, 1, 1) KZ_SPMM_V(8, 2, 1)
@@ -2379,8 +2464,8 @@ struct Launcher {
 
   // Fills in the launch shape of `a` (chunking, walk, hub rows, partials)
   // and returns the grid and LDS size.
-  template <typename T>
-  void spmm_shape(SpmmArgs<T>& a, const SpmmVariant<T>& v, int32_t walk, dim3& g, size_t& shm) const {
+  template <typename T, typename TX>
+  void spmm_shape(SpmmArgs<T, TX>& a, const SpmmVariant<T, TX>& v, int32_t walk, dim3& g, size_t& shm) const {
     const int B = a.B;
     const Tuning& tu = tuning();
     const int64_t rows = a.row1 - a.row0;
@@ -2402,8 +2487,8 @@ struct Launcher {
     shm = sizeof(double) * std::max<size_t>((size_t)teams * B, (size_t)(WG / 64) * MAXC * v.CW);
   }
 
-  template <typename T>
-  void spmm(SpmmArgs<T> a) {
+  template <typename T, typename TX = T>
+  void spmm(SpmmArgs<T, TX> a) {
     const int64_t rows = a.row1 - a.row0;
     if (rows <= 0) {
       if (a.ep != EP_NONE) fail(KATZ_EDEVICE, "internal: empty SpMM with a reduction");
@@ -2417,7 +2502,7 @@ struct Launcher {
     const int bw = B / nsl;
     a.ld = B;
     a.B = bw;
-    const SpmmVariant<T> v = spmm_variant<T>(a.val != nullptr, bw);
+    const SpmmVariant<T, TX> v = spmm_variant<T, TX>(a.val != nullptr, bw);
     dim3 g;
     size_t shm;
     spmm_shape(a, v, walk_for(v.slot), g, shm);
@@ -2430,9 +2515,10 @@ struct Launcher {
     if (sep && a.parts == 1) { nnz_sel = D->nnz_sep_left; cols_sel = D->cols_sep_left; }
     else if (sep) { nnz_sel = D->nnz_sep; cols_sel = D->cols_sep; }
     else { nnz_sel = D->nnz; cols_sel = D->cols_all; }
-    const double wb = (double)sizeof(T) * B;
-    int panels = 1 + (a.v ? 1 : 0) + (a.w ? 1 : 0) + ((a.dotv && a.dotv != a.v) ? 1 : 0);
-    double bytes = 8.0 * rows + 4.0 + (4.0 + (a.val ? 8.0 : 0.0)) * nnz_sel + wb * cols_sel + wb * rows * panels;
+    const double wb = (double)sizeof(T) * B, wbx = (double)sizeof(TX) * B;
+    const int panels = 1 + (a.v ? 1 : 0) + ((a.dotv && a.dotv != a.v) ? 1 : 0);
+    double bytes = 8.0 * rows + 4.0 + (4.0 + (a.val ? 8.0 : 0.0)) * nnz_sel + wbx * cols_sel + wb * rows * panels +
+                   (a.w ? wbx * rows : 0.0);
     const int kind = sep ? (a.parts == 1 ? PK_SPMM_RHS : PK_SPMM_SEP) : PK_SPMM_FULL;
     timed(kind, bytes, [&] {
       for (int sl = 0; sl < nsl; sl++) {
@@ -2603,6 +2689,60 @@ constexpr double kInnerTolFP32 = 1e-5;
 // Pinned host staging (w->hpin, 64 KiB), B <= 512:
 constexpr size_t kPinQ = 0, kPinMask0 = 2048, kPinMask1 = 4096, kPinBn2 = 8192, kPinRes = 12288,
                  kPinFlag = kPinFlagOff, kPinStat0 = 20480, kPinIter0 = 22528, kPinStat1 = 24576, kPinIter1 = 26624;
+// the row lists of the sparse one-column Schur right-hand side
+constexpr size_t kPinList = 32768;
+constexpr int kPinListCap = 8192;
+
+// The structure of the sparse one-column Schur right-hand side for b =
+// beta A e_qp (qp a permuted position), laid out in out[] as k_schur_rhs1
+// reads it: the rows of the blocks holding a neighbour of qp (nt), the
+// separator rows next to qp or to those rows, ascending (ns), per separator
+// row the offsets (ns + 1) into the entry pairs, then the pairs' block rows
+// and CSR entries (np each), sorted by (separator row, block row).  False
+// when it takes more than cap values.
+static bool sparse_rhs_rows(const HostIndex& H, int32_t qp, int32_t* out, int cap, int& nt, int& ns, int& np) {
+  std::vector<int32_t> blocks;
+  for (int32_t k = H.rp[qp]; k < H.split[qp]; k++)  // block columns (< n1) come first in a row
+    blocks.push_back((int32_t)(std::upper_bound(H.blk_start.begin(), H.blk_start.end(), H.col[k]) -
+                               H.blk_start.begin()) - 1);
+  std::sort(blocks.begin(), blocks.end());
+  blocks.erase(std::unique(blocks.begin(), blocks.end()), blocks.end());
+  std::vector<int32_t> trow;
+  for (int32_t b : blocks)
+    for (int32_t r = H.blk_start[b]; r < H.blk_start[b + 1]; r++) trow.push_back(r);
+  if ((int64_t)trow.size() > cap) return false;
+  // (separator row, block row, entry) for every entry of the block rows
+  // towards the separator; the block rows ascend, so a stable sort by the
+  // separator row keeps each row's terms in block-row order
+  struct Pair { int32_t i, j, k; };
+  std::vector<Pair> pr;
+  for (int32_t j : trow)
+    for (int32_t k = H.split[j]; k < H.rp[j + 1]; k++) pr.push_back({H.col[k], j, k});
+  if ((int64_t)trow.size() + 3 * (int64_t)pr.size() > cap) return false;
+  std::stable_sort(pr.begin(), pr.end(), [](const Pair& x, const Pair& y) { return x.i < y.i; });
+  std::vector<int32_t> srow(H.col.begin() + H.split[qp], H.col.begin() + H.rp[qp + 1]);
+  for (const Pair& x : pr) srow.push_back(x.i);
+  std::sort(srow.begin(), srow.end());
+  srow.erase(std::unique(srow.begin(), srow.end()), srow.end());
+  nt = (int)trow.size();
+  ns = (int)srow.size();
+  np = (int)pr.size();
+  if ((int64_t)nt + ns + (ns + 1) + 2 * (int64_t)np > cap) return false;
+  int32_t* o = out;
+  o = std::copy(trow.begin(), trow.end(), o);
+  o = std::copy(srow.begin(), srow.end(), o);
+  int32_t* off = o;
+  size_t p = 0;
+  for (int s = 0; s < ns; s++) {
+    off[s] = (int32_t)p;
+    while (p < pr.size() && pr[p].i == srow[s]) p++;
+  }
+  off[ns] = (int32_t)p;
+  o += ns + 1;
+  for (int t = 0; t < np; t++) o[t] = pr[t].j;
+  for (int t = 0; t < np; t++) o[np + t] = pr[t].k;
+  return true;
+}
 
 // Rank-r preconditioner on MFMA for FP32 panels: DW = D o (V^T r) by split-K
 // tiles + finalize; z = r + V DW with the <r, z> partials + finalize.
@@ -3004,7 +3144,10 @@ static void update_r_precond1(Launcher& L, const TV* V, T* x, T* p, T* r, const 
 // One correction solve M d = rhs for the columns in w->mask; d is left in
 // w->Dx (all n rows), per-column outcome in w->iters / w->status.
 template <typename T>
-static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, bool pcgnr = false) {
+// sp_rows (host, one column, first sweep): the rows b reaches (sparse_rhs_rows),
+// for the sparse Schur right-hand side; nullptr: the dense one.
+static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, bool pcgnr = false,
+                      const int32_t* sp_rows = nullptr, int sp_nt = 0, int sp_ns = 0, int sp_np = 0) {
   DeviceIndex* D = L.D;
   Workspace* w = L.w;
   const int B = L.B;
@@ -3217,6 +3360,19 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
   }
 
   // ---- a2: t = M11^{-1} b1 -> X[0:n1]; f = b2 + beta A21 t -> R2; rr
+  if (sp_rows) {
+    // one column, b = beta A e_q: only the listed rows are nonzero.  The
+    // lists go to w->seg (free until the next two-stage reduction).
+    int32_t* dl = (int32_t*)w->seg;
+    const size_t len = (size_t)sp_nt + 2 * (size_t)sp_ns + 1 + 2 * (size_t)sp_np;
+    HIPCHECK(hipMemcpyAsync(dl, sp_rows, sizeof(int32_t) * len, hipMemcpyHostToDevice, st));
+    L.fill<T>(X, (int64_t)n1, (T)0);
+    L.fill<T>(R2, (int64_t)n2, (T)0);
+    const int32_t* off = dl + sp_nt + sp_ns;
+    k_schur_rhs1<T><<<1, WG, 0, st>>>(dl, sp_nt, sp_ns, off, off + sp_ns + 1, off + sp_ns + 1 + sp_np, rhs, n1,
+                                      D->row_blk, D->blk_start, D->blk_off, Factors<T>::minv(D), D->val, beta, X,
+                                      R2, cs);
+  } else {
   m11(rhs, (T)1, nullptr, (T)0, X, nullptr);
   {
     SpmmArgs<T> a{};
@@ -3225,6 +3381,7 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
     a.v = rhs + (int64_t)n1 * B; a.cv = (T)1; a.w = nullptr; a.cw = (T)0; a.y = R2;
     a.ep = EP_RR_INIT; a.dotv = nullptr; a.cs = cs; a.n_active = nullptr;
     L.spmm(a);
+  }
   }
   // x2 (rows >= n1 of Dx) starts at 0; rows < n1 are written whole by the
   // back-solve (a4) before anything reads them
@@ -3359,9 +3516,28 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
   k_cols_setup<<<1, WG, 0, st>>>(B, w->bn2, 0.25 * tol * tol, w->thr, w->mask);
   res.assign(B, ColResult());
   for (int j = 0; j < B; j++) res[j].path = o.method == KATZ_METHOD_CG ? KATZ_PATH_CG : KATZ_PATH_LRC;
+  // one column: the rows b reaches, for the first sweep's sparse Schur
+  // right-hand side (a dense one when they are many)
+  int32_t* sp_rows = nullptr;
+  int sp_nt = 0, sp_ns = 0, sp_np = 0;
+  if (B == 1 && o.method == KATZ_METHOD_LRC && tuning().sparse_rhs && D->n2 > 0 &&
+      sparse_rhs_rows(H, hq[0], (int32_t*)(pin + kPinList), kPinListCap, sp_nt, sp_ns, sp_np))
+    sp_rows = (int32_t*)(pin + kPinList);
   double* hb = (double*)(pin + kPinBn2);
   double* hres = (double*)(pin + kPinRes);
   bool have_bn = false;
+  // Precision form, 16 columns and more: each sweep's residual is the last
+  // one minus M d for the sweep's FP32 correction d (half the gathered bytes
+  // of b - M K with K in FP64); <r, r> per column into res2.
+  const bool rec_res = D->precision == KATZ_PREC_MIXED && B >= 16 && tuning().rec_res;
+  auto residual_update_f32 = [&] {
+    SpmmArgs<double, float> a{};
+    a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+    a.x = (const float*)w->Dx; a.ca = D->beta; a.cb = D->beta; a.parts = 3;
+    a.v = w->Rhs; a.cv = 1.0; a.w = (const float*)w->Dx; a.cw = -1.0; a.y = w->Rhs;
+    a.ep = EP_RES; a.dotv = nullptr; a.out = w->res2; a.n_active = nullptr; a.cs = L.cs(0);
+    L.spmm(a);
+  };
   for (int sweep = 0; sweep < o.max_sweeps; sweep++) {
     bool any = false;
     for (int j = 0; j < B; j++) any |= !res[j].done;
@@ -3394,21 +3570,30 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
         if (cg_pass)
           solve_cg<float>(L, w->Rf, iters, o.check_every);
         else
-          solve_lrc<float>(L, w->Rf, iters, o.check_every, o.method == KATZ_METHOD_PCGNR);
+          solve_lrc<float>(L, w->Rf, iters, o.check_every, o.method == KATZ_METHOD_PCGNR, sweep == 0 ? sp_rows : nullptr,
+                           sp_nt, sp_ns, sp_np);
         // first sweep (one path for all columns): K = correction for every
         // column (those outside the mask are exactly 0: each solve clears Dx
         // and never touches inactive columns); later sweeps add
-        if (sweep == 0)
+        if (rec_res) {
+          // the correction as FP32 values (0 off the sweep's columns) into
+          // K, then r -= M d with d gathered in FP32 and summed in FP64
+          k_take_correction<<<grid_for(n, 64), WG, 0, st>>>(n, B, (float*)w->Dx, w->K, sweep == 0 ? nullptr : w->mask,
+                                                             w->fwd, sweep == 0 ? 0 : 1);
+          residual_update_f32();
+        } else if (sweep == 0) {
           k_axpy_mask<double, float><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const float*)w->Dx, nullptr,
                                                                     w->fwd, 0);
-        else
+        } else {
           k_axpy_mask<double, float><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const float*)w->Dx, w->mask,
                                                                     w->fwd, 1);
+        }
       } else {
         if (cg_pass)
           solve_cg<double>(L, rhs, iters, o.check_every);
         else
-          solve_lrc<double>(L, rhs, iters, o.check_every, o.method == KATZ_METHOD_PCGNR);
+          solve_lrc<double>(L, rhs, iters, o.check_every, o.method == KATZ_METHOD_PCGNR,
+                            sweep == 0 ? sp_rows : nullptr, sp_nt, sp_ns, sp_np);
         if (sweep == 0)
           k_axpy_mask<double, double><<<grid_for(n, 64), WG, 0, st>>>(n, B, w->K, (const double*)w->Dx, nullptr,
                                                                       nullptr, 0);
@@ -3424,14 +3609,17 @@ static void run_batch(const HostIndex& H, DeviceIndex* D, Workspace* w, hipStrea
     // a6: true FP64 residual r = b - M k, which is the next sweep's right-hand
     // side: Rhs = b, then Rhs = Rhs + beta A k - k in place (each element is
     // read and written by the same lane).  The first sweep's solve only read
-    // Rhs, which still holds b.
-    if (sweep > 0) put_b();
-    SpmmArgs<double> a{};
-    a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
-    a.x = w->K; a.ca = D->beta; a.cb = D->beta; a.parts = 3;
-    a.v = w->Rhs; a.cv = 1.0; a.w = w->K; a.cw = -1.0; a.y = w->Rhs;
-    a.ep = EP_RES; a.dotv = nullptr; a.out = w->res2; a.n_active = nullptr; a.cs = L.cs(0);
-    L.spmm(a);
+    // Rhs, which still holds b.  (The precision form at 16 columns and more
+    // has updated Rhs -= M d after each pass instead.)
+    if (!rec_res) {
+      if (sweep > 0) put_b();
+      SpmmArgs<double> a{};
+      a.row0 = 0; a.row1 = n; a.rp = D->rp; a.col = D->col; a.split = D->split; a.val = D->val;
+      a.x = w->K; a.ca = D->beta; a.cb = D->beta; a.parts = 3;
+      a.v = w->Rhs; a.cv = 1.0; a.w = w->K; a.cw = -1.0; a.y = w->Rhs;
+      a.ep = EP_RES; a.dotv = nullptr; a.out = w->res2; a.n_active = nullptr; a.cs = L.cs(0);
+      L.spmm(a);
+    }
     HIPCHECK(hipMemcpyAsync(hres, w->res2, sizeof(double) * B, hipMemcpyDeviceToHost, st));
     if (!have_bn) HIPCHECK(hipMemcpyAsync(hb, w->bn2, sizeof(double) * B, hipMemcpyDeviceToHost, st));
     L.sync();  // one host round trip per sweep

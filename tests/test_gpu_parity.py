@@ -588,3 +588,89 @@ def test_row_major_factor_gives_identical_results(tmp_path):
     assert res[0].files == res[1].files
     for k in res[0].files:
         assert np.array_equal(res[0][k], res[1][k]), k
+
+
+_SPRHS_SCRIPT = r"""
+import sys, numpy as np
+sys.path.insert(0, sys.argv[2])
+import katz_inputs as ki, paper_1912_06525_amd as K
+out = {}
+cases = []
+g = ki.workload("lnsbm4m", scale=0.004).graph
+cases.append(("sbm", g, None, g.labels))
+cases.append(("sbmw", g, ki.edge_weights(g, seed=3), g.labels))
+h = ki.chung_lu(200_000, 2.5, 10, seed=11)
+cases.append(("cl", h, None, None))
+for name, gr, val, lab in cases:
+    deg = np.diff(gr.row_ptr)
+    qs = list(ki.sample_queries(gr, 5, 21)) + [int(np.argmax(deg)), int(np.argmin(deg))]
+    for prec in (K.KATZ_PREC_FP64, K.KATZ_PREC_MIXED):
+        idx = K.KatzIndex.from_graph(gr, val=val, beta_frac=0.9, rank=16, labels=lab, max_block=32, precision=prec)
+        for j, q in enumerate(qs):
+            sc, st = idx.query([q], tol=1e-9)
+            out["%s_p%d_q%d" % (name, prec, j)] = sc[0]
+            out["%s_p%d_q%d_st" % (name, prec, j)] = np.array([st[0]["status"], st[0]["iters"], st[0]["sweeps"]])
+        idx.close()
+np.savez(sys.argv[1], **out)
+"""
+
+
+def test_sparse_schur_rhs_matches_dense(tmp_path):
+    """A one-column solve builds the first sweep's Schur right-hand side from
+    the rows b = beta A e_q reaches (KATZ_SPARSE_RHS, on by default) instead
+    of a block solve and an SpMM over every row.  Against the dense form
+    (KATZ_SPARSE_RHS=0), on community and Chung-Lu graphs, unweighted and
+    weighted, FP64 and the precision form, including the largest- and
+    smallest-degree nodes: the same status and number of sweeps (a wrong
+    right-hand side would be caught by the residual check and cost a sweep),
+    iterations within one, and scores within rounding of each other."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = []
+    for t, flag in enumerate(("1", "0")):
+        env = dict(os.environ)
+        env["KATZ_SPARSE_RHS"] = flag
+        f = str(tmp_path / ("sprhs%d.npz" % t))
+        print("KATZ_SPARSE_RHS", flag, flush=True)
+        subprocess.run([sys.executable, "-c", _SPRHS_SCRIPT, f, root], env=env, check=True, timeout=300)
+        res.append(np.load(f))
+    assert res[0].files == res[1].files
+    for k in res[0].files:
+        a, b = res[0][k], res[1][k]
+        if k.endswith("_st"):
+            assert a[0] == 0 and b[0] == 0 and a[2] == b[2] and abs(int(a[1]) - int(b[1])) <= 1, (k, a, b)
+        else:
+            tol = 1e-7 if "_p%d_" % K.KATZ_PREC_FP64 in k else 1e-5
+            assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b), k
+
+
+
+@pytest.mark.parametrize("B", [16, 40, 130])
+def test_precision_form_reported_residual_is_true_residual(B):
+    """From 16 columns the precision form updates each sweep's FP64 residual
+    as r -= M d for the sweep's FP32 correction d instead of forming b - M K
+    again.  The relative residual each column reports must be the true one
+    of the returned scores (the oracle's b - (I - beta A) k in FP64) up to
+    rounding, over two or more sweeps, and the scores must match the
+    oracle."""
+    g = ki.workload("lnsbm4m", scale=0.004).graph
+    A = oracle.csr_matrix(g.n, g.row_ptr, g.col)
+    beta = 0.9 / oracle.lambda_max(A)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=16, labels=g.labels, max_block=32,
+                                 precision=K.KATZ_PREC_MIXED)
+    qs = ki.sample_queries(g, B, 29 + B)
+    tol = 1e-10
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta, validate=False)["k"]
+    for method in (K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG):
+        sc, st = idx.query(qs, tol=tol, method=method)
+        true = oracle.katz_residual(A, beta, qs, sc.T)
+        assert max(x["sweeps"] for x in st) >= 2
+        for j in range(B):
+            assert st[j]["status"] == 0, st[j]
+            assert abs(st[j]["rel_residual"] - true[j]) <= 1e-12 + 1e-3 * true[j], (j, st[j], true[j])
+            assert true[j] <= tol * 1.01, (j, true[j])
+            c = ref[:, j]
+            assert np.linalg.norm(sc[j] - c) <= 1e-8 * np.linalg.norm(c), j
+    idx.close()
