@@ -615,15 +615,17 @@ np.savez(sys.argv[1], **out)
 """
 
 
-def test_sparse_schur_rhs_matches_dense(tmp_path):
-    """A one-column solve builds the first sweep's Schur right-hand side from
-    the rows b = beta A e_q reaches (KATZ_SPARSE_RHS, on by default) instead
-    of a block solve and an SpMM over every row.  Against the dense form
-    (KATZ_SPARSE_RHS=0), on community and Chung-Lu graphs, unweighted and
-    weighted, FP64 and the precision form, including the largest- and
-    smallest-degree nodes: the same status and number of sweeps (a wrong
-    right-hand side would be caught by the residual check and cost a sweep),
-    iterations within one, and scores within rounding of each other."""
+@pytest.mark.parametrize("switch", ["KATZ_SPARSE_RHS", "KATZ_FUSE"])
+def test_one_column_forms_match(tmp_path, switch):
+    """Two one-column forms against their plain versions, on community and
+    Chung-Lu graphs, unweighted and weighted, FP64 and the precision form,
+    including the largest- and smallest-degree nodes.  KATZ_SPARSE_RHS: the
+    first sweep's Schur right-hand side from the rows b = beta A e_q reaches
+    instead of a block solve and an SpMM over every row.  KATZ_FUSE: the
+    residual update, V^T r and the PCG step in one pass and one finalize
+    instead of separate passes.  The same status and number of sweeps (a
+    wrong right-hand side would be caught by the residual check and cost a
+    sweep), iterations within one, scores within rounding of each other."""
     import os
     import subprocess
     import sys
@@ -631,9 +633,9 @@ def test_sparse_schur_rhs_matches_dense(tmp_path):
     res = []
     for t, flag in enumerate(("1", "0")):
         env = dict(os.environ)
-        env["KATZ_SPARSE_RHS"] = flag
-        f = str(tmp_path / ("sprhs%d.npz" % t))
-        print("KATZ_SPARSE_RHS", flag, flush=True)
+        env[switch] = flag
+        f = str(tmp_path / ("sw%d.npz" % t))
+        print(switch, flag, flush=True)
         subprocess.run([sys.executable, "-c", _SPRHS_SCRIPT, f, root], env=env, check=True, timeout=300)
         res.append(np.load(f))
     assert res[0].files == res[1].files
