@@ -549,6 +549,26 @@ __device__ inline void wave_sum_spread(double (&a)[R], int lane) {
   }
 }
 
+// The halving exchanges of wave_sum_spread over the lane bits O = 32, 16,
+// ..., OMIN only: afterwards a[0, R * OMIN / 64) of lane l hold the sums,
+// over the lanes that differ from l only in those bits, of the values
+// base(l) + c, base(l) = sum over the steps of (bit O of l set ? the size of
+// the half kept : 0).
+template <int C, int R, int O, int OMIN>
+__device__ inline void wave_halve(double (&a)[R], int lane) {
+  if constexpr (O >= OMIN && C > 1) {
+    constexpr int H = C / 2;
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int h = 0; h < H; h++) {
+      const double send = up ? a[h] : a[h + H];
+      const double keep = up ? a[h + H] : a[h];
+      a[h] = keep + __shfl_xor(send, O, 64);
+    }
+    wave_halve<H, R, O / 2, OMIN>(a, lane);
+  }
+}
+
 // One column (B = 1): x += alpha p; r -= alpha q; then, in the same pass,
 // the partial sums of V^T r (rank values, registers) and <r, r>; partials
 // per workgroup: [W_0 .. W_{rank-1}, rr].  Finalized by EP_RR_VT.
@@ -1184,7 +1204,8 @@ __device__ inline void stage_v(double* sV, const TV* V, int64_t m, int rank, int
 // one, their sums unused), so many loads are in flight per wave instead of
 // one block's staging per barrier pair.  A thread visits rows r0 + rg,
 // r0 + rg + NR, ... as the staged form does when NR divides the block height.
-template <typename T, typename TV, int RMAX, bool DIRECT = false>
+// VR (DIRECT only): V is the row-major BF16 copy with rank == RMAX.
+template <typename T, typename TV, int RMAX, bool DIRECT = false, bool VR = false>
 __global__ __launch_bounds__(WG) void k_vt_rows(int64_t m, int B, int rank, int JW, const TV* V, const T* r,
                                                 int64_t rpc, double* partials, const int* n_active) {
   if (n_active && *n_active == 0) return;
@@ -1200,13 +1221,23 @@ __global__ __launch_bounds__(WG) void k_vt_rows(int64_t m, int B, int rank, int 
   if (DIRECT) {
     if (col_ok) {
       for (int64_t i = r0 + rg; i < r1; i += NR) {
-        TV vv[RMAX];
+        double vd[RMAX];
+        if constexpr (VR) {
+          float vf[RMAX];
+          load_vrow<RMAX>((const bf16*)V, i, vf);
 #pragma unroll
-        for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+          for (int k = 0; k < RMAX; k++) vd[k] = (double)vf[k];
+        } else {
+          TV vv[RMAX];
+#pragma unroll
+          for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+#pragma unroll
+          for (int k = 0; k < RMAX; k++) vd[k] = to_d(vv[k]);
+        }
         const double x = (double)r[i * B + j];
         __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the FMAs
 #pragma unroll
-        for (int k = 0; k < RMAX; k++) acc[k] += to_d(vv[k]) * x;
+        for (int k = 0; k < RMAX; k++) acc[k] += vd[k] * x;
       }
     }
   } else {
@@ -1227,6 +1258,34 @@ __global__ __launch_bounds__(WG) void k_vt_rows(int64_t m, int B, int rank, int 
   }
   const int64_t nv = (int64_t)rank * B;
   double* out = partials + (int64_t)blockIdx.x * nv;
+  if (JW <= 8) {
+    // the lanes of one column in a wave differ in bits 3-5 and in the bits
+    // [log2 JW, 3): halving exchanges over bits 5, 4, 3, butterflies over
+    // the others; then the wave sums in order through LDS
+    const int lane = tid % 64, wave = tid / 64;
+    wave_halve<RMAX, RMAX, 32, 8>(acc, lane);
+    constexpr int C8 = RMAX / 8;
+    for (int off = 4; off >= JW; off >>= 1) {
+#pragma unroll
+      for (int c = 0; c < C8; c++) acc[c] += __shfl_xor(acc[c], off, 64);
+    }
+    __syncthreads();  // sV is free (the staged path's last reads are done)
+    if ((lane & 7) < JW) {
+      const int base = ((lane >> 5) & 1) * (RMAX / 2) + ((lane >> 4) & 1) * (RMAX / 4) + ((lane >> 3) & 1) * C8;
+#pragma unroll
+      for (int c = 0; c < C8; c++) sV[(wave * RMAX + base + c) * JW + jl] = acc[c];
+    }
+    __syncthreads();
+    for (int t = tid; t < rank * JW; t += WG) {
+      const int k = t / JW, jj = t % JW, j2 = blockIdx.y * JW + jj;
+      if (j2 < B) {
+        double sum = 0.0;
+        for (int wv = 0; wv < WG / 64; wv++) sum += sV[(wv * RMAX + k) * JW + jj];
+        out[(int64_t)k * B + j2] = sum;
+      }
+    }
+    return;
+  }
   if (NR == 1) {
 #pragma unroll
     for (int k = 0; k < RMAX; k++)
@@ -1284,7 +1343,7 @@ __global__ __launch_bounds__(WG) void k_vt_reduce(const double* partials, int nc
 // (p <- z_new + bcg p, p <- z_new at init) for the active columns, no partials.
 // DIRECT: as in k_vt_rows (factor loads of a row issued together, no LDS
 // tile); the same value per element (DW is 0 past the rank).
-template <typename T, typename TV, int RMAX, bool PUPD = false, bool DIRECT = false>
+template <typename T, typename TV, int RMAX, bool PUPD = false, bool DIRECT = false, bool VR = false>
 __global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank, int JW, const TV* V,
                                                      const double* DW, const T* r, T* z, int z_has_base,
                                                      int64_t rpc, const int* n_active, double* partials,
@@ -1305,16 +1364,26 @@ __global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank,
   if (DIRECT) {
     if (col_ok) {
       for (int64_t i = r0 + rg; i < r1; i += NR) {
-        TV vv[RMAX];
+        double vd[RMAX];
+        if constexpr (VR) {
+          float vf[RMAX];
+          load_vrow<RMAX>((const bf16*)V, i, vf);
 #pragma unroll
-        for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+          for (int k = 0; k < RMAX; k++) vd[k] = (double)vf[k];
+        } else {
+          TV vv[RMAX];
+#pragma unroll
+          for (int k = 0; k < RMAX; k++) vv[k] = V[(int64_t)(k < rank ? k : rank - 1) * m + i];
+#pragma unroll
+          for (int k = 0; k < RMAX; k++) vd[k] = to_d(vv[k]);
+        }
         const int64_t o = i * B + j;
         const double rv = (double)r[o];
         const double pv = PUPD && !init ? (double)z[o] : 0.0;
         double sum = !PUPD && z_has_base ? (double)z[o] : rv;
         __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the FMAs
 #pragma unroll
-        for (int k = 0; k < RMAX; k++) sum += to_d(vv[k]) * dw[k];
+        for (int k = 0; k < RMAX; k++) sum += vd[k] * dw[k];
         if (PUPD) {
           z[o] = (T)(sum + b * pv);
         } else {
@@ -2795,43 +2864,48 @@ static void with_lowrank_factor(const DeviceIndex* D, F&& f) {
 }
 
 // The row-blocked low-rank kernels for rank <= 64 (RMAX from the rank).
-template <typename T, typename TV, bool DIRECT>
+template <typename T, typename TV, bool DIRECT, bool VR = false>
 static void launch_vt_rows(dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V, const T* R2,
                            int64_t rpc, double* partials, const int* nact) {
-  if (rk <= 8) k_vt_rows<T, TV, 8, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
-  else if (rk <= 16) k_vt_rows<T, TV, 16, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
-  else if (rk <= 32) k_vt_rows<T, TV, 32, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
-  else k_vt_rows<T, TV, 64, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
+  if (rk <= 8) k_vt_rows<T, TV, 8, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
+  else if (rk <= 16) k_vt_rows<T, TV, 16, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
+  else if (rk <= 32) k_vt_rows<T, TV, 32, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
+  else k_vt_rows<T, TV, 64, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
 }
-template <typename T, typename TV, bool PUPD, bool DIRECT>
+template <typename T, typename TV, bool PUPD, bool DIRECT, bool VR = false>
 static void launch_lowrank_rows(dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V,
                                 const double* DW, const T* R2, T* Z2, int has_base, int64_t rpc, const int* nact,
                                 double* partials, const double* bcg, const int* active, int init) {
   if (rk <= 8)
-    k_lowrank_rows<T, TV, 8, PUPD, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
-                                                             partials, bcg, active, init);
+    k_lowrank_rows<T, TV, 8, PUPD, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
+                                                                 partials, bcg, active, init);
   else if (rk <= 16)
-    k_lowrank_rows<T, TV, 16, PUPD, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
-                                                              partials, bcg, active, init);
+    k_lowrank_rows<T, TV, 16, PUPD, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc,
+                                                                  nact, partials, bcg, active, init);
   else if (rk <= 32)
-    k_lowrank_rows<T, TV, 32, PUPD, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
-                                                              partials, bcg, active, init);
+    k_lowrank_rows<T, TV, 32, PUPD, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc,
+                                                                  nact, partials, bcg, active, init);
   else
-    k_lowrank_rows<T, TV, 64, PUPD, DIRECT><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
-                                                              partials, bcg, active, init);
+    k_lowrank_rows<T, TV, 64, PUPD, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc,
+                                                                  nact, partials, bcg, active, init);
 }
+// Vr: the row-major BF16 factor (vrow_factor), read by the unstaged form.
 template <typename T, typename TV>
 static void vt_rows(bool direct, dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V,
-                    const T* R2, int64_t rpc, double* partials, const int* nact) {
-  if (direct) launch_vt_rows<T, TV, true>(g, st, m, B, rk, JW, V, R2, rpc, partials, nact);
+                    const T* R2, int64_t rpc, double* partials, const int* nact, const bf16* Vr = nullptr) {
+  if (direct && Vr) launch_vt_rows<T, bf16, true, true>(g, st, m, B, rk, JW, Vr, R2, rpc, partials, nact);
+  else if (direct) launch_vt_rows<T, TV, true>(g, st, m, B, rk, JW, V, R2, rpc, partials, nact);
   else launch_vt_rows<T, TV, false>(g, st, m, B, rk, JW, V, R2, rpc, partials, nact);
 }
 template <typename T, typename TV, bool PUPD>
 static void lowrank_rows(bool direct, dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V,
                          const double* DW, const T* R2, T* Z2, int has_base, int64_t rpc, const int* nact,
                          double* partials, const double* bcg = nullptr, const int* active = nullptr,
-                         int init = 0) {
-  if (direct)
+                         int init = 0, const bf16* Vr = nullptr) {
+  if (direct && Vr)
+    launch_lowrank_rows<T, bf16, PUPD, true, true>(g, st, m, B, rk, JW, Vr, DW, R2, Z2, has_base, rpc, nact,
+                                                   partials, bcg, active, init);
+  else if (direct)
     launch_lowrank_rows<T, TV, PUPD, true>(g, st, m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact, partials, bcg,
                                            active, init);
   else
@@ -2940,13 +3014,14 @@ static void precond_rows(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, c
   while (JW < B && JW < WG) JW <<= 1;
   const int njt = (B + JW - 1) / JW;
   const bool direct = JW <= tuning().lr_direct;
+  const bf16* vr = direct ? vrow_factor(D, V) : nullptr;
   const int64_t rpc = lowrank_rows_rpc<T>(D, m, direct);
   const int nchunk = (int)((m + rpc - 1) / rpc);
   const int64_t nv = (int64_t)rk * B;
   dim3 g((unsigned)nchunk, (unsigned)njt);
   L.need(nchunk, nv);
   L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
-    vt_rows<T, TV>(direct, g, st, m, B, rk, JW, V, R2, rpc, w->partials, nact);
+    vt_rows<T, TV>(direct, g, st, m, B, rk, JW, V, R2, rpc, w->partials, nact, vr);
   });
   k_vt_reduce<<<(unsigned)((nv + 63) / 64), WG, 0, st>>>(w->partials, nchunk, nv, B, D->D, w->DW, nact);
   int has_base = 0;
@@ -2958,7 +3033,8 @@ static void precond_rows(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, c
   }
   L.need(nchunk, B);
   L.timed(PK_LOWRANK, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m * (2 + has_base), [&] {
-    lowrank_rows<T, TV, false>(direct, g, st, m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials);
+    lowrank_rows<T, TV, false>(direct, g, st, m, B, rk, JW, V, w->DW, R2, Z2, has_base, rpc, nact, w->partials,
+                               nullptr, nullptr, 0, vr);
   });
   L.finalize(nchunk, B, ep, cs, nullptr, nact);
 }
@@ -3071,19 +3147,20 @@ static void precond_fused(Launcher& L, const TV* V, const T* R2, T* P2, int init
   while (JW < B && JW < WG) JW <<= 1;
   const int njt = (B + JW - 1) / JW;
   const bool direct = JW <= tuning().lr_direct;
+  const bf16* vr = direct ? vrow_factor(D, V) : nullptr;
   const int64_t rpc = lowrank_rows_rpc<T>(D, m, direct);
   const int nchunk = (int)((m + rpc - 1) / rpc);
   const int64_t nv = (int64_t)rk * B;
   dim3 g((unsigned)nchunk, (unsigned)njt);
   L.need(nchunk, nv);
   L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
-    vt_rows<T, TV>(direct, g, st, m, B, rk, JW, V, R2, rpc, w->partials, nact);
+    vt_rows<T, TV>(direct, g, st, m, B, rk, JW, V, R2, rpc, w->partials, nact, vr);
   });
   k_vt_reduce<<<(unsigned)((nv + 63) / 64), WG, 0, st>>>(w->partials, nchunk, nv, B, D->D, w->DW, nact, w->DW2);
   k_rz_lowrank<<<1, WG, 0, st>>>(rk, B, w->DW2, init, cs, nact);
   L.timed(PK_LOWRANK, pbytes, [&] {
     lowrank_rows<T, TV, true>(direct, g, st, m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr, cs.bcg,
-                              cs.active, init);
+                              cs.active, init, vr);
   });
 }
 

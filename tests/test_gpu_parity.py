@@ -557,22 +557,27 @@ for prec, up, rank in ((K.KATZ_PREC_FP64, 3, 16), (K.KATZ_PREC_FP64, 3, 32), (K.
                        (K.KATZ_PREC_FP64, 3, 20)):
     idx = K.KatzIndex.from_graph(g, beta_frac=0.9, rank=rank, labels=g.labels, max_block=32, precision=prec,
                                  u_precision=up)
-    qs = ki.sample_queries(g, 6, 7 + rank)
-    for j, q in enumerate(qs):
+    qs = ki.sample_queries(g, 8, 7 + rank)
+    for j, q in enumerate(qs[:6]):
         sc, st = idx.query([q], tol=1e-8)
         out["p%d_r%d_q%d" % (prec, rank, j)] = sc
         out["p%d_r%d_q%d_it" % (prec, rank, j)] = np.array([st[0]["iters"], st[0]["sweeps"]])
+    for nb in (2, 3, 8):
+        sc, st = idx.query(qs[:nb], tol=1e-8)
+        out["p%d_r%d_b%d" % (prec, rank, nb)] = sc
+        out["p%d_r%d_b%d_it" % (prec, rank, nb)] = np.array([[x["iters"], x["sweeps"]] for x in st])
     idx.close()
 np.savez(sys.argv[1], **out)
 """
 
 
 def test_row_major_factor_gives_identical_results(tmp_path):
-    """One-column solves read the BF16 low-rank factor from a row-major copy
-    (16-byte row loads) when the rank is 8, 16, 32 or 64; the column-major
-    reads (KATZ_VROW=0) take the same values in the same order, so scores and
-    iteration counts must be bit-identical.  Rank 20 has no row-major copy
-    and checks the fallback.  Each setting runs in a child process."""
+    """Solves of one to eight columns read the BF16 low-rank factor from a
+    row-major copy (16-byte row loads) when the rank is 8, 16, 32 or 64; the
+    column-major reads (KATZ_VROW=0) take the same values in the same order,
+    so scores and iteration counts must be bit-identical.  Rank 20 has no
+    row-major copy and checks the fallback.  Each setting runs in a child
+    process."""
     import os
     import subprocess
     import sys
