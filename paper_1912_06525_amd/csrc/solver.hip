@@ -1872,6 +1872,7 @@ struct Tuning {
   int m11_bpt;      // blocks per team and chunk of the batched small-block solve
   int autotune;     // tune the SpMM chunk walk per index (off when pinned by the environment)
   int m11_sub1;     // lanes per row of the A12 gather in the 1-3 column block solve
+  int m11_tile;     // rows per tile of the block solve for 2-15 columns
   int sparse_rhs;   // one-column Schur right-hand side from the rows b reaches
   int rec_res;      // precision form: residual updated by M d (FP32 d) per sweep
   int m11_small_min;  // narrowest batch taking the register block solve (5..513; default 16)
@@ -1900,6 +1901,7 @@ static const Tuning& tuning() {
     u.m11_bpt = env_int("KATZ_M11_BLOCKS_PER_TEAM", 1, 1, 64);
     u.autotune = env_int("KATZ_AUTOTUNE", 1, 0, 1) && !getenv("KATZ_XCD_SLAB") && !getenv("KATZ_SPMM_NWG");
     u.m11_sub1 = env_int("KATZ_M11_SUB", 4, 1, 16);
+    u.m11_tile = env_int("KATZ_M11_TILE", 64, 16, 256);
     u.sparse_rhs = env_int("KATZ_SPARSE_RHS", 1, 0, 1);
     u.rec_res = env_int("KATZ_REC_RES", 1, 0, 1);
     u.m11_small_min = env_int("KATZ_M11_SMALL_MIN", 16, 5, 513);
@@ -1988,6 +1990,10 @@ struct DeviceIndex {
   int32_t *rp = nullptr, *col = nullptr, *split = nullptr, *perm = nullptr, *iperm = nullptr;
   double* val = nullptr;
   int32_t *tile_row0 = nullptr, *row_blk = nullptr, *blk_start = nullptr;
+  // finer tiles (whole blocks, at most m11_tile rows unless one block is
+  // larger) for the block solve of 2-15 columns
+  int32_t* ntile_row0 = nullptr;
+  int n_ntiles = 0, max_ntile_rows = 0;
   int64_t* blk_off = nullptr;
   // blocks with more than kSmallBlock rows: one tile each, [big_row0, big_row1)
   int32_t *big_row0 = nullptr, *big_row1 = nullptr;
@@ -2199,6 +2205,21 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
     D->ntiles = (int)tiles.size() - 1;
     D->max_tile_rows = max_rows;
     D->tile_row0 = upload(D->allocs, tiles, by);
+    {
+      const int target = tuning().m11_tile;
+      std::vector<int32_t> nt{0};
+      for (int b = 0; b < nb; b++) {
+        const int32_t s = H.blk_start[b], e = H.blk_start[b + 1];
+        if (e - nt.back() > target && s > nt.back()) nt.push_back(s);
+      }
+      if (nt.back() != H.n1) nt.push_back(H.n1);
+      if (H.n1 == 0) nt.assign(1, 0);
+      int mr = 0;
+      for (size_t t = 0; t + 1 < nt.size(); t++) mr = std::max(mr, nt[t + 1] - nt[t]);
+      D->n_ntiles = (int)nt.size() - 1;
+      D->max_ntile_rows = mr;
+      D->ntile_row0 = upload(D->allocs, nt, by);
+    }
     D->row_blk = upload(D->allocs, row_blk, by);
     D->blk_start = upload(D->allocs, H.blk_start, by);
     D->blk_off = upload(D->allocs, H.blk_off, by);
@@ -3041,7 +3062,7 @@ static void precond_rows(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, c
 
 template <typename T, typename TV>
 static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep, const ColState& cs,
-                           const int* nact, int rpw, int nwg, bool dw_ready = false) {
+                           const int* nact, int rpw, int nwg) {
   DeviceIndex* D = L.D;
   Workspace* w = L.w;
   const int B = L.B, rk = D->rank;
@@ -3060,7 +3081,7 @@ static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep,
     L.need(nwg, std::max(1, rk));
   }
   const bf16* Vr = B == 1 ? vrow_factor(D, V) : nullptr;
-  if (rk > 0 && !dw_ready) {
+  if (rk > 0) {
     L.timed(PK_VT, (double)sizeof(TV) * m * rk + (double)sizeof(T) * B * m, [&] {
       if (Vr) vt1_vrow<T>(st, nwg, m, rk, Vr, R2, rpw, w->partials, nact);
       else if (B == 1 && rk <= 8) k_vt1<T, TV, 8><<<nwg, WG, 0, st>>>(m, rk, V, R2, rpw, w->partials, nact);
@@ -3248,10 +3269,16 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
     a.v = v; a.cv = cv; a.x2 = x2; a.ca = ca; a.out = out; a.B = B; a.n_active = nact;
     a.xcd = tuning().xcd;
     a.tile_row1 = nullptr;
-    int cb = std::max(1, std::min(B, (int)(32768 / sizeof(T) / std::max(1, D->max_tile_rows))));
+    // k_m11_apply for 2-15 columns: the finer tiles (more workgroups, fewer
+    // sequential passes each); one column keeps the 256-row tiles (measured
+    // faster there)
+    const bool fine = B >= 2 && B < 16;
+    if (fine) a.tile_row0 = D->ntile_row0;
+    const int tile_rows = fine ? D->max_ntile_rows : D->max_tile_rows;
+    int cb = std::max(1, std::min(B, (int)(32768 / sizeof(T) / std::max(1, tile_rows))));
     a.CB = cb;
     a.sub = cb >= 16 ? 1 : (cb >= 4 ? 2 : tuning().m11_sub1);
-    size_t shm = (size_t)D->max_tile_rows * cb * sizeof(T);
+    size_t shm = (size_t)tile_rows * cb * sizeof(T);
     const double wb = (double)sizeof(T) * B;
     double bytes = (double)sizeof(T) * D->minv_elems + 4.0 * n1 + wb * n1 + (v ? wb * n1 : 0.0) +
                    (x2 ? 8.0 * n1 + 4.0 * D->nnz_a12 + wb * D->cols_a12 : 0.0);
@@ -3317,7 +3344,7 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
         }
       });
     } else {
-      L.timed(PK_M11, bytes, [&] { k_m11_apply<T><<<D->ntiles, WG, shm, st>>>(a); });
+      L.timed(PK_M11, bytes, [&] { k_m11_apply<T><<<fine ? D->n_ntiles : D->ntiles, WG, shm, st>>>(a); });
     }
   };
   // z2 = G r2 + V (D o (V^T r2)), then <r2, z2> (EP_RZ_INIT / EP_RZ)
