@@ -275,8 +275,15 @@ void validate(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col, con
       if (rp[i + 1] < rp[i]) { bad = 1; break; }
   }, 8192);
   if (bad.load()) fail(KATZ_EINVAL, "row_ptr is not non-decreasing");
+  // symmetry: every entry (i, j) above the diagonal has its partner (j, i)
+  // with the same value (a binary search in row j), and there are as many
+  // entries below the diagonal as above.  The partners of distinct upper
+  // entries are distinct lower entries, so equal counts make every lower
+  // entry a partner: one search per pair instead of one per entry.
   std::atomic<int> asym{0};
+  std::atomic<int64_t> n_upper{0}, n_lower{0};
   parallel_for(n, [&](int64_t b, int64_t e) {
+    int64_t up = 0, lo = 0;
     for (int64_t i = b; i < e && !bad.load(std::memory_order_relaxed); i++) {
       int32_t s = rp[i], t = rp[i + 1];
       int32_t last = -1;
@@ -287,14 +294,18 @@ void validate(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col, con
         if (j == i) { bad = 4; break; }
         if (val && !(val[k] >= 0.0 && std::isfinite(val[k]))) { bad = 5; break; }
         last = j;
-        // symmetric partner (j, i) with the same value
+        if (j < i) { lo++; continue; }
+        up++;
         const int32_t* rb = col + rp[j];
         const int32_t* re = col + rp[j + 1];
         const int32_t* f = std::lower_bound(rb, re, (int32_t)i);
         if (f == re || *f != i || (val && val[f - col] != val[k])) asym = 1;
       }
     }
+    n_upper += up;
+    n_lower += lo;
   }, 2048);
+  if (n_upper.load() != n_lower.load()) asym = 1;
   switch (bad.load()) {
     case 2: fail(KATZ_EINVAL, "column index out of range");
     case 3: fail(KATZ_EINVAL, "columns must be strictly increasing within a row");
@@ -353,11 +364,10 @@ double lambda_max(int32_t n, const int32_t* rp, const int32_t* col, const double
       if (resid <= 1e-13 * std::fabs(theta) || bj <= 1e-14 * std::fabs(a)) break;
     }
     if (bj == 0.0) break;
-    for (int32_t i = 0; i < n; i++) {
-      double t = w[i] / bj;
-      qp[i] = q[i];
-      q[i] = t;
-    }
+    qp.swap(q);  // the previous vector; q = w / bj below
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; i++) q[i] = w[i] / bj;
+    });
     bprev = bj;
   }
   return theta;

@@ -192,6 +192,14 @@ def test_error_codes():
     with pytest.raises(K.KatzError) as e:
         K.KatzIndex(2, [0, 1, 1], [1], beta=0.1, device=-1)
     assert e.value.code == K.KATZ_ENOTSYM
+    # an entry below the diagonal only, a triangle with one direction missing,
+    # and a weighted pair whose two values differ
+    for n_, rp_, col_, val_ in ((2, [0, 0, 1], [0], None),
+                                (3, [0, 2, 3, 4], [1, 2, 0, 1], None),
+                                (2, [0, 1, 2], [1, 0], [1.0, 2.0])):
+        with pytest.raises(K.KatzError) as e:
+            K.KatzIndex(n_, rp_, col_, val_, beta=0.1, device=-1)
+        assert e.value.code == K.KATZ_ENOTSYM, (rp_, col_)
     with pytest.raises(K.KatzError) as e:
         K.KatzIndex(2, [0, 2, 2], [0, 1], beta=0.1, device=-1)
     assert e.value.code == K.KATZ_EINVAL
