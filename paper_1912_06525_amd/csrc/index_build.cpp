@@ -330,27 +330,54 @@ void spmv(int32_t n, const int32_t* rp, const int32_t* col, const double* val, c
   }, 8192);
 }
 
+// The vector work of lambda_max on the host: q, the previous vector qp and w
+// in host memory, the products and sums on all host cores.
+struct HostLambdaOps : LambdaOps {
+  int32_t n;
+  const int32_t *rp, *col;
+  const double* val;
+  std::vector<double> q, qp, w;
+  HostLambdaOps(int32_t n_, const int32_t* rp_, const int32_t* col_, const double* val_)
+      : n(n_), rp(rp_), col(col_), val(val_), q(n_), qp(n_, 0.0), w(n_) {}
+  void start(const double* q0) override { std::copy(q0, q0 + n, q.begin()); }
+  double apply_dot() override {
+    spmv(n, rp, col, val, q.data(), w.data());
+    return dot(q.data(), w.data(), n);
+  }
+  double update_norm2(double a, double bprev) override {
+    parallel_for(n, [&](int64_t b, int64_t e) {
+      for (int64_t i = b; i < e; i++) w[i] -= a * q[i] + bprev * qp[i];
+    });
+    return dot(w.data(), w.data(), n);
+  }
+  void advance(double bj) override {
+    qp.swap(q);  // the previous vector; q = w / bj
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; i++) q[i] = w[i] / bj;
+    });
+  }
+};
+
+}  // namespace
+
 // Largest eigenvalue of A by Lanczos without reorthogonalisation (the top Ritz
 // value is unaffected by the loss of orthogonality, which only duplicates
-// converged values).  Stops when the Ritz residual bound is below 1e-13 of the
-// Ritz value.
-double lambda_max(int32_t n, const int32_t* rp, const int32_t* col, const double* val, uint64_t seed) {
-  if (rp[n] == 0) return 0.0;
-  std::vector<double> q(n), qp(n, 0.0), w(n);
+// converged values), the vector work done by `ops`.  Stops when the Ritz
+// residual bound is below 1e-13 of the Ritz value.
+double lambda_max_with(int32_t n, uint64_t seed, LambdaOps& ops) {
+  std::vector<double> q(n);
   Rng rng{seed ^ 0x5A5A5A5AULL};
   for (int32_t i = 0; i < n; i++) q[i] = 0.5 + rng.unif();  // positive start: overlaps the Perron vector
   double nq = std::sqrt(dot(q.data(), q.data(), n));
   for (auto& v : q) v /= nq;
+  ops.start(q.data());
+  std::vector<double>().swap(q);
   std::vector<double> al, be;
   double theta = 0, bprev = 0;
   const int mmax = std::min<int64_t>(600, n);
   for (int j = 0; j < mmax; j++) {
-    spmv(n, rp, col, val, q.data(), w.data());
-    double a = dot(q.data(), w.data(), n);
-    parallel_for(n, [&](int64_t b, int64_t e) {
-      for (int64_t i = b; i < e; i++) w[i] -= a * q[i] + bprev * qp[i];
-    });
-    double bj = std::sqrt(dot(w.data(), w.data(), n));
+    const double a = ops.apply_dot();
+    const double bj = std::sqrt(ops.update_norm2(a, bprev));
     al.push_back(a);
     be.push_back(bj);
     int m = (int)al.size();
@@ -364,13 +391,18 @@ double lambda_max(int32_t n, const int32_t* rp, const int32_t* col, const double
       if (resid <= 1e-13 * std::fabs(theta) || bj <= 1e-14 * std::fabs(a)) break;
     }
     if (bj == 0.0) break;
-    qp.swap(q);  // the previous vector; q = w / bj below
-    parallel_for(n, [&](int64_t lo, int64_t hi) {
-      for (int64_t i = lo; i < hi; i++) q[i] = w[i] / bj;
-    });
+    ops.advance(bj);
     bprev = bj;
   }
   return theta;
+}
+
+namespace {
+
+double lambda_max(int32_t n, const int32_t* rp, const int32_t* col, const double* val, uint64_t seed) {
+  if (rp[n] == 0) return 0.0;
+  HostLambdaOps ops(n, rp, col, val);
+  return lambda_max_with(n, seed, ops);
 }
 
 // ------------------------------------------------------------- partition
@@ -952,7 +984,12 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
   H.precision = o.precision;
   H.u_precision_req = o.u_precision;
   H.u_precision = o.u_precision == 0 ? 2 : o.u_precision;  // auto: settled in lanczos_ritz
-  H.lambda_max = lambda_max(n, row_ptr, col, val, o.seed);
+  // large graphs with a device: the Lanczos vectors and products on the GPU
+  // (the same steps and stopping rule; sums in a fixed order)
+  int lam_dev = o.device >= 0 && n >= kLambdaDeviceMin && row_ptr[n] > 0;
+  if (const char* e = getenv("KATZ_LAMBDA_DEVICE")) lam_dev = lam_dev && atoi(e) != 0;
+  H.lambda_max = lam_dev ? device_lambda_max(o.device, n, nnz, row_ptr, col, val, o.seed)
+                         : lambda_max(n, row_ptr, col, val, o.seed);
   if (o.beta > 0) {
     H.beta = o.beta;
   } else {

@@ -76,6 +76,24 @@ bool lanczos_on_device(const HostIndex& H, const katz_build_opts& o);
 void save_host_index(const HostIndex& H, const char* path);
 void load_host_index(const char* path, HostIndex& H);
 
+// ------------------------------------------------------------ lambda_max
+// The vector work of the Lanczos iteration for lambda_max(A) (host or
+// device storage): start from q0 (unit norm), w = A q with <q, w>,
+// w -= a q + bprev qp with <w, w>, then qp = q, q = w / bj.
+struct LambdaOps {
+  virtual ~LambdaOps() = default;
+  virtual void start(const double* q0) = 0;
+  virtual double apply_dot() = 0;
+  virtual double update_norm2(double a, double bprev) = 0;
+  virtual void advance(double bj) = 0;
+};
+double lambda_max_with(int32_t n, uint64_t seed, LambdaOps& ops);
+// Graphs of at least this many nodes take lambda_max on the device when the
+// build has one (KATZ_LAMBDA_DEVICE=0: on the host).
+constexpr int32_t kLambdaDeviceMin = 2000000;
+double device_lambda_max(int device, int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                         const double* val, uint64_t seed);
+
 // ------------------------------------------------------- device index
 struct DeviceIndex;            // defined in the HIP solver
 DeviceIndex* device_upload(const HostIndex& H, int device);

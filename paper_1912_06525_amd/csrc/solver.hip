@@ -4345,6 +4345,154 @@ __global__ __launch_bounds__(WG) void k_ritz(int64_t m, int mm, int r, const dou
     if (t0 + t < r) U[i * r + t0 + t] = acc[t];
 }
 
+// ------------------------------------------------ lambda_max (device)
+// The vector work of the Lanczos iteration for lambda_max(A) on the caller's
+// CSR (original order), for large graphs at index build.  Every sum is
+// taken in a fixed order: kLamWG workgroups over contiguous row ranges, each
+// reduced by a fixed tree, the per-workgroup values summed on the host in
+// order.
+constexpr int kLamWG = 2048;
+constexpr int kLamTS = 8;  // lanes per row of the product
+
+// y = A x (kLamTS lanes per row) and partials[bid] = sum over the
+// workgroup's rows of x_i y_i.
+__global__ __launch_bounds__(WG) void k_lam_spmv(int32_t n, int64_t rows_per_wg, const int32_t* rp,
+                                                 const int32_t* col, const double* val, const double* x,
+                                                 double* y, double* partials) {
+  __shared__ double sh[WG / 64];
+  const int tid = threadIdx.x, lane = tid % kLamTS, team = tid / kLamTS;
+  constexpr int TEAMS = WG / kLamTS;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(n, r0 + rows_per_wg);
+  double acc = 0.0;
+  for (int64_t i = r0 + team; i < r1; i += TEAMS) {
+    double s = 0.0;
+    for (int32_t k = rp[i] + lane; k < rp[i + 1]; k += kLamTS) s += (val ? val[k] : 1.0) * x[col[k]];
+#pragma unroll
+    for (int off = 1; off < kLamTS; off <<= 1) s += __shfl_xor(s, off, kLamTS);
+    if (lane == 0) {
+      y[i] = s;
+      acc += x[i] * s;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (tid % 64 == 0) sh[tid / 64] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int wv = 0; wv < WG / 64; wv++) t += sh[wv];
+    partials[blockIdx.x] = t;
+  }
+}
+
+// w -= a q + b qp and partials[bid] = sum over the workgroup's rows of w_i^2.
+__global__ __launch_bounds__(WG) void k_lam_update(int32_t n, int64_t rows_per_wg, double a, double b,
+                                                   const double* q, const double* qp, double* w,
+                                                   double* partials) {
+  __shared__ double sh[WG / 64];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = min<int64_t>(n, r0 + rows_per_wg);
+  double acc = 0.0;
+  for (int64_t i = r0 + tid; i < r1; i += WG) {
+    const double v = w[i] - (a * q[i] + b * qp[i]);
+    w[i] = v;
+    acc += v * v;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (tid % 64 == 0) sh[tid / 64] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int wv = 0; wv < WG / 64; wv++) t += sh[wv];
+    partials[blockIdx.x] = t;
+  }
+}
+
+// q = w / bj
+__global__ __launch_bounds__(WG) void k_lam_scale(int32_t n, double bj, const double* w, double* q) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) q[i] = w[i] / bj;
+}
+
+namespace {
+struct DeviceLambdaOps : LambdaOps {
+  int32_t n;
+  int64_t rpw;
+  const int32_t *rp, *col;
+  const double* val;
+  double *q, *qp, *w, *part;
+  double* hpart;
+  hipStream_t st;
+  double host_sum() {
+    HIPCHECK(hipMemcpyAsync(hpart, part, sizeof(double) * kLamWG, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (int b = 0; b < kLamWG; b++) s += hpart[b];
+    return s;
+  }
+  void start(const double* q0) override {
+    HIPCHECK(hipMemcpyAsync(q, q0, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    k_fill<double><<<grid_for(n, WG * 4), WG, 0, st>>>(qp, (int64_t)n, 0.0);
+    HIPCHECK(hipStreamSynchronize(st));  // q0 is the caller's host memory
+  }
+  double apply_dot() override {
+    k_lam_spmv<<<kLamWG, WG, 0, st>>>(n, rpw, rp, col, val, q, w, part);
+    return host_sum();
+  }
+  double update_norm2(double a, double bprev) override {
+    k_lam_update<<<kLamWG, WG, 0, st>>>(n, rpw, a, bprev, q, qp, w, part);
+    return host_sum();
+  }
+  void advance(double bj) override {
+    std::swap(q, qp);  // the previous vector; q = w / bj
+    k_lam_scale<<<grid_for(n, WG * 4), WG, 0, st>>>(n, bj, w, q);
+  }
+};
+}  // namespace
+
+double device_lambda_max(int device, int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                         const double* val, uint64_t seed) {
+  std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
+  HIPCHECK(hipSetDevice(device));
+  std::vector<void*> tmp;
+  hipStream_t st = nullptr;
+  double* hpart = nullptr;
+  struct Freer {
+    std::vector<void*>& v;
+    hipStream_t& st;
+    double*& h;
+    ~Freer() {
+      for (void* p : v) (void)hipFree(p);
+      if (h) (void)hipHostFree(h);
+      if (st) (void)hipStreamDestroy(st);
+    }
+  } freer{tmp, st, hpart};
+  HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  HIPCHECK(hipHostMalloc((void**)&hpart, sizeof(double) * kLamWG, hipHostMallocDefault));
+  DeviceLambdaOps ops;
+  ops.n = n;
+  ops.rpw = ((int64_t)n + kLamWG - 1) / kLamWG;
+  ops.st = st;
+  ops.hpart = hpart;
+  int32_t* drp = dalloc<int32_t>(tmp, (int64_t)n + 1);
+  int32_t* dcol = dalloc<int32_t>(tmp, nnz);
+  double* dval = val ? dalloc<double>(tmp, nnz) : nullptr;
+  HIPCHECK(hipMemcpyAsync(drp, rp, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemcpyAsync(dcol, col, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, st));
+  if (val) HIPCHECK(hipMemcpyAsync(dval, val, sizeof(double) * (size_t)nnz, hipMemcpyHostToDevice, st));
+  ops.rp = drp;
+  ops.col = dcol;
+  ops.val = dval;
+  ops.q = dalloc<double>(tmp, n);
+  ops.qp = dalloc<double>(tmp, n);
+  ops.w = dalloc<double>(tmp, n);
+  ops.part = dalloc<double>(tmp, kLamWG);
+  const double lam = lambda_max_with(n, seed, ops);
+  HIPCHECK(hipStreamSynchronize(st));
+  HIPCHECK(hipGetLastError());
+  return lam;
+}
+
 void device_lanczos_R(HostIndex& H, DeviceIndex* D) {
   auto t0 = std::chrono::steady_clock::now();
   HIPCHECK(hipSetDevice(D->device));

@@ -244,3 +244,26 @@ def test_dcsbm_quarter_serving_top100_vs_oracle():
         assert ok, (i, j, qn[t], msg)
     _say("  %d top-100 lists equal the oracle's under the tie rule" % len(checks))
     idx.close()
+
+
+@pytest.mark.timeout(300)
+def test_device_lambda_max_matches_host_and_oracle():
+    """Graphs of 2M nodes and more take lambda_max (which fixes beta from
+    beta_frac) on the device at index build: the same Lanczos steps and stop
+    rule as the host, with sums in a fixed order.  Against the host build
+    (device -1) and the oracle's multi-core Lanczos, unweighted and
+    weighted."""
+    g = ki.chung_lu(2_100_000, 2.5, 8, seed=13)
+    w = ki.edge_weights(g, seed=5)
+    for val in (None, w):
+        _say("lambda_max, %s" % ("weighted" if val is not None else "unweighted"))
+        idx = K.KatzIndex.from_graph(g, val=val, beta_frac=0.5, rank=0, max_block=64)
+        lam_dev = idx.info.lambda_max
+        idx.close()
+        idx = K.KatzIndex.from_graph(g, val=val, beta_frac=0.5, rank=0, max_block=64, device=-1)
+        lam_host = idx.info.lambda_max
+        idx.close()
+        ref = oracle.lambda_max_mt(g.n, g.row_ptr, g.col, val)["lambda"]
+        _say("  device %.15g host %.15g oracle %.15g" % (lam_dev, lam_host, ref))
+        assert abs(lam_dev - lam_host) <= 1e-12 * lam_host
+        assert abs(lam_dev - ref) <= 1e-9 * ref
