@@ -205,7 +205,8 @@ def main():
             entry[name] = {"qps": args.steps / el, "ms_per_query": el * 1e3 / args.steps,
                            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
                            "latency_queries": nl,
-                           "iters_median": float(np.median(its + its2)), "iters_max": int(np.max(its + its2)),
+                           "iters_median": float(np.median(its + its2)),
+                           "iters_p99": float(np.percentile(its + its2, 99)), "iters_max": int(np.max(its + its2)),
                            "max_rel_residual": float(np.max(res + res2))}
             log("  %s: %.1f q/s, %.3f ms/query, p50 %.3f p99 %.3f ms over %d, iters median %g"
                 % (name, entry[name]["qps"], entry[name]["ms_per_query"], entry[name]["p50_ms"],
@@ -264,6 +265,7 @@ def main():
                 K.katz_profile_enable(False)
                 tab = kernel_rows(K)
                 entry[name]["kernels"] = tab
+                entry[name]["path_roofline"] = path_roofline(tab, args.steps, entry[name]["qps"])
                 if name == "lrc":
                     kernel_table = tab
         if c == head_c and not args.no_cpu:
@@ -326,10 +328,13 @@ def main():
                        "lrc_qps": round(head["lrc"].get("concurrent_qps", 0.0), 2),
                        "cg_qps": round(head["cg"].get("concurrent_qps", 0.0), 2)} if args.concurrency > 1 else None,
         "roofline": roofline,
+        "path_roofline": {m: head[m].get("path_roofline") for m in ("lrc", "cg")},
+        "iters": {m: {"median": head[m]["iters_median"], "p99": head[m]["iters_p99"]} for m in ("lrc", "cg")},
         "cpu_baseline": cpu["baseline"] if cpu else None,
         "parity_ok": all(parity) if parity else None,
         "legs": {k: {"lrc_qps": v["lrc"]["qps"], "cg_qps": v["cg"]["qps"], "lrc_over_cg": v["lrc_over_cg"],
                      "roofline_frac": (v.get("roofline") or {}).get("frac"),
+                     "path_frac": {m: (v[m].get("path_roofline") or {}).get("frac") for m in ("lrc", "cg")},
                      "max_rel_err_vs_oracle": v.get("max_rel_err_vs_oracle")} for k, v in legs.items()},
         "results": results,
     }
@@ -347,6 +352,16 @@ def kernel_rows(K):
         r["alg_bytes_per_launch"] = r["alg_bytes"] / r["launches"]
         r["achieved_GBs"] = r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
     return tab
+
+
+def path_roofline(tab, queries, qps):
+    """Path-level roofline: the algorithmic bytes of every profiled kernel per
+    query (the profiled pass solved `queries` queries), and queries/s as a
+    fraction of 8 TB/s over those bytes."""
+    per_query = sum(r["alg_bytes"] for r in tab) / max(1, queries)
+    return {"alg_bytes_per_query": per_query,
+            "roof_qps": HBM_PEAK_GBS * 1e9 / per_query if per_query > 0 else None,
+            "frac": round(qps * per_query / (HBM_PEAK_GBS * 1e9), 4) if per_query > 0 else None}
 
 
 def roofline_of(tab, workload_key, copy_gbs):
@@ -971,6 +986,7 @@ def run_leg(leg, args, torch, K, ki, dev, copy_gbs):
             K.katz_profile_enable(False)
             tab = kernel_rows(K)
             entry[name]["kernels"] = tab
+            entry[name]["path_roofline"] = path_roofline(tab, B, entry[name]["qps"])
             if name == "lrc":
                 wk = wl if args.scale == 1.0 else "%s_s%g" % (wl, args.scale)
                 entry["roofline"] = roofline_of(tab, "%s_b%d_c%g" % (wk, B, c), copy_gbs)
