@@ -497,7 +497,7 @@ __global__ __launch_bounds__(WG) void k_update_r(int64_t m, int B, int rows_per_
       const int j = cl + cm.CL * c;
       if (j < B && act[c]) {
         const int64_t o = i * B + j;
-        x[o] += al[c] * p[o];
+        if (x) x[o] += al[c] * p[o];  // NULL: done with the search-direction update
         T rv = r[o] - al[c] * q[o];
         r[o] = rv;
         dacc[c] += (double)rv * (double)rv;
@@ -630,18 +630,34 @@ __global__ __launch_bounds__(WG) void k_update_r_vt1(int64_t m, int rows_per_wg,
 
 // p = z + bcg p on the active columns; init: p = z on them (a column whose
 // start residual already meets its threshold is inactive and keeps its p).
+// x (non-NULL, not at init): also x += alpha p with the old p on the columns
+// whose step this iteration set (fresh), active or just converged.
 template <typename T>
-__global__ __launch_bounds__(WG) void k_update_p(int64_t m, int B, const T* z, T* p, int init, ColState cs) {
-  if (!init && *cs.n_active == 0) return;
+__global__ __launch_bounds__(WG) void k_update_p(int64_t m, int B, const T* z, T* p, int init, ColState cs,
+                                                 T* x = nullptr, const int* fresh = nullptr) {
+  if (!init && *cs.n_active == 0 && !x) return;
   const ColMap cm = colmap(B);
   const int tid = threadIdx.x, cl = tid % cm.CL, rg = tid / cm.CL;
   for (int c = 0; c < cm.NCL; c++) {
     const int j = cl + cm.CL * c;
-    if (j >= B || !cs.active[j]) continue;
-    const T b = init ? (T)0 : (T)cs.bcg[j];
-    for (int64_t i = (int64_t)blockIdx.x * cm.RG + rg; i < m; i += (int64_t)gridDim.x * cm.RG) {
-      const int64_t o = i * B + j;
-      p[o] = init ? z[o] : z[o] + b * p[o];
+    if (j >= B) continue;
+    const bool on = cs.active[j] != 0, xu = x && !init, xf = xu && fresh[j];
+    if (!on && !xf) continue;
+    // a just-converged column (xf, not on) gets p = z: its p is not read again
+    const T b = (init || !on) ? (T)0 : (T)cs.bcg[j];
+    const T al = xf ? (T)cs.alpha[j] : (T)0;
+    if (xu) {
+      for (int64_t i = (int64_t)blockIdx.x * cm.RG + rg; i < m; i += (int64_t)gridDim.x * cm.RG) {
+        const int64_t o = i * B + j;
+        const T po = p[o];
+        x[o] += al * po;
+        p[o] = z[o] + b * po;
+      }
+    } else {
+      for (int64_t i = (int64_t)blockIdx.x * cm.RG + rg; i < m; i += (int64_t)gridDim.x * cm.RG) {
+        const int64_t o = i * B + j;
+        p[o] = init ? z[o] : z[o] + b * p[o];
+      }
     }
   }
 }
@@ -1343,18 +1359,26 @@ __global__ __launch_bounds__(WG) void k_vt_reduce(const double* partials, int nc
 // (p <- z_new + bcg p, p <- z_new at init) for the active columns, no partials.
 // DIRECT: as in k_vt_rows (factor loads of a row issued together, no LDS
 // tile); the same value per element (DW is 0 past the rank).
-template <typename T, typename TV, int RMAX, bool PUPD = false, bool DIRECT = false, bool VR = false>
+// PUPD with XUP (never at init): also xk += alpha p with the old p on the
+// columns whose step this iteration set (fresh), active or just converged.
+template <typename T, typename TV, int RMAX, bool PUPD = false, bool DIRECT = false, bool VR = false,
+          bool XUP = false>
 __global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank, int JW, const TV* V,
-                                                     const double* DW, const T* r, T* z, int z_has_base,
-                                                     int64_t rpc, const int* n_active, double* partials,
-                                                     const double* bcg = nullptr, const int* active = nullptr,
-                                                     int init = 0) {
-  if (n_active && *n_active == 0) return;
+                                                     const double* DW, const T* __restrict__ r, T* __restrict__ z,
+                                                     int z_has_base, int64_t rpc, const int* n_active,
+                                                     double* partials, const double* bcg = nullptr,
+                                                     const int* active = nullptr, int init = 0,
+                                                     T* __restrict__ xk = nullptr, const double* alpha = nullptr,
+                                                     const int* fresh = nullptr) {
+  if (!XUP && n_active && *n_active == 0) return;
   constexpr int LD = RMAX + 2;
   __shared__ double sV[kVRows * LD];
   const int tid = threadIdx.x, jl = tid % JW, rg = tid / JW, NR = WG / JW;
   const int j = blockIdx.y * JW + jl;
   const bool col_ok = j < B && (!PUPD || active[j]);
+  constexpr bool xu = PUPD && XUP;  // XUP: never at init
+  const bool xf = xu && j < B && fresh[j];
+  const T xal = xf ? (T)alpha[j] : (T)0;
   const double b = PUPD && !init && col_ok ? bcg[j] : 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * rpc, r1 = min<int64_t>(m, r0 + rpc);
   double dw[RMAX];
@@ -1362,7 +1386,7 @@ __global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank,
   for (int k = 0; k < RMAX; k++) dw[k] = (col_ok && k < rank) ? DW[(int64_t)k * B + j] : 0.0;
   double dacc = 0.0;
   if (DIRECT) {
-    if (col_ok) {
+    if (col_ok || xf) {
       for (int64_t i = r0 + rg; i < r1; i += NR) {
         double vd[RMAX];
         if constexpr (VR) {
@@ -1379,12 +1403,16 @@ __global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank,
         }
         const int64_t o = i * B + j;
         const double rv = (double)r[o];
-        const double pv = PUPD && !init ? (double)z[o] : 0.0;
+        const T po = PUPD && !init ? z[o] : (T)0;
+        const double pv = (double)po;
         double sum = !PUPD && z_has_base ? (double)z[o] : rv;
         __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the FMAs
 #pragma unroll
         for (int k = 0; k < RMAX; k++) sum += vd[k] * dw[k];
         if (PUPD) {
+          // a just-converged column (xf, not col_ok) gets z = r: its p is
+          // not read again
+          if constexpr (xu) xk[o] += xal * po;
           z[o] = (T)(sum + b * pv);
         } else {
           const T zv = (T)sum;
@@ -1399,16 +1427,18 @@ __global__ __launch_bounds__(WG) void k_lowrank_rows(int64_t m, int B, int rank,
       __syncthreads();
       stage_v<TV, RMAX>(sV, V, m, rank, b0, nb);
       __syncthreads();
-      if (col_ok) {
+      if (col_ok || xf) {
         for (int ii = rg; ii < nb; ii += NR) {
           const int64_t o = (b0 + ii) * B + j;
           const double rv = (double)r[o];
-          const double pv = PUPD && !init ? (double)z[o] : 0.0;
+          const T po = PUPD && !init ? z[o] : (T)0;
+          const double pv = (double)po;
           double sum = !PUPD && z_has_base ? (double)z[o] : rv;
           const double* vr = sV + ii * LD;
 #pragma unroll
           for (int k = 0; k < RMAX; k++) sum += vr[k] * dw[k];
           if (PUPD) {
+            if constexpr (xu) xk[o] += xal * po;
             z[o] = (T)(sum + b * pv);
           } else {
             const T zv = (T)sum;
@@ -1628,7 +1658,7 @@ __device__ inline void rz_from_terms(int rank, int B, const double* DW2, int ini
 
 __global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int nwg, int nv, int ep, ColState cs,
                                                      int B, double* out, const double* D, const int* n_active,
-                                                     double* out2, int rz_mode) {
+                                                     double* out2, int rz_mode, int* fresh) {
   if (n_active && *n_active == 0) return;
   final_reduce<kFinWG>(partials, nwg, nv, [&](int j, double s) {
     switch (ep) {
@@ -1648,6 +1678,7 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(const double* partials, int
             cs.active[j] = 0;
           } else {
             cs.alpha[j] = cs.rz[j] / s;
+            if (fresh) fresh[j] = 1;
           }
         }
         break;
@@ -1873,6 +1904,7 @@ struct Tuning {
   int autotune;     // tune the SpMM chunk walk per index (off when pinned by the environment)
   int m11_sub1;     // lanes per row of the A12 gather in the 1-3 column block solve
   int m11_tile;     // rows per tile of the block solve for 2-15 columns
+  int defer_x;      // batched LRC: x += alpha p with the search-direction update
   int sparse_rhs;   // one-column Schur right-hand side from the rows b reaches
   int rec_res;      // precision form: residual updated by M d (FP32 d) per sweep
   int m11_small_min;  // narrowest batch taking the register block solve (5..513; default 16)
@@ -1902,6 +1934,7 @@ static const Tuning& tuning() {
     u.autotune = env_int("KATZ_AUTOTUNE", 1, 0, 1) && !getenv("KATZ_XCD_SLAB") && !getenv("KATZ_SPMM_NWG");
     u.m11_sub1 = env_int("KATZ_M11_SUB", 4, 1, 16);
     u.m11_tile = env_int("KATZ_M11_TILE", 64, 16, 256);
+    u.defer_x = env_int("KATZ_DEFER_X", 1, 0, 1);
     u.sparse_rhs = env_int("KATZ_SPARSE_RHS", 1, 0, 1);
     u.rec_res = env_int("KATZ_REC_RES", 1, 0, 1);
     u.m11_small_min = env_int("KATZ_M11_SMALL_MIN", 16, 5, 513);
@@ -1955,6 +1988,9 @@ struct Workspace {
   double *rz, *pq, *alpha, *bcg, *rr, *thr, *bn2, *res2, *colscale, *rn2, *inv, *fwd;
   float* Rf = nullptr;             // scaled FP32 right-hand side (precision form)
   int *active, *status, *iters, *n_active, *mask;
+  // batched LRC: columns whose step alpha was set by this iteration's S p
+  // (their x += alpha p rides on the search-direction update)
+  int* fresh = nullptr;
   int32_t* qpos = nullptr;
   void* tk_scratch = nullptr;    // top-K selection state and winners
   size_t tk_cap = 0;
@@ -2391,8 +2427,9 @@ static std::unique_ptr<Workspace> make_ws(DeviceIndex* D, int B) {
   w->thr = s + 5 * B; w->bn2 = s + 6 * B; w->res2 = s + 7 * B; w->colscale = s + 8 * B;
   w->rn2 = s + 9 * B; w->inv = s + 10 * B; w->fwd = s + 11 * B;
   if (D->precision == KATZ_PREC_MIXED) w->Rf = dalloc<float>(L, nB);
-  int* ip = dalloc<int>(L, 4 * (int64_t)B + 1);
+  int* ip = dalloc<int>(L, 5 * (int64_t)B + 1);
   w->active = ip; w->status = ip + B; w->iters = ip + 2 * B; w->mask = ip + 3 * B; w->n_active = ip + 4 * B;
+  w->fresh = ip + 4 * B + 1;
   w->qpos = dalloc<int32_t>(L, B);
   HIPCHECK(hipHostMalloc(&w->hpin, 64 * 1024, hipHostMallocDefault));
   HIPCHECK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
@@ -2440,6 +2477,7 @@ struct Launcher {
   hipStream_t st;
   int B;
   int iter_hint = 0;  // first poll of the adaptive schedule (0: default)
+  int* fresh_out = nullptr;  // EP_PQ finalizes flag the columns given a step here
 
   ColState cs(int max_iter) const {
     ColState c;
@@ -2512,7 +2550,8 @@ struct Launcher {
       src = w->seg;
       nwg = (int)nseg;
     }
-    k_finalize<<<1, kFinWG, 0, st>>>(src, nwg, nv, ep, cs, B, out, D->D, nact, out2, rz_mode);
+    k_finalize<<<1, kFinWG, 0, st>>>(src, nwg, nv, ep, cs, B, out, D->D, nact, out2, rz_mode,
+                                     ep == EP_PQ ? fresh_out : nullptr);
   }
 
   // SpMM kernel variant for this batch width: team size TS, column lanes CW,
@@ -2700,6 +2739,15 @@ struct Launcher {
     int best = 0;
     for (int c = 1; c < kCand; c++)
       if (ms[c] < 0.97f * ms[best]) best = c;
+    if (best != 0) {
+      // among the slab walks within 3% of the fastest, the one over the most
+      // workgroups: back-to-back launches find the caches warm, which
+      // flatters a narrow window; in the solve other kernels run between
+      // (4M-node SBM at 256 columns: 1,024 workgroups beat 512 by 2% there)
+      const float bms = ms[best];
+      for (int c = 1; c < kCand; c++)
+        if (ms[c] <= 1.03f * bms && walk_nwg(cand[c]) > walk_nwg(cand[best])) best = c;
+    }
     if (getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 0)
       fprintf(stderr, "[katz] SpMM walk, variant %d, rows %d..%d, B %d: default %.3f ms, xcd slabs x%d %.3f ms, "
                       "x%d %.3f ms, x%d %.3f ms, x%d %.3f ms -> candidate %d\n", v.slot, a.row0, a.row1, B,
@@ -2893,22 +2941,49 @@ static void launch_vt_rows(dim3 g, hipStream_t st, int64_t m, int B, int rk, int
   else if (rk <= 32) k_vt_rows<T, TV, 32, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
   else k_vt_rows<T, TV, 64, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, R2, rpc, partials, nact);
 }
+// XU: the deferred x update of k_lowrank_rows (xk, alpha, fresh)
+struct XU {
+  void* xk = nullptr;
+  const double* alpha = nullptr;
+  const int* fresh = nullptr;
+};
+template <typename T, typename TV, bool PUPD, bool DIRECT, bool VR = false, bool XUP = false>
+static void launch_lowrank_rows_x(dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V,
+                                  const double* DW, const T* R2, T* Z2, int has_base, int64_t rpc,
+                                  const int* nact, double* partials, const double* bcg, const int* active, int init,
+                                  XU xu) {
+  T* xk = (T*)xu.xk;
+  if (rk <= 8)
+    k_lowrank_rows<T, TV, 8, PUPD, DIRECT, VR, XUP><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc,
+                                                                      nact, partials, bcg, active, init, xk,
+                                                                      xu.alpha, xu.fresh);
+  else if (rk <= 16)
+    k_lowrank_rows<T, TV, 16, PUPD, DIRECT, VR, XUP><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc,
+                                                                       nact, partials, bcg, active, init, xk,
+                                                                       xu.alpha, xu.fresh);
+  else if (rk <= 32)
+    k_lowrank_rows<T, TV, 32, PUPD, DIRECT, VR, XUP><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc,
+                                                                       nact, partials, bcg, active, init, xk,
+                                                                       xu.alpha, xu.fresh);
+  else
+    k_lowrank_rows<T, TV, 64, PUPD, DIRECT, VR, XUP><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc,
+                                                                       nact, partials, bcg, active, init, xk,
+                                                                       xu.alpha, xu.fresh);
+}
+// xu.xk set (PUPD, not at init): the variant that also takes x += alpha p
 template <typename T, typename TV, bool PUPD, bool DIRECT, bool VR = false>
 static void launch_lowrank_rows(dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V,
                                 const double* DW, const T* R2, T* Z2, int has_base, int64_t rpc, const int* nact,
-                                double* partials, const double* bcg, const int* active, int init) {
-  if (rk <= 8)
-    k_lowrank_rows<T, TV, 8, PUPD, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
-                                                                 partials, bcg, active, init);
-  else if (rk <= 16)
-    k_lowrank_rows<T, TV, 16, PUPD, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc,
-                                                                  nact, partials, bcg, active, init);
-  else if (rk <= 32)
-    k_lowrank_rows<T, TV, 32, PUPD, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc,
-                                                                  nact, partials, bcg, active, init);
-  else
-    k_lowrank_rows<T, TV, 64, PUPD, DIRECT, VR><<<g, WG, 0, st>>>(m, B, rk, JW, V, DW, R2, Z2, has_base, rpc,
-                                                                  nact, partials, bcg, active, init);
+                                double* partials, const double* bcg, const int* active, int init, XU xu = XU()) {
+  if constexpr (PUPD) {
+    if (xu.xk && !init) {
+      launch_lowrank_rows_x<T, TV, PUPD, DIRECT, VR, true>(g, st, m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
+                                                           partials, bcg, active, init, xu);
+      return;
+    }
+  }
+  launch_lowrank_rows_x<T, TV, PUPD, DIRECT, VR, false>(g, st, m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact,
+                                                        partials, bcg, active, init, XU());
 }
 // Vr: the row-major BF16 factor (vrow_factor), read by the unstaged form.
 template <typename T, typename TV>
@@ -2922,16 +2997,16 @@ template <typename T, typename TV, bool PUPD>
 static void lowrank_rows(bool direct, dim3 g, hipStream_t st, int64_t m, int B, int rk, int JW, const TV* V,
                          const double* DW, const T* R2, T* Z2, int has_base, int64_t rpc, const int* nact,
                          double* partials, const double* bcg = nullptr, const int* active = nullptr,
-                         int init = 0, const bf16* Vr = nullptr) {
+                         int init = 0, const bf16* Vr = nullptr, XU xu = XU()) {
   if (direct && Vr)
     launch_lowrank_rows<T, bf16, PUPD, true, true>(g, st, m, B, rk, JW, Vr, DW, R2, Z2, has_base, rpc, nact,
-                                                   partials, bcg, active, init);
+                                                   partials, bcg, active, init, xu);
   else if (direct)
     launch_lowrank_rows<T, TV, PUPD, true>(g, st, m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact, partials, bcg,
-                                           active, init);
+                                           active, init, xu);
   else
     launch_lowrank_rows<T, TV, PUPD, false>(g, st, m, B, rk, JW, V, DW, R2, Z2, has_base, rpc, nact, partials,
-                                            bcg, active, init);
+                                            bcg, active, init, xu);
 }
 
 // Narrow batches run the unstaged kernels over one resident round of
@@ -3126,7 +3201,7 @@ static void precond_simple(Launcher& L, const TV* V, const T* R2, T* Z2, int ep,
 // iteration.
 template <typename T, typename TV>
 static void precond_fused(Launcher& L, const TV* V, const T* R2, T* P2, int init, const ColState& cs,
-                          const int* nact) {
+                          const int* nact, T* xk = nullptr) {
   DeviceIndex* D = L.D;
   Workspace* w = L.w;
   const int B = L.B, rk = D->rank;
@@ -3180,8 +3255,10 @@ static void precond_fused(Launcher& L, const TV* V, const T* R2, T* P2, int init
   k_vt_reduce<<<(unsigned)((nv + 63) / 64), WG, 0, st>>>(w->partials, nchunk, nv, B, D->D, w->DW, nact, w->DW2);
   k_rz_lowrank<<<1, WG, 0, st>>>(rk, B, w->DW2, init, cs, nact);
   L.timed(PK_LOWRANK, pbytes, [&] {
+    XU xu;
+    xu.xk = xk; xu.alpha = cs.alpha; xu.fresh = w->fresh;
     lowrank_rows<T, TV, true>(direct, g, st, m, B, rk, JW, V, w->DW, R2, P2, 0, rpc, nact, nullptr, cs.bcg,
-                              cs.active, init, vr);
+                              cs.active, init, vr, xk ? xu : XU());
   });
 }
 
@@ -3367,11 +3444,18 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
   // rank of at most 64 (or none), precond_fused updates p2 without forming z;
   // otherwise z is formed (with <r2, z>) and p2 updated after.
   const bool fuse_p = !D->ginv && D->rank <= 64 && !(std::is_same<T, float>::value && B >= 16 && D->rank > 0);
+  // Two or more columns: x += alpha p is taken by the search-direction
+  // update (which reads the old p anyway) instead of the residual update, on
+  // the columns whose step this iteration's S p set (w->fresh), so one panel
+  // pass fewer per iteration; same values, same bits.
+  const bool defer_x = B >= 2 && tuning().defer_x;
+  T* xd = defer_x ? K2 : nullptr;
   auto precond_p = [&](int init) {
+    T* xk = init ? nullptr : xd;
     if (!fuse_p) {
       precond(init ? EP_RZ_INIT : EP_RZ);
-      L.timed_cols(PK_UPDATE_P, 3.0 * sizeof(T) * n2, [&] {
-        k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, init, cs);
+      L.timed_cols(PK_UPDATE_P, (xk ? 5.0 : 3.0) * sizeof(T) * n2, [&] {
+        k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, Z2, P2, init, cs, xk, w->fresh);
       });
       return;
     }
@@ -3379,14 +3463,14 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
     if (D->rank == 0) {
       // z = r: <r, z> = <r, r>
       k_rz_lowrank<<<1, WG, 0, st>>>(0, B, nullptr, init, cs, nact);
-      L.timed_cols(PK_UPDATE_P, 3.0 * sizeof(T) * n2, [&] {
-        k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, R2, P2, init, cs);
+      L.timed_cols(PK_UPDATE_P, (xk ? 5.0 : 3.0) * sizeof(T) * n2, [&] {
+        k_update_p<T><<<grid_for((int64_t)n2, 64), WG, 0, st>>>(n2, B, R2, P2, init, cs, xk, w->fresh);
       });
       return;
     }
     with_lowrank_factor<T>(D, [&](auto* V) {
       typedef typename std::remove_cv<typename std::remove_pointer<decltype(V)>::type>::type TV;
-      precond_fused<T, TV>(L, V, R2, P2, init, cs, nact);
+      precond_fused<T, TV>(L, V, R2, P2, init, cs, nact, xk);
     });
   };
 
@@ -3496,6 +3580,10 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
   const int rpw2 = L.rows_per_wg(n2), nwg2 = Launcher::nwg_for(n2, rpw2);
   L.need(nwg2, B);
   const bool fuse_vt = B == 1 && D->rank > 0 && D->rank <= 64 && !D->ginv && fuse_p && tuning().fuse;
+  if (defer_x) {
+    L.fill<int>(w->fresh, (int64_t)B, 0);
+    L.fresh_out = w->fresh;  // the iterations' S p finalizes flag their columns
+  }
   L.iterate(sizeof(T) == 8 ? 1 : 2, max_iter, check_every, [&] {
       m11(nullptr, (T)0, P2, beta, X, w->n_active);   // t1' = M11^{-1} (beta A12 p2)
       SpmmArgs<T> a{};
@@ -3512,12 +3600,15 @@ static void solve_lrc(Launcher& L, const T* rhs, int max_iter, int check_every, 
         });
         return;
       }
-      L.timed_cols(PK_UPDATE_R, 6.0 * sizeof(T) * n2, [&] {
-        k_update_r<T><<<nwg2, WG, WG * sizeof(double), st>>>(n2, B, rpw2, K2, P2, R2, Q2, cs, w->partials);
+      L.timed_cols(PK_UPDATE_R, (defer_x ? 3.0 : 6.0) * sizeof(T) * n2, [&] {
+        k_update_r<T><<<nwg2, WG, WG * sizeof(double), st>>>(n2, B, rpw2, defer_x ? nullptr : K2, P2, R2, Q2, cs,
+                                                             w->partials);
       });
       L.finalize(nwg2, B, EP_RR, cs, nullptr, w->n_active);
       precond_p(0);
+      if (defer_x) L.fill<int>(w->fresh, (int64_t)B, 0);
   });
+  L.fresh_out = nullptr;
   // ---- a4: k1 = M11^{-1} (b1 + beta A12 k2) -> Dx[0:n1]
   m11(rhs, (T)1, K2, beta, Dx, nullptr);
 }
@@ -4178,7 +4269,7 @@ size_t carve_ws(const DeviceIndex* D, int B, char* base, Workspace* w) {
   double* DW2 = c.take<double>(rk * B);
   double* sc = c.take<double>(12 * (int64_t)B);
   float* Rf = D->precision == KATZ_PREC_MIXED ? c.take<float>(nB) : nullptr;
-  int* ip = c.take<int>(4 * (int64_t)B + 1);
+  int* ip = c.take<int>(5 * (int64_t)B + 1);
   int32_t* qpos = c.take<int32_t>(B);
   if (w) {
     w->B = B; w->n = D->n; w->n2 = D->n2; w->device = D->device;
@@ -4189,6 +4280,7 @@ size_t carve_ws(const DeviceIndex* D, int B, char* base, Workspace* w) {
     w->rn2 = sc + 9 * B; w->inv = sc + 10 * B; w->fwd = sc + 11 * B;
     w->Rf = Rf;
     w->active = ip; w->status = ip + B; w->iters = ip + 2 * B; w->mask = ip + 3 * B; w->n_active = ip + 4 * B;
+    w->fresh = ip + 4 * B + 1;
     w->qpos = qpos;
   }
   return c.off;
@@ -4224,7 +4316,7 @@ int device_query_noalloc(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa
     // fill kernel on the caller's stream: the previous call's contents remain
     Launcher L0{D, &w, st, B};
     L0.fill<double>(w.rz, 12 * (int64_t)B, 0.0);
-    L0.fill<int>(w.active, 4 * (int64_t)B + 1, 0);
+    L0.fill<int>(w.active, 5 * (int64_t)B + 1, 0);
     std::vector<ColResult> res;
     run_batch(H, D, &w, st, qa.q + c0, B, qa.opts, res);
     if (qa.scores) {

@@ -681,3 +681,26 @@ def test_precision_form_reported_residual_is_true_residual(B):
             c = ref[:, j]
             assert np.linalg.norm(sc[j] - c) <= 1e-8 * np.linalg.norm(c), j
     idx.close()
+
+
+
+def test_deferred_x_update_gives_identical_results(tmp_path):
+    """From two columns the LRC solve adds alpha p to the solution in the
+    search-direction update instead of the residual update (KATZ_DEFER_X);
+    the same values are added in the same precision, so scores and
+    iteration counts must be bit-identical both ways, in FP64 and in the
+    precision form.  Each setting runs in a child process."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = []
+    for t, flag in enumerate(("1", "0")):
+        env = dict(os.environ)
+        env["KATZ_DEFER_X"] = flag
+        f = str(tmp_path / ("defer%d.npz" % t))
+        print("KATZ_DEFER_X", flag, flush=True)
+        subprocess.run([sys.executable, "-c", _WALK_SCRIPT, f, root], env=env, check=True, timeout=300)
+        res.append(np.load(f))
+    for k in res[0].files:
+        assert np.array_equal(res[0][k], res[1][k]), k
