@@ -178,7 +178,11 @@ void katz_query_opts_default(katz_query_opts* o);
  * through its Cholesky factor (step 4), factors M22 when l_kind is CHOL (or
  * takes its zero-fill incomplete factor for IC0), and
  * runs Lanczos on R for the top `rank` eigenpairs (eq. RMatrix).  Then the
- * index is copied to the device once.
+ * index is copied to the device once.  With a device (opts->device >= 0), the
+ * Lanczos on R runs there for large separators, and so does the Lanczos for
+ * lambda_max from 2M nodes (a temporary device copy of the CSR, freed before
+ * the call returns; the same iteration and stop rule as on the host, so beta
+ * agrees with a host-only build to rounding).
  *   n, nnz, row_ptr[n+1], col_idx[nnz]: host CSR, int32, strictly increasing
  *     columns per row, no diagonal, symmetric.
  *   val: host FP64 nonnegative weights [nnz], or NULL for an unweighted graph.
