@@ -208,9 +208,9 @@ def main():
                            "iters_median": float(np.median(its + its2)),
                            "iters_p99": float(np.percentile(its + its2, 99)), "iters_max": int(np.max(its + its2)),
                            "max_rel_residual": float(np.max(res + res2))}
-            log("  %s: %.1f q/s, %.3f ms/query, p50 %.3f p99 %.3f ms over %d, iters median %g"
+            log("  %s: %.1f q/s, %.3f ms/query, p50 %.3f p99 %.3f max %.3f ms over %d, iters median %g"
                 % (name, entry[name]["qps"], entry[name]["ms_per_query"], entry[name]["p50_ms"],
-                   entry[name]["p99_ms"], nl, entry[name]["iters_median"]))
+                   entry[name]["p99_ms"], float(np.max(lat_ms)), nl, entry[name]["iters_median"]))
             if c == head_c and args.concurrency > 1 and not args.host_output:
                 # independent one-query solves from several host threads at once
                 import threading

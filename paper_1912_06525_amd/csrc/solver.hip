@@ -1897,6 +1897,7 @@ struct Tuning {
   int ew_rows;      // target rows per workgroup of those kernels
   int xcd;          // XCD-slab chunk order for the gathering kernels
   int graphs;       // replay captured iteration chunks as HIP graphs
+  int precapture;   // one column: capture every chunk length up to 8 at a kind's first capture
   int fuse;         // one-column residual update fused with V^T r
   int lr_nwg;       // max workgroups of the one-column low-rank kernels
   int vrow;         // one-column low-rank kernels read the row-major BF16 factor
@@ -1927,6 +1928,7 @@ static const Tuning& tuning() {
     u.ew_rows = env_int("KATZ_EW_ROWS", 256, 16, 65536);
     u.xcd = env_int("KATZ_XCD_SLAB", 0, 0, 1);
     u.graphs = env_int("KATZ_GRAPHS", 1, 0, 1);
+    u.precapture = env_int("KATZ_PRECAPTURE", 1, 0, 1);
     u.fuse = env_int("KATZ_FUSE", 1, 0, 1);
     u.lr_nwg = env_int("KATZ_LR_NWG", 512, 64, 65536);
     u.vrow = env_int("KATZ_VROW", 1, 0, 1);
@@ -2006,7 +2008,9 @@ struct Workspace {
   ProfEvents prof;
   hipStream_t stream = nullptr;          // the workspace's own stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;  // captured iteration chunks
+  // captured iteration chunks: solve kind, width, chunk length, iteration cap
+  struct ChunkGraph { int kind, B, len, max_iter; hipGraphExec_t ex; };
+  std::vector<ChunkGraph> graphs;
   // carved from caller-independent scratch (katz_query_noalloc): owns no
   // memory, stream or events; runs without graphs, profiling or autotuning
   bool external = false;
@@ -2071,7 +2075,7 @@ struct DeviceIndex {
 };
 constexpr int kLongRow = 256;
 // HIP graphs of iteration chunks kept per workspace.
-constexpr size_t kMaxGraphs = 64;
+constexpr size_t kMaxGraphs = 128;
 // Partial sums (rows x values) above which finalize reduces in two stages,
 // and the size of the first stage's output.
 constexpr int64_t kFinTwoStage = 1 << 20;
@@ -2298,7 +2302,7 @@ DeviceIndex* device_upload(const HostIndex& H, int device) {
 
 static void free_ws(Workspace* w) {
   std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
-  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
+  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.ex);
   w->graphs.clear();
   if (w->stream) (void)hipStreamDestroy(w->stream);
   if (w->ev_in) (void)hipEventDestroy(w->ev_in);
@@ -2764,12 +2768,40 @@ struct Launcher {
   // iterations after convergence still launch every kernel (which exits at
   // once) and each poll is a host round trip, so the schedule keeps both few
   // when consecutive solves need similar counts.  A chunk is captured once per
-  // workspace, key and length into a HIP graph and replayed (not while
-  // profiling; at most kMaxGraphs per workspace, further lengths run eagerly).
+  // workspace, solve kind, width, length and iteration cap into a HIP graph
+  // and replayed (not while profiling; at most kMaxGraphs per workspace,
+  // further lengths run eagerly).  One column: the first capture of a kind
+  // also captures every length up to 8, so that a later solve needing one
+  // iteration more or less than the last replays a graph instead of paying
+  // for a capture in its own latency.
   template <typename F>
-  void iterate(int64_t key, int max_iter, int check_every, F&& one_iter) {
+  void iterate(int kind, int max_iter, int check_every, F&& one_iter) {
     int* hflag = (int*)((char*)w->hpin + kPinFlagOff);
     const bool graphs = tuning().graphs && !g_prof_on.load(std::memory_order_relaxed) && !w->external;
+    auto find = [&](int len) -> hipGraphExec_t {
+      for (const auto& g : w->graphs)
+        if (g.kind == kind && g.B == B && g.len == len && g.max_iter == max_iter) return g.ex;
+      return nullptr;
+    };
+    auto capture = [&](int len) -> hipGraphExec_t {
+      std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
+      hipGraph_t gr = nullptr;
+      HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int s2 = 0; s2 < len; s2++) one_iter();
+      } catch (...) {
+        (void)hipStreamEndCapture(st, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      HIPCHECK(hipStreamEndCapture(st, &gr));
+      hipGraphExec_t ex = nullptr;
+      hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (e != hipSuccess) fail(KATZ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      w->graphs.push_back({kind, B, len, max_iter, ex});
+      return ex;
+    };
     int it = 0;
     for (int chunk = 0; it < max_iter; chunk++) {
       int want;
@@ -2777,27 +2809,17 @@ struct Launcher {
       else if (chunk == 0) want = iter_hint > 0 ? iter_hint : 8;
       else want = std::min(8, 1 << ((chunk - 1) / 2));
       const int len = std::min(want, max_iter - it);
-      const int64_t gkey = (key << 56) ^ ((int64_t)B << 40) ^ ((int64_t)len << 20) ^ (int64_t)max_iter;
       hipGraphExec_t ex = nullptr;
       if (graphs) {
-        for (auto& g : w->graphs)
-          if (g.first == gkey) ex = g.second;
+        ex = find(len);
         if (!ex && w->graphs.size() < kMaxGraphs) {
-          std::lock_guard<std::recursive_mutex> lk(hip_global_mu());
-          hipGraph_t gr = nullptr;
-          HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-          try {
-            for (int s2 = 0; s2 < len; s2++) one_iter();
-          } catch (...) {
-            (void)hipStreamEndCapture(st, &gr);
-            if (gr) (void)hipGraphDestroy(gr);
-            throw;
-          }
-          HIPCHECK(hipStreamEndCapture(st, &gr));
-          hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-          (void)hipGraphDestroy(gr);
-          if (e != hipSuccess) fail(KATZ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-          w->graphs.emplace_back(gkey, ex);
+          bool first = true;
+          for (const auto& g : w->graphs)
+            if (g.kind == kind && g.B == B && g.max_iter == max_iter) first = false;
+          ex = capture(len);
+          if (first && B == 1 && check_every == 0 && tuning().precapture)
+            for (int l = 1; l <= std::min(8, max_iter); l++)
+              if (l != len && w->graphs.size() < kMaxGraphs) capture(l);
         }
       }
       if (ex)

@@ -704,3 +704,56 @@ def test_deferred_x_update_gives_identical_results(tmp_path):
         res.append(np.load(f))
     for k in res[0].files:
         assert np.array_equal(res[0][k], res[1][k]), k
+
+
+_CHUNK_SCRIPT = r"""
+import sys, numpy as np
+sys.path.insert(0, sys.argv[2])
+import katz_inputs as ki, paper_1912_06525_amd as K
+g = ki.workload("lnsbm4m", scale=0.004).graph
+deg = np.diff(g.row_ptr)
+qs = list(ki.sample_queries(g, 12, 31)) + [int(np.argmax(deg)), int(np.argmin(deg))]
+out = {}
+for prec in (K.KATZ_PREC_FP64, K.KATZ_PREC_MIXED):
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.9, rank=16, labels=g.labels, max_block=32, precision=prec)
+    for m in (K.KATZ_METHOD_LRC, K.KATZ_METHOD_CG):
+        for ti, tol in enumerate((1e-6, 1e-9)):
+            for j, q in enumerate(qs):
+                sc, st = idx.query([q], tol=tol, method=m)
+                key = "p%d_m%d_t%d_q%d" % (prec, m, ti, j)
+                out[key] = sc[0]
+                out[key + "_it"] = np.array([st[0]["status"], st[0]["iters"], st[0]["sweeps"]])
+    idx.close()
+np.savez(sys.argv[1], **out)
+"""
+
+
+def test_iteration_graphs_give_identical_results(tmp_path):
+    """Iteration chunks replayed from captured HIP graphs (one column: every
+    chunk length up to 8 captured at a solve kind's first capture) launch the
+    same kernels with the same arguments as the eager loop (KATZ_GRAPHS=0):
+    one-column scores, statuses, iteration and sweep counts must be
+    bit-identical, over consecutive queries whose iteration counts differ (so
+    that the adaptive schedule's first chunk changes length), at two
+    tolerances, in FP64 and in the precision form.  Each setting runs in a
+    child process."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = []
+    for t, flag in enumerate(("1", "0")):
+        env = dict(os.environ)
+        env["KATZ_GRAPHS"] = flag
+        f = str(tmp_path / ("graphs%d.npz" % t))
+        print("KATZ_GRAPHS", flag, flush=True)
+        subprocess.run([sys.executable, "-c", _CHUNK_SCRIPT, f, root], env=env, check=True, timeout=300)
+        res.append(np.load(f))
+    assert res[0].files == res[1].files
+    its = set()
+    for k in res[0].files:
+        assert np.array_equal(res[0][k], res[1][k]), k
+        if k.endswith("_it"):
+            assert res[0][k][0] == 0, (k, res[0][k])
+            its.add(int(res[0][k][1]))
+    assert len(its) >= 3, its  # the first chunk's length really varied
