@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--precision", type=str, default="fp64", choices=["fp64", "mixed"],
                     help="one-query workload: FP64 path (the configuration's) or the precision form")
     ap.add_argument("--u-precision", type=int, default=0, help="low-rank factor storage (0 auto, 1 FP64, 2 FP32, 3 BF16)")
+    ap.add_argument("--partition", type=str, default="bfs", choices=["bfs", "louvain"],
+                    help="one-query workload: initial parts of the partition (bfs: one part cut into BFS chunks, "
+                         "the build's default; louvain: katz_communities capped at max_block)")
     ap.add_argument("--concurrency", type=int, default=2,
                     help="one-query workload: also time this many host threads solving independent single "
                          "queries at once (each on its own workspace stream); 0 or 1 to skip")
@@ -181,10 +184,15 @@ def main():
                 raise RuntimeError("query %d did not converge: %r" % (q, st[0]))
         return lat, its, res
 
+    labels = None
+    if args.partition == "louvain":
+        tb = time.time()
+        labels, passes = K.katz_communities(g.n, g.row_ptr, g.col, cap=args.max_block, passes=8)
+        log("communities: %d in %d passes (%.1fs)" % (int(labels.max()) + 1, passes, time.time() - tb))
     for c in cs:
         tb = time.time()
         idx = K.KatzIndex.from_graph(g, beta_frac=c, rank=args.rank, max_block=args.max_block, device=0,
-                                     u_precision=args.u_precision,
+                                     u_precision=args.u_precision, labels=labels,
                                      precision=K.KATZ_PREC_MIXED if args.precision == "mixed" else K.KATZ_PREC_FP64)
         info = idx.info
         log("c=%.2f index: n1=%d n2=%d blocks=%d sigma1=%.4f sigma_r+1=%.5f build %.1fs"
@@ -318,7 +326,8 @@ def main():
                                % (g.n, head_c, args.rank,
                                   "FP64" if args.precision == "fp64" else "FP32 inner solves + FP64 refinement"),
                    "n": g.n, "nnz": g.nnz, "c": head_c, "rank": args.rank, "batch": 1, "tol": tol,
-                   "output": "pinned host memory (PCIe-inclusive)" if args.host_output else "device memory"},
+                   "output": "pinned host memory (PCIe-inclusive)" if args.host_output else "device memory",
+                   "partition": args.partition},
         "p99_ms": round(head["lrc"]["p99_ms"], 4),
         "p50_ms": round(head["lrc"]["p50_ms"], 4),
         "latency_queries": head["lrc"]["latency_queries"],

@@ -196,6 +196,32 @@ int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
                      const double* val, const katz_build_opts* opts, katz_index** out);
 
 /*
+ * Communities to pass as katz_build_opts.labels for a graph without planted
+ * labels (Sec. 3.2 step 2 partitions with METIS; this library offers this
+ * instead, or the build's default of one part cut into BFS chunks).  It is
+ * the local-moving phase of the Louvain method on the modularity of the
+ * weighted graph, every community capped at `cap` nodes (the build's
+ * max_block suits): each node starts alone; a pass visits the nodes in id
+ * order and moves each to the neighbouring community of the largest
+ * modularity gain (its own wins ties, then the first reached in its row);
+ * a community at the cap takes no one; passes stop when one moves no node or
+ * after `passes`.  Serial, deterministic, O(nnz) per pass, host only.
+ *   n, nnz, row_ptr, col_idx, val: the CSR as for katz_index_build (checked
+ *     the same way; val NULL: unweighted).
+ *   cap >= 1; passes >= 0 (0: every node alone).
+ *   labels[n] (caller-owned, written): community ids 0, 1, ... in the
+ *     order a breadth-first search first reaches each community (from node
+ *     0, neighbours in row order, restarting at the smallest unreached
+ *     node).  The build lays the parts out in label order, so this keeps
+ *     neighbouring communities at nearby positions.
+ *   passes_run (nullable): the passes made.
+ * Errors: KATZ_EINVAL (malformed CSR, bad cap or passes, null labels),
+ * KATZ_ENOTSYM, KATZ_ENOMEM.
+ */
+int katz_communities(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx, const double* val,
+                     int32_t cap, int32_t passes, int32_t* labels, int32_t* passes_run);
+
+/*
  * Katz vectors of nq query nodes (Algorithm 2; Lemma 1 eqs. 5-6).
  *   q[nq]: host array of node ids in [0, n), original numbering.
  *   scores: nq * n FP64, query-major: scores[i*n + v] = K[v, q[i]]

@@ -32,7 +32,7 @@ _STATUS = {0: "KATZ_OK", -1: "KATZ_EINVAL", -2: "KATZ_ENOTSYM", -3: "KATZ_EDIVER
            -5: "KATZ_EDEVICE", -6: "KATZ_ENOCONV", -7: "KATZ_EBUSY", -8: "KATZ_EIO"}
 
 EXPORTED = ["katz_build_opts_default", "katz_query_opts_default", "katz_index_build", "katz_query",
-            "katz_query_noalloc",
+            "katz_query_noalloc", "katz_communities",
             "katz_topk_links", "katz_pair_scores", "katz_sparse_katz", "katz_index_save", "katz_index_load", "katz_index_free", "katz_index_info", "katz_index_partition",
             "katz_index_lowrank", "katz_profile_enable", "katz_profile_reset", "katz_profile_read",
             "katz_server_opts_default", "katz_server_create", "katz_server_submit", "katz_server_poll",
@@ -108,6 +108,8 @@ def _load():
     lib.katz_index_build.argtypes = [i32, i64, pi32, pi32, pdbl, ctypes.POINTER(katz_build_opts),
                                      ctypes.POINTER(P)]
     lib.katz_index_build.restype = ctypes.c_int
+    lib.katz_communities.argtypes = [i32, i64, pi32, pi32, pdbl, i32, i32, pi32, ctypes.POINTER(i32)]
+    lib.katz_communities.restype = ctypes.c_int
     lib.katz_query.argtypes = [P, pi32, i32, ctypes.POINTER(katz_query_opts), P,
                                ctypes.POINTER(katz_query_stats), P]
     lib.katz_query.restype = ctypes.c_int
@@ -214,6 +216,19 @@ def katz_index_build(n: int, row_ptr, col_idx, val=None, opts: Optional[katz_bui
                                ctypes.byref(opts) if opts is not None else None, ctypes.byref(h))
     _check(rc)
     return h
+
+
+def katz_communities(n: int, row_ptr, col_idx, val=None, cap: int = 64, passes: int = 8):
+    """Louvain local moving with communities capped at `cap` nodes: labels
+    (int32 [n]) for KatzIndex(labels=...), and the passes made."""
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    col = np.ascontiguousarray(col_idx, np.int32)
+    v = None if val is None else np.ascontiguousarray(val, np.float64)
+    labels = np.empty(int(n), np.int32)
+    done = ctypes.c_int32()
+    _check(_lib.katz_communities(int(n), int(rp[-1]), _pi32(rp), _pi32(col), _pdbl(v), int(cap), int(passes),
+                                 _pi32(labels), ctypes.byref(done)))
+    return labels, int(done.value)
 
 
 def katz_query(idx, q, opts: Optional[katz_query_opts], scores, stats=None, stream=None) -> int:

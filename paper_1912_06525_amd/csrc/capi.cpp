@@ -148,6 +148,15 @@ int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
   });
 }
 
+int katz_communities(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx, const double* val,
+                     int32_t cap, int32_t passes, int32_t* labels, int32_t* passes_run) {
+  return guarded([&]() -> int {
+    const int32_t done = katz::communities(n, nnz, row_ptr, col_idx, val, cap, passes, labels);
+    if (passes_run) *passes_run = done;
+    return KATZ_OK;
+  });
+}
+
 int katz_index_save(const katz_index* idx, const char* path) {
   return guarded([&]() -> int {
     if (!idx || !path) return set_error(KATZ_EINVAL, "null index or path");

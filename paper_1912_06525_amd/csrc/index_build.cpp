@@ -1109,4 +1109,108 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
   H.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// ------------------------------------------------------------ communities
+// Initial parts for the partition of an unlabeled graph (Sec. 3.2, step 2
+// partitions with METIS, which this library does not have): the
+// local-moving phase of the Louvain method (Blondel et al., 2008) on the
+// Newman-Girvan modularity of the weighted graph, with every community
+// capped at `cap` nodes.  Each node starts alone; a pass visits the nodes in
+// id order, takes each out of its community and puts it into the neighbouring
+// community (or back into its own) of the largest gain
+//   w(v, C) - k_v tot(C) / 2m
+// (w(v, C): the weight of v's edges into C; k_v: v's weighted degree; tot(C):
+// the summed degrees of C; 2m: the summed degrees of the graph), which is the
+// modularity change of the move up to the positive factor 1 / m.  Its own
+// community wins ties, and among the others the first reached in v's CSR
+// row.  Communities at the cap take no one.  Passes stop when one moves no
+// node or after `passes`.  No aggregation levels: the partition wants
+// communities no larger than a block, and the cap is reached within the
+// first level.  Serial and deterministic; O(nnz) per pass.  labels[v]:
+// community ids 0, 1, ... in breadth-first order (below).
+int32_t communities(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col, const double* val,
+                    int32_t cap, int32_t passes, int32_t* labels) {
+  validate(n, nnz, rp, col, val);
+  if (cap < 1) fail(KATZ_EINVAL, "cap must be >= 1");
+  if (passes < 0) fail(KATZ_EINVAL, "passes must be >= 0");
+  if (!labels) fail(KATZ_EINVAL, "null labels array");
+  std::vector<double> k(n, 0.0), tot(n);
+  std::vector<int32_t> comm(n), size(n, 1);
+  double m2 = 0.0;
+  for (int32_t v = 0; v < n; v++) {
+    double d = 0.0;
+    for (int32_t e = rp[v]; e < rp[v + 1]; e++) d += val ? val[e] : 1.0;
+    k[v] = d;
+    tot[v] = d;
+    comm[v] = v;
+    m2 += d;
+  }
+  int32_t done = 0;
+  if (m2 > 0.0) {
+    std::vector<double> wto(n, 0.0);
+    std::vector<int32_t> stamp(n, -1), touched;
+    for (int32_t pass = 0; pass < passes; pass++) {
+      int64_t moved = 0;
+      for (int32_t v = 0; v < n; v++) {
+        if (!(k[v] > 0.0)) continue;
+        const int32_t c0 = comm[v];
+        touched.clear();
+        stamp[c0] = v;
+        wto[c0] = 0.0;
+        for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
+          const int32_t c = comm[col[e]];
+          if (stamp[c] != v) {
+            stamp[c] = v;
+            wto[c] = 0.0;
+            touched.push_back(c);
+          }
+          wto[c] += val ? val[e] : 1.0;
+        }
+        tot[c0] -= k[v];
+        size[c0]--;
+        const double kv = k[v] / m2;
+        int32_t best = c0;
+        double gbest = wto[c0] - kv * tot[c0];
+        for (int32_t c : touched) {
+          if (c == c0 || size[c] >= cap) continue;
+          const double g = wto[c] - kv * tot[c];
+          if (g > gbest) {
+            gbest = g;
+            best = c;
+          }
+        }
+        comm[v] = best;
+        tot[best] += k[v];
+        size[best]++;
+        moved += best != c0;
+      }
+      done = pass + 1;
+      if (moved == 0) break;
+    }
+  }
+  // ids in the order a breadth-first search first reaches each community
+  // (from node 0, neighbours in CSR order, restarting at the smallest
+  // unreached node): the partition lays the parts out in id order, so
+  // neighbouring communities get nearby positions
+  std::vector<int32_t> id(n, -1), queue;
+  std::vector<char> seen(n, 0);
+  queue.reserve(n);
+  int32_t next = 0;
+  for (int32_t s = 0; s < n; s++) {
+    if (seen[s]) continue;
+    seen[s] = 1;
+    queue.push_back(s);
+    for (size_t h = queue.size() - 1; h < queue.size(); h++) {
+      const int32_t u = queue[h];
+      if (id[comm[u]] < 0) id[comm[u]] = next++;
+      for (int32_t e = rp[u]; e < rp[u + 1]; e++)
+        if (!seen[col[e]]) {
+          seen[col[e]] = 1;
+          queue.push_back(col[e]);
+        }
+    }
+  }
+  for (int32_t v = 0; v < n; v++) labels[v] = id[comm[v]];
+  return done;
+}
+
 }  // namespace katz

@@ -70,6 +70,11 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
 void lanczos_normals(uint64_t& state, double* out, int64_t n);
 std::vector<double> lanczos_ritz(HostIndex& H, const std::vector<double>& al, const std::vector<double>& be,
                                  int32_t r);
+// Louvain local moving with communities capped at `cap` nodes, for the
+// initial parts of an unlabeled graph (katz_communities); returns the passes
+// run.
+int32_t communities(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col, const double* val,
+                    int32_t cap, int32_t passes, int32_t* labels);
 // Whether the Lanczos on R should run on the device for these options.
 bool lanczos_on_device(const HostIndex& H, const katz_build_opts& o);
 // Index files (index_io.cpp): a loaded index is fully validated.

@@ -757,3 +757,21 @@ def test_iteration_graphs_give_identical_results(tmp_path):
             assert res[0][k][0] == 0, (k, res[0][k])
             its.add(int(res[0][k][1]))
     assert len(its) >= 3, its  # the first chunk's length really varied
+
+
+@pytest.mark.parametrize("prec", [K.KATZ_PREC_FP64, K.KATZ_PREC_MIXED])
+@pytest.mark.parametrize("B", [1, 20])
+def test_louvain_partition_matches_oracle(prec, B):
+    """An index whose initial parts are katz_communities (Louvain local
+    moving capped at max_block) instead of one part cut into BFS chunks:
+    blocks with internal edges on a Chung-Lu graph, the same oracle
+    parity."""
+    g = ki.chung_lu(20_000, 2.5, 10, seed=17)
+    beta = oracle_beta(g, 0.9)
+    lab, _ = K.katz_communities(g.n, g.row_ptr, g.col, cap=32, passes=8)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=16, max_block=32, labels=lab, precision=prec)
+    assert idx.info.max_block_size > 1
+    deg = np.diff(g.row_ptr)
+    qs = list(ki.sample_queries(g, B - 1, 5)) + [int(np.argmax(deg))] if B > 1 else [int(np.argmax(deg))]
+    _check(g, idx, beta, qs, 1e-8)
+    idx.close()

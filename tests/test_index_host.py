@@ -382,3 +382,148 @@ def test_build_phase_times():
     assert ph[2] > 0 and ph[10] > 0            # partition and the host Lanczos ran
     assert sum(ph) <= idx.info.build_seconds * 1.01 + 1e-3
     assert sum(ph) >= 0.5 * idx.info.build_seconds
+
+
+# ------------------------------------------------------------ communities
+def _modularity(n, rp, col, lab, val=None):
+    """Newman-Girvan modularity of the labelling, from its definition:
+    sum over C of [w_in(C) / 2m - (tot(C) / 2m)^2], w_in counting both
+    directions of every edge inside C."""
+    rp = np.asarray(rp)
+    col = np.asarray(col)
+    w = np.ones(len(col)) if val is None else np.asarray(val, float)
+    row = np.repeat(np.arange(n), np.diff(rp))
+    k = np.bincount(row, weights=w, minlength=n)
+    m2 = k.sum()
+    inside = w[lab[row] == lab[col]].sum()
+    tot = np.bincount(lab, weights=k)
+    return inside / m2 - (tot ** 2).sum() / m2 ** 2
+
+
+def _random_graph(n, p, seed, weighted):
+    rng = np.random.default_rng(seed)
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+    g = ki.from_edges(n, edges)
+    val = None
+    if weighted:
+        wt = {e: float(rng.uniform(0.2, 3.0)) for e in edges}
+        rows = np.repeat(np.arange(n), g.degrees())
+        val = np.array([wt[(min(a, b), max(a, b))] for a, b in zip(rows, g.col)])
+    return g, val
+
+
+def test_communities_recover_planted_sbm():
+    """40 planted communities of 30 nodes (p_in 0.5, p_out 0.002): local
+    moving finds them (adjusted Rand index above 0.95) and their modularity
+    to within 0.02."""
+    from sklearn.metrics import adjusted_rand_score
+    g = ki.sbm([30] * 40, 0.5, 0.002, seed=3)
+    lab, passes = K.katz_communities(g.n, g.row_ptr, g.col, cap=64, passes=20)
+    assert adjusted_rand_score(g.labels, lab) > 0.95
+    assert 1 <= passes < 20
+    q_found = _modularity(g.n, g.row_ptr, g.col, lab)
+    q_planted = _modularity(g.n, g.row_ptr, g.col, np.asarray(g.labels))
+    assert q_found > q_planted - 0.02
+
+
+def test_communities_closed_cases():
+    """Two disjoint 10-cliques: two communities (cap 10); cap 5 splits each
+    clique into parts of at most 5; passes = 0 leaves every node alone;
+    isolated nodes stay alone."""
+    edges = [(i, j) for base in (0, 10) for i in range(base, base + 10) for j in range(i + 1, base + 10)]
+    g = ki.from_edges(22, edges)  # nodes 20 and 21 isolated
+    lab, _ = K.katz_communities(g.n, g.row_ptr, g.col, cap=10, passes=10)
+    assert lab.tolist() == [0] * 10 + [1] * 10 + [2, 3]
+    lab5, _ = K.katz_communities(g.n, g.row_ptr, g.col, cap=5, passes=10)
+    assert np.bincount(lab5).max() <= 5
+    for c in np.unique(lab5):  # no community spans the two cliques
+        members = np.flatnonzero(lab5 == c)
+        assert len({int(v) // 10 for v in members if v < 20}) <= 1
+    lab0, p0 = K.katz_communities(g.n, g.row_ptr, g.col, cap=10, passes=0)
+    assert lab0.tolist() == list(range(22)) and p0 == 0
+
+
+def test_communities_numbered_in_breadth_first_order():
+    """Community ids follow the order in which a breadth-first search (from
+    node 0, neighbours in row order, restarting at the smallest unreached
+    node) first reaches each community; the ids are 0 .. ncomm - 1."""
+    from collections import deque
+    g = ki.chung_lu(3000, 2.5, 4, seed=9)  # several components
+    lab, _ = K.katz_communities(g.n, g.row_ptr, g.col, cap=16, passes=6)
+    seen = np.zeros(g.n, bool)
+    order = []
+    for s0 in range(g.n):
+        if seen[s0]:
+            continue
+        seen[s0] = True
+        dq = deque([s0])
+        while dq:
+            u = dq.popleft()
+            order.append(u)
+            for v in g.col[g.row_ptr[u]:g.row_ptr[u + 1]]:
+                if not seen[v]:
+                    seen[v] = True
+                    dq.append(v)
+    firsts = []
+    for u in order:
+        if lab[u] not in firsts:
+            firsts.append(int(lab[u]))
+    assert firsts == list(range(int(lab.max()) + 1))
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("cap", [4, 1000])
+def test_communities_local_optimum_by_brute_force(weighted, cap):
+    """Run to convergence, the labelling is a local optimum of the true
+    modularity (computed from its definition): no single node moves to a
+    neighbouring community with room for a gain above rounding.  Modularity never falls from one pass to the next, and two
+    calls give the same labels."""
+    g, val = _random_graph(60, 0.12, seed=5 + cap, weighted=weighted)
+    lab, passes = K.katz_communities(g.n, g.row_ptr, g.col, val, cap=cap, passes=100)
+    assert passes < 100
+    lab2, _ = K.katz_communities(g.n, g.row_ptr, g.col, val, cap=cap, passes=100)
+    assert np.array_equal(lab, lab2)
+    assert np.bincount(lab).max() <= cap
+    q = _modularity(g.n, g.row_ptr, g.col, lab, val)
+    for v in range(g.n):
+        nb = g.col[g.row_ptr[v]:g.row_ptr[v + 1]]
+        for c in set(lab[nb].tolist()):
+            if c == lab[v] or np.sum(lab == c) >= cap:
+                continue
+            t = lab.copy()
+            t[v] = c
+            assert _modularity(g.n, g.row_ptr, g.col, t, val) <= q + 1e-12, (v, c)
+    qs = [_modularity(g.n, g.row_ptr, g.col, K.katz_communities(g.n, g.row_ptr, g.col, val, cap=cap,
+                                                                 passes=p)[0], val) for p in range(passes + 1)]
+    assert all(b >= a - 1e-12 for a, b in zip(qs, qs[1:])), qs
+    assert qs[-1] > qs[0]
+
+
+def test_communities_as_partition_labels():
+    """Communities feed the build as labels: the partition stays block
+    diagonal with blocks within max_block."""
+    g = ki.chung_lu(5000, 2.5, 10, seed=4)
+    lab, _ = K.katz_communities(g.n, g.row_ptr, g.col, cap=32, passes=8)
+    idx = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=0, device=-1, max_block=32, labels=lab)
+    info = idx.info
+    perm, bp = idx.partition()
+    assert np.diff(bp).max() <= 32 and info.n1 + info.n2 == g.n
+    blk = np.full(g.n, -1)
+    for b in range(len(bp) - 1):
+        blk[bp[b]:bp[b + 1]] = b
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    pu, pv = perm[rows], perm[g.col]
+    interior = (pu < info.n1) & (pv < info.n1)
+    assert np.all(blk[pu[interior]] == blk[pv[interior]])
+    idx.close()
+
+
+def test_communities_errors():
+    g = ki.from_edges(3, [(0, 1), (1, 2)])
+    for cap, passes in ((0, 4), (4, -1)):
+        with pytest.raises(K.KatzError) as e:
+            K.katz_communities(g.n, g.row_ptr, g.col, cap=cap, passes=passes)
+        assert e.value.code == K.KATZ_EINVAL
+    with pytest.raises(K.KatzError) as e:
+        K.katz_communities(2, [0, 1, 1], [1])
+    assert e.value.code == K.KATZ_ENOTSYM
