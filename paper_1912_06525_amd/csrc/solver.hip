@@ -4182,7 +4182,6 @@ int device_sparse_katz(const HostIndex& H, DeviceIndex* D, const katz_query_opts
                        katz_query_stats* pst, int32_t* ids, double* corr) {
   if (s > kRerankMax) fail(KATZ_EINVAL, "Sparse-Katz list longer than 4096");
   HIPCHECK(hipSetDevice(D->device));
-  hipStream_t st = (hipStream_t)stream;
   const int64_t np = (int64_t)pcol.size();
   // one buffer: K_T entries, their positions, per-request sizes, candidates, outputs
   Carve lay{nullptr};
@@ -4194,12 +4193,19 @@ int device_sparse_katz(const HostIndex& H, DeviceIndex* D, const katz_query_opts
   lay.take<int32_t>((int64_t)nq * s);
   lay.take<int32_t>((int64_t)nq * s);
   lay.take<double>((int64_t)nq * s);
+  hipStream_t st = (hipStream_t)stream;
   auto buf = aux_take(D, lay.off);
+  // back to the pool once the stream is idle (also when a step below throws
+  // with work still queued, so that no other call reuses it in flight)
   struct Give {
     DeviceIndex* D;
     std::pair<void*, size_t> b;
-    ~Give() { aux_give(D, b); }
-  } give{D, buf};
+    hipStream_t st;
+    ~Give() {
+      (void)hipStreamSynchronize(st);
+      aux_give(D, b);
+    }
+  } give{D, buf, st};
   Carve c{(char*)buf.first};
   double* kt = c.take<double>(np);
   int32_t* d_inv = c.take<int32_t>(np);
