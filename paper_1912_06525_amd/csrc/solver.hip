@@ -1994,7 +1994,7 @@ struct Workspace {
   // (their x += alpha p rides on the search-direction update)
   int* fresh = nullptr;
   int32_t* qpos = nullptr;
-  void* tk_scratch = nullptr;    // top-K selection state and winners
+  char* tk_scratch = nullptr;    // top-K selection state and winners
   size_t tk_cap = 0;
   int32_t* tk_ids = nullptr;     // staging for host top-K output
   int32_t *pr_rows = nullptr, *pr_cols = nullptr;  // pair queries: rows, columns, values
@@ -2099,6 +2099,23 @@ T* dalloc(std::vector<void*>& list, int64_t count, int64_t* bytes = nullptr) {
   list.push_back(p);
   if (bytes) *bytes += count * (int64_t)sizeof(T);
   return (T*)p;
+}
+
+// Grows a workspace buffer: *p (allocated from `list`, or null) is replaced
+// by an allocation of `count` T and the old one freed.  Callers grow only
+// between uses: a workspace serves one call at a time, and every use before
+// the growth has been waited for (each batch of a call ends with a stream
+// synchronisation).
+template <typename T>
+void dregrow(std::vector<void*>& list, T*& p, int64_t count) {
+  std::lock_guard<std::recursive_mutex> g(hip_global_mu());
+  if (p) {
+    auto it = std::find(list.begin(), list.end(), (void*)p);
+    if (it != list.end()) list.erase(it);
+    (void)hipFree(p);
+    p = nullptr;
+  }
+  p = dalloc<T>(list, count);
 }
 
 template <typename T>
@@ -3947,10 +3964,13 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
       const int64_t np = p1 - p0;
       if (np > 0) {
         if (w->pr_cap < np) {
-          w->pr_rows = dalloc<int32_t>(w->allocs, np);
-          w->pr_cols = dalloc<int32_t>(w->allocs, np);
-          w->pr_out = dalloc<double>(w->allocs, np);
-          w->pr_cap = np;
+          // geometric growth, the old buffers freed: a run of calls with a
+          // slowly growing pair count stays within twice the largest need
+          const int64_t cap = std::max<int64_t>(np, w->pr_cap + w->pr_cap / 2);
+          dregrow(w->allocs, w->pr_rows, cap);
+          dregrow(w->allocs, w->pr_cols, cap);
+          dregrow(w->allocs, w->pr_out, cap);
+          w->pr_cap = cap;
         }
         std::vector<int32_t> cols(qa.pair_col + p0, qa.pair_col + p1);
         for (auto& x : cols) x -= c0;
@@ -3982,8 +4002,9 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
       const int K = qa.topk;
       size_t need = 64 * (size_t)B + 1024 * (size_t)B + 12 * (size_t)K * B + 1024;
       if (w->tk_cap < need) {
-        w->tk_scratch = dalloc<char>(w->allocs, (int64_t)need);
-        w->tk_cap = need;
+        const size_t cap = std::max(need, w->tk_cap + w->tk_cap / 2);
+        dregrow(w->allocs, w->tk_scratch, (int64_t)cap);
+        w->tk_cap = cap;
       }
       int32_t* ids = qa.ids + (int64_t)c0 * K;
       double* sc = qa.topk_scores ? qa.topk_scores + (int64_t)c0 * K : nullptr;
@@ -3991,9 +4012,10 @@ int device_query_ws(const HostIndex& H, DeviceIndex* D, const QueryArgs& qa, Wor
       double* dsc = sc;
       if (!dev_ids) {
         if (w->tk_out_cap < (int64_t)K * B) {
-          w->tk_ids = dalloc<int32_t>(w->allocs, (int64_t)K * B);
-          w->tk_sc = dalloc<double>(w->allocs, (int64_t)K * B);
-          w->tk_out_cap = (int64_t)K * B;
+          const int64_t cap = std::max<int64_t>((int64_t)K * B, w->tk_out_cap + w->tk_out_cap / 2);
+          dregrow(w->allocs, w->tk_ids, cap);
+          dregrow(w->allocs, w->tk_sc, cap);
+          w->tk_out_cap = cap;
         }
         dids = w->tk_ids;
         dsc = sc ? w->tk_sc : nullptr;

@@ -775,3 +775,35 @@ def test_louvain_partition_matches_oracle(prec, B):
     qs = list(ki.sample_queries(g, B - 1, 5)) + [int(np.argmax(deg))] if B > 1 else [int(np.argmax(deg))]
     _check(g, idx, beta, qs, 1e-8)
     idx.close()
+
+
+def test_growing_pair_and_topk_requests_on_one_index():
+    """Pair and top-K calls of growing and shrinking size on one index: the
+    workspace's pair and selection buffers are regrown (the old ones freed)
+    between calls, and every call still matches the oracle."""
+    g = ki.workload("lnsbm4m", scale=0.002).graph
+    beta = oracle_beta(g, 0.6)
+    idx = K.KatzIndex.from_graph(g, beta=beta, rank=8, labels=g.labels, max_block=32)
+    qs = ki.sample_queries(g, 8, 61)
+    ref = oracle.katz_oracle(g.n, g.row_ptr, g.col, qs, beta=beta, validate=False)["k"]
+    tau = 1e-8
+    tol = tau * (1 - 0.6) / (1 + 0.6)
+    rng = np.random.default_rng(9)
+    for npairs in (3, 40, 10, 700, 90):
+        j = rng.integers(0, len(qs), size=npairs)
+        dst = rng.integers(0, g.n, size=npairs).astype(np.int32)
+        sc, st = idx.pair_scores(qs[j], dst, tol=tol)
+        assert all(s["status"] == 0 for s in st)
+        for t in range(npairs):
+            k = ref[:, j[t]]
+            assert abs(sc[t] - k[dst[t]]) <= tau * np.linalg.norm(k), (npairs, t)
+    for K_ in (5, 60, 7, 150, 20):
+        ids, scs, st = idx.topk(qs, K_, tol=tol)
+        for jj, q in enumerate(qs):
+            k = ref[:, jj]
+            _, _, sid, ssc = oracle.topk_links(g.n, g.row_ptr, g.col, k, q, K_)
+            ok, msg, _ = oracle.topk_accept(ids[jj], sid, ssc, K_, 2 * tau * np.linalg.norm(k))
+            assert ok, (K_, msg)
+            m = ids[jj] >= 0
+            np.testing.assert_allclose(scs[jj][m], k[ids[jj][m]], rtol=0, atol=tau * np.linalg.norm(k))
+    idx.close()
