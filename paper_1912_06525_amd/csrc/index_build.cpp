@@ -1146,20 +1146,24 @@ int32_t communities(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* co
   }
   int32_t done = 0;
   if (m2 > 0.0) {
+    // wto[c] holds w(v, C) for the communities stamped with this visit's tick
     std::vector<double> wto(n, 0.0);
-    std::vector<int32_t> stamp(n, -1), touched;
+    std::vector<int64_t> stamp(n, -1);
+    std::vector<int32_t> touched;
+    int64_t tick = 0;
     for (int32_t pass = 0; pass < passes; pass++) {
       int64_t moved = 0;
       for (int32_t v = 0; v < n; v++) {
         if (!(k[v] > 0.0)) continue;
         const int32_t c0 = comm[v];
         touched.clear();
-        stamp[c0] = v;
+        tick++;
+        stamp[c0] = tick;
         wto[c0] = 0.0;
         for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
           const int32_t c = comm[col[e]];
-          if (stamp[c] != v) {
-            stamp[c] = v;
+          if (stamp[c] != tick) {
+            stamp[c] = tick;
             wto[c] = 0.0;
             touched.push_back(c);
           }

@@ -406,7 +406,8 @@ def _random_graph(n, p, seed, weighted):
     g = ki.from_edges(n, edges)
     val = None
     if weighted:
-        wt = {e: float(rng.uniform(0.2, 3.0)) for e in edges}
+        # one edge in eight of weight zero (allowed: weights are nonnegative)
+        wt = {e: float(rng.uniform(0.2, 3.0)) if rng.random() < 0.875 else 0.0 for e in edges}
         rows = np.repeat(np.arange(n), g.degrees())
         val = np.array([wt[(min(a, b), max(a, b))] for a, b in zip(rows, g.col)])
     return g, val
