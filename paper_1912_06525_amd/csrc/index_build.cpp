@@ -680,28 +680,29 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
   Partition R;
   R.perm.assign(n, -1);
   R.blk_start.push_back(0);
+  std::vector<int32_t> ord;  // LOCALITY: the nodes in BFS visit order
   if (locality) {
     // blocks by their first node in visit order, nodes within a block in
-    // visit order: sort the blocks by that key, then place the nodes while
-    // walking the visit order (O(n) apart from the sort of the block keys)
-    std::vector<int32_t> ord(n, -1);
+    // visit order: rank the blocks by that key, then place the nodes while
+    // walking the visit order (O(n))
+    ord.assign(n, -1);
     for (int32_t v = 0; v < n; v++) {
       if (visit[v] < 0 || visit[v] >= n || ord[visit[v]] >= 0) fail(KATZ_EDEVICE, "internal: BFS visit order");
       ord[visit[v]] = v;
     }
-    std::vector<std::pair<int64_t, int32_t>> kb(nbk, {INT64_MAX, 0});
-    for (int32_t b = 0; b < nbk; b++) kb[b].second = b;
-    for (int32_t v = 0; v < n; v++)
-      if (!insep[v]) kb[comp[v]].first = std::min(kb[comp[v]].first, visit[v]);
-    std::sort(kb.begin(), kb.end());
-    std::vector<int32_t> slot(nbk);
-    int32_t run = 0;
-    for (int32_t t = 0; t < nbk; t++) {
-      bo[t] = kb[t].second;
-      slot[bo[t]] = run;
-      run += (int32_t)blocks[bo[t]].size();
+    // the visit positions are distinct, so walking the visit order meets
+    // the blocks in the order of their first nodes
+    std::vector<int32_t> slot(nbk, -1);
+    int32_t run = 0, t = 0;
+    for (int32_t pos = 0; pos < n; pos++) {
+      const int32_t v = ord[pos];
+      if (insep[v] || slot[comp[v]] >= 0) continue;
+      bo[t++] = comp[v];
+      slot[comp[v]] = run;
+      run += (int32_t)blocks[comp[v]].size();
       R.blk_start.push_back(run);
     }
+    if (t != nbk) fail(KATZ_EDEVICE, "internal: block order");
     R.iperm.assign(run, -1);
     for (int32_t pos = 0; pos < n; pos++) {
       const int32_t v = ord[pos];
@@ -722,11 +723,18 @@ Partition make_partition(int32_t n, const int32_t* rp, const int32_t* col, const
   // separator order.  DEGREE: largest first, then by id (the hubs, which most
   // adjacency entries point to, share few cache lines of every gathered
   // panel).  LOCALITY: BFS visit order.
-  std::vector<std::pair<int64_t, int32_t>> sk;
-  for (int32_t v = 0; v < n; v++)
-    if (insep[v]) sk.emplace_back(locality ? visit[v] : -(int64_t)(rp[v + 1] - rp[v]), v);
-  std::sort(sk.begin(), sk.end());
-  for (auto& kv : sk) { R.perm[kv.second] = (int32_t)R.iperm.size(); R.iperm.push_back(kv.second); }
+  if (locality) {
+    for (int32_t pos = 0; pos < n; pos++) {
+      const int32_t v = ord[pos];
+      if (insep[v]) { R.perm[v] = (int32_t)R.iperm.size(); R.iperm.push_back(v); }
+    }
+  } else {
+    std::vector<std::pair<int64_t, int32_t>> sk;
+    for (int32_t v = 0; v < n; v++)
+      if (insep[v]) sk.emplace_back(-(int64_t)(rp[v + 1] - rp[v]), v);
+    std::sort(sk.begin(), sk.end());
+    for (auto& kv : sk) { R.perm[kv.second] = (int32_t)R.iperm.size(); R.iperm.push_back(kv.second); }
+  }
   R.n2 = n - R.n1;
   phase("order");
   for (int t = 0; t < 5; t++) R.seconds[t] = ph[t];
