@@ -1,0 +1,82 @@
+"""The boundary from plain C: include/katz.h compiles as C99 on its own, and a
+C program linked against the built library runs the host-side calls
+(communities, a host-only index build, info, the error path of a query on an
+index without a device, free).  CPU only: no GPU compute is called."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB_DIR = os.path.join(ROOT, "paper_1912_06525_amd")
+
+_C_PROGRAM = r"""
+#include <stdio.h>
+#include "katz.h"
+
+/* two triangles {0,1,2} and {3,4,5} joined by the edge 2-3 */
+static const int32_t rp[7] = {0, 2, 4, 7, 10, 12, 14};
+static const int32_t col[14] = {1, 2, 0, 2, 0, 1, 3, 2, 4, 5, 3, 5, 3, 4};
+
+int main(void) {
+  int32_t labels[6], passes = -1;
+  int rc = katz_communities(6, 14, rp, col, NULL, 3, 10, labels, &passes);
+  if (rc != KATZ_OK) { printf("communities %d %s\n", rc, katz_last_error()); return 1; }
+  printf("labels %d %d %d %d %d %d passes %d\n", labels[0], labels[1], labels[2], labels[3], labels[4],
+         labels[5], passes);
+  katz_build_opts o;
+  katz_build_opts_default(&o);
+  o.device = -1;
+  o.rank = 0;
+  o.beta_frac = 0.5;
+  o.labels = labels;
+  katz_index* idx = NULL;
+  rc = katz_index_build(6, 14, rp, col, NULL, &o, &idx);
+  if (rc != KATZ_OK) { printf("build %d %s\n", rc, katz_last_error()); return 1; }
+  katz_index_info_t info;
+  if (katz_index_info(idx, &info) != KATZ_OK) return 1;
+  printf("info n %d n1 %d n2 %d device %d c %.3f\n", info.n, info.n1, info.n2, info.device, info.c);
+  double scores[6];
+  int32_t q = 0;
+  rc = katz_query(idx, &q, 1, NULL, scores, NULL, NULL);
+  printf("query %d %s\n", rc == KATZ_EDEVICE, katz_last_error());
+  katz_index_free(idx);
+  rc = katz_communities(6, 14, rp, col, NULL, 0, 10, labels, NULL);
+  printf("bad cap %d\n", rc == KATZ_EINVAL);
+  return 0;
+}
+"""
+
+
+def test_header_is_c99():
+    gcc = shutil.which("gcc")
+    if not gcc:
+        pytest.skip("no gcc")
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-x", "c",
+                    os.path.join(ROOT, "include", "katz.h")], check=True)
+
+
+def test_c_program_against_the_library(tmp_path):
+    gcc = shutil.which("gcc")
+    if not gcc:
+        pytest.skip("no gcc")
+    lib = os.path.join(LIB_DIR, "libkatz_hip.so")
+    if not os.path.exists(lib):
+        pytest.skip("libkatz_hip.so is not built")
+    src = tmp_path / "abi.c"
+    src.write_text(_C_PROGRAM)
+    exe = tmp_path / "abi"
+    rocm_lib = "/opt/rocm/lib"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-L", LIB_DIR, "-l:libkatz_hip.so", "-Wl,-rpath," + LIB_DIR, "-Wl,-rpath," + rocm_lib,
+                    "-Wl,-rpath-link," + rocm_lib, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, timeout=120).stdout
+    lines = out.strip().splitlines()
+    assert lines[0].startswith("labels 0 0 0 1 1 1 passes "), out
+    assert lines[1].startswith("info n 6 n1 ") and " device -1 c 0.500" in lines[1], out
+    n1 = int(lines[1].split()[4])
+    n2 = int(lines[1].split()[6])
+    assert n1 + n2 == 6 and n2 >= 1, out
+    assert lines[2].startswith("query 1 "), out
+    assert lines[3] == "bad cap 1", out
