@@ -80,3 +80,37 @@ def test_c_program_against_the_library(tmp_path):
     assert n1 + n2 == 6 and n2 >= 1, out
     assert lines[2].startswith("query 1 "), out
     assert lines[3] == "bad cap 1", out
+
+
+_STRUCTS = ["katz_build_opts", "katz_query_opts", "katz_query_stats", "katz_index_info_t", "katz_server_opts",
+            "katz_server_info_t", "katz_kernel_stat"]
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct of the header has the same size and field offsets in the
+    ctypes binding as the C compiler gives it (field names as in the
+    header)."""
+    gcc = shutil.which("gcc")
+    if not gcc:
+        pytest.skip("no gcc")
+    K = pytest.importorskip("paper_1912_06525_amd")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "katz.h"', "int main(void) {"]
+    for name in _STRUCTS:
+        cls = getattr(K, name)
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for fname, _ in cls._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, fname, name, fname))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line)
+    import ctypes
+    for name in _STRUCTS:
+        cls = getattr(K, name)
+        assert int(got["%s size" % name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got["%s.%s" % (name, fname)]) == getattr(cls, fname).offset, (name, fname)
