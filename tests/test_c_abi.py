@@ -114,3 +114,15 @@ def test_binding_structs_match_the_header(tmp_path):
         assert int(got["%s size" % name]) == ctypes.sizeof(cls), name
         for fname, _ in cls._fields_:
             assert int(got["%s.%s" % (name, fname)]) == getattr(cls, fname).offset, (name, fname)
+
+
+def test_binding_constants_match_the_header():
+    """Every enumerator the header defines (status codes, precisions, factor
+    kinds, methods, orders, paths) has the same value in the binding."""
+    import re
+    K = pytest.importorskip("paper_1912_06525_amd")
+    src = open(os.path.join(ROOT, "include", "katz.h")).read()
+    found = re.findall(r"^\s*(KATZ_[A-Z0-9_]+)\s*=\s*(-?\d+)", src, re.M)
+    assert len(found) >= 24, found
+    for name, value in found:
+        assert getattr(K, name) == int(value), name
