@@ -196,6 +196,27 @@ int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
                      const double* val, const katz_build_opts* opts, katz_index** out);
 
 /*
+ * Another index of src's graph for other options, without repeating the
+ * steps that do not depend on beta (Algorithm 1; Sec. 3.2 steps 1-3: the
+ * CSR checks, lambda_max, the partition, the node order and the permuted
+ * adjacency are src's).  The M11 block inverses, the separator factor and
+ * the Lanczos on R (step 4 and eq. RMatrix) are computed afresh from opts
+ * exactly as katz_index_build computes them: beta or beta_frac, rank, l_kind,
+ * precision, u_precision, seed, lanczos_steps and device apply;
+ * max_block, labels and order are ignored (the partition is src's).  With
+ * the same graph, partition options and seed, the result equals a fresh
+ * build's.  For a new damping factor (per-beta reindexing) this skips the
+ * partition, most of a build's time on large graphs.
+ *   src: any index (built, loaded, or host-only); it is not modified and
+ *     stays valid.  opts: may be NULL (defaults).
+ *   *out receives the new index (free with katz_index_free).
+ * Errors: KATZ_EINVAL (null src or out, bad options), KATZ_EDIVERGE
+ * (beta * lambda_max >= 1, or a factor not positive definite), KATZ_ENOMEM,
+ * KATZ_EDEVICE.
+ */
+int katz_index_rebuild(const katz_index* src, const katz_build_opts* opts, katz_index** out);
+
+/*
  * Communities to pass as katz_build_opts.labels for a graph without planted
  * labels (Sec. 3.2 step 2 partitions with METIS; this library offers this
  * instead, or the build's default of one part cut into BFS chunks).  It is

@@ -32,7 +32,7 @@ _STATUS = {0: "KATZ_OK", -1: "KATZ_EINVAL", -2: "KATZ_ENOTSYM", -3: "KATZ_EDIVER
            -5: "KATZ_EDEVICE", -6: "KATZ_ENOCONV", -7: "KATZ_EBUSY", -8: "KATZ_EIO"}
 
 EXPORTED = ["katz_build_opts_default", "katz_query_opts_default", "katz_index_build", "katz_query",
-            "katz_query_noalloc", "katz_communities",
+            "katz_query_noalloc", "katz_communities", "katz_index_rebuild",
             "katz_topk_links", "katz_pair_scores", "katz_sparse_katz", "katz_index_save", "katz_index_load", "katz_index_free", "katz_index_info", "katz_index_partition",
             "katz_index_lowrank", "katz_profile_enable", "katz_profile_reset", "katz_profile_read",
             "katz_server_opts_default", "katz_server_create", "katz_server_submit", "katz_server_poll",
@@ -108,6 +108,8 @@ def _load():
     lib.katz_index_build.argtypes = [i32, i64, pi32, pi32, pdbl, ctypes.POINTER(katz_build_opts),
                                      ctypes.POINTER(P)]
     lib.katz_index_build.restype = ctypes.c_int
+    lib.katz_index_rebuild.argtypes = [P, ctypes.POINTER(katz_build_opts), ctypes.POINTER(P)]
+    lib.katz_index_rebuild.restype = ctypes.c_int
     lib.katz_communities.argtypes = [i32, i64, pi32, pi32, pdbl, i32, i32, pi32, ctypes.POINTER(i32)]
     lib.katz_communities.restype = ctypes.c_int
     lib.katz_query.argtypes = [P, pi32, i32, ctypes.POINTER(katz_query_opts), P,
@@ -369,6 +371,24 @@ class KatzIndex:
     @classmethod
     def from_graph(cls, g, **kw):
         return cls(g.n, g.row_ptr, g.col, **kw)
+
+    def rebuild(self, *, beta: float = 0.0, beta_frac: float = 0.5, rank: int = 32, l_kind: int = KATZ_L_AUTO,
+                precision: int = KATZ_PREC_FP64, seed: int = 12345, device: int = 0, lanczos_steps: int = 0,
+                u_precision: int = 0) -> "KatzIndex":
+        """katz_index_rebuild: this graph and partition, new beta-dependent
+        factors for these options."""
+        o = katz_build_opts_default()
+        o.beta, o.beta_frac, o.rank = beta, beta_frac, rank
+        o.l_kind, o.precision, o.seed, o.device, o.lanczos_steps = l_kind, precision, seed, device, lanczos_steps
+        o.u_precision = u_precision
+        h = ctypes.c_void_p()
+        _check(_lib.katz_index_rebuild(self.h, ctypes.byref(o), ctypes.byref(h)))
+        new = KatzIndex.__new__(KatzIndex)
+        new._labels = None
+        new.h = h
+        new.info = katz_index_info(h)
+        new.n = int(new.info.n)
+        return new
 
     @classmethod
     def load(cls, path: str, device: int = 0) -> "KatzIndex":

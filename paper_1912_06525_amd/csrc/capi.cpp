@@ -46,6 +46,18 @@ int check_queries(const katz_index* idx, const int32_t* q, int32_t nq) {
 
 katz_query_opts resolve(const katz_query_opts* o);
 
+// An index whose host part is complete: with a device (>= 0), upload it and
+// run the Lanczos on R there when the host part left it for the device.
+void finish_on_device(katz_index* idx, int32_t device) {
+  idx->device = device;
+  if (device < 0) return;
+  const auto t0 = std::chrono::steady_clock::now();
+  idx->dev = katz::device_upload(idx->host, device);
+  idx->host.phase_seconds[11] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  idx->host.build_seconds += idx->host.phase_seconds[11];
+  if (idx->host.lanczos_rank > 0) katz::device_lanczos_R(idx->host, idx->dev);
+}
+
 // K[dst[i], src[i]] for validated pairs into host out[], per-pair stats
 // (nullable); the distinct sources run as the columns of batched solves.
 int pair_scores_host(const katz_index* idx, const int32_t* src, const int32_t* dst, int32_t npairs,
@@ -131,14 +143,29 @@ int katz_index_build(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
     try {
       // with a device, a large Lanczos on R runs there after the upload
       katz::build_host_index(n, nnz, row_ptr, col_idx, val, o, idx->host, o.device >= 0);
-      idx->device = o.device;
-      if (o.device >= 0) {
-        const auto t0 = std::chrono::steady_clock::now();
-        idx->dev = katz::device_upload(idx->host, o.device);
-        idx->host.phase_seconds[11] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        idx->host.build_seconds += idx->host.phase_seconds[11];
-        if (idx->host.lanczos_rank > 0) katz::device_lanczos_R(idx->host, idx->dev);
-      }
+      finish_on_device(idx, o.device);
+    } catch (...) {
+      katz_index_free(idx);
+      throw;
+    }
+    *out = idx;
+    return KATZ_OK;
+  });
+}
+
+int katz_index_rebuild(const katz_index* src, const katz_build_opts* opts, katz_index** out) {
+  return guarded([&]() -> int {
+    if (!out) return set_error(KATZ_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!src) return set_error(KATZ_EINVAL, "null source index");
+    katz_build_opts o;
+    katz_build_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.u_precision < 0 || o.u_precision > 3) return set_error(KATZ_EINVAL, "bad u_precision");
+    auto* idx = new katz_index();
+    try {
+      katz::rebuild_host_index(src->host, o, idx->host, o.device >= 0);
+      finish_on_device(idx, o.device);
     } catch (...) {
       katz_index_free(idx);
       throw;

@@ -963,41 +963,22 @@ bool lanczos_on_device(const HostIndex& H, const katz_build_opts& o) {
   return H.n2 >= 65536;
 }
 
-void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
-                      const double* val, const katz_build_opts& o, HostIndex& H, bool defer_lanczos) {
-  auto t0 = std::chrono::steady_clock::now();
-  // KATZ_VERBOSE=1: phase times of the build on stderr
-  const bool verbose = getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 0;
-  auto tp = t0;
-  int slot = 0;
-  auto phase = [&](const char* what) {
-    auto t = std::chrono::steady_clock::now();
-    const double sec = std::chrono::duration<double>(t - tp).count();
-    // phase slots: validate 0, lambda_max 1, (partition 2-6), CSR 7, inverses 8, M22 9, Lanczos 10
-    if (slot < 12) H.phase_seconds[slot] = sec;
-    slot = slot == 1 ? 7 : slot + 1;
-    if (verbose) std::fprintf(stderr, "katz build: %-22s %8.3f s\n", what, sec);
-    tp = t;
-  };
-  validate(n, nnz, row_ptr, col, val);
-  phase("validate");
+namespace {
+
+// Checks the options and sets the index fields that come from them alone.
+void apply_options(const katz_build_opts& o, HostIndex& H) {
   if (o.rank < 0) fail(KATZ_EINVAL, "rank must be >= 0");
   if (o.max_block < 0) fail(KATZ_EINVAL, "max_block must be >= 0");
   if (o.l_kind < KATZ_L_AUTO || o.l_kind > KATZ_L_IC0) fail(KATZ_EINVAL, "bad l_kind");
   if (o.precision != KATZ_PREC_FP64 && o.precision != KATZ_PREC_MIXED) fail(KATZ_EINVAL, "bad precision");
   if (o.order < KATZ_ORDER_AUTO || o.order > KATZ_ORDER_LOCALITY) fail(KATZ_EINVAL, "bad order");
-  H.n = n;
-  H.nnz = nnz;
-  H.weighted = val != nullptr;
   H.precision = o.precision;
   H.u_precision_req = o.u_precision;
   H.u_precision = o.u_precision == 0 ? 2 : o.u_precision;  // auto: settled in lanczos_ritz
-  // large graphs with a device: the Lanczos vectors and products on the GPU
-  // (the same steps and stopping rule; sums in a fixed order)
-  int lam_dev = o.device >= 0 && n >= kLambdaDeviceMin && row_ptr[n] > 0;
-  if (const char* e = getenv("KATZ_LAMBDA_DEVICE")) lam_dev = lam_dev && atoi(e) != 0;
-  H.lambda_max = lam_dev ? device_lambda_max(o.device, n, nnz, row_ptr, col, val, o.seed)
-                         : lambda_max(n, row_ptr, col, val, o.seed);
+}
+
+// beta from the options (beta, or beta_frac / lambda_max) and c = beta lambda_max.
+void set_beta(const katz_build_opts& o, HostIndex& H) {
   if (o.beta > 0) {
     H.beta = o.beta;
   } else {
@@ -1006,55 +987,13 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
     H.beta = o.beta_frac / H.lambda_max;
   }
   H.c = H.beta * H.lambda_max;
-  phase("lambda_max");
-  if (!(H.c < 1.0)) fail(KATZ_EDIVERGE, "beta * lambda_max(A) >= 1: Katz series diverges and I - beta A is not positive definite");
-  if (o.labels)
-    for (int32_t v = 0; v < n; v++)
-      if (o.labels[v] < 0) fail(KATZ_EINVAL, "labels must be >= 0");
+}
 
-  int32_t max_block = o.max_block > 0 ? o.max_block : 64;
-  int32_t order_kind = o.order;
-  if (const char* e = getenv("KATZ_ORDER")) order_kind = atoi(e);
-  if (order_kind == KATZ_ORDER_AUTO) order_kind = KATZ_ORDER_LOCALITY;
-  Partition P = make_partition(n, row_ptr, col, o.labels, max_block, order_kind);
-  H.perm = std::move(P.perm);
-  H.iperm = std::move(P.iperm);
-  H.blk_start = std::move(P.blk_start);
-  H.n1 = P.n1;
-  H.n2 = P.n2;
-  for (int t = 0; t < 5; t++) H.phase_seconds[2 + t] = P.seconds[t];
-  if (verbose) std::fprintf(stderr, "katz build: %-22s %8.3f s\n", "partition",
-                            std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count());
-  tp = std::chrono::steady_clock::now();
-
-  // permuted CSR with sorted rows and the separator split
-  H.rp.assign(n + 1, 0);
-  for (int32_t i = 0; i < n; i++) {
-    int32_t v = H.iperm[i];
-    H.rp[i + 1] = H.rp[i] + (row_ptr[v + 1] - row_ptr[v]);
-  }
-  H.col.resize(nnz);
-  H.split.resize(n);
-  if (val) H.val.resize(nnz);
-  parallel_for(n, [&](int64_t b, int64_t e) {
-    std::vector<std::pair<int32_t, double>> tmp;
-    for (int64_t i = b; i < e; i++) {
-      int32_t v = H.iperm[i];
-      tmp.clear();
-      for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; k++) tmp.emplace_back(H.perm[col[k]], val ? val[k] : 1.0);
-      std::sort(tmp.begin(), tmp.end());
-      int32_t o2 = H.rp[i];
-      int32_t sp = H.rp[i + 1];
-      for (size_t k = 0; k < tmp.size(); k++) {
-        H.col[o2 + k] = tmp[k].first;
-        if (val) H.val[o2 + k] = tmp[k].second;
-        if (tmp[k].first >= H.n1 && sp == H.rp[i + 1]) sp = o2 + (int32_t)k;
-      }
-      H.split[i] = sp;
-    }
-  }, 4096);
-
-  phase("permuted CSR");
+// The part of the index that depends on beta (Sec. 3.2 step 4 and the
+// low-rank correction): the M11 block inverses, the separator factor and the
+// Lanczos on R, from the permuted CSR and the blocks already in H.
+void build_factors(const katz_build_opts& o, HostIndex& H, bool defer_lanczos,
+                   const std::function<void(const char*)>& phase) {
   // M11 block inverses
   int32_t nb = (int32_t)H.blk_start.size() - 1;
   H.blk_off.assign(nb + 1, 0);
@@ -1114,6 +1053,127 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
     lanczos_R(H, std::min(o.rank, H.n2), o.lanczos_steps, o.seed);
     phase("Lanczos on R");
   }
+}
+
+}  // namespace
+
+void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                      const double* val, const katz_build_opts& o, HostIndex& H, bool defer_lanczos) {
+  auto t0 = std::chrono::steady_clock::now();
+  // KATZ_VERBOSE=1: phase times of the build on stderr
+  const bool verbose = getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 0;
+  auto tp = t0;
+  int slot = 0;
+  auto phase = [&](const char* what) {
+    auto t = std::chrono::steady_clock::now();
+    const double sec = std::chrono::duration<double>(t - tp).count();
+    // phase slots: validate 0, lambda_max 1, (partition 2-6), CSR 7, inverses 8, M22 9, Lanczos 10
+    if (slot < 12) H.phase_seconds[slot] = sec;
+    slot = slot == 1 ? 7 : slot + 1;
+    if (verbose) std::fprintf(stderr, "katz build: %-22s %8.3f s\n", what, sec);
+    tp = t;
+  };
+  validate(n, nnz, row_ptr, col, val);
+  phase("validate");
+  apply_options(o, H);
+  H.n = n;
+  H.nnz = nnz;
+  H.weighted = val != nullptr;
+  // large graphs with a device: the Lanczos vectors and products on the GPU
+  // (the same steps and stopping rule; sums in a fixed order)
+  int lam_dev = o.device >= 0 && n >= kLambdaDeviceMin && row_ptr[n] > 0;
+  if (const char* e = getenv("KATZ_LAMBDA_DEVICE")) lam_dev = lam_dev && atoi(e) != 0;
+  H.lambda_max = lam_dev ? device_lambda_max(o.device, n, nnz, row_ptr, col, val, o.seed)
+                         : lambda_max(n, row_ptr, col, val, o.seed);
+  set_beta(o, H);
+  phase("lambda_max");
+  if (!(H.c < 1.0)) fail(KATZ_EDIVERGE, "beta * lambda_max(A) >= 1: Katz series diverges and I - beta A is not positive definite");
+  if (o.labels)
+    for (int32_t v = 0; v < n; v++)
+      if (o.labels[v] < 0) fail(KATZ_EINVAL, "labels must be >= 0");
+
+  int32_t max_block = o.max_block > 0 ? o.max_block : 64;
+  int32_t order_kind = o.order;
+  if (const char* e = getenv("KATZ_ORDER")) order_kind = atoi(e);
+  if (order_kind == KATZ_ORDER_AUTO) order_kind = KATZ_ORDER_LOCALITY;
+  Partition P = make_partition(n, row_ptr, col, o.labels, max_block, order_kind);
+  H.perm = std::move(P.perm);
+  H.iperm = std::move(P.iperm);
+  H.blk_start = std::move(P.blk_start);
+  H.n1 = P.n1;
+  H.n2 = P.n2;
+  for (int t = 0; t < 5; t++) H.phase_seconds[2 + t] = P.seconds[t];
+  if (verbose) std::fprintf(stderr, "katz build: %-22s %8.3f s\n", "partition",
+                            std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count());
+  tp = std::chrono::steady_clock::now();
+
+  // permuted CSR with sorted rows and the separator split
+  H.rp.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; i++) {
+    int32_t v = H.iperm[i];
+    H.rp[i + 1] = H.rp[i] + (row_ptr[v + 1] - row_ptr[v]);
+  }
+  H.col.resize(nnz);
+  H.split.resize(n);
+  if (val) H.val.resize(nnz);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    std::vector<std::pair<int32_t, double>> tmp;
+    for (int64_t i = b; i < e; i++) {
+      int32_t v = H.iperm[i];
+      tmp.clear();
+      for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; k++) tmp.emplace_back(H.perm[col[k]], val ? val[k] : 1.0);
+      std::sort(tmp.begin(), tmp.end());
+      int32_t o2 = H.rp[i];
+      int32_t sp = H.rp[i + 1];
+      for (size_t k = 0; k < tmp.size(); k++) {
+        H.col[o2 + k] = tmp[k].first;
+        if (val) H.val[o2 + k] = tmp[k].second;
+        if (tmp[k].first >= H.n1 && sp == H.rp[i + 1]) sp = o2 + (int32_t)k;
+      }
+      H.split[i] = sp;
+    }
+  }, 4096);
+
+  phase("permuted CSR");
+  build_factors(o, H, defer_lanczos, phase);
+  H.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// The index of the same graph for other options (another beta, rank,
+// factor kind, precision, storage, seed or step count): the validated CSR,
+// lambda_max, the partition, the node order and the permuted CSR of S are
+// reused (Sec. 3.2 steps 1-3 do not depend on beta); the block inverses, the
+// separator factor and the Lanczos on R are computed afresh as a build with
+// these options computes them.  max_block, labels and order are S's.
+void rebuild_host_index(const HostIndex& S, const katz_build_opts& o, HostIndex& H, bool defer_lanczos) {
+  auto t0 = std::chrono::steady_clock::now();
+  const bool verbose = getenv("KATZ_VERBOSE") && atoi(getenv("KATZ_VERBOSE")) > 0;
+  auto tp = t0;
+  int slot = 8;  // the build's slots of the block inverses, M22 and Lanczos phases
+  auto phase = [&](const char* what) {
+    auto t = std::chrono::steady_clock::now();
+    const double sec = std::chrono::duration<double>(t - tp).count();
+    if (slot < 12) H.phase_seconds[slot++] = sec;
+    if (verbose) std::fprintf(stderr, "katz rebuild: %-22s %8.3f s\n", what, sec);
+    tp = t;
+  };
+  apply_options(o, H);
+  H.n = S.n;
+  H.n1 = S.n1;
+  H.n2 = S.n2;
+  H.nnz = S.nnz;
+  H.weighted = S.weighted;
+  H.lambda_max = S.lambda_max;
+  set_beta(o, H);
+  if (!(H.c < 1.0)) fail(KATZ_EDIVERGE, "beta * lambda_max(A) >= 1: Katz series diverges and I - beta A is not positive definite");
+  H.perm = S.perm;
+  H.iperm = S.iperm;
+  H.rp = S.rp;
+  H.col = S.col;
+  H.split = S.split;
+  H.val = S.val;
+  H.blk_start = S.blk_start;
+  build_factors(o, H, defer_lanczos, phase);
   H.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 

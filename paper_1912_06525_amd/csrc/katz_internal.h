@@ -70,6 +70,10 @@ void build_host_index(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
 void lanczos_normals(uint64_t& state, double* out, int64_t n);
 std::vector<double> lanczos_ritz(HostIndex& H, const std::vector<double>& al, const std::vector<double>& be,
                                  int32_t r);
+// The index of the same graph and partition for other options (beta, rank,
+// factor kind, precision, storage, seed, steps): S's structure reused, the
+// beta-dependent factors computed afresh (katz_index_rebuild).
+void rebuild_host_index(const HostIndex& S, const katz_build_opts& o, HostIndex& H, bool defer_lanczos = false);
 // Louvain local moving with communities capped at `cap` nodes, for the
 // initial parts of an unlabeled graph (katz_communities); returns the passes
 // run.

@@ -528,3 +528,71 @@ def test_communities_errors():
     with pytest.raises(K.KatzError) as e:
         K.katz_communities(2, [0, 1, 1], [1])
     assert e.value.code == K.KATZ_ENOTSYM
+
+
+# ------------------------------------------------------------ rebuild for other options
+def _file_bytes(idx, path):
+    """The index file without its build-time field (bytes 92..100)."""
+    idx.save(path)
+    b = bytearray(open(path, "rb").read())
+    b[92:100] = b"\0" * 8
+    return bytes(b)
+
+
+_REBUILD_CASES = [
+    # (graph, weighted, partition options, source options, target options)
+    ("sbm2k", False, dict(labels=True, max_block=200), dict(beta_frac=0.3, rank=4),
+     dict(beta_frac=0.8, rank=8, l_kind=K.KATZ_L_CHOL)),
+    ("sbm2k", False, dict(labels=True, max_block=200), dict(beta_frac=0.5, rank=8, l_kind=K.KATZ_L_CHOL),
+     dict(beta_frac=0.95, rank=8, l_kind=K.KATZ_L_IC0)),
+    ("cl", False, dict(), dict(beta_frac=0.5, rank=16), dict(beta_frac=0.9, rank=24)),
+    ("cl", True, dict(order=K.KATZ_ORDER_DEGREE), dict(beta_frac=0.5, rank=16),
+     dict(beta_frac=0.7, rank=32, precision=K.KATZ_PREC_MIXED)),
+    ("cl", False, dict(), dict(beta_frac=0.2, rank=0), dict(beta=0.005, rank=5, u_precision=1, lanczos_steps=40)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(_REBUILD_CASES)))
+def test_rebuild_equals_a_fresh_build(case, tmp_path):
+    """katz_index_rebuild reuses the graph's checks, lambda_max, partition and
+    order and recomputes the beta-dependent factors: its index file equals a
+    fresh build's with the target options byte for byte (build time aside),
+    also from a loaded source, and the source is left unchanged."""
+    gname, weighted, popt, sopt, topt = _REBUILD_CASES[case]
+    g = ki.workload("sbm2k").graph if gname == "sbm2k" else ki.chung_lu(20000, 2.5, 8, seed=7)
+    val = ki.edge_weights(g, seed=2) if weighted else None
+    part = dict(popt)
+    if part.pop("labels", False):
+        part["labels"] = g.labels
+    src = K.KatzIndex(g.n, g.row_ptr, g.col, val, device=-1, **part, **sopt)
+    before = _file_bytes(src, str(tmp_path / "src.katz"))
+    fresh = K.KatzIndex(g.n, g.row_ptr, g.col, val, device=-1, **part, **topt)
+    want = _file_bytes(fresh, str(tmp_path / "fresh.katz"))
+    re = src.rebuild(device=-1, **topt)
+    assert _file_bytes(re, str(tmp_path / "re.katz")) == want
+    assert _file_bytes(src, str(tmp_path / "src2.katz")) == before
+    ph = list(re.info.build_phase_seconds)
+    assert ph[:8] == [0.0] * 8 and ph[8] >= 0.0
+    loaded = K.KatzIndex.load(str(tmp_path / "src.katz"), device=-1)
+    re2 = loaded.rebuild(device=-1, **topt)
+    assert _file_bytes(re2, str(tmp_path / "re2.katz")) == want
+    for x in (src, fresh, re, loaded, re2):
+        x.close()
+
+
+def test_rebuild_errors():
+    g = ki.workload("sbm2k").graph
+    src = K.KatzIndex.from_graph(g, beta_frac=0.5, rank=4, device=-1, labels=g.labels, max_block=200)
+    for kw, code in ((dict(beta_frac=1.0), K.KATZ_EDIVERGE), (dict(beta=1.0), K.KATZ_EDIVERGE),
+                     (dict(rank=-1), K.KATZ_EINVAL), (dict(u_precision=5), K.KATZ_EINVAL),
+                     (dict(l_kind=9), K.KATZ_EINVAL), (dict(precision=4), K.KATZ_EINVAL)):
+        with pytest.raises(K.KatzError) as e:
+            src.rebuild(device=-1, **kw)
+        assert e.value.code == code, kw
+    import ctypes
+    h = ctypes.c_void_p()
+    assert K._lib.katz_index_rebuild(None, None, ctypes.byref(h)) == K.KATZ_EINVAL
+    assert K._lib.katz_index_rebuild(src.h, None, None) == K.KATZ_EINVAL
+    # the source still answers host-side calls
+    assert src.info.rank == 4
+    src.close()
