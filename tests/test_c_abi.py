@@ -1,7 +1,7 @@
 """The boundary from plain C: include/katz.h compiles as C99 on its own, and a
 C program linked against the built library runs the host-side calls
 (communities, a host-only index build, info, the error path of a query on an
-index without a device, free).  CPU only: no GPU compute is called."""
+index without a device, a rebuild for another damping factor, free).  CPU only: no GPU compute is called."""
 import os
 import shutil
 import subprocess
@@ -41,6 +41,12 @@ int main(void) {
   int32_t q = 0;
   rc = katz_query(idx, &q, 1, NULL, scores, NULL, NULL);
   printf("query %d %s\n", rc == KATZ_EDEVICE, katz_last_error());
+  o.beta_frac = 0.8;
+  katz_index* idx2 = NULL;
+  rc = katz_index_rebuild(idx, &o, &idx2);
+  if (rc != KATZ_OK || katz_index_info(idx2, &info) != KATZ_OK) return 1;
+  printf("rebuild n1 %d c %.3f\n", info.n1, info.c);
+  katz_index_free(idx2);
   katz_index_free(idx);
   rc = katz_communities(6, 14, rp, col, NULL, 0, 10, labels, NULL);
   printf("bad cap %d\n", rc == KATZ_EINVAL);
@@ -79,7 +85,8 @@ def test_c_program_against_the_library(tmp_path):
     n2 = int(lines[1].split()[6])
     assert n1 + n2 == 6 and n2 >= 1, out
     assert lines[2].startswith("query 1 "), out
-    assert lines[3] == "bad cap 1", out
+    assert lines[3] == "rebuild n1 %d c 0.800" % n1, out
+    assert lines[4] == "bad cap 1", out
 
 
 _STRUCTS = ["katz_build_opts", "katz_query_opts", "katz_query_stats", "katz_index_info_t", "katz_server_opts",
