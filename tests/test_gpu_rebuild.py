@@ -1,5 +1,4 @@
-"""GPU check of katz_index_rebuild, kept out of collection until it has run
-on an MI355X (run it by naming this file): an index rebuilt on the device for
+"""GPU check of katz_index_rebuild: an index rebuilt on the device for
 another damping factor answers bit-identically to a fresh build with those
 options, in both precisions, one column and a batch, with the Lanczos on R on
 the host and on the device."""
